@@ -1,0 +1,190 @@
+"""FP64 CPU oracle of the PonD f+g step (test infrastructure).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  The product path (the HIP library and its Python
+binding) never imports or calls it, and it shares no code with them.
+
+The arithmetic lives in ``pond_oracle.c`` (plain C99, FP64); this module only
+marshals numpy arrays through ctypes.  State layout (oracle only): node
+``n = y*nx + x``; ``f[n, i]``, ``g[n, i]`` for velocity ``i = 4a + b`` with
+``c_i = (c_a, c_b)``; frame ``lam[n] = (u_x, u_y, T)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+NONCONVERGED = 1
+NONPHYSICAL = 2
+
+_lib = None
+
+
+class Params(ctypes.Structure):
+    """Mirror of ``oracle_params`` in pond_oracle.c."""
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
+        ("interp_points", ctypes.c_int), ("pc_max_iter", ctypes.c_int),
+        ("tau", ctypes.c_double), ("prandtl", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("pc_tol", ctypes.c_double),
+    ]
+
+
+def params(nx, ny, *, tau, gamma=1.4, prandtl=1.0, bc_x=0, bc_y=0, interp_points=4,
+           pc_tol=1e-13, pc_max_iter=32) -> Params:
+    return Params(nx, ny, bc_x, bc_y, interp_points, pc_max_iter, tau, prandtl, gamma, pc_tol)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.oracle_abi_version.restype = ctypes.c_int
+        L.oracle_lattice_1d.argtypes = [dp, dp]
+        L.oracle_lattice_2d.argtypes = [dp, dp, dp]
+        L.oracle_transform.argtypes = [dp, dp, dp, dp]
+        L.oracle_equilibrium.argtypes = [ctypes.c_double] * 5 + [dp, dp]
+        L.oracle_collide.argtypes = [dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, dp, dp]
+        L.oracle_lagrange.argtypes = [ctypes.c_int, ctypes.c_double, ip, dp]
+        L.oracle_lagrange.restype = ctypes.c_int
+        L.oracle_step.argtypes = [ctypes.POINTER(Params), dp, dp, dp, dp, dp, dp, ip, ip]
+        L.oracle_step.restype = ctypes.c_int
+        L.oracle_init.argtypes = [ctypes.c_long, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp]
+        L.oracle_init.restype = ctypes.c_int
+        L.oracle_moments.argtypes = [ctypes.c_long, dp, dp, dp, ctypes.c_double,
+                                     dp, dp, dp, dp, dp]
+        if L.oracle_abi_version() != 1:
+            raise RuntimeError("oracle library ABI mismatch; rebuild oracle/")
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def lattice_1d():
+    """D1Q4 abscissae and weights (Table I), ascending abscissae."""
+    c = np.zeros(4)
+    w = np.zeros(4)
+    lib().oracle_lattice_1d(_d(c), _d(w))
+    return c, w
+
+
+def lattice_2d():
+    """D2Q16 velocities (c_x, c_y) and weights, i = 4a + b."""
+    cx, cy, w = np.zeros(16), np.zeros(16), np.zeros(16)
+    lib().oracle_lattice_2d(_d(cx), _d(cy), _d(w))
+    return cx, cy, w
+
+
+def transform(pop, lam_src, lam_dst):
+    """Frame transformation of 16 populations from lam_src to lam_dst."""
+    pop = _f64(pop, (16,))
+    out = np.zeros(16)
+    lib().oracle_transform(_d(pop), _d(_f64(lam_src, (3,))), _d(_f64(lam_dst, (3,))), _d(out))
+    return out
+
+
+def equilibrium(rho, ux, uy, T, gamma):
+    f = np.zeros(16)
+    g = np.zeros(16)
+    lib().oracle_equilibrium(rho, ux, uy, T, gamma, _d(f), _d(g))
+    return f, g
+
+
+def collide(ft, gt, lam, tau, prandtl, gamma):
+    fo, go = np.zeros(16), np.zeros(16)
+    lib().oracle_collide(_d(_f64(ft, (16,))), _d(_f64(gt, (16,))), _d(_f64(lam, (3,))),
+                         tau, prandtl, gamma, _d(fo), _d(go))
+    return fo, go
+
+
+def lagrange(npts, y):
+    """(first node, weights) of the npts-point Lagrange stencil at coordinate y."""
+    base = np.zeros(1, dtype=np.int32)
+    w = np.zeros(npts)
+    if lib().oracle_lagrange(npts, float(y), _i(base), _d(w)) != 0:
+        raise ValueError("interp_points must be 3 or 4")
+    return int(base[0]), w
+
+
+@dataclass
+class State:
+    """Oracle state: f, g of shape (N, 16), lam of shape (N, 3)."""
+    f: np.ndarray
+    g: np.ndarray
+    lam: np.ndarray
+
+    def copy(self):
+        return State(self.f.copy(), self.g.copy(), self.lam.copy())
+
+
+def init(P: Params, rho, ux, uy, T) -> State:
+    N = P.nx * P.ny
+    rho, ux, uy, T = (_f64(a, (N,)) for a in (rho, ux, uy, T))
+    f, g, lam = np.zeros((N, 16)), np.zeros((N, 16)), np.zeros((N, 3))
+    nbad = lib().oracle_init(N, _d(rho), _d(ux), _d(uy), _d(T), P.gamma, _d(f), _d(g), _d(lam))
+    if nbad:
+        raise ValueError(f"{nbad} nodes with rho <= 0, T <= 0 or non-finite values")
+    return State(f, g, lam)
+
+
+@dataclass
+class StepStats:
+    iters: np.ndarray      # gathers per node in the last step
+    status: np.ndarray     # NONCONVERGED / NONPHYSICAL bits per node, last step
+    total_iters: int       # gathers summed over nodes and steps
+    nonconverged: int      # node-steps that hit the iteration cap
+    nonphysical: int       # node-steps flagged non-physical
+
+
+def step(P: Params, s: State, nsteps: int = 1):
+    """Advance nsteps; returns (new State, StepStats)."""
+    N = P.nx * P.ny
+    cur = s.copy()
+    nxt = State(np.zeros((N, 16)), np.zeros((N, 16)), np.zeros((N, 3)))
+    iters = np.zeros(N, dtype=np.int32)
+    status = np.zeros(N, dtype=np.int32)
+    tot = nonc = nbad = 0
+    for _ in range(nsteps):
+        bad = lib().oracle_step(ctypes.byref(P), _d(cur.f), _d(cur.g), _d(cur.lam),
+                                _d(nxt.f), _d(nxt.g), _d(nxt.lam), _i(iters), _i(status))
+        tot += int(iters.sum())
+        nonc += int(((status & NONCONVERGED) != 0).sum())
+        nbad += bad
+        cur, nxt = nxt, cur
+        if bad:
+            break
+    return cur, StepStats(iters.copy(), status.copy(), tot, nonc, nbad)
+
+
+def moments(P: Params, s: State):
+    """dict of rho, ux, uy, T, p, each of shape (ny, nx)."""
+    N = P.nx * P.ny
+    out = {k: np.zeros(N) for k in ("rho", "ux", "uy", "T", "p")}
+    lib().oracle_moments(N, _d(s.f), _d(s.g), _d(s.lam), P.gamma, _d(out["rho"]),
+                         _d(out["ux"]), _d(out["uy"]), _d(out["T"]), _d(out["p"]))
+    return {k: v.reshape(P.ny, P.nx) for k, v in out.items()}

@@ -1,0 +1,451 @@
+/*
+ * pond_oracle.c -- plain FP64 CPU oracle of the particles-on-demand (PonD)
+ * stream-and-collide step of the double-distribution-function BGK model,
+ * total-energy split, D2Q16 lattice.
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library.  It shares no code, header,
+ * table or constant with the GPU library, and the GPU library never calls it.
+ *
+ * Source: S. A. Hosseini, A. Bhadauria, I. V. Karlin, "Probing double
+ * distribution function models in the lattice Boltzmann method for highly
+ * compressible flows", arXiv:2405.11489.  Each function cites the passage it
+ * follows.  The step is written the slow, literal way:
+ *   for every destination node, every predictor-corrector iterate, every
+ *   discrete velocity and every stencil node, the stencil node's populations
+ *   are transformed into the iterate's frame (frame transformation, Sec.
+ *   "Frame transformation") and only then weighted by the interpolation kernel
+ *   (Eq. propagationInterpolated).
+ * No blocking, fusion or reordering beyond that.
+ *
+ * Readings of points the paper leaves open (all listed in the design notes):
+ *   - interpolation: Lagrange polynomial stencil; 4 points (cubic) by default,
+ *     3 points (the paper's "2nd-order" stencil) on request;
+ *   - the gather is evaluated at the departure point x - C_i(lambda_bar) dt,
+ *     with C_i in the destination frame;
+ *   - the destination frame is found by a predictor-corrector fixed-point
+ *     iteration (predictor: the node's own frame at time t), which the paper
+ *     takes from its PonD reference; the converged populations are re-projected
+ *     onto the frame of their own moments before the collision;
+ *   - Grad order N = 3 for both f and g;
+ *   - the collision sign is -(1/tau)(f - f^eq) (Eq. boltz_eq carries a
+ *     typo'd sign; the g-equations of Sec. II have the correct one);
+ *   - discrete relaxation time: nu = (tau - 1/2) T, omega = 1/tau;
+ *   - Prandtl number != 1: quasi-equilibrium with the Fourier part of the
+ *     energy flux relaxed at omega_1 = 1/tau_1, tau_1 = 1/2 + (tau - 1/2)/Pr,
+ *     and the viscous-heating part u . P^neq at omega (Sec. II points to the
+ *     quasi-equilibrium approach without giving its form).
+ *
+ * Units: lattice units, dx = dt = 1, r = 1, T_L = 1 (Table I column rT_L).
+ * Layout (oracle only): node n = y*nx + x; populations pop[n*16 + i];
+ * frame lam[n*3 + {0,1,2}] = (u_x, u_y, T).  Velocity i = 4a + b has
+ * c_i = (c_a, c_b) with the D1Q4 abscissae in ascending order.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_ABI 1
+#define Q1 4
+#define Q 16
+
+typedef struct {
+    int nx, ny;
+    int bc_x, bc_y;        /* 0 = periodic, 1 = clamp (zero-gradient) */
+    int interp_points;     /* 4 = cubic Lagrange, 3 = quadratic Lagrange */
+    int pc_max_iter;       /* predictor-corrector iteration cap (>= 1) */
+    double tau;            /* discrete relaxation time, > 1/2 */
+    double prandtl;        /* > 0; 1 = the paper's plain BGK */
+    double gamma;          /* adiabatic exponent, c_v = 1/(gamma - 1) */
+    double pc_tol;         /* predictor-corrector tolerance */
+} oracle_params;
+
+/* status bits per node written by oracle_step */
+#define ORACLE_NONCONVERGED 1
+#define ORACLE_NONPHYSICAL 2
+
+int oracle_abi_version(void) { return ORACLE_ABI; }
+
+/* Table I, row D1Q4 (rT_L = 1): abscissae +-sqrt(3 -+ sqrt 6) with weights
+ * (3 +- sqrt 6)/12, the inner pair carrying the larger weight. */
+void oracle_lattice_1d(double c[Q1], double w[Q1])
+{
+    double s6 = sqrt(6.0);
+    double c_in = sqrt(3.0 - s6), c_out = sqrt(3.0 + s6);
+    double w_in = (3.0 + s6) / 12.0, w_out = (3.0 - s6) / 12.0;
+    c[0] = -c_out; c[1] = -c_in; c[2] = c_in; c[3] = c_out;
+    w[0] = w_out;  w[1] = w_in;  w[2] = w_in; w[3] = w_out;
+}
+
+/* Table I, D2Q16 = D1Q4 x D1Q4: velocity i = 4a + b. */
+void oracle_lattice_2d(double cx[Q], double cy[Q], double w[Q])
+{
+    double c[Q1], w1[Q1];
+    oracle_lattice_1d(c, w1);
+    for (int a = 0; a < Q1; a++)
+        for (int b = 0; b < Q1; b++) {
+            cx[4 * a + b] = c[a];
+            cy[4 * a + b] = c[b];
+            w[4 * a + b] = w1[a] * w1[b];
+        }
+}
+
+static double kron(int a, int b) { return a == b ? 1.0 : 0.0; }
+
+/*
+ * Frame transformation M_{lam_src -> lam_dst} (Sec. "Frame transformation").
+ *   1. Lab-frame moments up to order three of the populations, with the
+ *      particle velocities of the source frame C_i = sqrt(T_src) c_i + u_src
+ *      (Eq. genericMomentUptoO3).
+ *   2. Grad coefficients a_0..a_3 in the destination frame (the four equations
+ *      that follow Eq. gradGeneralTransform), with theta = T_dst / T_L and the
+ *      overline read as the sum over the distinct index permutations.
+ *   3. Populations f_i = w_i sum_{n<=3} (1/n!) a_(n) : H_(n)(c_i)
+ *      (Eq. gradGeneralTransform; with rT_L = 1 the normalisation is 1/n!).
+ * Full rank-2 and rank-3 tensors are used, contracted index by index.
+ * out may alias pop.
+ */
+void oracle_transform(const double *pop, const double *lam_src, const double *lam_dst, double *out)
+{
+    double cx[Q], cy[Q], w[Q];
+    oracle_lattice_2d(cx, cy, w);
+
+    double M0 = 0.0, M1[2] = {0.0, 0.0}, M2[2][2] = {{0.0}}, M3[2][2][2] = {{{0.0}}};
+    double sTs = sqrt(lam_src[2]);
+    for (int i = 0; i < Q; i++) {
+        double V[2] = {sTs * cx[i] + lam_src[0], sTs * cy[i] + lam_src[1]};
+        M0 += pop[i];
+        for (int a = 0; a < 2; a++) {
+            M1[a] += pop[i] * V[a];
+            for (int b = 0; b < 2; b++) {
+                M2[a][b] += pop[i] * V[a] * V[b];
+                for (int g = 0; g < 2; g++)
+                    M3[a][b][g] += pop[i] * V[a] * V[b] * V[g];
+            }
+        }
+    }
+
+    double th = lam_dst[2];
+    double sq = sqrt(th);
+    double u[2] = {lam_dst[0], lam_dst[1]};
+    double a0 = M0, a1[2], a2[2][2], a3[2][2][2];
+    for (int a = 0; a < 2; a++)
+        a1[a] = (M1[a] - M0 * u[a]) / sq;
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            a2[a][b] = (M2[a][b] - M0 * th * kron(a, b)
+                        - sq * (u[a] * a1[b] + a1[a] * u[b])
+                        - M0 * u[a] * u[b]) / th;
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            for (int g = 0; g < 2; g++) {
+                double sym_u_S = u[a] * (M0 * kron(b, g) + a2[b][g])
+                               + u[b] * (M0 * kron(a, g) + a2[a][g])
+                               + u[g] * (M0 * kron(a, b) + a2[a][b]);
+                double sym_a1_I = a1[a] * kron(b, g) + a1[b] * kron(a, g) + a1[g] * kron(a, b);
+                double sym_a1_uu = a1[a] * u[b] * u[g] + a1[b] * u[a] * u[g] + a1[g] * u[a] * u[b];
+                a3[a][b][g] = (M3[a][b][g] - th * sym_u_S - th * sq * sym_a1_I
+                               - sq * sym_a1_uu - M0 * u[a] * u[b] * u[g]) / (th * sq);
+            }
+
+    double res[Q];
+    for (int i = 0; i < Q; i++) {
+        double c[2] = {cx[i], cy[i]};
+        double s = a0;
+        for (int a = 0; a < 2; a++)
+            s += a1[a] * c[a];
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++)
+                s += 0.5 * a2[a][b] * (c[a] * c[b] - kron(a, b));
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++)
+                for (int g = 0; g < 2; g++) {
+                    double H3 = c[a] * c[b] * c[g]
+                              - (c[a] * kron(b, g) + c[b] * kron(a, g) + c[g] * kron(a, b));
+                    s += a3[a][b][g] * H3 / 6.0;
+                }
+        res[i] = w[i] * s;
+    }
+    memcpy(out, res, sizeof res);
+}
+
+/*
+ * Local equilibria in the frame (u, T) (Sec. "Discrete velocity solver ...:
+ * PonD"): f_i^eq = rho w_i, and the total-energy-split g^eq of Sec. II,
+ * g^eq = (U'/rho + v^2/2) f^eq with v -> C_i = sqrt(T) c_i + u and
+ * U' = U - rho D T / 2 = rho T (c_v - 1) for D = 2, c_v = 1/(gamma - 1).
+ */
+void oracle_equilibrium(double rho, double ux, double uy, double T, double gamma,
+                        double *feq, double *geq)
+{
+    double cx[Q], cy[Q], w[Q];
+    oracle_lattice_2d(cx, cy, w);
+    double cv = 1.0 / (gamma - 1.0);
+    double sT = sqrt(T);
+    for (int i = 0; i < Q; i++) {
+        double Cx = sT * cx[i] + ux, Cy = sT * cy[i] + uy;
+        feq[i] = rho * w[i];
+        geq[i] = w[i] * (rho * (cv - 1.0) * T + 0.5 * rho * (Cx * Cx + Cy * Cy));
+    }
+}
+
+/*
+ * BGK collision of f and g in the frame lam = (u, T) of their own moments.
+ * f*_i = f_i + omega (f_i^eq - f_i) with omega = 1/tau.
+ * Pr = 1: g*_i = g_i + omega (g_i^eq - g_i), the paper's model.
+ * Pr != 1 (quasi-equilibrium reading): with P^neq = sum_i C_i C_i (f_i - f_i^eq)
+ * and dq = u . P^neq, g^qe_i = g^eq_i + w_i (c_i . dq)/sqrt(T) carries the
+ * equilibrium energy flux plus the viscous-heating flux; then
+ * g*_i = g_i + omega_1 (g^qe_i - g_i) + omega (g^eq_i - g^qe_i).
+ * The Fourier part of the energy flux relaxes at omega_1, the viscous-heating
+ * part at omega; the zeroth moment (total energy) is untouched by either.
+ */
+void oracle_collide(const double *ft, const double *gt, const double *lam,
+                    double tau, double prandtl, double gamma, double *fo, double *go)
+{
+    double cx[Q], cy[Q], w[Q], feq[Q], geq[Q];
+    oracle_lattice_2d(cx, cy, w);
+    double rho = 0.0;
+    for (int i = 0; i < Q; i++)
+        rho += ft[i];
+    double ux = lam[0], uy = lam[1], T = lam[2];
+    oracle_equilibrium(rho, ux, uy, T, gamma, feq, geq);
+    double omega = 1.0 / tau;
+    double fin[Q], gin[Q];
+    memcpy(fin, ft, sizeof fin);
+    memcpy(gin, gt, sizeof gin);
+    for (int i = 0; i < Q; i++)
+        fo[i] = fin[i] + omega * (feq[i] - fin[i]);
+    if (prandtl == 1.0) {
+        for (int i = 0; i < Q; i++)
+            go[i] = gin[i] + omega * (geq[i] - gin[i]);
+        return;
+    }
+    double tau1 = 0.5 + (tau - 0.5) / prandtl;
+    double omega1 = 1.0 / tau1;
+    double sT = sqrt(T);
+    double P[2][2] = {{0.0}};
+    for (int i = 0; i < Q; i++) {
+        double C[2] = {sT * cx[i] + ux, sT * cy[i] + uy};
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++)
+                P[a][b] += C[a] * C[b] * (fin[i] - feq[i]);
+    }
+    double u[2] = {ux, uy};
+    double dq[2];
+    for (int a = 0; a < 2; a++)
+        dq[a] = u[0] * P[0][a] + u[1] * P[1][a];
+    for (int i = 0; i < Q; i++) {
+        double gqe = geq[i] + w[i] * (cx[i] * dq[0] + cy[i] * dq[1]) / sT;
+        go[i] = gin[i] + omega1 * (gqe - gin[i]) + omega * (geq[i] - gqe);
+    }
+}
+
+/*
+ * Lagrange interpolation stencil for a departure coordinate y (in node
+ * units).  npts = 4: nodes floor(y)-1 .. floor(y)+2 (cubic).  npts = 3: nodes
+ * m-1, m, m+1 with m = floor(y + 1/2) (quadratic, ties to the upper node).
+ * The weights are the Lagrange basis polynomials, written as the textbook
+ * product prod_{m != j} (y - y_m)/(y_j - y_m).  *base receives the first node.
+ */
+int oracle_lagrange(int npts, double y, int *base, double *wts)
+{
+    int first;
+    if (npts == 4)
+        first = (int)floor(y) - 1;
+    else if (npts == 3)
+        first = (int)floor(y + 0.5) - 1;
+    else
+        return -1;
+    for (int j = 0; j < npts; j++) {
+        double l = 1.0;
+        for (int m = 0; m < npts; m++)
+            if (m != j)
+                l *= (y - (double)(first + m)) / (double)(j - m);
+        wts[j] = l;
+    }
+    *base = first;
+    return 0;
+}
+
+static int node_index(int i, int n, int bc)
+{
+    if (bc == 0) {
+        int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+/*
+ * Streaming with interpolated reconstruction, gather form
+ * (Eq. propagationInterpolated): for each velocity i, the departure point is
+ * y_i = x - C_i(lam_bar) dt (dt = 1), and
+ *   {f_i, g_i}(x) = sum_s W(y_i - x_s) [M_{lam_s -> lam_bar} {f, g}(x_s)]_i,
+ * every stencil node transformed from its own frame lam_s.
+ */
+static void gather(const oracle_params *P, const double *f, const double *g, const double *lam,
+                   int x, int y, const double *lam_bar, double *ft, double *gt)
+{
+    double cx[Q], cy[Q], w[Q];
+    oracle_lattice_2d(cx, cy, w);
+    int np = P->interp_points;
+    double sT = sqrt(lam_bar[2]);
+    double tf[Q], tg[Q], wx[4], wy[4];
+    for (int i = 0; i < Q; i++) {
+        double Cx = sT * cx[i] + lam_bar[0];
+        double Cy = sT * cy[i] + lam_bar[1];
+        double yx = (double)x - Cx, yy = (double)y - Cy;
+        int bx, by;
+        oracle_lagrange(np, yx, &bx, wx);
+        oracle_lagrange(np, yy, &by, wy);
+        double sf = 0.0, sg = 0.0;
+        for (int sy = 0; sy < np; sy++) {
+            int jy = node_index(by + sy, P->ny, P->bc_y);
+            for (int sx = 0; sx < np; sx++) {
+                int jx = node_index(bx + sx, P->nx, P->bc_x);
+                long s = (long)jy * P->nx + jx;
+                oracle_transform(f + Q * s, lam + 3 * s, lam_bar, tf);
+                oracle_transform(g + Q * s, lam + 3 * s, lam_bar, tg);
+                double W = wx[sx] * wy[sy];
+                sf += W * tf[i];
+                sg += W * tg[i];
+            }
+        }
+        ft[i] = sf;
+        gt[i] = sg;
+    }
+}
+
+/*
+ * Conserved moments of (f, g) living in frame lam (Sec. II, density and
+ * momentum of f, total energy E = sum g for the total-energy split) and the
+ * frame they imply: u = j/rho, T = (E - |j|^2/(2 rho)) / (rho c_v).
+ */
+static void conserved(const double *ft, const double *gt, const double *lam, double cv,
+                      double *rho, double *jx, double *jy, double *E, double *lam_new)
+{
+    double cx[Q], cy[Q], w[Q];
+    oracle_lattice_2d(cx, cy, w);
+    double sT = sqrt(lam[2]);
+    double r = 0.0, px = 0.0, py = 0.0, e = 0.0;
+    for (int i = 0; i < Q; i++) {
+        r += ft[i];
+        px += ft[i] * (sT * cx[i] + lam[0]);
+        py += ft[i] * (sT * cy[i] + lam[1]);
+        e += gt[i];
+    }
+    *rho = r; *jx = px; *jy = py; *E = e;
+    lam_new[0] = px / r;
+    lam_new[1] = py / r;
+    lam_new[2] = (e - (px * px + py * py) / (2.0 * r)) / (r * cv);
+}
+
+/*
+ * One time step for every node, reading only the time-t state (Jacobi).
+ * Per destination node:
+ *   lam^0 = its own frame at time t;  for k = 0, 1, ...:
+ *     gather (f~, g~) in lam^k; lam^{k+1} = frame of their conserved moments;
+ *     stop when max(|u^{k+1} - u^k|_inf / sqrt(T^{k+1}), |T^{k+1} - T^k| / T^{k+1})
+ *     <= pc_tol, or after pc_max_iter gathers (node counted non-converged);
+ *   re-project (f~, g~) from the last gather frame onto lam* = lam^{k+1};
+ *   collide in lam*; store f*, g*, lam*.
+ * iters[n] receives the number of gathers, status[n] the ORACLE_* bits.
+ * Returns the number of non-physical nodes (rho <= 0, T <= 0 or non-finite).
+ */
+int oracle_step(const oracle_params *P, const double *f, const double *g, const double *lam,
+                double *fo, double *go, double *lamo, int *iters, int *status)
+{
+    long N = (long)P->nx * P->ny;
+    double cv = 1.0 / (P->gamma - 1.0);
+    int nbad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nbad)
+    for (long n = 0; n < N; n++) {
+        int x = (int)(n % P->nx), y = (int)(n / P->nx);
+        double lg[3] = {lam[3 * n], lam[3 * n + 1], lam[3 * n + 2]};
+        double ln[3] = {lg[0], lg[1], lg[2]};
+        double ft[Q], gt[Q];
+        int k, conv = 0, bad = 0, used = 0;
+        for (k = 0; k < P->pc_max_iter; k++) {
+            double rho, jx, jy, E;
+            gather(P, f, g, lam, x, y, lg, ft, gt);
+            conserved(ft, gt, lg, cv, &rho, &jx, &jy, &E, ln);
+            used = k + 1;
+            if (!(rho > 0.0) || !(ln[2] > 0.0) || !isfinite(ln[0]) || !isfinite(ln[1]) ||
+                !isfinite(ln[2]) || !isfinite(E)) {
+                bad = 1;
+                break;
+            }
+            double du = fmax(fabs(ln[0] - lg[0]), fabs(ln[1] - lg[1])) / sqrt(ln[2]);
+            double dT = fabs(ln[2] - lg[2]) / ln[2];
+            if (fmax(du, dT) <= P->pc_tol) {
+                conv = 1;
+                break;
+            }
+            if (k + 1 < P->pc_max_iter)
+                memcpy(lg, ln, sizeof lg);
+        }
+        iters[n] = used;
+        status[n] = (conv ? 0 : ORACLE_NONCONVERGED) | (bad ? ORACLE_NONPHYSICAL : 0);
+        if (bad) {
+            nbad += 1;
+            for (int i = 0; i < Q; i++) {
+                fo[Q * n + i] = NAN;
+                go[Q * n + i] = NAN;
+            }
+            lamo[3 * n] = lamo[3 * n + 1] = lamo[3 * n + 2] = NAN;
+            continue;
+        }
+        oracle_transform(ft, lg, ln, ft);
+        oracle_transform(gt, lg, ln, gt);
+        oracle_collide(ft, gt, ln, P->tau, P->prandtl, P->gamma, fo + Q * n, go + Q * n);
+        lamo[3 * n] = ln[0];
+        lamo[3 * n + 1] = ln[1];
+        lamo[3 * n + 2] = ln[2];
+    }
+    return nbad;
+}
+
+/*
+ * Initial state: equilibrium populations in each node's own frame
+ * (f_i = rho w_i, g_i = g_i^eq), frame = (u, T).  Returns the number of
+ * rejected nodes (rho <= 0, T <= 0 or non-finite input); nothing is written
+ * for those.
+ */
+int oracle_init(long N, const double *rho, const double *ux, const double *uy, const double *T,
+                double gamma, double *f, double *g, double *lam)
+{
+    int nbad = 0;
+    for (long n = 0; n < N; n++) {
+        if (!(rho[n] > 0.0) || !(T[n] > 0.0) || !isfinite(rho[n]) || !isfinite(T[n]) ||
+            !isfinite(ux[n]) || !isfinite(uy[n])) {
+            nbad++;
+            continue;
+        }
+        oracle_equilibrium(rho[n], ux[n], uy[n], T[n], gamma, f + Q * n, g + Q * n);
+        lam[3 * n] = ux[n];
+        lam[3 * n + 1] = uy[n];
+        lam[3 * n + 2] = T[n];
+    }
+    return nbad;
+}
+
+/*
+ * Macroscopic fields from the stored state (Sec. II): rho = sum f,
+ * rho u = sum f C_i, E = sum g, T = (E - rho |u|^2 / 2)/(rho c_v), p = rho T.
+ */
+void oracle_moments(long N, const double *f, const double *g, const double *lam, double gamma,
+                    double *rho, double *ux, double *uy, double *T, double *p)
+{
+    double cv = 1.0 / (gamma - 1.0);
+    for (long n = 0; n < N; n++) {
+        double r, jx, jy, E, ln[3];
+        conserved(f + Q * n, g + Q * n, lam + 3 * n, cv, &r, &jx, &jy, &E, ln);
+        rho[n] = r;
+        ux[n] = ln[0];
+        uy[n] = ln[1];
+        T[n] = ln[2];
+        if (p)
+            p[n] = r * ln[2];
+    }
+}
