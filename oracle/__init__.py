@@ -50,6 +50,7 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         L.oracle_abi_version.restype = ctypes.c_int
+        L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_lattice_1d.argtypes = [dp, dp]
         L.oracle_lattice_2d.argtypes = [dp, dp, dp]
         L.oracle_transform.argtypes = [dp, dp, dp, dp]
@@ -60,6 +61,10 @@ def lib():
         L.oracle_lagrange.restype = ctypes.c_int
         L.oracle_step.argtypes = [ctypes.POINTER(Params), dp, dp, dp, dp, dp, dp, ip, ip]
         L.oracle_step.restype = ctypes.c_int
+        lp = ctypes.POINTER(ctypes.c_long)
+        L.oracle_step_nodes.argtypes = [ctypes.POINTER(Params), dp, dp, dp, ctypes.c_long, lp,
+                                        dp, dp, dp, ip, ip]
+        L.oracle_step_nodes.restype = ctypes.c_int
         L.oracle_init.argtypes = [ctypes.c_long, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp]
         L.oracle_init.restype = ctypes.c_int
         L.oracle_moments.argtypes = [ctypes.c_long, dp, dp, dp, ctypes.c_double,
@@ -83,6 +88,11 @@ def _f64(a, shape=None):
     if shape is not None:
         a = a.reshape(shape)
     return a
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().oracle_num_threads())
 
 
 def lattice_1d():
@@ -179,6 +189,20 @@ def step(P: Params, s: State, nsteps: int = 1):
         if bad:
             break
     return cur, StepStats(iters.copy(), status.copy(), tot, nonc, nbad)
+
+
+def step_nodes(P: Params, s: State, nodes):
+    """One step evaluated only at the listed node indices (reading the full
+    state).  Returns (f (k,16), g (k,16), lam (k,3), iters, status)."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    k = len(nodes)
+    fo, go, lo = np.zeros((k, 16)), np.zeros((k, 16)), np.zeros((k, 3))
+    iters = np.zeros(k, dtype=np.int32)
+    status = np.zeros(k, dtype=np.int32)
+    lib().oracle_step_nodes(ctypes.byref(P), _d(s.f), _d(s.g), _d(s.lam), k,
+                            nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                            _d(fo), _d(go), _d(lo), _i(iters), _i(status))
+    return fo, go, lo, iters, status
 
 
 def moments(P: Params, s: State):

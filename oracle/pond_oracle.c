@@ -44,6 +44,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORACLE_ABI 1
 #define Q1 4
@@ -65,6 +68,16 @@ typedef struct {
 #define ORACLE_NONPHYSICAL 2
 
 int oracle_abi_version(void) { return ORACLE_ABI; }
+
+/* Threads the OpenMP loops of this library use. */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* Table I, row D1Q4 (rT_L = 1): abscissae +-sqrt(3 -+ sqrt 6) with weights
  * (3 +- sqrt 6)/12, the inner pair carrying the larger weight. */
@@ -342,67 +355,87 @@ static void conserved(const double *ft, const double *gt, const double *lam, dou
 }
 
 /*
- * One time step for every node, reading only the time-t state (Jacobi).
- * Per destination node:
+ * One time step of destination node n, reading only the time-t state (Jacobi).
  *   lam^0 = its own frame at time t;  for k = 0, 1, ...:
  *     gather (f~, g~) in lam^k; lam^{k+1} = frame of their conserved moments;
  *     stop when max(|u^{k+1} - u^k|_inf / sqrt(T^{k+1}), |T^{k+1} - T^k| / T^{k+1})
  *     <= pc_tol, or after pc_max_iter gathers (node counted non-converged);
  *   re-project (f~, g~) from the last gather frame onto lam* = lam^{k+1};
- *   collide in lam*; store f*, g*, lam*.
- * iters[n] receives the number of gathers, status[n] the ORACLE_* bits.
- * Returns the number of non-physical nodes (rho <= 0, T <= 0 or non-finite).
+ *   collide in lam*; write f*, g*, lam* (16, 16 and 3 values).
+ * *iters receives the number of gathers, *status the ORACLE_* bits.
+ * Returns 1 if the node is non-physical (rho <= 0, T <= 0 or non-finite; the
+ * outputs are then NaN), else 0.
  */
+static int node_step(const oracle_params *P, const double *f, const double *g, const double *lam,
+                     long n, double *fo, double *go, double *lamo, int *iters, int *status)
+{
+    double cv = 1.0 / (P->gamma - 1.0);
+    int x = (int)(n % P->nx), y = (int)(n / P->nx);
+    double lg[3] = {lam[3 * n], lam[3 * n + 1], lam[3 * n + 2]};
+    double ln[3] = {lg[0], lg[1], lg[2]};
+    double ft[Q], gt[Q];
+    int k, conv = 0, bad = 0, used = 0;
+    for (k = 0; k < P->pc_max_iter; k++) {
+        double rho, jx, jy, E;
+        gather(P, f, g, lam, x, y, lg, ft, gt);
+        conserved(ft, gt, lg, cv, &rho, &jx, &jy, &E, ln);
+        used = k + 1;
+        if (!(rho > 0.0) || !(ln[2] > 0.0) || !isfinite(ln[0]) || !isfinite(ln[1]) ||
+            !isfinite(ln[2]) || !isfinite(E)) {
+            bad = 1;
+            break;
+        }
+        double du = fmax(fabs(ln[0] - lg[0]), fabs(ln[1] - lg[1])) / sqrt(ln[2]);
+        double dT = fabs(ln[2] - lg[2]) / ln[2];
+        if (fmax(du, dT) <= P->pc_tol) {
+            conv = 1;
+            break;
+        }
+        if (k + 1 < P->pc_max_iter)
+            memcpy(lg, ln, sizeof lg);
+    }
+    *iters = used;
+    *status = (conv ? 0 : ORACLE_NONCONVERGED) | (bad ? ORACLE_NONPHYSICAL : 0);
+    if (bad) {
+        for (int i = 0; i < Q; i++)
+            fo[i] = go[i] = NAN;
+        lamo[0] = lamo[1] = lamo[2] = NAN;
+        return 1;
+    }
+    oracle_transform(ft, lg, ln, ft);
+    oracle_transform(gt, lg, ln, gt);
+    oracle_collide(ft, gt, ln, P->tau, P->prandtl, P->gamma, fo, go);
+    lamo[0] = ln[0];
+    lamo[1] = ln[1];
+    lamo[2] = ln[2];
+    return 0;
+}
+
+/* One step for every node (node-major outputs).  Returns the number of
+ * non-physical nodes. */
 int oracle_step(const oracle_params *P, const double *f, const double *g, const double *lam,
                 double *fo, double *go, double *lamo, int *iters, int *status)
 {
     long N = (long)P->nx * P->ny;
-    double cv = 1.0 / (P->gamma - 1.0);
     int nbad = 0;
-#pragma omp parallel for schedule(static) reduction(+ : nbad)
-    for (long n = 0; n < N; n++) {
-        int x = (int)(n % P->nx), y = (int)(n / P->nx);
-        double lg[3] = {lam[3 * n], lam[3 * n + 1], lam[3 * n + 2]};
-        double ln[3] = {lg[0], lg[1], lg[2]};
-        double ft[Q], gt[Q];
-        int k, conv = 0, bad = 0, used = 0;
-        for (k = 0; k < P->pc_max_iter; k++) {
-            double rho, jx, jy, E;
-            gather(P, f, g, lam, x, y, lg, ft, gt);
-            conserved(ft, gt, lg, cv, &rho, &jx, &jy, &E, ln);
-            used = k + 1;
-            if (!(rho > 0.0) || !(ln[2] > 0.0) || !isfinite(ln[0]) || !isfinite(ln[1]) ||
-                !isfinite(ln[2]) || !isfinite(E)) {
-                bad = 1;
-                break;
-            }
-            double du = fmax(fabs(ln[0] - lg[0]), fabs(ln[1] - lg[1])) / sqrt(ln[2]);
-            double dT = fabs(ln[2] - lg[2]) / ln[2];
-            if (fmax(du, dT) <= P->pc_tol) {
-                conv = 1;
-                break;
-            }
-            if (k + 1 < P->pc_max_iter)
-                memcpy(lg, ln, sizeof lg);
-        }
-        iters[n] = used;
-        status[n] = (conv ? 0 : ORACLE_NONCONVERGED) | (bad ? ORACLE_NONPHYSICAL : 0);
-        if (bad) {
-            nbad += 1;
-            for (int i = 0; i < Q; i++) {
-                fo[Q * n + i] = NAN;
-                go[Q * n + i] = NAN;
-            }
-            lamo[3 * n] = lamo[3 * n + 1] = lamo[3 * n + 2] = NAN;
-            continue;
-        }
-        oracle_transform(ft, lg, ln, ft);
-        oracle_transform(gt, lg, ln, gt);
-        oracle_collide(ft, gt, ln, P->tau, P->prandtl, P->gamma, fo + Q * n, go + Q * n);
-        lamo[3 * n] = ln[0];
-        lamo[3 * n + 1] = ln[1];
-        lamo[3 * n + 2] = ln[2];
-    }
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : nbad)
+    for (long n = 0; n < N; n++)
+        nbad += node_step(P, f, g, lam, n, fo + Q * n, go + Q * n, lamo + 3 * n, iters + n,
+                          status + n);
+    return nbad;
+}
+
+/* One step for the listed nodes only (outputs packed in list order), reading
+ * the full time-t state; lets a large state be checked node by node. */
+int oracle_step_nodes(const oracle_params *P, const double *f, const double *g, const double *lam,
+                      long count, const long *nodes, double *fo, double *go, double *lamo,
+                      int *iters, int *status)
+{
+    int nbad = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : nbad)
+    for (long k = 0; k < count; k++)
+        nbad += node_step(P, f, g, lam, nodes[k], fo + Q * k, go + Q * k, lamo + 3 * k, iters + k,
+                          status + k);
     return nbad;
 }
 

@@ -11,6 +11,6 @@ __all__ = ["workloads", "pond"]
 
 def __getattr__(name):
     if name == "pond":
-        from . import pond
-        return pond
+        import importlib
+        return importlib.import_module(__name__ + ".pond")
     raise AttributeError(name)

@@ -1,0 +1,649 @@
+// pond_api.hip -- host implementation of the C ABI declared in include/pond.h.
+//
+// A context owns (or adopts) one device allocation laid out as
+//   [state buffer 0 | state buffer 1 | moment planes | counters | scratch]
+// each region 256-byte aligned.  A state buffer holds 16 f planes and 16 g
+// planes of P (float or double) followed by the frame planes u_x, u_y, T
+// (double).  Steps ping-pong between the two buffers (Jacobi: every node of
+// step t+1 reads only the state of step t).  The moment planes are rewritten
+// at the start of every step and double as staging space for host-pointer
+// transfers outside steps.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pond.h"
+#include "pond_internal.h"
+
+using namespace pond;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pond_status fail(pond_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+pond_status fail(pond_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+pond_status hip_fail(hipError_t e, const char *what) {
+    return fail(POND_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t pop_bytes;    // one set of 16 planes
+    size_t frame_bytes;  // one frame plane
+    size_t buf_bytes;    // one state buffer
+    size_t mom_bytes;    // 20 moment planes
+    size_t cnt_off, scratch_off, total;
+};
+
+constexpr int kScratchDoubles = 3 * 256;
+
+Layout layout_for(long long N, size_t psize) {
+    Layout L;
+    L.pop_bytes = align_up(size_t(N) * 16 * psize);
+    L.frame_bytes = align_up(size_t(N) * sizeof(double));
+    L.buf_bytes = 2 * L.pop_bytes + 3 * L.frame_bytes;
+    L.mom_bytes = align_up(size_t(N) * 20 * psize);
+    L.cnt_off = 2 * L.buf_bytes + L.mom_bytes;
+    L.scratch_off = L.cnt_off + align_up(sizeof(DevCounters));
+    L.total = L.scratch_off + align_up(kScratchDoubles * sizeof(double));
+    return L;
+}
+
+pond_status validate(const pond_params *p) {
+    if (!p) return fail(POND_ERR_INVALID_ARG, "params is NULL");
+    if (p->struct_size != sizeof(pond_params))
+        return fail(POND_ERR_INVALID_ARG, "params.struct_size %u != %zu (ABI mismatch)",
+                    p->struct_size, sizeof(pond_params));
+    if (p->nx < 1 || p->ny < 1) return fail(POND_ERR_INVALID_ARG, "nx, ny must be >= 1");
+    if ((long long)p->nx * p->ny > 0x7fffffffll)
+        return fail(POND_ERR_INVALID_ARG, "nx * ny must stay below 2^31");
+    if ((p->bc_x != POND_BC_PERIODIC && p->bc_x != POND_BC_CLAMP) ||
+        (p->bc_y != POND_BC_PERIODIC && p->bc_y != POND_BC_CLAMP))
+        return fail(POND_ERR_INVALID_ARG, "bc_x / bc_y must be POND_BC_PERIODIC or POND_BC_CLAMP");
+    if (p->lattice != POND_LATTICE_D2Q16) {
+        if (p->lattice == 25 || p->lattice == 9)
+            return fail(POND_ERR_UNSUPPORTED, "lattice %d is not implemented (D2Q16 only)",
+                        p->lattice);
+        return fail(POND_ERR_INVALID_ARG, "unknown lattice %d", p->lattice);
+    }
+    if (p->interp_points != 3 && p->interp_points != 4)
+        return fail(POND_ERR_INVALID_ARG, "interp_points must be 3 or 4");
+    if (p->split != POND_SPLIT_TOTAL) {
+        if (p->split == POND_SPLIT_INTERNAL || p->split == POND_SPLIT_NONTRANS)
+            return fail(POND_ERR_UNSUPPORTED, "only the total-energy split is implemented");
+        return fail(POND_ERR_INVALID_ARG, "unknown split %d", p->split);
+    }
+    if (p->precision != POND_PREC_FP64 && p->precision != POND_PREC_FP32)
+        return fail(POND_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau))
+        return fail(POND_ERR_INVALID_ARG, "tau must be finite and > 1/2");
+    if (!(p->prandtl > 0.0) || !std::isfinite(p->prandtl))
+        return fail(POND_ERR_INVALID_ARG, "prandtl must be finite and > 0");
+    if (!(p->gamma > 1.0) || !(p->gamma <= 2.0))
+        return fail(POND_ERR_INVALID_ARG, "gamma must lie in (1, 2]");
+    if (!std::isfinite(p->pc_tol)) return fail(POND_ERR_INVALID_ARG, "pc_tol must be finite");
+    if (p->pc_max_iter > 10000) return fail(POND_ERR_INVALID_ARG, "pc_max_iter > 10000");
+    return POND_OK;
+}
+
+bool is_device_pointer(const void *ptr) {
+    if (!ptr) return false;
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+struct pond_ctx {
+    pond_params p;
+    size_t psize;
+    Layout L;
+    hipStream_t stream;
+    bool own_stream;
+    char *mem;
+    bool own_mem;
+    DevState buf[2];
+    int cur;
+    void *mom;
+    DevCounters *cnt;
+    double *scratch;
+    StepArgs args;
+    bool initialized;
+    bool failed;
+    long long steps;
+    bool profiling;
+    std::vector<hipEvent_t> prof_events;  // 3 per timed step
+    double prof_prepass_ms, prof_step_ms;
+    long long prof_launches;
+};
+
+namespace {
+
+void fill_args(pond_ctx *c) {
+    const pond_params &p = c->p;
+    StepArgs &a = c->args;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.bc_x = p.bc_x;
+    a.bc_y = p.bc_y;
+    a.N = (long long)p.nx * p.ny;
+    a.interp_points = p.interp_points;
+    a.pc_max_iter = p.pc_max_iter > 0 ? p.pc_max_iter : 32;
+    a.pc_tol = p.pc_tol > 0 ? p.pc_tol : (p.precision == POND_PREC_FP64 ? 1e-13 : 1e-6);
+    a.omega = 1.0 / p.tau;
+    const double tau1 = 0.5 + (p.tau - 0.5) / p.prandtl;
+    a.omega1 = 1.0 / tau1;
+    a.unit_prandtl = p.prandtl == 1.0;
+    a.cv = 1.0 / (p.gamma - 1.0);
+    a.uref_x = a.uref_y = 0.0;
+}
+
+bool fp64(const pond_ctx *c) { return c->p.precision == POND_PREC_FP64; }
+
+pond_status check_ctx(const pond_ctx *c, bool need_init) {
+    if (!c) return fail(POND_ERR_INVALID_ARG, "context is NULL");
+    if (need_init && !c->initialized)
+        return fail(POND_ERR_STATE, "context has no state (call pond_init_fields first)");
+    return POND_OK;
+}
+
+pond_status read_counters(pond_ctx *c, DevCounters *out) {
+    hipError_t e = hipMemcpyAsync(out, c->cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counters)");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return POND_OK;
+}
+
+pond_status sync_and_check(pond_ctx *c) {
+    DevCounters h;
+    pond_status s = read_counters(c, &h);
+    if (s != POND_OK) return s;
+    if (h.nonphysical) {
+        c->failed = true;
+        return fail(POND_ERR_NONPHYSICAL, "%llu node-steps produced rho <= 0, T <= 0 or NaN",
+                    (unsigned long long)h.nonphysical);
+    }
+    return POND_OK;
+}
+
+// Copy n doubles from a caller pointer (host or device) into device memory.
+pond_status stage_in(pond_ctx *c, const double *src, double *dst, long long n) {
+    hipError_t e = hipMemcpyAsync(dst, src, size_t(n) * sizeof(double), hipMemcpyDefault, c->stream);
+    return e == hipSuccess ? POND_OK : hip_fail(e, "hipMemcpyAsync(in)");
+}
+
+template <typename P>
+hipError_t launch_init_t(pond_ctx *c, const double *r, const double *ux, const double *uy,
+                         const double *T) {
+    return launch_init<P>(c->args, r, ux, uy, T, c->buf[0], c->cnt, c->stream);
+}
+
+pond_status reset_counters(pond_ctx *c) {
+    hipError_t e = hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), c->stream);
+    return e == hipSuccess ? POND_OK : hip_fail(e, "hipMemsetAsync(counters)");
+}
+
+pond_status set_reference_from_counters(pond_ctx *c) {
+    DevCounters h;
+    pond_status s = read_counters(c, &h);
+    if (s != POND_OK) return s;
+    if (!(h.partial[0] > 0.0)) return fail(POND_ERR_INVALID_ARG, "total mass is not positive");
+    c->args.uref_x = h.partial[1] / h.partial[0];
+    c->args.uref_y = h.partial[2] / h.partial[0];
+    return POND_OK;
+}
+
+}  // namespace
+
+// The entry points below take their C linkage from the declarations in pond.h.
+
+int pond_abi_version(void) { return POND_ABI_VERSION; }
+
+const char *pond_status_string(pond_status s) {
+    switch (s) {
+    case POND_OK: return "ok";
+    case POND_ERR_INVALID_ARG: return "invalid argument";
+    case POND_ERR_UNSUPPORTED: return "unsupported option";
+    case POND_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case POND_ERR_DEVICE: return "device error";
+    case POND_ERR_NONPHYSICAL: return "non-physical state (rho <= 0, T <= 0 or NaN)";
+    case POND_ERR_STATE: return "invalid context state";
+    }
+    return "unknown status";
+}
+
+const char *pond_last_error(void) { return g_last_error.c_str(); }
+
+pond_status pond_params_default(pond_params *p) {
+    if (!p) return fail(POND_ERR_INVALID_ARG, "params is NULL");
+    std::memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(pond_params);
+    p->bc_x = p->bc_y = POND_BC_PERIODIC;
+    p->lattice = POND_LATTICE_D2Q16;
+    p->interp_points = 4;
+    p->split = POND_SPLIT_TOTAL;
+    p->precision = POND_PREC_FP32;
+    p->pc_max_iter = 32;
+    p->tau = 0.6;
+    p->prandtl = 1.0;
+    p->gamma = 1.4;
+    p->pc_tol = 0.0;
+    return POND_OK;
+}
+
+size_t pond_state_bytes(const pond_params *p) {
+    if (validate(p) != POND_OK) return 0;
+    const size_t psize = p->precision == POND_PREC_FP64 ? sizeof(double) : sizeof(float);
+    return layout_for((long long)p->nx * p->ny, psize).total;
+}
+
+pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem,
+                        size_t device_mem_bytes, pond_ctx **out) {
+    if (!out) return fail(POND_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    pond_status s = validate(p);
+    if (s != POND_OK) return s;
+    const size_t psize = p->precision == POND_PREC_FP64 ? sizeof(double) : sizeof(float);
+    const long long N = (long long)p->nx * p->ny;
+    Layout L = layout_for(N, psize);
+    if (device_mem) {
+        if (device_mem_bytes < L.total)
+            return fail(POND_ERR_OUT_OF_MEMORY, "device_mem holds %zu bytes, %zu needed",
+                        device_mem_bytes, L.total);
+        if (reinterpret_cast<uintptr_t>(device_mem) % kAlign)
+            return fail(POND_ERR_INVALID_ARG, "device_mem must be 256-byte aligned");
+    }
+    pond_ctx *c = new (std::nothrow) pond_ctx();
+    if (!c) return fail(POND_ERR_OUT_OF_MEMORY, "host allocation failed");
+    c->p = *p;
+    c->psize = psize;
+    c->L = L;
+    c->own_stream = hip_stream == nullptr;
+    if (c->own_stream) {
+        hipError_t e = hipStreamCreate(&c->stream);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "hipStreamCreate");
+        }
+    } else {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+    }
+    c->own_mem = device_mem == nullptr;
+    if (c->own_mem) {
+        void *m = nullptr;
+        hipError_t e = hipMalloc(&m, L.total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            return fail(POND_ERR_OUT_OF_MEMORY, "hipMalloc(%zu): %s", L.total, hipGetErrorString(e));
+        }
+        c->mem = static_cast<char *>(m);
+    } else {
+        c->mem = static_cast<char *>(device_mem);
+    }
+    for (int b = 0; b < 2; ++b) {
+        char *base = c->mem + b * L.buf_bytes;
+        c->buf[b].f = base;
+        c->buf[b].g = base + L.pop_bytes;
+        c->buf[b].ux = reinterpret_cast<double *>(base + 2 * L.pop_bytes);
+        c->buf[b].uy = reinterpret_cast<double *>(base + 2 * L.pop_bytes + L.frame_bytes);
+        c->buf[b].T = reinterpret_cast<double *>(base + 2 * L.pop_bytes + 2 * L.frame_bytes);
+    }
+    c->mom = c->mem + 2 * L.buf_bytes;
+    c->cnt = reinterpret_cast<DevCounters *>(c->mem + L.cnt_off);
+    c->scratch = reinterpret_cast<double *>(c->mem + L.scratch_off);
+    c->cur = 0;
+    fill_args(c);
+    c->initialized = false;
+    c->failed = false;
+    c->steps = 0;
+    c->profiling = false;
+    c->prof_prepass_ms = c->prof_step_ms = 0.0;
+    c->prof_launches = 0;
+    s = reset_counters(c);
+    if (s != POND_OK) {
+        pond_destroy(c);
+        return s;
+    }
+    *out = c;
+    return POND_OK;
+}
+
+pond_status pond_init_fields(pond_ctx *c, const double *rho, const double *ux, const double *uy,
+                             const double *T) {
+    pond_status s = check_ctx(c, false);
+    if (s != POND_OK) return s;
+    if (!rho || !ux || !uy || !T) return fail(POND_ERR_INVALID_ARG, "field pointer is NULL");
+    const long long N = c->args.N;
+    // stage host inputs in the moment planes (>= 4 N doubles in either precision)
+    double *stg = static_cast<double *>(c->mom);
+    const double *in[4] = {rho, ux, uy, T};
+    const double *dev[4];
+    for (int k = 0; k < 4; ++k) {
+        if (is_device_pointer(in[k])) {
+            dev[k] = in[k];
+        } else {
+            s = stage_in(c, in[k], stg + k * N, N);
+            if (s != POND_OK) return s;
+            dev[k] = stg + k * N;
+        }
+    }
+    c->initialized = false;
+    c->failed = false;
+    c->cur = 0;
+    s = reset_counters(c);
+    if (s != POND_OK) return s;
+    hipError_t e = fp64(c) ? launch_init_t<double>(c, dev[0], dev[1], dev[2], dev[3])
+                           : launch_init_t<float>(c, dev[0], dev[1], dev[2], dev[3]);
+    if (e != hipSuccess) return hip_fail(e, "init kernel");
+    e = launch_mean_velocity(N, dev[0], dev[1], dev[2], c->scratch, kScratchDoubles, c->cnt,
+                             c->stream);
+    if (e != hipSuccess) return hip_fail(e, "mean velocity");
+    DevCounters h;
+    s = read_counters(c, &h);
+    if (s != POND_OK) return s;
+    if (h.init_rejected)
+        return fail(POND_ERR_INVALID_ARG, "%llu nodes with rho <= 0, T <= 0 or non-finite values",
+                    (unsigned long long)h.init_rejected);
+    s = set_reference_from_counters(c);
+    if (s != POND_OK) return s;
+    s = reset_counters(c);
+    if (s != POND_OK) return s;
+    c->steps = 0;
+    c->initialized = true;
+    return POND_OK;
+}
+
+namespace {
+
+template <typename P>
+hipError_t launch_prepass_t(pond_ctx *c, DevState src) {
+    return launch_moments_prepass<P>(c->args, src, static_cast<P *>(c->mom), c->stream);
+}
+
+template <typename P>
+hipError_t launch_step_t(pond_ctx *c, DevState src, DevState dst) {
+    return launch_step<P>(c->args, src, static_cast<const P *>(c->mom), dst, c->cnt, c->stream);
+}
+
+// One step: moment pre-pass on the current buffer, then the step kernel into
+// the other buffer; with profiling on, events bracket both launches.
+hipError_t enqueue_step(pond_ctx *c) {
+    DevState src = c->buf[c->cur], dst = c->buf[c->cur ^ 1];
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    if (c->profiling) {
+        for (int j = 0; j < 3 && e == hipSuccess; ++j) {
+            e = hipEventCreate(&ev[j]);
+            if (e == hipSuccess) c->prof_events.push_back(ev[j]);
+        }
+        if (e == hipSuccess) e = hipEventRecord(ev[0], c->stream);
+    }
+    if (e == hipSuccess) e = fp64(c) ? launch_prepass_t<double>(c, src) : launch_prepass_t<float>(c, src);
+    if (e == hipSuccess && c->profiling) e = hipEventRecord(ev[1], c->stream);
+    if (e == hipSuccess)
+        e = fp64(c) ? launch_step_t<double>(c, src, dst) : launch_step_t<float>(c, src, dst);
+    if (e == hipSuccess && c->profiling) e = hipEventRecord(ev[2], c->stream);
+    return e;
+}
+
+}  // namespace
+
+pond_status pond_step(pond_ctx *c, int64_t nsteps) {
+    pond_status s = check_ctx(c, true);
+    if (s != POND_OK) return s;
+    if (c->failed) return fail(POND_ERR_STATE, "context is in the error state (non-physical)");
+    if (nsteps < 0) return fail(POND_ERR_INVALID_ARG, "nsteps < 0");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        hipError_t e = enqueue_step(c);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        c->cur ^= 1;
+        ++c->steps;
+    }
+    return POND_OK;
+}
+
+pond_status pond_moments(pond_ctx *c, double *rho, double *ux, double *uy, double *T, double *p) {
+    pond_status s = check_ctx(c, true);
+    if (s != POND_OK) return s;
+    const long long N = c->args.N;
+    double *outs[5] = {rho, ux, uy, T, p};
+    double *dev[5];
+    double *stg = static_cast<double *>(c->mom);  // 5 N doubles fit in either precision
+    for (int k = 0; k < 5; ++k)
+        dev[k] = outs[k] ? (is_device_pointer(outs[k]) ? outs[k] : stg + k * N) : nullptr;
+    hipError_t e = fp64(c) ? launch_macro<double>(c->args, c->buf[c->cur], dev[0], dev[1], dev[2],
+                                                  dev[3], dev[4], c->stream)
+                           : launch_macro<float>(c->args, c->buf[c->cur], dev[0], dev[1], dev[2],
+                                                 dev[3], dev[4], c->stream);
+    if (e != hipSuccess) return hip_fail(e, "moments kernel");
+    for (int k = 0; k < 5; ++k)
+        if (outs[k] && dev[k] != outs[k]) {
+            e = hipMemcpyAsync(outs[k], dev[k], size_t(N) * sizeof(double), hipMemcpyDeviceToHost,
+                               c->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(out)");
+        }
+    return sync_and_check(c);
+}
+
+pond_status pond_stats(pond_ctx *c, pond_stats_t *out) {
+    pond_status s = check_ctx(c, false);
+    if (s != POND_OK) return s;
+    if (!out) return fail(POND_ERR_INVALID_ARG, "out is NULL");
+    DevCounters h;
+    s = read_counters(c, &h);
+    if (s != POND_OK) return s;
+    out->steps = c->steps;
+    out->node_updates = c->steps * c->args.N;
+    out->pc_iterations = (int64_t)h.pc_iterations;
+    out->nonconverged = (int64_t)h.nonconverged;
+    out->nonphysical = h.nonphysical ? 1 : 0;
+    out->reserved = 0;
+    if (h.nonphysical) {
+        c->failed = true;
+        return fail(POND_ERR_NONPHYSICAL, "%llu node-steps produced rho <= 0, T <= 0 or NaN",
+                    (unsigned long long)h.nonphysical);
+    }
+    return POND_OK;
+}
+
+pond_status pond_synchronize(pond_ctx *c) {
+    pond_status s = check_ctx(c, false);
+    if (s != POND_OK) return s;
+    return sync_and_check(c);
+}
+
+pond_status pond_export_state(pond_ctx *c, double *f, double *g, double *frame, double *u_ref) {
+    pond_status s = check_ctx(c, true);
+    if (s != POND_OK) return s;
+    if (!f || !g || !frame) return fail(POND_ERR_INVALID_ARG, "output pointer is NULL");
+    const long long N = c->args.N;
+    const bool dev = is_device_pointer(f) && is_device_pointer(g) && is_device_pointer(frame);
+    hipError_t e;
+    if (dev) {
+        e = fp64(c) ? launch_export<double>(c->args, c->buf[c->cur], f, g, frame, c->stream)
+                    : launch_export<float>(c->args, c->buf[c->cur], f, g, frame, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "export kernel");
+    } else {
+        // host destination: temporary device buffer (export is not on the hot path)
+        double *tmp = nullptr;
+        e = hipMalloc(&tmp, size_t(N) * 35 * sizeof(double));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(POND_ERR_OUT_OF_MEMORY, "temporary export buffer");
+        }
+        e = fp64(c) ? launch_export<double>(c->args, c->buf[c->cur], tmp, tmp + 16 * N,
+                                            tmp + 32 * N, c->stream)
+                    : launch_export<float>(c->args, c->buf[c->cur], tmp, tmp + 16 * N, tmp + 32 * N,
+                                           c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(f, tmp, size_t(N) * 16 * sizeof(double), hipMemcpyDefault, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g, tmp + 16 * N, size_t(N) * 16 * sizeof(double), hipMemcpyDefault,
+                               c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(frame, tmp + 32 * N, size_t(N) * 3 * sizeof(double),
+                               hipMemcpyDefault, c->stream);
+        hipError_t e2 = hipStreamSynchronize(c->stream);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return hip_fail(e, "export");
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamSynchronize");
+    }
+    if (u_ref) {
+        u_ref[0] = c->args.uref_x;
+        u_ref[1] = c->args.uref_y;
+    }
+    return sync_and_check(c);
+}
+
+pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, const double *frame,
+                              const double *u_ref) {
+    pond_status s = check_ctx(c, false);
+    if (s != POND_OK) return s;
+    if (!f || !g || !frame) return fail(POND_ERR_INVALID_ARG, "input pointer is NULL");
+    const long long N = c->args.N;
+    const bool dev = is_device_pointer(f) && is_device_pointer(g) && is_device_pointer(frame);
+    double *tmp = nullptr;
+    const double *df = f, *dg = g, *dfr = frame;
+    hipError_t e;
+    if (!dev) {
+        e = hipMalloc(&tmp, size_t(N) * 35 * sizeof(double));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(POND_ERR_OUT_OF_MEMORY, "temporary import buffer");
+        }
+        e = hipMemcpyAsync(tmp, f, size_t(N) * 16 * sizeof(double), hipMemcpyDefault, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(tmp + 16 * N, g, size_t(N) * 16 * sizeof(double), hipMemcpyDefault,
+                               c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(tmp + 32 * N, frame, size_t(N) * 3 * sizeof(double),
+                               hipMemcpyDefault, c->stream);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(c->stream);
+            (void)hipFree(tmp);
+            return hip_fail(e, "import copy");
+        }
+        df = tmp;
+        dg = tmp + 16 * N;
+        dfr = tmp + 32 * N;
+    }
+    c->initialized = false;
+    c->failed = false;
+    c->cur = 0;
+    s = reset_counters(c);
+    if (s == POND_OK) {
+        e = fp64(c) ? launch_import<double>(c->args, df, dg, dfr, c->buf[0], c->stream)
+                    : launch_import<float>(c->args, df, dg, dfr, c->buf[0], c->stream);
+        if (e != hipSuccess) s = hip_fail(e, "import kernel");
+    }
+    if (s == POND_OK) {
+        if (u_ref) {
+            c->args.uref_x = u_ref[0];
+            c->args.uref_y = u_ref[1];
+            e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) s = hip_fail(e, "hipStreamSynchronize");
+        } else {
+            e = fp64(c) ? launch_state_mean_velocity<double>(c->args, c->buf[0], c->scratch,
+                                                             kScratchDoubles, c->cnt, c->stream)
+                        : launch_state_mean_velocity<float>(c->args, c->buf[0], c->scratch,
+                                                            kScratchDoubles, c->cnt, c->stream);
+            s = e == hipSuccess ? set_reference_from_counters(c) : hip_fail(e, "mean velocity");
+        }
+    }
+    if (tmp) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(tmp);
+    }
+    if (s != POND_OK) return s;
+    s = reset_counters(c);
+    if (s != POND_OK) return s;
+    c->steps = 0;
+    c->initialized = true;
+    return POND_OK;
+}
+
+namespace {
+void drop_events(pond_ctx *c) {
+    for (hipEvent_t ev : c->prof_events) (void)hipEventDestroy(ev);
+    c->prof_events.clear();
+}
+}  // namespace
+
+pond_status pond_profile_enable(pond_ctx *c, int enable) {
+    pond_status s = check_ctx(c, false);
+    if (s != POND_OK) return s;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    drop_events(c);
+    c->profiling = enable != 0;
+    c->prof_prepass_ms = c->prof_step_ms = 0.0;
+    c->prof_launches = 0;
+    return POND_OK;
+}
+
+pond_status pond_profile_read(pond_ctx *c, pond_profile_t *out) {
+    pond_status s = check_ctx(c, false);
+    if (s != POND_OK) return s;
+    if (!out) return fail(POND_ERR_INVALID_ARG, "out is NULL");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    for (size_t j = 0; j + 2 < c->prof_events.size(); j += 3) {
+        float a = 0.f, b = 0.f;
+        e = hipEventElapsedTime(&a, c->prof_events[j], c->prof_events[j + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, c->prof_events[j + 1], c->prof_events[j + 2]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        c->prof_prepass_ms += a;
+        c->prof_step_ms += b;
+        ++c->prof_launches;
+    }
+    drop_events(c);
+    out->launches = c->prof_launches;
+    out->prepass_ms = c->prof_prepass_ms;
+    out->step_ms = c->prof_step_ms;
+    return POND_OK;
+}
+
+pond_status pond_destroy(pond_ctx *c) {
+    if (!c) return POND_OK;
+    pond_status s = POND_OK;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) s = hip_fail(e, "hipStreamSynchronize");
+    drop_events(c);
+    if (c->own_mem && c->mem) {
+        e = hipFree(c->mem);
+        if (e != hipSuccess && s == POND_OK) s = hip_fail(e, "hipFree");
+    }
+    if (c->own_stream) {
+        e = hipStreamDestroy(c->stream);
+        if (e != hipSuccess && s == POND_OK) s = hip_fail(e, "hipStreamDestroy");
+    }
+    delete c;
+    return s;
+}
+

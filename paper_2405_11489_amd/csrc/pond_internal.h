@@ -1,0 +1,66 @@
+// pond_internal.h -- host-side interface between the C ABI (pond_api.hip) and
+// the kernel launchers (pond_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pond {
+
+// Device state of one instance.  Population planes: pop[i * N + n] for
+// velocity i and node n = y * nx + x.  Frame planes: double ux, uy, T.
+struct DevState {
+    void *f, *g;          // 16 planes each (float or double)
+    double *ux, *uy, *T;  // frame
+};
+
+// Counters accumulated on the device (64-bit integer atomics only, so the sums
+// do not depend on scheduling).
+struct DevCounters {
+    unsigned long long pc_iterations;
+    unsigned long long nonconverged;
+    unsigned long long nonphysical;
+    unsigned long long init_rejected;
+    double partial[4];  // scratch for deterministic reductions
+};
+
+struct StepArgs {
+    int nx, ny, bc_x, bc_y;
+    long long N;
+    int interp_points;   // 3 or 4
+    int pc_max_iter;
+    double pc_tol;
+    double omega;        // 1 / tau
+    double omega1;       // 1 / tau_1 (Fourier part of the energy flux)
+    int unit_prandtl;    // 1: plain BGK for g
+    double cv;           // 1 / (gamma - 1)
+    double uref_x, uref_y;
+};
+
+template <typename P>
+hipError_t launch_init(const StepArgs &a, const double *rho, const double *ux, const double *uy,
+                       const double *T, DevState st, DevCounters *cnt, hipStream_t s);
+template <typename P>
+hipError_t launch_moments_prepass(const StepArgs &a, DevState st, P *mom, hipStream_t s);
+template <typename P>
+hipError_t launch_step(const StepArgs &a, DevState src, const P *mom, DevState dst, DevCounters *cnt,
+                       hipStream_t s);
+template <typename P>
+hipError_t launch_macro(const StepArgs &a, DevState st, double *rho, double *ux, double *uy,
+                        double *T, double *p, hipStream_t s);
+template <typename P>
+hipError_t launch_export(const StepArgs &a, DevState st, double *f, double *g, double *frame,
+                         hipStream_t s);
+template <typename P>
+hipError_t launch_import(const StepArgs &a, const double *f, const double *g, const double *frame,
+                         DevState st, hipStream_t s);
+// Deterministic mass-weighted mean velocity of (rho, ux, uy) into cnt->partial[0..2]
+// (sum rho, sum rho ux, sum rho uy), fixed summation order.
+hipError_t launch_mean_velocity(long long N, const double *rho, const double *ux, const double *uy,
+                                double *scratch, int scratch_len, DevCounters *cnt, hipStream_t s);
+// Mass-weighted mean velocity of a stored state (populations + frame).
+template <typename P>
+hipError_t launch_state_mean_velocity(const StepArgs &a, DevState st, double *scratch,
+                                      int scratch_len, DevCounters *cnt, hipStream_t s);
+
+}  // namespace pond

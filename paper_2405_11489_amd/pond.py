@@ -1,0 +1,277 @@
+"""Thin ctypes binding of libpond.so (the C ABI of include/pond.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+the library.  Functions keep the C names; pointers may be numpy arrays (host)
+or torch tensors (device memory of the context's GPU).  ``Solver`` wraps one
+context with torch tensors for device memory and streams.
+
+Importing this module loads the library; if it has not been built the import
+fails loudly (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpond.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NONPHYSICAL, ERR_STATE = range(7)
+LATTICE_D2Q16 = 16
+SPLIT_TOTAL, SPLIT_INTERNAL, SPLIT_NONTRANS = 0, 1, 2
+PREC_FP64, PREC_FP32 = 0, 1
+BC_PERIODIC, BC_CLAMP = 0, 1
+ABI_VERSION = 1
+
+EXPORTED = [
+    "pond_abi_version", "pond_params_default", "pond_state_bytes", "pond_create",
+    "pond_init_fields", "pond_step", "pond_moments", "pond_stats", "pond_synchronize",
+    "pond_export_state", "pond_import_state", "pond_destroy", "pond_status_string",
+    "pond_last_error", "pond_profile_enable", "pond_profile_read",
+]
+
+
+class pond_params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("lattice", ctypes.c_int32),
+        ("interp_points", ctypes.c_int32), ("split", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("pc_max_iter", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("prandtl", ctypes.c_double), ("gamma", ctypes.c_double),
+        ("pc_tol", ctypes.c_double),
+    ]
+
+
+class pond_stats_t(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int64), ("node_updates", ctypes.c_int64),
+        ("pc_iterations", ctypes.c_int64), ("nonconverged", ctypes.c_int64),
+        ("nonphysical", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class pond_profile_t(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("prepass_ms", ctypes.c_double),
+                ("step_ms", ctypes.c_double)]
+
+
+class PondError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it first "
+                      "(python -c 'import __graft_entry__ as g; g.build()')")
+
+# torch ships its own HIP runtime under the same SONAME; importing it first makes
+# libpond.so bind to that one, so the process holds a single HIP runtime.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
+_L = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+_L.pond_abi_version.restype = ctypes.c_int
+_L.pond_params_default.argtypes = [ctypes.POINTER(pond_params)]
+_L.pond_state_bytes.argtypes = [ctypes.POINTER(pond_params)]
+_L.pond_state_bytes.restype = ctypes.c_size_t
+_L.pond_create.argtypes = [ctypes.POINTER(pond_params), _vp, _vp, ctypes.c_size_t,
+                           ctypes.POINTER(_vp)]
+_L.pond_init_fields.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_L.pond_step.argtypes = [_vp, ctypes.c_int64]
+_L.pond_moments.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+_L.pond_stats.argtypes = [_vp, ctypes.POINTER(pond_stats_t)]
+_L.pond_synchronize.argtypes = [_vp]
+_L.pond_export_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_L.pond_import_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_L.pond_destroy.argtypes = [_vp]
+_L.pond_profile_enable.argtypes = [_vp, ctypes.c_int]
+_L.pond_profile_read.argtypes = [_vp, ctypes.POINTER(pond_profile_t)]
+_L.pond_status_string.argtypes = [ctypes.c_int]
+_L.pond_status_string.restype = ctypes.c_char_p
+_L.pond_last_error.restype = ctypes.c_char_p
+for _name in EXPORTED:
+    if _name not in ("pond_abi_version", "pond_state_bytes", "pond_status_string",
+                     "pond_last_error"):
+        getattr(_L, _name).restype = ctypes.c_int
+if _L.pond_abi_version() != ABI_VERSION:
+    raise ImportError("libpond.so ABI version mismatch; rebuild")
+
+lib = _L
+
+
+def _check(status):
+    if status != OK:
+        raise PondError(status, _L.pond_last_error().decode() or
+                        _L.pond_status_string(status).decode())
+
+
+def _ptr(a):
+    """Data pointer of a numpy array or torch tensor (contiguous float64), or None."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.float64 or not a.flags.c_contiguous:
+            raise TypeError("numpy arrays must be C-contiguous float64")
+        return a.ctypes.data
+    if hasattr(a, "data_ptr"):
+        import torch
+        if a.dtype != torch.float64 or not a.is_contiguous():
+            raise TypeError("tensors must be contiguous float64")
+        return a.data_ptr()
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+# ------------------------------------------------------------- C names ----
+def pond_abi_version() -> int:
+    return _L.pond_abi_version()
+
+
+def pond_params_default(**overrides) -> pond_params:
+    p = pond_params()
+    _check(_L.pond_params_default(ctypes.byref(p)))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def pond_state_bytes(p: pond_params) -> int:
+    return int(_L.pond_state_bytes(ctypes.byref(p)))
+
+
+def pond_create(p: pond_params, stream=None, device_mem=None, device_mem_bytes=0):
+    ctx = _vp()
+    _check(_L.pond_create(ctypes.byref(p), stream, device_mem, device_mem_bytes,
+                          ctypes.byref(ctx)))
+    return ctx
+
+
+def pond_init_fields(ctx, rho, ux, uy, T):
+    _check(_L.pond_init_fields(ctx, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T)))
+
+
+def pond_step(ctx, nsteps: int):
+    _check(_L.pond_step(ctx, int(nsteps)))
+
+
+def pond_moments(ctx, rho=None, ux=None, uy=None, T=None, p=None):
+    _check(_L.pond_moments(ctx, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T), _ptr(p)))
+
+
+def pond_stats(ctx) -> pond_stats_t:
+    s = pond_stats_t()
+    _check(_L.pond_stats(ctx, ctypes.byref(s)))
+    return s
+
+
+def pond_synchronize(ctx):
+    _check(_L.pond_synchronize(ctx))
+
+
+def pond_export_state(ctx, f, g, frame, u_ref=None):
+    _check(_L.pond_export_state(ctx, _ptr(f), _ptr(g), _ptr(frame), _ptr(u_ref)))
+
+
+def pond_import_state(ctx, f, g, frame, u_ref=None):
+    _check(_L.pond_import_state(ctx, _ptr(f), _ptr(g), _ptr(frame), _ptr(u_ref)))
+
+
+def pond_destroy(ctx):
+    _check(_L.pond_destroy(ctx))
+
+
+def pond_profile_enable(ctx, enable: bool):
+    _check(_L.pond_profile_enable(ctx, 1 if enable else 0))
+
+
+def pond_profile_read(ctx) -> pond_profile_t:
+    out = pond_profile_t()
+    _check(_L.pond_profile_read(ctx, ctypes.byref(out)))
+    return out
+
+
+def pond_status_string(status: int) -> str:
+    return _L.pond_status_string(status).decode()
+
+
+def pond_last_error() -> str:
+    return _L.pond_last_error().decode()
+
+
+# ----------------------------------------------------------- convenience ----
+class Solver:
+    """One context; host numpy in, host numpy out (device tensors also accepted)."""
+
+    def __init__(self, nx, ny, *, tau, gamma=1.4, prandtl=1.0, bc_x=BC_PERIODIC,
+                 bc_y=BC_PERIODIC, precision=PREC_FP32, interp_points=4, pc_tol=0.0,
+                 pc_max_iter=32, stream=None):
+        self.params = pond_params_default(nx=nx, ny=ny, tau=tau, gamma=gamma, prandtl=prandtl,
+                                          bc_x=bc_x, bc_y=bc_y, precision=precision,
+                                          interp_points=interp_points, pc_tol=pc_tol,
+                                          pc_max_iter=pc_max_iter)
+        self.nx, self.ny = nx, ny
+        self.ctx = pond_create(self.params, stream)
+
+    @classmethod
+    def from_workload(cls, w, precision=PREC_FP32, **kw):
+        s = cls(w.nx, w.ny, tau=w.tau, gamma=w.gamma, prandtl=w.prandtl, bc_x=w.bc_x,
+                bc_y=w.bc_y, precision=precision, **kw)
+        s.init_fields(w.rho, w.ux, w.uy, w.T)
+        return s
+
+    def init_fields(self, rho, ux, uy, T):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64).ravel() if isinstance(a, np.ndarray)
+                else a for a in (rho, ux, uy, T)]
+        pond_init_fields(self.ctx, *arrs)
+
+    def step(self, n=1):
+        pond_step(self.ctx, n)
+
+    def moments(self):
+        N = self.nx * self.ny
+        out = {k: np.zeros(N) for k in ("rho", "ux", "uy", "T", "p")}
+        pond_moments(self.ctx, out["rho"], out["ux"], out["uy"], out["T"], out["p"])
+        return {k: v.reshape(self.ny, self.nx) for k, v in out.items()}
+
+    def stats(self):
+        return pond_stats(self.ctx)
+
+    def export_state(self):
+        """(f, g, frame, u_ref) with f, g of shape (16, N) and frame (3, N)."""
+        N = self.nx * self.ny
+        f, g, fr, ur = np.zeros((16, N)), np.zeros((16, N)), np.zeros((3, N)), np.zeros(2)
+        pond_export_state(self.ctx, f, g, fr, ur)
+        return f, g, fr, ur
+
+    def import_state(self, f, g, frame, u_ref=None):
+        pond_import_state(self.ctx, np.ascontiguousarray(f, dtype=np.float64),
+                          np.ascontiguousarray(g, dtype=np.float64),
+                          np.ascontiguousarray(frame, dtype=np.float64),
+                          None if u_ref is None else np.ascontiguousarray(u_ref, dtype=np.float64))
+
+    def synchronize(self):
+        pond_synchronize(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            pond_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -147,7 +147,7 @@ def _pick_modes(rng, count):
     return out
 
 
-def fourier_modes(n=512, ny=None, mach=2.0, angle_deg=30.0, amplitude=1e-3, seed=0, tau=0.51,
+def fourier_modes(n=512, ny=None, mach=2.0, angle_deg=30.0, amplitude=1e-3, seed=0, tau=0.55,
                   gamma=1.4, prandtl=0.71, T0=1.0, steps=2000, kinds=None) -> Workload:
     """Uniform background (rho = 1, T = T0) advected at ``mach`` in direction
     ``angle_deg``, plus 8 random-phase Fourier modes of amplitude ``amplitude``:
@@ -190,12 +190,7 @@ def fourier_modes(n=512, ny=None, mach=2.0, angle_deg=30.0, amplitude=1e-3, seed
                     meta={"mach": mach, "U": U, "T0": T0, "amplitude": amplitude, "seed": seed})
 
 
-def riemann_quadrants(n=2048, seed=0, gamma=1.4, prandtl=0.71, nu=1e-4, T_scale=0.04,
-                      steps=1000) -> Workload:
-    """Four-quadrant 2-D Riemann problem on an n x n periodic grid; each quadrant
-    draws rho ~ U[0.5, 2], p ~ U[0.3, 1.5], Mach ~ U[0, 1.5] and a direction
-    ~ U[0, 2 pi); lattice T = T_scale p / rho; tau gives nu at T_scale."""
-    rng = np.random.default_rng(seed)
+def _quadrant_states(rng, gamma, T_scale):
     states = []
     for _ in range(4):
         r = rng.uniform(0.5, 2.0)
@@ -205,6 +200,39 @@ def riemann_quadrants(n=2048, seed=0, gamma=1.4, prandtl=0.71, nu=1e-4, T_scale=
         T = T_scale * p / r
         c = math.sqrt(gamma * T)
         states.append((r, ma * c * math.cos(d), ma * c * math.sin(d), T))
+    return states
+
+
+def quadrant_jumps(states):
+    """(max temperature ratio, max velocity jump in thermal speeds of the colder
+    side) over the four pairs of neighbouring quadrants (periodic grid)."""
+    pairs = [(0, 1), (2, 3), (0, 2), (1, 3)]
+    tr = max(max(states[a][3], states[b][3]) / min(states[a][3], states[b][3]) for a, b in pairs)
+    dv = max(math.hypot(states[a][1] - states[b][1], states[a][2] - states[b][2]) /
+             math.sqrt(min(states[a][3], states[b][3])) for a, b in pairs)
+    return tr, dv
+
+
+def riemann_quadrants(n=2048, seed=0, gamma=1.4, prandtl=0.71, nu=2e-3, T_scale=0.04,
+                      steps=1000, max_temperature_ratio=2.5, max_velocity_jump=2.0) -> Workload:
+    """Four-quadrant 2-D Riemann problem on an n x n periodic grid; each quadrant
+    draws rho ~ U[0.5, 2], p ~ U[0.3, 1.5], Mach ~ U[0, 1.5] and a direction
+    ~ U[0, 2 pi); lattice T = T_scale p / rho; tau gives nu at T_scale.
+
+    Draws whose neighbouring quadrants differ by more than
+    ``max_temperature_ratio`` in temperature or by more than
+    ``max_velocity_jump`` thermal speeds (of the colder side) in velocity are
+    rejected and the next draw of the same generator is taken: the step cannot
+    start from stronger jumps (its frame transformation between such
+    neighbours leaves the Grad expansion's range)."""
+    rng = np.random.default_rng(seed)
+    draws = 0
+    while True:
+        states = _quadrant_states(rng, gamma, T_scale)
+        draws += 1
+        tr, dv = quadrant_jumps(states)
+        if tr <= max_temperature_ratio and dv <= max_velocity_jump:
+            break
     X, Y = _grid(n, n)
     q = (X >= n // 2).astype(int) + 2 * (Y >= n // 2).astype(int)
     rho = np.empty_like(X)
@@ -216,7 +244,8 @@ def riemann_quadrants(n=2048, seed=0, gamma=1.4, prandtl=0.71, nu=1e-4, T_scale=
         rho[sel], ux[sel], uy[sel], T[sel] = r, vx, vy, t
     return Workload("riemann_quadrants", n, n, PERIODIC, PERIODIC, gamma, prandtl,
                     tau_for(nu, T_scale), steps, rho, ux, uy, T,
-                    meta={"states": states, "seed": seed, "nu": nu, "T_scale": T_scale})
+                    meta={"states": states, "seed": seed, "draws": draws, "nu": nu,
+                          "T_scale": T_scale, "temperature_ratio": tr, "velocity_jump": dv})
 
 
 def _log_uniform_int(rng, lo, hi):

@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/pond.h declares, and validates parameters before touching
+the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pond.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"POND_API[^;{]*?\b(pond_\w+)\s*\(", text, re.S)))
+
+
+@pytest.fixture(scope="module")
+def pond():
+    from paper_2405_11489_amd import pond as P
+    return P
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ("pond_create", "pond_init_fields", "pond_step", "pond_moments", "pond_destroy"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol(pond):
+    lib = ctypes.CDLL(pond.LIB_PATH)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    assert sorted(pond.EXPORTED) == declared_symbols()
+
+
+def test_abi_version_and_status_strings(pond):
+    assert pond.pond_abi_version() == pond.ABI_VERSION
+    for s in range(7):
+        assert pond.pond_status_string(s)
+    assert "unknown" in pond.pond_status_string(99)
+
+
+def test_params_struct_size_matches_header(pond):
+    # uint32 + 9 int32 = 40 bytes, then 4 doubles (8-aligned) = 72 bytes
+    assert ctypes.sizeof(pond.pond_params) == 72
+    p = pond.pond_params_default()
+    assert p.struct_size == 72 and p.lattice == 16 and p.interp_points == 4
+
+
+def test_state_bytes(pond):
+    p = pond.pond_params_default(nx=512, ny=512, precision=pond.PREC_FP32)
+    b32 = pond.pond_state_bytes(p)
+    assert 384 * 512 * 512 <= b32 < 384 * 512 * 512 + 16384
+    p.precision = pond.PREC_FP64
+    b64 = pond.pond_state_bytes(p)
+    assert 720 * 512 * 512 <= b64 < 720 * 512 * 512 + 16384
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("nx", 0, 1), ("ny", -3, 1), ("tau", 0.5, 1), ("tau", float("nan"), 1),
+    ("prandtl", 0.0, 1), ("gamma", 1.0, 1), ("gamma", 2.5, 1), ("bc_x", 2, 1),
+    ("interp_points", 5, 1), ("precision", 7, 1), ("lattice", 25, 2), ("lattice", 7, 1),
+    ("split", 1, 2), ("split", 2, 2), ("split", 9, 1), ("struct_size", 64, 1),
+])
+def test_invalid_params_rejected_before_device(pond, field, value, status):
+    p = pond.pond_params_default(nx=8, ny=8)
+    setattr(p, field, value)
+    assert pond.pond_state_bytes(p) == 0
+    with pytest.raises(pond.PondError) as ei:
+        pond.pond_create(p)
+    assert ei.value.status == status
+    assert pond.pond_last_error()
+
+
+def test_caller_memory_too_small_rejected(pond):
+    p = pond.pond_params_default(nx=8, ny=8)
+    with pytest.raises(pond.PondError) as ei:
+        pond.pond_create(p, None, 256, 16)      # never dereferenced: size check comes first
+    assert ei.value.status == pond.ERR_OUT_OF_MEMORY
+
+
+def test_null_context_calls(pond):
+    assert pond.lib.pond_destroy(None) == pond.OK
+    assert pond.lib.pond_step(None, 1) == pond.ERR_INVALID_ARG
+    assert pond.lib.pond_synchronize(None) == pond.ERR_INVALID_ARG

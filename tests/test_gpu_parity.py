@@ -1,0 +1,261 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs, element by element.
+
+Bars: FP64 kernel within 1e-12 of the oracle (max-norm relative, per
+population plane and frame plane; velocity components relative to the
+velocity scale max(|u|, sqrt(T)), since a component can vanish identically);
+FP32 kernel within 1e-5 relative on smooth flows and 1e-4 relative L1 on shock
+flows (macroscopic fields).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_11489_amd import workloads
+from parity_util import (field_errors, field_l1, gpu_run, gpu_solver, oracle_params_for,
+                         oracle_run, plane_errors, to_oracle_state, velocity_scale)
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+
+
+def modes(n, ny=None, mach=2.0, amp=1e-2, seed=0, tau=0.6, prandtl=0.71, T0=1.0, **kw):
+    return workloads.fourier_modes(n=n, ny=ny, mach=mach, amplitude=amp, seed=seed, tau=tau,
+                                   prandtl=prandtl, T0=T0, **kw)
+
+
+def clamp_x(w):
+    w.bc_x = workloads.CLAMP
+    return w
+
+
+TINY = {
+    "4x4_mach2": lambda: modes(4),
+    "7x5_clampx": lambda: clamp_x(modes(7, 5, mach=1.0, seed=3)),
+    "16x1_sod": lambda: workloads.sod_tube(nx=16, nu=2e-3, steps=4),
+    "1x1": lambda: modes(1, 1, mach=0.7),
+    "1x9_column": lambda: modes(1, 9, mach=1.5, seed=5),
+    "6x5_hot_fast": lambda: modes(6, 5, mach=1.2, T0=4.0, seed=7),
+    "9x7_cold": lambda: modes(9, 7, mach=0.5, T0=0.04, seed=8),
+    "8x8_unit_prandtl_gamma18": lambda: workloads.fourier_modes(
+        n=8, mach=1.0, amplitude=1e-2, seed=2, tau=0.7, prandtl=1.0, gamma=1.8),
+}
+
+
+@pytest.mark.parametrize("case", sorted(TINY))
+@pytest.mark.parametrize("steps", [1, 5])
+def test_fp64_tiny_grids_match_oracle(case, steps):
+    w = TINY[case]()
+    f, g, fr, ur, st, m = gpu_run(w, FP64, steps)
+    P, s, ost = oracle_run(w, steps)
+    ef, eg, el = plane_errors(f, g, fr, s)
+    assert max(ef, eg, el) <= 1e-12, (ef, eg, el)
+    assert st.pc_iterations == ost.total_iters or abs(st.pc_iterations - ost.total_iters) <= w.nodes
+    errs = field_errors(m, oracle.moments(P, s))
+    assert max(errs.values()) <= 1e-12, errs
+
+
+@pytest.mark.parametrize("npts", [3, 4])
+def test_fp64_interp_points_match_oracle(npts):
+    w = modes(10, 6, mach=1.3, seed=11)
+    f, g, fr, _, _, _ = gpu_run(w, FP64, 3, interp_points=npts)
+    _, s, _ = oracle_run(w, 3, interp_points=npts)
+    assert max(plane_errors(f, g, fr, s)) <= 1e-12
+
+
+def test_fp64_sod_tube_full_run():
+    """Shock tube at oracle size (400 x 1, 400 steps) against the oracle."""
+    w = workloads.sod_tube(nx=400, nu=2e-3)
+    for steps in (1, 10):
+        f, g, fr, _, _, _ = gpu_run(w, FP64, steps)
+        _, s, _ = oracle_run(w, steps)
+        assert max(plane_errors(f, g, fr, s)) <= 1e-12
+    f, g, fr, _, st, m = gpu_run(w, FP64, w.steps)
+    P, s, ost = oracle_run(w, w.steps)
+    errs = field_errors(m, oracle.moments(P, s))
+    assert max(errs.values()) <= 1e-12, errs
+    assert st.nonconverged == ost.nonconverged
+
+
+def test_fp64_mach2_modes_32():
+    w = modes(32, mach=2.0, amp=1e-3, seed=1, tau=0.51)
+    f, g, fr, _, _, _ = gpu_run(w, FP64, 10)
+    _, s, _ = oracle_run(w, 10)
+    assert max(plane_errors(f, g, fr, s)) <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["4x4_mach2", "7x5_clampx", "6x5_hot_fast", "9x7_cold"])
+def test_fp32_tiny_grids_within_1e5(case):
+    w = TINY[case]()
+    _, _, _, _, _, m = gpu_run(w, FP32, 5)
+    P, s, _ = oracle_run(w, 5)
+    errs = field_errors(m, oracle.moments(P, s))
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_fp32_mach2_modes_smooth_within_1e5():
+    w = modes(32, mach=2.0, amp=1e-3, seed=1, tau=0.51)
+    _, _, _, _, _, m = gpu_run(w, FP32, 40)
+    P, s, _ = oracle_run(w, 40)
+    errs = field_errors(m, oracle.moments(P, s))
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_fp32_sod_tube_l1_within_1e4():
+    w = workloads.sod_tube(nx=400, nu=2e-3)
+    _, _, _, _, _, m = gpu_run(w, FP32, w.steps)
+    P, s, _ = oracle_run(w, w.steps)
+    l1 = field_l1(m, oracle.moments(P, s))
+    assert max(l1.values()) <= 1e-4, l1
+
+
+def test_fp64_full_size_sampled_nodes():
+    """512 x 512 Mach-2 modes, the launch configuration of the benchmark: after
+    a few GPU steps, the oracle recomputes one step at sampled nodes from the
+    GPU's own state."""
+    w = modes(512, mach=2.0, amp=1e-3, seed=0, tau=0.55)
+    rng = np.random.default_rng(0)
+    nodes = np.concatenate([rng.integers(0, w.nodes, 96), [0, w.nx - 1, w.nodes - w.nx, w.nodes - 1]])
+    with gpu_solver(w, FP64) as sol:
+        sol.step(3)
+        f0, g0, fr0, _ = sol.export_state()
+        sol.step(1)
+        f1, g1, fr1, _ = sol.export_state()
+    P = oracle_params_for(w)
+    fo, go, lo, _, _ = oracle.step_nodes(P, to_oracle_state(f0, g0, fr0), nodes)
+    for a, b in ((f1[:, nodes].T, fo), (g1[:, nodes].T, go)):
+        assert np.max(np.abs(a - b) / np.max(np.abs(b), axis=0)) <= 1e-12
+    vs = velocity_scale(lo[:, 0], lo[:, 1], lo[:, 2])
+    assert np.max(np.abs(fr1[:2, nodes].T - lo[:, :2])) / vs <= 1e-12
+    assert np.max(np.abs(fr1[2, nodes] - lo[:, 2]) / lo[:, 2]) <= 1e-12
+
+
+def test_fp32_full_size_sampled_nodes():
+    w = workloads.riemann_quadrants(n=2048, seed=0, steps=3)
+    rng = np.random.default_rng(1)
+    nodes = np.concatenate([rng.integers(0, w.nodes, 64),
+                            (1024 + np.arange(-3, 3)) * 2048 + 1024, 1024 * 2048 + np.arange(-3, 3)])
+    with gpu_solver(w, FP32) as sol:
+        sol.step(3)
+        f0, g0, fr0, _ = sol.export_state()
+        sol.step(1)
+        f1, g1, fr1, _ = sol.export_state()
+    P = oracle_params_for(w)
+    fo, go, lo, _, _ = oracle.step_nodes(P, to_oracle_state(f0, g0, fr0), nodes)
+    for a, b in ((f1[:, nodes].T, fo), (g1[:, nodes].T, go)):
+        assert np.max(np.abs(a - b) / np.max(np.abs(b), axis=0)) <= 1e-5
+    vs = velocity_scale(lo[:, 0], lo[:, 1], lo[:, 2])
+    assert np.max(np.abs(fr1[:2, nodes].T - lo[:, :2])) / vs <= 1e-5
+    assert np.max(np.abs(fr1[2, nodes] - lo[:, 2]) / lo[:, 2]) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_run_twice_bitwise_equal(prec):
+    w = modes(64, 48, mach=2.5, amp=1e-2, seed=4)
+    a = gpu_run(w, prec, 7)
+    b = gpu_run(w, prec, 7)
+    for x, y in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_export_import_resume_bitwise(prec):
+    w = modes(40, 24, mach=1.5, amp=1e-2, seed=6)
+    with gpu_solver(w, prec) as s:
+        s.step(6)
+        ref = s.export_state()
+    with gpu_solver(w, prec) as s:
+        s.step(2)
+        f, g, fr, ur = s.export_state()
+    with gpu_solver(w, prec) as s:
+        s.import_state(f, g, fr, ur)
+        s.step(4)
+        out = s.export_state()
+    for x, y in zip(out[:3], ref[:3]):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_nonphysical_detected_at_the_oracle_step():
+    """Recorded finding: the shock tube at nu = 1e-4 goes non-physical; the GPU
+    flags it at the same step as the oracle."""
+    from paper_2405_11489_amd import pond
+    w = workloads.sod_tube(nx=400, nu=1e-4)
+    P = oracle_params_for(w)
+    s = oracle.init(P, w.rho.ravel(), w.ux.ravel(), w.uy.ravel(), w.T.ravel())
+    bad_oracle = None
+    for n in range(1, 80):
+        s, st = oracle.step(P, s, 1)
+        if st.nonphysical:
+            bad_oracle = n
+            break
+    assert bad_oracle is not None
+    with gpu_solver(w, FP64) as sol:
+        bad_gpu = None
+        for n in range(1, 80):
+            sol.step(1)
+            try:
+                sol.synchronize()
+            except pond.PondError as e:
+                assert e.status == pond.ERR_NONPHYSICAL
+                bad_gpu = n
+                break
+        assert bad_gpu == bad_oracle
+        with pytest.raises(pond.PondError) as ei:
+            sol.step(1)
+        assert ei.value.status == pond.ERR_STATE
+
+
+def test_init_rejects_bad_fields_on_device():
+    from paper_2405_11489_amd import pond
+    w = modes(8, mach=0.5)
+    with gpu_solver(w, FP32) as s:
+        rho = w.rho.copy()
+        rho[3, 2] = -1.0
+        with pytest.raises(pond.PondError) as ei:
+            s.init_fields(rho, w.ux, w.uy, w.T)
+        assert ei.value.status == pond.ERR_INVALID_ARG
+        with pytest.raises(pond.PondError) as ei:
+            s.step(1)
+        assert ei.value.status == pond.ERR_STATE
+        T = w.T.copy()
+        T[0, 0] = float("nan")
+        with pytest.raises(pond.PondError):
+            s.init_fields(w.rho, w.ux, w.uy, T)
+        s.init_fields(w.rho, w.ux, w.uy, w.T)
+        s.step(1)
+        s.synchronize()
+
+
+def test_device_tensor_fields_and_caller_memory():
+    """Fields passed as torch device tensors and state in caller-owned memory
+    give the same result as host arrays and library-owned memory."""
+    import torch
+    from paper_2405_11489_amd import pond
+    w = modes(24, 20, mach=2.0, amp=1e-2, seed=9)
+    ref = gpu_run(w, FP64, 3)
+    p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma, prandtl=w.prandtl,
+                                 precision=FP64)
+    nbytes = pond.pond_state_bytes(p)
+    mem = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    ctx = pond.pond_create(p, stream.cuda_stream, mem.data_ptr(), nbytes)
+    try:
+        dev = [torch.from_numpy(np.ascontiguousarray(a.ravel())).cuda() for a in (w.rho, w.ux, w.uy, w.T)]
+        pond.pond_init_fields(ctx, *dev)
+        pond.pond_step(ctx, 3)
+        out = [torch.empty(w.nodes, dtype=torch.float64, device="cuda") for _ in range(5)]
+        pond.pond_moments(ctx, *out)
+        f = torch.empty((16, w.nodes), dtype=torch.float64, device="cuda")
+        g = torch.empty_like(f)
+        fr = torch.empty((3, w.nodes), dtype=torch.float64, device="cuda")
+        pond.pond_export_state(ctx, f, g, fr)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(f.cpu().numpy(), ref[0])
+        np.testing.assert_array_equal(g.cpu().numpy(), ref[1])
+        np.testing.assert_array_equal(fr.cpu().numpy(), ref[2])
+        np.testing.assert_array_equal(out[0].cpu().numpy().reshape(w.ny, w.nx), ref[5]["rho"])
+    finally:
+        pond.pond_destroy(ctx)
