@@ -54,8 +54,10 @@ def log(*a):
 
 
 def cpu_baseline(w, seconds):
-    """The FP64 oracle timed on this host's cores: one step evaluated at a
-    random sample of nodes of the same workload state, sized to ~``seconds``."""
+    """The FP64 oracle, unmodified, timed on this host's cores: whole-grid steps
+    of the same workload from its initial state, as many as fit in
+    ~``seconds`` (at least one); if one whole-grid step would take much
+    longer, one step at a random sample of nodes instead."""
     import oracle
     P = oracle.params(w.nx, w.ny, tau=w.tau, gamma=w.gamma, prandtl=w.prandtl, bc_x=w.bc_x,
                       bc_y=w.bc_y)
@@ -64,16 +66,26 @@ def cpu_baseline(w, seconds):
     pilot = rng.integers(0, w.nodes, 512)
     t0 = time.perf_counter()
     oracle.step_nodes(P, s, pilot)
-    rate = len(pilot) / (time.perf_counter() - t0)
-    count = int(min(w.nodes, max(1024, rate * seconds)))
-    nodes = rng.permutation(w.nodes)[:count]
-    t0 = time.perf_counter()
-    _, _, _, iters, _ = oracle.step_nodes(P, s, nodes)
-    dt = time.perf_counter() - t0
-    return {"value": count / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"one step at {count} random nodes of the {w.nx}x{w.ny} workload "
-                      f"(initial state, mean {iters.mean():.2f} PC gathers), {dt:.1f} s"}
+    step_s = (time.perf_counter() - t0) / len(pilot) * w.nodes
+    if step_s <= seconds:
+        nsteps = max(1, int(seconds / step_s))
+        t0 = time.perf_counter()
+        _, st = oracle.step(P, s, nsteps)
+        dt = time.perf_counter() - t0
+        updates = nsteps * w.nodes
+        sample = (f"{nsteps} whole-grid step(s) of the {w.nx}x{w.ny} workload from its initial "
+                  f"state (mean {st.total_iters / updates:.2f} PC gathers), {dt:.1f} s")
+    else:
+        count = int(max(1024, seconds / step_s * w.nodes))
+        nodes = rng.permutation(w.nodes)[:count]
+        t0 = time.perf_counter()
+        _, _, _, iters, _ = oracle.step_nodes(P, s, nodes)
+        dt = time.perf_counter() - t0
+        updates = count
+        sample = (f"one step at {count} random nodes of the {w.nx}x{w.ny} workload "
+                  f"(initial state, mean {iters.mean():.2f} PC gathers), {dt:.1f} s")
+    return {"value": updates / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": sample}
 
 
 def main():
@@ -85,6 +97,9 @@ def main():
     ap.add_argument("--interp-points", type=int, default=4, choices=[3, 4])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel", choices=["tiled", "global"], default="tiled")
+    ap.add_argument("--tile", type=int, default=None, help="POND_TILE_* id (default: library's)")
+    ap.add_argument("--lds-nodes", type=int, default=None)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -100,8 +115,14 @@ def main():
     w = workloads.fourier_modes(n=512, mach=2.0, angle_deg=30.0, amplitude=1e-3, seed=0,
                                 tau=0.55, prandtl=0.71, gamma=1.4, steps=2000)
     stream = torch.cuda.Stream()
+    tuning = {"kernel": pond.KERNEL_TILED if args.kernel == "tiled" else pond.KERNEL_GLOBAL}
+    if args.tile is not None:
+        tuning["tile"] = args.tile
+    if args.lds_nodes is not None:
+        tuning["lds_nodes"] = args.lds_nodes
     sol = pond.Solver.from_workload(w, precision=prec, stream=stream.cuda_stream,
-                                    interp_points=args.interp_points)
+                                    interp_points=args.interp_points, tuning=tuning)
+    tun = pond.pond_get_tuning(sol.ctx)
     log(f"workload {w.name} {w.nx}x{w.ny}, {args.precision}, warmup {args.warmup}, "
         f"steps {args.steps}")
     sol.step(args.warmup)
@@ -141,13 +162,15 @@ def main():
                 "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                 "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
                 "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
-                "kernel": "step_kernel<float,4>", "flops_per_launch": flops,
+                "kernel": "step_tiled_kernel<float,4,..>" if args.kernel == "tiled" else "step_kernel<float,4>",
+                "flops_per_launch": flops,
                 "hbm_GBs_algorithmic": N * BYTES_STEP_FP32 / (step_ms * 1e-3) / 1e9}
     else:
         achieved = flops / (step_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "kernel": "step_kernel<double,4>", "flops_per_launch": flops,
+                "kernel": "step_tiled_kernel<double,4,..>" if args.kernel == "tiled" else "step_kernel<double,4>",
+                "flops_per_launch": flops,
                 "hbm_GBs_algorithmic": N * BYTES_STEP_FP64 / (step_ms * 1e-3) / 1e9}
 
     cpu = None
@@ -165,6 +188,7 @@ def main():
                    "mach": 2.0, "tau": w.tau, "prandtl": w.prandtl, "gamma": w.gamma,
                    "precision": args.precision, "interp_points": args.interp_points,
                    "parallelism": "single_gpu"},
+        "tuning": {"kernel": args.kernel, "tile": tun.tile, "lds_nodes": tun.lds_nodes},
         "pc_iterations_mean": kbar,
         "nonconverged_node_steps": st1.nonconverged - st0.nonconverged,
         "kernel_ms": {"step": step_ms, "prepass": pre_ms},

@@ -177,6 +177,28 @@ POND_API pond_status pond_export_state(pond_ctx *c, double *f, double *g, double
 POND_API pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, const double *frame,
                               const double *u_ref);
 
+/* Launch configuration of the step kernel (performance only: every
+ * configuration computes the same numbers, bit for bit).
+ *   kernel:    POND_KERNEL_TILED (default) stages each block's source region in
+ *              LDS; POND_KERNEL_GLOBAL reads every tap from HBM (reference).
+ *   tile:      POND_TILE_* block shape of the tiled kernel (destination nodes).
+ *   lds_nodes: LDS capacity per block, in nodes (20 moments each: 80 B in FP32,
+ *              160 B in FP64); taps outside the staged region read HBM.
+ * pond_set_tuning validates the values (POND_ERR_INVALID_ARG otherwise);
+ * lds_nodes <= 0 selects the default for the tile. */
+enum { POND_KERNEL_TILED = 0, POND_KERNEL_GLOBAL = 1 };
+enum { POND_TILE_16x16 = 0, POND_TILE_32x8 = 1, POND_TILE_16x8 = 2, POND_TILE_8x8 = 3,
+       POND_TILE_256x1 = 4, POND_TILE_64x1 = 5 };
+typedef struct {
+    int32_t kernel;
+    int32_t tile;
+    int32_t lds_nodes;
+    int32_t reserved;
+} pond_tuning;
+
+POND_API pond_status pond_get_tuning(pond_ctx *c, pond_tuning *out);
+POND_API pond_status pond_set_tuning(pond_ctx *c, const pond_tuning *t);
+
 /* Kernel timing on the context stream, for measurement.  While enabled,
  * pond_step brackets each of its launches with HIP events; the results give
  * the summed device time of the moment pre-pass and of the step kernel over

@@ -134,6 +134,8 @@ struct pond_ctx {
     bool initialized;
     bool failed;
     long long steps;
+    pond_tuning tuning;
+    TileConfig tc;
     bool profiling;
     std::vector<hipEvent_t> prof_events;  // 3 per timed step
     double prof_prepass_ms, prof_step_ms;
@@ -162,6 +164,58 @@ void fill_args(pond_ctx *c) {
 }
 
 bool fp64(const pond_ctx *c) { return c->p.precision == POND_PREC_FP64; }
+
+int default_lds_nodes(int tile, bool dbl) {
+    // The step kernels hold two waves per SIMD (register-limited), i.e. two
+    // 256-lane or four 128-lane blocks per CU; split the 160 KiB of LDS between
+    // them.  A 16 x 16 tile at T = 1, Mach 2 needs a 26 x 26 source region.
+    int tx, ty;
+    tile_dims(static_cast<TileShape>(tile), tx, ty);
+    const int blocks_per_cu = tx * ty >= 256 ? 2 : 4;
+    const int bytes = 160 * 1024 / blocks_per_cu - 1024;
+    return bytes / (dbl ? 160 : 80);
+}
+
+int halo_for(int tile, int cap) {
+    int tx, ty;
+    tile_dims(static_cast<TileShape>(tile), tx, ty);
+    int h = -1;
+    while ((tx + 2 * (h + 1)) * (ty + 2 * (h + 1)) <= cap) ++h;
+    return h;
+}
+
+pond_tuning default_tuning(const pond_params &p) {
+    pond_tuning t;
+    t.kernel = POND_KERNEL_TILED;
+    if (p.ny < 8)
+        t.tile = POND_TILE_64x1;
+    else
+        t.tile = p.precision == POND_PREC_FP64 ? POND_TILE_16x8 : POND_TILE_16x16;
+    t.lds_nodes = default_lds_nodes(t.tile, p.precision == POND_PREC_FP64);
+    t.reserved = 0;
+    return t;
+}
+
+pond_status apply_tuning(pond_ctx *c, const pond_tuning &t) {
+    if (t.kernel != POND_KERNEL_TILED && t.kernel != POND_KERNEL_GLOBAL)
+        return fail(POND_ERR_INVALID_ARG, "unknown kernel %d", t.kernel);
+    if (t.tile < POND_TILE_16x16 || t.tile > POND_TILE_64x1)
+        return fail(POND_ERR_INVALID_ARG, "unknown tile %d", t.tile);
+    pond_tuning u = t;
+    if (u.lds_nodes <= 0) u.lds_nodes = default_lds_nodes(u.tile, fp64(c));
+    const size_t bytes = size_t(u.lds_nodes) * 20 * c->psize;
+    if (bytes > 160 * 1024)
+        return fail(POND_ERR_INVALID_ARG, "lds_nodes %d needs %zu bytes of LDS (> 160 KiB)",
+                    u.lds_nodes, bytes);
+    const int h = halo_for(u.tile, u.lds_nodes);
+    if (h < 0) return fail(POND_ERR_INVALID_ARG, "lds_nodes %d smaller than the tile", u.lds_nodes);
+    u.reserved = 0;
+    c->tuning = u;
+    c->tc.shape = static_cast<TileShape>(u.tile);
+    c->tc.cap = u.lds_nodes;
+    c->tc.halo_cap = h;
+    return POND_OK;
+}
 
 pond_status check_ctx(const pond_ctx *c, bool need_init) {
     if (!c) return fail(POND_ERR_INVALID_ARG, "context is NULL");
@@ -325,7 +379,8 @@ pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem
     c->profiling = false;
     c->prof_prepass_ms = c->prof_step_ms = 0.0;
     c->prof_launches = 0;
-    s = reset_counters(c);
+    s = apply_tuning(c, default_tuning(c->p));
+    if (s == POND_OK) s = reset_counters(c);
     if (s != POND_OK) {
         pond_destroy(c);
         return s;
@@ -388,7 +443,10 @@ hipError_t launch_prepass_t(pond_ctx *c, DevState src) {
 
 template <typename P>
 hipError_t launch_step_t(pond_ctx *c, DevState src, DevState dst) {
-    return launch_step<P>(c->args, src, static_cast<const P *>(c->mom), dst, c->cnt, c->stream);
+    if (c->tuning.kernel == POND_KERNEL_GLOBAL)
+        return launch_step<P>(c->args, src, static_cast<const P *>(c->mom), dst, c->cnt, c->stream);
+    return launch_step_tiled<P>(c->args, c->tc, src, static_cast<const P *>(c->mom), dst, c->cnt,
+                                c->stream);
 }
 
 // One step: moment pre-pass on the current buffer, then the step kernel into
@@ -594,6 +652,21 @@ void drop_events(pond_ctx *c) {
     c->prof_events.clear();
 }
 }  // namespace
+
+pond_status pond_get_tuning(pond_ctx *c, pond_tuning *out) {
+    pond_status s = check_ctx(c, false);
+    if (s != POND_OK) return s;
+    if (!out) return fail(POND_ERR_INVALID_ARG, "out is NULL");
+    *out = c->tuning;
+    return POND_OK;
+}
+
+pond_status pond_set_tuning(pond_ctx *c, const pond_tuning *t) {
+    pond_status s = check_ctx(c, false);
+    if (s != POND_OK) return s;
+    if (!t) return fail(POND_ERR_INVALID_ARG, "tuning is NULL");
+    return apply_tuning(c, *t);
+}
 
 pond_status pond_profile_enable(pond_ctx *c, int enable) {
     pond_status s = check_ctx(c, false);

@@ -31,32 +31,57 @@ __host__ __device__ constexpr double w1(int a) { return (a == 0 || a == 3) ? kWo
 constexpr int kQ = 16;       // D2Q16 velocities, i = 4a + b, c_i = (c1(a), c1(b))
 constexpr int kNM = 10;      // moments / Grad coefficients per distribution
 
-// Reconstruction weights of the N = 3 Grad expansion (Eq. gradGeneralTransform
-// with rT_L = 1) for velocity (a, b), expressed on the normalised central
-// moments m_pq (same ordering as the moments):
-//   pop_i = w_i sum_k R_k(c_i) m_k,
-// obtained by writing the Hermite coefficients a0 = m00, a1 = m10|m01,
-// a2 = m20 - m00 | m11 | m02 - m00, a3 = m30 - 3 m10 | m21 - m01 | m12 - m10 |
-// m03 - 3 m01 into sum_n a_(n) : H_(n)(c_i) / n!.
-template <int A, int B>
-struct Recon {
-    static constexpr double cx = c1(A), cy = c1(B), w = w1(A) * w1(B);
-    static constexpr double Hxx = cx * cx - 1.0, Hyy = cy * cy - 1.0, Hxy = cx * cy;
-    static constexpr double Hxxx = cx * cx * cx - 3.0 * cx, Hyyy = cy * cy * cy - 3.0 * cy;
-    static constexpr double Hxxy = Hxx * cy, Hxyy = cx * Hyy;
-    static constexpr double r[kNM] = {
-        w * (1.0 - 0.5 * Hxx - 0.5 * Hyy),
-        w * (cx - 0.5 * Hxxx - 0.5 * Hxyy),
-        w * (cy - 0.5 * Hxxy - 0.5 * Hyyy),
-        w * 0.5 * Hxx,
-        w * Hxy,
-        w * 0.5 * Hyy,
-        w * Hxxx / 6.0,
-        w * 0.5 * Hxxy,
-        w * 0.5 * Hxyy,
-        w * Hyyy / 6.0,
-    };
+// Per-velocity constants, i = 4a + b with c_i = (c1(a), c1(b)).
+//  recon[i][k]: weights of the N = 3 Grad reconstruction (Eq.
+//    gradGeneralTransform with rT_L = 1) on the normalised central moments m_k
+//    (same ordering as the moments): pop_i = sum_k recon[i][k] m_k, from the
+//    Hermite coefficients a0 = m00, a1 = m10|m01, a2 = m20 - m00 | m11 |
+//    m02 - m00, a3 = m30 - 3 m10 | m21 - m01 | m12 - m10 | m03 - 3 m01 written
+//    into w_i sum_n a_(n) : H_(n)(c_i) / n!.
+//  herm[i][k]: the same reconstruction on the Hermite coefficients a_k:
+//    pop_i = sum_k herm[i][k] a_k = w_i (a0 + a1.H1 + a2:H2/2 + a3:H3/6).
+struct VelocityTables {
+    double recon[kQ][kNM];
+    double herm[kQ][kNM];
 };
+
+constexpr VelocityTables make_velocity_tables() {
+    VelocityTables t{};
+    for (int i = 0; i < kQ; ++i) {
+        const double cx = c1(i / 4), cy = c1(i % 4), w = w1(i / 4) * w1(i % 4);
+        const double Hxx = cx * cx - 1.0, Hyy = cy * cy - 1.0, Hxy = cx * cy;
+        const double Hxxx = cx * cx * cx - 3.0 * cx, Hyyy = cy * cy * cy - 3.0 * cy;
+        const double Hxxy = Hxx * cy, Hxyy = cx * Hyy;
+        const double r[kNM] = {1.0 - 0.5 * Hxx - 0.5 * Hyy, cx - 0.5 * Hxxx - 0.5 * Hxyy,
+                               cy - 0.5 * Hxxy - 0.5 * Hyyy, 0.5 * Hxx, Hxy, 0.5 * Hyy,
+                               Hxxx / 6.0, 0.5 * Hxxy, 0.5 * Hxyy, Hyyy / 6.0};
+        const double h[kNM] = {1.0, cx, cy, 0.5 * Hxx, Hxy, 0.5 * Hyy,
+                               Hxxx / 6.0, 0.5 * Hxxy, 0.5 * Hxyy, Hyyy / 6.0};
+        for (int k = 0; k < kNM; ++k) {
+            t.recon[i][k] = w * r[k];
+            t.herm[i][k] = w * h[k];
+        }
+    }
+    return t;
+}
+
+template <typename P>
+struct VelocityTablesP {
+    P recon[kQ][kNM];
+    P herm[kQ][kNM];
+};
+
+template <typename P>
+constexpr VelocityTablesP<P> make_velocity_tables_p() {
+    const VelocityTables d = make_velocity_tables();
+    VelocityTablesP<P> t{};
+    for (int i = 0; i < kQ; ++i)
+        for (int k = 0; k < kNM; ++k) {
+            t.recon[i][k] = P(d.recon[i][k]);
+            t.herm[i][k] = P(d.herm[i][k]);
+        }
+    return t;
+}
 
 // Central moments about d = (dx, dy), scaled by 1/s^(p+q): the normalised
 // moments m_pq of xi = (V - d)/s, from raw moments M about the same origin.
@@ -99,25 +124,6 @@ __device__ __forceinline__ void hermite_from_central(const P m[kNM], P a[kNM]) {
     a[7] = m[7] - m[2];
     a[8] = m[8] - m[1];
     a[9] = m[9] - P(3) * m[2];
-}
-
-// Population of velocity (A, B) from normalised central moments.
-template <typename P, int A, int B>
-__device__ __forceinline__ P pop_from_central(const P m[kNM]) {
-    using R = Recon<A, B>;
-    P s = P(R::r[0]) * m[0];
-#pragma unroll
-    for (int k = 1; k < kNM; ++k) s += P(R::r[k]) * m[k];
-    return s;
-}
-
-// Population of velocity (A, B) from Hermite coefficients: w_i sum a:H/n!.
-template <typename P, int A, int B>
-__device__ __forceinline__ P pop_from_hermite(const P a[kNM]) {
-    using R = Recon<A, B>;
-    return P(R::w) * (a[0] + P(R::cx) * a[1] + P(R::cy) * a[2] + P(0.5 * R::Hxx) * a[3] +
-                      P(R::Hxy) * a[4] + P(0.5 * R::Hyy) * a[5] + P(R::Hxxx / 6.0) * a[6] +
-                      P(0.5 * R::Hxxy) * a[7] + P(0.5 * R::Hxyy) * a[8] + P(R::Hyyy / 6.0) * a[9]);
 }
 
 // Lagrange interpolation weights for a departure coordinate y (node units).

@@ -37,6 +37,28 @@ struct StepArgs {
     double uref_x, uref_y;
 };
 
+// Tiled step launch configuration: block shape, LDS capacity (nodes of the
+// staged source region) and the largest halo that fits it.
+enum class TileShape : int { T16x16 = 0, T32x8 = 1, T16x8 = 2, T8x8 = 3, T256x1 = 4, T64x1 = 5 };
+
+struct TileConfig {
+    TileShape shape;
+    int cap;       // nodes of LDS per block
+    int halo_cap;  // largest symmetric halo h with (TX + 2h)(TY + 2h) <= cap
+};
+
+inline void tile_dims(TileShape s, int &tx, int &ty) {
+    switch (s) {
+    case TileShape::T16x16: tx = 16; ty = 16; return;
+    case TileShape::T32x8: tx = 32; ty = 8; return;
+    case TileShape::T16x8: tx = 16; ty = 8; return;
+    case TileShape::T8x8: tx = 8; ty = 8; return;
+    case TileShape::T256x1: tx = 256; ty = 1; return;
+    case TileShape::T64x1: tx = 64; ty = 1; return;
+    }
+    tx = ty = 0;
+}
+
 template <typename P>
 hipError_t launch_init(const StepArgs &a, const double *rho, const double *ux, const double *uy,
                        const double *T, DevState st, DevCounters *cnt, hipStream_t s);
@@ -45,6 +67,9 @@ hipError_t launch_moments_prepass(const StepArgs &a, DevState st, P *mom, hipStr
 template <typename P>
 hipError_t launch_step(const StepArgs &a, DevState src, const P *mom, DevState dst, DevCounters *cnt,
                        hipStream_t s);
+template <typename P>
+hipError_t launch_step_tiled(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
+                             DevState dst, DevCounters *cnt, hipStream_t s);
 template <typename P>
 hipError_t launch_macro(const StepArgs &a, DevState st, double *rho, double *ux, double *uy,
                         double *T, double *p, hipStream_t s);

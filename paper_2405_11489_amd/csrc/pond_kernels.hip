@@ -18,22 +18,13 @@
 // moments of the stencil nodes are interpolated at the departure point and the
 // frame transformation is applied once to the interpolated moments, instead of
 // transforming every stencil node first (the two agree to rounding).
-#include <utility>
-
-#include "pond_device.h"
-#include "pond_internal.h"
+#include "pond_step_common.h"
 
 namespace pond {
 
 namespace {
 
 constexpr int kBlock = 256;
-
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 template <typename P>
 __device__ __forceinline__ P *plane(void *base, int i, long long N) {
@@ -74,6 +65,8 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs a, const double *
 }
 
 // ---------------------------------------------------- moments pre-pass ----
+// Moments up to order three of f and g of every node (Eq. genericMomentUptoO3),
+// about u_ref, stored as grouped planes.
 template <typename P>
 __global__ __launch_bounds__(kBlock) void moments_kernel(StepArgs a, DevState st,
                                                          P *__restrict__ mom) {
@@ -81,9 +74,9 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(StepArgs a, DevState st
     if (n >= a.N) return;
     const P s = P(sqrt(st.T[n]));
     const P dx = P(st.ux[n] - a.uref_x), dy = P(st.uy[n] - a.uref_y);
-    P Mf[kNM], Mg[kNM];
+    P M[kNMom];
 #pragma unroll
-    for (int k = 0; k < kNM; ++k) Mf[k] = Mg[k] = P(0);
+    for (int k = 0; k < kNMom; ++k) M[k] = P(0);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         const P fi = plane<P>(st.f, i, a.N)[n];
@@ -93,80 +86,16 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(StepArgs a, DevState st
                              Vy * Vy,      Vx * Vx * Vx, Vx * Vx * Vy, Vx * Vy * Vy, Vy * Vy * Vy};
 #pragma unroll
         for (int k = 0; k < kNM; ++k) {
-            Mf[k] += fi * mono[k];
-            Mg[k] += gi * mono[k];
+            M[k] += fi * mono[k];
+            M[kNM + k] += gi * mono[k];
         }
     }
-#pragma unroll
-    for (int k = 0; k < kNM; ++k) {
-        mom[(long long)k * a.N + n] = Mf[k];
-        mom[(long long)(kNM + k) * a.N + n] = Mg[k];
-    }
+    store_moments(mom, a.N, n, M);
 }
 
-// ---------------------------------------------------------------- step ----
-// Per-iteration gather geometry of one lane: interpolation weights and node
-// offsets of the NP-point stencils along x (per a) and y (per b).
-template <typename P, int NP>
-struct Stencil {
-    P wx[4][NP], wy[4][NP];
-    int col[4][NP];   // x index
-    int row[4][NP];   // y index * nx
-};
-
-template <typename P, int NP, int I>
-__device__ __forceinline__ void gather_velocity(const StepArgs &a, const P *__restrict__ mom,
-                                                const Stencil<P, NP> &S, P dux, P duy, P is,
-                                                P *ft, P *gt) {
-    constexpr int A = I / 4, B = I % 4;
-    P Mf[kNM], Mg[kNM];
-#pragma unroll
-    for (int k = 0; k < kNM; ++k) Mf[k] = Mg[k] = P(0);
-#pragma unroll
-    for (int q = 0; q < NP; ++q) {
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const P W = S.wx[A][p] * S.wy[B][q];
-            const long long idx = (long long)S.row[B][q] + S.col[A][p];
-#pragma unroll
-            for (int k = 0; k < kNM; ++k) {
-                Mf[k] += W * mom[(long long)k * a.N + idx];
-                Mg[k] += W * mom[(long long)(kNM + k) * a.N + idx];
-            }
-        }
-    }
-    P m[kNM];
-    central_normalised(Mf, dux, duy, is, m);
-    ft[I] = pop_from_central<P, A, B>(m);
-    central_normalised(Mg, dux, duy, is, m);
-    gt[I] = pop_from_central<P, A, B>(m);
-}
-
-template <typename P, int NP, int... Is>
-__device__ __forceinline__ void gather_all(std::integer_sequence<int, Is...>, const StepArgs &a,
-                                           const P *__restrict__ mom, const Stencil<P, NP> &S,
-                                           P dux, P duy, P is, P *ft, P *gt) {
-    (gather_velocity<P, NP, Is>(a, mom, S, dux, duy, is, ft, gt), ...);
-}
-
-template <typename P, int I>
-__device__ __forceinline__ void store_velocity(const StepArgs &a, DevState dst, long long n,
-                                               const P *af, const P *ag, bool bad) {
-    constexpr int A = I / 4, B = I % 4;
-    P fv = pop_from_hermite<P, A, B>(af);
-    P gv = pop_from_hermite<P, A, B>(ag);
-    if (bad) fv = gv = P(NAN);
-    plane<P>(dst.f, I, a.N)[n] = fv;
-    plane<P>(dst.g, I, a.N)[n] = gv;
-}
-
-template <typename P, int... Is>
-__device__ __forceinline__ void store_all(std::integer_sequence<int, Is...>, const StepArgs &a,
-                                          DevState dst, long long n, const P *af, const P *ag,
-                                          bool bad) {
-    (store_velocity<P, Is>(a, dst, n, af, ag, bad), ...);
-}
-
+// ----------------------------------------------------- step (global taps) ----
+// Reference step kernel: one lane per node in row-major order, taps read
+// straight from the HBM moment planes.
 template <typename P, int NP>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
                                                       const P *__restrict__ mom, DevState dst,
@@ -174,157 +103,141 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = n < a.N;
     int x = 0, y = 0;
-    double lg0 = 0.0, lg1 = 0.0, lg2 = 1.0;  // frame of the current gather
+    double l0 = 0.0, l1 = 0.0, l2 = 1.0;
     if (live) {
         x = int(n % a.nx);
         y = int(n / a.nx);
-        lg0 = src.ux[n];
-        lg1 = src.uy[n];
-        lg2 = src.T[n];
+        l0 = src.ux[n];
+        l1 = src.uy[n];
+        l2 = src.T[n];
     }
-    double ln0 = lg0, ln1 = lg1, ln2 = lg2;  // frame of the gathered moments
-    double rho = 1.0;
-    P ft[kQ], gt[kQ];
-    bool done = !live, conv = false, bad = false;
-    int used = 0;
-    Stencil<P, NP> S;
+    const GlobalTaps<P, NP> taps{mom, a.N, a.nx, a.ny, a.bc_x, a.bc_y};
+    node_step<P, NP>(a, taps, x, y, n, live, l0, l1, l2, dst, cnt);
+}
 
-    for (int k = 0; k < a.pc_max_iter; ++k) {
-        if (!done) {
-            const double s = sqrt(lg2);
-            // departure points y_i = x - C_i(lam_bar) dt, split per axis
+// ------------------------------------------------------ step (LDS tiles) ----
+// Tap source of the tiled kernel: the moments of the block's source region
+// (unwrapped rectangle [X0, X1] x [Y0, Y1], W wide) staged in LDS as grouped
+// planes of stride cap; a velocity whose stencil leaves the region reads HBM.
+template <typename P, int NP>
+struct TileTaps {
+    const P *lds;
+    int cap, X0, Y0, X1, Y1, W;
+    GlobalTaps<P, NP> glob;
+
+    __device__ __forceinline__ void gather(int bx, int by, const P wx[NP], const P wy[NP],
+                                           P Mf[kNM], P Mg[kNM]) const {
+        const bool inside = bx >= X0 && bx + NP - 1 <= X1 && by >= Y0 && by + NP - 1 <= Y1;
+        if (inside) {
+            const int base = (by - Y0) * W + (bx - X0);
+            // one stencil row at a time: bounds the loads in flight per lane
+#pragma unroll 1
+            for (int q = 0; q < NP; ++q)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const double dep_x = double(x) - (s * c1(c) + lg0);
-                const double dep_y = double(y) - (s * c1(c) + lg1);
-                const int bx = lagrange<NP>(dep_x, S.wx[c]);
-                const int by = lagrange<NP>(dep_y, S.wy[c]);
+                for (int p = 0; p < NP; ++p) {
+                    const P Wt = wx[p] * wy[q];
+                    P M[kNMom];
+                    load_moments(lds, cap, base + q * W + p, M);
 #pragma unroll
-                for (int j = 0; j < NP; ++j) {
-                    S.col[c][j] = wrap_index(bx + j, a.nx, a.bc_x);
-                    S.row[c][j] = wrap_index(by + j, a.ny, a.bc_y) * a.nx;
+                    for (int k = 0; k < kNM; ++k) {
+                        Mf[k] += Wt * M[k];
+                        Mg[k] += Wt * M[kNM + k];
+                    }
                 }
-            }
-            const P dux = P(lg0 - a.uref_x), duy = P(lg1 - a.uref_y), is = P(1.0 / s);
-            gather_all<P, NP>(std::make_integer_sequence<int, kQ>{}, a, mom, S, dux, duy, is, ft, gt);
-
-            // conserved moments (FP64) and the frame they imply
-            double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) {
-                const double fi = double(ft[i]);
-                r += fi;
-                jx += fi * (s * c1(i / 4) + lg0);
-                jy += fi * (s * c1(i % 4) + lg1);
-                E += double(gt[i]);
-            }
-            rho = r;
-            ln0 = jx / r;
-            ln1 = jy / r;
-            ln2 = (E - (jx * jx + jy * jy) / (2.0 * r)) / (r * a.cv);
-            used = k + 1;
-            if (!(r > 0.0) || !(ln2 > 0.0) || !isfinite(ln0) || !isfinite(ln1) || !isfinite(ln2) ||
-                !isfinite(E)) {
-                bad = true;
-                done = true;
-            } else {
-                const double du = fmax(fabs(ln0 - lg0), fabs(ln1 - lg1)) / sqrt(ln2);
-                const double dT = fabs(ln2 - lg2) / ln2;
-                if (fmax(du, dT) <= a.pc_tol) {
-                    conv = true;
-                    done = true;
-                } else if (k + 1 < a.pc_max_iter) {
-                    lg0 = ln0;
-                    lg1 = ln1;
-                    lg2 = ln2;
-                }
-            }
-        }
-        if (__all(done)) break;  // wave-uniform exit once every lane has converged
-    }
-
-    if (live) {
-        // lab moments of the gathered populations (frame lg) about u_ref
-        const P s = P(sqrt(lg2));
-        const P dx = P(lg0 - a.uref_x), dy = P(lg1 - a.uref_y);
-        P Mf[kNM], Mg[kNM];
-#pragma unroll
-        for (int k = 0; k < kNM; ++k) Mf[k] = Mg[k] = P(0);
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            const P Vx = s * P(c1(i / 4)) + dx, Vy = s * P(c1(i % 4)) + dy;
-            const P mono[kNM] = {P(1),        Vx,           Vy,           Vx * Vx,      Vx * Vy,
-                                 Vy * Vy,     Vx * Vx * Vx, Vx * Vx * Vy, Vx * Vy * Vy, Vy * Vy * Vy};
-#pragma unroll
-            for (int k = 0; k < kNM; ++k) {
-                Mf[k] += ft[i] * mono[k];
-                Mg[k] += gt[i] * mono[k];
-            }
-        }
-        // re-projection onto lam* = (ln0, ln1, ln2): Grad coefficients there
-        const double sT = sqrt(ln2);
-        const P is = P(1.0 / sT);
-        const P tx = P(ln0 - a.uref_x), ty = P(ln1 - a.uref_y);
-        P m[kNM], af[kNM], ag[kNM];
-        central_normalised(Mf, tx, ty, is, m);
-        hermite_from_central(m, af);
-        central_normalised(Mg, tx, ty, is, m);
-        hermite_from_central(m, ag);
-
-        // BGK collision in lam*, on the Grad coefficients.
-        // f: f^eq = rho w_i has only a0; every higher coefficient decays by (1 - omega).
-        // g: g^eq = w_i [rho (c_v - 1) T + rho |C_i|^2 / 2] has
-        //    a0 = rho c_v T + rho |u|^2 / 2, a1 = rho sqrt(T) u, a2 = rho T I, a3 = 0.
-        const double om = a.omega;
-        double geq[kNM];
-        geq[0] = rho * (a.cv - 1.0) * ln2 + 0.5 * rho * (2.0 * ln2 + ln0 * ln0 + ln1 * ln1);
-        geq[1] = rho * sT * ln0;
-        geq[2] = rho * sT * ln1;
-        geq[3] = rho * ln2;
-        geq[4] = 0.0;
-        geq[5] = rho * ln2;
-        geq[6] = geq[7] = geq[8] = geq[9] = 0.0;
-        if (a.unit_prandtl) {
-#pragma unroll
-            for (int k = 0; k < kNM; ++k) ag[k] = ag[k] + P(om) * (P(geq[k]) - ag[k]);
         } else {
-            // quasi-equilibrium: energy flux of g^eq plus the viscous heating u . P^neq,
-            // P^neq = T a2(f) + sqrt(T) (u a1(f) + a1(f) u) in lam*.
-            const double a1x = double(af[1]), a1y = double(af[2]);
-            const double Pxx = ln2 * double(af[3]) + sT * 2.0 * ln0 * a1x;
-            const double Pxy = ln2 * double(af[4]) + sT * (ln0 * a1y + a1x * ln1);
-            const double Pyy = ln2 * double(af[5]) + sT * 2.0 * ln1 * a1y;
-            const double dqx = ln0 * Pxx + ln1 * Pxy;
-            const double dqy = ln0 * Pxy + ln1 * Pyy;
-            double gqe[kNM];
-#pragma unroll
-            for (int k = 0; k < kNM; ++k) gqe[k] = geq[k];
-            gqe[1] += dqx / sT;
-            gqe[2] += dqy / sT;
-            const double om1 = a.omega1;
-#pragma unroll
-            for (int k = 0; k < kNM; ++k)
-                ag[k] = ag[k] + P(om1) * (P(gqe[k]) - ag[k]) + P(om) * (P(geq[k]) - P(gqe[k]));
+            glob.gather(bx, by, wx, wy, Mf, Mg);
         }
-        const P decay = P(1.0 - om);
+    }
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
+// give each XCD a contiguous range of tiles so that neighbouring tiles, which
+// share halo moments, share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb / 8, r = nb % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
+__device__ __forceinline__ int block_min(int v, int *red) {
 #pragma unroll
-        for (int k = 1; k < kNM; ++k) af[k] *= decay;
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    const int w = threadIdx.x / 64, nw = (blockDim.x + 63) / 64;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    int r = red[0];
+    for (int i = 1; i < nw; ++i) r = min(r, red[i]);
+    return r;
+}
 
-        store_all<P>(std::make_integer_sequence<int, kQ>{}, a, dst, n, af, ag, bad);
-        dst.ux[n] = bad ? NAN : ln0;
-        dst.uy[n] = bad ? NAN : ln1;
-        dst.T[n] = bad ? NAN : ln2;
+template <int NP>
+__device__ __forceinline__ void stencil_extent(int x, double u, double s, int &lo, int &hi) {
+    // departure coordinates x - (s c + u) for c = +-c_out bound all stencils
+    const double dlo = double(x) - (s * c1(3) + u), dhi = double(x) - (s * c1(0) + u);
+    const double clo = fmin(fmax(dlo, double(x) - 4096.0), double(x) + 4096.0);
+    const double chi = fmin(fmax(dhi, double(x) - 4096.0), double(x) + 4096.0);
+    if (NP == 4) {
+        lo = int(floor(clo)) - 1;
+        hi = int(floor(chi)) + 2;
+    } else {
+        lo = int(floor(clo + 0.5)) - 1;
+        hi = int(floor(chi + 0.5)) + 1;
+    }
+}
+
+template <typename P, int NP, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void step_tiled_kernel(StepArgs a, DevState src,
+                                                            const P *__restrict__ mom,
+                                                            DevState dst, DevCounters *cnt,
+                                                            int cap, int halo_cap, int tiles_x) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    P *lds = reinterpret_cast<P *>(smem_raw);
+    __shared__ int red[4][(TX * TY + 63) / 64];
+
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx0 = (tile % tiles_x) * TX, ty0 = (tile / tiles_x) * TY;
+    const int x = tx0 + int(threadIdx.x) % TX, y = ty0 + int(threadIdx.x) / TX;
+    const bool live = x < a.nx && y < a.ny;
+    const long long n = live ? (long long)y * a.nx + x : 0;
+    double l0 = 0.0, l1 = 0.0, l2 = 1.0;
+    if (live) {
+        l0 = src.ux[n];
+        l1 = src.uy[n];
+        l2 = src.T[n];
     }
 
-    // counters: one atomic per wave
-    const unsigned long long it = wave_sum((unsigned long long)used);
-    const unsigned long long nc = wave_sum((unsigned long long)(live && !conv && !bad));
-    const unsigned long long nb = wave_sum((unsigned long long)(live && bad));
-    if ((threadIdx.x & 63) == 0) {
-        if (it) atomicAdd(&cnt->pc_iterations, it);
-        if (nc) atomicAdd(&cnt->nonconverged, nc);
-        if (nb) atomicAdd(&cnt->nonphysical, nb);
+    // source region of the block: union of the predictor stencils, clipped to
+    // the tile plus halo_cap so that it fits the LDS capacity
+    constexpr int kFar = 1 << 30;
+    int lx = kFar, hx = -kFar, ly = kFar, hy = -kFar;
+    if (live && isfinite(l0) && isfinite(l1) && l2 > 0.0 && isfinite(l2)) {
+        const double s = sqrt(l2);
+        stencil_extent<NP>(x, l0, s, lx, hx);
+        stencil_extent<NP>(y, l1, s, ly, hy);
     }
+    int X0 = block_min(lx, red[0]);
+    int X1 = -block_min(-hx, red[1]);
+    int Y0 = block_min(ly, red[2]);
+    int Y1 = -block_min(-hy, red[3]);
+    X0 = max(X0, tx0 - halo_cap);
+    X1 = min(X1, tx0 + TX - 1 + halo_cap);
+    Y0 = max(Y0, ty0 - halo_cap);
+    Y1 = min(Y1, ty0 + TY - 1 + halo_cap);
+    const int W = X1 >= X0 ? X1 - X0 + 1 : 0;
+    const int H = Y1 >= Y0 ? Y1 - Y0 + 1 : 0;
+
+    for (int idx = threadIdx.x; idx < W * H; idx += TX * TY) {
+        const int gx = wrap_index(X0 + idx % W, a.nx, a.bc_x);
+        const int gy = wrap_index(Y0 + idx / W, a.ny, a.bc_y);
+        P M[kNMom];
+        load_moments(mom, a.N, (long long)gy * a.nx + gx, M);
+        store_moments(lds, cap, idx, M);
+    }
+    __syncthreads();
+
+    const TileTaps<P, NP> taps{lds, cap, X0, Y0, X1, Y1, W,
+                               GlobalTaps<P, NP>{mom, a.N, a.nx, a.ny, a.bc_x, a.bc_y}};
+    node_step<P, NP>(a, taps, x, y, n, live, l0, l1, l2, dst, cnt);
 }
 
 // ------------------------------------------------------ macroscopic ----
@@ -483,6 +396,47 @@ hipError_t launch_step(const StepArgs &a, DevState src, const P *mom, DevState d
     return hipGetLastError();
 }
 
+namespace {
+
+template <typename P, int NP, int TX, int TY>
+hipError_t launch_tiled_t(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
+                          DevState dst, DevCounters *cnt, hipStream_t s) {
+    auto kern = step_tiled_kernel<P, NP, TX, TY>;
+    const size_t lds = size_t(tc.cap) * kNMom * sizeof(P);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    const int tiles_x = (a.nx + TX - 1) / TX, tiles_y = (a.ny + TY - 1) / TY;
+    hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y), dim3(TX * TY), lds, s, a, src, mom, dst, cnt,
+                       tc.cap, tc.halo_cap, tiles_x);
+    return hipGetLastError();
+}
+
+template <typename P, int NP>
+hipError_t launch_tiled_np(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
+                           DevState dst, DevCounters *cnt, hipStream_t s) {
+    switch (tc.shape) {
+    case TileShape::T16x16: return launch_tiled_t<P, NP, 16, 16>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T32x8: return launch_tiled_t<P, NP, 32, 8>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T16x8: return launch_tiled_t<P, NP, 16, 8>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T8x8: return launch_tiled_t<P, NP, 8, 8>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T256x1: return launch_tiled_t<P, NP, 256, 1>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T64x1: return launch_tiled_t<P, NP, 64, 1>(a, tc, src, mom, dst, cnt, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+template <typename P>
+hipError_t launch_step_tiled(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
+                             DevState dst, DevCounters *cnt, hipStream_t s) {
+    if (a.interp_points == 3) return launch_tiled_np<P, 3>(a, tc, src, mom, dst, cnt, s);
+    return launch_tiled_np<P, 4>(a, tc, src, mom, dst, cnt, s);
+}
+
 template <typename P>
 hipError_t launch_macro(const StepArgs &a, DevState st, double *rho, double *ux, double *uy,
                         double *T, double *p, hipStream_t s) {
@@ -534,6 +488,8 @@ hipError_t launch_state_mean_velocity(const StepArgs &a, DevState st, double *sc
     template hipError_t launch_moments_prepass<P>(const StepArgs &, DevState, P *, hipStream_t);   \
     template hipError_t launch_step<P>(const StepArgs &, DevState, const P *, DevState,            \
                                        DevCounters *, hipStream_t);                                \
+    template hipError_t launch_step_tiled<P>(const StepArgs &, const TileConfig &, DevState,       \
+                                             const P *, DevState, DevCounters *, hipStream_t);     \
     template hipError_t launch_macro<P>(const StepArgs &, DevState, double *, double *, double *,  \
                                         double *, double *, hipStream_t);                          \
     template hipError_t launch_export<P>(const StepArgs &, DevState, double *, double *, double *, \

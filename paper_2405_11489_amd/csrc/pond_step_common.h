@@ -1,0 +1,318 @@
+// pond_step_common.h -- per-node body of the PonD step shared by the step
+// kernels: departure stencils, the predictor-corrector loop over a tap source,
+// re-projection, collision in Grad-coefficient space and the store.
+//
+// Moment storage ("grouped planes"): the 20 moments of a node (f moments 0-9,
+// g moments 10-19, ordering of pond_device.h) are held as G vector groups
+// (float: 5 float4, double: 10 double2); group k of node idx sits at
+// base[k * stride + idx].  The same layout serves the HBM moment planes
+// (stride = N) and the LDS tiles (stride = tile capacity).
+#pragma once
+
+#include <utility>
+
+#include "pond_device.h"
+#include "pond_internal.h"
+
+namespace pond {
+
+template <typename P>
+struct MomVec;
+template <>
+struct MomVec<float> {
+    using V = float4;
+    static constexpr int G = 5;
+};
+template <>
+struct MomVec<double> {
+    using V = double2;
+    static constexpr int G = 10;
+};
+
+constexpr int kNMom = 2 * kNM;  // 20 moments per node
+
+template <typename P>
+__device__ __forceinline__ void load_moments(const P *__restrict__ base, long long stride,
+                                             long long idx, P M[kNMom]) {
+    using V = typename MomVec<P>::V;
+    const V *b = reinterpret_cast<const V *>(base);
+    if constexpr (MomVec<P>::G == 5) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const V v = b[k * stride + idx];
+            M[4 * k] = v.x;
+            M[4 * k + 1] = v.y;
+            M[4 * k + 2] = v.z;
+            M[4 * k + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            const V v = b[k * stride + idx];
+            M[2 * k] = v.x;
+            M[2 * k + 1] = v.y;
+        }
+    }
+}
+
+template <typename P>
+__device__ __forceinline__ void store_moments(P *__restrict__ base, long long stride,
+                                              long long idx, const P M[kNMom]) {
+    using V = typename MomVec<P>::V;
+    V *b = reinterpret_cast<V *>(base);
+    if constexpr (MomVec<P>::G == 5) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            b[k * stride + idx] = V{M[4 * k], M[4 * k + 1], M[4 * k + 2], M[4 * k + 3]};
+    } else {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) b[k * stride + idx] = V{M[2 * k], M[2 * k + 1]};
+    }
+}
+
+template <typename P>
+__device__ __forceinline__ P *pop_plane(void *base, int i, long long N) {
+    return static_cast<P *>(base) + (long long)i * N;
+}
+template <typename P>
+__device__ __forceinline__ const P *pop_plane(const void *base, int i, long long N) {
+    return static_cast<const P *>(base) + (long long)i * N;
+}
+
+static __constant__ VelocityTablesP<float> kTabF = make_velocity_tables_p<float>();
+static __constant__ VelocityTablesP<double> kTabD = make_velocity_tables_p<double>();
+
+template <typename P>
+__device__ __forceinline__ const VelocityTablesP<P> &vtab();
+template <>
+__device__ __forceinline__ const VelocityTablesP<float> &vtab<float>() {
+    return kTabF;
+}
+template <>
+__device__ __forceinline__ const VelocityTablesP<double> &vtab<double>() {
+    return kTabD;
+}
+
+// Tap source reading the HBM moment planes with periodic / clamp wrapping.
+// gather() accumulates sum_{p,q} wx[p] wy[q] M(bx + p, by + q) for the NP x NP
+// stencil whose first node is (bx, by) in unwrapped grid coordinates.
+template <typename P, int NP>
+struct GlobalTaps {
+    const P *mom;
+    long long N;
+    int nx, ny, bc_x, bc_y;
+
+    __device__ __forceinline__ void gather(int bx, int by, const P wx[NP], const P wy[NP],
+                                           P Mf[kNM], P Mg[kNM]) const {
+        int col[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) col[j] = wrap_index(bx + j, nx, bc_x);
+#pragma unroll 1
+        for (int q = 0; q < NP; ++q) {
+            const long long row = (long long)wrap_index(by + q, ny, bc_y) * nx;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const P W = wx[p] * wy[q];
+                P M[kNMom];
+                load_moments(mom, N, row + col[p], M);
+#pragma unroll
+                for (int k = 0; k < kNM; ++k) {
+                    Mf[k] += W * M[k];
+                    Mg[k] += W * M[kNM + k];
+                }
+            }
+        }
+    }
+};
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename P>
+__device__ __forceinline__ void monomials(P Vx, P Vy, P mono[kNM]) {
+    const P Vxx = Vx * Vx, Vyy = Vy * Vy;
+    mono[0] = P(1);
+    mono[1] = Vx;
+    mono[2] = Vy;
+    mono[3] = Vxx;
+    mono[4] = Vx * Vy;
+    mono[5] = Vyy;
+    mono[6] = Vxx * Vx;
+    mono[7] = Vxx * Vy;
+    mono[8] = Vx * Vyy;
+    mono[9] = Vyy * Vy;
+}
+
+// The whole step of one destination node (x, y) = node n whose time-t frame
+// is (l0, l1, l2).  Lanes with live == false take part in the wave-level
+// predictor-corrector exit and the counter reduction only.
+//
+// Per predictor-corrector gather, for each velocity i: departure point and
+// Lagrange weights, interpolation of the 20 moments, frame transformation of
+// the interpolated moments into the iterate frame (population i of f and g);
+// the FP64 sums rho, j, E and the lab moments of the gathered populations are
+// accumulated on the fly, so no population array is kept.
+template <typename P, int NP, class Taps>
+__device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, int x, int y,
+                                          long long n, bool live, double l0, double l1, double l2,
+                                          DevState dst, DevCounters *cnt) {
+    const VelocityTablesP<P> &tab = vtab<P>();
+    double lg0 = l0, lg1 = l1, lg2 = l2;     // frame of the current gather
+    double ln0 = lg0, ln1 = lg1, ln2 = lg2;  // frame of the gathered moments
+    double rho = 1.0;
+    P Mf[kNM], Mg[kNM];  // lab moments (about u_ref) of the last gather's populations
+#pragma unroll
+    for (int k = 0; k < kNM; ++k) Mf[k] = Mg[k] = P(0);
+    bool done = !live, conv = false, bad = false;
+    int used = 0;
+
+    for (int it = 0; it < a.pc_max_iter; ++it) {
+        if (!done) {
+            const double s = sqrt(lg2);
+            const P sP = P(s), dux = P(lg0 - a.uref_x), duy = P(lg1 - a.uref_y), is = P(1.0 / s);
+            double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+#pragma unroll
+            for (int k = 0; k < kNM; ++k) Mf[k] = Mg[k] = P(0);
+#pragma unroll 1
+            for (int i = 0; i < kQ; ++i) {
+                const double cx = c1(i >> 2), cy = c1(i & 3);
+                // departure point x - C_i(lam_bar) dt and its stencil
+                P wx[NP], wy[NP];
+                const int bx = lagrange<NP>(double(x) - (s * cx + lg0), wx);
+                const int by = lagrange<NP>(double(y) - (s * cy + lg1), wy);
+                P If[kNM], Ig[kNM];
+#pragma unroll
+                for (int k = 0; k < kNM; ++k) If[k] = Ig[k] = P(0);
+                taps.gather(bx, by, wx, wy, If, Ig);
+                // frame transformation of the interpolated moments: population i
+                P m[kNM];
+                central_normalised(If, dux, duy, is, m);
+                P fi = P(0), gi = P(0);
+#pragma unroll
+                for (int k = 0; k < kNM; ++k) fi += tab.recon[i][k] * m[k];
+                central_normalised(Ig, dux, duy, is, m);
+#pragma unroll
+                for (int k = 0; k < kNM; ++k) gi += tab.recon[i][k] * m[k];
+                // conserved moments in FP64
+                const double fd = double(fi);
+                r += fd;
+                jx += fd * (s * cx + lg0);
+                jy += fd * (s * cy + lg1);
+                E += double(gi);
+                // lab moments of the gathered populations, for the re-projection
+                P mono[kNM];
+                monomials(sP * P(cx) + dux, sP * P(cy) + duy, mono);
+#pragma unroll
+                for (int k = 0; k < kNM; ++k) {
+                    Mf[k] += fi * mono[k];
+                    Mg[k] += gi * mono[k];
+                }
+            }
+            rho = r;
+            ln0 = jx / r;
+            ln1 = jy / r;
+            ln2 = (E - (jx * jx + jy * jy) / (2.0 * r)) / (r * a.cv);
+            used = it + 1;
+            if (!(r > 0.0) || !(ln2 > 0.0) || !isfinite(ln0) || !isfinite(ln1) || !isfinite(ln2) ||
+                !isfinite(E)) {
+                bad = true;
+                done = true;
+            } else {
+                const double du = fmax(fabs(ln0 - lg0), fabs(ln1 - lg1)) / sqrt(ln2);
+                const double dT = fabs(ln2 - lg2) / ln2;
+                if (fmax(du, dT) <= a.pc_tol) {
+                    conv = true;
+                    done = true;
+                } else if (it + 1 < a.pc_max_iter) {
+                    lg0 = ln0;
+                    lg1 = ln1;
+                    lg2 = ln2;
+                }
+            }
+        }
+        if (__all(done)) break;  // wave-uniform exit once every lane has converged
+    }
+
+    if (live) {
+        // re-projection onto lam* = (ln0, ln1, ln2): Grad coefficients there
+        const double sT = sqrt(ln2);
+        const P is = P(1.0 / sT);
+        const P tx = P(ln0 - a.uref_x), ty = P(ln1 - a.uref_y);
+        P m[kNM], af[kNM], ag[kNM];
+        central_normalised(Mf, tx, ty, is, m);
+        hermite_from_central(m, af);
+        central_normalised(Mg, tx, ty, is, m);
+        hermite_from_central(m, ag);
+
+        // BGK collision in lam*, on the Grad coefficients.
+        // f: f^eq = rho w_i has only a0; every higher coefficient decays by (1 - omega).
+        // g: g^eq = w_i [rho (c_v - 1) T + rho |C_i|^2 / 2] has
+        //    a0 = rho c_v T + rho |u|^2 / 2, a1 = rho sqrt(T) u, a2 = rho T I, a3 = 0.
+        const double om = a.omega;
+        double geq[kNM];
+        geq[0] = rho * (a.cv - 1.0) * ln2 + 0.5 * rho * (2.0 * ln2 + ln0 * ln0 + ln1 * ln1);
+        geq[1] = rho * sT * ln0;
+        geq[2] = rho * sT * ln1;
+        geq[3] = rho * ln2;
+        geq[4] = 0.0;
+        geq[5] = rho * ln2;
+        geq[6] = geq[7] = geq[8] = geq[9] = 0.0;
+        if (a.unit_prandtl) {
+#pragma unroll
+            for (int k = 0; k < kNM; ++k) ag[k] = ag[k] + P(om) * (P(geq[k]) - ag[k]);
+        } else {
+            // quasi-equilibrium: energy flux of g^eq plus the viscous heating u . P^neq,
+            // P^neq = T a2(f) + sqrt(T) (u a1(f) + a1(f) u) in lam*.
+            const double a1x = double(af[1]), a1y = double(af[2]);
+            const double Pxx = ln2 * double(af[3]) + sT * 2.0 * ln0 * a1x;
+            const double Pxy = ln2 * double(af[4]) + sT * (ln0 * a1y + a1x * ln1);
+            const double Pyy = ln2 * double(af[5]) + sT * 2.0 * ln1 * a1y;
+            const double dqx = ln0 * Pxx + ln1 * Pxy;
+            const double dqy = ln0 * Pxy + ln1 * Pyy;
+            double gqe[kNM];
+#pragma unroll
+            for (int k = 0; k < kNM; ++k) gqe[k] = geq[k];
+            gqe[1] += dqx / sT;
+            gqe[2] += dqy / sT;
+            const double om1 = a.omega1;
+#pragma unroll
+            for (int k = 0; k < kNM; ++k)
+                ag[k] = ag[k] + P(om1) * (P(gqe[k]) - ag[k]) + P(om) * (P(geq[k]) - P(gqe[k]));
+        }
+        const P decay = P(1.0 - om);
+#pragma unroll
+        for (int k = 1; k < kNM; ++k) af[k] *= decay;
+
+        // reconstruct and store the post-collision populations
+#pragma unroll 4
+        for (int i = 0; i < kQ; ++i) {
+            P fv = P(0), gv = P(0);
+#pragma unroll
+            for (int k = 0; k < kNM; ++k) {
+                fv += tab.herm[i][k] * af[k];
+                gv += tab.herm[i][k] * ag[k];
+            }
+            if (bad) fv = gv = P(NAN);
+            pop_plane<P>(dst.f, i, a.N)[n] = fv;
+            pop_plane<P>(dst.g, i, a.N)[n] = gv;
+        }
+        dst.ux[n] = bad ? NAN : ln0;
+        dst.uy[n] = bad ? NAN : ln1;
+        dst.T[n] = bad ? NAN : ln2;
+    }
+
+    // counters: one atomic per wave
+    const unsigned long long itc = wave_sum((unsigned long long)used);
+    const unsigned long long nc = wave_sum((unsigned long long)(live && !conv && !bad));
+    const unsigned long long nb = wave_sum((unsigned long long)(live && bad));
+    if ((threadIdx.x & 63) == 0) {
+        if (itc) atomicAdd(&cnt->pc_iterations, itc);
+        if (nc) atomicAdd(&cnt->nonconverged, nc);
+        if (nb) atomicAdd(&cnt->nonphysical, nb);
+    }
+}
+
+}  // namespace pond

@@ -29,8 +29,11 @@ EXPORTED = [
     "pond_abi_version", "pond_params_default", "pond_state_bytes", "pond_create",
     "pond_init_fields", "pond_step", "pond_moments", "pond_stats", "pond_synchronize",
     "pond_export_state", "pond_import_state", "pond_destroy", "pond_status_string",
-    "pond_last_error", "pond_profile_enable", "pond_profile_read",
+    "pond_last_error", "pond_profile_enable", "pond_profile_read", "pond_get_tuning",
+    "pond_set_tuning",
 ]
+KERNEL_TILED, KERNEL_GLOBAL = 0, 1
+TILE_16x16, TILE_32x8, TILE_16x8, TILE_8x8, TILE_256x1, TILE_64x1 = range(6)
 
 
 class pond_params(ctypes.Structure):
@@ -55,6 +58,11 @@ class pond_stats_t(ctypes.Structure):
 class pond_profile_t(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("prepass_ms", ctypes.c_double),
                 ("step_ms", ctypes.c_double)]
+
+
+class pond_tuning(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("lds_nodes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PondError(RuntimeError):
@@ -91,6 +99,8 @@ _L.pond_export_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _L.pond_import_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _L.pond_destroy.argtypes = [_vp]
 _L.pond_profile_enable.argtypes = [_vp, ctypes.c_int]
+_L.pond_get_tuning.argtypes = [_vp, ctypes.POINTER(pond_tuning)]
+_L.pond_set_tuning.argtypes = [_vp, ctypes.POINTER(pond_tuning)]
 _L.pond_profile_read.argtypes = [_vp, ctypes.POINTER(pond_profile_t)]
 _L.pond_status_string.argtypes = [ctypes.c_int]
 _L.pond_status_string.restype = ctypes.c_char_p
@@ -187,6 +197,23 @@ def pond_destroy(ctx):
     _check(_L.pond_destroy(ctx))
 
 
+def pond_get_tuning(ctx) -> pond_tuning:
+    t = pond_tuning()
+    _check(_L.pond_get_tuning(ctx, ctypes.byref(t)))
+    return t
+
+
+def pond_set_tuning(ctx, kernel=None, tile=None, lds_nodes=None):
+    t = pond_get_tuning(ctx)
+    if kernel is not None:
+        t.kernel = kernel
+    if tile is not None:
+        t.tile = tile
+    if lds_nodes is not None:
+        t.lds_nodes = lds_nodes
+    _check(_L.pond_set_tuning(ctx, ctypes.byref(t)))
+
+
 def pond_profile_enable(ctx, enable: bool):
     _check(_L.pond_profile_enable(ctx, 1 if enable else 0))
 
@@ -211,13 +238,15 @@ class Solver:
 
     def __init__(self, nx, ny, *, tau, gamma=1.4, prandtl=1.0, bc_x=BC_PERIODIC,
                  bc_y=BC_PERIODIC, precision=PREC_FP32, interp_points=4, pc_tol=0.0,
-                 pc_max_iter=32, stream=None):
+                 pc_max_iter=32, stream=None, tuning=None):
         self.params = pond_params_default(nx=nx, ny=ny, tau=tau, gamma=gamma, prandtl=prandtl,
                                           bc_x=bc_x, bc_y=bc_y, precision=precision,
                                           interp_points=interp_points, pc_tol=pc_tol,
                                           pc_max_iter=pc_max_iter)
         self.nx, self.ny = nx, ny
         self.ctx = pond_create(self.params, stream)
+        if tuning:
+            pond_set_tuning(self.ctx, **tuning)
 
     @classmethod
     def from_workload(cls, w, precision=PREC_FP32, **kw):

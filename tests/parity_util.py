@@ -24,7 +24,8 @@ def gpu_solver(w, precision, **kw):
 
 
 def gpu_run(w, precision, steps, **kw):
-    """Returns (f (16,N), g (16,N), frame (3,N), u_ref, stats, moments)."""
+    """Returns (f (16,N), g (16,N), frame (3,N), u_ref, stats, moments).
+    ``tuning={...}`` selects the kernel / tile / LDS capacity."""
     with gpu_solver(w, precision, **kw) as s:
         s.step(steps)
         f, g, fr, ur = s.export_state()

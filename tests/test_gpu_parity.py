@@ -259,3 +259,28 @@ def test_device_tensor_fields_and_caller_memory():
         np.testing.assert_array_equal(out[0].cpu().numpy().reshape(w.ny, w.nx), ref[5]["rho"])
     finally:
         pond.pond_destroy(ctx)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_kernels_tiles_and_lds_capacities_bitwise_equal(prec):
+    """The step is computed per node with a fixed operation order, so the
+    reference kernel (taps from HBM), the tiled kernel with every block shape,
+    and LDS capacities small enough to force the HBM fallback for part of the
+    taps all give the same bits (ragged 70 x 45 grid, Mach 2.5, clamp in x)."""
+    from paper_2405_11489_amd import pond
+    w = clamp_x(modes(70, 45, mach=2.5, amp=2e-2, seed=12))
+    ref = gpu_run(w, prec, 4, tuning={"kernel": pond.KERNEL_GLOBAL})
+    configs = [(pond.TILE_16x16, 0), (pond.TILE_32x8, 0), (pond.TILE_16x8, 0), (pond.TILE_8x8, 0),
+               (pond.TILE_64x1, 0), (pond.TILE_256x1, 0), (pond.TILE_16x16, 300),
+               (pond.TILE_8x8, 100)]
+    for tile, cap in configs:
+        out = gpu_run(w, prec, 4, tuning={"kernel": pond.KERNEL_TILED, "tile": tile, "lds_nodes": cap})
+        for x, y in zip(out[:3], ref[:3]):
+            np.testing.assert_array_equal(x, y, err_msg=f"tile {tile} cap {cap}")
+
+
+def test_quasi_1d_tiled_matches_oracle():
+    w = workloads.sod_tube(nx=300, nu=2e-3, steps=20)
+    f, g, fr, _, _, _ = gpu_run(w, FP64, w.steps)
+    _, s, _ = oracle_run(w, w.steps)
+    assert max(plane_errors(f, g, fr, s)) <= 1e-12
