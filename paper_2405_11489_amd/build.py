@@ -22,14 +22,16 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
-    """Compile libpond.so (always recompiles) and return its path."""
-    tmp = LIB + ".tmp"
+def build(verbose: bool = False, jobs: int = 2, defines=(), out: str = LIB) -> str:
+    """Compile libpond.so (always recompiles) and return its path.  ``defines``
+    are extra -D compile-time tuning macros; ``out`` the library path."""
+    tmp = out + ".tmp"
     objs = []
     procs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], *["-D" + d for d in defines], "-c",
+               os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))
@@ -41,10 +43,10 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":

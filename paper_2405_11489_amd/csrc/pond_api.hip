@@ -166,12 +166,16 @@ void fill_args(pond_ctx *c) {
 bool fp64(const pond_ctx *c) { return c->p.precision == POND_PREC_FP64; }
 
 int default_lds_nodes(int tile, bool dbl) {
-    // The step kernels hold two waves per SIMD (register-limited), i.e. two
-    // 256-lane or four 128-lane blocks per CU; split the 160 KiB of LDS between
-    // them.  A 16 x 16 tile at T = 1, Mach 2 needs a 26 x 26 source region.
+    // The step kernels are register-limited to two waves per SIMD in FP32 and
+    // one in FP64, i.e. 8 or 4 waves per CU; split the 160 KiB of LDS between
+    // the blocks that fit.  A 16 x 16 tile at T = 1, Mach 2 needs a 26 x 26
+    // source region.
     int tx, ty;
     tile_dims(static_cast<TileShape>(tile), tx, ty);
-    const int blocks_per_cu = tx * ty >= 256 ? 2 : 4;
+    const int waves_per_block = (tx * ty + 63) / 64;
+    const int waves_per_cu = dbl ? 4 : 8;
+    int blocks_per_cu = waves_per_cu / waves_per_block;
+    if (blocks_per_cu < 1) blocks_per_cu = 1;
     const int bytes = 160 * 1024 / blocks_per_cu - 1024;
     return bytes / (dbl ? 160 : 80);
 }
@@ -190,7 +194,7 @@ pond_tuning default_tuning(const pond_params &p) {
     if (p.ny < 8)
         t.tile = POND_TILE_64x1;
     else
-        t.tile = p.precision == POND_PREC_FP64 ? POND_TILE_16x8 : POND_TILE_16x16;
+        t.tile = p.precision == POND_PREC_FP64 ? POND_TILE_16x8 : POND_TILE_32x8;
     t.lds_nodes = default_lds_nodes(t.tile, p.precision == POND_PREC_FP64);
     t.reserved = 0;
     return t;

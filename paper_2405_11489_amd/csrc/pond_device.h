@@ -131,6 +131,7 @@ __device__ __forceinline__ void hermite_from_central(const P m[kNM], P a[kNM]) {
 // m = floor(y + 1/2) (quadratic).  Returns the first node.
 template <int NP, typename P>
 __device__ __forceinline__ int lagrange(double y, P w[NP]) {
+    y = fmin(fmax(y, -1.0e9), 1.0e9);  // keeps the node index representable
     if constexpr (NP == 4) {
         const double fl = floor(y);
         const P d = P(y - fl);

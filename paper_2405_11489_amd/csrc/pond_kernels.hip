@@ -130,8 +130,8 @@ struct TileTaps {
         const bool inside = bx >= X0 && bx + NP - 1 <= X1 && by >= Y0 && by + NP - 1 <= Y1;
         if (inside) {
             const int base = (by - Y0) * W + (bx - X0);
-            // one stencil row at a time: bounds the loads in flight per lane
-#pragma unroll 1
+            // POND_ROW_UNROLL stencil rows per trip: bounds the loads in flight per lane
+#pragma unroll POND_ROW_UNROLL
             for (int q = 0; q < NP; ++q)
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
@@ -185,8 +185,19 @@ __device__ __forceinline__ void stencil_extent(int x, double u, double s, int &l
     }
 }
 
+// Minimum waves per SIMD requested from the register allocator for the tiled
+// kernel (compile-time tuning; 0 leaves the choice to the compiler).
+#ifndef POND_TILED_WAVES_PER_EU
+#define POND_TILED_WAVES_PER_EU 0
+#endif
+#if POND_TILED_WAVES_PER_EU > 0
+#define POND_TILED_ATTR __attribute__((amdgpu_waves_per_eu(POND_TILED_WAVES_PER_EU)))
+#else
+#define POND_TILED_ATTR
+#endif
+
 template <typename P, int NP, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void step_tiled_kernel(StepArgs a, DevState src,
+__global__ __launch_bounds__(TX *TY) POND_TILED_ATTR void step_tiled_kernel(StepArgs a, DevState src,
                                                             const P *__restrict__ mom,
                                                             DevState dst, DevCounters *cnt,
                                                             int cap, int halo_cap, int tiles_x) {

@@ -11,6 +11,12 @@
 
 #include <utility>
 
+// Stencil rows interpolated per loop trip in the tap gather (compile-time
+// tuning: more rows in flight hide more LDS latency at the cost of registers).
+#ifndef POND_ROW_UNROLL
+#define POND_ROW_UNROLL 1
+#endif
+
 #include "pond_device.h"
 #include "pond_internal.h"
 
@@ -107,7 +113,7 @@ struct GlobalTaps {
         int col[NP];
 #pragma unroll
         for (int j = 0; j < NP; ++j) col[j] = wrap_index(bx + j, nx, bc_x);
-#pragma unroll 1
+#pragma unroll POND_ROW_UNROLL
         for (int q = 0; q < NP; ++q) {
             const long long row = (long long)wrap_index(by + q, ny, bc_y) * nx;
 #pragma unroll
@@ -129,6 +135,31 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Coefficients B with pop_i = sum_j B_j M_j for raw moments M (about u_ref):
+// the reconstruction weights r of velocity i on the normalised central
+// moments about d = (dx, dy) (frame velocity - u_ref) with scale is = 1/sqrt(T),
+// composed with that shift and scaling (the transpose of central_normalised).
+// One coefficient vector serves both f and g.
+template <typename P>
+__device__ __forceinline__ void pop_coeffs(const P r[kNM], P dx, P dy, P is, P B[kNM]) {
+    const P is2 = is * is, is3 = is2 * is;
+    const P r00 = r[0], r10 = r[1] * is, r01 = r[2] * is;
+    const P r20 = r[3] * is2, r11 = r[4] * is2, r02 = r[5] * is2;
+    const P r30 = r[6] * is3, r21 = r[7] * is3, r12 = r[8] * is3, r03 = r[9] * is3;
+    const P ex = -dx, ey = -dy, exx = ex * ex, eyy = ey * ey, exy = ex * ey;
+    B[9] = r03;
+    B[8] = r12;
+    B[7] = r21;
+    B[6] = r30;
+    B[5] = r02 + ex * r12 + P(3) * ey * r03;
+    B[4] = r11 + P(2) * ex * r21 + P(2) * ey * r12;
+    B[3] = r20 + P(3) * ex * r30 + ey * r21;
+    B[2] = r01 + ex * r11 + P(2) * ey * r02 + exx * r21 + P(2) * exy * r12 + P(3) * eyy * r03;
+    B[1] = r10 + P(2) * ex * r20 + ey * r11 + P(3) * exx * r30 + P(2) * exy * r21 + eyy * r12;
+    B[0] = r00 + ex * r10 + ey * r01 + exx * r20 + exy * r11 + eyy * r02 + exx * ex * r30 +
+           exx * ey * r21 + ex * eyy * r12 + eyy * ey * r03;
 }
 
 template <typename P>
@@ -188,14 +219,14 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                 for (int k = 0; k < kNM; ++k) If[k] = Ig[k] = P(0);
                 taps.gather(bx, by, wx, wy, If, Ig);
                 // frame transformation of the interpolated moments: population i
-                P m[kNM];
-                central_normalised(If, dux, duy, is, m);
+                P B[kNM];
+                pop_coeffs(tab.recon[i], dux, duy, is, B);
                 P fi = P(0), gi = P(0);
 #pragma unroll
-                for (int k = 0; k < kNM; ++k) fi += tab.recon[i][k] * m[k];
-                central_normalised(Ig, dux, duy, is, m);
-#pragma unroll
-                for (int k = 0; k < kNM; ++k) gi += tab.recon[i][k] * m[k];
+                for (int k = 0; k < kNM; ++k) {
+                    fi += B[k] * If[k];
+                    gi += B[k] * Ig[k];
+                }
                 // conserved moments in FP64
                 const double fd = double(fi);
                 r += fd;
