@@ -47,10 +47,47 @@ FLOPS64_PER_NODE = 60
 # moment planes read 80, populations + frame written 128 + 24.
 BYTES_STEP_FP32 = 24 + 80 + 152
 BYTES_STEP_FP64 = 24 + 160 + 280
+TILE_DIMS = {0: "16,16", 1: "32,8", 2: "16,8", 3: "8,8", 4: "256,1", 5: "64,1"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    """sha256 over the kernel sources (csrc/*.h, *.hip, by file name): ties an
+    HBM-traffic record in profiles/ to the code it was measured on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2405_11489_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(d, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def traffic_record(kernel, precision):
+    """HBM bytes per launch of ``kernel`` from a 'traffic-record:' line of a
+    profiles/*.md summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled
+    by the same counter's reading for a plain copy of known size), or None when
+    no record matches the current kernel sources."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None
+    want = kernel_source_hash()
+    for name in sorted(os.listdir(d)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(d, name)) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+                if (kv.get("kernel") == kernel and kv.get("precision") == precision
+                        and kv.get("sources_sha256") == want):
+                    return float(kv["bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(w, seconds):
@@ -68,13 +105,16 @@ def cpu_baseline(w, seconds):
     oracle.step_nodes(P, s, pilot)
     step_s = (time.perf_counter() - t0) / len(pilot) * w.nodes
     if step_s <= seconds:
-        nsteps = max(1, int(seconds / step_s))
-        t0 = time.perf_counter()
-        _, st = oracle.step(P, s, nsteps)
-        dt = time.perf_counter() - t0
+        nsteps, iters, dt = 0, 0, 0.0
+        while dt < seconds:
+            t0 = time.perf_counter()
+            s, st = oracle.step(P, s, 1)
+            dt += time.perf_counter() - t0
+            nsteps += 1
+            iters += st.total_iters
         updates = nsteps * w.nodes
         sample = (f"{nsteps} whole-grid step(s) of the {w.nx}x{w.ny} workload from its initial "
-                  f"state (mean {st.total_iters / updates:.2f} PC gathers), {dt:.1f} s")
+                  f"state (mean {iters / updates:.2f} PC gathers), {dt:.1f} s")
     else:
         count = int(max(1024, seconds / step_s * w.nodes))
         nodes = rng.permutation(w.nodes)[:count]
@@ -100,6 +140,9 @@ def main():
     ap.add_argument("--kernel", choices=["tiled", "global"], default="tiled")
     ap.add_argument("--tile", type=int, default=None, help="POND_TILE_* id (default: library's)")
     ap.add_argument("--lds-nodes", type=int, default=None)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the timed region, run 3 plain device copies of MIB MiB each "
+                         "(the reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -145,6 +188,15 @@ def main():
     pond.pond_profile_enable(sol.ctx, False)
     st1 = sol.stats()
     sol.close()
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {n * 4} bytes read + written")
+        del a, b
 
     N = w.nodes
     updates = N * args.steps
@@ -156,21 +208,25 @@ def main():
         f"kernels: step {step_ms:.4f} ms, prepass {pre_ms:.4f} ms per launch")
 
     flops = N * (FLOPS_PER_ITER * kbar + FLOPS_PER_NODE)
+    kname = f"step_tiled_kernel<{'float' if prec == pond.PREC_FP32 else 'double'},{args.interp_points}," \
+            f"{TILE_DIMS[tun.tile]}>" if args.kernel == "tiled" else \
+            f"step_kernel<{'float' if prec == pond.PREC_FP32 else 'double'},{args.interp_points}>"
+    traffic = traffic_record(kname, args.precision)
     if prec == pond.PREC_FP32:
         achieved = flops / (step_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch",
                 "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
                 "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
-                "kernel": "step_tiled_kernel<float,4,..>" if args.kernel == "tiled" else "step_kernel<float,4>",
-                "flops_per_launch": flops,
+                "kernel": kname, "flops_per_launch": flops,
                 "hbm_GBs_algorithmic": N * BYTES_STEP_FP32 / (step_ms * 1e-3) / 1e9}
     else:
         achieved = flops / (step_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "kernel": "step_tiled_kernel<double,4,..>" if args.kernel == "tiled" else "step_kernel<double,4>",
-                "flops_per_launch": flops,
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch",
+                "kernel": kname, "flops_per_launch": flops,
                 "hbm_GBs_algorithmic": N * BYTES_STEP_FP64 / (step_ms * 1e-3) / 1e9}
 
     cpu = None
