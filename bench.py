@@ -128,6 +128,205 @@ def cpu_baseline(w, seconds):
             "kind": "oracle", "sample": sample}
 
 
+def _ctx_for(pond, w, prec, stream=None):
+    p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma, prandtl=w.prandtl,
+                                 bc_x=w.bc_x, bc_y=w.bc_y, precision=prec)
+    c = pond.pond_create(p, stream)
+    pond.pond_init_fields(c, *[np.ascontiguousarray(a.ravel()) for a in (w.rho, w.ux, w.uy, w.T)])
+    return c
+
+
+def bench_batch(args, pond, workloads):
+    """Mixed batch: half quasi-1-D shock tubes (256..8192 nodes), half 2-D
+    perturbed flows (64^2..1024^2), Mach 0.5..3, 200..2000 steps each.  Timed:
+    every instance to its own step count through batches (one batch per
+    phase; a phase runs until the next instance finishes, then the finished
+    ones leave).  Plain: each instance alone with pond_step, timed over its
+    first min(steps, 200) steps and scaled to its step count."""
+    import torch
+    prec = pond.PREC_FP32 if args.precision == "fp32" else pond.PREC_FP64
+    max_size = args.max_size or 1024
+    max_steps = args.max_steps or 2000
+    ws = workloads.batch_instances(seed=0, count=args.instances, flow_range=(64, max_size),
+                                   steps_range=(min(200, max_steps), max_steps))
+    updates = sum(w.nodes * w.steps for w in ws)
+    log(f"batch: {len(ws)} instances, {sum(w.nodes for w in ws)} nodes, {updates:.3e} node-updates")
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    # autotune one instance of every size class (untimed)
+    t0 = time.perf_counter()
+    pond.pond_tuning_cache_clear()
+    seen = set()
+    for w in ws:
+        key = (w.ny == 1, round(math.log2(w.nx)), round(math.log2(max(w.ny, 1))))
+        if key in seen:
+            continue
+        seen.add(key)
+        c = _ctx_for(pond, w, prec, sp)
+        pond.pond_autotune(c, 2)
+        pond.pond_destroy(c)
+    log(f"autotuned {len(seen)} size classes in {time.perf_counter() - t0:.1f} s")
+
+    # plain path
+    plain_s = 0.0
+    for i, w in enumerate(ws):
+        c = _ctx_for(pond, w, prec, sp)
+        k = min(w.steps, 200)
+        pond.pond_step(c, 2)
+        pond.pond_synchronize(c)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        pond.pond_step(c, k)
+        e1.record(stream)
+        e1.synchronize()
+        plain_s += e0.elapsed_time(e1) * 1e-3 * w.steps / k
+        pond.pond_destroy(c)
+        if i % 32 == 31:
+            log(f"plain: {i + 1} instances timed")
+    plain = updates / plain_s / 1e6
+
+    # batched
+    ctxs = [_ctx_for(pond, w, prec, sp) for w in ws]
+    remaining = [w.steps for w in ws]
+    active = list(range(len(ws)))
+    torch.cuda.synchronize()
+    phases = 0
+    tiles = []
+    t0 = time.perf_counter()
+    while active:
+        b = pond.pond_batch_create([ctxs[i] for i in active], sp)
+        tiles.append(pond.pond_batch_get_info(b).tiles)
+        k = min(remaining[i] for i in active)
+        pond.pond_batch_step(b, k)
+        pond.pond_batch_synchronize(b)
+        pond.pond_batch_destroy(b)
+        for i in active:
+            remaining[i] -= k
+        active = [i for i in active if remaining[i] > 0]
+        phases += 1
+        if phases % 32 == 0:
+            log(f"batched: {phases} phases, {len(active)} instances left")
+    wall = time.perf_counter() - t0
+    nonconv = sum(pond.pond_stats(c).nonconverged for c in ctxs)
+    iters = sum(pond.pond_stats(c).pc_iterations for c in ctxs)
+    for c in ctxs:
+        pond.pond_destroy(c)
+    batched = updates / wall / 1e6
+    log(f"batched {batched:.1f} MLUPS in {wall:.2f} s over {phases} phases; plain {plain:.1f} MLUPS")
+    return {
+        "metric": "PonD f+g MLUPS (batched)", "value": batched, "unit": "MLUPS", "n_gpus": 1,
+        "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if prec == pond.PREC_FP32 else "f64", "data": "synthetic",
+        "config": {"workload": f"mixed_batch_{len(ws)}", "instances": len(ws),
+                   "tubes": "nx 256..8192 x 1, clamp x", "flows": f"64^2..{max_size}^2 periodic",
+                   "mach": "0.5..3", "steps": f"{min(200, max_steps)}..{max_steps}",
+                   "precision": args.precision, "parallelism": "single_gpu"},
+        "node_updates": updates, "wall_s": wall, "phases": phases,
+        "tiles_first_phase": tiles[0], "pc_iterations_mean": iters / updates,
+        "nonconverged_node_steps": nonconv,
+        "plain": {"value": plain, "unit": "MLUPS",
+                  "how": "each instance alone (pond_step), min(steps, 200) steps timed with "
+                         "HIP events, scaled to its step count"},
+        "speedup_vs_plain": batched / plain,
+    }
+
+
+def bench_serve(args, pond, workloads):
+    """Serving: requests of three kinds (shock tube on an N x N grid, shear
+    flow, 2-D Riemann), N log-uniform in [64, max_size], steps log-uniform in
+    [100, max_steps].  First every request runs alone (plain path, FIFO) to
+    measure its service time; the plain capacity is requests / total service
+    time.  Then the same requests arrive as a Poisson stream at ``load`` times
+    that capacity and go through the continuous-batching server (HBM budget
+    ``budget_gib``); the serial FIFO latencies for the same arrival times
+    follow from the measured service times."""
+    import torch
+    max_size = args.max_size or 1024
+    max_steps = args.max_steps or 2000
+    reqs = workloads.serving_requests(seed=0, count=args.instances, size_range=(64, max_size),
+                                      steps_range=(100, max_steps))
+    ws = [w for _, w in reqs]
+    updates = sum(w.nodes * w.steps for w in ws)
+    log(f"serve: {len(ws)} requests, {updates:.3e} node-updates")
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    service, plain_failed = [], 0
+    for i, w in enumerate(ws):
+        t0 = time.perf_counter()
+        c = _ctx_for(pond, w, pond.PREC_FP32, sp)
+        pond.pond_step(c, w.steps)
+        try:
+            pond.pond_moments(c, np.zeros(w.nodes))
+        except pond.PondError as e:
+            if e.status != pond.ERR_NONPHYSICAL:
+                raise
+            plain_failed += 1
+            log(f"request {i} ({w.name} {w.nx}x{w.ny}) went non-physical")
+        pond.pond_destroy(c)
+        service.append(time.perf_counter() - t0)
+        if i % 32 == 31:
+            log(f"plain: {i + 1} requests served")
+    total = sum(service)
+    capacity = len(ws) / total
+    rng = np.random.default_rng(1)
+    arrivals = np.cumsum(rng.exponential(1.0 / (args.load * capacity), size=len(ws)))
+    end, serial_lat = 0.0, []
+    for a, s_ in zip(arrivals, service):
+        end = max(end, a) + s_
+        serial_lat.append(end - a)
+
+    cfg = pond.pond_server_config_default(hbm_budget_bytes=int(args.budget_gib * (1 << 30)))
+    if args.fill_nodes is not None:
+        cfg.fill_nodes = args.fill_nodes
+    srv = pond.pond_server_create(cfg)
+    ids = []
+    t0 = time.perf_counter()
+    for i, (a, w) in enumerate(zip(arrivals, ws)):
+        delay = a - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma,
+                                     prandtl=w.prandtl, bc_x=w.bc_x, bc_y=w.bc_y)
+        ids.append(pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, w.steps))
+        if i % 32 == 31:
+            log(f"served: {i + 1} requests submitted")
+    pond.pond_server_wait(srv, 0)
+    wall = time.perf_counter() - t0
+    infos = [pond.pond_server_poll(srv, i) for i in ids]
+    st = pond.pond_server_get_stats(srv)
+    pond.pond_server_destroy(srv)
+    failed = sum(inf.state != pond.REQ_DONE for inf in infos)
+    lat = np.array([inf.t_done - inf.t_submit for inf in infos])
+    first = min(inf.t_submit for inf in infos)
+    last = max(inf.t_done for inf in infos)
+    served = updates / (last - first) / 1e6
+    plain = updates / total / 1e6
+    sl = np.array(serial_lat)
+    log(f"served {served:.1f} MLUPS, p50 {np.percentile(lat, 50):.3f} s, p99 "
+        f"{np.percentile(lat, 99):.3f} s; serial FIFO p50 {np.percentile(sl, 50):.3f} s, p99 "
+        f"{np.percentile(sl, 99):.3f} s; plain {plain:.1f} MLUPS")
+    return {
+        "metric": "PonD f+g MLUPS (served)", "value": served, "unit": "MLUPS", "n_gpus": 1,
+        "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"poisson_requests_{len(ws)}", "requests": len(ws),
+                   "sizes": f"N x N, N log-uniform 64..{max_size}",
+                   "steps": f"log-uniform 100..{max_steps}", "load": args.load,
+                   "hbm_budget_gib": args.budget_gib, "chunk_steps": cfg.chunk_steps,
+                   "fill_nodes": cfg.fill_nodes,
+                   "parallelism": "single_gpu"},
+        "node_updates": updates, "failed": failed, "failed_plain": plain_failed, "wall_s": wall,
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "mean": float(lat.mean())},
+        "serial_fifo": {"plain_MLUPS": plain, "capacity_req_per_s": capacity,
+                        "latency_s": {"p50": float(np.percentile(sl, 50)),
+                                      "p99": float(np.percentile(sl, 99)),
+                                      "mean": float(sl.mean())}},
+        "server_stats": {k: getattr(st, k) for k, _ in st._fields_},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +339,18 @@ def main():
     ap.add_argument("--kernel", choices=["tiled", "global"], default="tiled")
     ap.add_argument("--tile", type=int, default=None, help="POND_TILE_* id (default: library's)")
     ap.add_argument("--lds-nodes", type=int, default=None)
+    ap.add_argument("--workload", choices=["modes512", "batch", "serve"], default="modes512",
+                    help="modes512: one 512^2 Mach-2 instance (headline); batch: the mixed "
+                         "256-instance batch; serve: a Poisson request stream through the server")
+    ap.add_argument("--instances", type=int, default=256, help="batch / serve: instance count")
+    ap.add_argument("--max-size", type=int, default=None,
+                    help="batch: largest 2-D side (default 1024); serve: largest side (default 1024)")
+    ap.add_argument("--max-steps", type=int, default=None,
+                    help="batch: most steps (default 2000); serve: most steps (default 2000)")
+    ap.add_argument("--budget-gib", type=float, default=2.0, help="serve: HBM admission budget")
+    ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / plain capacity")
+    ap.add_argument("--fill-nodes", type=int, default=None,
+                    help="serve: server fill_nodes (0 = step every admitted request each round)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed region, run 3 plain device copies of MIB MiB each "
                          "(the reference kernel for scaling HBM byte counters)")
@@ -154,6 +365,12 @@ def main():
     from paper_2405_11489_amd import pond, workloads
 
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        print(json.dumps(bench_batch(args, pond, workloads)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args, pond, workloads)), flush=True)
+        return
     prec = pond.PREC_FP32 if args.precision == "fp32" else pond.PREC_FP64
     w = workloads.fourier_modes(n=512, mach=2.0, angle_deg=30.0, amplitude=1e-3, seed=0,
                                 tau=0.55, prandtl=0.71, gamma=1.4, steps=2000)

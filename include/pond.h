@@ -184,8 +184,10 @@ POND_API pond_status pond_import_state(pond_ctx *c, const double *f, const doubl
  *   tile:      POND_TILE_* block shape of the tiled kernel (destination nodes).
  *   lds_nodes: LDS capacity per block, in nodes (20 moments each: 80 B in FP32,
  *              160 B in FP64); taps outside the staged region read HBM.
+ *   batch_tile_width: tile of this context when it steps inside a pond_batch.
  * pond_set_tuning validates the values (POND_ERR_INVALID_ARG otherwise);
- * lds_nodes <= 0 selects the default for the tile. */
+ * lds_nodes <= 0 selects the default for the tile.  Refused (POND_ERR_STATE)
+ * while the context is a member of a batch. */
 enum { POND_KERNEL_TILED = 0, POND_KERNEL_GLOBAL = 1 };
 enum { POND_TILE_16x16 = 0, POND_TILE_32x8 = 1, POND_TILE_16x8 = 2, POND_TILE_8x8 = 3,
        POND_TILE_256x1 = 4, POND_TILE_64x1 = 5 };
@@ -193,7 +195,8 @@ typedef struct {
     int32_t kernel;
     int32_t tile;
     int32_t lds_nodes;
-    int32_t reserved;
+    int32_t batch_tile_width;  /* batched step: tile width in {16, 32, 64, 128, 256}
+                                  (height 256 / width); 0 = autotuned or default */
 } pond_tuning;
 
 POND_API pond_status pond_get_tuning(pond_ctx *c, pond_tuning *out);
@@ -215,8 +218,176 @@ POND_API pond_status pond_profile_enable(pond_ctx *c, int enable);
 /* Synchronise, then report the timing accumulated since pond_profile_enable(c, 1). */
 POND_API pond_status pond_profile_read(pond_ctx *c, pond_profile_t *out);
 
-/* Release the context and the memory it allocated.  NULL-safe. */
+/* Release the context and the memory it allocated.  NULL-safe.  Refused
+ * (POND_ERR_STATE) while the context is a member of a batch. */
 POND_API pond_status pond_destroy(pond_ctx *c);
+
+/* ------------------------------------------------------------- batches ----
+ * A batch advances several contexts together, each by the same step as
+ * pond_step (the step of Sec. "Discrete velocity solver ...: PonD" with
+ * Eq. propagationInterpolated; results are bit for bit those of pond_step on
+ * the member alone).  One batched step is one moment pre-pass over the nodes
+ * of every member and one persistent step launch whose blocks take tiles of
+ * any member from eight work queues (one per XCD); both launches are replayed
+ * from HIP graphs captured at creation.
+ *
+ * Members must be initialised, not in the error state, not in another batch,
+ * and share precision and interp_points; sizes, boundary conditions and
+ * physical parameters may differ.  While a context is a member it refuses
+ * pond_step, pond_init_fields, pond_import_state, pond_set_tuning and
+ * pond_destroy (POND_ERR_STATE); pond_moments, pond_stats and
+ * pond_export_state stay available and see every batched step enqueued
+ * before them.  The batch does not own its members: destroy the batch, then
+ * the contexts. */
+typedef struct pond_batch pond_batch; /* opaque */
+
+typedef struct {
+    int32_t members;      /* contexts in the batch */
+    int32_t tiles;        /* tiles per batched step, all members */
+    int32_t grid_blocks;  /* blocks of the persistent step launch */
+    int32_t lds_nodes;    /* LDS capacity per block, in nodes */
+    int64_t nodes;        /* nodes per batched step, all members */
+    int64_t steps;        /* batched steps enqueued since creation */
+    int32_t graph_steps;  /* steps per launch of the larger captured graph */
+    int32_t reserved;
+} pond_batch_info_t;
+
+/* Build a batch of n contexts (array of n distinct handles, copied).
+ * hip_stream: stream of the batched steps (NULL: the batch creates its own).
+ * Synchronises the members' streams.  Each member steps with tiles of width
+ * pond_tuning.batch_tile_width, else the autotuned width of its size class,
+ * else a default (32 in FP32, 16 in FP64, 256 for grids of fewer than 8
+ * rows).  Allocates a small device table (members x ~200 bytes). */
+POND_API pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream,
+                                       pond_batch **out);
+
+/* Enqueue nsteps (>= 0) batched steps; asynchronous.  Refused
+ * (POND_ERR_STATE) once a member is known to be in the error state. */
+POND_API pond_status pond_batch_step(pond_batch *b, int64_t nsteps);
+
+/* Wait for the batch's stream, then read every member's flags: members with
+ * non-physical values enter the error state and the call returns
+ * POND_ERR_NONPHYSICAL (the other members are unaffected and their results
+ * stay valid). */
+POND_API pond_status pond_batch_synchronize(pond_batch *b);
+
+POND_API pond_status pond_batch_get_info(pond_batch *b, pond_batch_info_t *out);
+
+/* Tile width the batch uses for member i (0 <= i < members). */
+POND_API pond_status pond_batch_member_tile_width(pond_batch *b, int i, int *width);
+
+/* Synchronise, release the batch's graphs and table, and return the members
+ * to single-context use.  NULL-safe. */
+POND_API pond_status pond_batch_destroy(pond_batch *b);
+
+/* Autotuner: time `steps` (>= 1) steps of c with each candidate tile shape
+ * of the single-context kernel and each candidate batch tile width (one-member
+ * batches), restoring c's state, step count and counters after every
+ * candidate; apply the fastest of each to c, store them for c's size class
+ * (precision, stencil, boundary conditions, rounded log2 of nx and of ny) in a
+ * process-wide cache that pond_create and pond_batch_create consult, and
+ * return them in *out (nullable).  Allocates one state buffer's worth of
+ * device memory while it runs.  Every candidate computes the same numbers. */
+POND_API pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out);
+
+/* Forget every autotuned size class. */
+POND_API pond_status pond_tuning_cache_clear(void);
+
+/* -------------------------------------------------------------- serving ----
+ * A server takes requests (parameters, initial fields, step count), queues
+ * them first in, first out, and serves them with continuous batching: a worker
+ * thread admits the head of the queue whenever its footprint
+ * (pond_state_bytes) fits the HBM budget next to the admitted requests; each
+ * round it steps, through one pond_batch (rebuilt when the selection
+ * changes), the admitted requests with the least remaining work until the
+ * round holds fill_nodes nodes (shortest-remaining-work first, filled to keep
+ * the chip busy); it re-examines the queue every chunk_steps steps and as
+ * soon as a request finishes, and releases a finished request's device memory
+ * after copying its outputs to host memory.  Each request's results are those
+ * of pond_step on it alone (the step of Sec. "Discrete velocity solver ...:
+ * PonD"), whatever traffic it shared the GPU with.  All API calls are
+ * thread-safe; the server owns every context it creates. */
+typedef struct pond_server pond_server; /* opaque */
+
+typedef struct {
+    uint32_t struct_size;      /* = sizeof(pond_server_config) */
+    int32_t precision;         /* POND_PREC_* shared by all requests (default FP32) */
+    int32_t interp_points;     /* 3 or 4, shared by all requests (default 4) */
+    int32_t max_members;       /* cap on running requests; <= 0: none (default) */
+    int64_t hbm_budget_bytes;  /* admission cap on the summed pond_state_bytes of running
+                                  requests (default 64 GiB) */
+    int64_t chunk_steps;       /* batched steps between queue checks; 0: run until the
+                                  next request finishes (default 64) */
+    int64_t fill_nodes;        /* each round steps the requests with the least remaining
+                                  work (nodes x steps) until the round holds this many
+                                  nodes; <= 0: every admitted request (default 2^19) */
+    int64_t autotune_steps;    /* > 0: pond_autotune (with this many steps) the first
+                                  request of every new size class at admission
+                                  (default 0) */
+} pond_server_config;
+
+enum { POND_REQ_QUEUED = 0, POND_REQ_RUNNING = 1, POND_REQ_DONE = 2, POND_REQ_FAILED = 3 };
+/* Request flags: outputs kept in host memory at completion. */
+enum { POND_REQ_KEEP_MOMENTS = 1, /* rho, u_x, u_y, T, p: 5 N doubles */
+       POND_REQ_KEEP_STATE = 2 }; /* pond_export_state layout + u_ref: 35 N + 2 doubles */
+
+typedef struct {
+    int32_t state;        /* POND_REQ_* */
+    int32_t error;        /* pond_status of a failed request (POND_ERR_NONPHYSICAL, ...) */
+    int64_t steps_done;
+    int64_t steps_total;
+    int64_t state_bytes;  /* its footprint against the budget */
+    double t_submit;      /* seconds since pond_server_create (steady clock) */
+    double t_admit;       /* -1 until admitted */
+    double t_done;        /* -1 until finished; latency = t_done - t_submit */
+} pond_request_info;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed;
+    int64_t admission_waits;  /* rounds in which the queue head did not fit */
+    int64_t batch_builds;     /* batches built (membership changes) */
+    int64_t batched_steps;    /* batched steps run */
+    int64_t node_updates;     /* node updates of all requests */
+    int64_t queued, running;  /* now */
+    int64_t used_bytes;       /* footprint of the running requests now */
+} pond_server_stats_t;
+
+POND_API pond_status pond_server_config_default(pond_server_config *c);
+
+/* Start a server (and its worker thread) on the current device, with its own
+ * stream. */
+POND_API pond_status pond_server_create(const pond_server_config *cfg, pond_server **out);
+
+/* Queue a request.  The four fields (host memory, nx * ny doubles each, layout
+ * of pond_init_fields) are copied before the call returns.  Requests whose
+ * parameters are invalid, whose precision or interp_points differ from the
+ * server's, or whose footprint exceeds the whole budget are refused
+ * (POND_ERR_INVALID_ARG); invalid field values fail the request at admission.
+ * *id > 0 identifies it. */
+POND_API pond_status pond_server_submit(pond_server *s, const pond_params *p, const double *rho,
+                                        const double *ux, const double *uy, const double *T,
+                                        int64_t nsteps, int32_t flags, int64_t *id);
+
+POND_API pond_status pond_server_poll(pond_server *s, int64_t id, pond_request_info *out);
+
+/* Block until request id has finished (id = 0: until every submitted request
+ * has finished). */
+POND_API pond_status pond_server_wait(pond_server *s, int64_t id);
+
+/* Copy a finished request's kept outputs (nullable destinations; host
+ * memory): moments 5 N doubles (rho, u_x, u_y, T, p), state 35 N + 2 doubles
+ * (f, g, frame, u_ref as pond_export_state).  A failed request returns its
+ * error. */
+POND_API pond_status pond_server_result(pond_server *s, int64_t id, double *moments, double *state);
+
+/* Drop a finished request's record and outputs. */
+POND_API pond_status pond_server_release(pond_server *s, int64_t id);
+
+POND_API pond_status pond_server_get_stats(pond_server *s, pond_server_stats_t *out);
+
+/* Drop the queued requests, let the running ones finish, stop the worker and
+ * free everything.  NULL-safe. */
+POND_API pond_status pond_server_destroy(pond_server *s);
 
 /* Static description of a status code (never NULL). */
 POND_API const char *pond_status_string(pond_status s);

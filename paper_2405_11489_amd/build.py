@@ -3,6 +3,11 @@
 hipcc compiles the kernels and the C-ABI host code into one shared library next
 to this file.  Packed-FP32 instructions are disabled for all device code; hipcc's
 host pass warns that it does not know that target feature, which is harmless.
+
+Floating-point contraction is limited to single source expressions
+(-ffp-contract=on): a multiply-add is fused the same way wherever the per-node
+code is inlined, so every kernel variant (HBM gather, each tile shape, the
+batched persistent kernel) produces the same bits.
 """
 import os
 import subprocess
@@ -11,11 +16,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpond.so")
-SOURCES = ["pond_kernels.hip", "pond_api.hip"]
+SOURCES = ["pond_kernels.hip", "pond_batch.hip", "pond_server.hip", "pond_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,

@@ -18,16 +18,16 @@
 #include <string>
 #include <vector>
 
-#include "pond.h"
-#include "pond_internal.h"
+#include "pond_ctx.h"
 
 using namespace pond;
 
+namespace pond {
+
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-pond_status fail(pond_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 pond_status fail(pond_status s, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -42,18 +42,7 @@ pond_status hip_fail(hipError_t e, const char *what) {
     return fail(POND_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-constexpr size_t kAlign = 256;
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-struct Layout {
-    size_t pop_bytes;    // one set of 16 planes
-    size_t frame_bytes;  // one frame plane
-    size_t buf_bytes;    // one state buffer
-    size_t mom_bytes;    // 20 moment planes
-    size_t cnt_off, scratch_off, total;
-};
-
-constexpr int kScratchDoubles = 3 * 256;
+const char *last_error() { return g_last_error.c_str(); }
 
 Layout layout_for(long long N, size_t psize) {
     Layout L;
@@ -66,6 +55,46 @@ Layout layout_for(long long N, size_t psize) {
     L.total = L.scratch_off + align_up(kScratchDoubles * sizeof(double));
     return L;
 }
+
+int default_lds_nodes_for_threads(int threads, bool dbl) {
+    // The step kernels are register-limited to two waves per SIMD in FP32 and
+    // one in FP64, i.e. 8 or 4 waves per CU; split the 160 KiB of LDS between
+    // the blocks that fit.  A 16 x 16 tile at T = 1, Mach 2 needs a 26 x 26
+    // source region.
+    const int waves_per_block = (threads + 63) / 64;
+    const int waves_per_cu = dbl ? 4 : 8;
+    int blocks_per_cu = waves_per_cu / waves_per_block;
+    if (blocks_per_cu < 1) blocks_per_cu = 1;
+    const int bytes = 160 * 1024 / blocks_per_cu - 1024;
+    return bytes / (dbl ? 160 : 80);
+}
+
+pond_status check_ctx(const pond_ctx *c, bool need_init) {
+    if (!c) return fail(POND_ERR_INVALID_ARG, "context is NULL");
+    if (need_init && !c->initialized)
+        return fail(POND_ERR_STATE, "context has no state (call pond_init_fields first)");
+    return POND_OK;
+}
+
+pond_status read_counters(pond_ctx *c, DevCounters *out) {
+    hipError_t e = hipMemcpyAsync(out, c->cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counters)");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return POND_OK;
+}
+
+pond_status write_counters(pond_ctx *c, const DevCounters &in) {
+    hipError_t e = hipMemcpyAsync(c->cnt, &in, sizeof(DevCounters), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counters)");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return POND_OK;
+}
+
+}  // namespace pond
+
+namespace {
 
 pond_status validate(const pond_params *p) {
     if (!p) return fail(POND_ERR_INVALID_ARG, "params is NULL");
@@ -117,31 +146,6 @@ bool is_device_pointer(const void *ptr) {
 
 }  // namespace
 
-struct pond_ctx {
-    pond_params p;
-    size_t psize;
-    Layout L;
-    hipStream_t stream;
-    bool own_stream;
-    char *mem;
-    bool own_mem;
-    DevState buf[2];
-    int cur;
-    void *mom;
-    DevCounters *cnt;
-    double *scratch;
-    StepArgs args;
-    bool initialized;
-    bool failed;
-    long long steps;
-    pond_tuning tuning;
-    TileConfig tc;
-    bool profiling;
-    std::vector<hipEvent_t> prof_events;  // 3 per timed step
-    double prof_prepass_ms, prof_step_ms;
-    long long prof_launches;
-};
-
 namespace {
 
 void fill_args(pond_ctx *c) {
@@ -166,26 +170,15 @@ void fill_args(pond_ctx *c) {
 bool fp64(const pond_ctx *c) { return c->p.precision == POND_PREC_FP64; }
 
 int default_lds_nodes(int tile, bool dbl) {
-    // The step kernels are register-limited to two waves per SIMD in FP32 and
-    // one in FP64, i.e. 8 or 4 waves per CU; split the 160 KiB of LDS between
-    // the blocks that fit.  A 16 x 16 tile at T = 1, Mach 2 needs a 26 x 26
-    // source region.
     int tx, ty;
     tile_dims(static_cast<TileShape>(tile), tx, ty);
-    const int waves_per_block = (tx * ty + 63) / 64;
-    const int waves_per_cu = dbl ? 4 : 8;
-    int blocks_per_cu = waves_per_cu / waves_per_block;
-    if (blocks_per_cu < 1) blocks_per_cu = 1;
-    const int bytes = 160 * 1024 / blocks_per_cu - 1024;
-    return bytes / (dbl ? 160 : 80);
+    return default_lds_nodes_for_threads(tx * ty, dbl);
 }
 
-int halo_for(int tile, int cap) {
+int halo_for(int tile, int cap, bool single_row) {
     int tx, ty;
     tile_dims(static_cast<TileShape>(tile), tx, ty);
-    int h = -1;
-    while ((tx + 2 * (h + 1)) * (ty + 2 * (h + 1)) <= cap) ++h;
-    return h;
+    return halo_for_dims(tx, ty, cap, single_row);
 }
 
 pond_tuning default_tuning(const pond_params &p) {
@@ -196,7 +189,7 @@ pond_tuning default_tuning(const pond_params &p) {
     else
         t.tile = p.precision == POND_PREC_FP64 ? POND_TILE_16x8 : POND_TILE_32x8;
     t.lds_nodes = default_lds_nodes(t.tile, p.precision == POND_PREC_FP64);
-    t.reserved = 0;
+    t.batch_tile_width = 0;
     return t;
 }
 
@@ -211,28 +204,16 @@ pond_status apply_tuning(pond_ctx *c, const pond_tuning &t) {
     if (bytes > 160 * 1024)
         return fail(POND_ERR_INVALID_ARG, "lds_nodes %d needs %zu bytes of LDS (> 160 KiB)",
                     u.lds_nodes, bytes);
-    const int h = halo_for(u.tile, u.lds_nodes);
+    const int h = halo_for(u.tile, u.lds_nodes, c->p.ny == 1);
     if (h < 0) return fail(POND_ERR_INVALID_ARG, "lds_nodes %d smaller than the tile", u.lds_nodes);
-    u.reserved = 0;
+    if (u.batch_tile_width != 0 && u.batch_tile_width != 16 && u.batch_tile_width != 32 &&
+        u.batch_tile_width != 64 && u.batch_tile_width != 128 && u.batch_tile_width != 256)
+        return fail(POND_ERR_INVALID_ARG, "batch_tile_width %d not in {0, 16, 32, 64, 128, 256}",
+                    u.batch_tile_width);
     c->tuning = u;
     c->tc.shape = static_cast<TileShape>(u.tile);
     c->tc.cap = u.lds_nodes;
     c->tc.halo_cap = h;
-    return POND_OK;
-}
-
-pond_status check_ctx(const pond_ctx *c, bool need_init) {
-    if (!c) return fail(POND_ERR_INVALID_ARG, "context is NULL");
-    if (need_init && !c->initialized)
-        return fail(POND_ERR_STATE, "context has no state (call pond_init_fields first)");
-    return POND_OK;
-}
-
-pond_status read_counters(pond_ctx *c, DevCounters *out) {
-    hipError_t e = hipMemcpyAsync(out, c->cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counters)");
-    e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     return POND_OK;
 }
 
@@ -265,6 +246,12 @@ pond_status reset_counters(pond_ctx *c) {
     return e == hipSuccess ? POND_OK : hip_fail(e, "hipMemsetAsync(counters)");
 }
 
+// Operations that write the state or step it are refused while a batch owns the context.
+pond_status check_unbatched(const pond_ctx *c) {
+    if (c->batch) return fail(POND_ERR_STATE, "context is a member of a batch (destroy the batch first)");
+    return POND_OK;
+}
+
 pond_status set_reference_from_counters(pond_ctx *c) {
     DevCounters h;
     pond_status s = read_counters(c, &h);
@@ -294,7 +281,7 @@ const char *pond_status_string(pond_status s) {
     return "unknown status";
 }
 
-const char *pond_last_error(void) { return g_last_error.c_str(); }
+const char *pond_last_error(void) { return last_error(); }
 
 pond_status pond_params_default(pond_params *p) {
     if (!p) return fail(POND_ERR_INVALID_ARG, "params is NULL");
@@ -383,7 +370,10 @@ pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem
     c->profiling = false;
     c->prof_prepass_ms = c->prof_step_ms = 0.0;
     c->prof_launches = 0;
+    c->batch = nullptr;
     s = apply_tuning(c, default_tuning(c->p));
+    pond_tuning tuned;
+    if (s == POND_OK && tuning_cache_lookup(c->p, &tuned)) s = apply_tuning(c, tuned);
     if (s == POND_OK) s = reset_counters(c);
     if (s != POND_OK) {
         pond_destroy(c);
@@ -397,6 +387,7 @@ pond_status pond_init_fields(pond_ctx *c, const double *rho, const double *ux, c
                              const double *T) {
     pond_status s = check_ctx(c, false);
     if (s != POND_OK) return s;
+    if ((s = check_unbatched(c)) != POND_OK) return s;
     if (!rho || !ux || !uy || !T) return fail(POND_ERR_INVALID_ARG, "field pointer is NULL");
     const long long N = c->args.N;
     // stage host inputs in the moment planes (>= 4 N doubles in either precision)
@@ -479,6 +470,7 @@ hipError_t enqueue_step(pond_ctx *c) {
 pond_status pond_step(pond_ctx *c, int64_t nsteps) {
     pond_status s = check_ctx(c, true);
     if (s != POND_OK) return s;
+    if ((s = check_unbatched(c)) != POND_OK) return s;
     if (c->failed) return fail(POND_ERR_STATE, "context is in the error state (non-physical)");
     if (nsteps < 0) return fail(POND_ERR_INVALID_ARG, "nsteps < 0");
     for (int64_t k = 0; k < nsteps; ++k) {
@@ -587,6 +579,7 @@ pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, con
                               const double *u_ref) {
     pond_status s = check_ctx(c, false);
     if (s != POND_OK) return s;
+    if ((s = check_unbatched(c)) != POND_OK) return s;
     if (!f || !g || !frame) return fail(POND_ERR_INVALID_ARG, "input pointer is NULL");
     const long long N = c->args.N;
     const bool dev = is_device_pointer(f) && is_device_pointer(g) && is_device_pointer(frame);
@@ -669,6 +662,7 @@ pond_status pond_set_tuning(pond_ctx *c, const pond_tuning *t) {
     pond_status s = check_ctx(c, false);
     if (s != POND_OK) return s;
     if (!t) return fail(POND_ERR_INVALID_ARG, "tuning is NULL");
+    if ((s = check_unbatched(c)) != POND_OK) return s;
     return apply_tuning(c, *t);
 }
 
@@ -708,6 +702,7 @@ pond_status pond_profile_read(pond_ctx *c, pond_profile_t *out) {
 
 pond_status pond_destroy(pond_ctx *c) {
     if (!c) return POND_OK;
+    if (c->batch) return fail(POND_ERR_STATE, "context is a member of a batch (destroy the batch first)");
     pond_status s = POND_OK;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) s = hip_fail(e, "hipStreamSynchronize");

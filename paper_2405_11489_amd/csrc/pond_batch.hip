@@ -1,0 +1,638 @@
+// pond_batch.hip -- many PonD instances advanced together, and the tile-shape
+// autotuner.
+//
+// A batch steps its member contexts with two launches per step for all of
+// them at once, captured in a HIP graph:
+//   1. a flat moment pre-pass over every member's nodes (each 256-node block
+//      belongs to one member);
+//   2. one persistent step launch: a few blocks per CU pull tiles of any
+//      member from eight work queues, one per XCD (block b runs on XCD b % 8
+//      and drains queue b % 8 first, then steals from the others), so small
+//      and large instances share the chip without a launch per instance.
+// The last block to finish the step launch rewinds the queues and advances
+// the batch's device step counter; member m reads buffer
+// (parity0[m] + step) & 1, so the same captured graph serves every step and
+// the graph holds no memset node.
+//
+// Every node goes through the same per-node code as the single-instance
+// kernels (tile_step / node_step with the member's own arguments), so a
+// member's results do not depend on the batch it runs in.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "pond_ctx.h"
+#include "pond_tile.h"
+
+namespace pond {
+namespace {
+
+constexpr int kBatchThreads = 256;
+constexpr int kQueues = 8;  // one per XCD
+
+struct BatchMember {
+    StepArgs a;
+    DevState buf[2];
+    void *mom;
+    DevCounters *cnt;
+    int parity0;   // current buffer of the member when the step counter is 0
+    int lg;        // tile width 2^lg, height 256 >> lg
+    int tiles_x;
+    int halo_cap;
+    int tile_off;  // first tile of the member in the flat tile list
+    int blk_off;   // first pre-pass block of the member
+};
+
+struct BatchCtl {
+    unsigned long long step;      // batched steps completed
+    unsigned int next[kQueues];   // tile cursor of each queue
+    unsigned int done;            // blocks finished in the running step launch
+    unsigned int pad;
+    int qbeg[kQueues + 1];        // queue q owns flat tiles [qbeg[q], qbeg[q + 1])
+};
+
+// Largest i in [0, n) with off[i] <= v (off strictly increasing, off[0] = 0).
+__device__ __forceinline__ int find_member(const int *__restrict__ off, int n, int v) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ unsigned long long load_step(const BatchCtl *ctl) {
+    return __hip_atomic_load(&ctl->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename P>
+__global__ __launch_bounds__(kBatchThreads) void batch_moments_kernel(
+    const BatchMember *__restrict__ mem, const int *__restrict__ blk_off, int nmem,
+    const BatchCtl *ctl) {
+    const int i = __builtin_amdgcn_readfirstlane(find_member(blk_off, nmem, int(blockIdx.x)));
+    const StepArgs a = mem[i].a;
+    const long long n = (long long)(int(blockIdx.x) - mem[i].blk_off) * kBatchThreads + threadIdx.x;
+    if (n >= a.N) return;
+    const int par = int((mem[i].parity0 + load_step(ctl)) & 1);
+    node_moments<P>(a, mem[i].buf[par], static_cast<P *>(mem[i].mom), n);
+}
+
+template <typename P, int NP>
+__global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
+    const BatchMember *__restrict__ mem, const int *__restrict__ tile_off, int nmem,
+    BatchCtl *ctl, int cap) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int red[16];
+    __shared__ int s_tile;
+    const unsigned long long step = load_step(ctl);
+    const int home = int(blockIdx.x) % kQueues;
+    int tried = 0;  // queues found empty so far (thread 0 only)
+    for (;;) {
+        __syncthreads();  // the previous tile is finished with LDS and s_tile
+        if (threadIdx.x == 0) {
+            int t = -1;
+            while (tried < kQueues) {
+                const int q = (home + tried) % kQueues;
+                const int len = ctl->qbeg[q + 1] - ctl->qbeg[q];
+                const unsigned k = atomicAdd(&ctl->next[q], 1u);
+                if (int(k) < len) {
+                    t = ctl->qbeg[q] + int(k);
+                    break;
+                }
+                ++tried;
+            }
+            s_tile = t;
+        }
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);
+        if (t < 0) break;
+        const int i = __builtin_amdgcn_readfirstlane(find_member(tile_off, nmem, t));
+        const StepArgs a = mem[i].a;
+        const int lg = mem[i].lg, tiles_x = mem[i].tiles_x;
+        const int lt = t - mem[i].tile_off;
+        const int par = int((mem[i].parity0 + step) & 1);
+        tile_step<P, NP>(a, mem[i].buf[par], static_cast<const P *>(mem[i].mom), mem[i].buf[par ^ 1],
+                         mem[i].cnt, reinterpret_cast<P *>(smem_raw), cap, mem[i].halo_cap,
+                         (lt % tiles_x) << lg, (lt / tiles_x) * (kBatchThreads >> lg), Shape256{lg},
+                         red);
+    }
+    // the last block out rewinds the queues and advances the step counter
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned d = atomicAdd(&ctl->done, 1u);
+        if (d == gridDim.x - 1) {
+            for (int q = 0; q < kQueues; ++q) atomicExch(&ctl->next[q], 0u);
+            atomicExch(&ctl->done, 0u);
+            atomicAdd(&ctl->step, 1ull);
+            __threadfence();
+        }
+    }
+}
+
+template <typename P, int NP>
+const void *step_kernel_ptr() {
+    return reinterpret_cast<const void *>(batch_step_kernel<P, NP>);
+}
+
+const void *batch_step_fn(bool dbl, int np) {
+    if (dbl) return np == 3 ? step_kernel_ptr<double, 3>() : step_kernel_ptr<double, 4>();
+    return np == 3 ? step_kernel_ptr<float, 3>() : step_kernel_ptr<float, 4>();
+}
+
+// ----------------------------------------------------- tuning cache ----
+// Size class of an instance: precision, stencil, and the rounded log2 of each
+// axis (a single-row grid is its own class).
+using TuneKey = std::tuple<int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, pond_tuning> g_tune;
+
+int log2_class(int n) { return n <= 1 ? -1 : int(std::lround(std::log2(double(n)))); }
+
+TuneKey tune_key(const pond_params &p) {
+    return TuneKey(p.precision * 16 + p.interp_points, p.bc_x * 2 + p.bc_y, log2_class(p.nx),
+                   log2_class(p.ny));
+}
+
+int default_batch_width(const pond_params &p) {
+    if (p.ny < 8) return 256;
+    return p.precision == POND_PREC_FP64 ? 16 : 32;
+}
+
+int lg2(int w) {
+    int l = 0;
+    while ((1 << l) < w) ++l;
+    return l;
+}
+
+}  // namespace
+
+bool tuning_cache_lookup(const pond_params &p, pond_tuning *out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(p));
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+}  // namespace pond
+
+using namespace pond;
+
+struct pond_batch {
+    std::vector<pond_ctx *> members;
+    std::vector<int> widths;
+    bool dbl;
+    int np;
+    hipStream_t stream;
+    bool own_stream;
+    void *dev;  // [members | tile offsets | block offsets | control]
+    BatchMember *d_mem;
+    int *d_tile_off, *d_blk_off;
+    BatchCtl *d_ctl;
+    int cap, grid, tiles, blocks;
+    long long nodes;
+    long long steps;
+    hipGraph_t graph[2];
+    hipGraphExec_t exec[2];  // 1 step, kGraphSteps steps
+    hipEvent_t done_ev;
+    std::vector<hipStream_t> other_streams;  // member streams other than the batch's
+    std::vector<hipEvent_t> other_ev;
+};
+
+namespace {
+
+constexpr int kGraphSteps = 8;
+
+hipError_t enqueue_batch_step(pond_batch *b) {
+    if (b->dbl)
+        hipLaunchKernelGGL(batch_moments_kernel<double>, dim3(b->blocks), dim3(kBatchThreads), 0,
+                           b->stream, b->d_mem, b->d_blk_off, int(b->members.size()), b->d_ctl);
+    else
+        hipLaunchKernelGGL(batch_moments_kernel<float>, dim3(b->blocks), dim3(kBatchThreads), 0,
+                           b->stream, b->d_mem, b->d_blk_off, int(b->members.size()), b->d_ctl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = size_t(b->cap) * kNMom * (b->dbl ? sizeof(double) : sizeof(float));
+    const int n = int(b->members.size());
+    if (b->dbl) {
+        if (b->np == 3)
+            hipLaunchKernelGGL((batch_step_kernel<double, 3>), dim3(b->grid), dim3(kBatchThreads),
+                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->d_ctl, b->cap);
+        else
+            hipLaunchKernelGGL((batch_step_kernel<double, 4>), dim3(b->grid), dim3(kBatchThreads),
+                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->d_ctl, b->cap);
+    } else {
+        if (b->np == 3)
+            hipLaunchKernelGGL((batch_step_kernel<float, 3>), dim3(b->grid), dim3(kBatchThreads),
+                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->d_ctl, b->cap);
+        else
+            hipLaunchKernelGGL((batch_step_kernel<float, 4>), dim3(b->grid), dim3(kBatchThreads),
+                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->d_ctl, b->cap);
+    }
+    return hipGetLastError();
+}
+
+hipError_t capture(pond_batch *b, int steps, hipGraph_t *g, hipGraphExec_t *x) {
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < steps && le == hipSuccess; ++k) le = enqueue_batch_step(b);
+    e = hipStreamEndCapture(b->stream, g);
+    if (le != hipSuccess) return le;
+    if (e != hipSuccess) return e;
+    return hipGraphInstantiate(x, *g, nullptr, nullptr, 0);
+}
+
+void release(pond_batch *b) {
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (int k = 0; k < 2; ++k) {
+        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+    }
+    if (b->done_ev) (void)hipEventDestroy(b->done_ev);
+    for (hipEvent_t ev : b->other_ev) (void)hipEventDestroy(ev);
+    if (b->dev) (void)hipFree(b->dev);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    for (pond_ctx *c : b->members)
+        if (c && c->batch == b) c->batch = nullptr;
+    delete b;
+}
+
+// Members' widths: explicit per-context width, else the tuning cache, else
+// the default for the instance's shape.
+int member_width(const pond_ctx *c) {
+    if (c->tuning.batch_tile_width > 0) return c->tuning.batch_tile_width;
+    pond_tuning t;
+    if (tuning_cache_lookup(c->p, &t) && t.batch_tile_width > 0) return t.batch_tile_width;
+    return default_batch_width(c->p);
+}
+
+}  // namespace
+
+pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, pond_batch **out) {
+    if (!out) return fail(POND_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!ctxs || n < 1) return fail(POND_ERR_INVALID_ARG, "a batch needs at least one context");
+    for (int i = 0; i < n; ++i) {
+        const pond_ctx *c = ctxs[i];
+        if (!c) return fail(POND_ERR_INVALID_ARG, "context %d is NULL", i);
+        if (!c->initialized) return fail(POND_ERR_STATE, "context %d has no state", i);
+        if (c->failed) return fail(POND_ERR_STATE, "context %d is in the error state", i);
+        if (c->batch) return fail(POND_ERR_STATE, "context %d already belongs to a batch", i);
+        if (c->p.precision != ctxs[0]->p.precision || c->p.interp_points != ctxs[0]->p.interp_points)
+            return fail(POND_ERR_INVALID_ARG,
+                        "context %d: members must share precision and interp_points", i);
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return fail(POND_ERR_INVALID_ARG, "context %d appears twice", i);
+    }
+    pond_batch *b = new (std::nothrow) pond_batch();
+    if (!b) return fail(POND_ERR_OUT_OF_MEMORY, "host allocation failed");
+    b->members.assign(ctxs, ctxs + n);
+    b->dbl = ctxs[0]->p.precision == POND_PREC_FP64;
+    b->np = ctxs[0]->p.interp_points;
+    b->own_stream = hip_stream == nullptr;
+    hipError_t e = hipSuccess;
+    if (b->own_stream)
+        e = hipStreamCreate(&b->stream);
+    else
+        b->stream = static_cast<hipStream_t>(hip_stream);
+    if (e != hipSuccess) {
+        b->stream = nullptr;
+        release(b);
+        return hip_fail(e, "hipStreamCreate");
+    }
+
+    // LDS per block and the persistent grid
+    b->cap = default_lds_nodes_for_threads(kBatchThreads, b->dbl);
+    const size_t lds = size_t(b->cap) * kNMom * (b->dbl ? sizeof(double) : sizeof(float));
+    const void *kern = batch_step_fn(b->dbl, b->np);
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    int per_cu = 0, cus = 0, dev = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBatchThreads, lds);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "batch launch configuration");
+    }
+    if (per_cu < 1) per_cu = 1;
+
+    // descriptors
+    std::vector<BatchMember> hm(n);
+    std::vector<int> toff(n), boff(n);
+    long long tiles = 0, blocks = 0, nodes = 0;
+    for (int i = 0; i < n; ++i) {
+        pond_ctx *c = ctxs[i];
+        const int w = member_width(c), lg = lg2(w), h = kBatchThreads >> lg;
+        const int tx = (c->p.nx + w - 1) / w, ty = (c->p.ny + h - 1) / h;
+        const int halo = halo_for_dims(w, h, b->cap, c->p.ny == 1);
+        if (halo < 0) {
+            release(b);
+            return fail(POND_ERR_INVALID_ARG, "context %d: tile %dx%d does not fit %d LDS nodes", i,
+                        w, h, b->cap);
+        }
+        BatchMember &m = hm[i];
+        m.a = c->args;
+        m.buf[0] = c->buf[0];
+        m.buf[1] = c->buf[1];
+        m.mom = c->mom;
+        m.cnt = c->cnt;
+        m.parity0 = c->cur;
+        m.lg = lg;
+        m.tiles_x = tx;
+        m.halo_cap = halo;
+        m.tile_off = int(tiles);
+        m.blk_off = int(blocks);
+        toff[i] = int(tiles);
+        boff[i] = int(blocks);
+        tiles += (long long)tx * ty;
+        blocks += (c->args.N + kBatchThreads - 1) / kBatchThreads;
+        nodes += c->args.N;
+        b->widths.push_back(w);
+    }
+    if (tiles > 0x7fffffffll || blocks > 0x7fffffffll) {
+        release(b);
+        return fail(POND_ERR_INVALID_ARG, "batch too large (%lld tiles)", tiles);
+    }
+    b->tiles = int(tiles);
+    b->blocks = int(blocks);
+    b->nodes = nodes;
+    b->grid = int(std::min<long long>(tiles, (long long)per_cu * cus));
+    BatchCtl ctl{};
+    for (int q = 0; q <= kQueues; ++q) ctl.qbeg[q] = int(tiles * q / kQueues);
+
+    const size_t mem_bytes = align_up(sizeof(BatchMember) * n);
+    const size_t off_bytes = align_up(sizeof(int) * n);
+    e = hipMalloc(&b->dev, mem_bytes + 2 * off_bytes + align_up(sizeof(BatchCtl)));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b->dev = nullptr;
+        release(b);
+        return fail(POND_ERR_OUT_OF_MEMORY, "batch descriptor allocation failed");
+    }
+    char *base = static_cast<char *>(b->dev);
+    b->d_mem = reinterpret_cast<BatchMember *>(base);
+    b->d_tile_off = reinterpret_cast<int *>(base + mem_bytes);
+    b->d_blk_off = reinterpret_cast<int *>(base + mem_bytes + off_bytes);
+    b->d_ctl = reinterpret_cast<BatchCtl *>(base + mem_bytes + 2 * off_bytes);
+    // members' pending work (initialisation, earlier steps) precedes the batch's
+    for (pond_ctx *c : b->members)
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(b->d_mem, hm.data(), sizeof(BatchMember) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_tile_off, toff.data(), sizeof(int) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_blk_off, boff.data(), sizeof(int) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = capture(b, 1, &b->graph[0], &b->exec[0]);
+    if (e == hipSuccess) e = capture(b, kGraphSteps, &b->graph[1], &b->exec[1]);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming);
+    for (pond_ctx *c : b->members) {
+        if (e != hipSuccess) break;
+        if (c->stream == b->stream) continue;
+        if (std::find(b->other_streams.begin(), b->other_streams.end(), c->stream) !=
+            b->other_streams.end())
+            continue;
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) {
+            b->other_streams.push_back(c->stream);
+            b->other_ev.push_back(ev);
+        }
+    }
+    if (e != hipSuccess) {
+        pond_status s = hip_fail(e, "batch set-up");
+        release(b);
+        return s;
+    }
+    for (pond_ctx *c : b->members) c->batch = b;
+    b->steps = 0;
+    *out = b;
+    return POND_OK;
+}
+
+pond_status pond_batch_step(pond_batch *b, int64_t nsteps) {
+    if (!b) return fail(POND_ERR_INVALID_ARG, "batch is NULL");
+    if (nsteps < 0) return fail(POND_ERR_INVALID_ARG, "nsteps < 0");
+    for (const pond_ctx *c : b->members)
+        if (c->failed) return fail(POND_ERR_STATE, "a member is in the error state (non-physical)");
+    if (nsteps == 0) return POND_OK;
+    hipError_t e = hipSuccess;
+    // work already queued on the members' own streams (e.g. moments read-outs) goes first
+    for (size_t k = 0; k < b->other_streams.size() && e == hipSuccess; ++k) {
+        e = hipEventRecord(b->other_ev[k], b->other_streams[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->other_ev[k], 0);
+    }
+    for (int64_t k = 0; k + kGraphSteps <= nsteps && e == hipSuccess; k += kGraphSteps)
+        e = hipGraphLaunch(b->exec[1], b->stream);
+    for (int64_t k = 0; k < nsteps % kGraphSteps && e == hipSuccess; ++k)
+        e = hipGraphLaunch(b->exec[0], b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->done_ev, b->stream);
+    for (size_t k = 0; k < b->other_streams.size() && e == hipSuccess; ++k)
+        e = hipStreamWaitEvent(b->other_streams[k], b->done_ev, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch step launch");
+    for (pond_ctx *c : b->members) {
+        c->cur ^= int(nsteps & 1);
+        c->steps += nsteps;
+    }
+    b->steps += nsteps;
+    return POND_OK;
+}
+
+pond_status pond_batch_synchronize(pond_batch *b) {
+    if (!b) return fail(POND_ERR_INVALID_ARG, "batch is NULL");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    int bad = 0;
+    for (pond_ctx *c : b->members) {
+        DevCounters h;
+        pond_status s = read_counters(c, &h);
+        if (s != POND_OK) return s;
+        if (h.nonphysical) {
+            c->failed = true;
+            ++bad;
+        }
+    }
+    if (bad) return fail(POND_ERR_NONPHYSICAL, "%d member(s) produced rho <= 0, T <= 0 or NaN", bad);
+    return POND_OK;
+}
+
+pond_status pond_batch_get_info(pond_batch *b, pond_batch_info_t *out) {
+    if (!b || !out) return fail(POND_ERR_INVALID_ARG, "batch or out is NULL");
+    out->members = int32_t(b->members.size());
+    out->tiles = b->tiles;
+    out->grid_blocks = b->grid;
+    out->lds_nodes = b->cap;
+    out->nodes = b->nodes;
+    out->steps = b->steps;
+    out->graph_steps = kGraphSteps;
+    out->reserved = 0;
+    return POND_OK;
+}
+
+pond_status pond_batch_member_tile_width(pond_batch *b, int i, int *width) {
+    if (!b || !width) return fail(POND_ERR_INVALID_ARG, "batch or width is NULL");
+    if (i < 0 || i >= int(b->members.size())) return fail(POND_ERR_INVALID_ARG, "member %d out of range", i);
+    *width = b->widths[i];
+    return POND_OK;
+}
+
+pond_status pond_batch_destroy(pond_batch *b) {
+    if (!b) return POND_OK;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    release(b);
+    return e == hipSuccess ? POND_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+// ------------------------------------------------------------ autotune ----
+namespace {
+
+struct Saved {
+    void *tmp = nullptr;
+    int cur = 0;
+    long long steps = 0;
+    DevCounters cnt{};
+    pond_tuning tuning{};
+};
+
+pond_status save_state(pond_ctx *c, Saved &s) {
+    s.cur = c->cur;
+    s.steps = c->steps;
+    s.tuning = c->tuning;
+    pond_status st = read_counters(c, &s.cnt);
+    if (st != POND_OK) return st;
+    hipError_t e = hipMalloc(&s.tmp, c->L.buf_bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        s.tmp = nullptr;
+        return fail(POND_ERR_OUT_OF_MEMORY, "autotune state copy (%zu bytes)", c->L.buf_bytes);
+    }
+    e = hipMemcpyAsync(s.tmp, c->buf[s.cur].f, c->L.buf_bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? POND_OK : hip_fail(e, "autotune save");
+}
+
+pond_status restore_state(pond_ctx *c, const Saved &s) {
+    hipError_t e = hipMemcpyAsync(c->buf[s.cur].f, s.tmp, c->L.buf_bytes, hipMemcpyDeviceToDevice,
+                                  c->stream);
+    if (e != hipSuccess) return hip_fail(e, "autotune restore");
+    c->cur = s.cur;
+    c->steps = s.steps;
+    c->failed = false;
+    return write_counters(c, s.cnt);
+}
+
+// Device time of `steps` steps of c (single-instance path, or a one-member
+// batch when batch_width > 0), after one untimed step; the state is restored.
+pond_status time_candidate(pond_ctx *c, const Saved &sv, int steps, int batch_width, double *ms) {
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    pond_status s = e == hipSuccess ? POND_OK : hip_fail(e, "hipEventCreate");
+    pond_batch *b = nullptr;
+    if (s == POND_OK && batch_width > 0) {
+        c->tuning.batch_tile_width = batch_width;
+        s = pond_batch_create(&c, 1, c->stream, &b);
+    }
+    if (s == POND_OK) s = b ? pond_batch_step(b, 1) : pond_step(c, 1);
+    if (s == POND_OK) {
+        e = hipEventRecord(ev[0], c->stream);
+        if (e != hipSuccess) s = hip_fail(e, "hipEventRecord");
+    }
+    if (s == POND_OK) s = b ? pond_batch_step(b, steps) : pond_step(c, steps);
+    if (s == POND_OK) {
+        e = hipEventRecord(ev[1], c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+        if (e != hipSuccess) s = hip_fail(e, "autotune timing");
+        *ms = t;
+    }
+    if (b) {
+        pond_status s2 = pond_batch_destroy(b);
+        if (s == POND_OK) s = s2;
+    }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    pond_status s3 = restore_state(c, sv);
+    return s == POND_OK ? s3 : s;
+}
+
+}  // namespace
+
+pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out) {
+    pond_status s = check_ctx(c, true);
+    if (s != POND_OK) return s;
+    if (c->batch) return fail(POND_ERR_STATE, "context is a member of a batch");
+    if (c->failed) return fail(POND_ERR_STATE, "context is in the error state");
+    if (steps < 1) return fail(POND_ERR_INVALID_ARG, "steps must be >= 1");
+    const bool dbl = c->p.precision == POND_PREC_FP64, row = c->p.ny < 8;
+    std::vector<int> tiles, widths;
+    if (row) {
+        tiles = {POND_TILE_64x1, POND_TILE_256x1};
+        widths = {256};
+    } else if (dbl) {
+        tiles = {POND_TILE_16x8, POND_TILE_16x16, POND_TILE_8x8};
+        widths = {16, 32, 64};
+    } else {
+        tiles = {POND_TILE_32x8, POND_TILE_16x16, POND_TILE_16x8};
+        widths = {32, 16, 64};
+    }
+    Saved sv;
+    s = save_state(c, sv);
+    double best_t = 1e300, best_w = 1e300;
+    pond_tuning best = c->tuning;
+    for (int tile : tiles) {
+        if (s != POND_OK) break;
+        pond_tuning t = sv.tuning;
+        t.kernel = POND_KERNEL_TILED;
+        t.tile = tile;
+        t.lds_nodes = 0;
+        s = pond_set_tuning(c, &t);
+        double ms = 0.0;
+        if (s == POND_OK) s = time_candidate(c, sv, steps, 0, &ms);
+        if (s == POND_OK && ms < best_t) {
+            best_t = ms;
+            best.kernel = c->tuning.kernel;
+            best.tile = c->tuning.tile;
+            best.lds_nodes = c->tuning.lds_nodes;
+        }
+    }
+    for (int w : widths) {
+        if (s != POND_OK) break;
+        double ms = 0.0;
+        s = time_candidate(c, sv, steps, w, &ms);
+        if (s == POND_OK && ms < best_w) {
+            best_w = ms;
+            best.batch_tile_width = w;
+        }
+    }
+    if (sv.tmp) (void)hipFree(sv.tmp);
+    if (s != POND_OK) {
+        c->tuning = sv.tuning;
+        (void)pond_set_tuning(c, &sv.tuning);
+        return s;
+    }
+    s = pond_set_tuning(c, &best);
+    if (s != POND_OK) return s;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(c->p)] = best;
+    }
+    if (out) *out = best;
+    return POND_OK;
+}
+
+pond_status pond_tuning_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return POND_OK;
+}

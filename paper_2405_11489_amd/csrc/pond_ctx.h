@@ -1,0 +1,89 @@
+// pond_ctx.h -- the context object behind the opaque pond_ctx handle, and the
+// host helpers shared by the single-instance ABI (pond_api.hip) and the
+// batched / serving layer (pond_batch.hip, pond_server.hip).  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "pond.h"
+#include "pond_internal.h"
+
+namespace pond {
+
+// Record a message for pond_last_error() on this thread and return s.
+pond_status fail(pond_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+pond_status hip_fail(hipError_t e, const char *what);
+const char *last_error();
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// One context's device allocation:
+//   [state buffer 0 | state buffer 1 | moment planes | counters | scratch]
+struct Layout {
+    size_t pop_bytes;    // one set of 16 planes
+    size_t frame_bytes;  // one frame plane
+    size_t buf_bytes;    // one state buffer
+    size_t mom_bytes;    // 20 moment planes
+    size_t cnt_off, scratch_off, total;
+};
+
+constexpr int kScratchDoubles = 3 * 256;
+
+Layout layout_for(long long N, size_t psize);
+
+// LDS nodes per block that let the blocks of the register-limited occupancy
+// share the 160 KiB of a CU (threads: block size).
+int default_lds_nodes_for_threads(int threads, bool dbl);
+
+// Largest halo h of a tx x ty tile whose source region fits cap nodes:
+// (tx + 2h)(ty + 2h) <= cap, or tx + 2h <= cap for a single-row grid (whose
+// region is one row).  -1 if not even the tile fits.
+inline int halo_for_dims(int tx, int ty, int cap, bool single_row) {
+    if (single_row) return cap >= tx ? (cap - tx) / 2 : -1;
+    int h = -1;
+    while ((tx + 2 * (h + 1)) * (ty + 2 * (h + 1)) <= cap) ++h;
+    return h;
+}
+
+}  // namespace pond
+
+struct pond_ctx {
+    pond_params p;
+    size_t psize;
+    pond::Layout L;
+    hipStream_t stream;
+    bool own_stream;
+    char *mem;
+    bool own_mem;
+    pond::DevState buf[2];
+    int cur;
+    void *mom;
+    pond::DevCounters *cnt;
+    double *scratch;
+    pond::StepArgs args;
+    bool initialized;
+    bool failed;
+    long long steps;
+    pond_tuning tuning;
+    pond::TileConfig tc;
+    bool profiling;
+    std::vector<hipEvent_t> prof_events;  // 3 per timed step
+    double prof_prepass_ms, prof_step_ms;
+    long long prof_launches;
+    pond_batch *batch;  // batch that owns the stepping of this context, or NULL
+};
+
+namespace pond {
+
+pond_status check_ctx(const pond_ctx *c, bool need_init);
+pond_status read_counters(pond_ctx *c, DevCounters *out);
+pond_status write_counters(pond_ctx *c, const DevCounters &in);
+
+// Autotuned launch configuration of p's size class, if pond_autotune stored one.
+bool tuning_cache_lookup(const pond_params &p, pond_tuning *out);
+
+}  // namespace pond

@@ -18,7 +18,7 @@
 // moments of the stencil nodes are interpolated at the departure point and the
 // frame transformation is applied once to the interpolated moments, instead of
 // transforming every stencil node first (the two agree to rounding).
-#include "pond_step_common.h"
+#include "pond_tile.h"
 
 namespace pond {
 
@@ -72,25 +72,7 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(StepArgs a, DevState st
                                                          P *__restrict__ mom) {
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= a.N) return;
-    const P s = P(sqrt(st.T[n]));
-    const P dx = P(st.ux[n] - a.uref_x), dy = P(st.uy[n] - a.uref_y);
-    P M[kNMom];
-#pragma unroll
-    for (int k = 0; k < kNMom; ++k) M[k] = P(0);
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const P fi = plane<P>(st.f, i, a.N)[n];
-        const P gi = plane<P>(st.g, i, a.N)[n];
-        const P Vx = s * P(c1(i / 4)) + dx, Vy = s * P(c1(i % 4)) + dy;
-        const P mono[kNM] = {P(1),         Vx,          Vy,          Vx * Vx,     Vx * Vy,
-                             Vy * Vy,      Vx * Vx * Vx, Vx * Vx * Vy, Vx * Vy * Vy, Vy * Vy * Vy};
-#pragma unroll
-        for (int k = 0; k < kNM; ++k) {
-            M[k] += fi * mono[k];
-            M[kNM + k] += gi * mono[k];
-        }
-    }
-    store_moments(mom, a.N, n, M);
+    node_moments<P>(a, st, mom, n);
 }
 
 // ----------------------------------------------------- step (global taps) ----
@@ -116,73 +98,12 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
 }
 
 // ------------------------------------------------------ step (LDS tiles) ----
-// Tap source of the tiled kernel: the moments of the block's source region
-// (unwrapped rectangle [X0, X1] x [Y0, Y1], W wide) staged in LDS as grouped
-// planes of stride cap; a velocity whose stencil leaves the region reads HBM.
-template <typename P, int NP>
-struct TileTaps {
-    const P *lds;
-    int cap, X0, Y0, X1, Y1, W;
-    GlobalTaps<P, NP> glob;
-
-    __device__ __forceinline__ void gather(int bx, int by, const P wx[NP], const P wy[NP],
-                                           P Mf[kNM], P Mg[kNM]) const {
-        const bool inside = bx >= X0 && bx + NP - 1 <= X1 && by >= Y0 && by + NP - 1 <= Y1;
-        if (inside) {
-            const int base = (by - Y0) * W + (bx - X0);
-            // POND_ROW_UNROLL stencil rows per trip: bounds the loads in flight per lane
-#pragma unroll POND_ROW_UNROLL
-            for (int q = 0; q < NP; ++q)
-#pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    const P Wt = wx[p] * wy[q];
-                    P M[kNMom];
-                    load_moments(lds, cap, base + q * W + p, M);
-#pragma unroll
-                    for (int k = 0; k < kNM; ++k) {
-                        Mf[k] += Wt * M[k];
-                        Mg[k] += Wt * M[kNM + k];
-                    }
-                }
-        } else {
-            glob.gather(bx, by, wx, wy, Mf, Mg);
-        }
-    }
-};
-
 // Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
 // give each XCD a contiguous range of tiles so that neighbouring tiles, which
 // share halo moments, share that XCD's L2.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
     const int q = nb / 8, r = nb % 8, x = b % 8;
     return x * q + (x < r ? x : r) + b / 8;
-}
-
-__device__ __forceinline__ int block_min(int v, int *red) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-    const int w = threadIdx.x / 64, nw = (blockDim.x + 63) / 64;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
-    int r = red[0];
-    for (int i = 1; i < nw; ++i) r = min(r, red[i]);
-    return r;
-}
-
-template <int NP>
-__device__ __forceinline__ void stencil_extent(int x, double u, double s, int &lo, int &hi) {
-    // departure coordinates x - (s c + u) for c = +-c_out bound all stencils
-    const double dlo = double(x) - (s * c1(3) + u), dhi = double(x) - (s * c1(0) + u);
-    const double clo = fmin(fmax(dlo, double(x) - 4096.0), double(x) + 4096.0);
-    const double chi = fmin(fmax(dhi, double(x) - 4096.0), double(x) + 4096.0);
-    if (NP == 4) {
-        lo = int(floor(clo)) - 1;
-        hi = int(floor(chi)) + 2;
-    } else {
-        lo = int(floor(clo + 0.5)) - 1;
-        hi = int(floor(chi + 0.5)) + 1;
-    }
 }
 
 // Minimum waves per SIMD requested from the register allocator for the tiled
@@ -202,53 +123,10 @@ __global__ __launch_bounds__(TX *TY) POND_TILED_ATTR void step_tiled_kernel(Step
                                                             DevState dst, DevCounters *cnt,
                                                             int cap, int halo_cap, int tiles_x) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    P *lds = reinterpret_cast<P *>(smem_raw);
-    __shared__ int red[4][(TX * TY + 63) / 64];
-
+    __shared__ int red[16];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int tx0 = (tile % tiles_x) * TX, ty0 = (tile / tiles_x) * TY;
-    const int x = tx0 + int(threadIdx.x) % TX, y = ty0 + int(threadIdx.x) / TX;
-    const bool live = x < a.nx && y < a.ny;
-    const long long n = live ? (long long)y * a.nx + x : 0;
-    double l0 = 0.0, l1 = 0.0, l2 = 1.0;
-    if (live) {
-        l0 = src.ux[n];
-        l1 = src.uy[n];
-        l2 = src.T[n];
-    }
-
-    // source region of the block: union of the predictor stencils, clipped to
-    // the tile plus halo_cap so that it fits the LDS capacity
-    constexpr int kFar = 1 << 30;
-    int lx = kFar, hx = -kFar, ly = kFar, hy = -kFar;
-    if (live && isfinite(l0) && isfinite(l1) && l2 > 0.0 && isfinite(l2)) {
-        const double s = sqrt(l2);
-        stencil_extent<NP>(x, l0, s, lx, hx);
-        stencil_extent<NP>(y, l1, s, ly, hy);
-    }
-    int X0 = block_min(lx, red[0]);
-    int X1 = -block_min(-hx, red[1]);
-    int Y0 = block_min(ly, red[2]);
-    int Y1 = -block_min(-hy, red[3]);
-    X0 = max(X0, tx0 - halo_cap);
-    X1 = min(X1, tx0 + TX - 1 + halo_cap);
-    Y0 = max(Y0, ty0 - halo_cap);
-    Y1 = min(Y1, ty0 + TY - 1 + halo_cap);
-    const int W = X1 >= X0 ? X1 - X0 + 1 : 0;
-    const int H = Y1 >= Y0 ? Y1 - Y0 + 1 : 0;
-
-    for (int idx = threadIdx.x; idx < W * H; idx += TX * TY) {
-        const int gx = wrap_index(X0 + idx % W, a.nx, a.bc_x);
-        const int gy = wrap_index(Y0 + idx / W, a.ny, a.bc_y);
-        P M[kNMom];
-        load_moments(mom, a.N, (long long)gy * a.nx + gx, M);
-        store_moments(lds, cap, idx, M);
-    }
-    __syncthreads();
-
-    const TileTaps<P, NP> taps{lds, cap, X0, Y0, X1, Y1, W,
-                               GlobalTaps<P, NP>{mom, a.N, a.nx, a.ny, a.bc_x, a.bc_y}};
-    node_step<P, NP>(a, taps, x, y, n, live, l0, l1, l2, dst, cnt);
+    tile_step<P, NP>(a, src, mom, dst, cnt, reinterpret_cast<P *>(smem_raw), cap, halo_cap,
+                     (tile % tiles_x) * TX, (tile / tiles_x) * TY, FixedShape<TX, TY>{}, red);
 }
 
 // ------------------------------------------------------ macroscopic ----

@@ -1,0 +1,178 @@
+// pond_tile.h -- one block's share of the PonD step: a rectangular tile of
+// destination nodes whose source moments are staged in LDS.  Shared by the
+// single-instance tiled kernel (tile shape fixed at compile time) and the
+// batched persistent kernel (shape chosen per instance at run time).
+#pragma once
+
+#include "pond_step_common.h"
+
+namespace pond {
+
+// Tap source of a tile: the moments of the block's source region (unwrapped
+// rectangle [X0, X1] x [Y0, Y1], W wide) staged in LDS as grouped planes of
+// stride cap; a velocity whose stencil leaves the region reads HBM.  With a
+// single grid row (flat_y) every stencil row is row 0, so the region is one
+// row and all NP stencil rows read it (same arithmetic as the HBM gather).
+template <typename P, int NP>
+struct TileTaps {
+    const P *lds;
+    int cap, X0, Y0, X1, Y1, W;
+    bool flat_y;
+    GlobalTaps<P, NP> glob;
+
+    __device__ __forceinline__ void gather(int bx, int by, const P wx[NP], const P wy[NP],
+                                           P Mf[kNM], P Mg[kNM]) const {
+        const bool inside =
+            bx >= X0 && bx + NP - 1 <= X1 && (flat_y || (by >= Y0 && by + NP - 1 <= Y1));
+        if (inside) {
+            const int rs = flat_y ? 0 : W;
+            const int base = (flat_y ? 0 : by - Y0) * W + (bx - X0);
+            // POND_ROW_UNROLL stencil rows per trip: bounds the loads in flight per lane
+#pragma unroll POND_ROW_UNROLL
+            for (int q = 0; q < NP; ++q)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    const P Wt = wx[p] * wy[q];
+                    P M[kNMom];
+                    load_moments(lds, cap, base + q * rs + p, M);
+#pragma unroll
+                    for (int k = 0; k < kNM; ++k) {
+                        Mf[k] += Wt * M[k];
+                        Mg[k] += Wt * M[kNM + k];
+                    }
+                }
+        } else {
+            glob.gather(bx, by, wx, wy, Mf, Mg);
+        }
+    }
+};
+
+// Minimum over the block (at most 4 waves); red holds one int per wave.
+__device__ __forceinline__ int block_min(int v, int *red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    const int w = threadIdx.x / 64, nw = (blockDim.x + 63) / 64;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    int r = red[0];
+    for (int i = 1; i < nw; ++i) r = min(r, red[i]);
+    return r;
+}
+
+// Unwrapped index range [lo, hi] of the stencils of every velocity of a node at
+// coordinate x with frame velocity u and sqrt(T) = s along one axis.
+template <int NP>
+__device__ __forceinline__ void stencil_extent(int x, double u, double s, int &lo, int &hi) {
+    // departure coordinates x - (s c + u) for c = +-c_out bound all stencils
+    const double dlo = double(x) - (s * c1(3) + u), dhi = double(x) - (s * c1(0) + u);
+    const double clo = fmin(fmax(dlo, double(x) - 4096.0), double(x) + 4096.0);
+    const double chi = fmin(fmax(dhi, double(x) - 4096.0), double(x) + 4096.0);
+    if (NP == 4) {
+        lo = int(floor(clo)) - 1;
+        hi = int(floor(chi)) + 2;
+    } else {
+        lo = int(floor(clo + 0.5)) - 1;
+        hi = int(floor(chi + 0.5)) + 1;
+    }
+}
+
+// Tile shapes: TX x TY destination nodes, one lane each, lane t at (t % TX, t / TX).
+template <int TX, int TY>
+struct FixedShape {
+    __device__ __forceinline__ int tx() const { return TX; }
+    __device__ __forceinline__ int ty() const { return TY; }
+    __device__ __forceinline__ int lx(int t) const { return t % TX; }
+    __device__ __forceinline__ int ly(int t) const { return t / TX; }
+};
+// 256 lanes, TX = 2^lg, TY = 256 / TX.
+struct Shape256 {
+    int lg;
+    __device__ __forceinline__ int tx() const { return 1 << lg; }
+    __device__ __forceinline__ int ty() const { return 256 >> lg; }
+    __device__ __forceinline__ int lx(int t) const { return t & ((1 << lg) - 1); }
+    __device__ __forceinline__ int ly(int t) const { return t >> lg; }
+};
+
+// The tile with first node (tx0, ty0): load the time-t frames, bound the
+// source region by the union of the predictor stencils clipped to the tile
+// plus halo_cap (so that it fits cap nodes of LDS; a single-row grid stages
+// one row, so its halo_cap only bounds x), stage the region's
+// moments, then run every lane's node step.  Every thread of the block must
+// call it (it synchronises the block).  red: 4 x 4 ints of shared memory.
+template <typename P, int NP, class Shape>
+__device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const P *__restrict__ mom,
+                                          DevState dst, DevCounters *cnt, P *lds, int cap,
+                                          int halo_cap, int tx0, int ty0, Shape sh, int *red) {
+    const int nthreads = sh.tx() * sh.ty();
+    const int x = tx0 + sh.lx(int(threadIdx.x)), y = ty0 + sh.ly(int(threadIdx.x));
+    const bool live = x < a.nx && y < a.ny;
+    const long long n = live ? (long long)y * a.nx + x : 0;
+    double l0 = 0.0, l1 = 0.0, l2 = 1.0;
+    if (live) {
+        l0 = src.ux[n];
+        l1 = src.uy[n];
+        l2 = src.T[n];
+    }
+
+    constexpr int kFar = 1 << 30;
+    int lx = kFar, hx = -kFar, ly = kFar, hy = -kFar;
+    if (live && isfinite(l0) && isfinite(l1) && l2 > 0.0 && isfinite(l2)) {
+        const double s = sqrt(l2);
+        stencil_extent<NP>(x, l0, s, lx, hx);
+        stencil_extent<NP>(y, l1, s, ly, hy);
+    }
+    const bool flat_y = a.ny == 1;
+    int X0 = block_min(lx, red);
+    int X1 = -block_min(-hx, red + 4);
+    int Y0 = block_min(ly, red + 8);
+    int Y1 = -block_min(-hy, red + 12);
+    X0 = max(X0, tx0 - halo_cap);
+    X1 = min(X1, tx0 + sh.tx() - 1 + halo_cap);
+    Y0 = max(Y0, ty0 - halo_cap);
+    Y1 = min(Y1, ty0 + sh.ty() - 1 + halo_cap);
+    if (flat_y) Y0 = Y1 = 0;
+    const int W = X1 >= X0 ? X1 - X0 + 1 : 0;
+    const int H = Y1 >= Y0 ? Y1 - Y0 + 1 : 0;
+
+    for (int idx = threadIdx.x; idx < W * H; idx += nthreads) {
+        const int gx = wrap_index(X0 + idx % W, a.nx, a.bc_x);
+        const int gy = wrap_index(Y0 + idx / W, a.ny, a.bc_y);
+        P M[kNMom];
+        load_moments(mom, a.N, (long long)gy * a.nx + gx, M);
+        store_moments(lds, cap, idx, M);
+    }
+    __syncthreads();
+
+    const TileTaps<P, NP> taps{lds, cap, X0, Y0, X1, Y1, W, flat_y,
+                               GlobalTaps<P, NP>{mom, a.N, a.nx, a.ny, a.bc_x, a.bc_y}};
+    node_step<P, NP>(a, taps, x, y, n, live, l0, l1, l2, dst, cnt);
+}
+
+// Moments up to order three of f and g of node n (Eq. genericMomentUptoO3),
+// about u_ref, stored as grouped planes.
+template <typename P>
+__device__ __forceinline__ void node_moments(const StepArgs &a, DevState st, P *__restrict__ mom,
+                                             long long n) {
+    const P s = P(sqrt(st.T[n]));
+    const P dx = P(st.ux[n] - a.uref_x), dy = P(st.uy[n] - a.uref_y);
+    P M[kNMom];
+#pragma unroll
+    for (int k = 0; k < kNMom; ++k) M[k] = P(0);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const P fi = pop_plane<P>(st.f, i, a.N)[n];
+        const P gi = pop_plane<P>(st.g, i, a.N)[n];
+        const P Vx = s * P(c1(i / 4)) + dx, Vy = s * P(c1(i % 4)) + dy;
+        const P mono[kNM] = {P(1),         Vx,          Vy,          Vx * Vx,     Vx * Vy,
+                             Vy * Vy,      Vx * Vx * Vx, Vx * Vx * Vy, Vx * Vy * Vy, Vy * Vy * Vy};
+#pragma unroll
+        for (int k = 0; k < kNM; ++k) {
+            M[k] += fi * mono[k];
+            M[kNM + k] += gi * mono[k];
+        }
+    }
+    store_moments(mom, a.N, n, M);
+}
+
+}  // namespace pond

@@ -30,8 +30,14 @@ EXPORTED = [
     "pond_init_fields", "pond_step", "pond_moments", "pond_stats", "pond_synchronize",
     "pond_export_state", "pond_import_state", "pond_destroy", "pond_status_string",
     "pond_last_error", "pond_profile_enable", "pond_profile_read", "pond_get_tuning",
-    "pond_set_tuning",
+    "pond_set_tuning", "pond_batch_create", "pond_batch_step", "pond_batch_synchronize",
+    "pond_batch_get_info", "pond_batch_member_tile_width", "pond_batch_destroy",
+    "pond_autotune", "pond_tuning_cache_clear", "pond_server_config_default",
+    "pond_server_create", "pond_server_submit", "pond_server_poll", "pond_server_wait",
+    "pond_server_result", "pond_server_release", "pond_server_get_stats", "pond_server_destroy",
 ]
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
+REQ_KEEP_MOMENTS, REQ_KEEP_STATE = 1, 2
 KERNEL_TILED, KERNEL_GLOBAL = 0, 1
 TILE_16x16, TILE_32x8, TILE_16x8, TILE_8x8, TILE_256x1, TILE_64x1 = range(6)
 
@@ -62,7 +68,34 @@ class pond_profile_t(ctypes.Structure):
 
 class pond_tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("lds_nodes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lds_nodes", ctypes.c_int32), ("batch_tile_width", ctypes.c_int32)]
+
+
+class pond_batch_info_t(ctypes.Structure):
+    _fields_ = [("members", ctypes.c_int32), ("tiles", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("lds_nodes", ctypes.c_int32),
+                ("nodes", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("graph_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class pond_server_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("interp_points", ctypes.c_int32), ("max_members", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64), ("chunk_steps", ctypes.c_int64),
+                ("fill_nodes", ctypes.c_int64), ("autotune_steps", ctypes.c_int64)]
+
+
+class pond_request_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("error", ctypes.c_int32),
+                ("steps_done", ctypes.c_int64), ("steps_total", ctypes.c_int64),
+                ("state_bytes", ctypes.c_int64), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class pond_server_stats_t(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "submitted", "admitted", "completed", "failed", "admission_waits", "batch_builds",
+        "batched_steps", "node_updates", "queued", "running", "used_bytes")]
 
 
 class PondError(RuntimeError):
@@ -102,6 +135,24 @@ _L.pond_profile_enable.argtypes = [_vp, ctypes.c_int]
 _L.pond_get_tuning.argtypes = [_vp, ctypes.POINTER(pond_tuning)]
 _L.pond_set_tuning.argtypes = [_vp, ctypes.POINTER(pond_tuning)]
 _L.pond_profile_read.argtypes = [_vp, ctypes.POINTER(pond_profile_t)]
+_L.pond_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+_L.pond_batch_step.argtypes = [_vp, ctypes.c_int64]
+_L.pond_batch_synchronize.argtypes = [_vp]
+_L.pond_batch_get_info.argtypes = [_vp, ctypes.POINTER(pond_batch_info_t)]
+_L.pond_batch_member_tile_width.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+_L.pond_batch_destroy.argtypes = [_vp]
+_L.pond_autotune.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(pond_tuning)]
+_L.pond_tuning_cache_clear.argtypes = []
+_L.pond_server_config_default.argtypes = [ctypes.POINTER(pond_server_config)]
+_L.pond_server_create.argtypes = [ctypes.POINTER(pond_server_config), ctypes.POINTER(_vp)]
+_L.pond_server_submit.argtypes = [_vp, ctypes.POINTER(pond_params), _vp, _vp, _vp, _vp,
+                                  ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+_L.pond_server_poll.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(pond_request_info)]
+_L.pond_server_wait.argtypes = [_vp, ctypes.c_int64]
+_L.pond_server_result.argtypes = [_vp, ctypes.c_int64, _vp, _vp]
+_L.pond_server_release.argtypes = [_vp, ctypes.c_int64]
+_L.pond_server_get_stats.argtypes = [_vp, ctypes.POINTER(pond_server_stats_t)]
+_L.pond_server_destroy.argtypes = [_vp]
 _L.pond_status_string.argtypes = [ctypes.c_int]
 _L.pond_status_string.restype = ctypes.c_char_p
 _L.pond_last_error.restype = ctypes.c_char_p
@@ -203,7 +254,7 @@ def pond_get_tuning(ctx) -> pond_tuning:
     return t
 
 
-def pond_set_tuning(ctx, kernel=None, tile=None, lds_nodes=None):
+def pond_set_tuning(ctx, kernel=None, tile=None, lds_nodes=None, batch_tile_width=None):
     t = pond_get_tuning(ctx)
     if kernel is not None:
         t.kernel = kernel
@@ -211,7 +262,103 @@ def pond_set_tuning(ctx, kernel=None, tile=None, lds_nodes=None):
         t.tile = tile
     if lds_nodes is not None:
         t.lds_nodes = lds_nodes
+    if batch_tile_width is not None:
+        t.batch_tile_width = batch_tile_width
     _check(_L.pond_set_tuning(ctx, ctypes.byref(t)))
+
+
+def pond_batch_create(ctxs, stream=None):
+    arr = (_vp * len(ctxs))(*[c.value if isinstance(c, _vp) else c for c in ctxs])
+    b = _vp()
+    _check(_L.pond_batch_create(arr, len(ctxs), stream, ctypes.byref(b)))
+    return b
+
+
+def pond_batch_step(b, nsteps: int):
+    _check(_L.pond_batch_step(b, int(nsteps)))
+
+
+def pond_batch_synchronize(b):
+    _check(_L.pond_batch_synchronize(b))
+
+
+def pond_batch_get_info(b) -> pond_batch_info_t:
+    out = pond_batch_info_t()
+    _check(_L.pond_batch_get_info(b, ctypes.byref(out)))
+    return out
+
+
+def pond_batch_member_tile_width(b, i: int) -> int:
+    w = ctypes.c_int()
+    _check(_L.pond_batch_member_tile_width(b, i, ctypes.byref(w)))
+    return w.value
+
+
+def pond_batch_destroy(b):
+    _check(_L.pond_batch_destroy(b))
+
+
+def pond_autotune(ctx, steps: int = 5) -> pond_tuning:
+    t = pond_tuning()
+    _check(_L.pond_autotune(ctx, int(steps), ctypes.byref(t)))
+    return t
+
+
+def pond_tuning_cache_clear():
+    _check(_L.pond_tuning_cache_clear())
+
+
+def pond_server_config_default(**overrides) -> pond_server_config:
+    c = pond_server_config()
+    _check(_L.pond_server_config_default(ctypes.byref(c)))
+    for k, v in overrides.items():
+        if not hasattr(c, k):
+            raise AttributeError(k)
+        setattr(c, k, v)
+    return c
+
+
+def pond_server_create(cfg: pond_server_config):
+    s = _vp()
+    _check(_L.pond_server_create(ctypes.byref(cfg), ctypes.byref(s)))
+    return s
+
+
+def pond_server_submit(srv, p: pond_params, rho, ux, uy, T, nsteps: int, flags: int = 0) -> int:
+    """Fields: host float64 arrays of nx * ny values (copied before return)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (rho, ux, uy, T)]
+    rid = ctypes.c_int64()
+    _check(_L.pond_server_submit(srv, ctypes.byref(p), *[_ptr(a) for a in arrs], int(nsteps),
+                                 int(flags), ctypes.byref(rid)))
+    return rid.value
+
+
+def pond_server_poll(srv, rid: int) -> pond_request_info:
+    out = pond_request_info()
+    _check(_L.pond_server_poll(srv, int(rid), ctypes.byref(out)))
+    return out
+
+
+def pond_server_wait(srv, rid: int = 0):
+    _check(_L.pond_server_wait(srv, int(rid)))
+
+
+def pond_server_result(srv, rid: int, moments=None, state=None):
+    _check(_L.pond_server_result(srv, int(rid), _ptr(moments), _ptr(state)))
+
+
+def pond_server_release(srv, rid: int):
+    _check(_L.pond_server_release(srv, int(rid)))
+
+
+def pond_server_get_stats(srv) -> pond_server_stats_t:
+    out = pond_server_stats_t()
+    _check(_L.pond_server_get_stats(srv, ctypes.byref(out)))
+    return out
+
+
+def pond_server_destroy(srv):
+    _check(_L.pond_server_destroy(srv))
 
 
 def pond_profile_enable(ctx, enable: bool):

@@ -190,12 +190,13 @@ def fourier_modes(n=512, ny=None, mach=2.0, angle_deg=30.0, amplitude=1e-3, seed
                     meta={"mach": mach, "U": U, "T0": T0, "amplitude": amplitude, "seed": seed})
 
 
-def _quadrant_states(rng, gamma, T_scale):
+def _quadrant_states(rng, gamma, T_scale, rho_range=(0.5, 2.0), p_range=(0.3, 1.5),
+                     mach_range=(0.0, 1.5)):
     states = []
     for _ in range(4):
-        r = rng.uniform(0.5, 2.0)
-        p = rng.uniform(0.3, 1.5)
-        ma = rng.uniform(0.0, 1.5)
+        r = rng.uniform(*rho_range)
+        p = rng.uniform(*p_range)
+        ma = rng.uniform(*mach_range)
         d = rng.uniform(0.0, 2 * math.pi)
         T = T_scale * p / r
         c = math.sqrt(gamma * T)
@@ -214,7 +215,8 @@ def quadrant_jumps(states):
 
 
 def riemann_quadrants(n=2048, seed=0, gamma=1.4, prandtl=0.71, nu=2e-3, T_scale=0.04,
-                      steps=1000, max_temperature_ratio=2.5, max_velocity_jump=2.0) -> Workload:
+                      steps=1000, max_temperature_ratio=2.5, max_velocity_jump=2.0,
+                      rho_range=(0.5, 2.0), p_range=(0.3, 1.5), mach_range=(0.0, 1.5)) -> Workload:
     """Four-quadrant 2-D Riemann problem on an n x n periodic grid; each quadrant
     draws rho ~ U[0.5, 2], p ~ U[0.3, 1.5], Mach ~ U[0, 1.5] and a direction
     ~ U[0, 2 pi); lattice T = T_scale p / rho; tau gives nu at T_scale.
@@ -228,7 +230,7 @@ def riemann_quadrants(n=2048, seed=0, gamma=1.4, prandtl=0.71, nu=2e-3, T_scale=
     rng = np.random.default_rng(seed)
     draws = 0
     while True:
-        states = _quadrant_states(rng, gamma, T_scale)
+        states = _quadrant_states(rng, gamma, T_scale, rho_range, p_range, mach_range)
         draws += 1
         tr, dv = quadrant_jumps(states)
         if tr <= max_temperature_ratio and dv <= max_velocity_jump:
@@ -253,10 +255,14 @@ def _log_uniform_int(rng, lo, hi):
 
 
 def batch_instances(seed=0, count=256, tube_range=(256, 8192), flow_range=(64, 1024),
-                    steps_range=(200, 2000), mach_range=(0.5, 3.0)):
+                    steps_range=(200, 2000), mach_range=(0.5, 3.0), flow_tau=0.6):
     """Mixed batch: half quasi-1-D shock tubes (nx x 1, clamp / periodic) with a
     uniform frame shift, half 2-D periodic perturbed flows (N x N) on an
-    advected background.  Sizes log-uniform, Mach and step counts uniform."""
+    advected background.  Sizes log-uniform, Mach and step counts uniform.
+
+    The flows use tau = ``flow_tau``: at T = 1 the step is linearly unstable at
+    tau = 0.55 from Mach ~2.75 on (within 350-1450 steps), stable at 0.6 up to
+    Mach 3 over 2000 steps."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
@@ -268,17 +274,19 @@ def batch_instances(seed=0, count=256, tube_range=(256, 8192), flow_range=(64, 1
         else:
             N = _log_uniform_int(rng, *flow_range)
             w = fourier_modes(n=N, mach=mach, angle_deg=float(rng.uniform(0, 360)),
-                              seed=int(rng.integers(1 << 30)), steps=steps)
+                              seed=int(rng.integers(1 << 30)), steps=steps, tau=flow_tau)
         w.meta["instance"] = i
         out.append(w)
     return out
 
 
 def serving_requests(seed=0, count=256, size_range=(64, 2048), steps_range=(100, 5000),
-                     rate_per_s=1.0):
+                     rate_per_s=1.0, flow_tau=0.6):
     """Poisson request stream: list of (arrival_time_s, Workload).  Kinds are
     uniform over {planar shock tube, shear wave, 2-D Riemann}; size N x N with N
-    log-uniform; steps log-uniform."""
+    log-uniform; steps log-uniform.  The Riemann requests draw Mach <= 0.8 and
+    p >= 0.5 with neighbour velocity jumps <= 0.75 thermal speed and
+    temperature ratios <= 2; the shear flows use tau = ``flow_tau``."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -291,9 +299,13 @@ def serving_requests(seed=0, count=256, size_range=(64, 2048), steps_range=(100,
             w = sod_tube(nx=N, ny=N, steps=steps)
         elif kind == 1:
             w = fourier_modes(n=N, mach=float(rng.uniform(0.5, 3.0)), seed=int(rng.integers(1 << 30)),
-                              steps=steps, kinds=["shear"] * 8)
+                              steps=steps, kinds=["shear"] * 8, tau=flow_tau)
         else:
-            w = riemann_quadrants(n=N, seed=int(rng.integers(1 << 30)), nu=2e-3, steps=steps)
+            # long runs need gentle interfaces: quadrant draws with neighbour velocity
+            # jumps near or above 1 thermal speed go non-physical within 250-1750 steps
+            w = riemann_quadrants(n=N, seed=int(rng.integers(1 << 30)), nu=2e-3, steps=steps,
+                                  p_range=(0.5, 1.5), mach_range=(0.0, 0.8),
+                                  max_velocity_jump=0.75, max_temperature_ratio=2.0)
         w.meta["request"] = i
         out.append((t, w))
     return out

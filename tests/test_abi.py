@@ -85,3 +85,35 @@ def test_null_context_calls(pond):
     assert pond.lib.pond_destroy(None) == pond.OK
     assert pond.lib.pond_step(None, 1) == pond.ERR_INVALID_ARG
     assert pond.lib.pond_synchronize(None) == pond.ERR_INVALID_ARG
+
+
+def test_batch_and_server_structs_and_host_side_validation(pond):
+    """Batch, autotune and server entry points validate their arguments before
+    any device call (these calls need no GPU)."""
+    assert ctypes.sizeof(pond.pond_tuning) == 16
+    assert ctypes.sizeof(pond.pond_batch_info_t) == 40
+    assert ctypes.sizeof(pond.pond_server_config) == 48
+    assert ctypes.sizeof(pond.pond_request_info) == 56
+    assert ctypes.sizeof(pond.pond_server_stats_t) == 88
+    for call in (lambda: pond.pond_batch_create([]),
+                 lambda: pond.pond_batch_step(None, 1),
+                 lambda: pond.pond_batch_synchronize(None),
+                 lambda: pond.pond_batch_get_info(None),
+                 lambda: pond.pond_autotune(None, 1),
+                 lambda: pond.pond_server_poll(None, 1),
+                 lambda: pond.pond_server_wait(None, 0)):
+        with pytest.raises(pond.PondError) as ei:
+            call()
+        assert ei.value.status == pond.ERR_INVALID_ARG
+    pond.pond_batch_destroy(None)
+    pond.pond_server_destroy(None)
+    c = pond.pond_server_config_default()
+    assert c.struct_size == 48 and c.hbm_budget_bytes == 64 << 30 and c.chunk_steps == 64
+    assert c.fill_nodes == 1 << 19
+    assert c.precision == pond.PREC_FP32 and c.interp_points == 4
+    for bad in (dict(struct_size=12), dict(hbm_budget_bytes=0), dict(chunk_steps=-1),
+                dict(precision=7), dict(interp_points=5)):
+        cfg = pond.pond_server_config_default(**bad)
+        with pytest.raises(pond.PondError) as ei:
+            pond.pond_server_create(cfg)
+        assert ei.value.status == pond.ERR_INVALID_ARG
