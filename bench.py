@@ -297,6 +297,14 @@ def bench_serve(args, pond, workloads):
     st = pond.pond_server_get_stats(srv)
     pond.pond_server_destroy(srv)
     failed = sum(inf.state != pond.REQ_DONE for inf in infos)
+    if args.dump:
+        with open(args.dump, "w") as fh:
+            json.dump([{"i": i, "kind": w.name, "nx": w.nx, "ny": w.ny, "steps": w.steps,
+                        "arrival": float(a), "service_plain": s_, "serial_latency": sl_,
+                        "t_submit": inf.t_submit, "t_admit": inf.t_admit, "t_done": inf.t_done,
+                        "state": inf.state}
+                       for i, (w, a, s_, sl_, inf) in enumerate(zip(ws, arrivals, service,
+                                                                   serial_lat, infos))], fh)
     lat = np.array([inf.t_done - inf.t_submit for inf in infos])
     first = min(inf.t_submit for inf in infos)
     last = max(inf.t_done for inf in infos)
@@ -349,6 +357,7 @@ def main():
                     help="batch: most steps (default 2000); serve: most steps (default 2000)")
     ap.add_argument("--budget-gib", type=float, default=2.0, help="serve: HBM admission budget")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / plain capacity")
+    ap.add_argument("--dump", default=None, help="serve: write per-request records (JSON) here")
     ap.add_argument("--fill-nodes", type=int, default=None,
                     help="serve: server fill_nodes (0 = step every admitted request each round)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

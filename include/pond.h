@@ -227,9 +227,9 @@ POND_API pond_status pond_destroy(pond_ctx *c);
  * pond_step (the step of Sec. "Discrete velocity solver ...: PonD" with
  * Eq. propagationInterpolated; results are bit for bit those of pond_step on
  * the member alone).  One batched step is one moment pre-pass over the nodes
- * of every member and one persistent step launch whose blocks take tiles of
- * any member from eight work queues (one per XCD); both launches are replayed
- * from HIP graphs captured at creation.
+ * of every member and one step launch over the tiles of every member (one
+ * block per tile, each XCD taking a contiguous range of the tile list); both
+ * launches are replayed from HIP graphs captured at creation.
  *
  * Members must be initialised, not in the error state, not in another batch,
  * and share precision and interp_points; sizes, boundary conditions and
@@ -244,7 +244,7 @@ typedef struct pond_batch pond_batch; /* opaque */
 typedef struct {
     int32_t members;      /* contexts in the batch */
     int32_t tiles;        /* tiles per batched step, all members */
-    int32_t grid_blocks;  /* blocks of the persistent step launch */
+    int32_t grid_blocks;  /* blocks of the step launch (one per tile) */
     int32_t lds_nodes;    /* LDS capacity per block, in nodes */
     int64_t nodes;        /* nodes per batched step, all members */
     int64_t steps;        /* batched steps enqueued since creation */
@@ -350,6 +350,11 @@ typedef struct {
     int64_t node_updates;     /* node updates of all requests */
     int64_t queued, running;  /* now */
     int64_t used_bytes;       /* footprint of the running requests now */
+    int64_t rounds;           /* batched rounds run */
+    int64_t ns_admit;         /* worker time creating and initialising contexts */
+    int64_t ns_build;         /* worker time building batches */
+    int64_t ns_step;          /* worker time enqueueing and waiting for batched steps */
+    int64_t ns_retire;        /* worker time collecting outputs and freeing contexts */
 } pond_server_stats_t;
 
 POND_API pond_status pond_server_config_default(pond_server_config *c);

@@ -7,7 +7,7 @@ host pass warns that it does not know that target feature, which is harmless.
 Floating-point contraction is limited to single source expressions
 (-ffp-contract=on): a multiply-add is fused the same way wherever the per-node
 code is inlined, so every kernel variant (HBM gather, each tile shape, the
-batched persistent kernel) produces the same bits.
+batched kernel) produces the same bits.
 """
 import os
 import subprocess

@@ -2,17 +2,19 @@
 // autotuner.
 //
 // A batch steps its member contexts with two launches per step for all of
-// them at once, captured in a HIP graph:
+// them at once, replayed from captured HIP graphs:
 //   1. a flat moment pre-pass over every member's nodes (each 256-node block
 //      belongs to one member);
-//   2. one persistent step launch: a few blocks per CU pull tiles of any
-//      member from eight work queues, one per XCD (block b runs on XCD b % 8
-//      and drains queue b % 8 first, then steals from the others), so small
-//      and large instances share the chip without a launch per instance.
-// The last block to finish the step launch rewinds the queues and advances
-// the batch's device step counter; member m reads buffer
-// (parity0[m] + step) & 1, so the same captured graph serves every step and
-// the graph holds no memset node.
+//   2. one step launch over the flat list of every member's tiles, one block
+//      per tile; the hardware dispatcher balances the tiles over the CUs, and
+//      the block -> tile map gives each XCD a contiguous range of the list.
+// Which of a member's two state buffers is current alternates every step;
+// the launches take that parity as an argument, so the batch keeps one graph
+// per starting parity and needs no device-side step counter.
+//
+// (A persistent variant -- a fixed grid pulling tiles from per-XCD atomic
+// queues -- ran 2.4x slower on one 512 x 512 instance: same-address
+// device-scope atomics serialise, and the cost grew with the grid.)
 //
 // Every node goes through the same per-node code as the single-instance
 // kernels (tile_step / node_step with the member's own arguments), so a
@@ -20,7 +22,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -35,27 +36,18 @@ namespace pond {
 namespace {
 
 constexpr int kBatchThreads = 256;
-constexpr int kQueues = 8;  // one per XCD
 
 struct BatchMember {
     StepArgs a;
     DevState buf[2];
     void *mom;
     DevCounters *cnt;
-    int parity0;   // current buffer of the member when the step counter is 0
+    int parity0;   // current buffer of the member when the batch was built
     int lg;        // tile width 2^lg, height 256 >> lg
     int tiles_x;
     int halo_cap;
     int tile_off;  // first tile of the member in the flat tile list
     int blk_off;   // first pre-pass block of the member
-};
-
-struct BatchCtl {
-    unsigned long long step;      // batched steps completed
-    unsigned int next[kQueues];   // tile cursor of each queue
-    unsigned int done;            // blocks finished in the running step launch
-    unsigned int pad;
-    int qbeg[kQueues + 1];        // queue q owns flat tiles [qbeg[q], qbeg[q + 1])
 };
 
 // Largest i in [0, n) with off[i] <= v (off strictly increasing, off[0] = 0).
@@ -71,72 +63,32 @@ __device__ __forceinline__ int find_member(const int *__restrict__ off, int n, i
     return lo;
 }
 
-__device__ __forceinline__ unsigned long long load_step(const BatchCtl *ctl) {
-    return __hip_atomic_load(&ctl->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
+// flip: parity of the batched steps taken since the batch was built.
 template <typename P>
 __global__ __launch_bounds__(kBatchThreads) void batch_moments_kernel(
-    const BatchMember *__restrict__ mem, const int *__restrict__ blk_off, int nmem,
-    const BatchCtl *ctl) {
+    const BatchMember *__restrict__ mem, const int *__restrict__ blk_off, int nmem, int flip) {
     const int i = __builtin_amdgcn_readfirstlane(find_member(blk_off, nmem, int(blockIdx.x)));
     const StepArgs a = mem[i].a;
     const long long n = (long long)(int(blockIdx.x) - mem[i].blk_off) * kBatchThreads + threadIdx.x;
     if (n >= a.N) return;
-    const int par = int((mem[i].parity0 + load_step(ctl)) & 1);
-    node_moments<P>(a, mem[i].buf[par], static_cast<P *>(mem[i].mom), n);
+    node_moments<P>(a, mem[i].buf[mem[i].parity0 ^ flip], static_cast<P *>(mem[i].mom), n);
 }
 
 template <typename P, int NP>
 __global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
-    const BatchMember *__restrict__ mem, const int *__restrict__ tile_off, int nmem,
-    BatchCtl *ctl, int cap) {
+    const BatchMember *__restrict__ mem, const int *__restrict__ tile_off, int nmem, int cap,
+    int flip) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int red[16];
-    __shared__ int s_tile;
-    const unsigned long long step = load_step(ctl);
-    const int home = int(blockIdx.x) % kQueues;
-    int tried = 0;  // queues found empty so far (thread 0 only)
-    for (;;) {
-        __syncthreads();  // the previous tile is finished with LDS and s_tile
-        if (threadIdx.x == 0) {
-            int t = -1;
-            while (tried < kQueues) {
-                const int q = (home + tried) % kQueues;
-                const int len = ctl->qbeg[q + 1] - ctl->qbeg[q];
-                const unsigned k = atomicAdd(&ctl->next[q], 1u);
-                if (int(k) < len) {
-                    t = ctl->qbeg[q] + int(k);
-                    break;
-                }
-                ++tried;
-            }
-            s_tile = t;
-        }
-        __syncthreads();
-        const int t = __builtin_amdgcn_readfirstlane(s_tile);
-        if (t < 0) break;
-        const int i = __builtin_amdgcn_readfirstlane(find_member(tile_off, nmem, t));
-        const StepArgs a = mem[i].a;
-        const int lg = mem[i].lg, tiles_x = mem[i].tiles_x;
-        const int lt = t - mem[i].tile_off;
-        const int par = int((mem[i].parity0 + step) & 1);
-        tile_step<P, NP>(a, mem[i].buf[par], static_cast<const P *>(mem[i].mom), mem[i].buf[par ^ 1],
-                         mem[i].cnt, reinterpret_cast<P *>(smem_raw), cap, mem[i].halo_cap,
-                         (lt % tiles_x) << lg, (lt / tiles_x) * (kBatchThreads >> lg), Shape256{lg},
-                         red);
-    }
-    // the last block out rewinds the queues and advances the step counter
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned d = atomicAdd(&ctl->done, 1u);
-        if (d == gridDim.x - 1) {
-            for (int q = 0; q < kQueues; ++q) atomicExch(&ctl->next[q], 0u);
-            atomicExch(&ctl->done, 0u);
-            atomicAdd(&ctl->step, 1ull);
-            __threadfence();
-        }
-    }
+    const int t = xcd_tile(int(blockIdx.x), int(gridDim.x));
+    const int i = __builtin_amdgcn_readfirstlane(find_member(tile_off, nmem, t));
+    const StepArgs a = mem[i].a;
+    const int lg = mem[i].lg, tiles_x = mem[i].tiles_x;
+    const int lt = t - mem[i].tile_off;
+    const int par = mem[i].parity0 ^ flip;
+    tile_step<P, NP>(a, mem[i].buf[par], static_cast<const P *>(mem[i].mom), mem[i].buf[par ^ 1],
+                     mem[i].cnt, reinterpret_cast<P *>(smem_raw), cap, mem[i].halo_cap,
+                     (lt % tiles_x) << lg, (lt / tiles_x) * (kBatchThreads >> lg), Shape256{lg}, red);
 }
 
 template <typename P, int NP>
@@ -195,15 +147,15 @@ struct pond_batch {
     int np;
     hipStream_t stream;
     bool own_stream;
-    void *dev;  // [members | tile offsets | block offsets | control]
+    void *dev;  // [members | tile offsets | block offsets]
     BatchMember *d_mem;
     int *d_tile_off, *d_blk_off;
-    BatchCtl *d_ctl;
-    int cap, grid, tiles, blocks;
+    int cap, tiles, blocks;
     long long nodes;
     long long steps;
-    hipGraph_t graph[2];
-    hipGraphExec_t exec[2];  // 1 step, kGraphSteps steps
+    // [parity][0]: one step, [parity][1]: kGraphSteps steps, starting at that parity
+    hipGraph_t graph[2][2];
+    hipGraphExec_t exec[2][2];
     hipEvent_t done_ev;
     std::vector<hipStream_t> other_streams;  // member streams other than the batch's
     std::vector<hipEvent_t> other_ev;
@@ -212,41 +164,42 @@ struct pond_batch {
 namespace {
 
 constexpr int kGraphSteps = 8;
+static_assert(kGraphSteps % 2 == 0, "the long graph must leave the buffer parity unchanged");
 
-hipError_t enqueue_batch_step(pond_batch *b) {
+hipError_t enqueue_batch_step(pond_batch *b, int flip) {
+    const int n = int(b->members.size());
     if (b->dbl)
         hipLaunchKernelGGL(batch_moments_kernel<double>, dim3(b->blocks), dim3(kBatchThreads), 0,
-                           b->stream, b->d_mem, b->d_blk_off, int(b->members.size()), b->d_ctl);
+                           b->stream, b->d_mem, b->d_blk_off, n, flip);
     else
         hipLaunchKernelGGL(batch_moments_kernel<float>, dim3(b->blocks), dim3(kBatchThreads), 0,
-                           b->stream, b->d_mem, b->d_blk_off, int(b->members.size()), b->d_ctl);
+                           b->stream, b->d_mem, b->d_blk_off, n, flip);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = size_t(b->cap) * kNMom * (b->dbl ? sizeof(double) : sizeof(float));
-    const int n = int(b->members.size());
     if (b->dbl) {
         if (b->np == 3)
-            hipLaunchKernelGGL((batch_step_kernel<double, 3>), dim3(b->grid), dim3(kBatchThreads),
-                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->d_ctl, b->cap);
+            hipLaunchKernelGGL((batch_step_kernel<double, 3>), dim3(b->tiles), dim3(kBatchThreads),
+                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->cap, flip);
         else
-            hipLaunchKernelGGL((batch_step_kernel<double, 4>), dim3(b->grid), dim3(kBatchThreads),
-                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->d_ctl, b->cap);
+            hipLaunchKernelGGL((batch_step_kernel<double, 4>), dim3(b->tiles), dim3(kBatchThreads),
+                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->cap, flip);
     } else {
         if (b->np == 3)
-            hipLaunchKernelGGL((batch_step_kernel<float, 3>), dim3(b->grid), dim3(kBatchThreads),
-                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->d_ctl, b->cap);
+            hipLaunchKernelGGL((batch_step_kernel<float, 3>), dim3(b->tiles), dim3(kBatchThreads),
+                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->cap, flip);
         else
-            hipLaunchKernelGGL((batch_step_kernel<float, 4>), dim3(b->grid), dim3(kBatchThreads),
-                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->d_ctl, b->cap);
+            hipLaunchKernelGGL((batch_step_kernel<float, 4>), dim3(b->tiles), dim3(kBatchThreads),
+                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->cap, flip);
     }
     return hipGetLastError();
 }
 
-hipError_t capture(pond_batch *b, int steps, hipGraph_t *g, hipGraphExec_t *x) {
+hipError_t capture(pond_batch *b, int steps, int flip, hipGraph_t *g, hipGraphExec_t *x) {
     hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
-    for (int k = 0; k < steps && le == hipSuccess; ++k) le = enqueue_batch_step(b);
+    for (int k = 0; k < steps && le == hipSuccess; ++k) le = enqueue_batch_step(b, flip ^ (k & 1));
     e = hipStreamEndCapture(b->stream, g);
     if (le != hipSuccess) return le;
     if (e != hipSuccess) return e;
@@ -255,10 +208,11 @@ hipError_t capture(pond_batch *b, int steps, hipGraph_t *g, hipGraphExec_t *x) {
 
 void release(pond_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
-    for (int k = 0; k < 2; ++k) {
-        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
-        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
-    }
+    for (int f = 0; f < 2; ++f)
+        for (int k = 0; k < 2; ++k) {
+            if (b->exec[f][k]) (void)hipGraphExecDestroy(b->exec[f][k]);
+            if (b->graph[f][k]) (void)hipGraphDestroy(b->graph[f][k]);
+        }
     if (b->done_ev) (void)hipEventDestroy(b->done_ev);
     for (hipEvent_t ev : b->other_ev) (void)hipEventDestroy(ev);
     if (b->dev) (void)hipFree(b->dev);
@@ -312,20 +266,15 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
         return hip_fail(e, "hipStreamCreate");
     }
 
-    // LDS per block and the persistent grid
+    // LDS per block: the register-limited occupancy's share of the CU
     b->cap = default_lds_nodes_for_threads(kBatchThreads, b->dbl);
     const size_t lds = size_t(b->cap) * kNMom * (b->dbl ? sizeof(double) : sizeof(float));
-    const void *kern = batch_step_fn(b->dbl, b->np);
-    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    int per_cu = 0, cus = 0, dev = 0;
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBatchThreads, lds);
-    if (e == hipSuccess) e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    e = hipFuncSetAttribute(batch_step_fn(b->dbl, b->np), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            int(lds));
     if (e != hipSuccess) {
         release(b);
         return hip_fail(e, "batch launch configuration");
     }
-    if (per_cu < 1) per_cu = 1;
 
     // descriptors
     std::vector<BatchMember> hm(n);
@@ -367,13 +316,10 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
     b->tiles = int(tiles);
     b->blocks = int(blocks);
     b->nodes = nodes;
-    b->grid = int(std::min<long long>(tiles, (long long)per_cu * cus));
-    BatchCtl ctl{};
-    for (int q = 0; q <= kQueues; ++q) ctl.qbeg[q] = int(tiles * q / kQueues);
 
     const size_t mem_bytes = align_up(sizeof(BatchMember) * n);
     const size_t off_bytes = align_up(sizeof(int) * n);
-    e = hipMalloc(&b->dev, mem_bytes + 2 * off_bytes + align_up(sizeof(BatchCtl)));
+    e = hipMalloc(&b->dev, mem_bytes + 2 * off_bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         b->dev = nullptr;
@@ -384,16 +330,16 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
     b->d_mem = reinterpret_cast<BatchMember *>(base);
     b->d_tile_off = reinterpret_cast<int *>(base + mem_bytes);
     b->d_blk_off = reinterpret_cast<int *>(base + mem_bytes + off_bytes);
-    b->d_ctl = reinterpret_cast<BatchCtl *>(base + mem_bytes + 2 * off_bytes);
     // members' pending work (initialisation, earlier steps) precedes the batch's
     for (pond_ctx *c : b->members)
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipMemcpy(b->d_mem, hm.data(), sizeof(BatchMember) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_tile_off, toff.data(), sizeof(int) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_blk_off, boff.data(), sizeof(int) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = capture(b, 1, &b->graph[0], &b->exec[0]);
-    if (e == hipSuccess) e = capture(b, kGraphSteps, &b->graph[1], &b->exec[1]);
+    for (int f = 0; f < 2; ++f) {
+        if (e == hipSuccess) e = capture(b, 1, f, &b->graph[f][0], &b->exec[f][0]);
+        if (e == hipSuccess) e = capture(b, kGraphSteps, f, &b->graph[f][1], &b->exec[f][1]);
+    }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming);
     for (pond_ctx *c : b->members) {
         if (e != hipSuccess) break;
@@ -431,10 +377,12 @@ pond_status pond_batch_step(pond_batch *b, int64_t nsteps) {
         e = hipEventRecord(b->other_ev[k], b->other_streams[k]);
         if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->other_ev[k], 0);
     }
+    // kGraphSteps is even: the long graph leaves the parity unchanged
+    const int f = int(b->steps & 1);
     for (int64_t k = 0; k + kGraphSteps <= nsteps && e == hipSuccess; k += kGraphSteps)
-        e = hipGraphLaunch(b->exec[1], b->stream);
+        e = hipGraphLaunch(b->exec[f][1], b->stream);
     for (int64_t k = 0; k < nsteps % kGraphSteps && e == hipSuccess; ++k)
-        e = hipGraphLaunch(b->exec[0], b->stream);
+        e = hipGraphLaunch(b->exec[f ^ int(k & 1)][0], b->stream);
     if (e == hipSuccess) e = hipEventRecord(b->done_ev, b->stream);
     for (size_t k = 0; k < b->other_streams.size() && e == hipSuccess; ++k)
         e = hipStreamWaitEvent(b->other_streams[k], b->done_ev, 0);
@@ -469,7 +417,7 @@ pond_status pond_batch_get_info(pond_batch *b, pond_batch_info_t *out) {
     if (!b || !out) return fail(POND_ERR_INVALID_ARG, "batch or out is NULL");
     out->members = int32_t(b->members.size());
     out->tiles = b->tiles;
-    out->grid_blocks = b->grid;
+    out->grid_blocks = b->tiles;
     out->lds_nodes = b->cap;
     out->nodes = b->nodes;
     out->steps = b->steps;

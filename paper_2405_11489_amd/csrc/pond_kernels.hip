@@ -98,13 +98,6 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
 }
 
 // ------------------------------------------------------ step (LDS tiles) ----
-// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
-// give each XCD a contiguous range of tiles so that neighbouring tiles, which
-// share halo moments, share that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-    const int q = nb / 8, r = nb % 8, x = b % 8;
-    return x * q + (x < r ? x : r) + b / 8;
-}
 
 // Minimum waves per SIMD requested from the register allocator for the tiled
 // kernel (compile-time tuning; 0 leaves the choice to the compiler).

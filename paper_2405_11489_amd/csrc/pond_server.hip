@@ -132,8 +132,11 @@ void worker_loop(pond_server *s) {
             s->queue.pop_front();
             s->used_bytes += r->bytes;
             lk.unlock();
+            const double ta = s->now();
             pond_status st = admit(s, r);
+            const double tb = s->now();
             lk.lock();
+            s->stats.ns_admit += int64_t((tb - ta) * 1e9);
             r->fields.clear();
             r->fields.shrink_to_fit();
             if (st != POND_OK) {
@@ -177,6 +180,7 @@ void worker_loop(pond_server *s) {
         for (Request *r : run) k = std::min(k, r->steps_total - r->steps_done);
         if (s->cfg.chunk_steps > 0) k = std::min<int64_t>(k, s->cfg.chunk_steps);
         lk.unlock();
+        const double t_round = s->now();
         pond_status st = POND_OK;
         if (dirty || !batch) {
             if (batch) (void)pond_batch_destroy(batch);
@@ -188,8 +192,10 @@ void worker_loop(pond_server *s) {
             current = run;
             dirty = false;
         }
+        const double t_built = s->now();
         if (st == POND_OK && k > 0) st = pond_batch_step(batch, k);
         pond_status sync = st == POND_OK ? pond_batch_synchronize(batch) : st;
+        const double t_stepped = s->now();
         // retire finished and failed members
         std::vector<Request *> finished;
         for (Request *r : run) {
@@ -216,7 +222,12 @@ void worker_loop(pond_server *s) {
             r->ctx = nullptr;
         }
         (void)sync;
+        const double t_retired = s->now();
         lk.lock();
+        s->stats.ns_build += int64_t((t_built - t_round) * 1e9);
+        s->stats.ns_step += int64_t((t_stepped - t_built) * 1e9);
+        s->stats.ns_retire += int64_t((t_retired - t_stepped) * 1e9);
+        ++s->stats.rounds;
         s->stats.batched_steps += k;
         for (Request *r : run) s->stats.node_updates += (st == POND_OK ? k : 0) * nodes_of(r->p);
         for (size_t j = 0; j < finished.size(); ++j) {

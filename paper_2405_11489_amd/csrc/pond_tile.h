@@ -1,7 +1,7 @@
 // pond_tile.h -- one block's share of the PonD step: a rectangular tile of
 // destination nodes whose source moments are staged in LDS.  Shared by the
 // single-instance tiled kernel (tile shape fixed at compile time) and the
-// batched persistent kernel (shape chosen per instance at run time).
+// batched kernel (shape chosen per instance at run time).
 #pragma once
 
 #include "pond_step_common.h"
@@ -75,6 +75,14 @@ __device__ __forceinline__ void stencil_extent(int x, double u, double s, int &l
         lo = int(floor(clo + 0.5)) - 1;
         hi = int(floor(chi + 0.5)) + 1;
     }
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
+// give each XCD a contiguous range of tiles so that neighbouring tiles, which
+// share halo moments, share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb / 8, r = nb % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
 }
 
 // Tile shapes: TX x TY destination nodes, one lane each, lane t at (t % TX, t / TX).

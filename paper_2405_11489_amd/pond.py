@@ -16,7 +16,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpond.so")
+# POND_LIB_PATH selects another build of the library (e.g. one compiled with
+# different tuning macros); the default is the in-tree build.
+LIB_PATH = os.environ.get("POND_LIB_PATH") or os.path.join(HERE, "libpond.so")
 
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NONPHYSICAL, ERR_STATE = range(7)
 LATTICE_D2Q16 = 16
@@ -95,7 +97,8 @@ class pond_request_info(ctypes.Structure):
 class pond_server_stats_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "submitted", "admitted", "completed", "failed", "admission_waits", "batch_builds",
-        "batched_steps", "node_updates", "queued", "running", "used_bytes")]
+        "batched_steps", "node_updates", "queued", "running", "used_bytes", "rounds",
+        "ns_admit", "ns_build", "ns_step", "ns_retire")]
 
 
 class PondError(RuntimeError):

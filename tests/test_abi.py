@@ -94,7 +94,7 @@ def test_batch_and_server_structs_and_host_side_validation(pond):
     assert ctypes.sizeof(pond.pond_batch_info_t) == 40
     assert ctypes.sizeof(pond.pond_server_config) == 48
     assert ctypes.sizeof(pond.pond_request_info) == 56
-    assert ctypes.sizeof(pond.pond_server_stats_t) == 88
+    assert ctypes.sizeof(pond.pond_server_stats_t) == 128
     for call in (lambda: pond.pond_batch_create([]),
                  lambda: pond.pond_batch_step(None, 1),
                  lambda: pond.pond_batch_synchronize(None),

@@ -1,7 +1,7 @@
 """Batched stepping and the autotuner on the GPU, through the C ABI.
 
 A batch advances every member by the same step as pond_step, with one
-pre-pass and one persistent launch per step for all members (replayed from a
+pre-pass and one step launch per step for all members (replayed from a
 captured HIP graph), so each member's state after k batched steps must equal,
 bit for bit, the state of the same instance stepped k times alone.  The mixes
 below span 2-D periodic and clamped grids, quasi-1-D tubes, ragged sizes
