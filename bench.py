@@ -156,16 +156,17 @@ def bench_batch(args, pond, workloads):
     # autotune one instance of every size class (untimed)
     t0 = time.perf_counter()
     pond.pond_tuning_cache_clear()
-    seen = set()
-    for w in ws:
+    seen = {}
+    for w in ([] if args.no_autotune else ws):
         key = (w.ny == 1, round(math.log2(w.nx)), round(math.log2(max(w.ny, 1))))
         if key in seen:
             continue
-        seen.add(key)
         c = _ctx_for(pond, w, prec, sp)
-        pond.pond_autotune(c, 2)
+        t = pond.pond_autotune(c, 3)
+        seen[key] = (t.tile, t.batch_tile_width)
         pond.pond_destroy(c)
-    log(f"autotuned {len(seen)} size classes in {time.perf_counter() - t0:.1f} s")
+    log(f"autotuned {len(seen)} size classes in {time.perf_counter() - t0:.1f} s: "
+        + ", ".join(f"{k}: tile {v[0]} width {v[1]}" for k, v in sorted(seen.items())))
 
     # plain path
     plain_s = 0.0
@@ -224,6 +225,8 @@ def bench_batch(args, pond, workloads):
                    "precision": args.precision, "parallelism": "single_gpu"},
         "node_updates": updates, "wall_s": wall, "phases": phases,
         "tiles_first_phase": tiles[0], "pc_iterations_mean": iters / updates,
+        "autotuned": {f"{'tube' if k[0] else 'flow'} 2^{k[1]} x 2^{k[2]}": {"tile": v[0], "batch_width": v[1]}
+                      for k, v in sorted(seen.items())},
         "nonconverged_node_steps": nonconv,
         "plain": {"value": plain, "unit": "MLUPS",
                   "how": "each instance alone (pond_step), min(steps, 200) steps timed with "
@@ -358,6 +361,7 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=2.0, help="serve: HBM admission budget")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / plain capacity")
     ap.add_argument("--dump", default=None, help="serve: write per-request records (JSON) here")
+    ap.add_argument("--no-autotune", action="store_true", help="batch: default tiles, no autotuning")
     ap.add_argument("--fill-nodes", type=int, default=None,
                     help="serve: server fill_nodes (0 = step every admitted request each round)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

@@ -252,6 +252,16 @@ pond_status check_unbatched(const pond_ctx *c) {
     return POND_OK;
 }
 
+// Stencil reach of the frame just loaded (from cnt->partial[3]) and, unless the
+// tuning was set explicitly, the autotuned configuration of the context's class.
+pond_status finish_init(pond_ctx *c, const DevCounters &h) {
+    const double r = std::ceil(h.partial[3]);
+    c->reach = r > 1e6 ? 1000000 : int(r);
+    pond_tuning t;
+    if (!c->user_tuned && tuning_cache_lookup(c, &t)) return apply_tuning(c, t);
+    return POND_OK;
+}
+
 pond_status set_reference_from_counters(pond_ctx *c) {
     DevCounters h;
     pond_status s = read_counters(c, &h);
@@ -371,9 +381,9 @@ pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem
     c->prof_prepass_ms = c->prof_step_ms = 0.0;
     c->prof_launches = 0;
     c->batch = nullptr;
+    c->reach = 0;
+    c->user_tuned = false;
     s = apply_tuning(c, default_tuning(c->p));
-    pond_tuning tuned;
-    if (s == POND_OK && tuning_cache_lookup(c->p, &tuned)) s = apply_tuning(c, tuned);
     if (s == POND_OK) s = reset_counters(c);
     if (s != POND_OK) {
         pond_destroy(c);
@@ -414,6 +424,8 @@ pond_status pond_init_fields(pond_ctx *c, const double *rho, const double *ux, c
     e = launch_mean_velocity(N, dev[0], dev[1], dev[2], c->scratch, kScratchDoubles, c->cnt,
                              c->stream);
     if (e != hipSuccess) return hip_fail(e, "mean velocity");
+    e = launch_frame_reach(N, dev[1], dev[2], dev[3], c->scratch, kScratchDoubles, c->cnt, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "frame reach");
     DevCounters h;
     s = read_counters(c, &h);
     if (s != POND_OK) return s;
@@ -421,6 +433,7 @@ pond_status pond_init_fields(pond_ctx *c, const double *rho, const double *ux, c
         return fail(POND_ERR_INVALID_ARG, "%llu nodes with rho <= 0, T <= 0 or non-finite values",
                     (unsigned long long)h.init_rejected);
     s = set_reference_from_counters(c);
+    if (s == POND_OK) s = finish_init(c, h);
     if (s != POND_OK) return s;
     s = reset_counters(c);
     if (s != POND_OK) return s;
@@ -621,8 +634,6 @@ pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, con
         if (u_ref) {
             c->args.uref_x = u_ref[0];
             c->args.uref_y = u_ref[1];
-            e = hipStreamSynchronize(c->stream);
-            if (e != hipSuccess) s = hip_fail(e, "hipStreamSynchronize");
         } else {
             e = fp64(c) ? launch_state_mean_velocity<double>(c->args, c->buf[0], c->scratch,
                                                              kScratchDoubles, c->cnt, c->stream)
@@ -630,6 +641,13 @@ pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, con
                                                             kScratchDoubles, c->cnt, c->stream);
             s = e == hipSuccess ? set_reference_from_counters(c) : hip_fail(e, "mean velocity");
         }
+    }
+    if (s == POND_OK) {
+        e = launch_frame_reach(N, c->buf[0].ux, c->buf[0].uy, c->buf[0].T, c->scratch,
+                               kScratchDoubles, c->cnt, c->stream);
+        DevCounters h;
+        s = e == hipSuccess ? read_counters(c, &h) : hip_fail(e, "frame reach");
+        if (s == POND_OK) s = finish_init(c, h);
     }
     if (tmp) {
         (void)hipStreamSynchronize(c->stream);
@@ -663,7 +681,9 @@ pond_status pond_set_tuning(pond_ctx *c, const pond_tuning *t) {
     if (s != POND_OK) return s;
     if (!t) return fail(POND_ERR_INVALID_ARG, "tuning is NULL");
     if ((s = check_unbatched(c)) != POND_OK) return s;
-    return apply_tuning(c, *t);
+    s = apply_tuning(c, *t);
+    if (s == POND_OK) c->user_tuned = true;
+    return s;
 }
 
 pond_status pond_profile_enable(pond_ctx *c, int enable) {

@@ -102,17 +102,19 @@ const void *batch_step_fn(bool dbl, int np) {
 }
 
 // ----------------------------------------------------- tuning cache ----
-// Size class of an instance: precision, stencil, and the rounded log2 of each
-// axis (a single-row grid is its own class).
-using TuneKey = std::tuple<int, int, int, int>;
+// Class of an instance: precision, stencil, boundary conditions, the rounded
+// log2 of each axis (a single-row grid is its own class) and the stencil
+// reach of its initial frame (the best tile shape depends on the halo).
+using TuneKey = std::tuple<int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, pond_tuning> g_tune;
 
 int log2_class(int n) { return n <= 1 ? -1 : int(std::lround(std::log2(double(n)))); }
 
-TuneKey tune_key(const pond_params &p) {
+TuneKey tune_key(const pond_ctx *c) {
+    const pond_params &p = c->p;
     return TuneKey(p.precision * 16 + p.interp_points, p.bc_x * 2 + p.bc_y, log2_class(p.nx),
-                   log2_class(p.ny));
+                   log2_class(p.ny), std::min(c->reach, 12));
 }
 
 int default_batch_width(const pond_params &p) {
@@ -128,9 +130,9 @@ int lg2(int w) {
 
 }  // namespace
 
-bool tuning_cache_lookup(const pond_params &p, pond_tuning *out) {
+bool tuning_cache_lookup(const pond_ctx *c, pond_tuning *out) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(tune_key(p));
+    auto it = g_tune.find(tune_key(c));
     if (it == g_tune.end()) return false;
     *out = it->second;
     return true;
@@ -227,7 +229,7 @@ void release(pond_batch *b) {
 int member_width(const pond_ctx *c) {
     if (c->tuning.batch_tile_width > 0) return c->tuning.batch_tile_width;
     pond_tuning t;
-    if (tuning_cache_lookup(c->p, &t) && t.batch_tile_width > 0) return t.batch_tile_width;
+    if (tuning_cache_lookup(c, &t) && t.batch_tile_width > 0) return t.batch_tile_width;
     return default_batch_width(c->p);
 }
 
@@ -478,9 +480,13 @@ pond_status restore_state(pond_ctx *c, const Saved &s) {
     return write_counters(c, s.cnt);
 }
 
-// Device time of `steps` steps of c (single-instance path, or a one-member
-// batch when batch_width > 0), after one untimed step; the state is restored.
-pond_status time_candidate(pond_ctx *c, const Saved &sv, int steps, int batch_width, double *ms) {
+// Device time per step of c (single-instance path, or a one-member batch when
+// batch_width > 0) over at least `steps` steps and at least kMinTuneMs of
+// device time, after one untimed step; the state is restored afterwards.
+constexpr double kMinTuneMs = 2.0;
+constexpr int kMaxTuneSteps = 512;
+
+pond_status time_candidate(pond_ctx *c, const Saved &sv, int steps, int batch_width, double *ms_per_step) {
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipError_t e = hipEventCreate(&ev[0]);
     if (e == hipSuccess) e = hipEventCreate(&ev[1]);
@@ -491,18 +497,27 @@ pond_status time_candidate(pond_ctx *c, const Saved &sv, int steps, int batch_wi
         s = pond_batch_create(&c, 1, c->stream, &b);
     }
     if (s == POND_OK) s = b ? pond_batch_step(b, 1) : pond_step(c, 1);
-    if (s == POND_OK) {
+    int n = steps;
+    for (;;) {
+        if (s != POND_OK) break;
         e = hipEventRecord(ev[0], c->stream);
-        if (e != hipSuccess) s = hip_fail(e, "hipEventRecord");
-    }
-    if (s == POND_OK) s = b ? pond_batch_step(b, steps) : pond_step(c, steps);
-    if (s == POND_OK) {
+        if (e != hipSuccess) {
+            s = hip_fail(e, "hipEventRecord");
+            break;
+        }
+        s = b ? pond_batch_step(b, n) : pond_step(c, n);
+        if (s != POND_OK) break;
         e = hipEventRecord(ev[1], c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
         float t = 0.f;
         if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
-        if (e != hipSuccess) s = hip_fail(e, "autotune timing");
-        *ms = t;
+        if (e != hipSuccess) {
+            s = hip_fail(e, "autotune timing");
+            break;
+        }
+        *ms_per_step = t / n;
+        if (t >= kMinTuneMs || n >= kMaxTuneSteps) break;
+        n = std::min(kMaxTuneSteps, std::max(2 * n, int(n * kMinTuneMs / std::max(t, 1e-3f)) + 1));
     }
     if (b) {
         pond_status s2 = pond_batch_destroy(b);
@@ -514,6 +529,15 @@ pond_status time_candidate(pond_ctx *c, const Saved &sv, int steps, int batch_wi
     return s == POND_OK ? s3 : s;
 }
 
+// Index of the fastest candidate; the first (the default) unless another is
+// faster by more than 3 %.
+size_t pick(const std::vector<double> &t) {
+    size_t best = 0;
+    for (size_t k = 1; k < t.size(); ++k)
+        if (t[k] < t[best] && t[k] < 0.97 * t[0]) best = k;
+    return best;
+}
+
 }  // namespace
 
 pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out) {
@@ -523,7 +547,7 @@ pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out) {
     if (c->failed) return fail(POND_ERR_STATE, "context is in the error state");
     if (steps < 1) return fail(POND_ERR_INVALID_ARG, "steps must be >= 1");
     const bool dbl = c->p.precision == POND_PREC_FP64, row = c->p.ny < 8;
-    std::vector<int> tiles, widths;
+    std::vector<int> tiles, widths;  // default first
     if (row) {
         tiles = {POND_TILE_64x1, POND_TILE_256x1};
         widths = {256};
@@ -536,31 +560,23 @@ pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out) {
     }
     Saved sv;
     s = save_state(c, sv);
-    double best_t = 1e300, best_w = 1e300;
-    pond_tuning best = c->tuning;
-    for (int tile : tiles) {
-        if (s != POND_OK) break;
-        pond_tuning t = sv.tuning;
-        t.kernel = POND_KERNEL_TILED;
-        t.tile = tile;
-        t.lds_nodes = 0;
-        s = pond_set_tuning(c, &t);
-        double ms = 0.0;
-        if (s == POND_OK) s = time_candidate(c, sv, steps, 0, &ms);
-        if (s == POND_OK && ms < best_t) {
-            best_t = ms;
-            best.kernel = c->tuning.kernel;
-            best.tile = c->tuning.tile;
-            best.lds_nodes = c->tuning.lds_nodes;
+    // two interleaved rounds; each candidate keeps its faster measurement
+    std::vector<double> tt(tiles.size(), 1e300), tw(widths.size(), 1e300);
+    for (int round = 0; round < 2 && s == POND_OK; ++round) {
+        for (size_t k = 0; k < tiles.size() && s == POND_OK; ++k) {
+            pond_tuning t = sv.tuning;
+            t.kernel = POND_KERNEL_TILED;
+            t.tile = tiles[k];
+            t.lds_nodes = 0;
+            s = pond_set_tuning(c, &t);
+            double ms = 0.0;
+            if (s == POND_OK) s = time_candidate(c, sv, steps, 0, &ms);
+            if (s == POND_OK) tt[k] = std::min(tt[k], ms);
         }
-    }
-    for (int w : widths) {
-        if (s != POND_OK) break;
-        double ms = 0.0;
-        s = time_candidate(c, sv, steps, w, &ms);
-        if (s == POND_OK && ms < best_w) {
-            best_w = ms;
-            best.batch_tile_width = w;
+        for (size_t k = 0; k < widths.size() && widths.size() > 1 && s == POND_OK; ++k) {
+            double ms = 0.0;
+            s = time_candidate(c, sv, steps, widths[k], &ms);
+            if (s == POND_OK) tw[k] = std::min(tw[k], ms);
         }
     }
     if (sv.tmp) (void)hipFree(sv.tmp);
@@ -569,11 +585,17 @@ pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out) {
         (void)pond_set_tuning(c, &sv.tuning);
         return s;
     }
+    pond_tuning best = sv.tuning;
+    best.kernel = POND_KERNEL_TILED;
+    best.tile = tiles[pick(tt)];
+    best.lds_nodes = 0;
+    best.batch_tile_width = widths[widths.size() > 1 ? pick(tw) : 0];
     s = pond_set_tuning(c, &best);
     if (s != POND_OK) return s;
+    best = c->tuning;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[tune_key(c->p)] = best;
+        g_tune[tune_key(c)] = best;
     }
     if (out) *out = best;
     return POND_OK;

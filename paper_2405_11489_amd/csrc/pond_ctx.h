@@ -75,6 +75,8 @@ struct pond_ctx {
     double prof_prepass_ms, prof_step_ms;
     long long prof_launches;
     pond_batch *batch;  // batch that owns the stepping of this context, or NULL
+    int reach;          // ceil of the largest stencil reach of the initial frame (nodes)
+    bool user_tuned;    // tuning set explicitly: the tuning cache does not override it
 };
 
 namespace pond {
@@ -83,7 +85,8 @@ pond_status check_ctx(const pond_ctx *c, bool need_init);
 pond_status read_counters(pond_ctx *c, DevCounters *out);
 pond_status write_counters(pond_ctx *c, const DevCounters &in);
 
-// Autotuned launch configuration of p's size class, if pond_autotune stored one.
-bool tuning_cache_lookup(const pond_params &p, pond_tuning *out);
+// Autotuned launch configuration of c's class (size and stencil reach), if
+// pond_autotune stored one.
+bool tuning_cache_lookup(const pond_ctx *c, pond_tuning *out);
 
 }  // namespace pond

@@ -83,6 +83,10 @@ hipError_t launch_import(const StepArgs &a, const double *f, const double *g, co
 // (sum rho, sum rho ux, sum rho uy), fixed summation order.
 hipError_t launch_mean_velocity(long long N, const double *rho, const double *ux, const double *uy,
                                 double *scratch, int scratch_len, DevCounters *cnt, hipStream_t s);
+// Largest stencil reach max(|u_x|, |u_y|) + c_out sqrt(T) over the nodes of a
+// frame, into cnt->partial[3].
+hipError_t launch_frame_reach(long long N, const double *ux, const double *uy, const double *T,
+                              double *scratch, int scratch_len, DevCounters *cnt, hipStream_t s);
 // Mass-weighted mean velocity of a stored state (populations + frame).
 template <typename P>
 hipError_t launch_state_mean_velocity(const StepArgs &a, DevState st, double *scratch,

@@ -223,6 +223,36 @@ __global__ void final_sums_kernel(const double *scratch, int nblocks, DevCounter
     cnt->partial[2] = s2;
 }
 
+// per-block maxima of max(|u_x|, |u_y|) + c_out sqrt(T) (the reach of a node's
+// departure stencils, in nodes); non-finite values are skipped
+__global__ __launch_bounds__(kBlock) void reach_partial_kernel(long long N, const double *ux,
+                                                               const double *uy, const double *T,
+                                                               double *scratch) {
+    __shared__ double sh[kBlock];
+    const long long chunk = (N + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = lo + chunk < N ? lo + chunk : N;
+    double m = 0.0;
+    for (long long n = lo + threadIdx.x; n < hi; n += blockDim.x) {
+        const double r = fmax(fabs(ux[n]), fabs(uy[n])) + c1(3) * sqrt(fmax(T[n], 0.0));
+        if (isfinite(r)) m = fmax(m, r);
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scratch[blockIdx.x] = sh[0];
+}
+
+__global__ void reach_final_kernel(const double *scratch, int nblocks, DevCounters *cnt) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double m = 0.0;
+    for (int b = 0; b < nblocks; ++b) m = fmax(m, scratch[b]);
+    cnt->partial[3] = m;
+}
+
 struct FieldLoader {
     const double *rho, *ux, *uy;
     __device__ void operator()(long long n, double &r, double &jx, double &jy) const {
@@ -350,6 +380,15 @@ hipError_t launch_mean_velocity(long long N, const double *rho, const double *ux
     hipLaunchKernelGGL(partial_sums_kernel<FieldLoader>, dim3(kRedBlocks), dim3(kBlock), 0, s, N,
                        FieldLoader{rho, ux, uy}, scratch);
     hipLaunchKernelGGL(final_sums_kernel, dim3(1), dim3(64), 0, s, scratch, kRedBlocks, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_reach(long long N, const double *ux, const double *uy, const double *T,
+                              double *scratch, int scratch_len, DevCounters *cnt, hipStream_t s) {
+    if (scratch_len < kRedBlocks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reach_partial_kernel, dim3(kRedBlocks), dim3(kBlock), 0, s, N, ux, uy, T,
+                       scratch);
+    hipLaunchKernelGGL(reach_final_kernel, dim3(1), dim3(64), 0, s, scratch, kRedBlocks, cnt);
     return hipGetLastError();
 }
 

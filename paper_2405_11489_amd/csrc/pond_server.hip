@@ -86,7 +86,7 @@ pond_status admit(pond_server *s, Request *r) {
     st = pond_init_fields(r->ctx, f, f + N, f + 2 * N, f + 3 * N);
     if (st == POND_OK && s->cfg.autotune_steps > 0) {
         pond_tuning t;
-        if (!tuning_cache_lookup(r->p, &t)) st = pond_autotune(r->ctx, int(s->cfg.autotune_steps), nullptr);
+        if (!tuning_cache_lookup(r->ctx, &t)) st = pond_autotune(r->ctx, int(s->cfg.autotune_steps), nullptr);
     }
     if (st != POND_OK) {
         (void)pond_destroy(r->ctx);
