@@ -11,6 +11,12 @@ re-projection, collision, store).  Inputs are resident in HBM before the timed
 region; W untimed warm-up steps, then exactly K timed steps bracketed by
 synchronisations, timed with HIP events on the context's stream.
 
+Other workloads (``--workload``): ``sod400`` (the 400 x 1 shock tube),
+``quadrants2048`` (the 2048 x 2048 four-quadrant Riemann problem), ``batch``
+(256 mixed instances through pond_batch, against each alone) and ``serve``
+(a Poisson request stream through pond_server, against serial FIFO through
+the plain path).
+
 Prints ONE JSON line on stdout (everything else goes to stderr).
 """
 import argparse
@@ -350,9 +356,11 @@ def main():
     ap.add_argument("--kernel", choices=["tiled", "global"], default="tiled")
     ap.add_argument("--tile", type=int, default=None, help="POND_TILE_* id (default: library's)")
     ap.add_argument("--lds-nodes", type=int, default=None)
-    ap.add_argument("--workload", choices=["modes512", "batch", "serve"], default="modes512",
-                    help="modes512: one 512^2 Mach-2 instance (headline); batch: the mixed "
-                         "256-instance batch; serve: a Poisson request stream through the server")
+    ap.add_argument("--workload", choices=["modes512", "sod400", "quadrants2048", "batch", "serve"],
+                    default="modes512",
+                    help="modes512: one 512^2 Mach-2 instance (headline); sod400: the 400x1 shock "
+                         "tube; quadrants2048: the 2048^2 four-quadrant Riemann problem; batch: the "
+                         "mixed 256-instance batch; serve: a Poisson request stream through the server")
     ap.add_argument("--instances", type=int, default=256, help="batch / serve: instance count")
     ap.add_argument("--max-size", type=int, default=None,
                     help="batch: largest 2-D side (default 1024); serve: largest side (default 1024)")
@@ -385,8 +393,17 @@ def main():
         print(json.dumps(bench_serve(args, pond, workloads)), flush=True)
         return
     prec = pond.PREC_FP32 if args.precision == "fp32" else pond.PREC_FP64
-    w = workloads.fourier_modes(n=512, mach=2.0, angle_deg=30.0, amplitude=1e-3, seed=0,
-                                tau=0.55, prandtl=0.71, gamma=1.4, steps=2000)
+    if args.workload == "sod400":
+        w = workloads.sod_tube(nx=400, nu=2e-3)
+        wname, wconf = "sod_tube_400x1", {"nu": 2e-3, "T_scale": 0.04}
+    elif args.workload == "quadrants2048":
+        w = workloads.riemann_quadrants(n=2048, seed=0)
+        wname, wconf = "riemann_quadrants_2048x2048", {"nu": w.meta["nu"], "seed": 0,
+                                                       "states": w.meta["states"]}
+    else:
+        w = workloads.fourier_modes(n=512, mach=2.0, angle_deg=30.0, amplitude=1e-3, seed=0,
+                                    tau=0.55, prandtl=0.71, gamma=1.4, steps=2000)
+        wname, wconf = "mach2_fourier_modes_512x512", {"mach": 2.0}
     stream = torch.cuda.Stream()
     tuning = {"kernel": pond.KERNEL_TILED if args.kernel == "tiled" else pond.KERNEL_GLOBAL}
     if args.tile is not None:
@@ -470,8 +487,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if prec == pond.PREC_FP32 else "f64", "data": "synthetic",
-        "config": {"workload": "mach2_fourier_modes_512x512", "nx": w.nx, "ny": w.ny,
-                   "mach": 2.0, "tau": w.tau, "prandtl": w.prandtl, "gamma": w.gamma,
+        "config": {"workload": wname, "nx": w.nx, "ny": w.ny, **wconf,
+                   "tau": w.tau, "prandtl": w.prandtl, "gamma": w.gamma,
                    "precision": args.precision, "interp_points": args.interp_points,
                    "parallelism": "single_gpu"},
         "tuning": {"kernel": args.kernel, "tile": tun.tile, "lds_nodes": tun.lds_nodes},

@@ -135,3 +135,41 @@ def test_low_viscosity_mach2_is_unstable():
                 bad = True
                 break
     assert bad
+
+
+def _first_nonphysical(w, steps, prec=FP32, chunk=250):
+    from paper_2405_11489_amd import pond
+    with gpu_solver(w, prec) as sol:
+        done = 0
+        while done < steps:
+            sol.step(min(chunk, steps - done))
+            done += min(chunk, steps - done)
+            try:
+                sol.synchronize()
+            except pond.PondError as e:
+                assert e.status == pond.ERR_NONPHYSICAL
+                return done
+    return None
+
+
+def test_high_mach_stability_needs_tau_above_055():
+    """Recorded finding: on the T = 1 background the step at tau = 0.55 turns
+    unstable from about Mach 2.75 on; tau = 0.6 runs 2000 steps at Mach 3
+    (the advected flows of the batch and serving workloads use tau = 0.6)."""
+    unstable = workloads.fourier_modes(n=128, mach=3.0, amplitude=1e-3, seed=0, tau=0.55)
+    stable = workloads.fourier_modes(n=128, mach=3.0, amplitude=1e-3, seed=0, tau=0.6)
+    assert _first_nonphysical(unstable, 2000) is not None
+    assert _first_nonphysical(stable, 2000) is None
+
+
+def test_riemann_interfaces_with_large_velocity_jumps_fail():
+    """Recorded finding: four-quadrant problems drawn from the full ranges
+    (Mach <= 1.5) go non-physical within a few hundred steps when neighbouring
+    quadrants slide past each other at more than ~1 thermal speed, while the
+    gentle draws (Mach <= 0.8, p >= 0.5, jumps <= 1) run 2000 steps."""
+    harsh = workloads.riemann_quadrants(n=256, seed=1000, nu=2e-3, steps=2000)
+    gentle = workloads.riemann_quadrants(n=256, seed=1000, nu=2e-3, steps=2000,
+                                         p_range=(0.5, 1.5), mach_range=(0.0, 0.8),
+                                         max_velocity_jump=1.0)
+    assert _first_nonphysical(harsh, 2000) is not None
+    assert _first_nonphysical(gentle, 2000) is None
