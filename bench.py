@@ -408,6 +408,7 @@ def main():
     tuning = {"kernel": pond.KERNEL_TILED if args.kernel == "tiled" else pond.KERNEL_GLOBAL}
     if args.tile is not None:
         tuning["tile"] = args.tile
+        tuning["lds_nodes"] = 0  # the tile's default unless given
     if args.lds_nodes is not None:
         tuning["lds_nodes"] = args.lds_nodes
     sol = pond.Solver.from_workload(w, precision=prec, stream=stream.cuda_stream,

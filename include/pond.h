@@ -280,14 +280,18 @@ POND_API pond_status pond_batch_member_tile_width(pond_batch *b, int i, int *wid
  * to single-context use.  NULL-safe. */
 POND_API pond_status pond_batch_destroy(pond_batch *b);
 
-/* Autotuner: time `steps` (>= 1) steps of c with each candidate tile shape
- * of the single-context kernel and each candidate batch tile width (one-member
- * batches), restoring c's state, step count and counters after every
- * candidate; apply the fastest of each to c, store them for c's size class
- * (precision, stencil, boundary conditions, rounded log2 of nx and of ny) in a
- * process-wide cache that pond_create and pond_batch_create consult, and
- * return them in *out (nullable).  Allocates one state buffer's worth of
- * device memory while it runs.  Every candidate computes the same numbers. */
+/* Autotuner: time at least `steps` (>= 1) steps and 2 ms of device time of c
+ * with each candidate tile shape and LDS capacity of the single-context
+ * kernel and each candidate batch tile width (one-member batches), in two
+ * interleaved rounds, restoring c's state, step count and counters after
+ * every candidate.  A candidate replaces the default only when more than 3 %
+ * faster.  Applies the result to c, stores it for c's class (precision,
+ * stencil, boundary conditions, rounded log2 of nx and of ny, and the stencil
+ * reach max(|u_x|, |u_y|) + c_out sqrt(T) of the initial frame, rounded up)
+ * in a process-wide cache that pond_init_fields / pond_import_state (unless
+ * the tuning was set explicitly) and pond_batch_create consult, and returns
+ * it in *out (nullable).  Allocates one state buffer's worth of device memory
+ * while it runs.  Every candidate computes the same numbers. */
 POND_API pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out);
 
 /* Forget every autotuned size class. */

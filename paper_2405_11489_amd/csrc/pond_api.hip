@@ -56,14 +56,9 @@ Layout layout_for(long long N, size_t psize) {
     return L;
 }
 
-int default_lds_nodes_for_threads(int threads, bool dbl) {
-    // The step kernels are register-limited to two waves per SIMD in FP32 and
-    // one in FP64, i.e. 8 or 4 waves per CU; split the 160 KiB of LDS between
-    // the blocks that fit.  A 16 x 16 tile at T = 1, Mach 2 needs a 26 x 26
-    // source region.
-    const int waves_per_block = (threads + 63) / 64;
-    const int waves_per_cu = dbl ? 4 : 8;
-    int blocks_per_cu = waves_per_cu / waves_per_block;
+int lds_nodes_for_blocks(int blocks_per_cu, bool dbl) {
+    // one KiB per block stays free for the kernels' static shared memory and
+    // the allocation granularity
     if (blocks_per_cu < 1) blocks_per_cu = 1;
     const int bytes = 160 * 1024 / blocks_per_cu - 1024;
     return bytes / (dbl ? 160 : 80);
@@ -169,10 +164,12 @@ void fill_args(pond_ctx *c) {
 
 bool fp64(const pond_ctx *c) { return c->p.precision == POND_PREC_FP64; }
 
-int default_lds_nodes(int tile, bool dbl) {
-    int tx, ty;
-    tile_dims(static_cast<TileShape>(tile), tx, ty);
-    return default_lds_nodes_for_threads(tx * ty, dbl);
+// The step kernels are register-limited (two or three waves per SIMD in FP32,
+// one in FP64 with the cubic stencil); the LDS of a CU is split between the
+// blocks that fit by registers.  A 32 x 8 tile at T = 1, Mach 2 needs a
+// 40 x 16 source region.
+int default_lds_nodes(int tile, bool dbl, int np) {
+    return lds_nodes_for_blocks(tiled_blocks_per_cu(dbl, np, static_cast<TileShape>(tile)), dbl);
 }
 
 int halo_for(int tile, int cap, bool single_row) {
@@ -187,8 +184,12 @@ pond_tuning default_tuning(const pond_params &p) {
     if (p.ny < 8)
         t.tile = POND_TILE_64x1;
     else
-        t.tile = p.precision == POND_PREC_FP64 ? POND_TILE_16x8 : POND_TILE_32x8;
-    t.lds_nodes = default_lds_nodes(t.tile, p.precision == POND_PREC_FP64);
+        t.tile = POND_TILE_32x8;
+    t.lds_nodes = default_lds_nodes(t.tile, p.precision == POND_PREC_FP64, p.interp_points);
+    // FP64 moments take twice the LDS: measured at 512^2, Mach 2, one 32 x 8
+    // block per CU holding its whole 40 x 16 source region beats two blocks
+    // that fall back to HBM for part of the taps (527 vs 323 MLUPS)
+    if (p.precision == POND_PREC_FP64 && p.ny >= 8) t.lds_nodes = lds_nodes_for_blocks(1, true);
     t.batch_tile_width = 0;
     return t;
 }
@@ -199,7 +200,7 @@ pond_status apply_tuning(pond_ctx *c, const pond_tuning &t) {
     if (t.tile < POND_TILE_16x16 || t.tile > POND_TILE_64x1)
         return fail(POND_ERR_INVALID_ARG, "unknown tile %d", t.tile);
     pond_tuning u = t;
-    if (u.lds_nodes <= 0) u.lds_nodes = default_lds_nodes(u.tile, fp64(c));
+    if (u.lds_nodes <= 0) u.lds_nodes = default_lds_nodes(u.tile, fp64(c), c->p.interp_points);
     const size_t bytes = size_t(u.lds_nodes) * 20 * c->psize;
     if (bytes > 160 * 1024)
         return fail(POND_ERR_INVALID_ARG, "lds_nodes %d needs %zu bytes of LDS (> 160 KiB)",

@@ -45,7 +45,6 @@ struct BatchMember {
     int parity0;   // current buffer of the member when the batch was built
     int lg;        // tile width 2^lg, height 256 >> lg
     int tiles_x;
-    int halo_cap;
     int tile_off;  // first tile of the member in the flat tile list
     int blk_off;   // first pre-pass block of the member
 };
@@ -87,8 +86,8 @@ __global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
     const int lt = t - mem[i].tile_off;
     const int par = mem[i].parity0 ^ flip;
     tile_step<P, NP>(a, mem[i].buf[par], static_cast<const P *>(mem[i].mom), mem[i].buf[par ^ 1],
-                     mem[i].cnt, reinterpret_cast<P *>(smem_raw), cap, mem[i].halo_cap,
-                     (lt % tiles_x) << lg, (lt / tiles_x) * (kBatchThreads >> lg), Shape256{lg}, red);
+                     mem[i].cnt, reinterpret_cast<P *>(smem_raw), cap, (lt % tiles_x) << lg,
+                     (lt / tiles_x) * (kBatchThreads >> lg), Shape256{lg}, red);
 }
 
 template <typename P, int NP>
@@ -268,11 +267,15 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
         return hip_fail(e, "hipStreamCreate");
     }
 
-    // LDS per block: the register-limited occupancy's share of the CU
-    b->cap = default_lds_nodes_for_threads(kBatchThreads, b->dbl);
+    // LDS per block: the share of a CU of the blocks that fit by registers
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_fn(b->dbl, b->np),
+                                                     kBatchThreads, 0);
+    b->cap = lds_nodes_for_blocks(e == hipSuccess ? per_cu : 1, b->dbl);
     const size_t lds = size_t(b->cap) * kNMom * (b->dbl ? sizeof(double) : sizeof(float));
-    e = hipFuncSetAttribute(batch_step_fn(b->dbl, b->np), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            int(lds));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(batch_step_fn(b->dbl, b->np),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) {
         release(b);
         return hip_fail(e, "batch launch configuration");
@@ -301,7 +304,6 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
         m.parity0 = c->cur;
         m.lg = lg;
         m.tiles_x = tx;
-        m.halo_cap = halo;
         m.tile_off = int(tiles);
         m.blk_off = int(blocks);
         toff[i] = int(tiles);
@@ -561,13 +563,24 @@ pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out) {
     Saved sv;
     s = save_state(c, sv);
     // two interleaved rounds; each candidate keeps its faster measurement
-    std::vector<double> tt(tiles.size(), 1e300), tw(widths.size(), 1e300);
+    // single-path candidates: each tile with the LDS share of the blocks that fit
+    // by registers (lds 0 = default), and with the larger share of one block fewer
+    struct Cand {
+        int tile, lds;
+    };
+    std::vector<Cand> cands;
+    for (int tile : tiles) {
+        cands.push_back({tile, 0});
+        const int blocks = tiled_blocks_per_cu(dbl, c->p.interp_points, static_cast<TileShape>(tile));
+        if (blocks >= 2) cands.push_back({tile, lds_nodes_for_blocks(blocks - 1, dbl)});
+    }
+    std::vector<double> tt(cands.size(), 1e300), tw(widths.size(), 1e300);
     for (int round = 0; round < 2 && s == POND_OK; ++round) {
-        for (size_t k = 0; k < tiles.size() && s == POND_OK; ++k) {
+        for (size_t k = 0; k < cands.size() && s == POND_OK; ++k) {
             pond_tuning t = sv.tuning;
             t.kernel = POND_KERNEL_TILED;
-            t.tile = tiles[k];
-            t.lds_nodes = 0;
+            t.tile = cands[k].tile;
+            t.lds_nodes = cands[k].lds;
             s = pond_set_tuning(c, &t);
             double ms = 0.0;
             if (s == POND_OK) s = time_candidate(c, sv, steps, 0, &ms);
@@ -587,8 +600,8 @@ pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out) {
     }
     pond_tuning best = sv.tuning;
     best.kernel = POND_KERNEL_TILED;
-    best.tile = tiles[pick(tt)];
-    best.lds_nodes = 0;
+    best.tile = cands[pick(tt)].tile;
+    best.lds_nodes = cands[pick(tt)].lds;
     best.batch_tile_width = widths[widths.size() > 1 ? pick(tw) : 0];
     s = pond_set_tuning(c, &best);
     if (s != POND_OK) return s;

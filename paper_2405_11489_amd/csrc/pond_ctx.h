@@ -35,9 +35,9 @@ constexpr int kScratchDoubles = 3 * 256;
 
 Layout layout_for(long long N, size_t psize);
 
-// LDS nodes per block that let the blocks of the register-limited occupancy
-// share the 160 KiB of a CU (threads: block size).
-int default_lds_nodes_for_threads(int threads, bool dbl);
+// LDS nodes per block (20 moments of P each) that let blocks_per_cu blocks
+// share the 160 KiB of a CU.
+int lds_nodes_for_blocks(int blocks_per_cu, bool dbl);
 
 // Largest halo h of a tx x ty tile whose source region fits cap nodes:
 // (tx + 2h)(ty + 2h) <= cap, or tx + 2h <= cap for a single-row grid (whose

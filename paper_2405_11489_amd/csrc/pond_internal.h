@@ -44,7 +44,7 @@ enum class TileShape : int { T16x16 = 0, T32x8 = 1, T16x8 = 2, T8x8 = 3, T256x1 
 struct TileConfig {
     TileShape shape;
     int cap;       // nodes of LDS per block
-    int halo_cap;  // largest symmetric halo h with (TX + 2h)(TY + 2h) <= cap
+    int halo_cap;  // largest symmetric halo h with (TX + 2h)(TY + 2h) <= cap (>= 0: the tile fits)
 };
 
 inline void tile_dims(TileShape s, int &tx, int &ty) {
@@ -58,6 +58,10 @@ inline void tile_dims(TileShape s, int &tx, int &ty) {
     }
     tx = ty = 0;
 }
+
+// Blocks of the tiled step kernel (precision, stencil, shape) that fit one CU
+// by registers and waves alone (no dynamic LDS).
+int tiled_blocks_per_cu(bool dbl, int np, TileShape shape);
 
 template <typename P>
 hipError_t launch_init(const StepArgs &a, const double *rho, const double *ux, const double *uy,

@@ -114,11 +114,11 @@ template <typename P, int NP, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) POND_TILED_ATTR void step_tiled_kernel(StepArgs a, DevState src,
                                                             const P *__restrict__ mom,
                                                             DevState dst, DevCounters *cnt,
-                                                            int cap, int halo_cap, int tiles_x) {
+                                                            int cap, int tiles_x) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int red[16];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step<P, NP>(a, src, mom, dst, cnt, reinterpret_cast<P *>(smem_raw), cap, halo_cap,
+    tile_step<P, NP>(a, src, mom, dst, cnt, reinterpret_cast<P *>(smem_raw), cap,
                      (tile % tiles_x) * TX, (tile / tiles_x) * TY, FixedShape<TX, TY>{}, red);
 }
 
@@ -322,8 +322,21 @@ hipError_t launch_tiled_t(const StepArgs &a, const TileConfig &tc, DevState src,
     }
     const int tiles_x = (a.nx + TX - 1) / TX, tiles_y = (a.ny + TY - 1) / TY;
     hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y), dim3(TX * TY), lds, s, a, src, mom, dst, cnt,
-                       tc.cap, tc.halo_cap, tiles_x);
+                       tc.cap, tiles_x);
     return hipGetLastError();
+}
+
+template <typename P, int NP>
+const void *tiled_kernel_ptr(TileShape shape) {
+    switch (shape) {
+    case TileShape::T16x16: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, 16, 16>);
+    case TileShape::T32x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, 32, 8>);
+    case TileShape::T16x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, 16, 8>);
+    case TileShape::T8x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, 8, 8>);
+    case TileShape::T256x1: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, 256, 1>);
+    case TileShape::T64x1: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, 64, 1>);
+    }
+    return nullptr;
 }
 
 template <typename P, int NP>
@@ -347,6 +360,19 @@ hipError_t launch_step_tiled(const StepArgs &a, const TileConfig &tc, DevState s
                              DevState dst, DevCounters *cnt, hipStream_t s) {
     if (a.interp_points == 3) return launch_tiled_np<P, 3>(a, tc, src, mom, dst, cnt, s);
     return launch_tiled_np<P, 4>(a, tc, src, mom, dst, cnt, s);
+}
+
+int tiled_blocks_per_cu(bool dbl, int np, TileShape shape) {
+    const void *k = dbl ? (np == 3 ? tiled_kernel_ptr<double, 3>(shape) : tiled_kernel_ptr<double, 4>(shape))
+                        : (np == 3 ? tiled_kernel_ptr<float, 3>(shape) : tiled_kernel_ptr<float, 4>(shape));
+    int tx = 0, ty = 0;
+    tile_dims(shape, tx, ty);
+    int n = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, tx * ty, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n < 1 ? 1 : n;
 }
 
 template <typename P>

@@ -6,6 +6,17 @@
 
 #include "pond_step_common.h"
 
+// Taps of a stencil row whose LDS loads are issued together; the row's later
+// taps are loaded only after these are consumed (0: the whole row at once).
+// Fewer loads in flight per lane -> fewer live registers -> more waves per
+// SIMD: FP32 165 VGPRs (3 waves) with groups of 2, FP64 238 (2 waves) with 1.
+#ifndef POND_TAP_GROUP_F32
+#define POND_TAP_GROUP_F32 2
+#endif
+#ifndef POND_TAP_GROUP_F64
+#define POND_TAP_GROUP_F64 1
+#endif
+
 namespace pond {
 
 // Tap source of a tile: the moments of the block's source region (unwrapped
@@ -29,9 +40,11 @@ struct TileTaps {
             const int base = (flat_y ? 0 : by - Y0) * W + (bx - X0);
             // POND_ROW_UNROLL stencil rows per trip: bounds the loads in flight per lane
 #pragma unroll POND_ROW_UNROLL
-            for (int q = 0; q < NP; ++q)
+            for (int q = 0; q < NP; ++q) {
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
+                    constexpr int kGroup = sizeof(P) == 8 ? POND_TAP_GROUP_F64 : POND_TAP_GROUP_F32;
+                    if (kGroup > 0 && p > 0 && p % kGroup == 0) asm volatile("" ::: "memory");
                     const P Wt = wx[p] * wy[q];
                     P M[kNMom];
                     load_moments(lds, cap, base + q * rs + p, M);
@@ -41,6 +54,7 @@ struct TileTaps {
                         Mg[k] += Wt * M[kNM + k];
                     }
                 }
+            }
         } else {
             glob.gather(bx, by, wx, wy, Mf, Mg);
         }
@@ -102,16 +116,48 @@ struct Shape256 {
     __device__ __forceinline__ int ly(int t) const { return t >> lg; }
 };
 
+// Source region of a tile: the union [X0, X1] x [Y0, Y1] of its lanes'
+// predictor stencils.  When that exceeds cap nodes, the parts sticking out of
+// the tile are cut to at most h nodes per side, with the largest h whose
+// region fits (h = 0, the tile itself, always fits); an asymmetric halo (the
+// upwind side of an advected flow) is kept whole when it fits.  A single-row
+// grid stages one row.
+__device__ __forceinline__ void clip_region(int tx0, int ty0, int tx, int ty, int cap, bool flat_y,
+                                            int &X0, int &X1, int &Y0, int &Y1) {
+    if (flat_y) Y0 = Y1 = 0;
+    if (X1 < X0 || Y1 < Y0) return;  // no live lane
+    const int tx1 = tx0 + tx - 1, ty1 = ty0 + ty - 1;
+    auto area = [&](int h) {
+        const long long w = (long long)min(X1, tx1 + h) - max(X0, tx0 - h) + 1;
+        const long long v = flat_y ? 1 : (long long)min(Y1, ty1 + h) - max(Y0, ty0 - h) + 1;
+        return w * v;
+    };
+    int hi = max(max(tx0 - X0, X1 - tx1), flat_y ? 0 : max(ty0 - Y0, Y1 - ty1));
+    if (hi <= 0 || area(hi) <= cap) return;
+    int lo = 0;  // area(lo) <= cap < area(hi)
+    while (hi - lo > 1) {
+        const int mid = lo + (hi - lo) / 2;
+        if (area(mid) <= cap)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    X0 = max(X0, tx0 - lo);
+    X1 = min(X1, tx1 + lo);
+    if (!flat_y) {
+        Y0 = max(Y0, ty0 - lo);
+        Y1 = min(Y1, ty1 + lo);
+    }
+}
+
 // The tile with first node (tx0, ty0): load the time-t frames, bound the
-// source region by the union of the predictor stencils clipped to the tile
-// plus halo_cap (so that it fits cap nodes of LDS; a single-row grid stages
-// one row, so its halo_cap only bounds x), stage the region's
-// moments, then run every lane's node step.  Every thread of the block must
-// call it (it synchronises the block).  red: 4 x 4 ints of shared memory.
+// source region (clip_region), stage the region's moments, then run every
+// lane's node step.  Every thread of the block must call it (it synchronises
+// the block).  red: 4 x 4 ints of shared memory.
 template <typename P, int NP, class Shape>
 __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const P *__restrict__ mom,
-                                          DevState dst, DevCounters *cnt, P *lds, int cap,
-                                          int halo_cap, int tx0, int ty0, Shape sh, int *red) {
+                                          DevState dst, DevCounters *cnt, P *lds, int cap, int tx0,
+                                          int ty0, Shape sh, int *red) {
     const int nthreads = sh.tx() * sh.ty();
     const int x = tx0 + sh.lx(int(threadIdx.x)), y = ty0 + sh.ly(int(threadIdx.x));
     const bool live = x < a.nx && y < a.ny;
@@ -135,11 +181,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const
     int X1 = -block_min(-hx, red + 4);
     int Y0 = block_min(ly, red + 8);
     int Y1 = -block_min(-hy, red + 12);
-    X0 = max(X0, tx0 - halo_cap);
-    X1 = min(X1, tx0 + sh.tx() - 1 + halo_cap);
-    Y0 = max(Y0, ty0 - halo_cap);
-    Y1 = min(Y1, ty0 + sh.ty() - 1 + halo_cap);
-    if (flat_y) Y0 = Y1 = 0;
+    clip_region(tx0, ty0, sh.tx(), sh.ty(), cap, flat_y, X0, X1, Y0, Y1);
     const int W = X1 >= X0 ? X1 - X0 + 1 : 0;
     const int H = Y1 >= Y0 ? Y1 - Y0 + 1 : 0;
 
