@@ -39,12 +39,17 @@ PEAK_HBM_GBS = 8000.0
 
 # Algorithmic flops of the step kernel per node-update, from the method's
 # arithmetic in interpolate-then-transform form (derivation in the design notes):
-#   per predictor-corrector iteration: departure points and cubic weights 112,
-#   interpolation 16 velocities x 16 taps x (1 weight product + 20 moments x FMA)
-#   = 10496, frame transformation 16 velocities x 2 distributions x 65 = 2080;
+#   per predictor-corrector iteration: departure points and weights 112,
+#   interpolation 16 velocities x NP^2 taps x (1 weight product + 20 moments x
+#   FMA) = 10496 for the cubic stencil (NP = 4), 5904 for the quadratic one,
+#   frame transformation 16 velocities x 2 distributions x 65 = 2080;
 #   once per node: moments of the gathered populations 784, re-projection 110,
 #   collision 60, reconstruction 640.
-FLOPS_PER_ITER = 112 + 10496 + 2080
+def flops_per_iter(np_):
+    return 112 + 16 * np_ * np_ * 41 + 2080
+
+
+FLOPS_PER_ITER = flops_per_iter(4)
 FLOPS_PER_NODE = 784 + 110 + 60 + 640
 # double-precision part: conserved sums and frame per iteration, equilibrium once
 FLOPS64_PER_ITER = 140
@@ -455,7 +460,7 @@ def main():
     log(f"time {ms:.1f} ms (host {wall * 1e3:.1f} ms), {mlups:.1f} MLUPS, K {kbar:.3f}, "
         f"kernels: step {step_ms:.4f} ms, prepass {pre_ms:.4f} ms per launch")
 
-    flops = N * (FLOPS_PER_ITER * kbar + FLOPS_PER_NODE)
+    flops = N * (flops_per_iter(args.interp_points) * kbar + FLOPS_PER_NODE)
     kname = f"step_tiled_kernel<{'float' if prec == pond.PREC_FP32 else 'double'},{args.interp_points}," \
             f"{TILE_DIMS[tun.tile]}>" if args.kernel == "tiled" else \
             f"step_kernel<{'float' if prec == pond.PREC_FP32 else 'double'},{args.interp_points}>"

@@ -207,12 +207,19 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
 #pragma unroll
             for (int k = 0; k < kNM; ++k) Mf[k] = Mg[k] = P(0);
+            // velocity i = 4 ia + ib has x-component c(ia) and y-component c(ib):
+            // the x-stencil serves the four velocities of one ia
 #pragma unroll 1
-            for (int i = 0; i < kQ; ++i) {
-                const double cx = c1(i >> 2), cy = c1(i & 3);
-                // departure point x - C_i(lam_bar) dt and its stencil
-                P wx[NP], wy[NP];
+            for (int ia = 0; ia < 4; ++ia) {
+                const double cx = c1(ia);
+                // departure point x - C_i(lam_bar) dt and its stencil, x then y
+                P wx[NP];
                 const int bx = lagrange<NP>(double(x) - (s * cx + lg0), wx);
+#pragma unroll 1
+                for (int ib = 0; ib < 4; ++ib) {
+                const int i = 4 * ia + ib;
+                const double cy = c1(ib);
+                P wy[NP];
                 const int by = lagrange<NP>(double(y) - (s * cy + lg1), wy);
                 P If[kNM], Ig[kNM];
 #pragma unroll
@@ -240,6 +247,7 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                 for (int k = 0; k < kNM; ++k) {
                     Mf[k] += fi * mono[k];
                     Mg[k] += gi * mono[k];
+                }
                 }
             }
             rho = r;

@@ -173,3 +173,36 @@ def test_riemann_interfaces_with_large_velocity_jumps_fail():
                                          max_velocity_jump=1.0)
     assert _first_nonphysical(harsh, 2000) is not None
     assert _first_nonphysical(gentle, 2000) is None
+
+
+@pytest.mark.parametrize("npts", [4, 3])
+def test_stencil_accuracy_shear_decay_and_sod(npts):
+    """The paper's quadratic stencil (3 points) against this build's cubic one
+    (4 points): an advected shear wave (L = 64, U = 0.6, T = 1, tau = 0.6,
+    800 steps) must decay at nu k^2 with nu = (tau - 1/2) T, and the 400 x 1
+    shock tube must match the exact Riemann solution.  The measured errors
+    are reported in the design notes (cubic: 0.46 % and 4.0e-3; quadratic:
+    L1 1.26e-2); the bars are the cubic stencil's closed-form pins (1 % decay,
+    L1 < 1e-2), widened for the quadratic one's extra numerical diffusion."""
+    w = workloads.shear_wave(L=64, ny=4, tau=0.6, U=0.6, A=1e-4, steps=800)
+    k = 2 * math.pi / w.nx
+    amps = []
+    with gpu_solver(w, FP64, interp_points=npts) as sol:
+        for n in range(0, w.steps + 1, 40):
+            m = sol.moments()
+            amps.append(np.abs(np.fft.fft(m["uy"][0])[1]) / w.nx)
+            if n < w.steps:
+                sol.step(40)
+    ts = np.arange(0, w.steps + 1, 40)
+    decay = -np.polyfit(ts, np.log(amps), 1)[0]
+    expected = cf.shear_viscosity(w.tau, 1.0) * k * k
+    rel = abs(decay - expected) / expected
+    sod = workloads.sod_tube(nx=400, nu=2e-3)
+    *_, st, m = gpu_run(sod, FP64, sod.steps, interp_points=npts)
+    x = (np.arange(400) + 0.5) / 400
+    r_ex, _, _ = riemann.sample(sod.meta["left"], sod.meta["right"], sod.gamma, (x - 0.5) / 0.2)
+    l1 = np.abs(m["rho"][0] - r_ex).mean()
+    print(f"interp_points {npts}: shear decay error {rel:.4f}, Sod L1(rho) {l1:.5f}")
+    assert st.nonphysical == 0
+    assert rel < (0.01 if npts == 4 else 0.15), rel
+    assert l1 < (1e-2 if npts == 4 else 2e-2), l1
