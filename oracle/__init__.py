@@ -33,12 +33,17 @@ class Params(ctypes.Structure):
         ("interp_points", ctypes.c_int), ("pc_max_iter", ctypes.c_int),
         ("tau", ctypes.c_double), ("prandtl", ctypes.c_double),
         ("gamma", ctypes.c_double), ("pc_tol", ctypes.c_double),
+        ("split", ctypes.c_int),
     ]
 
 
+TOTAL, INTERNAL = 0, 1  # energy splits (Eqs. total_energy_g, int_energy_g)
+
+
 def params(nx, ny, *, tau, gamma=1.4, prandtl=1.0, bc_x=0, bc_y=0, interp_points=4,
-           pc_tol=1e-13, pc_max_iter=32) -> Params:
-    return Params(nx, ny, bc_x, bc_y, interp_points, pc_max_iter, tau, prandtl, gamma, pc_tol)
+           pc_tol=1e-13, pc_max_iter=32, split=TOTAL) -> Params:
+    return Params(nx, ny, bc_x, bc_y, interp_points, pc_max_iter, tau, prandtl, gamma, pc_tol,
+                  split)
 
 
 def lib():
@@ -55,8 +60,12 @@ def lib():
         L.oracle_lattice_2d.argtypes = [dp, dp, dp]
         L.oracle_transform.argtypes = [dp, dp, dp, dp]
         L.oracle_equilibrium.argtypes = [ctypes.c_double] * 5 + [dp, dp]
+        L.oracle_equilibrium_split.argtypes = [ctypes.c_int] + [ctypes.c_double] * 5 + [dp, dp]
         L.oracle_collide.argtypes = [dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, dp, dp]
+        L.oracle_collide_split.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, dp, dp]
+        L.oracle_internal_source.argtypes = [dp, dp, dp, dp, dp]
         L.oracle_lagrange.argtypes = [ctypes.c_int, ctypes.c_double, ip, dp]
         L.oracle_lagrange.restype = ctypes.c_int
         L.oracle_step.argtypes = [ctypes.POINTER(Params), dp, dp, dp, dp, dp, dp, ip, ip]
@@ -65,11 +74,12 @@ def lib():
         L.oracle_step_nodes.argtypes = [ctypes.POINTER(Params), dp, dp, dp, ctypes.c_long, lp,
                                         dp, dp, dp, ip, ip]
         L.oracle_step_nodes.restype = ctypes.c_int
-        L.oracle_init.argtypes = [ctypes.c_long, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp]
-        L.oracle_init.restype = ctypes.c_int
-        L.oracle_moments.argtypes = [ctypes.c_long, dp, dp, dp, ctypes.c_double,
-                                     dp, dp, dp, dp, dp]
-        if L.oracle_abi_version() != 1:
+        L.oracle_init_split.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp, dp, dp,
+                                        ctypes.c_double, dp, dp, dp]
+        L.oracle_init_split.restype = ctypes.c_int
+        L.oracle_moments_split.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp, dp,
+                                           ctypes.c_double, dp, dp, dp, dp, dp]
+        if L.oracle_abi_version() != 2:
             raise RuntimeError("oracle library ABI mismatch; rebuild oracle/")
         _lib = L
     return _lib
@@ -118,18 +128,28 @@ def transform(pop, lam_src, lam_dst):
     return out
 
 
-def equilibrium(rho, ux, uy, T, gamma):
+def equilibrium(rho, ux, uy, T, gamma, split=TOTAL):
     f = np.zeros(16)
     g = np.zeros(16)
-    lib().oracle_equilibrium(rho, ux, uy, T, gamma, _d(f), _d(g))
+    lib().oracle_equilibrium_split(split, rho, ux, uy, T, gamma, _d(f), _d(g))
     return f, g
 
 
-def collide(ft, gt, lam, tau, prandtl, gamma):
+def collide(ft, gt, lam, tau, prandtl, gamma, split=TOTAL):
     fo, go = np.zeros(16), np.zeros(16)
-    lib().oracle_collide(_d(_f64(ft, (16,))), _d(_f64(gt, (16,))), _d(_f64(lam, (3,))),
-                         tau, prandtl, gamma, _d(fo), _d(go))
+    lib().oracle_collide_split(split, _d(_f64(ft, (16,))), _d(_f64(gt, (16,))),
+                               _d(_f64(lam, (3,))), tau, prandtl, gamma, _d(fo), _d(go))
     return fo, go
+
+
+def internal_source(f, lam, a, grad):
+    """Source of the internal-energy g-equation over one step, per velocity:
+    S_i = -f_i (C_i - u) . (a + C_i . grad u) with grad[alpha][beta] =
+    d_alpha u_beta, for populations f in the frame lam."""
+    S = np.zeros(16)
+    lib().oracle_internal_source(_d(_f64(f, (16,))), _d(_f64(lam, (3,))), _d(_f64(a, (2,))),
+                                 _d(_f64(grad, (2, 2))), _d(S))
+    return S
 
 
 def lagrange(npts, y):
@@ -156,7 +176,8 @@ def init(P: Params, rho, ux, uy, T) -> State:
     N = P.nx * P.ny
     rho, ux, uy, T = (_f64(a, (N,)) for a in (rho, ux, uy, T))
     f, g, lam = np.zeros((N, 16)), np.zeros((N, 16)), np.zeros((N, 3))
-    nbad = lib().oracle_init(N, _d(rho), _d(ux), _d(uy), _d(T), P.gamma, _d(f), _d(g), _d(lam))
+    nbad = lib().oracle_init_split(P.split, N, _d(rho), _d(ux), _d(uy), _d(T), P.gamma, _d(f),
+                                   _d(g), _d(lam))
     if nbad:
         raise ValueError(f"{nbad} nodes with rho <= 0, T <= 0 or non-finite values")
     return State(f, g, lam)
@@ -209,6 +230,6 @@ def moments(P: Params, s: State):
     """dict of rho, ux, uy, T, p, each of shape (ny, nx)."""
     N = P.nx * P.ny
     out = {k: np.zeros(N) for k in ("rho", "ux", "uy", "T", "p")}
-    lib().oracle_moments(N, _d(s.f), _d(s.g), _d(s.lam), P.gamma, _d(out["rho"]),
-                         _d(out["ux"]), _d(out["uy"]), _d(out["T"]), _d(out["p"]))
+    lib().oracle_moments_split(P.split, N, _d(s.f), _d(s.g), _d(s.lam), P.gamma, _d(out["rho"]),
+                               _d(out["ux"]), _d(out["uy"]), _d(out["T"]), _d(out["p"]))
     return {k: v.reshape(P.ny, P.nx) for k, v in out.items()}

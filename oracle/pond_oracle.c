@@ -1,7 +1,7 @@
 /*
  * pond_oracle.c -- plain FP64 CPU oracle of the particles-on-demand (PonD)
  * stream-and-collide step of the double-distribution-function BGK model,
- * total-energy split, D2Q16 lattice.
+ * total-energy split and internal-energy split, D2Q16 lattice.
  *
  * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU
  * baseline leg of the benchmark load this library.  It shares no code, header,
@@ -34,7 +34,13 @@
  *   - Prandtl number != 1: quasi-equilibrium with the Fourier part of the
  *     energy flux relaxed at omega_1 = 1/tau_1, tau_1 = 1/2 + (tau - 1/2)/Pr,
  *     and the viscous-heating part u . P^neq at omega (Sec. II points to the
- *     quasi-equilibrium approach without giving its form).
+ *     quasi-equilibrium approach without giving its form); in the internal-
+ *     energy split g carries no viscous-heating flux, so g relaxes at omega_1;
+ *   - internal-energy split source -f (v - u).(d_t u + v.grad u): added after
+ *     the collision with the re-projected gathered f, u the new frame
+ *     velocity, d_t u the difference between the new and the time-t frame
+ *     velocity of the node, grad u central differences of the time-t frame
+ *     velocities of the four neighbours (wrapped or clamped like the stencil).
  *
  * Units: lattice units, dx = dt = 1, r = 1, T_L = 1 (Table I column rT_L).
  * Layout (oracle only): node n = y*nx + x; populations pop[n*16 + i];
@@ -48,7 +54,7 @@
 #include <omp.h>
 #endif
 
-#define ORACLE_ABI 1
+#define ORACLE_ABI 2
 #define Q1 4
 #define Q 16
 
@@ -61,6 +67,8 @@ typedef struct {
     double prandtl;        /* > 0; 1 = the paper's plain BGK */
     double gamma;          /* adiabatic exponent, c_v = 1/(gamma - 1) */
     double pc_tol;         /* predictor-corrector tolerance */
+    int split;             /* 0 = total energy (Eq. total_energy_g), 1 = internal energy
+                              (Eq. int_energy_g) */
 } oracle_params;
 
 /* status bits per node written by oracle_step */
@@ -184,12 +192,14 @@ void oracle_transform(const double *pop, const double *lam_src, const double *la
 
 /*
  * Local equilibria in the frame (u, T) (Sec. "Discrete velocity solver ...:
- * PonD"): f_i^eq = rho w_i, and the total-energy-split g^eq of Sec. II,
- * g^eq = (U'/rho + v^2/2) f^eq with v -> C_i = sqrt(T) c_i + u and
- * U' = U - rho D T / 2 = rho T (c_v - 1) for D = 2, c_v = 1/(gamma - 1).
+ * PonD"): f_i^eq = rho w_i, and the g^eq of Sec. II with v -> C_i =
+ * sqrt(T) c_i + u and U' = U - rho D T / 2 = rho T (c_v - 1) for D = 2,
+ * c_v = 1/(gamma - 1):
+ *   split 0 (total energy):    g^eq = (U'/rho + v^2/2) f^eq;
+ *   split 1 (internal energy): g^eq = (U'/rho + (v - u)^2/2) f^eq.
  */
-void oracle_equilibrium(double rho, double ux, double uy, double T, double gamma,
-                        double *feq, double *geq)
+void oracle_equilibrium_split(int split, double rho, double ux, double uy, double T,
+                              double gamma, double *feq, double *geq)
 {
     double cx[Q], cy[Q], w[Q];
     oracle_lattice_2d(cx, cy, w);
@@ -197,9 +207,19 @@ void oracle_equilibrium(double rho, double ux, double uy, double T, double gamma
     double sT = sqrt(T);
     for (int i = 0; i < Q; i++) {
         double Cx = sT * cx[i] + ux, Cy = sT * cy[i] + uy;
+        if (split == 1) {
+            Cx -= ux;
+            Cy -= uy;
+        }
         feq[i] = rho * w[i];
         geq[i] = w[i] * (rho * (cv - 1.0) * T + 0.5 * rho * (Cx * Cx + Cy * Cy));
     }
+}
+
+void oracle_equilibrium(double rho, double ux, double uy, double T, double gamma,
+                        double *feq, double *geq)
+{
+    oracle_equilibrium_split(0, rho, ux, uy, T, gamma, feq, geq);
 }
 
 /*
@@ -213,8 +233,8 @@ void oracle_equilibrium(double rho, double ux, double uy, double T, double gamma
  * The Fourier part of the energy flux relaxes at omega_1, the viscous-heating
  * part at omega; the zeroth moment (total energy) is untouched by either.
  */
-void oracle_collide(const double *ft, const double *gt, const double *lam,
-                    double tau, double prandtl, double gamma, double *fo, double *go)
+void oracle_collide_split(int split, const double *ft, const double *gt, const double *lam,
+                          double tau, double prandtl, double gamma, double *fo, double *go)
 {
     double cx[Q], cy[Q], w[Q], feq[Q], geq[Q];
     oracle_lattice_2d(cx, cy, w);
@@ -222,7 +242,7 @@ void oracle_collide(const double *ft, const double *gt, const double *lam,
     for (int i = 0; i < Q; i++)
         rho += ft[i];
     double ux = lam[0], uy = lam[1], T = lam[2];
-    oracle_equilibrium(rho, ux, uy, T, gamma, feq, geq);
+    oracle_equilibrium_split(split, rho, ux, uy, T, gamma, feq, geq);
     double omega = 1.0 / tau;
     double fin[Q], gin[Q];
     memcpy(fin, ft, sizeof fin);
@@ -236,6 +256,12 @@ void oracle_collide(const double *ft, const double *gt, const double *lam,
     }
     double tau1 = 0.5 + (tau - 0.5) / prandtl;
     double omega1 = 1.0 / tau1;
+    if (split == 1) {
+        /* internal energy: the flux of g is the heat flux alone */
+        for (int i = 0; i < Q; i++)
+            go[i] = gin[i] + omega1 * (geq[i] - gin[i]);
+        return;
+    }
     double sT = sqrt(T);
     double P[2][2] = {{0.0}};
     for (int i = 0; i < Q; i++) {
@@ -251,6 +277,34 @@ void oracle_collide(const double *ft, const double *gt, const double *lam,
     for (int i = 0; i < Q; i++) {
         double gqe = geq[i] + w[i] * (cx[i] * dq[0] + cy[i] * dq[1]) / sT;
         go[i] = gin[i] + omega1 * (gqe - gin[i]) + omega * (geq[i] - gqe);
+    }
+}
+
+void oracle_collide(const double *ft, const double *gt, const double *lam,
+                    double tau, double prandtl, double gamma, double *fo, double *go)
+{
+    oracle_collide_split(0, ft, gt, lam, tau, prandtl, gamma, fo, go);
+}
+
+/*
+ * Source of the internal-energy g-equation (Eq. int_g_evolution), one time
+ * step: S_i = -f_i (C_i - u) . (a + C_i . grad u), with C_i = sqrt(T) c_i + u
+ * in the frame lam = (u, T) of the populations f, a = d_t u and
+ * grad[alpha][beta] = d_alpha u_beta.
+ */
+void oracle_internal_source(const double *f, const double *lam, const double a[2],
+                            const double grad[2][2], double *S)
+{
+    double cx[Q], cy[Q], w[Q];
+    oracle_lattice_2d(cx, cy, w);
+    double sT = sqrt(lam[2]);
+    for (int i = 0; i < Q; i++) {
+        double C[2] = {sT * cx[i] + lam[0], sT * cy[i] + lam[1]};
+        double dv[2] = {sT * cx[i], sT * cy[i]};
+        double s = 0.0;
+        for (int b = 0; b < 2; b++)
+            s += dv[b] * (a[b] + C[0] * grad[0][b] + C[1] * grad[1][b]);
+        S[i] = -f[i] * s;
     }
 }
 
@@ -331,11 +385,13 @@ static void gather(const oracle_params *P, const double *f, const double *g, con
 }
 
 /*
- * Conserved moments of (f, g) living in frame lam (Sec. II, density and
- * momentum of f, total energy E = sum g for the total-energy split) and the
- * frame they imply: u = j/rho, T = (E - |j|^2/(2 rho)) / (rho c_v).
+ * Conserved moments of (f, g) living in frame lam (Sec. II): density and
+ * momentum of f, and the frame they imply: u = j/rho and
+ *   total-energy split:    E = sum g,     T = (E - |j|^2/(2 rho)) / (rho c_v);
+ *   internal-energy split: U = sum g,     T = U / (rho c_v)  (E = U + K).
+ * *E receives sum g.
  */
-static void conserved(const double *ft, const double *gt, const double *lam, double cv,
+static void conserved(int split, const double *ft, const double *gt, const double *lam, double cv,
                       double *rho, double *jx, double *jy, double *E, double *lam_new)
 {
     double cx[Q], cy[Q], w[Q];
@@ -351,7 +407,7 @@ static void conserved(const double *ft, const double *gt, const double *lam, dou
     *rho = r; *jx = px; *jy = py; *E = e;
     lam_new[0] = px / r;
     lam_new[1] = py / r;
-    lam_new[2] = (e - (px * px + py * py) / (2.0 * r)) / (r * cv);
+    lam_new[2] = split == 1 ? e / (r * cv) : (e - (px * px + py * py) / (2.0 * r)) / (r * cv);
 }
 
 /*
@@ -361,7 +417,8 @@ static void conserved(const double *ft, const double *gt, const double *lam, dou
  *     stop when max(|u^{k+1} - u^k|_inf / sqrt(T^{k+1}), |T^{k+1} - T^k| / T^{k+1})
  *     <= pc_tol, or after pc_max_iter gathers (node counted non-converged);
  *   re-project (f~, g~) from the last gather frame onto lam* = lam^{k+1};
- *   collide in lam*; write f*, g*, lam* (16, 16 and 3 values).
+ *   collide in lam* (internal-energy split: then add the g source);
+ *   write f*, g*, lam* (16, 16 and 3 values).
  * *iters receives the number of gathers, *status the ORACLE_* bits.
  * Returns 1 if the node is non-physical (rho <= 0, T <= 0 or non-finite; the
  * outputs are then NaN), else 0.
@@ -378,7 +435,7 @@ static int node_step(const oracle_params *P, const double *f, const double *g, c
     for (k = 0; k < P->pc_max_iter; k++) {
         double rho, jx, jy, E;
         gather(P, f, g, lam, x, y, lg, ft, gt);
-        conserved(ft, gt, lg, cv, &rho, &jx, &jy, &E, ln);
+        conserved(P->split, ft, gt, lg, cv, &rho, &jx, &jy, &E, ln);
         used = k + 1;
         if (!(rho > 0.0) || !(ln[2] > 0.0) || !isfinite(ln[0]) || !isfinite(ln[1]) ||
             !isfinite(ln[2]) || !isfinite(E)) {
@@ -404,7 +461,26 @@ static int node_step(const oracle_params *P, const double *f, const double *g, c
     }
     oracle_transform(ft, lg, ln, ft);
     oracle_transform(gt, lg, ln, gt);
-    oracle_collide(ft, gt, ln, P->tau, P->prandtl, P->gamma, fo, go);
+    oracle_collide_split(P->split, ft, gt, ln, P->tau, P->prandtl, P->gamma, fo, go);
+    if (P->split == 1) {
+        /* d_t u: new minus time-t frame velocity of the node; grad u: central
+           differences of the neighbours' time-t frame velocities */
+        const double *l0 = lam + 3 * n;
+        long xm = (long)y * P->nx + node_index(x - 1, P->nx, P->bc_x);
+        long xp = (long)y * P->nx + node_index(x + 1, P->nx, P->bc_x);
+        long ym = (long)node_index(y - 1, P->ny, P->bc_y) * P->nx + x;
+        long yp = (long)node_index(y + 1, P->ny, P->bc_y) * P->nx + x;
+        double a[2] = {ln[0] - l0[0], ln[1] - l0[1]};
+        double grad[2][2];
+        for (int b = 0; b < 2; b++) {
+            grad[0][b] = 0.5 * (lam[3 * xp + b] - lam[3 * xm + b]);
+            grad[1][b] = 0.5 * (lam[3 * yp + b] - lam[3 * ym + b]);
+        }
+        double S[Q];
+        oracle_internal_source(ft, ln, a, grad, S);
+        for (int i = 0; i < Q; i++)
+            go[i] += S[i];
+    }
     lamo[0] = ln[0];
     lamo[1] = ln[1];
     lamo[2] = ln[2];
@@ -441,12 +517,12 @@ int oracle_step_nodes(const oracle_params *P, const double *f, const double *g, 
 
 /*
  * Initial state: equilibrium populations in each node's own frame
- * (f_i = rho w_i, g_i = g_i^eq), frame = (u, T).  Returns the number of
- * rejected nodes (rho <= 0, T <= 0 or non-finite input); nothing is written
- * for those.
+ * (f_i = rho w_i, g_i = g_i^eq of the split), frame = (u, T).  Returns the
+ * number of rejected nodes (rho <= 0, T <= 0 or non-finite input); nothing is
+ * written for those.
  */
-int oracle_init(long N, const double *rho, const double *ux, const double *uy, const double *T,
-                double gamma, double *f, double *g, double *lam)
+int oracle_init_split(int split, long N, const double *rho, const double *ux, const double *uy,
+                      const double *T, double gamma, double *f, double *g, double *lam)
 {
     int nbad = 0;
     for (long n = 0; n < N; n++) {
@@ -455,7 +531,7 @@ int oracle_init(long N, const double *rho, const double *ux, const double *uy, c
             nbad++;
             continue;
         }
-        oracle_equilibrium(rho[n], ux[n], uy[n], T[n], gamma, f + Q * n, g + Q * n);
+        oracle_equilibrium_split(split, rho[n], ux[n], uy[n], T[n], gamma, f + Q * n, g + Q * n);
         lam[3 * n] = ux[n];
         lam[3 * n + 1] = uy[n];
         lam[3 * n + 2] = T[n];
@@ -463,17 +539,23 @@ int oracle_init(long N, const double *rho, const double *ux, const double *uy, c
     return nbad;
 }
 
+int oracle_init(long N, const double *rho, const double *ux, const double *uy, const double *T,
+                double gamma, double *f, double *g, double *lam)
+{
+    return oracle_init_split(0, N, rho, ux, uy, T, gamma, f, g, lam);
+}
+
 /*
  * Macroscopic fields from the stored state (Sec. II): rho = sum f,
- * rho u = sum f C_i, E = sum g, T = (E - rho |u|^2 / 2)/(rho c_v), p = rho T.
+ * rho u = sum f C_i, T from sum g as in conserved(), p = rho T.
  */
-void oracle_moments(long N, const double *f, const double *g, const double *lam, double gamma,
-                    double *rho, double *ux, double *uy, double *T, double *p)
+void oracle_moments_split(int split, long N, const double *f, const double *g, const double *lam,
+                          double gamma, double *rho, double *ux, double *uy, double *T, double *p)
 {
     double cv = 1.0 / (gamma - 1.0);
     for (long n = 0; n < N; n++) {
         double r, jx, jy, E, ln[3];
-        conserved(f + Q * n, g + Q * n, lam + 3 * n, cv, &r, &jx, &jy, &E, ln);
+        conserved(split, f + Q * n, g + Q * n, lam + 3 * n, cv, &r, &jx, &jy, &E, ln);
         rho[n] = r;
         ux[n] = ln[0];
         uy[n] = ln[1];
@@ -481,4 +563,10 @@ void oracle_moments(long N, const double *f, const double *g, const double *lam,
         if (p)
             p[n] = r * ln[2];
     }
+}
+
+void oracle_moments(long N, const double *f, const double *g, const double *lam, double gamma,
+                    double *rho, double *ux, double *uy, double *T, double *p)
+{
+    oracle_moments_split(0, N, f, g, lam, gamma, rho, ux, uy, T, p);
 }
