@@ -1,5 +1,6 @@
 #!/usr/bin/env python3
 """Benchmark of the PonD f+g step (DDF-BGK, total-energy split, D2Q16) on one MI355X.
+(``--split internal``: the internal-energy split with its source term.)
 
 Workload: 512 x 512 periodic grid, uniform background (rho = 1, T = 1) advected
 at Mach 2 (30 degrees), plus 8 seeded random-phase shear / acoustic / entropy
@@ -51,6 +52,9 @@ def flops_per_iter(np_):
 
 FLOPS_PER_ITER = flops_per_iter(4)
 FLOPS_PER_NODE = 784 + 110 + 60 + 640
+# internal-energy split, once per node: velocity gradient and d_t u 10, and per
+# velocity the pre-collision population (10 FMA) and the source term 17
+FLOPS_SOURCE_PER_NODE = 10 + 16 * (20 + 17)
 # double-precision part: conserved sums and frame per iteration, equilibrium once
 FLOPS64_PER_ITER = 140
 FLOPS64_PER_NODE = 60
@@ -101,14 +105,14 @@ def traffic_record(kernel, precision):
     return None
 
 
-def cpu_baseline(w, seconds):
+def cpu_baseline(w, seconds, split=0):
     """The FP64 oracle, unmodified, timed on this host's cores: whole-grid steps
     of the same workload from its initial state, as many as fit in
     ~``seconds`` (at least one); if one whole-grid step would take much
     longer, one step at a random sample of nodes instead."""
     import oracle
     P = oracle.params(w.nx, w.ny, tau=w.tau, gamma=w.gamma, prandtl=w.prandtl, bc_x=w.bc_x,
-                      bc_y=w.bc_y)
+                      bc_y=w.bc_y, split=split)
     s = oracle.init(P, w.rho.ravel(), w.ux.ravel(), w.uy.ravel(), w.T.ravel())
     rng = np.random.default_rng(0)
     pilot = rng.integers(0, w.nodes, 512)
@@ -356,6 +360,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--interp-points", type=int, default=4, choices=[3, 4])
+    ap.add_argument("--pc-tol", type=float, default=0.0,
+                    help="predictor-corrector tolerance (0: the library default)")
+    ap.add_argument("--size", type=int, default=512,
+                    help="modes512 workload: grid edge (other sizes are diagnostics)")
+    ap.add_argument("--split", choices=["total", "internal"], default="total",
+                    help="energy split carried by g (single-instance workloads)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", choices=["tiled", "global"], default="tiled")
@@ -406,9 +416,10 @@ def main():
         wname, wconf = "riemann_quadrants_2048x2048", {"nu": w.meta["nu"], "seed": 0,
                                                        "states": w.meta["states"]}
     else:
-        w = workloads.fourier_modes(n=512, mach=2.0, angle_deg=30.0, amplitude=1e-3, seed=0,
+        n = args.size
+        w = workloads.fourier_modes(n=n, mach=2.0, angle_deg=30.0, amplitude=1e-3, seed=0,
                                     tau=0.55, prandtl=0.71, gamma=1.4, steps=2000)
-        wname, wconf = "mach2_fourier_modes_512x512", {"mach": 2.0}
+        wname, wconf = f"mach2_fourier_modes_{n}x{n}", {"mach": 2.0}
     stream = torch.cuda.Stream()
     tuning = {"kernel": pond.KERNEL_TILED if args.kernel == "tiled" else pond.KERNEL_GLOBAL}
     if args.tile is not None:
@@ -416,11 +427,13 @@ def main():
         tuning["lds_nodes"] = 0  # the tile's default unless given
     if args.lds_nodes is not None:
         tuning["lds_nodes"] = args.lds_nodes
+    split = pond.SPLIT_INTERNAL if args.split == "internal" else pond.SPLIT_TOTAL
     sol = pond.Solver.from_workload(w, precision=prec, stream=stream.cuda_stream,
-                                    interp_points=args.interp_points, tuning=tuning)
+                                    interp_points=args.interp_points, split=split,
+                                    pc_tol=args.pc_tol, tuning=tuning)
     tun = pond.pond_get_tuning(sol.ctx)
-    log(f"workload {w.name} {w.nx}x{w.ny}, {args.precision}, warmup {args.warmup}, "
-        f"steps {args.steps}")
+    log(f"workload {w.name} {w.nx}x{w.ny}, {args.precision}, {args.split} split, "
+        f"warmup {args.warmup}, steps {args.steps}")
     sol.step(args.warmup)
     sol.synchronize()
     st0 = sol.stats()
@@ -460,10 +473,11 @@ def main():
     log(f"time {ms:.1f} ms (host {wall * 1e3:.1f} ms), {mlups:.1f} MLUPS, K {kbar:.3f}, "
         f"kernels: step {step_ms:.4f} ms, prepass {pre_ms:.4f} ms per launch")
 
-    flops = N * (flops_per_iter(args.interp_points) * kbar + FLOPS_PER_NODE)
-    kname = f"step_tiled_kernel<{'float' if prec == pond.PREC_FP32 else 'double'},{args.interp_points}," \
-            f"{TILE_DIMS[tun.tile]}>" if args.kernel == "tiled" else \
-            f"step_kernel<{'float' if prec == pond.PREC_FP32 else 'double'},{args.interp_points}>"
+    flops = N * (flops_per_iter(args.interp_points) * kbar + FLOPS_PER_NODE +
+                 (FLOPS_SOURCE_PER_NODE if split == pond.SPLIT_INTERNAL else 0))
+    ptype = "float" if prec == pond.PREC_FP32 else "double"
+    kname = f"step_tiled_kernel<{ptype},{args.interp_points},{split},{TILE_DIMS[tun.tile]}>" \
+        if args.kernel == "tiled" else f"step_kernel<{ptype},{args.interp_points},{split}>"
     traffic = traffic_record(kname, args.precision)
     if prec == pond.PREC_FP32:
         achieved = flops / (step_ms * 1e-3) / 1e12
@@ -485,7 +499,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
-        cpu = cpu_baseline(w, args.cpu_seconds)
+        cpu = cpu_baseline(w, args.cpu_seconds, split)
         log(f"oracle: {cpu['value']:.4f} MLUPS on {cpu['cores']} threads ({cpu['sample']})")
 
     out = {
@@ -496,10 +510,12 @@ def main():
         "config": {"workload": wname, "nx": w.nx, "ny": w.ny, **wconf,
                    "tau": w.tau, "prandtl": w.prandtl, "gamma": w.gamma,
                    "precision": args.precision, "interp_points": args.interp_points,
+                   "split": args.split,
                    "parallelism": "single_gpu"},
         "tuning": {"kernel": args.kernel, "tile": tun.tile, "lds_nodes": tun.lds_nodes},
         "pc_iterations_mean": kbar,
         "nonconverged_node_steps": st1.nonconverged - st0.nonconverged,
+        "nonphysical_node_steps": st1.nonphysical - st0.nonphysical,
         "kernel_ms": {"step": step_ms, "prepass": pre_ms},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -4,7 +4,8 @@
  *
  * The library advances the double-distribution-function BGK model in its
  * total-energy split (Hosseini, Bhadauria, Karlin, arXiv:2405.11489, Sec. II,
- * Eq. total_energy_g and the first g-equation) on the D2Q16 lattice of Table I,
+ * Eq. total_energy_g and the first g-equation; the internal-energy split of
+ * Eqs. int_energy_g, int_g_evolution on request) on the D2Q16 lattice of Table I,
  * with particle velocities shifted and scaled to each node's frame (u, T)
  * (Sec. "Discrete velocity solver ...: PonD"), semi-Lagrangian streaming with
  * Lagrange interpolation and the frame transformation of Sec. "Frame
@@ -67,9 +68,18 @@ typedef enum {
  * (abscissae +-sqrt(3 -+ sqrt 6), weights (3 +- sqrt 6)/12). */
 enum { POND_LATTICE_D2Q16 = 16 };
 
-/* Energy split: Eqs. Es.  Only the total-energy split (Eq. total_energy_g,
- * g^eq = (U'/rho + v^2/2) f^eq) is implemented; the others return
- * POND_ERR_UNSUPPORTED. */
+/* Energy split: Eqs. Es.
+ *   POND_SPLIT_TOTAL: g carries the total energy (Eq. total_energy_g,
+ *     g^eq = (U'/rho + v^2/2) f^eq) and has no source (the paper's choice).
+ *   POND_SPLIT_INTERNAL: g carries the internal energy (Eq. int_energy_g,
+ *     g^eq = (U'/rho + (v - u)^2/2) f^eq, sum g = rho c_v T) and, after the
+ *     collision, receives the source of Eq. int_g_evolution once per step,
+ *     S_i = -f~_i (C_i - u) . (d_t u + C_i . grad u), with f~ the re-projected
+ *     pre-collision populations, d_t u the new minus the old frame velocity of
+ *     the node and grad u central differences of the neighbours' old frame
+ *     velocities (the boundary rule of bc_x / bc_y picks the neighbours).
+ *     With prandtl != 1, g relaxes at 1/tau_1 (its flux is the heat flux).
+ *   POND_SPLIT_NONTRANS (Eq. nontrans_energy_g) returns POND_ERR_UNSUPPORTED. */
 enum { POND_SPLIT_TOTAL = 0, POND_SPLIT_INTERNAL = 1, POND_SPLIT_NONTRANS = 2 };
 
 /* Arithmetic of the step.  FP64: everything in double.  FP32: populations,
@@ -89,7 +99,7 @@ typedef struct {
     int32_t lattice;       /* POND_LATTICE_D2Q16 */
     int32_t interp_points; /* 4 = cubic Lagrange (default); 3 = quadratic, the paper's
                               "2nd-order" stencil (end of Sec. "Streaming") */
-    int32_t split;         /* POND_SPLIT_TOTAL */
+    int32_t split;         /* POND_SPLIT_TOTAL (default) or POND_SPLIT_INTERNAL */
     int32_t precision;     /* POND_PREC_* */
     int32_t pc_max_iter;   /* predictor-corrector cap; <= 0 selects 32 */
     double tau;            /* relaxation time in lattice units, > 1/2; the discrete
@@ -145,7 +155,8 @@ POND_API pond_status pond_create(const pond_params *p, void *hip_stream, void *d
 /* Initialise every node at equilibrium in its own frame: f_i = rho w_i,
  * g_i = w_i [rho (c_v - 1) T + rho |C_i|^2 / 2] with C_i = sqrt(T) c_i + u
  * (Sec. "Discrete velocity solver ...: PonD" and the total-split g^eq of Sec.
- * II), frame (u, T).  Arrays of nx*ny doubles.  rho <= 0, T <= 0 or a
+ * II; the internal split puts C_i - u = sqrt(T) c_i in place of C_i), frame
+ * (u, T).  Arrays of nx*ny doubles.  rho <= 0, T <= 0 or a
  * non-finite value anywhere gives POND_ERR_INVALID_ARG (the context is then
  * left uninitialised).  Synchronises the stream.  Resets the counters. */
 POND_API pond_status pond_init_fields(pond_ctx *c, const double *rho, const double *ux, const double *uy,
@@ -155,7 +166,8 @@ POND_API pond_status pond_init_fields(pond_ctx *c, const double *rho, const doub
 POND_API pond_status pond_step(pond_ctx *c, int64_t nsteps);
 
 /* Macroscopic fields of the current state (Sec. II): rho = sum f, rho u =
- * sum f C_i, E = sum g, T = (E - rho |u|^2 / 2) / (rho c_v), p = rho T.
+ * sum f C_i, E = sum g, T = (E - rho |u|^2 / 2) / (rho c_v), p = rho T
+ * (internal split: U = sum g, T = U / (rho c_v)).
  * Any output pointer may be NULL to skip it.  Synchronises the stream. */
 POND_API pond_status pond_moments(pond_ctx *c, double *rho, double *ux, double *uy, double *T, double *p);
 

@@ -110,9 +110,9 @@ pond_status validate(const pond_params *p) {
     }
     if (p->interp_points != 3 && p->interp_points != 4)
         return fail(POND_ERR_INVALID_ARG, "interp_points must be 3 or 4");
-    if (p->split != POND_SPLIT_TOTAL) {
-        if (p->split == POND_SPLIT_INTERNAL || p->split == POND_SPLIT_NONTRANS)
-            return fail(POND_ERR_UNSUPPORTED, "only the total-energy split is implemented");
+    if (p->split != POND_SPLIT_TOTAL && p->split != POND_SPLIT_INTERNAL) {
+        if (p->split == POND_SPLIT_NONTRANS)
+            return fail(POND_ERR_UNSUPPORTED, "the non-translational split is not implemented");
         return fail(POND_ERR_INVALID_ARG, "unknown split %d", p->split);
     }
     if (p->precision != POND_PREC_FP64 && p->precision != POND_PREC_FP32)
@@ -158,6 +158,7 @@ void fill_args(pond_ctx *c) {
     const double tau1 = 0.5 + (p.tau - 0.5) / p.prandtl;
     a.omega1 = 1.0 / tau1;
     a.unit_prandtl = p.prandtl == 1.0;
+    a.split = p.split;
     a.cv = 1.0 / (p.gamma - 1.0);
     a.uref_x = a.uref_y = 0.0;
 }
@@ -168,8 +169,9 @@ bool fp64(const pond_ctx *c) { return c->p.precision == POND_PREC_FP64; }
 // one in FP64 with the cubic stencil); the LDS of a CU is split between the
 // blocks that fit by registers.  A 32 x 8 tile at T = 1, Mach 2 needs a
 // 40 x 16 source region.
-int default_lds_nodes(int tile, bool dbl, int np) {
-    return lds_nodes_for_blocks(tiled_blocks_per_cu(dbl, np, static_cast<TileShape>(tile)), dbl);
+int default_lds_nodes(int tile, bool dbl, int np, int split) {
+    return lds_nodes_for_blocks(tiled_blocks_per_cu(dbl, np, split, static_cast<TileShape>(tile)),
+                                dbl);
 }
 
 int halo_for(int tile, int cap, bool single_row) {
@@ -185,7 +187,8 @@ pond_tuning default_tuning(const pond_params &p) {
         t.tile = POND_TILE_64x1;
     else
         t.tile = POND_TILE_32x8;
-    t.lds_nodes = default_lds_nodes(t.tile, p.precision == POND_PREC_FP64, p.interp_points);
+    t.lds_nodes =
+        default_lds_nodes(t.tile, p.precision == POND_PREC_FP64, p.interp_points, p.split);
     // FP64 moments take twice the LDS: measured at 512^2, Mach 2, one 32 x 8
     // block per CU holding its whole 40 x 16 source region beats two blocks
     // that fall back to HBM for part of the taps (527 vs 323 MLUPS)
@@ -200,7 +203,8 @@ pond_status apply_tuning(pond_ctx *c, const pond_tuning &t) {
     if (t.tile < POND_TILE_16x16 || t.tile > POND_TILE_64x1)
         return fail(POND_ERR_INVALID_ARG, "unknown tile %d", t.tile);
     pond_tuning u = t;
-    if (u.lds_nodes <= 0) u.lds_nodes = default_lds_nodes(u.tile, fp64(c), c->p.interp_points);
+    if (u.lds_nodes <= 0)
+        u.lds_nodes = default_lds_nodes(u.tile, fp64(c), c->p.interp_points, c->p.split);
     const size_t bytes = size_t(u.lds_nodes) * 20 * c->psize;
     if (bytes > 160 * 1024)
         return fail(POND_ERR_INVALID_ARG, "lds_nodes %d needs %zu bytes of LDS (> 160 KiB)",

@@ -73,8 +73,9 @@ __global__ __launch_bounds__(kBatchThreads) void batch_moments_kernel(
     node_moments<P>(a, mem[i].buf[mem[i].parity0 ^ flip], static_cast<P *>(mem[i].mom), n);
 }
 
-template <typename P, int NP>
-__global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
+template <typename P, int NP, int S>
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(
+    step_min_waves<P, S>()))) void batch_step_kernel(
     const BatchMember *__restrict__ mem, const int *__restrict__ tile_off, int nmem, int cap,
     int flip) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -85,23 +86,24 @@ __global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
     const int lg = mem[i].lg, tiles_x = mem[i].tiles_x;
     const int lt = t - mem[i].tile_off;
     const int par = mem[i].parity0 ^ flip;
-    tile_step<P, NP>(a, mem[i].buf[par], static_cast<const P *>(mem[i].mom), mem[i].buf[par ^ 1],
+    tile_step<P, NP, S>(a, mem[i].buf[par], static_cast<const P *>(mem[i].mom), mem[i].buf[par ^ 1],
                      mem[i].cnt, reinterpret_cast<P *>(smem_raw), cap, (lt % tiles_x) << lg,
                      (lt / tiles_x) * (kBatchThreads >> lg), Shape256{lg}, red);
 }
 
-template <typename P, int NP>
+template <typename P, int NP, int S>
 const void *step_kernel_ptr() {
-    return reinterpret_cast<const void *>(batch_step_kernel<P, NP>);
+    return reinterpret_cast<const void *>(batch_step_kernel<P, NP, S>);
 }
 
-const void *batch_step_fn(bool dbl, int np) {
-    if (dbl) return np == 3 ? step_kernel_ptr<double, 3>() : step_kernel_ptr<double, 4>();
-    return np == 3 ? step_kernel_ptr<float, 3>() : step_kernel_ptr<float, 4>();
+const void *batch_step_fn(bool dbl, int np, int split) {
+    return with_variant(np, split, [&](auto n, auto sp) {
+        return dbl ? step_kernel_ptr<double, n(), sp()>() : step_kernel_ptr<float, n(), sp()>();
+    });
 }
 
 // ----------------------------------------------------- tuning cache ----
-// Class of an instance: precision, stencil, boundary conditions, the rounded
+// Class of an instance: energy split, precision, stencil, boundary conditions, the rounded
 // log2 of each axis (a single-row grid is its own class) and the stencil
 // reach of its initial frame (the best tile shape depends on the halo).
 using TuneKey = std::tuple<int, int, int, int, int>;
@@ -112,7 +114,8 @@ int log2_class(int n) { return n <= 1 ? -1 : int(std::lround(std::log2(double(n)
 
 TuneKey tune_key(const pond_ctx *c) {
     const pond_params &p = c->p;
-    return TuneKey(p.precision * 16 + p.interp_points, p.bc_x * 2 + p.bc_y, log2_class(p.nx),
+    return TuneKey(p.split * 64 + p.precision * 16 + p.interp_points, p.bc_x * 2 + p.bc_y,
+                   log2_class(p.nx),
                    log2_class(p.ny), std::min(c->reach, 12));
 }
 
@@ -145,7 +148,7 @@ struct pond_batch {
     std::vector<pond_ctx *> members;
     std::vector<int> widths;
     bool dbl;
-    int np;
+    int np, split;
     hipStream_t stream;
     bool own_stream;
     void *dev;  // [members | tile offsets | block offsets]
@@ -178,21 +181,17 @@ hipError_t enqueue_batch_step(pond_batch *b, int flip) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = size_t(b->cap) * kNMom * (b->dbl ? sizeof(double) : sizeof(float));
-    if (b->dbl) {
-        if (b->np == 3)
-            hipLaunchKernelGGL((batch_step_kernel<double, 3>), dim3(b->tiles), dim3(kBatchThreads),
-                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->cap, flip);
+    with_variant(b->np, b->split, [&](auto np, auto sp) {
+        if (b->dbl)
+            hipLaunchKernelGGL((batch_step_kernel<double, np(), sp()>), dim3(b->tiles),
+                               dim3(kBatchThreads), lds, b->stream, b->d_mem, b->d_tile_off, n,
+                               b->cap, flip);
         else
-            hipLaunchKernelGGL((batch_step_kernel<double, 4>), dim3(b->tiles), dim3(kBatchThreads),
-                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->cap, flip);
-    } else {
-        if (b->np == 3)
-            hipLaunchKernelGGL((batch_step_kernel<float, 3>), dim3(b->tiles), dim3(kBatchThreads),
-                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->cap, flip);
-        else
-            hipLaunchKernelGGL((batch_step_kernel<float, 4>), dim3(b->tiles), dim3(kBatchThreads),
-                               lds, b->stream, b->d_mem, b->d_tile_off, n, b->cap, flip);
-    }
+            hipLaunchKernelGGL((batch_step_kernel<float, np(), sp()>), dim3(b->tiles),
+                               dim3(kBatchThreads), lds, b->stream, b->d_mem, b->d_tile_off, n,
+                               b->cap, flip);
+        return 0;
+    });
     return hipGetLastError();
 }
 
@@ -244,9 +243,10 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
         if (!c->initialized) return fail(POND_ERR_STATE, "context %d has no state", i);
         if (c->failed) return fail(POND_ERR_STATE, "context %d is in the error state", i);
         if (c->batch) return fail(POND_ERR_STATE, "context %d already belongs to a batch", i);
-        if (c->p.precision != ctxs[0]->p.precision || c->p.interp_points != ctxs[0]->p.interp_points)
+        if (c->p.precision != ctxs[0]->p.precision ||
+            c->p.interp_points != ctxs[0]->p.interp_points || c->p.split != ctxs[0]->p.split)
             return fail(POND_ERR_INVALID_ARG,
-                        "context %d: members must share precision and interp_points", i);
+                        "context %d: members must share precision, interp_points and split", i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == c) return fail(POND_ERR_INVALID_ARG, "context %d appears twice", i);
     }
@@ -255,6 +255,7 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
     b->members.assign(ctxs, ctxs + n);
     b->dbl = ctxs[0]->p.precision == POND_PREC_FP64;
     b->np = ctxs[0]->p.interp_points;
+    b->split = ctxs[0]->p.split;
     b->own_stream = hip_stream == nullptr;
     hipError_t e = hipSuccess;
     if (b->own_stream)
@@ -269,12 +270,12 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
 
     // LDS per block: the share of a CU of the blocks that fit by registers
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_fn(b->dbl, b->np),
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_fn(b->dbl, b->np, b->split),
                                                      kBatchThreads, 0);
     b->cap = lds_nodes_for_blocks(e == hipSuccess ? per_cu : 1, b->dbl);
     const size_t lds = size_t(b->cap) * kNMom * (b->dbl ? sizeof(double) : sizeof(float));
     if (e == hipSuccess)
-        e = hipFuncSetAttribute(batch_step_fn(b->dbl, b->np),
+        e = hipFuncSetAttribute(batch_step_fn(b->dbl, b->np, b->split),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) {
         release(b);
@@ -571,7 +572,8 @@ pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out) {
     std::vector<Cand> cands;
     for (int tile : tiles) {
         cands.push_back({tile, 0});
-        const int blocks = tiled_blocks_per_cu(dbl, c->p.interp_points, static_cast<TileShape>(tile));
+        const int blocks = tiled_blocks_per_cu(dbl, c->p.interp_points, c->p.split,
+                                               static_cast<TileShape>(tile));
         if (blocks >= 2) cands.push_back({tile, lds_nodes_for_blocks(blocks - 1, dbl)});
     }
     std::vector<double> tt(cands.size(), 1e300), tw(widths.size(), 1e300);

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace pond {
 
 // Device state of one instance.  Population planes: pop[i * N + n] for
@@ -33,6 +35,7 @@ struct StepArgs {
     double omega;        // 1 / tau
     double omega1;       // 1 / tau_1 (Fourier part of the energy flux)
     int unit_prandtl;    // 1: plain BGK for g
+    int split;           // 0: total energy in g; 1: internal energy in g (plus its source)
     double cv;           // 1 / (gamma - 1)
     double uref_x, uref_y;
 };
@@ -59,9 +62,22 @@ inline void tile_dims(TileShape s, int &tx, int &ty) {
     tx = ty = 0;
 }
 
-// Blocks of the tiled step kernel (precision, stencil, shape) that fit one CU
-// by registers and waves alone (no dynamic LDS).
-int tiled_blocks_per_cu(bool dbl, int np, TileShape shape);
+// Blocks of the tiled step kernel (precision, stencil, energy split, shape)
+// that fit one CU by registers and waves alone (no dynamic LDS).
+int tiled_blocks_per_cu(bool dbl, int np, int split, TileShape shape);
+
+// Calls f(np, split) with both as std::integral_constant (np: 3 or 4 stencil
+// points per axis, split: 0 total, 1 internal energy), so kernels can be
+// picked by compile-time variant.
+template <class F>
+inline auto with_variant(int np, int split, F &&f) {
+    using std::integral_constant;
+    if (np == 3)
+        return split == 1 ? f(integral_constant<int, 3>{}, integral_constant<int, 1>{})
+                          : f(integral_constant<int, 3>{}, integral_constant<int, 0>{});
+    return split == 1 ? f(integral_constant<int, 4>{}, integral_constant<int, 1>{})
+                      : f(integral_constant<int, 4>{}, integral_constant<int, 0>{});
+}
 
 template <typename P>
 hipError_t launch_init(const StepArgs &a, const double *rho, const double *ux, const double *uy,

@@ -52,10 +52,12 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs a, const double *
         return;
     }
     const double s = sqrt(t);
+    // total split: g^eq uses the lab velocity C_i; internal split: C_i - u
+    const double ox = a.split ? 0.0 : vx, oy = a.split ? 0.0 : vy;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         const double w = w1(i / 4) * w1(i % 4);
-        const double Cx = s * c1(i / 4) + vx, Cy = s * c1(i % 4) + vy;
+        const double Cx = s * c1(i / 4) + ox, Cy = s * c1(i % 4) + oy;
         plane<P>(st.f, i, a.N)[n] = P(r * w);
         plane<P>(st.g, i, a.N)[n] = P(w * (r * (a.cv - 1.0) * t + 0.5 * r * (Cx * Cx + Cy * Cy)));
     }
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(StepArgs a, DevState st
 // ----------------------------------------------------- step (global taps) ----
 // Reference step kernel: one lane per node in row-major order, taps read
 // straight from the HBM moment planes.
-template <typename P, int NP>
+template <typename P, int NP, int S>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
                                                       const P *__restrict__ mom, DevState dst,
                                                       DevCounters *cnt) {
@@ -94,31 +96,29 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
         l2 = src.T[n];
     }
     const GlobalTaps<P, NP> taps{mom, a.N, a.nx, a.ny, a.bc_x, a.bc_y};
-    node_step<P, NP>(a, taps, x, y, n, live, l0, l1, l2, dst, cnt);
+    node_step<P, NP, S>(a, taps, x, y, n, live, l0, l1, l2, src, dst, cnt);
 }
 
 // ------------------------------------------------------ step (LDS tiles) ----
 
 // Minimum waves per SIMD requested from the register allocator for the tiled
-// kernel (compile-time tuning; 0 leaves the choice to the compiler).
+// kernel (compile-time tuning; 0 keeps the defaults of step_min_waves).
 #ifndef POND_TILED_WAVES_PER_EU
 #define POND_TILED_WAVES_PER_EU 0
 #endif
-#if POND_TILED_WAVES_PER_EU > 0
-#define POND_TILED_ATTR __attribute__((amdgpu_waves_per_eu(POND_TILED_WAVES_PER_EU)))
-#else
-#define POND_TILED_ATTR
-#endif
+#define POND_TILED_ATTR(P, S)                                                            \
+    __attribute__((amdgpu_waves_per_eu(POND_TILED_WAVES_PER_EU > 0 ? POND_TILED_WAVES_PER_EU \
+                                                                   : step_min_waves<P, S>())))
 
-template <typename P, int NP, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) POND_TILED_ATTR void step_tiled_kernel(StepArgs a, DevState src,
+template <typename P, int NP, int S, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) POND_TILED_ATTR(P, S) void step_tiled_kernel(StepArgs a, DevState src,
                                                             const P *__restrict__ mom,
                                                             DevState dst, DevCounters *cnt,
                                                             int cap, int tiles_x) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int red[16];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step<P, NP>(a, src, mom, dst, cnt, reinterpret_cast<P *>(smem_raw), cap,
+    tile_step<P, NP, S>(a, src, mom, dst, cnt, reinterpret_cast<P *>(smem_raw), cap,
                      (tile % tiles_x) * TX, (tile / tiles_x) * TY, FixedShape<TX, TY>{}, red);
 }
 
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void macro_kernel(StepArgs a, DevState st, 
         jy += fi * (s * c1(i % 4) + vy);
         E += double(plane<P>(st.g, i, a.N)[n]);
     }
-    const double t = (E - (jx * jx + jy * jy) / (2.0 * r)) / (r * a.cv);
+    const double t = (a.split ? E : E - (jx * jx + jy * jy) / (2.0 * r)) / (r * a.cv);
     if (rho) rho[n] = r;
     if (ux) ux[n] = jx / r;
     if (uy) uy[n] = jy / r;
@@ -299,21 +299,19 @@ hipError_t launch_moments_prepass(const StepArgs &a, DevState st, P *mom, hipStr
 template <typename P>
 hipError_t launch_step(const StepArgs &a, DevState src, const P *mom, DevState dst,
                        DevCounters *cnt, hipStream_t s) {
-    if (a.interp_points == 3)
-        hipLaunchKernelGGL((step_kernel<P, 3>), dim3(grid_for(a.N)), dim3(kBlock), 0, s, a, src,
-                           mom, dst, cnt);
-    else
-        hipLaunchKernelGGL((step_kernel<P, 4>), dim3(grid_for(a.N)), dim3(kBlock), 0, s, a, src,
-                           mom, dst, cnt);
-    return hipGetLastError();
+    return with_variant(a.interp_points, a.split, [&](auto np, auto sp) {
+        hipLaunchKernelGGL((step_kernel<P, np(), sp()>), dim3(grid_for(a.N)), dim3(kBlock), 0, s, a,
+                           src, mom, dst, cnt);
+        return hipGetLastError();
+    });
 }
 
 namespace {
 
-template <typename P, int NP, int TX, int TY>
+template <typename P, int NP, int S, int TX, int TY>
 hipError_t launch_tiled_t(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
                           DevState dst, DevCounters *cnt, hipStream_t s) {
-    auto kern = step_tiled_kernel<P, NP, TX, TY>;
+    auto kern = step_tiled_kernel<P, NP, S, TX, TY>;
     const size_t lds = size_t(tc.cap) * kNMom * sizeof(P);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -326,29 +324,29 @@ hipError_t launch_tiled_t(const StepArgs &a, const TileConfig &tc, DevState src,
     return hipGetLastError();
 }
 
-template <typename P, int NP>
+template <typename P, int NP, int S>
 const void *tiled_kernel_ptr(TileShape shape) {
     switch (shape) {
-    case TileShape::T16x16: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, 16, 16>);
-    case TileShape::T32x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, 32, 8>);
-    case TileShape::T16x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, 16, 8>);
-    case TileShape::T8x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, 8, 8>);
-    case TileShape::T256x1: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, 256, 1>);
-    case TileShape::T64x1: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, 64, 1>);
+    case TileShape::T16x16: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, 16, 16>);
+    case TileShape::T32x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, 32, 8>);
+    case TileShape::T16x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, 16, 8>);
+    case TileShape::T8x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, 8, 8>);
+    case TileShape::T256x1: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, 256, 1>);
+    case TileShape::T64x1: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, 64, 1>);
     }
     return nullptr;
 }
 
-template <typename P, int NP>
-hipError_t launch_tiled_np(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
-                           DevState dst, DevCounters *cnt, hipStream_t s) {
+template <typename P, int NP, int S>
+hipError_t launch_tiled_v(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
+                          DevState dst, DevCounters *cnt, hipStream_t s) {
     switch (tc.shape) {
-    case TileShape::T16x16: return launch_tiled_t<P, NP, 16, 16>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T32x8: return launch_tiled_t<P, NP, 32, 8>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T16x8: return launch_tiled_t<P, NP, 16, 8>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T8x8: return launch_tiled_t<P, NP, 8, 8>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T256x1: return launch_tiled_t<P, NP, 256, 1>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T64x1: return launch_tiled_t<P, NP, 64, 1>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T16x16: return launch_tiled_t<P, NP, S, 16, 16>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T32x8: return launch_tiled_t<P, NP, S, 32, 8>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T16x8: return launch_tiled_t<P, NP, S, 16, 8>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T8x8: return launch_tiled_t<P, NP, S, 8, 8>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T256x1: return launch_tiled_t<P, NP, S, 256, 1>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T64x1: return launch_tiled_t<P, NP, S, 64, 1>(a, tc, src, mom, dst, cnt, s);
     }
     return hipErrorInvalidValue;
 }
@@ -358,13 +356,16 @@ hipError_t launch_tiled_np(const StepArgs &a, const TileConfig &tc, DevState src
 template <typename P>
 hipError_t launch_step_tiled(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
                              DevState dst, DevCounters *cnt, hipStream_t s) {
-    if (a.interp_points == 3) return launch_tiled_np<P, 3>(a, tc, src, mom, dst, cnt, s);
-    return launch_tiled_np<P, 4>(a, tc, src, mom, dst, cnt, s);
+    return with_variant(a.interp_points, a.split, [&](auto np, auto sp) {
+        return launch_tiled_v<P, np(), sp()>(a, tc, src, mom, dst, cnt, s);
+    });
 }
 
-int tiled_blocks_per_cu(bool dbl, int np, TileShape shape) {
-    const void *k = dbl ? (np == 3 ? tiled_kernel_ptr<double, 3>(shape) : tiled_kernel_ptr<double, 4>(shape))
-                        : (np == 3 ? tiled_kernel_ptr<float, 3>(shape) : tiled_kernel_ptr<float, 4>(shape));
+int tiled_blocks_per_cu(bool dbl, int np, int split, TileShape shape) {
+    const void *k = with_variant(np, split, [&](auto n, auto sp) {
+        return dbl ? tiled_kernel_ptr<double, n(), sp()>(shape)
+                   : tiled_kernel_ptr<float, n(), sp()>(shape);
+    });
     int tx = 0, ty = 0;
     tile_dims(shape, tx, ty);
     int n = 0;

@@ -178,18 +178,20 @@ __device__ __forceinline__ void monomials(P Vx, P Vy, P mono[kNM]) {
 }
 
 // The whole step of one destination node (x, y) = node n whose time-t frame
-// is (l0, l1, l2).  Lanes with live == false take part in the wave-level
-// predictor-corrector exit and the counter reduction only.
+// is (l0, l1, l2), for the energy split S (0: total energy, 1: internal
+// energy); src is the time-t state (its frames feed the velocity gradient of
+// the internal-energy split).  Lanes with live == false take part
+// in the wave-level predictor-corrector exit and the counter reduction only.
 //
 // Per predictor-corrector gather, for each velocity i: departure point and
 // Lagrange weights, interpolation of the 20 moments, frame transformation of
 // the interpolated moments into the iterate frame (population i of f and g);
 // the FP64 sums rho, j, E and the lab moments of the gathered populations are
 // accumulated on the fly, so no population array is kept.
-template <typename P, int NP, class Taps>
+template <typename P, int NP, int S, class Taps>
 __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, int x, int y,
                                           long long n, bool live, double l0, double l1, double l2,
-                                          DevState dst, DevCounters *cnt) {
+                                          const DevState &src, DevState dst, DevCounters *cnt) {
     const VelocityTablesP<P> &tab = vtab<P>();
     double lg0 = l0, lg1 = l1, lg2 = l2;     // frame of the current gather
     double ln0 = lg0, ln1 = lg1, ln2 = lg2;  // frame of the gathered moments
@@ -253,7 +255,11 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             rho = r;
             ln0 = jx / r;
             ln1 = jy / r;
-            ln2 = (E - (jx * jx + jy * jy) / (2.0 * r)) / (r * a.cv);
+            // total split: sum g = E = rho c_v T + |j|^2 / (2 rho); internal: sum g = rho c_v T
+            if constexpr (S == 1)
+                ln2 = E / (r * a.cv);
+            else
+                ln2 = (E - (jx * jx + jy * jy) / (2.0 * r)) / (r * a.cv);
             used = it + 1;
             if (!(r > 0.0) || !(ln2 > 0.0) || !isfinite(ln0) || !isfinite(ln1) || !isfinite(ln2) ||
                 !isfinite(E)) {
@@ -288,20 +294,29 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
 
         // BGK collision in lam*, on the Grad coefficients.
         // f: f^eq = rho w_i has only a0; every higher coefficient decays by (1 - omega).
-        // g: g^eq = w_i [rho (c_v - 1) T + rho |C_i|^2 / 2] has
-        //    a0 = rho c_v T + rho |u|^2 / 2, a1 = rho sqrt(T) u, a2 = rho T I, a3 = 0.
+        // g, total split: g^eq = w_i [rho (c_v - 1) T + rho |C_i|^2 / 2] has
+        //    a0 = rho c_v T + rho |u|^2 / 2, a1 = rho sqrt(T) u, a2 = rho T I, a3 = 0;
+        // g, internal split: C_i - u in place of C_i, so a0 = rho c_v T, a1 = 0.
         const double om = a.omega;
         double geq[kNM];
-        geq[0] = rho * (a.cv - 1.0) * ln2 + 0.5 * rho * (2.0 * ln2 + ln0 * ln0 + ln1 * ln1);
-        geq[1] = rho * sT * ln0;
-        geq[2] = rho * sT * ln1;
+        if constexpr (S == 1) {
+            geq[0] = rho * a.cv * ln2;
+            geq[1] = geq[2] = 0.0;
+        } else {
+            geq[0] = rho * (a.cv - 1.0) * ln2 + 0.5 * rho * (2.0 * ln2 + ln0 * ln0 + ln1 * ln1);
+            geq[1] = rho * sT * ln0;
+            geq[2] = rho * sT * ln1;
+        }
         geq[3] = rho * ln2;
         geq[4] = 0.0;
         geq[5] = rho * ln2;
         geq[6] = geq[7] = geq[8] = geq[9] = 0.0;
-        if (a.unit_prandtl) {
+        if (S == 1 || a.unit_prandtl) {
+            // internal split: the flux of g is the heat flux alone, relaxed at omega_1
+            // (omega at Pr = 1)
+            const double og = a.unit_prandtl ? om : a.omega1;
 #pragma unroll
-            for (int k = 0; k < kNM; ++k) ag[k] = ag[k] + P(om) * (P(geq[k]) - ag[k]);
+            for (int k = 0; k < kNM; ++k) ag[k] = ag[k] + P(og) * (P(geq[k]) - ag[k]);
         } else {
             // quasi-equilibrium: energy flux of g^eq plus the viscous heating u . P^neq,
             // P^neq = T a2(f) + sqrt(T) (u a1(f) + a1(f) u) in lam*.
@@ -321,11 +336,33 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             for (int k = 0; k < kNM; ++k)
                 ag[k] = ag[k] + P(om1) * (P(gqe[k]) - ag[k]) + P(om) * (P(geq[k]) - P(gqe[k]));
         }
+        // internal split: source of the g-equation, S_i = -f~_i (C_i - u) . (a + C_i . grad u)
+        // with f~ the re-projected pre-collision populations, a = d_t u = u* - u(t) and
+        // grad[al][be] = d_al u_be from central differences of the time-t frames
+        P afp[kNM];
+        P ax = P(0), ay = P(0), gxx = P(0), gxy = P(0), gyx = P(0), gyy = P(0);
+        if constexpr (S == 1) {
+#pragma unroll
+            for (int k = 0; k < kNM; ++k) afp[k] = af[k];
+            const long long row = (long long)y * a.nx;
+            const long long xm = row + wrap_index(x - 1, a.nx, a.bc_x);
+            const long long xp = row + wrap_index(x + 1, a.nx, a.bc_x);
+            const long long ym = (long long)wrap_index(y - 1, a.ny, a.bc_y) * a.nx + x;
+            const long long yp = (long long)wrap_index(y + 1, a.ny, a.bc_y) * a.nx + x;
+            // the time-t velocity is read again rather than kept live across the loop
+            ax = P(ln0 - src.ux[n]);
+            ay = P(ln1 - src.uy[n]);
+            gxx = P(0.5 * (src.ux[xp] - src.ux[xm]));
+            gxy = P(0.5 * (src.uy[xp] - src.uy[xm]));
+            gyx = P(0.5 * (src.ux[yp] - src.ux[ym]));
+            gyy = P(0.5 * (src.uy[yp] - src.uy[ym]));
+        }
         const P decay = P(1.0 - om);
 #pragma unroll
         for (int k = 1; k < kNM; ++k) af[k] *= decay;
 
         // reconstruct and store the post-collision populations
+        const P sTP = P(sT), u0 = P(ln0), u1 = P(ln1);
 #pragma unroll 4
         for (int i = 0; i < kQ; ++i) {
             P fv = P(0), gv = P(0);
@@ -333,6 +370,14 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             for (int k = 0; k < kNM; ++k) {
                 fv += tab.herm[i][k] * af[k];
                 gv += tab.herm[i][k] * ag[k];
+            }
+            if constexpr (S == 1) {
+                P ft = P(0);
+#pragma unroll
+                for (int k = 0; k < kNM; ++k) ft += tab.herm[i][k] * afp[k];
+                const P ex = sTP * P(c1(i / 4)), ey = sTP * P(c1(i % 4));
+                const P Cx = ex + u0, Cy = ey + u1;
+                gv -= ft * (ex * (ax + Cx * gxx + Cy * gyx) + ey * (ay + Cx * gxy + Cy * gyy));
             }
             if (bad) fv = gv = P(NAN);
             pop_plane<P>(dst.f, i, a.N)[n] = fv;

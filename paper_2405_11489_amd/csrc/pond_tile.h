@@ -91,6 +91,15 @@ __device__ __forceinline__ void stencil_extent(int x, double u, double s, int &l
     }
 }
 
+// Minimum waves per SIMD asked of the register allocator for the step kernels
+// (168 VGPRs allow three).  FP32 with the internal-energy split needs the
+// request: its source term would otherwise tip the allocation over to two
+// waves; the FP32 total split reaches three unforced, FP64 holds two.
+template <typename P, int S>
+constexpr int step_min_waves() {
+    return (sizeof(P) == 4 && S == 1) ? 3 : 1;
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
 // give each XCD a contiguous range of tiles so that neighbouring tiles, which
 // share halo moments, share that XCD's L2.
@@ -152,9 +161,9 @@ __device__ __forceinline__ void clip_region(int tx0, int ty0, int tx, int ty, in
 
 // The tile with first node (tx0, ty0): load the time-t frames, bound the
 // source region (clip_region), stage the region's moments, then run every
-// lane's node step.  Every thread of the block must call it (it synchronises
-// the block).  red: 4 x 4 ints of shared memory.
-template <typename P, int NP, class Shape>
+// lane's node step (energy split S).  Every thread of the block must call it
+// (it synchronises the block).  red: 4 x 4 ints of shared memory.
+template <typename P, int NP, int S, class Shape>
 __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const P *__restrict__ mom,
                                           DevState dst, DevCounters *cnt, P *lds, int cap, int tx0,
                                           int ty0, Shape sh, int *red) {
@@ -196,7 +205,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const
 
     const TileTaps<P, NP> taps{lds, cap, X0, Y0, X1, Y1, W, flat_y,
                                GlobalTaps<P, NP>{mom, a.N, a.nx, a.ny, a.bc_x, a.bc_y}};
-    node_step<P, NP>(a, taps, x, y, n, live, l0, l1, l2, dst, cnt);
+    node_step<P, NP, S>(a, taps, x, y, n, live, l0, l1, l2, src, dst, cnt);
 }
 
 // Moments up to order three of f and g of node n (Eq. genericMomentUptoO3),

@@ -388,11 +388,11 @@ class Solver:
 
     def __init__(self, nx, ny, *, tau, gamma=1.4, prandtl=1.0, bc_x=BC_PERIODIC,
                  bc_y=BC_PERIODIC, precision=PREC_FP32, interp_points=4, pc_tol=0.0,
-                 pc_max_iter=32, stream=None, tuning=None):
+                 pc_max_iter=32, split=SPLIT_TOTAL, stream=None, tuning=None):
         self.params = pond_params_default(nx=nx, ny=ny, tau=tau, gamma=gamma, prandtl=prandtl,
                                           bc_x=bc_x, bc_y=bc_y, precision=precision,
                                           interp_points=interp_points, pc_tol=pc_tol,
-                                          pc_max_iter=pc_max_iter)
+                                          pc_max_iter=pc_max_iter, split=split)
         self.nx, self.ny = nx, ny
         self.ctx = pond_create(self.params, stream)
         if tuning:

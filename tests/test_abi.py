@@ -62,7 +62,7 @@ def test_state_bytes(pond):
     ("nx", 0, 1), ("ny", -3, 1), ("tau", 0.5, 1), ("tau", float("nan"), 1),
     ("prandtl", 0.0, 1), ("gamma", 1.0, 1), ("gamma", 2.5, 1), ("bc_x", 2, 1),
     ("interp_points", 5, 1), ("precision", 7, 1), ("lattice", 25, 2), ("lattice", 7, 1),
-    ("split", 1, 2), ("split", 2, 2), ("split", 9, 1), ("struct_size", 64, 1),
+    ("split", 2, 2), ("split", 9, 1), ("struct_size", 64, 1),
 ])
 def test_invalid_params_rejected_before_device(pond, field, value, status):
     p = pond.pond_params_default(nx=8, ny=8)
@@ -72,6 +72,13 @@ def test_invalid_params_rejected_before_device(pond, field, value, status):
         pond.pond_create(p)
     assert ei.value.status == status
     assert pond.pond_last_error()
+
+
+def test_internal_split_accepted_with_the_same_state_size(pond):
+    p = pond.pond_params_default(nx=64, ny=32)
+    b0 = pond.pond_state_bytes(p)
+    p.split = pond.SPLIT_INTERNAL
+    assert pond.pond_state_bytes(p) == b0 > 0
 
 
 def test_caller_memory_too_small_rejected(pond):
