@@ -112,8 +112,11 @@ typedef struct {
     double gamma;          /* adiabatic exponent, 1 < gamma <= 2 (Eq. spec_heat,
                               c_v = 1/(gamma - 1) >= D/2 keeps U' >= 0) */
     double pc_tol;         /* predictor-corrector tolerance on
-                              max(|du|_inf / sqrt(T), |dT| / T); <= 0 selects 1e-13
-                              (FP64) or 1e-6 (FP32) */
+                              max(|du|_inf / sqrt(T), |dT| / T_E); <= 0 selects 1e-13
+                              (FP64) or 1e-6 (FP32).  T_E = T in FP64; in FP32
+                              T_E = E / (rho c_v), the scale of the energy T is
+                              recovered from (T + |u|^2 / (2 c_v) in the total split,
+                              T in the internal split) */
 } pond_params;
 
 /* Per-context counters since the last pond_init_fields / pond_import_state. */

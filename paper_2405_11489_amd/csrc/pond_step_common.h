@@ -267,7 +267,13 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                 done = true;
             } else {
                 const double du = fmax(fabs(ln0 - lg0), fabs(ln1 - lg1)) / sqrt(ln2);
-                const double dT = fabs(ln2 - lg2) / ln2;
+                // FP64: the change of T relative to T.  FP32: relative to the scale of
+                // the energy T is recovered from, E / (rho c_v) (T itself in the internal
+                // split, T + |u|^2 / (2 c_v) in the total split): single-precision
+                // populations resolve E, and so T, only to a fraction of that scale
+                double Tscale = ln2;
+                if constexpr (sizeof(P) == 4) Tscale = E / (r * a.cv);
+                const double dT = fabs(ln2 - lg2) / Tscale;
                 if (fmax(du, dT) <= a.pc_tol) {
                     conv = true;
                     done = true;

@@ -284,3 +284,24 @@ def test_quasi_1d_tiled_matches_oracle():
     f, g, fr, _, _, _ = gpu_run(w, FP64, w.steps)
     _, s, _ = oracle_run(w, w.steps)
     assert max(plane_errors(f, g, fr, s)) <= 1e-12
+
+
+def test_fp32_convergence_test_stops_at_the_energy_resolution():
+    """The total split recovers T from E - |j|^2 / (2 rho); FP32 populations
+    resolve that only to a fraction of E / (rho c_v), which is 2.1 T at Mach 2.
+    The FP32 test measures the change of T on that scale, so no node spends a
+    third gather chasing rounding noise: the 512^2 Mach-2 workload converges
+    in two gathers per node (at most), and its fields stay within 1e-5 of the
+    FP64 path's."""
+    w = modes(512, mach=2.0, amp=1e-3, seed=0, tau=0.55)
+    with gpu_solver(w, FP32) as s:
+        s.step(30)
+        st = s.stats()
+        m32 = s.moments()
+    # (a node whose frame does not move converges after one gather)
+    assert 1.999 * st.node_updates <= st.pc_iterations <= 2 * st.node_updates
+    with gpu_solver(w, FP64) as s:
+        s.step(30)
+        m64 = s.moments()
+    errs = field_errors(m32, m64)
+    assert max(errs.values()) <= 1e-5, errs
