@@ -6,8 +6,9 @@ binding) never imports or calls it, and it shares no code with them.
 
 The arithmetic lives in ``pond_oracle.c`` (plain C99, FP64); this module only
 marshals numpy arrays through ctypes.  State layout (oracle only): node
-``n = y*nx + x``; ``f[n, i]``, ``g[n, i]`` for velocity ``i = 4a + b`` with
-``c_i = (c_a, c_b)``; frame ``lam[n] = (u_x, u_y, T)``.
+``n = y*nx + x``; ``f[n, i]``, ``g[n, i]`` for velocity ``i = q1*a + b`` with
+``c_i = (c_a, c_b)`` (q1 = 4 on D2Q16, 5 on D2Q25); frame
+``lam[n] = (u_x, u_y, T)``.
 """
 from __future__ import annotations
 
@@ -33,17 +34,28 @@ class Params(ctypes.Structure):
         ("interp_points", ctypes.c_int), ("pc_max_iter", ctypes.c_int),
         ("tau", ctypes.c_double), ("prandtl", ctypes.c_double),
         ("gamma", ctypes.c_double), ("pc_tol", ctypes.c_double),
-        ("split", ctypes.c_int),
+        ("split", ctypes.c_int), ("lattice", ctypes.c_int),
     ]
 
 
-TOTAL, INTERNAL = 0, 1  # energy splits (Eqs. total_energy_g, int_energy_g)
+# energy splits (Eqs. total_energy_g, int_energy_g, nt_energy_g)
+TOTAL, INTERNAL, NONTRANS = 0, 1, 2
 
 
 def params(nx, ny, *, tau, gamma=1.4, prandtl=1.0, bc_x=0, bc_y=0, interp_points=4,
-           pc_tol=1e-13, pc_max_iter=32, split=TOTAL) -> Params:
+           pc_tol=1e-13, pc_max_iter=32, split=TOTAL, lattice=16) -> Params:
+    if lattice not in (16, 25):
+        raise ValueError("lattice must be 16 (D2Q16) or 25 (D2Q25)")
+    if split == NONTRANS and prandtl != 1.0:
+        raise ValueError("the non-translational split is built with Pr = 1 only")
     return Params(nx, ny, bc_x, bc_y, interp_points, pc_max_iter, tau, prandtl, gamma, pc_tol,
-                  split)
+                  split, lattice)
+
+
+def _q1(q):
+    if q not in (16, 25):
+        raise ValueError("16 or 25 populations expected")
+    return 4 if q == 16 else 5
 
 
 def lib():
@@ -59,6 +71,23 @@ def lib():
         L.oracle_lattice_1d.argtypes = [dp, dp]
         L.oracle_lattice_2d.argtypes = [dp, dp, dp]
         L.oracle_transform.argtypes = [dp, dp, dp, dp]
+        L.oracle_lattice_1d_q.argtypes = [ctypes.c_int, dp, dp]
+        L.oracle_lattice_1d_q.restype = ctypes.c_int
+        L.oracle_lattice_2d_q.argtypes = [ctypes.c_int, dp, dp, dp]
+        L.oracle_lattice_2d_q.restype = ctypes.c_int
+        L.oracle_transform_hermite.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
+        L.oracle_transform_hermite.restype = ctypes.c_int
+        L.oracle_transform_q.argtypes = [ctypes.c_int, dp, dp, dp, dp]
+        L.oracle_equilibrium_q.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.c_double] * 5 + \
+            [dp, dp]
+        L.oracle_collide_q.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, dp, dp]
+        L.oracle_internal_source_q.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
+        L.oracle_init_q.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, dp, dp, dp, dp,
+                                    ctypes.c_double, dp, dp, dp]
+        L.oracle_init_q.restype = ctypes.c_int
+        L.oracle_moments_q.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, dp, dp, dp,
+                                       ctypes.c_double, dp, dp, dp, dp, dp]
         L.oracle_equilibrium.argtypes = [ctypes.c_double] * 5 + [dp, dp]
         L.oracle_equilibrium_split.argtypes = [ctypes.c_int] + [ctypes.c_double] * 5 + [dp, dp]
         L.oracle_collide.argtypes = [dp, dp, dp, ctypes.c_double, ctypes.c_double,
@@ -79,7 +108,7 @@ def lib():
         L.oracle_init_split.restype = ctypes.c_int
         L.oracle_moments_split.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp, dp,
                                            ctypes.c_double, dp, dp, dp, dp, dp]
-        if L.oracle_abi_version() != 2:
+        if L.oracle_abi_version() != 3:
             raise RuntimeError("oracle library ABI mismatch; rebuild oracle/")
         _lib = L
     return _lib
@@ -105,40 +134,62 @@ def num_threads() -> int:
     return int(lib().oracle_num_threads())
 
 
-def lattice_1d():
-    """D1Q4 abscissae and weights (Table I), ascending abscissae."""
-    c = np.zeros(4)
-    w = np.zeros(4)
-    lib().oracle_lattice_1d(_d(c), _d(w))
+def lattice_1d(q1=4):
+    """D1Q4 (q1 = 4) or D1Q5 (q1 = 5) abscissae and weights (Table I),
+    ascending abscissae."""
+    c = np.zeros(q1)
+    w = np.zeros(q1)
+    if not lib().oracle_lattice_1d_q(q1, _d(c), _d(w)):
+        raise ValueError("q1 must be 4 or 5")
     return c, w
 
 
-def lattice_2d():
-    """D2Q16 velocities (c_x, c_y) and weights, i = 4a + b."""
-    cx, cy, w = np.zeros(16), np.zeros(16), np.zeros(16)
-    lib().oracle_lattice_2d(_d(cx), _d(cy), _d(w))
+def lattice_2d(q1=4):
+    """D2Q16 (q1 = 4) or D2Q25 (q1 = 5) velocities (c_x, c_y) and weights,
+    i = q1*a + b."""
+    q = q1 * q1
+    cx, cy, w = np.zeros(q), np.zeros(q), np.zeros(q)
+    if not lib().oracle_lattice_2d_q(q1, _d(cx), _d(cy), _d(w)):
+        raise ValueError("q1 must be 4 or 5")
     return cx, cy, w
 
 
 def transform(pop, lam_src, lam_dst):
-    """Frame transformation of 16 populations from lam_src to lam_dst."""
-    pop = _f64(pop, (16,))
-    out = np.zeros(16)
-    lib().oracle_transform(_d(pop), _d(_f64(lam_src, (3,))), _d(_f64(lam_dst, (3,))), _d(out))
+    """Frame transformation of 16 (D2Q16: the printed a0..a3) or 25 (D2Q25:
+    order-4 Hermite projection) populations from lam_src to lam_dst."""
+    pop = _f64(pop).ravel()
+    q1 = _q1(len(pop))
+    out = np.zeros(len(pop))
+    lib().oracle_transform_q(q1, _d(pop), _d(_f64(lam_src, (3,))), _d(_f64(lam_dst, (3,))),
+                             _d(out))
     return out
 
 
-def equilibrium(rho, ux, uy, T, gamma, split=TOTAL):
-    f = np.zeros(16)
-    g = np.zeros(16)
-    lib().oracle_equilibrium_split(split, rho, ux, uy, T, gamma, _d(f), _d(g))
+def transform_hermite(pop, lam_src, lam_dst, order):
+    """Frame transformation as the Hermite projection of the given order."""
+    pop = _f64(pop).ravel()
+    q1 = _q1(len(pop))
+    out = np.zeros(len(pop))
+    if lib().oracle_transform_hermite(q1, order, _d(pop), _d(_f64(lam_src, (3,))),
+                                      _d(_f64(lam_dst, (3,))), _d(out)) != 0:
+        raise ValueError("order must be <= min(4, q1 - 1)")
+    return out
+
+
+def equilibrium(rho, ux, uy, T, gamma, split=TOTAL, lattice=16):
+    q1 = _q1(lattice)
+    f = np.zeros(lattice)
+    g = np.zeros(lattice)
+    lib().oracle_equilibrium_q(q1, split, rho, ux, uy, T, gamma, _d(f), _d(g))
     return f, g
 
 
 def collide(ft, gt, lam, tau, prandtl, gamma, split=TOTAL):
-    fo, go = np.zeros(16), np.zeros(16)
-    lib().oracle_collide_split(split, _d(_f64(ft, (16,))), _d(_f64(gt, (16,))),
-                               _d(_f64(lam, (3,))), tau, prandtl, gamma, _d(fo), _d(go))
+    ft, gt = _f64(ft).ravel(), _f64(gt).ravel()
+    q1 = _q1(len(ft))
+    fo, go = np.zeros(len(ft)), np.zeros(len(ft))
+    lib().oracle_collide_q(q1, split, _d(ft), _d(gt), _d(_f64(lam, (3,))), tau, prandtl, gamma,
+                           _d(fo), _d(go))
     return fo, go
 
 
@@ -146,9 +197,10 @@ def internal_source(f, lam, a, grad):
     """Source of the internal-energy g-equation over one step, per velocity:
     S_i = -f_i (C_i - u) . (a + C_i . grad u) with grad[alpha][beta] =
     d_alpha u_beta, for populations f in the frame lam."""
-    S = np.zeros(16)
-    lib().oracle_internal_source(_d(_f64(f, (16,))), _d(_f64(lam, (3,))), _d(_f64(a, (2,))),
-                                 _d(_f64(grad, (2, 2))), _d(S))
+    f = _f64(f).ravel()
+    S = np.zeros(len(f))
+    lib().oracle_internal_source_q(_q1(len(f)), _d(f), _d(_f64(lam, (3,))), _d(_f64(a, (2,))),
+                                   _d(_f64(grad, (2, 2))), _d(S))
     return S
 
 
@@ -163,7 +215,7 @@ def lagrange(npts, y):
 
 @dataclass
 class State:
-    """Oracle state: f, g of shape (N, 16), lam of shape (N, 3)."""
+    """Oracle state: f, g of shape (N, Q), lam of shape (N, 3)."""
     f: np.ndarray
     g: np.ndarray
     lam: np.ndarray
@@ -174,10 +226,11 @@ class State:
 
 def init(P: Params, rho, ux, uy, T) -> State:
     N = P.nx * P.ny
+    q = P.lattice
     rho, ux, uy, T = (_f64(a, (N,)) for a in (rho, ux, uy, T))
-    f, g, lam = np.zeros((N, 16)), np.zeros((N, 16)), np.zeros((N, 3))
-    nbad = lib().oracle_init_split(P.split, N, _d(rho), _d(ux), _d(uy), _d(T), P.gamma, _d(f),
-                                   _d(g), _d(lam))
+    f, g, lam = np.zeros((N, q)), np.zeros((N, q)), np.zeros((N, 3))
+    nbad = lib().oracle_init_q(_q1(q), P.split, N, _d(rho), _d(ux), _d(uy), _d(T), P.gamma,
+                               _d(f), _d(g), _d(lam))
     if nbad:
         raise ValueError(f"{nbad} nodes with rho <= 0, T <= 0 or non-finite values")
     return State(f, g, lam)
@@ -195,8 +248,9 @@ class StepStats:
 def step(P: Params, s: State, nsteps: int = 1):
     """Advance nsteps; returns (new State, StepStats)."""
     N = P.nx * P.ny
+    q = P.lattice
     cur = s.copy()
-    nxt = State(np.zeros((N, 16)), np.zeros((N, 16)), np.zeros((N, 3)))
+    nxt = State(np.zeros((N, q)), np.zeros((N, q)), np.zeros((N, 3)))
     iters = np.zeros(N, dtype=np.int32)
     status = np.zeros(N, dtype=np.int32)
     tot = nonc = nbad = 0
@@ -214,10 +268,11 @@ def step(P: Params, s: State, nsteps: int = 1):
 
 def step_nodes(P: Params, s: State, nodes):
     """One step evaluated only at the listed node indices (reading the full
-    state).  Returns (f (k,16), g (k,16), lam (k,3), iters, status)."""
+    state).  Returns (f (k,Q), g (k,Q), lam (k,3), iters, status)."""
     nodes = np.ascontiguousarray(nodes, dtype=np.int64)
     k = len(nodes)
-    fo, go, lo = np.zeros((k, 16)), np.zeros((k, 16)), np.zeros((k, 3))
+    q = P.lattice
+    fo, go, lo = np.zeros((k, q)), np.zeros((k, q)), np.zeros((k, 3))
     iters = np.zeros(k, dtype=np.int32)
     status = np.zeros(k, dtype=np.int32)
     lib().oracle_step_nodes(ctypes.byref(P), _d(s.f), _d(s.g), _d(s.lam), k,
@@ -230,6 +285,7 @@ def moments(P: Params, s: State):
     """dict of rho, ux, uy, T, p, each of shape (ny, nx)."""
     N = P.nx * P.ny
     out = {k: np.zeros(N) for k in ("rho", "ux", "uy", "T", "p")}
-    lib().oracle_moments_split(P.split, N, _d(s.f), _d(s.g), _d(s.lam), P.gamma, _d(out["rho"]),
-                               _d(out["ux"]), _d(out["uy"]), _d(out["T"]), _d(out["p"]))
+    lib().oracle_moments_q(_q1(P.lattice), P.split, N, _d(s.f), _d(s.g), _d(s.lam), P.gamma,
+                           _d(out["rho"]), _d(out["ux"]), _d(out["uy"]), _d(out["T"]),
+                           _d(out["p"]))
     return {k: v.reshape(P.ny, P.nx) for k, v in out.items()}

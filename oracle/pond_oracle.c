@@ -1,7 +1,8 @@
 /*
  * pond_oracle.c -- plain FP64 CPU oracle of the particles-on-demand (PonD)
- * stream-and-collide step of the double-distribution-function BGK model,
- * total-energy split and internal-energy split, D2Q16 lattice.
+ * stream-and-collide step of the double-distribution-function BGK model:
+ * total-energy, internal-energy and non-translational energy splits, on the
+ * D2Q16 and D2Q25 lattices of Table I.
  *
  * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU
  * baseline leg of the benchmark load this library.  It shares no code, header,
@@ -27,7 +28,10 @@
  *     iteration (predictor: the node's own frame at time t), which the paper
  *     takes from its PonD reference; the converged populations are re-projected
  *     onto the frame of their own moments before the collision;
- *   - Grad order N = 3 for both f and g;
+ *   - Grad order N = 3 for both f and g on D2Q16, N = 4 on D2Q25 (the order
+ *     the non-translational split needs for f's fourth moment, Sec. II); the
+ *     order-4 coefficients follow the same definition as the printed a0..a3,
+ *     the Hermite projection in the destination frame;
  *   - the collision sign is -(1/tau)(f - f^eq) (Eq. boltz_eq carries a
  *     typo'd sign; the g-equations of Sec. II have the correct one);
  *   - discrete relaxation time: nu = (tau - 1/2) T, omega = 1/tau;
@@ -40,12 +44,15 @@
  *     the collision with the re-projected gathered f, u the new frame
  *     velocity, d_t u the difference between the new and the time-t frame
  *     velocity of the node, grad u central differences of the time-t frame
- *     velocities of the four neighbours (wrapped or clamped like the stencil).
+ *     velocities of the four neighbours (wrapped or clamped like the stencil);
+ *   - non-translational split: the paper's single-relaxation BGK only (Pr = 1;
+ *     its quasi-equilibrium form is not given and not built here).
  *
  * Units: lattice units, dx = dt = 1, r = 1, T_L = 1 (Table I column rT_L).
- * Layout (oracle only): node n = y*nx + x; populations pop[n*16 + i];
- * frame lam[n*3 + {0,1,2}] = (u_x, u_y, T).  Velocity i = 4a + b has
- * c_i = (c_a, c_b) with the D1Q4 abscissae in ascending order.
+ * Layout (oracle only): node n = y*nx + x; populations pop[n*Q + i] with
+ * Q = 16 or 25; frame lam[n*3 + {0,1,2}] = (u_x, u_y, T).  Velocity
+ * i = q1*a + b (q1 = 4 or 5) has c_i = (c_a, c_b) with the one-dimensional
+ * abscissae in ascending order.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -54,9 +61,10 @@
 #include <omp.h>
 #endif
 
-#define ORACLE_ABI 2
-#define Q1 4
-#define Q 16
+#define ORACLE_ABI 3
+#define Q1 4      /* D1Q4 */
+#define Q 16      /* D2Q16 */
+#define QMAX 25   /* D2Q25 */
 
 typedef struct {
     int nx, ny;
@@ -68,7 +76,9 @@ typedef struct {
     double gamma;          /* adiabatic exponent, c_v = 1/(gamma - 1) */
     double pc_tol;         /* predictor-corrector tolerance */
     int split;             /* 0 = total energy (Eq. total_energy_g), 1 = internal energy
-                              (Eq. int_energy_g) */
+                              (Eq. int_energy_g), 2 = non-translational energy
+                              (Eq. nt_energy_g) */
+    int lattice;           /* 16 = D2Q16 (D1Q4 x D1Q4), 25 = D2Q25 (D1Q5 x D1Q5) */
 } oracle_params;
 
 /* status bits per node written by oracle_step */
@@ -110,6 +120,50 @@ void oracle_lattice_2d(double cx[Q], double cy[Q], double w[Q])
             w[4 * a + b] = w1[a] * w1[b];
         }
 }
+
+/* Table I, row D1Q5 (rT_L = 1): abscissae 0, +-sqrt(5 -+ sqrt 10) with weights
+ * 8/15 at the origin, (7 + 2 sqrt 10)/60 on the inner pair, (7 - 2 sqrt 10)/60
+ * on the outer pair. */
+void oracle_lattice_1d_q5(double c[5], double w[5])
+{
+    double s10 = sqrt(10.0);
+    double c_in = sqrt(5.0 - s10), c_out = sqrt(5.0 + s10);
+    double w_in = (7.0 + 2.0 * s10) / 60.0, w_out = (7.0 - 2.0 * s10) / 60.0;
+    c[0] = -c_out; c[1] = -c_in; c[2] = 0.0; c[3] = c_in; c[4] = c_out;
+    w[0] = w_out;  w[1] = w_in;  w[2] = 8.0 / 15.0; w[3] = w_in; w[4] = w_out;
+}
+
+/* One-dimensional rule of the lattice with q1 = 4 (D1Q4) or 5 (D1Q5) points;
+ * returns q1, or 0 for any other value. */
+int oracle_lattice_1d_q(int q1, double *c, double *w)
+{
+    if (q1 == 4)
+        oracle_lattice_1d(c, w);
+    else if (q1 == 5)
+        oracle_lattice_1d_q5(c, w);
+    else
+        return 0;
+    return q1;
+}
+
+/* Tensor-product lattice D1Qq1 x D1Qq1: velocity i = q1*a + b has
+ * c_i = (c_a, c_b), w_i = w_a w_b.  Returns Q = q1^2, or 0. */
+int oracle_lattice_2d_q(int q1, double *cx, double *cy, double *w)
+{
+    double c[5], w1[5];
+    if (!oracle_lattice_1d_q(q1, c, w1))
+        return 0;
+    for (int a = 0; a < q1; a++)
+        for (int b = 0; b < q1; b++) {
+            cx[q1 * a + b] = c[a];
+            cy[q1 * a + b] = c[b];
+            w[q1 * a + b] = w1[a] * w1[b];
+        }
+    return q1 * q1;
+}
+
+/* q1 of a lattice given by its velocity count (16 or 25), else 0. */
+static int q1_of(int lattice) { return lattice == 16 ? 4 : (lattice == 25 ? 5 : 0); }
 
 static double kron(int a, int b) { return a == b ? 1.0 : 0.0; }
 
@@ -190,30 +244,120 @@ void oracle_transform(const double *pop, const double *lam_src, const double *la
     memcpy(out, res, sizeof res);
 }
 
+/* Probabilists' Hermite polynomial He_n(x) from the three-term recurrence
+ * He_{n+1} = x He_n - n He_{n-1}, He_0 = 1, He_1 = x. */
+static double hermite(int n, double x)
+{
+    if (n == 0)
+        return 1.0;
+    double h0 = 1.0, h1 = x;
+    for (int k = 1; k < n; k++) {
+        double h2 = x * h1 - k * h0;
+        h0 = h1;
+        h1 = h2;
+    }
+    return h1;
+}
+
+static double factorial(int n)
+{
+    double r = 1.0;
+    for (int k = 2; k <= n; k++)
+        r *= k;
+    return r;
+}
+
+/*
+ * Frame transformation as the Hermite projection of order N = order in the
+ * destination frame (Sec. "Frame transformation", Eq. gradGeneralTransform).
+ * The Grad coefficient tensors a_(n) of the destination frame are the Hermite
+ * moments of the populations in the reduced velocity
+ * xi_i = (C_i(lam_src) - u_dst) / sqrt(T_dst): a rank-n component with k
+ * indices x and n - k indices y is
+ *   A_{k, n-k} = sum_i pop_i He_k(xi_ix) He_{n-k}(xi_iy)
+ * (the printed a0..a3 are this projection written through the source-frame
+ * moments).  Reconstruction: a_(n) : H_(n)(c_i) / n! counts each component
+ * once per ordering of its indices, C(n, k) times, so
+ *   out_i = w_i sum_{k + l <= N} A_{k,l} He_k(c_ix) He_l(c_iy) / (k! l!).
+ * Only moments of the populations up to order N enter.  Needs the Hermite
+ * polynomials up to order N to be orthogonal on the lattice (N <= q1 - 1,
+ * N <= 4); returns -1 otherwise, 0 on success.  out may alias pop.
+ */
+int oracle_transform_hermite(int q1, int order, const double *pop, const double *lam_src,
+                             const double *lam_dst, double *out)
+{
+    double cx[QMAX], cy[QMAX], w[QMAX];
+    int q = oracle_lattice_2d_q(q1, cx, cy, w);
+    if (!q || order < 0 || order > 4 || order > q1 - 1)
+        return -1;
+    double A[5][5] = {{0.0}};
+    double sTs = sqrt(lam_src[2]), sTd = sqrt(lam_dst[2]);
+    for (int i = 0; i < q; i++) {
+        double xi_x = (sTs * cx[i] + lam_src[0] - lam_dst[0]) / sTd;
+        double xi_y = (sTs * cy[i] + lam_src[1] - lam_dst[1]) / sTd;
+        for (int k = 0; k <= order; k++)
+            for (int l = 0; k + l <= order; l++)
+                A[k][l] += pop[i] * hermite(k, xi_x) * hermite(l, xi_y);
+    }
+    double res[QMAX];
+    for (int i = 0; i < q; i++) {
+        double s = 0.0;
+        for (int k = 0; k <= order; k++)
+            for (int l = 0; k + l <= order; l++)
+                s += A[k][l] * hermite(k, cx[i]) * hermite(l, cy[i]) /
+                     (factorial(k) * factorial(l));
+        res[i] = w[i] * s;
+    }
+    memcpy(out, res, sizeof(double) * q);
+    return 0;
+}
+
+/* The frame transformation of a lattice: the printed a0..a3 (oracle_transform)
+ * on D2Q16 (q1 = 4), the order-4 Hermite projection on D2Q25 (q1 = 5). */
+void oracle_transform_q(int q1, const double *pop, const double *lam_src, const double *lam_dst,
+                        double *out)
+{
+    if (q1 == 4)
+        oracle_transform(pop, lam_src, lam_dst, out);
+    else
+        oracle_transform_hermite(q1, 4, pop, lam_src, lam_dst, out);
+}
+
 /*
  * Local equilibria in the frame (u, T) (Sec. "Discrete velocity solver ...:
  * PonD"): f_i^eq = rho w_i, and the g^eq of Sec. II with v -> C_i =
  * sqrt(T) c_i + u and U' = U - rho D T / 2 = rho T (c_v - 1) for D = 2,
  * c_v = 1/(gamma - 1):
- *   split 0 (total energy):    g^eq = (U'/rho + v^2/2) f^eq;
- *   split 1 (internal energy): g^eq = (U'/rho + (v - u)^2/2) f^eq.
+ *   split 0 (total energy):             g^eq = (U'/rho + v^2/2) f^eq;
+ *   split 1 (internal energy):          g^eq = (U'/rho + (v - u)^2/2) f^eq;
+ *   split 2 (non-translational energy): g^eq = (U'/rho) f^eq.
+ * Lattice D1Qq1 x D1Qq1, q1 = 4 or 5.
  */
-void oracle_equilibrium_split(int split, double rho, double ux, double uy, double T,
-                              double gamma, double *feq, double *geq)
+void oracle_equilibrium_q(int q1, int split, double rho, double ux, double uy, double T,
+                          double gamma, double *feq, double *geq)
 {
-    double cx[Q], cy[Q], w[Q];
-    oracle_lattice_2d(cx, cy, w);
+    double cx[QMAX], cy[QMAX], w[QMAX];
+    int q = oracle_lattice_2d_q(q1, cx, cy, w);
     double cv = 1.0 / (gamma - 1.0);
     double sT = sqrt(T);
-    for (int i = 0; i < Q; i++) {
+    for (int i = 0; i < q; i++) {
         double Cx = sT * cx[i] + ux, Cy = sT * cy[i] + uy;
         if (split == 1) {
             Cx -= ux;
             Cy -= uy;
         }
         feq[i] = rho * w[i];
-        geq[i] = w[i] * (rho * (cv - 1.0) * T + 0.5 * rho * (Cx * Cx + Cy * Cy));
+        if (split == 2)
+            geq[i] = w[i] * rho * (cv - 1.0) * T;
+        else
+            geq[i] = w[i] * (rho * (cv - 1.0) * T + 0.5 * rho * (Cx * Cx + Cy * Cy));
     }
+}
+
+void oracle_equilibrium_split(int split, double rho, double ux, double uy, double T,
+                              double gamma, double *feq, double *geq)
+{
+    oracle_equilibrium_q(4, split, rho, ux, uy, T, gamma, feq, geq);
 }
 
 void oracle_equilibrium(double rho, double ux, double uy, double T, double gamma,
@@ -225,7 +369,8 @@ void oracle_equilibrium(double rho, double ux, double uy, double T, double gamma
 /*
  * BGK collision of f and g in the frame lam = (u, T) of their own moments.
  * f*_i = f_i + omega (f_i^eq - f_i) with omega = 1/tau.
- * Pr = 1: g*_i = g_i + omega (g_i^eq - g_i), the paper's model.
+ * Pr = 1 (and the non-translational split): g*_i = g_i + omega (g_i^eq - g_i),
+ * the paper's model.
  * Pr != 1 (quasi-equilibrium reading): with P^neq = sum_i C_i C_i (f_i - f_i^eq)
  * and dq = u . P^neq, g^qe_i = g^eq_i + w_i (c_i . dq)/sqrt(T) carries the
  * equilibrium energy flux plus the viscous-heating flux; then
@@ -233,24 +378,25 @@ void oracle_equilibrium(double rho, double ux, double uy, double T, double gamma
  * The Fourier part of the energy flux relaxes at omega_1, the viscous-heating
  * part at omega; the zeroth moment (total energy) is untouched by either.
  */
-void oracle_collide_split(int split, const double *ft, const double *gt, const double *lam,
-                          double tau, double prandtl, double gamma, double *fo, double *go)
+void oracle_collide_q(int q1, int split, const double *ft, const double *gt, const double *lam,
+                      double tau, double prandtl, double gamma, double *fo, double *go)
 {
-    double cx[Q], cy[Q], w[Q], feq[Q], geq[Q];
-    oracle_lattice_2d(cx, cy, w);
+    double cx[QMAX], cy[QMAX], w[QMAX], feq[QMAX], geq[QMAX];
+    int q = oracle_lattice_2d_q(q1, cx, cy, w);
     double rho = 0.0;
-    for (int i = 0; i < Q; i++)
+    for (int i = 0; i < q; i++)
         rho += ft[i];
     double ux = lam[0], uy = lam[1], T = lam[2];
-    oracle_equilibrium_split(split, rho, ux, uy, T, gamma, feq, geq);
+    oracle_equilibrium_q(q1, split, rho, ux, uy, T, gamma, feq, geq);
     double omega = 1.0 / tau;
-    double fin[Q], gin[Q];
-    memcpy(fin, ft, sizeof fin);
-    memcpy(gin, gt, sizeof gin);
-    for (int i = 0; i < Q; i++)
+    double fin[QMAX], gin[QMAX];
+    memcpy(fin, ft, sizeof(double) * q);
+    memcpy(gin, gt, sizeof(double) * q);
+    for (int i = 0; i < q; i++)
         fo[i] = fin[i] + omega * (feq[i] - fin[i]);
-    if (prandtl == 1.0) {
-        for (int i = 0; i < Q; i++)
+    if (prandtl == 1.0 || split == 2) {
+        /* the non-translational split is taken with the paper's BGK only */
+        for (int i = 0; i < q; i++)
             go[i] = gin[i] + omega * (geq[i] - gin[i]);
         return;
     }
@@ -258,13 +404,13 @@ void oracle_collide_split(int split, const double *ft, const double *gt, const d
     double omega1 = 1.0 / tau1;
     if (split == 1) {
         /* internal energy: the flux of g is the heat flux alone */
-        for (int i = 0; i < Q; i++)
+        for (int i = 0; i < q; i++)
             go[i] = gin[i] + omega1 * (geq[i] - gin[i]);
         return;
     }
     double sT = sqrt(T);
     double P[2][2] = {{0.0}};
-    for (int i = 0; i < Q; i++) {
+    for (int i = 0; i < q; i++) {
         double C[2] = {sT * cx[i] + ux, sT * cy[i] + uy};
         for (int a = 0; a < 2; a++)
             for (int b = 0; b < 2; b++)
@@ -274,10 +420,16 @@ void oracle_collide_split(int split, const double *ft, const double *gt, const d
     double dq[2];
     for (int a = 0; a < 2; a++)
         dq[a] = u[0] * P[0][a] + u[1] * P[1][a];
-    for (int i = 0; i < Q; i++) {
+    for (int i = 0; i < q; i++) {
         double gqe = geq[i] + w[i] * (cx[i] * dq[0] + cy[i] * dq[1]) / sT;
         go[i] = gin[i] + omega1 * (gqe - gin[i]) + omega * (geq[i] - gqe);
     }
+}
+
+void oracle_collide_split(int split, const double *ft, const double *gt, const double *lam,
+                          double tau, double prandtl, double gamma, double *fo, double *go)
+{
+    oracle_collide_q(4, split, ft, gt, lam, tau, prandtl, gamma, fo, go);
 }
 
 void oracle_collide(const double *ft, const double *gt, const double *lam,
@@ -292,13 +444,13 @@ void oracle_collide(const double *ft, const double *gt, const double *lam,
  * in the frame lam = (u, T) of the populations f, a = d_t u and
  * grad[alpha][beta] = d_alpha u_beta.
  */
-void oracle_internal_source(const double *f, const double *lam, const double a[2],
-                            const double grad[2][2], double *S)
+void oracle_internal_source_q(int q1, const double *f, const double *lam, const double a[2],
+                              const double grad[2][2], double *S)
 {
-    double cx[Q], cy[Q], w[Q];
-    oracle_lattice_2d(cx, cy, w);
+    double cx[QMAX], cy[QMAX], w[QMAX];
+    int q = oracle_lattice_2d_q(q1, cx, cy, w);
     double sT = sqrt(lam[2]);
-    for (int i = 0; i < Q; i++) {
+    for (int i = 0; i < q; i++) {
         double C[2] = {sT * cx[i] + lam[0], sT * cy[i] + lam[1]};
         double dv[2] = {sT * cx[i], sT * cy[i]};
         double s = 0.0;
@@ -306,6 +458,12 @@ void oracle_internal_source(const double *f, const double *lam, const double a[2
             s += dv[b] * (a[b] + C[0] * grad[0][b] + C[1] * grad[1][b]);
         S[i] = -f[i] * s;
     }
+}
+
+void oracle_internal_source(const double *f, const double *lam, const double a[2],
+                            const double grad[2][2], double *S)
+{
+    oracle_internal_source_q(4, f, lam, a, grad, S);
 }
 
 /*
@@ -354,12 +512,13 @@ static int node_index(int i, int n, int bc)
 static void gather(const oracle_params *P, const double *f, const double *g, const double *lam,
                    int x, int y, const double *lam_bar, double *ft, double *gt)
 {
-    double cx[Q], cy[Q], w[Q];
-    oracle_lattice_2d(cx, cy, w);
+    double cx[QMAX], cy[QMAX], w[QMAX];
+    int q1 = q1_of(P->lattice);
+    int q = oracle_lattice_2d_q(q1, cx, cy, w);
     int np = P->interp_points;
     double sT = sqrt(lam_bar[2]);
-    double tf[Q], tg[Q], wx[4], wy[4];
-    for (int i = 0; i < Q; i++) {
+    double tf[QMAX], tg[QMAX], wx[4], wy[4];
+    for (int i = 0; i < q; i++) {
         double Cx = sT * cx[i] + lam_bar[0];
         double Cy = sT * cy[i] + lam_bar[1];
         double yx = (double)x - Cx, yy = (double)y - Cy;
@@ -372,8 +531,8 @@ static void gather(const oracle_params *P, const double *f, const double *g, con
             for (int sx = 0; sx < np; sx++) {
                 int jx = node_index(bx + sx, P->nx, P->bc_x);
                 long s = (long)jy * P->nx + jx;
-                oracle_transform(f + Q * s, lam + 3 * s, lam_bar, tf);
-                oracle_transform(g + Q * s, lam + 3 * s, lam_bar, tg);
+                oracle_transform_q(q1, f + (long)q * s, lam + 3 * s, lam_bar, tf);
+                oracle_transform_q(q1, g + (long)q * s, lam + 3 * s, lam_bar, tg);
                 double W = wx[sx] * wy[sy];
                 sf += W * tf[i];
                 sg += W * tg[i];
@@ -388,21 +547,27 @@ static void gather(const oracle_params *P, const double *f, const double *g, con
  * Conserved moments of (f, g) living in frame lam (Sec. II): density and
  * momentum of f, and the frame they imply: u = j/rho and
  *   total-energy split:    E = sum g,     T = (E - |j|^2/(2 rho)) / (rho c_v);
- *   internal-energy split: U = sum g,     T = U / (rho c_v)  (E = U + K).
- * *E receives sum g.
+ *   internal-energy split: U = sum g,     T = U / (rho c_v)  (E = U + K);
+ *   non-translational split: E = sum (g + |C_i|^2 f / 2) (Eq. nt_energy_g),
+ *                          T = (E - |j|^2/(2 rho)) / (rho c_v).
+ * *E receives the split's energy sum (sum g, or E of the non-translational
+ * split).
  */
-static void conserved(int split, const double *ft, const double *gt, const double *lam, double cv,
-                      double *rho, double *jx, double *jy, double *E, double *lam_new)
+static void conserved(int q1, int split, const double *ft, const double *gt, const double *lam,
+                      double cv, double *rho, double *jx, double *jy, double *E, double *lam_new)
 {
-    double cx[Q], cy[Q], w[Q];
-    oracle_lattice_2d(cx, cy, w);
+    double cx[QMAX], cy[QMAX], w[QMAX];
+    int q = oracle_lattice_2d_q(q1, cx, cy, w);
     double sT = sqrt(lam[2]);
     double r = 0.0, px = 0.0, py = 0.0, e = 0.0;
-    for (int i = 0; i < Q; i++) {
+    for (int i = 0; i < q; i++) {
+        double Cx = sT * cx[i] + lam[0], Cy = sT * cy[i] + lam[1];
         r += ft[i];
-        px += ft[i] * (sT * cx[i] + lam[0]);
-        py += ft[i] * (sT * cy[i] + lam[1]);
+        px += ft[i] * Cx;
+        py += ft[i] * Cy;
         e += gt[i];
+        if (split == 2)
+            e += 0.5 * (Cx * Cx + Cy * Cy) * ft[i];
     }
     *rho = r; *jx = px; *jy = py; *E = e;
     lam_new[0] = px / r;
@@ -427,15 +592,16 @@ static int node_step(const oracle_params *P, const double *f, const double *g, c
                      long n, double *fo, double *go, double *lamo, int *iters, int *status)
 {
     double cv = 1.0 / (P->gamma - 1.0);
+    int q1 = q1_of(P->lattice), q = q1 * q1;
     int x = (int)(n % P->nx), y = (int)(n / P->nx);
     double lg[3] = {lam[3 * n], lam[3 * n + 1], lam[3 * n + 2]};
     double ln[3] = {lg[0], lg[1], lg[2]};
-    double ft[Q], gt[Q];
+    double ft[QMAX], gt[QMAX];
     int k, conv = 0, bad = 0, used = 0;
     for (k = 0; k < P->pc_max_iter; k++) {
         double rho, jx, jy, E;
         gather(P, f, g, lam, x, y, lg, ft, gt);
-        conserved(P->split, ft, gt, lg, cv, &rho, &jx, &jy, &E, ln);
+        conserved(q1, P->split, ft, gt, lg, cv, &rho, &jx, &jy, &E, ln);
         used = k + 1;
         if (!(rho > 0.0) || !(ln[2] > 0.0) || !isfinite(ln[0]) || !isfinite(ln[1]) ||
             !isfinite(ln[2]) || !isfinite(E)) {
@@ -454,14 +620,14 @@ static int node_step(const oracle_params *P, const double *f, const double *g, c
     *iters = used;
     *status = (conv ? 0 : ORACLE_NONCONVERGED) | (bad ? ORACLE_NONPHYSICAL : 0);
     if (bad) {
-        for (int i = 0; i < Q; i++)
+        for (int i = 0; i < q; i++)
             fo[i] = go[i] = NAN;
         lamo[0] = lamo[1] = lamo[2] = NAN;
         return 1;
     }
-    oracle_transform(ft, lg, ln, ft);
-    oracle_transform(gt, lg, ln, gt);
-    oracle_collide_split(P->split, ft, gt, ln, P->tau, P->prandtl, P->gamma, fo, go);
+    oracle_transform_q(q1, ft, lg, ln, ft);
+    oracle_transform_q(q1, gt, lg, ln, gt);
+    oracle_collide_q(q1, P->split, ft, gt, ln, P->tau, P->prandtl, P->gamma, fo, go);
     if (P->split == 1) {
         /* d_t u: new minus time-t frame velocity of the node; grad u: central
            differences of the neighbours' time-t frame velocities */
@@ -476,9 +642,9 @@ static int node_step(const oracle_params *P, const double *f, const double *g, c
             grad[0][b] = 0.5 * (lam[3 * xp + b] - lam[3 * xm + b]);
             grad[1][b] = 0.5 * (lam[3 * yp + b] - lam[3 * ym + b]);
         }
-        double S[Q];
-        oracle_internal_source(ft, ln, a, grad, S);
-        for (int i = 0; i < Q; i++)
+        double S[QMAX];
+        oracle_internal_source_q(q1, ft, ln, a, grad, S);
+        for (int i = 0; i < q; i++)
             go[i] += S[i];
     }
     lamo[0] = ln[0];
@@ -493,10 +659,13 @@ int oracle_step(const oracle_params *P, const double *f, const double *g, const 
                 double *fo, double *go, double *lamo, int *iters, int *status)
 {
     long N = (long)P->nx * P->ny;
+    long q = (long)P->lattice;
+    if (!q1_of(P->lattice))
+        return -1;
     int nbad = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : nbad)
     for (long n = 0; n < N; n++)
-        nbad += node_step(P, f, g, lam, n, fo + Q * n, go + Q * n, lamo + 3 * n, iters + n,
+        nbad += node_step(P, f, g, lam, n, fo + q * n, go + q * n, lamo + 3 * n, iters + n,
                           status + n);
     return nbad;
 }
@@ -507,10 +676,13 @@ int oracle_step_nodes(const oracle_params *P, const double *f, const double *g, 
                       long count, const long *nodes, double *fo, double *go, double *lamo,
                       int *iters, int *status)
 {
+    long q = (long)P->lattice;
+    if (!q1_of(P->lattice))
+        return -1;
     int nbad = 0;
 #pragma omp parallel for schedule(dynamic, 4) reduction(+ : nbad)
     for (long k = 0; k < count; k++)
-        nbad += node_step(P, f, g, lam, nodes[k], fo + Q * k, go + Q * k, lamo + 3 * k, iters + k,
+        nbad += node_step(P, f, g, lam, nodes[k], fo + q * k, go + q * k, lamo + 3 * k, iters + k,
                           status + k);
     return nbad;
 }
@@ -521,9 +693,11 @@ int oracle_step_nodes(const oracle_params *P, const double *f, const double *g, 
  * number of rejected nodes (rho <= 0, T <= 0 or non-finite input); nothing is
  * written for those.
  */
-int oracle_init_split(int split, long N, const double *rho, const double *ux, const double *uy,
-                      const double *T, double gamma, double *f, double *g, double *lam)
+int oracle_init_q(int q1, int split, long N, const double *rho, const double *ux,
+                  const double *uy, const double *T, double gamma, double *f, double *g,
+                  double *lam)
 {
+    long q = (long)q1 * q1;
     int nbad = 0;
     for (long n = 0; n < N; n++) {
         if (!(rho[n] > 0.0) || !(T[n] > 0.0) || !isfinite(rho[n]) || !isfinite(T[n]) ||
@@ -531,12 +705,18 @@ int oracle_init_split(int split, long N, const double *rho, const double *ux, co
             nbad++;
             continue;
         }
-        oracle_equilibrium_split(split, rho[n], ux[n], uy[n], T[n], gamma, f + Q * n, g + Q * n);
+        oracle_equilibrium_q(q1, split, rho[n], ux[n], uy[n], T[n], gamma, f + q * n, g + q * n);
         lam[3 * n] = ux[n];
         lam[3 * n + 1] = uy[n];
         lam[3 * n + 2] = T[n];
     }
     return nbad;
+}
+
+int oracle_init_split(int split, long N, const double *rho, const double *ux, const double *uy,
+                      const double *T, double gamma, double *f, double *g, double *lam)
+{
+    return oracle_init_q(4, split, N, rho, ux, uy, T, gamma, f, g, lam);
 }
 
 int oracle_init(long N, const double *rho, const double *ux, const double *uy, const double *T,
@@ -549,13 +729,15 @@ int oracle_init(long N, const double *rho, const double *ux, const double *uy, c
  * Macroscopic fields from the stored state (Sec. II): rho = sum f,
  * rho u = sum f C_i, T from sum g as in conserved(), p = rho T.
  */
-void oracle_moments_split(int split, long N, const double *f, const double *g, const double *lam,
-                          double gamma, double *rho, double *ux, double *uy, double *T, double *p)
+void oracle_moments_q(int q1, int split, long N, const double *f, const double *g,
+                      const double *lam, double gamma, double *rho, double *ux, double *uy,
+                      double *T, double *p)
 {
     double cv = 1.0 / (gamma - 1.0);
+    long q = (long)q1 * q1;
     for (long n = 0; n < N; n++) {
         double r, jx, jy, E, ln[3];
-        conserved(split, f + Q * n, g + Q * n, lam + 3 * n, cv, &r, &jx, &jy, &E, ln);
+        conserved(q1, split, f + q * n, g + q * n, lam + 3 * n, cv, &r, &jx, &jy, &E, ln);
         rho[n] = r;
         ux[n] = ln[0];
         uy[n] = ln[1];
@@ -563,6 +745,12 @@ void oracle_moments_split(int split, long N, const double *f, const double *g, c
         if (p)
             p[n] = r * ln[2];
     }
+}
+
+void oracle_moments_split(int split, long N, const double *f, const double *g, const double *lam,
+                          double gamma, double *rho, double *ux, double *uy, double *T, double *p)
+{
+    oracle_moments_q(4, split, N, f, g, lam, gamma, rho, ux, uy, T, p);
 }
 
 void oracle_moments(long N, const double *f, const double *g, const double *lam, double gamma,
