@@ -46,12 +46,23 @@ PEAK_HBM_GBS = 8000.0
 #   frame transformation 16 velocities x 2 distributions x 65 = 2080;
 #   once per node: moments of the gathered populations 784, re-projection 110,
 #   collision 60, reconstruction 640.
-def flops_per_iter(np_):
+#
+# D2Q25 (Grad order 4, 15 moments per distribution), same accounting: per
+# iteration departure points 175, interpolation 25 x NP^2 x (1 + 15 x 4),
+# transformation 25 x 2 x 85 (30 FMAs and the shared order-4 shift/scale);
+# once per node 1850 + 250 + 80 + 1500.
+def flops_per_iter(np_, q=16):
+    if q == 25:
+        return 175 + 25 * np_ * np_ * 61 + 4250
     return 112 + 16 * np_ * np_ * 41 + 2080
 
 
+def flops_per_node(q=16):
+    return 3680 if q == 25 else 784 + 110 + 60 + 640
+
+
 FLOPS_PER_ITER = flops_per_iter(4)
-FLOPS_PER_NODE = 784 + 110 + 60 + 640
+FLOPS_PER_NODE = flops_per_node()
 # internal-energy split, once per node: velocity gradient and d_t u 10, and per
 # velocity the pre-collision population (10 FMA) and the source term 17
 FLOPS_SOURCE_PER_NODE = 10 + 16 * (20 + 17)
@@ -105,14 +116,14 @@ def traffic_record(kernel, precision):
     return None
 
 
-def cpu_baseline(w, seconds, split=0):
+def cpu_baseline(w, seconds, split=0, lattice=16):
     """The FP64 oracle, unmodified, timed on this host's cores: whole-grid steps
     of the same workload from its initial state, as many as fit in
     ~``seconds`` (at least one); if one whole-grid step would take much
     longer, one step at a random sample of nodes instead."""
     import oracle
     P = oracle.params(w.nx, w.ny, tau=w.tau, gamma=w.gamma, prandtl=w.prandtl, bc_x=w.bc_x,
-                      bc_y=w.bc_y, split=split)
+                      bc_y=w.bc_y, split=split, lattice=lattice)
     s = oracle.init(P, w.rho.ravel(), w.ux.ravel(), w.uy.ravel(), w.T.ravel())
     rng = np.random.default_rng(0)
     pilot = rng.integers(0, w.nodes, 512)
@@ -364,8 +375,11 @@ def main():
                     help="predictor-corrector tolerance (0: the library default)")
     ap.add_argument("--size", type=int, default=512,
                     help="modes512 workload: grid edge (other sizes are diagnostics)")
-    ap.add_argument("--split", choices=["total", "internal"], default="total",
-                    help="energy split carried by g (single-instance workloads)")
+    ap.add_argument("--split", choices=["total", "internal", "nontrans"], default="total",
+                    help="energy split carried by g (single-instance workloads); nontrans "
+                         "runs at Pr = 1")
+    ap.add_argument("--lattice", type=int, choices=[16, 25], default=16,
+                    help="D2Q16 or D2Q25 (single-instance workloads)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", choices=["tiled", "global"], default="tiled")
@@ -427,10 +441,13 @@ def main():
         tuning["lds_nodes"] = 0  # the tile's default unless given
     if args.lds_nodes is not None:
         tuning["lds_nodes"] = args.lds_nodes
-    split = pond.SPLIT_INTERNAL if args.split == "internal" else pond.SPLIT_TOTAL
+    split = {"total": pond.SPLIT_TOTAL, "internal": pond.SPLIT_INTERNAL,
+             "nontrans": pond.SPLIT_NONTRANS}[args.split]
+    if split == pond.SPLIT_NONTRANS:
+        w.prandtl = 1.0
     sol = pond.Solver.from_workload(w, precision=prec, stream=stream.cuda_stream,
                                     interp_points=args.interp_points, split=split,
-                                    pc_tol=args.pc_tol, tuning=tuning)
+                                    lattice=args.lattice, pc_tol=args.pc_tol, tuning=tuning)
     tun = pond.pond_get_tuning(sol.ctx)
     log(f"workload {w.name} {w.nx}x{w.ny}, {args.precision}, {args.split} split, "
         f"warmup {args.warmup}, steps {args.steps}")
@@ -473,11 +490,13 @@ def main():
     log(f"time {ms:.1f} ms (host {wall * 1e3:.1f} ms), {mlups:.1f} MLUPS, K {kbar:.3f}, "
         f"kernels: step {step_ms:.4f} ms, prepass {pre_ms:.4f} ms per launch")
 
-    flops = N * (flops_per_iter(args.interp_points) * kbar + FLOPS_PER_NODE +
+    flops = N * (flops_per_iter(args.interp_points, args.lattice) * kbar +
+                 flops_per_node(args.lattice) +
                  (FLOPS_SOURCE_PER_NODE if split == pond.SPLIT_INTERNAL else 0))
     ptype = "float" if prec == pond.PREC_FP32 else "double"
-    kname = f"step_tiled_kernel<{ptype},{args.interp_points},{split},{TILE_DIMS[tun.tile]}>" \
-        if args.kernel == "tiled" else f"step_kernel<{ptype},{args.interp_points},{split}>"
+    lat = f"D2Q{args.lattice}"
+    kname = f"step_tiled_kernel<{ptype},{args.interp_points},{split},{lat},{TILE_DIMS[tun.tile]}>" \
+        if args.kernel == "tiled" else f"step_kernel<{ptype},{args.interp_points},{split},{lat}>"
     traffic = traffic_record(kname, args.precision)
     if prec == pond.PREC_FP32:
         achieved = flops / (step_ms * 1e-3) / 1e12
@@ -499,7 +518,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
-        cpu = cpu_baseline(w, args.cpu_seconds, split)
+        cpu = cpu_baseline(w, args.cpu_seconds, split, args.lattice)
         log(f"oracle: {cpu['value']:.4f} MLUPS on {cpu['cores']} threads ({cpu['sample']})")
 
     out = {
@@ -510,7 +529,7 @@ def main():
         "config": {"workload": wname, "nx": w.nx, "ny": w.ny, **wconf,
                    "tau": w.tau, "prandtl": w.prandtl, "gamma": w.gamma,
                    "precision": args.precision, "interp_points": args.interp_points,
-                   "split": args.split,
+                   "split": args.split, "lattice": args.lattice,
                    "parallelism": "single_gpu"},
         "tuning": {"kernel": args.kernel, "tile": tun.tile, "lds_nodes": tun.lds_nodes},
         "pc_iterations_mean": kbar,

@@ -65,8 +65,13 @@ typedef enum {
 } pond_status;
 
 /* Lattice: Table I.  D2Q16 = D1Q4 x D1Q4, the fourth-order Gauss-Hermite rule
- * (abscissae +-sqrt(3 -+ sqrt 6), weights (3 +- sqrt 6)/12). */
-enum { POND_LATTICE_D2Q16 = 16 };
+ * (abscissae +-sqrt(3 -+ sqrt 6), weights (3 +- sqrt 6)/12), Grad order 3.
+ * D2Q25 = D1Q5 x D1Q5, the fifth-order rule (abscissae 0, +-sqrt(5 -+ sqrt 10),
+ * weights 8/15, (7 +- 2 sqrt 10)/60), Grad order 4: the frame transformation
+ * keeps the moments up to order four, which the non-translational split needs
+ * for f (Sec. II).  D2Q25 runs the cubic stencil with the total or the
+ * non-translational split (other combinations: POND_ERR_UNSUPPORTED). */
+enum { POND_LATTICE_D2Q16 = 16, POND_LATTICE_D2Q25 = 25 };
 
 /* Energy split: Eqs. Es.
  *   POND_SPLIT_TOTAL: g carries the total energy (Eq. total_energy_g,
@@ -79,7 +84,10 @@ enum { POND_LATTICE_D2Q16 = 16 };
  *     the node and grad u central differences of the neighbours' old frame
  *     velocities (the boundary rule of bc_x / bc_y picks the neighbours).
  *     With prandtl != 1, g relaxes at 1/tau_1 (its flux is the heat flux).
- *   POND_SPLIT_NONTRANS (Eq. nontrans_energy_g) returns POND_ERR_UNSUPPORTED. */
+ *   POND_SPLIT_NONTRANS: g carries the non-translational energy (Eq. nt_energy_g,
+ *     g^eq = (U'/rho) f^eq, U' = rho (c_v - 1) T); the energy is
+ *     E = sum (g + |C_i|^2 f / 2).  Built with the paper's BGK only: prandtl
+ *     must be 1 (else POND_ERR_UNSUPPORTED). */
 enum { POND_SPLIT_TOTAL = 0, POND_SPLIT_INTERNAL = 1, POND_SPLIT_NONTRANS = 2 };
 
 /* Arithmetic of the step.  FP64: everything in double.  FP32: populations,
@@ -96,10 +104,11 @@ typedef struct {
     uint32_t struct_size;  /* = sizeof(pond_params); ABI guard */
     int32_t nx, ny;        /* nodes per axis, >= 1; ny == 1 is a quasi-1-D run */
     int32_t bc_x, bc_y;    /* POND_BC_* */
-    int32_t lattice;       /* POND_LATTICE_D2Q16 */
+    int32_t lattice;       /* POND_LATTICE_D2Q16 (default) or POND_LATTICE_D2Q25 */
     int32_t interp_points; /* 4 = cubic Lagrange (default); 3 = quadratic, the paper's
                               "2nd-order" stencil (end of Sec. "Streaming") */
-    int32_t split;         /* POND_SPLIT_TOTAL (default) or POND_SPLIT_INTERNAL */
+    int32_t split;         /* POND_SPLIT_TOTAL (default), POND_SPLIT_INTERNAL or
+                              POND_SPLIT_NONTRANS */
     int32_t precision;     /* POND_PREC_* */
     int32_t pc_max_iter;   /* predictor-corrector cap; <= 0 selects 32 */
     double tau;            /* relaxation time in lattice units, > 1/2; the discrete
@@ -180,8 +189,9 @@ POND_API pond_status pond_stats(pond_ctx *c, pond_stats_t *out);
 /* Wait for the context's stream and report device-side flags. */
 POND_API pond_status pond_synchronize(pond_ctx *c);
 
-/* Raw state, converted to double: f and g as 16 planes of nx*ny values
- * (plane i = velocity i = 4a + b with c_i = (c_a, c_b), c_a ascending), frame
+/* Raw state, converted to double: f and g as Q planes of nx*ny values (Q = the
+ * lattice, 16 or 25; plane i = velocity i = q1 a + b with c_i = (c_a, c_b),
+ * q1 = 4 or 5, c_a ascending), frame
  * as 3 planes (u_x, u_y, T), and the 2-vector reference velocity the FP32
  * moments are taken about (nullable).  Synchronises the stream. */
 POND_API pond_status pond_export_state(pond_ctx *c, double *f, double *g, double *frame, double *u_ref);

@@ -44,24 +44,24 @@ pond_status hip_fail(hipError_t e, const char *what) {
 
 const char *last_error() { return g_last_error.c_str(); }
 
-Layout layout_for(long long N, size_t psize) {
+Layout layout_for(long long N, size_t psize, int lattice) {
     Layout L;
-    L.pop_bytes = align_up(size_t(N) * 16 * psize);
+    L.pop_bytes = align_up(size_t(N) * size_t(lattice) * psize);
     L.frame_bytes = align_up(size_t(N) * sizeof(double));
     L.buf_bytes = 2 * L.pop_bytes + 3 * L.frame_bytes;
-    L.mom_bytes = align_up(size_t(N) * 20 * psize);
+    L.mom_bytes = align_up(size_t(N) * moment_values(lattice, psize == 8) * psize);
     L.cnt_off = 2 * L.buf_bytes + L.mom_bytes;
     L.scratch_off = L.cnt_off + align_up(sizeof(DevCounters));
     L.total = L.scratch_off + align_up(kScratchDoubles * sizeof(double));
     return L;
 }
 
-int lds_nodes_for_blocks(int blocks_per_cu, bool dbl) {
+int lds_nodes_for_blocks(int blocks_per_cu, bool dbl, int lattice) {
     // one KiB per block stays free for the kernels' static shared memory and
     // the allocation granularity
     if (blocks_per_cu < 1) blocks_per_cu = 1;
     const int bytes = 160 * 1024 / blocks_per_cu - 1024;
-    return bytes / (dbl ? 160 : 80);
+    return bytes / (moment_values(lattice, dbl) * (dbl ? 8 : 4));
 }
 
 pond_status check_ctx(const pond_ctx *c, bool need_init) {
@@ -102,25 +102,29 @@ pond_status validate(const pond_params *p) {
     if ((p->bc_x != POND_BC_PERIODIC && p->bc_x != POND_BC_CLAMP) ||
         (p->bc_y != POND_BC_PERIODIC && p->bc_y != POND_BC_CLAMP))
         return fail(POND_ERR_INVALID_ARG, "bc_x / bc_y must be POND_BC_PERIODIC or POND_BC_CLAMP");
-    if (p->lattice != POND_LATTICE_D2Q16) {
-        if (p->lattice == 25 || p->lattice == 9)
-            return fail(POND_ERR_UNSUPPORTED, "lattice %d is not implemented (D2Q16 only)",
-                        p->lattice);
+    if (p->lattice != POND_LATTICE_D2Q16 && p->lattice != POND_LATTICE_D2Q25) {
+        if (p->lattice == 9)
+            return fail(POND_ERR_UNSUPPORTED, "lattice 9 is not implemented (D2Q16, D2Q25)");
         return fail(POND_ERR_INVALID_ARG, "unknown lattice %d", p->lattice);
     }
     if (p->interp_points != 3 && p->interp_points != 4)
         return fail(POND_ERR_INVALID_ARG, "interp_points must be 3 or 4");
-    if (p->split != POND_SPLIT_TOTAL && p->split != POND_SPLIT_INTERNAL) {
-        if (p->split == POND_SPLIT_NONTRANS)
-            return fail(POND_ERR_UNSUPPORTED, "the non-translational split is not implemented");
+    if (p->split != POND_SPLIT_TOTAL && p->split != POND_SPLIT_INTERNAL &&
+        p->split != POND_SPLIT_NONTRANS)
         return fail(POND_ERR_INVALID_ARG, "unknown split %d", p->split);
-    }
     if (p->precision != POND_PREC_FP64 && p->precision != POND_PREC_FP32)
         return fail(POND_ERR_INVALID_ARG, "unknown precision %d", p->precision);
     if (!(p->tau > 0.5) || !std::isfinite(p->tau))
         return fail(POND_ERR_INVALID_ARG, "tau must be finite and > 1/2");
     if (!(p->prandtl > 0.0) || !std::isfinite(p->prandtl))
         return fail(POND_ERR_INVALID_ARG, "prandtl must be finite and > 0");
+    if (p->split == POND_SPLIT_NONTRANS && p->prandtl != 1.0)
+        return fail(POND_ERR_UNSUPPORTED,
+                    "the non-translational split is built with Pr = 1 (the paper's BGK) only");
+    if (p->lattice == POND_LATTICE_D2Q25 && p->split == POND_SPLIT_INTERNAL)
+        return fail(POND_ERR_UNSUPPORTED, "D2Q25 runs the total or non-translational split");
+    if (p->lattice == POND_LATTICE_D2Q25 && p->interp_points != 4)
+        return fail(POND_ERR_UNSUPPORTED, "D2Q25 runs the cubic stencil (interp_points = 4)");
     if (!(p->gamma > 1.0) || !(p->gamma <= 2.0))
         return fail(POND_ERR_INVALID_ARG, "gamma must lie in (1, 2]");
     if (!std::isfinite(p->pc_tol)) return fail(POND_ERR_INVALID_ARG, "pc_tol must be finite");
@@ -159,6 +163,7 @@ void fill_args(pond_ctx *c) {
     a.omega1 = 1.0 / tau1;
     a.unit_prandtl = p.prandtl == 1.0;
     a.split = p.split;
+    a.lattice = p.lattice;
     a.cv = 1.0 / (p.gamma - 1.0);
     a.uref_x = a.uref_y = 0.0;
 }
@@ -169,9 +174,9 @@ bool fp64(const pond_ctx *c) { return c->p.precision == POND_PREC_FP64; }
 // one in FP64 with the cubic stencil); the LDS of a CU is split between the
 // blocks that fit by registers.  A 32 x 8 tile at T = 1, Mach 2 needs a
 // 40 x 16 source region.
-int default_lds_nodes(int tile, bool dbl, int np, int split) {
-    return lds_nodes_for_blocks(tiled_blocks_per_cu(dbl, np, split, static_cast<TileShape>(tile)),
-                                dbl);
+int default_lds_nodes(int tile, bool dbl, int np, int split, int lattice) {
+    return lds_nodes_for_blocks(
+        tiled_blocks_per_cu(lattice, dbl, np, split, static_cast<TileShape>(tile)), dbl, lattice);
 }
 
 int halo_for(int tile, int cap, bool single_row) {
@@ -188,11 +193,13 @@ pond_tuning default_tuning(const pond_params &p) {
     else
         t.tile = POND_TILE_32x8;
     t.lds_nodes =
-        default_lds_nodes(t.tile, p.precision == POND_PREC_FP64, p.interp_points, p.split);
+        default_lds_nodes(t.tile, p.precision == POND_PREC_FP64, p.interp_points, p.split,
+                          p.lattice);
     // FP64 moments take twice the LDS: measured at 512^2, Mach 2, one 32 x 8
     // block per CU holding its whole 40 x 16 source region beats two blocks
     // that fall back to HBM for part of the taps (527 vs 323 MLUPS)
-    if (p.precision == POND_PREC_FP64 && p.ny >= 8) t.lds_nodes = lds_nodes_for_blocks(1, true);
+    if (p.precision == POND_PREC_FP64 && p.ny >= 8 && p.lattice == POND_LATTICE_D2Q16)
+        t.lds_nodes = lds_nodes_for_blocks(1, true);
     t.batch_tile_width = 0;
     return t;
 }
@@ -204,8 +211,9 @@ pond_status apply_tuning(pond_ctx *c, const pond_tuning &t) {
         return fail(POND_ERR_INVALID_ARG, "unknown tile %d", t.tile);
     pond_tuning u = t;
     if (u.lds_nodes <= 0)
-        u.lds_nodes = default_lds_nodes(u.tile, fp64(c), c->p.interp_points, c->p.split);
-    const size_t bytes = size_t(u.lds_nodes) * 20 * c->psize;
+        u.lds_nodes =
+            default_lds_nodes(u.tile, fp64(c), c->p.interp_points, c->p.split, c->p.lattice);
+    const size_t bytes = size_t(u.lds_nodes) * moment_values(c->p.lattice, fp64(c)) * c->psize;
     if (bytes > 160 * 1024)
         return fail(POND_ERR_INVALID_ARG, "lds_nodes %d needs %zu bytes of LDS (> 160 KiB)",
                     u.lds_nodes, bytes);
@@ -318,7 +326,7 @@ pond_status pond_params_default(pond_params *p) {
 size_t pond_state_bytes(const pond_params *p) {
     if (validate(p) != POND_OK) return 0;
     const size_t psize = p->precision == POND_PREC_FP64 ? sizeof(double) : sizeof(float);
-    return layout_for((long long)p->nx * p->ny, psize).total;
+    return layout_for((long long)p->nx * p->ny, psize, p->lattice).total;
 }
 
 pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem,
@@ -329,7 +337,7 @@ pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem
     if (s != POND_OK) return s;
     const size_t psize = p->precision == POND_PREC_FP64 ? sizeof(double) : sizeof(float);
     const long long N = (long long)p->nx * p->ny;
-    Layout L = layout_for(N, psize);
+    Layout L = layout_for(N, psize, p->lattice);
     if (device_mem) {
         if (device_mem_bytes < L.total)
             return fail(POND_ERR_OUT_OF_MEMORY, "device_mem holds %zu bytes, %zu needed",
@@ -555,6 +563,7 @@ pond_status pond_export_state(pond_ctx *c, double *f, double *g, double *frame, 
     if (s != POND_OK) return s;
     if (!f || !g || !frame) return fail(POND_ERR_INVALID_ARG, "output pointer is NULL");
     const long long N = c->args.N;
+    const long long Q = c->p.lattice;  // planes per distribution
     const bool dev = is_device_pointer(f) && is_device_pointer(g) && is_device_pointer(frame);
     hipError_t e;
     if (dev) {
@@ -564,22 +573,22 @@ pond_status pond_export_state(pond_ctx *c, double *f, double *g, double *frame, 
     } else {
         // host destination: temporary device buffer (export is not on the hot path)
         double *tmp = nullptr;
-        e = hipMalloc(&tmp, size_t(N) * 35 * sizeof(double));
+        e = hipMalloc(&tmp, size_t(N) * (2 * Q + 3) * sizeof(double));
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return fail(POND_ERR_OUT_OF_MEMORY, "temporary export buffer");
         }
-        e = fp64(c) ? launch_export<double>(c->args, c->buf[c->cur], tmp, tmp + 16 * N,
-                                            tmp + 32 * N, c->stream)
-                    : launch_export<float>(c->args, c->buf[c->cur], tmp, tmp + 16 * N, tmp + 32 * N,
+        e = fp64(c) ? launch_export<double>(c->args, c->buf[c->cur], tmp, tmp + Q * N,
+                                            tmp + 2 * Q * N, c->stream)
+                    : launch_export<float>(c->args, c->buf[c->cur], tmp, tmp + Q * N, tmp + 2 * Q * N,
                                            c->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(f, tmp, size_t(N) * 16 * sizeof(double), hipMemcpyDefault, c->stream);
+            e = hipMemcpyAsync(f, tmp, size_t(N) * Q * sizeof(double), hipMemcpyDefault, c->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(g, tmp + 16 * N, size_t(N) * 16 * sizeof(double), hipMemcpyDefault,
+            e = hipMemcpyAsync(g, tmp + Q * N, size_t(N) * Q * sizeof(double), hipMemcpyDefault,
                                c->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(frame, tmp + 32 * N, size_t(N) * 3 * sizeof(double),
+            e = hipMemcpyAsync(frame, tmp + 2 * Q * N, size_t(N) * 3 * sizeof(double),
                                hipMemcpyDefault, c->stream);
         hipError_t e2 = hipStreamSynchronize(c->stream);
         (void)hipFree(tmp);
@@ -600,22 +609,23 @@ pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, con
     if ((s = check_unbatched(c)) != POND_OK) return s;
     if (!f || !g || !frame) return fail(POND_ERR_INVALID_ARG, "input pointer is NULL");
     const long long N = c->args.N;
+    const long long Q = c->p.lattice;  // planes per distribution
     const bool dev = is_device_pointer(f) && is_device_pointer(g) && is_device_pointer(frame);
     double *tmp = nullptr;
     const double *df = f, *dg = g, *dfr = frame;
     hipError_t e;
     if (!dev) {
-        e = hipMalloc(&tmp, size_t(N) * 35 * sizeof(double));
+        e = hipMalloc(&tmp, size_t(N) * (2 * Q + 3) * sizeof(double));
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return fail(POND_ERR_OUT_OF_MEMORY, "temporary import buffer");
         }
-        e = hipMemcpyAsync(tmp, f, size_t(N) * 16 * sizeof(double), hipMemcpyDefault, c->stream);
+        e = hipMemcpyAsync(tmp, f, size_t(N) * Q * sizeof(double), hipMemcpyDefault, c->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(tmp + 16 * N, g, size_t(N) * 16 * sizeof(double), hipMemcpyDefault,
+            e = hipMemcpyAsync(tmp + Q * N, g, size_t(N) * Q * sizeof(double), hipMemcpyDefault,
                                c->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(tmp + 32 * N, frame, size_t(N) * 3 * sizeof(double),
+            e = hipMemcpyAsync(tmp + 2 * Q * N, frame, size_t(N) * 3 * sizeof(double),
                                hipMemcpyDefault, c->stream);
         if (e != hipSuccess) {
             (void)hipStreamSynchronize(c->stream);
@@ -623,8 +633,8 @@ pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, con
             return hip_fail(e, "import copy");
         }
         df = tmp;
-        dg = tmp + 16 * N;
-        dfr = tmp + 32 * N;
+        dg = tmp + Q * N;
+        dfr = tmp + 2 * Q * N;
     }
     c->initialized = false;
     c->failed = false;

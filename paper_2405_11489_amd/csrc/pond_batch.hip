@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(
     const int lg = mem[i].lg, tiles_x = mem[i].tiles_x;
     const int lt = t - mem[i].tile_off;
     const int par = mem[i].parity0 ^ flip;
-    tile_step<P, NP, S>(a, mem[i].buf[par], static_cast<const P *>(mem[i].mom), mem[i].buf[par ^ 1],
+    tile_step<P, NP, S, D2Q16>(a, mem[i].buf[par], static_cast<const P *>(mem[i].mom), mem[i].buf[par ^ 1],
                      mem[i].cnt, reinterpret_cast<P *>(smem_raw), cap, (lt % tiles_x) << lg,
                      (lt / tiles_x) * (kBatchThreads >> lg), Shape256{lg}, red);
 }
@@ -243,6 +243,9 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
         if (!c->initialized) return fail(POND_ERR_STATE, "context %d has no state", i);
         if (c->failed) return fail(POND_ERR_STATE, "context %d is in the error state", i);
         if (c->batch) return fail(POND_ERR_STATE, "context %d already belongs to a batch", i);
+        if (c->p.lattice != POND_LATTICE_D2Q16 || c->p.split == POND_SPLIT_NONTRANS)
+            return fail(POND_ERR_UNSUPPORTED,
+                        "context %d: batches run D2Q16 with the total or internal split", i);
         if (c->p.precision != ctxs[0]->p.precision ||
             c->p.interp_points != ctxs[0]->p.interp_points || c->p.split != ctxs[0]->p.split)
             return fail(POND_ERR_INVALID_ARG,
@@ -572,9 +575,10 @@ pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out) {
     std::vector<Cand> cands;
     for (int tile : tiles) {
         cands.push_back({tile, 0});
-        const int blocks = tiled_blocks_per_cu(dbl, c->p.interp_points, c->p.split,
+        const int blocks = tiled_blocks_per_cu(c->p.lattice, dbl, c->p.interp_points, c->p.split,
                                                static_cast<TileShape>(tile));
-        if (blocks >= 2) cands.push_back({tile, lds_nodes_for_blocks(blocks - 1, dbl)});
+        if (blocks >= 2)
+            cands.push_back({tile, lds_nodes_for_blocks(blocks - 1, dbl, c->p.lattice)});
     }
     std::vector<double> tt(cands.size(), 1e300), tw(widths.size(), 1e300);
     for (int round = 0; round < 2 && s == POND_OK; ++round) {

@@ -24,20 +24,24 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // One context's device allocation:
 //   [state buffer 0 | state buffer 1 | moment planes | counters | scratch]
 struct Layout {
-    size_t pop_bytes;    // one set of 16 planes
+    size_t pop_bytes;    // one set of Q planes (Q = 16 or 25)
     size_t frame_bytes;  // one frame plane
     size_t buf_bytes;    // one state buffer
-    size_t mom_bytes;    // 20 moment planes
+    size_t mom_bytes;    // moment planes (2 NM values per node, padded to the groups)
     size_t cnt_off, scratch_off, total;
 };
 
 constexpr int kScratchDoubles = 3 * 256;
 
-Layout layout_for(long long N, size_t psize);
+// Values of a node's moment groups (2 NM moments, padded): 20 on D2Q16; on
+// D2Q25 32 floats or 30 doubles.
+inline int moment_values(int lattice, bool dbl) { return lattice == 25 ? (dbl ? 30 : 32) : 20; }
 
-// LDS nodes per block (20 moments of P each) that let blocks_per_cu blocks
-// share the 160 KiB of a CU.
-int lds_nodes_for_blocks(int blocks_per_cu, bool dbl);
+Layout layout_for(long long N, size_t psize, int lattice);
+
+// LDS nodes per block (the moment groups of one node each) that let
+// blocks_per_cu blocks share the 160 KiB of a CU.
+int lds_nodes_for_blocks(int blocks_per_cu, bool dbl, int lattice = 16);
 
 // Largest halo h of a tx x ty tile whose source region fits cap nodes:
 // (tx + 2h)(ty + 2h) <= cap, or tx + 2h <= cap for a single-row grid (whose

@@ -1,10 +1,12 @@
 // pond_device.h -- device-side lattice constants and per-node arithmetic of the
-// PonD f+g step (D2Q16, total-energy split).
+// PonD f+g step (lattices D2Q16 and D2Q25 of Table I).
 //
-// Moment ordering used everywhere on the device (10 per distribution):
-//   k : 0    1    2    3    4    5    6    7    8    9
-//  pq : 00   10   01   20   11   02   30   21   12   03
-// where M_pq = sum_i pop_i V_ix^p V_iy^q.  Device moments are taken about a
+// Moment ordering used everywhere on the device (10 per distribution on D2Q16,
+// orders 0..3; 15 on D2Q25, orders 0..4):
+//   k : 0    1    2    3    4    5    6    7    8    9    10   11   12   13   14
+//  pq : 00   10   01   20   11   02   30   21   12   03   40   31   22   13   04
+// where M_pq = sum_i pop_i V_ix^p V_iy^q (order n starts at k = n(n+1)/2, p
+// descending).  Device moments are taken about a
 // fixed per-instance reference velocity u_ref (V = C - u_ref), which keeps the
 // float planes free of the cancellation a Mach-2 background would cause; any
 // fixed origin gives the same transform.
@@ -63,6 +65,172 @@ constexpr VelocityTables make_velocity_tables() {
         }
     }
     return t;
+}
+
+// ---------------------------------------------------------------- lattices
+// Table I, D1Q5 (rT_L = 1): abscissae -c_out, -c_in, 0, c_in, c_out with
+// c_in = sqrt(5 - sqrt 10), c_out = sqrt(5 + sqrt 10); weights 8/15 at 0,
+// (7 + 2 sqrt 10)/60 on the inner pair, (7 - 2 sqrt 10)/60 on the outer pair.
+constexpr double kC5in = 1.3556261799742657;
+constexpr double kC5out = 2.8569700138728056;
+constexpr double kW5zero = 0.53333333333333333;
+constexpr double kW5in = 0.22207592200561266;
+constexpr double kW5out = 0.011257411327720682;
+
+// Lattice traits: Q1 points per axis, Q = Q1^2 velocities (i = Q1 a + b,
+// c_i = (c(a), c(b))), Grad order N = Q1 - 1 with NM = (N + 1)(N + 2)/2
+// moments / coefficients per distribution.
+struct D2Q16 {
+    static constexpr int Q1 = 4, Q = 16, N = 3, NM = 10;
+    __host__ __device__ static constexpr double c(int a) { return c1(a); }
+    __host__ __device__ static constexpr double w(int a) { return w1(a); }
+};
+struct D2Q25 {
+    static constexpr int Q1 = 5, Q = 25, N = 4, NM = 15;
+    __host__ __device__ static constexpr double c(int a) {
+        return a == 0 ? -kC5out : (a == 1 ? -kC5in : (a == 2 ? 0.0 : (a == 3 ? kC5in : kC5out)));
+    }
+    __host__ __device__ static constexpr double w(int a) {
+        return (a == 0 || a == 4) ? kW5out : (a == 2 ? kW5zero : kW5in);
+    }
+};
+
+// Index k of the moment with exponents (p, q) (orders up to 4), and back.
+__host__ __device__ constexpr int mom_index(int p, int q) {
+    return (p + q) * (p + q + 1) / 2 + q;
+}
+__host__ __device__ constexpr int mom_order(int k) {
+    return k < 1 ? 0 : (k < 3 ? 1 : (k < 6 ? 2 : (k < 10 ? 3 : 4)));
+}
+__host__ __device__ constexpr int mom_py(int k) {
+    return k - mom_order(k) * (mom_order(k) + 1) / 2;
+}
+__host__ __device__ constexpr int mom_px(int k) { return mom_order(k) - mom_py(k); }
+
+// Coefficient of x^p in the probabilists' Hermite polynomial He_n(x), n <= 4:
+// He_0 = 1, He_1 = x, He_2 = x^2 - 1, He_3 = x^3 - 3x, He_4 = x^4 - 6x^2 + 3.
+__host__ __device__ constexpr double he_coef(int n, int p) {
+    return p == n ? 1.0
+         : (n == 2 && p == 0) ? -1.0
+         : (n == 3 && p == 1) ? -3.0
+         : (n == 4 && p == 2) ? -6.0
+         : (n == 4 && p == 0) ? 3.0
+         : 0.0;
+}
+__host__ __device__ constexpr double he_value(int n, double x) {
+    return he_coef(n, 0) + x * (he_coef(n, 1) + x * (he_coef(n, 2) + x * (he_coef(n, 3) +
+                                                                            x * he_coef(n, 4))));
+}
+// n! and C(n, k) for n <= 4
+__host__ __device__ constexpr double factorial_c(int n) {
+    return n <= 1 ? 1.0 : (n == 2 ? 2.0 : (n == 3 ? 6.0 : 24.0));
+}
+__host__ __device__ constexpr double binom_c(int n, int k) {
+    return factorial_c(n) / (factorial_c(k) * factorial_c(n - k));
+}
+
+// Reconstruction tables of a lattice (the D2Q16 tables above, written for any
+// order): herm[i][k(a,b)] = w_i He_a(c_ix) He_b(c_iy) / (a! b!), so that
+// pop_i = sum_k herm[i][k] A_k for Hermite coefficients A_ab; recon[i][k(p,q)]
+// = sum_{a >= p, b >= q} herm[i][k(a,b)] he_a[p] he_b[q], the same
+// reconstruction on the normalised central moments m_pq.
+template <class L>
+struct LatticeTables {
+    double recon[L::Q][L::NM];
+    double herm[L::Q][L::NM];
+};
+
+template <class L>
+constexpr LatticeTables<L> make_lattice_tables() {
+    LatticeTables<L> t{};
+    for (int i = 0; i < L::Q; ++i) {
+        const double cx = L::c(i / L::Q1), cy = L::c(i % L::Q1);
+        const double w = L::w(i / L::Q1) * L::w(i % L::Q1);
+        for (int k = 0; k < L::NM; ++k) {
+            const int a = mom_px(k), b = mom_py(k);
+            t.herm[i][k] = w * he_value(a, cx) * he_value(b, cy) / (factorial_c(a) * factorial_c(b));
+        }
+        for (int k = 0; k < L::NM; ++k) {
+            const int p = mom_px(k), q = mom_py(k);
+            double r = 0.0;
+            for (int j = 0; j < L::NM; ++j) {
+                const int a = mom_px(j), b = mom_py(j);
+                if (a >= p && b >= q) r += t.herm[i][j] * he_coef(a, p) * he_coef(b, q);
+            }
+            t.recon[i][k] = r;
+        }
+    }
+    return t;
+}
+
+template <typename P, class L>
+struct LatticeTablesP {
+    P recon[L::Q][L::NM];
+    P herm[L::Q][L::NM];
+};
+
+template <typename P, class L>
+constexpr LatticeTablesP<P, L> make_lattice_tables_p() {
+    const LatticeTables<L> d = make_lattice_tables<L>();
+    LatticeTablesP<P, L> t{};
+    for (int i = 0; i < L::Q; ++i)
+        for (int k = 0; k < L::NM; ++k) {
+            t.recon[i][k] = P(d.recon[i][k]);
+            t.herm[i][k] = P(d.herm[i][k]);
+        }
+    return t;
+}
+
+// Generic order-N versions of central_normalised / hermite_from_central (the
+// D2Q16 ones below are written out for N = 3).
+// m_pq = is^(p+q) sum_{r<=p, t<=q} C(p,r) C(q,t) (-dx)^(p-r) (-dy)^(q-t) M_rt.
+template <class L, typename P>
+__device__ __forceinline__ void central_normalised_n(const P M[L::NM], P dx, P dy, P is,
+                                                     P m[L::NM]) {
+    constexpr int N = L::N;
+    P ex[N + 1], ey[N + 1], sc[N + 1];
+    ex[0] = ey[0] = sc[0] = P(1);
+#pragma unroll
+    for (int j = 1; j <= N; ++j) {
+        ex[j] = ex[j - 1] * (-dx);
+        ey[j] = ey[j - 1] * (-dy);
+        sc[j] = sc[j - 1] * is;
+    }
+    // shift in x: T[p][t] = sum_r C(p,r) ex^(p-r) M[r][t]
+    P T[L::NM];
+#pragma unroll
+    for (int k = 0; k < L::NM; ++k) {
+        const int p = mom_px(k), t = mom_py(k);
+        P acc = P(0);
+#pragma unroll
+        for (int r = 0; r <= p; ++r) acc += P(binom_c(p, r)) * ex[p - r] * M[mom_index(r, t)];
+        T[k] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < L::NM; ++k) {
+        const int p = mom_px(k), q = mom_py(k);
+        P acc = P(0);
+#pragma unroll
+        for (int t = 0; t <= q; ++t) acc += P(binom_c(q, t)) * ey[q - t] * T[mom_index(p, t)];
+        m[k] = acc * sc[p + q];
+    }
+}
+
+// A_ab = sum_{p<=a, q<=b} he_a[p] he_b[q] m_pq.
+template <class L, typename P>
+__device__ __forceinline__ void hermite_from_central_n(const P m[L::NM], P A[L::NM]) {
+#pragma unroll
+    for (int k = 0; k < L::NM; ++k) {
+        const int a = mom_px(k), b = mom_py(k);
+        P acc = P(0);
+#pragma unroll
+        for (int j = 0; j < L::NM; ++j) {
+            const int p = mom_px(j), q = mom_py(j);
+            if (p <= a && q <= b && he_coef(a, p) != 0.0 && he_coef(b, q) != 0.0)
+                acc += P(he_coef(a, p) * he_coef(b, q)) * m[j];
+        }
+        A[k] = acc;
+    }
 }
 
 template <typename P>

@@ -12,7 +12,7 @@ namespace pond {
 // Device state of one instance.  Population planes: pop[i * N + n] for
 // velocity i and node n = y * nx + x.  Frame planes: double ux, uy, T.
 struct DevState {
-    void *f, *g;          // 16 planes each (float or double)
+    void *f, *g;          // Q planes each (float or double), Q = 16 or 25
     double *ux, *uy, *T;  // frame
 };
 
@@ -35,7 +35,9 @@ struct StepArgs {
     double omega;        // 1 / tau
     double omega1;       // 1 / tau_1 (Fourier part of the energy flux)
     int unit_prandtl;    // 1: plain BGK for g
-    int split;           // 0: total energy in g; 1: internal energy in g (plus its source)
+    int split;           // 0: total energy in g; 1: internal energy in g (plus its source);
+                         // 2: non-translational energy in g
+    int lattice;         // 16 (D2Q16) or 25 (D2Q25)
     double cv;           // 1 / (gamma - 1)
     double uref_x, uref_y;
 };
@@ -62,13 +64,13 @@ inline void tile_dims(TileShape s, int &tx, int &ty) {
     tx = ty = 0;
 }
 
-// Blocks of the tiled step kernel (precision, stencil, energy split, shape)
-// that fit one CU by registers and waves alone (no dynamic LDS).
-int tiled_blocks_per_cu(bool dbl, int np, int split, TileShape shape);
+// Blocks of the tiled step kernel (lattice, precision, stencil, energy split,
+// shape) that fit one CU by registers and waves alone (no dynamic LDS).
+int tiled_blocks_per_cu(int lattice, bool dbl, int np, int split, TileShape shape);
 
 // Calls f(np, split) with both as std::integral_constant (np: 3 or 4 stencil
 // points per axis, split: 0 total, 1 internal energy), so kernels can be
-// picked by compile-time variant.
+// picked by compile-time variant.  The batched path's variants (D2Q16).
 template <class F>
 inline auto with_variant(int np, int split, F &&f) {
     using std::integral_constant;
@@ -77,6 +79,24 @@ inline auto with_variant(int np, int split, F &&f) {
                           : f(integral_constant<int, 3>{}, integral_constant<int, 0>{});
     return split == 1 ? f(integral_constant<int, 4>{}, integral_constant<int, 1>{})
                       : f(integral_constant<int, 4>{}, integral_constant<int, 0>{});
+}
+
+// The single-instance variants of a lattice: D2Q16 takes both stencils and the
+// three energy splits (0 total, 1 internal, 2 non-translational); D2Q25 the
+// cubic stencil with the total or non-translational split (the API rejects
+// other combinations before a launch).
+template <class L, class F>
+inline auto with_lattice_variant(int np, int split, F &&f) {
+    using std::integral_constant;
+    if constexpr (L::Q == 16) {
+        if (split == 2)
+            return np == 3 ? f(integral_constant<int, 3>{}, integral_constant<int, 2>{})
+                           : f(integral_constant<int, 4>{}, integral_constant<int, 2>{});
+        return with_variant(np, split, static_cast<F &&>(f));
+    } else {
+        return split == 2 ? f(integral_constant<int, 4>{}, integral_constant<int, 2>{})
+                          : f(integral_constant<int, 4>{}, integral_constant<int, 0>{});
+    }
 }
 
 template <typename P>

@@ -1,214 +1,29 @@
-// pond_kernels.hip -- HIP kernels of the PonD f+g step for gfx950 (MI355X).
+// pond_kernels.hip -- HIP kernels of the PonD f+g step for gfx950 (MI355X):
+// the D2Q16 instantiation of the lattice-dependent kernels
+// (pond_lattice_kernels.h; D2Q25 in pond_kernels25.hip), the launchers that
+// pick the lattice, and the lattice-independent reductions.
 //
 // One kernel source, instantiated for P = double (FP64 mode) and P = float
 // (FP32 mode: populations, moments, interpolation and frame transformation in
 // float; conserved sums, temperature recovery and the predictor-corrector test
 // in double).
-//
-// Step = two launches on one stream:
-//   1. moments pre-pass: per node, the 10 + 10 moments up to order three of f
-//      and g (Eq. genericMomentUptoO3) about the instance's reference velocity,
-//      written as 20 planes;
-//   2. step: per destination node (one lane), the predictor-corrector loop
-//      (gather -> conserved sums -> new frame -> convergence test, wave exits
-//      when every lane has converged), then re-projection onto the frame of
-//      the gathered moments and BGK relaxation in Grad-coefficient space, and
-//      the store of f*, g* and the frame into the other state buffer.
-// The gather evaluates Eq. propagationInterpolated through linearity: the
-// moments of the stencil nodes are interpolated at the departure point and the
-// frame transformation is applied once to the interpolated moments, instead of
-// transforming every stencil node first (the two agree to rounding).
-#include "pond_tile.h"
+#include "pond_lattice_kernels.h"
 
 namespace pond {
 
+template struct Launch<float, D2Q16>;
+template struct Launch<double, D2Q16>;
+extern template struct Launch<float, D2Q25>;
+extern template struct Launch<double, D2Q25>;
+
 namespace {
 
-constexpr int kBlock = 256;
-
-template <typename P>
-__device__ __forceinline__ P *plane(void *base, int i, long long N) {
-    return static_cast<P *>(base) + (long long)i * N;
-}
-template <typename P>
-__device__ __forceinline__ const P *plane(const void *base, int i, long long N) {
-    return static_cast<const P *>(base) + (long long)i * N;
-}
-
-// ---------------------------------------------------------------- init ----
-template <typename P>
-__global__ __launch_bounds__(kBlock) void init_kernel(StepArgs a, const double *__restrict__ rho,
-                                                      const double *__restrict__ ux,
-                                                      const double *__restrict__ uy,
-                                                      const double *__restrict__ T, DevState st,
-                                                      DevCounters *cnt) {
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= a.N) return;
-    const double r = rho[n], vx = ux[n], vy = uy[n], t = T[n];
-    const bool ok = (r > 0.0) && (t > 0.0) && isfinite(r) && isfinite(t) && isfinite(vx) &&
-                    isfinite(vy);
-    if (!ok) {
-        atomicAdd(&cnt->init_rejected, 1ull);
-        return;
-    }
-    const double s = sqrt(t);
-    // total split: g^eq uses the lab velocity C_i; internal split: C_i - u
-    const double ox = a.split ? 0.0 : vx, oy = a.split ? 0.0 : vy;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const double w = w1(i / 4) * w1(i % 4);
-        const double Cx = s * c1(i / 4) + ox, Cy = s * c1(i % 4) + oy;
-        plane<P>(st.f, i, a.N)[n] = P(r * w);
-        plane<P>(st.g, i, a.N)[n] = P(w * (r * (a.cv - 1.0) * t + 0.5 * r * (Cx * Cx + Cy * Cy)));
-    }
-    st.ux[n] = vx;
-    st.uy[n] = vy;
-    st.T[n] = t;
-}
-
-// ---------------------------------------------------- moments pre-pass ----
-// Moments up to order three of f and g of every node (Eq. genericMomentUptoO3),
-// about u_ref, stored as grouped planes.
-template <typename P>
-__global__ __launch_bounds__(kBlock) void moments_kernel(StepArgs a, DevState st,
-                                                         P *__restrict__ mom) {
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= a.N) return;
-    node_moments<P>(a, st, mom, n);
-}
-
-// ----------------------------------------------------- step (global taps) ----
-// Reference step kernel: one lane per node in row-major order, taps read
-// straight from the HBM moment planes.
-template <typename P, int NP, int S>
-__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
-                                                      const P *__restrict__ mom, DevState dst,
-                                                      DevCounters *cnt) {
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = n < a.N;
-    int x = 0, y = 0;
-    double l0 = 0.0, l1 = 0.0, l2 = 1.0;
-    if (live) {
-        x = int(n % a.nx);
-        y = int(n / a.nx);
-        l0 = src.ux[n];
-        l1 = src.uy[n];
-        l2 = src.T[n];
-    }
-    const GlobalTaps<P, NP> taps{mom, a.N, a.nx, a.ny, a.bc_x, a.bc_y};
-    node_step<P, NP, S>(a, taps, x, y, n, live, l0, l1, l2, src, dst, cnt);
-}
-
-// ------------------------------------------------------ step (LDS tiles) ----
-
-// Minimum waves per SIMD requested from the register allocator for the tiled
-// kernel (compile-time tuning; 0 keeps the defaults of step_min_waves).
-#ifndef POND_TILED_WAVES_PER_EU
-#define POND_TILED_WAVES_PER_EU 0
-#endif
-#define POND_TILED_ATTR(P, S)                                                            \
-    __attribute__((amdgpu_waves_per_eu(POND_TILED_WAVES_PER_EU > 0 ? POND_TILED_WAVES_PER_EU \
-                                                                   : step_min_waves<P, S>())))
-
-template <typename P, int NP, int S, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) POND_TILED_ATTR(P, S) void step_tiled_kernel(StepArgs a, DevState src,
-                                                            const P *__restrict__ mom,
-                                                            DevState dst, DevCounters *cnt,
-                                                            int cap, int tiles_x) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int red[16];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step<P, NP, S>(a, src, mom, dst, cnt, reinterpret_cast<P *>(smem_raw), cap,
-                     (tile % tiles_x) * TX, (tile / tiles_x) * TY, FixedShape<TX, TY>{}, red);
-}
-
-// ------------------------------------------------------ macroscopic ----
-template <typename P>
-__global__ __launch_bounds__(kBlock) void macro_kernel(StepArgs a, DevState st, double *rho,
-                                                       double *ux, double *uy, double *T,
-                                                       double *p) {
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= a.N) return;
-    const double s = sqrt(st.T[n]), vx = st.ux[n], vy = st.uy[n];
-    double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const double fi = double(plane<P>(st.f, i, a.N)[n]);
-        r += fi;
-        jx += fi * (s * c1(i / 4) + vx);
-        jy += fi * (s * c1(i % 4) + vy);
-        E += double(plane<P>(st.g, i, a.N)[n]);
-    }
-    const double t = (a.split ? E : E - (jx * jx + jy * jy) / (2.0 * r)) / (r * a.cv);
-    if (rho) rho[n] = r;
-    if (ux) ux[n] = jx / r;
-    if (uy) uy[n] = jy / r;
-    if (T) T[n] = t;
-    if (p) p[n] = r * t;
-}
-
-template <typename P>
-__global__ __launch_bounds__(kBlock) void export_kernel(StepArgs a, DevState st, double *f,
-                                                        double *g, double *frame) {
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= a.N) return;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        f[(long long)i * a.N + n] = double(plane<P>(st.f, i, a.N)[n]);
-        g[(long long)i * a.N + n] = double(plane<P>(st.g, i, a.N)[n]);
-    }
-    frame[n] = st.ux[n];
-    frame[a.N + n] = st.uy[n];
-    frame[2 * a.N + n] = st.T[n];
-}
-
-template <typename P>
-__global__ __launch_bounds__(kBlock) void import_kernel(StepArgs a, const double *f,
-                                                        const double *g, const double *frame,
-                                                        DevState st) {
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= a.N) return;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        plane<P>(st.f, i, a.N)[n] = P(f[(long long)i * a.N + n]);
-        plane<P>(st.g, i, a.N)[n] = P(g[(long long)i * a.N + n]);
-    }
-    st.ux[n] = frame[n];
-    st.uy[n] = frame[a.N + n];
-    st.T[n] = frame[2 * a.N + n];
-}
+using lk::kBlock;
+using lk::grid_for;
+using lk::partial_sums_kernel;
 
 // ------------------------------------------- deterministic reductions ----
 constexpr int kRedBlocks = 256;
-
-// per-block sums of (rho, rho ux, rho uy) over a fixed contiguous chunk
-template <typename Loader>
-__global__ __launch_bounds__(kBlock) void partial_sums_kernel(long long N, Loader ld,
-                                                              double *scratch) {
-    __shared__ double sh[3][kBlock];
-    const long long chunk = (N + gridDim.x - 1) / gridDim.x;
-    const long long lo = (long long)blockIdx.x * chunk;
-    const long long hi = lo + chunk < N ? lo + chunk : N;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (long long n = lo + threadIdx.x; n < hi; n += blockDim.x) {
-        double r, jx, jy;
-        ld(n, r, jx, jy);
-        s0 += r;
-        s1 += jx;
-        s2 += jy;
-    }
-    sh[0][threadIdx.x] = s0;
-    sh[1][threadIdx.x] = s1;
-    sh[2][threadIdx.x] = s2;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int c = 0; c < 3; ++c) scratch[blockIdx.x * 3 + c] = sh[c][0];
-}
 
 __global__ void final_sums_kernel(const double *scratch, int nblocks, DevCounters *cnt) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -262,142 +77,62 @@ struct FieldLoader {
     }
 };
 
-template <typename P>
-struct StateLoader {
-    DevState st;
-    long long N;
-    __device__ void operator()(long long n, double &r, double &jx, double &jy) const {
-        const double s = sqrt(st.T[n]);
-        r = jx = jy = 0.0;
-        for (int i = 0; i < kQ; ++i) {
-            const double fi = double(static_cast<const P *>(st.f)[(long long)i * N + n]);
-            r += fi;
-            jx += fi * (s * c1(i / 4) + st.ux[n]);
-            jy += fi * (s * c1(i % 4) + st.uy[n]);
-        }
-    }
-};
-
-unsigned grid_for(long long N) { return unsigned((N + kBlock - 1) / kBlock); }
-
 }  // namespace
 
 template <typename P>
 hipError_t launch_init(const StepArgs &a, const double *rho, const double *ux, const double *uy,
                        const double *T, DevState st, DevCounters *cnt, hipStream_t s) {
-    hipLaunchKernelGGL(init_kernel<P>, dim3(grid_for(a.N)), dim3(kBlock), 0, s, a, rho, ux, uy, T,
-                       st, cnt);
-    return hipGetLastError();
+    return a.lattice == 25 ? Launch<P, D2Q25>::init(a, rho, ux, uy, T, st, cnt, s)
+                           : Launch<P, D2Q16>::init(a, rho, ux, uy, T, st, cnt, s);
 }
 
 template <typename P>
 hipError_t launch_moments_prepass(const StepArgs &a, DevState st, P *mom, hipStream_t s) {
-    hipLaunchKernelGGL(moments_kernel<P>, dim3(grid_for(a.N)), dim3(kBlock), 0, s, a, st, mom);
-    return hipGetLastError();
+    return a.lattice == 25 ? Launch<P, D2Q25>::moments(a, st, mom, s)
+                           : Launch<P, D2Q16>::moments(a, st, mom, s);
 }
 
 template <typename P>
 hipError_t launch_step(const StepArgs &a, DevState src, const P *mom, DevState dst,
                        DevCounters *cnt, hipStream_t s) {
-    return with_variant(a.interp_points, a.split, [&](auto np, auto sp) {
-        hipLaunchKernelGGL((step_kernel<P, np(), sp()>), dim3(grid_for(a.N)), dim3(kBlock), 0, s, a,
-                           src, mom, dst, cnt);
-        return hipGetLastError();
-    });
+    return a.lattice == 25 ? Launch<P, D2Q25>::step(a, src, mom, dst, cnt, s)
+                           : Launch<P, D2Q16>::step(a, src, mom, dst, cnt, s);
 }
-
-namespace {
-
-template <typename P, int NP, int S, int TX, int TY>
-hipError_t launch_tiled_t(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
-                          DevState dst, DevCounters *cnt, hipStream_t s) {
-    auto kern = step_tiled_kernel<P, NP, S, TX, TY>;
-    const size_t lds = size_t(tc.cap) * kNMom * sizeof(P);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-    }
-    const int tiles_x = (a.nx + TX - 1) / TX, tiles_y = (a.ny + TY - 1) / TY;
-    hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y), dim3(TX * TY), lds, s, a, src, mom, dst, cnt,
-                       tc.cap, tiles_x);
-    return hipGetLastError();
-}
-
-template <typename P, int NP, int S>
-const void *tiled_kernel_ptr(TileShape shape) {
-    switch (shape) {
-    case TileShape::T16x16: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, 16, 16>);
-    case TileShape::T32x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, 32, 8>);
-    case TileShape::T16x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, 16, 8>);
-    case TileShape::T8x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, 8, 8>);
-    case TileShape::T256x1: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, 256, 1>);
-    case TileShape::T64x1: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, 64, 1>);
-    }
-    return nullptr;
-}
-
-template <typename P, int NP, int S>
-hipError_t launch_tiled_v(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
-                          DevState dst, DevCounters *cnt, hipStream_t s) {
-    switch (tc.shape) {
-    case TileShape::T16x16: return launch_tiled_t<P, NP, S, 16, 16>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T32x8: return launch_tiled_t<P, NP, S, 32, 8>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T16x8: return launch_tiled_t<P, NP, S, 16, 8>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T8x8: return launch_tiled_t<P, NP, S, 8, 8>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T256x1: return launch_tiled_t<P, NP, S, 256, 1>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T64x1: return launch_tiled_t<P, NP, S, 64, 1>(a, tc, src, mom, dst, cnt, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-}  // namespace
 
 template <typename P>
 hipError_t launch_step_tiled(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
                              DevState dst, DevCounters *cnt, hipStream_t s) {
-    return with_variant(a.interp_points, a.split, [&](auto np, auto sp) {
-        return launch_tiled_v<P, np(), sp()>(a, tc, src, mom, dst, cnt, s);
-    });
+    return a.lattice == 25 ? Launch<P, D2Q25>::step_tiled(a, tc, src, mom, dst, cnt, s)
+                           : Launch<P, D2Q16>::step_tiled(a, tc, src, mom, dst, cnt, s);
 }
 
-int tiled_blocks_per_cu(bool dbl, int np, int split, TileShape shape) {
-    const void *k = with_variant(np, split, [&](auto n, auto sp) {
-        return dbl ? tiled_kernel_ptr<double, n(), sp()>(shape)
-                   : tiled_kernel_ptr<float, n(), sp()>(shape);
-    });
-    int tx = 0, ty = 0;
-    tile_dims(shape, tx, ty);
-    int n = 0;
-    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, tx * ty, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        return 1;
-    }
-    return n < 1 ? 1 : n;
+int tiled_blocks_per_cu(int lattice, bool dbl, int np, int split, TileShape shape) {
+    if (lattice == 25)
+        return dbl ? Launch<double, D2Q25>::tiled_blocks_per_cu(np, split, shape)
+                   : Launch<float, D2Q25>::tiled_blocks_per_cu(np, split, shape);
+    return dbl ? Launch<double, D2Q16>::tiled_blocks_per_cu(np, split, shape)
+               : Launch<float, D2Q16>::tiled_blocks_per_cu(np, split, shape);
 }
 
 template <typename P>
 hipError_t launch_macro(const StepArgs &a, DevState st, double *rho, double *ux, double *uy,
                         double *T, double *p, hipStream_t s) {
-    hipLaunchKernelGGL(macro_kernel<P>, dim3(grid_for(a.N)), dim3(kBlock), 0, s, a, st, rho, ux,
-                       uy, T, p);
-    return hipGetLastError();
+    return a.lattice == 25 ? Launch<P, D2Q25>::macro(a, st, rho, ux, uy, T, p, s)
+                           : Launch<P, D2Q16>::macro(a, st, rho, ux, uy, T, p, s);
 }
 
 template <typename P>
 hipError_t launch_export(const StepArgs &a, DevState st, double *f, double *g, double *frame,
                          hipStream_t s) {
-    hipLaunchKernelGGL(export_kernel<P>, dim3(grid_for(a.N)), dim3(kBlock), 0, s, a, st, f, g,
-                       frame);
-    return hipGetLastError();
+    return a.lattice == 25 ? Launch<P, D2Q25>::exp(a, st, f, g, frame, s)
+                           : Launch<P, D2Q16>::exp(a, st, f, g, frame, s);
 }
 
 template <typename P>
 hipError_t launch_import(const StepArgs &a, const double *f, const double *g, const double *frame,
                          DevState st, hipStream_t s) {
-    hipLaunchKernelGGL(import_kernel<P>, dim3(grid_for(a.N)), dim3(kBlock), 0, s, a, f, g, frame,
-                       st);
-    return hipGetLastError();
+    return a.lattice == 25 ? Launch<P, D2Q25>::imp(a, f, g, frame, st, s)
+                           : Launch<P, D2Q16>::imp(a, f, g, frame, st, s);
 }
 
 hipError_t launch_mean_velocity(long long N, const double *rho, const double *ux, const double *uy,
@@ -423,8 +158,10 @@ template <typename P>
 hipError_t launch_state_mean_velocity(const StepArgs &a, DevState st, double *scratch,
                                       int scratch_len, DevCounters *cnt, hipStream_t s) {
     if (scratch_len < 3 * kRedBlocks) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(partial_sums_kernel<StateLoader<P>>, dim3(kRedBlocks), dim3(kBlock), 0, s,
-                       a.N, StateLoader<P>{st, a.N}, scratch);
+    hipError_t e = a.lattice == 25
+                       ? Launch<P, D2Q25>::state_partial_sums(a, st, scratch, kRedBlocks, s)
+                       : Launch<P, D2Q16>::state_partial_sums(a, st, scratch, kRedBlocks, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(final_sums_kernel, dim3(1), dim3(64), 0, s, scratch, kRedBlocks, cnt);
     return hipGetLastError();
 }

@@ -1,0 +1,383 @@
+// pond_lattice_kernels.h -- the kernels of the PonD f+g step that depend on the
+// lattice (D2Q16 or D2Q25), and their launchers, as templates over the
+// arithmetic type P and the lattice L.  pond_kernels.hip instantiates them for
+// D2Q16 and pond_kernels25.hip for D2Q25 (two translation units compiled in
+// parallel); the launchers are reached through Launch<P, L>.
+//
+// Step = two launches on one stream:
+//   1. moments pre-pass: per node, the moments of f and g up to the lattice's
+//      Grad order (Eq. genericMomentUptoO3) about the instance's reference
+//      velocity, written as grouped planes;
+//   2. step: per destination node (one lane), the predictor-corrector loop
+//      (gather -> conserved sums -> new frame -> convergence test, wave exits
+//      when every lane has converged), then re-projection onto the frame of
+//      the gathered moments and BGK relaxation in Grad-coefficient space, and
+//      the store of f*, g* and the frame into the other state buffer.
+// The gather evaluates Eq. propagationInterpolated through linearity: the
+// moments of the stencil nodes are interpolated at the departure point and the
+// frame transformation is applied once to the interpolated moments, instead of
+// transforming every stencil node first (the two agree to rounding).
+#pragma once
+
+#include "pond_tile.h"
+
+namespace pond {
+namespace lk {
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(long long N) { return unsigned((N + kBlock - 1) / kBlock); }
+
+template <typename P>
+__device__ __forceinline__ P *plane(void *base, int i, long long N) {
+    return static_cast<P *>(base) + (long long)i * N;
+}
+template <typename P>
+__device__ __forceinline__ const P *plane(const void *base, int i, long long N) {
+    return static_cast<const P *>(base) + (long long)i * N;
+}
+
+// ---------------------------------------------------------------- init ----
+// Equilibrium in each node's own frame: f_i = rho w_i; g_i = g_i^eq of the split
+// (total: lab velocity C_i; internal: C_i - u; non-translational: U'/rho only).
+template <typename P, class L>
+__global__ __launch_bounds__(kBlock) void init_kernel(StepArgs a, const double *__restrict__ rho,
+                                                      const double *__restrict__ ux,
+                                                      const double *__restrict__ uy,
+                                                      const double *__restrict__ T, DevState st,
+                                                      DevCounters *cnt) {
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= a.N) return;
+    const double r = rho[n], vx = ux[n], vy = uy[n], t = T[n];
+    const bool ok = (r > 0.0) && (t > 0.0) && isfinite(r) && isfinite(t) && isfinite(vx) &&
+                    isfinite(vy);
+    if (!ok) {
+        atomicAdd(&cnt->init_rejected, 1ull);
+        return;
+    }
+    const double s = sqrt(t);
+    // total split: g^eq uses the lab velocity C_i; internal split: C_i - u
+    const double ox = a.split ? 0.0 : vx, oy = a.split ? 0.0 : vy;
+    const double kin = a.split == 2 ? 0.0 : 0.5;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double w = L::w(i / L::Q1) * L::w(i % L::Q1);
+        const double Cx = s * L::c(i / L::Q1) + ox, Cy = s * L::c(i % L::Q1) + oy;
+        plane<P>(st.f, i, a.N)[n] = P(r * w);
+        plane<P>(st.g, i, a.N)[n] = P(w * (r * (a.cv - 1.0) * t + kin * r * (Cx * Cx + Cy * Cy)));
+    }
+    st.ux[n] = vx;
+    st.uy[n] = vy;
+    st.T[n] = t;
+}
+
+// ---------------------------------------------------- moments pre-pass ----
+template <typename P, class L>
+__global__ __launch_bounds__(kBlock) void moments_kernel(StepArgs a, DevState st,
+                                                         P *__restrict__ mom) {
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= a.N) return;
+    node_moments<P, L>(a, st, mom, n);
+}
+
+// ----------------------------------------------------- step (global taps) ----
+// Reference step kernel: one lane per node in row-major order, taps read
+// straight from the HBM moment planes.
+template <typename P, int NP, int S, class L>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
+                                                      const P *__restrict__ mom, DevState dst,
+                                                      DevCounters *cnt) {
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = n < a.N;
+    int x = 0, y = 0;
+    double l0 = 0.0, l1 = 0.0, l2 = 1.0;
+    if (live) {
+        x = int(n % a.nx);
+        y = int(n / a.nx);
+        l0 = src.ux[n];
+        l1 = src.uy[n];
+        l2 = src.T[n];
+    }
+    const GlobalTaps<P, NP, L> taps{mom, a.N, a.nx, a.ny, a.bc_x, a.bc_y};
+    node_step<P, NP, S, L>(a, taps, x, y, n, live, l0, l1, l2, src, dst, cnt);
+}
+
+// ------------------------------------------------------ step (LDS tiles) ----
+
+// Minimum waves per SIMD requested from the register allocator for the tiled
+// kernel (compile-time tuning; 0 keeps the defaults of step_min_waves).
+#ifndef POND_TILED_WAVES_PER_EU
+#define POND_TILED_WAVES_PER_EU 0
+#endif
+#define POND_TILED_ATTR(P, S)                                                            \
+    __attribute__((amdgpu_waves_per_eu(POND_TILED_WAVES_PER_EU > 0 ? POND_TILED_WAVES_PER_EU \
+                                                                   : step_min_waves<P, S>())))
+
+template <typename P, int NP, int S, class L, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) POND_TILED_ATTR(P, S) void step_tiled_kernel(StepArgs a, DevState src,
+                                                            const P *__restrict__ mom,
+                                                            DevState dst, DevCounters *cnt,
+                                                            int cap, int tiles_x) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int red[16];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    tile_step<P, NP, S, L>(a, src, mom, dst, cnt, reinterpret_cast<P *>(smem_raw), cap,
+                           (tile % tiles_x) * TX, (tile / tiles_x) * TY, FixedShape<TX, TY>{}, red);
+}
+
+// ------------------------------------------------------ macroscopic ----
+template <typename P, class L>
+__global__ __launch_bounds__(kBlock) void macro_kernel(StepArgs a, DevState st, double *rho,
+                                                       double *ux, double *uy, double *T,
+                                                       double *p) {
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= a.N) return;
+    const double s = sqrt(st.T[n]), vx = st.ux[n], vy = st.uy[n];
+    double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double fi = double(plane<P>(st.f, i, a.N)[n]);
+        const double Cx = s * L::c(i / L::Q1) + vx, Cy = s * L::c(i % L::Q1) + vy;
+        r += fi;
+        jx += fi * Cx;
+        jy += fi * Cy;
+        E += double(plane<P>(st.g, i, a.N)[n]);
+        if (a.split == 2) E += 0.5 * fi * (Cx * Cx + Cy * Cy);
+    }
+    const double t = (a.split == 1 ? E : E - (jx * jx + jy * jy) / (2.0 * r)) / (r * a.cv);
+    if (rho) rho[n] = r;
+    if (ux) ux[n] = jx / r;
+    if (uy) uy[n] = jy / r;
+    if (T) T[n] = t;
+    if (p) p[n] = r * t;
+}
+
+template <typename P, class L>
+__global__ __launch_bounds__(kBlock) void export_kernel(StepArgs a, DevState st, double *f,
+                                                        double *g, double *frame) {
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= a.N) return;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        f[(long long)i * a.N + n] = double(plane<P>(st.f, i, a.N)[n]);
+        g[(long long)i * a.N + n] = double(plane<P>(st.g, i, a.N)[n]);
+    }
+    frame[n] = st.ux[n];
+    frame[a.N + n] = st.uy[n];
+    frame[2 * a.N + n] = st.T[n];
+}
+
+template <typename P, class L>
+__global__ __launch_bounds__(kBlock) void import_kernel(StepArgs a, const double *f,
+                                                        const double *g, const double *frame,
+                                                        DevState st) {
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= a.N) return;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        plane<P>(st.f, i, a.N)[n] = P(f[(long long)i * a.N + n]);
+        plane<P>(st.g, i, a.N)[n] = P(g[(long long)i * a.N + n]);
+    }
+    st.ux[n] = frame[n];
+    st.uy[n] = frame[a.N + n];
+    st.T[n] = frame[2 * a.N + n];
+}
+
+// per-block sums of (rho, rho ux, rho uy) over a fixed contiguous chunk
+template <typename Loader>
+__global__ __launch_bounds__(kBlock) void partial_sums_kernel(long long N, Loader ld,
+                                                              double *scratch) {
+    __shared__ double sh[3][kBlock];
+    const long long chunk = (N + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = lo + chunk < N ? lo + chunk : N;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (long long n = lo + threadIdx.x; n < hi; n += blockDim.x) {
+        double r, jx, jy;
+        ld(n, r, jx, jy);
+        s0 += r;
+        s1 += jx;
+        s2 += jy;
+    }
+    sh[0][threadIdx.x] = s0;
+    sh[1][threadIdx.x] = s1;
+    sh[2][threadIdx.x] = s2;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) scratch[blockIdx.x * 3 + c] = sh[c][0];
+}
+
+template <typename P, class L>
+struct StateLoader {
+    DevState st;
+    long long N;
+    __device__ void operator()(long long n, double &r, double &jx, double &jy) const {
+        const double s = sqrt(st.T[n]);
+        r = jx = jy = 0.0;
+        for (int i = 0; i < L::Q; ++i) {
+            const double fi = double(static_cast<const P *>(st.f)[(long long)i * N + n]);
+            r += fi;
+            jx += fi * (s * L::c(i / L::Q1) + st.ux[n]);
+            jy += fi * (s * L::c(i % L::Q1) + st.uy[n]);
+        }
+    }
+};
+
+template <typename P, int NP, int S, class L>
+const void *tiled_kernel_ptr(TileShape shape) {
+    switch (shape) {
+    case TileShape::T16x16: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, L, 16, 16>);
+    case TileShape::T32x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, L, 32, 8>);
+    case TileShape::T16x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, L, 16, 8>);
+    case TileShape::T8x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, L, 8, 8>);
+    case TileShape::T256x1: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, L, 256, 1>);
+    case TileShape::T64x1: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, L, 64, 1>);
+    }
+    return nullptr;
+}
+
+template <typename P, int NP, int S, class L, int TX, int TY>
+hipError_t launch_tiled_t(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
+                          DevState dst, DevCounters *cnt, hipStream_t s) {
+    auto kern = step_tiled_kernel<P, NP, S, L, TX, TY>;
+    const size_t lds = size_t(tc.cap) * nmom_padded<P, L>() * sizeof(P);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    const int tiles_x = (a.nx + TX - 1) / TX, tiles_y = (a.ny + TY - 1) / TY;
+    hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y), dim3(TX * TY), lds, s, a, src, mom, dst, cnt,
+                       tc.cap, tiles_x);
+    return hipGetLastError();
+}
+
+template <typename P, int NP, int S, class L>
+hipError_t launch_tiled_v(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
+                          DevState dst, DevCounters *cnt, hipStream_t s) {
+    switch (tc.shape) {
+    case TileShape::T16x16: return launch_tiled_t<P, NP, S, L, 16, 16>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T32x8: return launch_tiled_t<P, NP, S, L, 32, 8>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T16x8: return launch_tiled_t<P, NP, S, L, 16, 8>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T8x8: return launch_tiled_t<P, NP, S, L, 8, 8>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T256x1: return launch_tiled_t<P, NP, S, L, 256, 1>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T64x1: return launch_tiled_t<P, NP, S, L, 64, 1>(a, tc, src, mom, dst, cnt, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lk
+
+// Launchers of the lattice-dependent kernels for arithmetic type P on lattice L
+// (the variants a lattice supports: with_lattice_variant).  The members are
+// defined out of the class, so an explicit instantiation declaration keeps a
+// translation unit from instantiating another lattice's kernels.
+template <typename P, class L>
+struct Launch {
+    static hipError_t init(const StepArgs &a, const double *rho, const double *ux,
+                           const double *uy, const double *T, DevState st, DevCounters *cnt,
+                           hipStream_t s);
+    static hipError_t moments(const StepArgs &a, DevState st, P *mom, hipStream_t s);
+    static hipError_t step(const StepArgs &a, DevState src, const P *mom, DevState dst,
+                           DevCounters *cnt, hipStream_t s);
+    static hipError_t step_tiled(const StepArgs &a, const TileConfig &tc, DevState src,
+                                 const P *mom, DevState dst, DevCounters *cnt, hipStream_t s);
+    static hipError_t macro(const StepArgs &a, DevState st, double *rho, double *ux, double *uy,
+                            double *T, double *p, hipStream_t s);
+    static hipError_t exp(const StepArgs &a, DevState st, double *f, double *g, double *frame,
+                          hipStream_t s);
+    static hipError_t imp(const StepArgs &a, const double *f, const double *g, const double *frame,
+                          DevState st, hipStream_t s);
+    // per-block (rho, j) sums of a state into scratch[3 * nblocks]
+    static hipError_t state_partial_sums(const StepArgs &a, DevState st, double *scratch,
+                                         int nblocks, hipStream_t s);
+    static int tiled_blocks_per_cu(int np, int split, TileShape shape);
+};
+
+template <typename P, class L>
+hipError_t Launch<P, L>::init(const StepArgs &a, const double *rho, const double *ux,
+                              const double *uy, const double *T, DevState st, DevCounters *cnt,
+                              hipStream_t s) {
+    hipLaunchKernelGGL((lk::init_kernel<P, L>), dim3(lk::grid_for(a.N)), dim3(lk::kBlock), 0, s,
+                       a, rho, ux, uy, T, st, cnt);
+    return hipGetLastError();
+}
+
+template <typename P, class L>
+hipError_t Launch<P, L>::moments(const StepArgs &a, DevState st, P *mom, hipStream_t s) {
+    hipLaunchKernelGGL((lk::moments_kernel<P, L>), dim3(lk::grid_for(a.N)), dim3(lk::kBlock), 0,
+                       s, a, st, mom);
+    return hipGetLastError();
+}
+
+template <typename P, class L>
+hipError_t Launch<P, L>::step(const StepArgs &a, DevState src, const P *mom, DevState dst,
+                              DevCounters *cnt, hipStream_t s) {
+    return with_lattice_variant<L>(a.interp_points, a.split, [&](auto np, auto sp) {
+        hipLaunchKernelGGL((lk::step_kernel<P, np(), sp(), L>), dim3(lk::grid_for(a.N)),
+                           dim3(lk::kBlock), 0, s, a, src, mom, dst, cnt);
+        return hipGetLastError();
+    });
+}
+
+template <typename P, class L>
+hipError_t Launch<P, L>::step_tiled(const StepArgs &a, const TileConfig &tc, DevState src,
+                                    const P *mom, DevState dst, DevCounters *cnt, hipStream_t s) {
+    return with_lattice_variant<L>(a.interp_points, a.split, [&](auto np, auto sp) {
+        return lk::launch_tiled_v<P, np(), sp(), L>(a, tc, src, mom, dst, cnt, s);
+    });
+}
+
+template <typename P, class L>
+hipError_t Launch<P, L>::macro(const StepArgs &a, DevState st, double *rho, double *ux,
+                               double *uy, double *T, double *p, hipStream_t s) {
+    hipLaunchKernelGGL((lk::macro_kernel<P, L>), dim3(lk::grid_for(a.N)), dim3(lk::kBlock), 0, s,
+                       a, st, rho, ux, uy, T, p);
+    return hipGetLastError();
+}
+
+template <typename P, class L>
+hipError_t Launch<P, L>::exp(const StepArgs &a, DevState st, double *f, double *g, double *frame,
+                             hipStream_t s) {
+    hipLaunchKernelGGL((lk::export_kernel<P, L>), dim3(lk::grid_for(a.N)), dim3(lk::kBlock), 0, s,
+                       a, st, f, g, frame);
+    return hipGetLastError();
+}
+
+template <typename P, class L>
+hipError_t Launch<P, L>::imp(const StepArgs &a, const double *f, const double *g,
+                             const double *frame, DevState st, hipStream_t s) {
+    hipLaunchKernelGGL((lk::import_kernel<P, L>), dim3(lk::grid_for(a.N)), dim3(lk::kBlock), 0, s,
+                       a, f, g, frame, st);
+    return hipGetLastError();
+}
+
+template <typename P, class L>
+hipError_t Launch<P, L>::state_partial_sums(const StepArgs &a, DevState st, double *scratch,
+                                            int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL((lk::partial_sums_kernel<lk::StateLoader<P, L>>), dim3(nblocks),
+                       dim3(lk::kBlock), 0, s, a.N, lk::StateLoader<P, L>{st, a.N}, scratch);
+    return hipGetLastError();
+}
+
+template <typename P, class L>
+int Launch<P, L>::tiled_blocks_per_cu(int np, int split, TileShape shape) {
+    const void *k = with_lattice_variant<L>(np, split, [&](auto n, auto sp) {
+        return lk::tiled_kernel_ptr<P, n(), sp(), L>(shape);
+    });
+    int tx = 0, ty = 0;
+    tile_dims(shape, tx, ty);
+    int n = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, tx * ty, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n < 1 ? 1 : n;
+}
+
+}  // namespace pond

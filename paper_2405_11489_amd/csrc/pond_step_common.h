@@ -2,11 +2,12 @@
 // kernels: departure stencils, the predictor-corrector loop over a tap source,
 // re-projection, collision in Grad-coefficient space and the store.
 //
-// Moment storage ("grouped planes"): the 20 moments of a node (f moments 0-9,
-// g moments 10-19, ordering of pond_device.h) are held as G vector groups
-// (float: 5 float4, double: 10 double2); group k of node idx sits at
-// base[k * stride + idx].  The same layout serves the HBM moment planes
-// (stride = N) and the LDS tiles (stride = tile capacity).
+// Moment storage ("grouped planes"): the 2 NM moments of a node (f moments
+// 0..NM-1, g moments NM..2NM-1, ordering of pond_device.h; NM = 10 on D2Q16,
+// 15 on D2Q25) are held as G vector groups (float: float4, the last padded;
+// double: double2); group k of node idx sits at base[k * stride + idx].  The
+// same layout serves the HBM moment planes (stride = N) and the LDS tiles
+// (stride = tile capacity).
 #pragma once
 
 #include <utility>
@@ -22,29 +23,40 @@
 
 namespace pond {
 
-template <typename P>
+template <typename P, int NMOM>
 struct MomVec;
-template <>
-struct MomVec<float> {
+template <int NMOM>
+struct MomVec<float, NMOM> {
     using V = float4;
-    static constexpr int G = 5;
+    static constexpr int W = 4;
+    static constexpr int G = (NMOM + 3) / 4;
 };
-template <>
-struct MomVec<double> {
+template <int NMOM>
+struct MomVec<double, NMOM> {
     using V = double2;
-    static constexpr int G = 10;
+    static constexpr int W = 2;
+    static constexpr int G = (NMOM + 1) / 2;
 };
 
-constexpr int kNMom = 2 * kNM;  // 20 moments per node
+constexpr int kNMom = 2 * kNM;  // 20 moments per node on D2Q16
 
-template <typename P>
+// Moments per node of a lattice, and the values a node's groups hold (padded).
+template <class L>
+constexpr int nmom() { return 2 * L::NM; }
+template <typename P, class L>
+constexpr int nmom_padded() {
+    return MomVec<P, nmom<L>()>::G * MomVec<P, nmom<L>()>::W;
+}
+
+template <typename P, int NMOM = kNMom>
 __device__ __forceinline__ void load_moments(const P *__restrict__ base, long long stride,
-                                             long long idx, P M[kNMom]) {
-    using V = typename MomVec<P>::V;
+                                             long long idx, P *M) {
+    using MV = MomVec<P, NMOM>;
+    using V = typename MV::V;
     const V *b = reinterpret_cast<const V *>(base);
-    if constexpr (MomVec<P>::G == 5) {
+    if constexpr (MV::W == 4) {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < MV::G; ++k) {
             const V v = b[k * stride + idx];
             M[4 * k] = v.x;
             M[4 * k + 1] = v.y;
@@ -53,7 +65,7 @@ __device__ __forceinline__ void load_moments(const P *__restrict__ base, long lo
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < 10; ++k) {
+        for (int k = 0; k < MV::G; ++k) {
             const V v = b[k * stride + idx];
             M[2 * k] = v.x;
             M[2 * k + 1] = v.y;
@@ -61,18 +73,19 @@ __device__ __forceinline__ void load_moments(const P *__restrict__ base, long lo
     }
 }
 
-template <typename P>
+template <typename P, int NMOM = kNMom>
 __device__ __forceinline__ void store_moments(P *__restrict__ base, long long stride,
-                                              long long idx, const P M[kNMom]) {
-    using V = typename MomVec<P>::V;
+                                              long long idx, const P *M) {
+    using MV = MomVec<P, NMOM>;
+    using V = typename MV::V;
     V *b = reinterpret_cast<V *>(base);
-    if constexpr (MomVec<P>::G == 5) {
+    if constexpr (MV::W == 4) {
 #pragma unroll
-        for (int k = 0; k < 5; ++k)
+        for (int k = 0; k < MV::G; ++k)
             b[k * stride + idx] = V{M[4 * k], M[4 * k + 1], M[4 * k + 2], M[4 * k + 3]};
     } else {
 #pragma unroll
-        for (int k = 0; k < 10; ++k) b[k * stride + idx] = V{M[2 * k], M[2 * k + 1]};
+        for (int k = 0; k < MV::G; ++k) b[k * stride + idx] = V{M[2 * k], M[2 * k + 1]};
     }
 }
 
@@ -87,6 +100,8 @@ __device__ __forceinline__ const P *pop_plane(const void *base, int i, long long
 
 static __constant__ VelocityTablesP<float> kTabF = make_velocity_tables_p<float>();
 static __constant__ VelocityTablesP<double> kTabD = make_velocity_tables_p<double>();
+static __constant__ LatticeTablesP<float, D2Q25> kTab25F = make_lattice_tables_p<float, D2Q25>();
+static __constant__ LatticeTablesP<double, D2Q25> kTab25D = make_lattice_tables_p<double, D2Q25>();
 
 template <typename P>
 __device__ __forceinline__ const VelocityTablesP<P> &vtab();
@@ -99,17 +114,28 @@ __device__ __forceinline__ const VelocityTablesP<double> &vtab<double>() {
     return kTabD;
 }
 
+// Reconstruction tables of lattice L (recon, herm; see pond_device.h).
+template <typename P, class L>
+__device__ __forceinline__ const auto &ltab() {
+    if constexpr (L::Q == 16)
+        return vtab<P>();
+    else if constexpr (sizeof(P) == 4)
+        return kTab25F;
+    else
+        return kTab25D;
+}
+
 // Tap source reading the HBM moment planes with periodic / clamp wrapping.
 // gather() accumulates sum_{p,q} wx[p] wy[q] M(bx + p, by + q) for the NP x NP
 // stencil whose first node is (bx, by) in unwrapped grid coordinates.
-template <typename P, int NP>
+template <typename P, int NP, class L = D2Q16>
 struct GlobalTaps {
     const P *mom;
     long long N;
     int nx, ny, bc_x, bc_y;
 
     __device__ __forceinline__ void gather(int bx, int by, const P wx[NP], const P wy[NP],
-                                           P Mf[kNM], P Mg[kNM]) const {
+                                           P Mf[L::NM], P Mg[L::NM]) const {
         int col[NP];
 #pragma unroll
         for (int j = 0; j < NP; ++j) col[j] = wrap_index(bx + j, nx, bc_x);
@@ -119,12 +145,12 @@ struct GlobalTaps {
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const P W = wx[p] * wy[q];
-                P M[kNMom];
-                load_moments(mom, N, row + col[p], M);
+                P M[nmom_padded<P, L>()];
+                load_moments<P, nmom<L>()>(mom, N, row + col[p], M);
 #pragma unroll
-                for (int k = 0; k < kNM; ++k) {
+                for (int k = 0; k < L::NM; ++k) {
                     Mf[k] += W * M[k];
-                    Mg[k] += W * M[kNM + k];
+                    Mg[k] += W * M[L::NM + k];
                 }
             }
         }
@@ -162,6 +188,55 @@ __device__ __forceinline__ void pop_coeffs(const P r[kNM], P dx, P dy, P is, P B
            exx * ey * r21 + ex * eyy * r12 + eyy * ey * r03;
 }
 
+// pop_coeffs for any order: B_rt = sum_{p >= r, q >= t} r_pq is^(p+q) C(p,r) C(q,t)
+// (-dx)^(p-r) (-dy)^(q-t), the shift applied in y, then in x.
+template <class L, typename P>
+__device__ __forceinline__ void pop_coeffs_n(const P r[L::NM], P dx, P dy, P is, P B[L::NM]) {
+    constexpr int N = L::N;
+    P ex[N + 1], ey[N + 1], sc[N + 1];
+    ex[0] = ey[0] = sc[0] = P(1);
+#pragma unroll
+    for (int j = 1; j <= N; ++j) {
+        ex[j] = ex[j - 1] * (-dx);
+        ey[j] = ey[j - 1] * (-dy);
+        sc[j] = sc[j - 1] * is;
+    }
+    P R[L::NM], T[L::NM];
+#pragma unroll
+    for (int k = 0; k < L::NM; ++k) R[k] = r[k] * sc[mom_px(k) + mom_py(k)];
+#pragma unroll
+    for (int k = 0; k < L::NM; ++k) {
+        const int p = mom_px(k), t = mom_py(k);
+        P acc = R[k];
+#pragma unroll
+        for (int q = t + 1; q <= N - p; ++q)
+            acc += P(binom_c(q, t)) * ey[q - t] * R[mom_index(p, q)];
+        T[k] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < L::NM; ++k) {
+        const int rr = mom_px(k), t = mom_py(k);
+        P acc = T[k];
+#pragma unroll
+        for (int p = rr + 1; p <= N - t; ++p)
+            acc += P(binom_c(p, rr)) * ex[p - rr] * T[mom_index(p, t)];
+        B[k] = acc;
+    }
+}
+
+template <class L, typename P>
+__device__ __forceinline__ void monomials_n(P Vx, P Vy, P mono[L::NM]) {
+    P px[L::N + 1], py[L::N + 1];
+    px[0] = py[0] = P(1);
+#pragma unroll
+    for (int j = 1; j <= L::N; ++j) {
+        px[j] = px[j - 1] * Vx;
+        py[j] = py[j - 1] * Vy;
+    }
+#pragma unroll
+    for (int k = 0; k < L::NM; ++k) mono[k] = px[mom_px(k)] * py[mom_py(k)];
+}
+
 template <typename P>
 __device__ __forceinline__ void monomials(P Vx, P Vy, P mono[kNM]) {
     const P Vxx = Vx * Vx, Vyy = Vy * Vy;
@@ -179,8 +254,8 @@ __device__ __forceinline__ void monomials(P Vx, P Vy, P mono[kNM]) {
 
 // The whole step of one destination node (x, y) = node n whose time-t frame
 // is (l0, l1, l2), for the energy split S (0: total energy, 1: internal
-// energy); src is the time-t state (its frames feed the velocity gradient of
-// the internal-energy split).  Lanes with live == false take part
+// energy, 2: non-translational energy) on lattice L; src is the time-t state
+// (its frames feed the velocity gradient of the internal-energy split).  Lanes with live == false take part
 // in the wave-level predictor-corrector exit and the counter reduction only.
 //
 // Per predictor-corrector gather, for each velocity i: departure point and
@@ -188,17 +263,18 @@ __device__ __forceinline__ void monomials(P Vx, P Vy, P mono[kNM]) {
 // the interpolated moments into the iterate frame (population i of f and g);
 // the FP64 sums rho, j, E and the lab moments of the gathered populations are
 // accumulated on the fly, so no population array is kept.
-template <typename P, int NP, int S, class Taps>
+template <typename P, int NP, int S, class L, class Taps>
 __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, int x, int y,
                                           long long n, bool live, double l0, double l1, double l2,
                                           const DevState &src, DevState dst, DevCounters *cnt) {
-    const VelocityTablesP<P> &tab = vtab<P>();
+    constexpr int NM = L::NM;
+    const auto &tab = ltab<P, L>();
     double lg0 = l0, lg1 = l1, lg2 = l2;     // frame of the current gather
     double ln0 = lg0, ln1 = lg1, ln2 = lg2;  // frame of the gathered moments
     double rho = 1.0;
-    P Mf[kNM], Mg[kNM];  // lab moments (about u_ref) of the last gather's populations
+    P Mf[NM], Mg[NM];  // lab moments (about u_ref) of the last gather's populations
 #pragma unroll
-    for (int k = 0; k < kNM; ++k) Mf[k] = Mg[k] = P(0);
+    for (int k = 0; k < NM; ++k) Mf[k] = Mg[k] = P(0);
     bool done = !live, conv = false, bad = false;
     int used = 0;
 
@@ -208,31 +284,34 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             const P sP = P(s), dux = P(lg0 - a.uref_x), duy = P(lg1 - a.uref_y), is = P(1.0 / s);
             double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
 #pragma unroll
-            for (int k = 0; k < kNM; ++k) Mf[k] = Mg[k] = P(0);
-            // velocity i = 4 ia + ib has x-component c(ia) and y-component c(ib):
-            // the x-stencil serves the four velocities of one ia
+            for (int k = 0; k < NM; ++k) Mf[k] = Mg[k] = P(0);
+            // velocity i = Q1 ia + ib has x-component c(ia) and y-component c(ib):
+            // the x-stencil serves the Q1 velocities of one ia
 #pragma unroll 1
-            for (int ia = 0; ia < 4; ++ia) {
-                const double cx = c1(ia);
+            for (int ia = 0; ia < L::Q1; ++ia) {
+                const double cx = L::c(ia);
                 // departure point x - C_i(lam_bar) dt and its stencil, x then y
                 P wx[NP];
                 const int bx = lagrange<NP>(double(x) - (s * cx + lg0), wx);
 #pragma unroll 1
-                for (int ib = 0; ib < 4; ++ib) {
-                const int i = 4 * ia + ib;
-                const double cy = c1(ib);
+                for (int ib = 0; ib < L::Q1; ++ib) {
+                const int i = L::Q1 * ia + ib;
+                const double cy = L::c(ib);
                 P wy[NP];
                 const int by = lagrange<NP>(double(y) - (s * cy + lg1), wy);
-                P If[kNM], Ig[kNM];
+                P If[NM], Ig[NM];
 #pragma unroll
-                for (int k = 0; k < kNM; ++k) If[k] = Ig[k] = P(0);
+                for (int k = 0; k < NM; ++k) If[k] = Ig[k] = P(0);
                 taps.gather(bx, by, wx, wy, If, Ig);
                 // frame transformation of the interpolated moments: population i
-                P B[kNM];
-                pop_coeffs(tab.recon[i], dux, duy, is, B);
+                P B[NM];
+                if constexpr (L::Q == 16)
+                    pop_coeffs(tab.recon[i], dux, duy, is, B);
+                else
+                    pop_coeffs_n<L>(tab.recon[i], dux, duy, is, B);
                 P fi = P(0), gi = P(0);
 #pragma unroll
-                for (int k = 0; k < kNM; ++k) {
+                for (int k = 0; k < NM; ++k) {
                     fi += B[k] * If[k];
                     gi += B[k] * Ig[k];
                 }
@@ -242,11 +321,19 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                 jx += fd * (s * cx + lg0);
                 jy += fd * (s * cy + lg1);
                 E += double(gi);
+                if constexpr (S == 2) {
+                    // non-translational split: f carries the translational energy
+                    const double Cx = s * cx + lg0, Cy = s * cy + lg1;
+                    E += 0.5 * fd * (Cx * Cx + Cy * Cy);
+                }
                 // lab moments of the gathered populations, for the re-projection
-                P mono[kNM];
-                monomials(sP * P(cx) + dux, sP * P(cy) + duy, mono);
+                P mono[NM];
+                if constexpr (L::Q == 16)
+                    monomials(sP * P(cx) + dux, sP * P(cy) + duy, mono);
+                else
+                    monomials_n<L>(sP * P(cx) + dux, sP * P(cy) + duy, mono);
 #pragma unroll
-                for (int k = 0; k < kNM; ++k) {
+                for (int k = 0; k < NM; ++k) {
                     Mf[k] += fi * mono[k];
                     Mg[k] += gi * mono[k];
                 }
@@ -255,7 +342,8 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             rho = r;
             ln0 = jx / r;
             ln1 = jy / r;
-            // total split: sum g = E = rho c_v T + |j|^2 / (2 rho); internal: sum g = rho c_v T
+            // total split: sum g = E = rho c_v T + |j|^2 / (2 rho); internal: sum g = rho c_v T;
+            // non-translational: E = sum g + sum f |C|^2 / 2 = rho c_v T + |j|^2 / (2 rho)
             if constexpr (S == 1)
                 ln2 = E / (r * a.cv);
             else
@@ -292,37 +380,51 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
         const double sT = sqrt(ln2);
         const P is = P(1.0 / sT);
         const P tx = P(ln0 - a.uref_x), ty = P(ln1 - a.uref_y);
-        P m[kNM], af[kNM], ag[kNM];
-        central_normalised(Mf, tx, ty, is, m);
-        hermite_from_central(m, af);
-        central_normalised(Mg, tx, ty, is, m);
-        hermite_from_central(m, ag);
+        P m[NM], af[NM], ag[NM];
+        if constexpr (L::Q == 16) {
+            central_normalised(Mf, tx, ty, is, m);
+            hermite_from_central(m, af);
+            central_normalised(Mg, tx, ty, is, m);
+            hermite_from_central(m, ag);
+        } else {
+            central_normalised_n<L>(Mf, tx, ty, is, m);
+            hermite_from_central_n<L>(m, af);
+            central_normalised_n<L>(Mg, tx, ty, is, m);
+            hermite_from_central_n<L>(m, ag);
+        }
 
         // BGK collision in lam*, on the Grad coefficients.
         // f: f^eq = rho w_i has only a0; every higher coefficient decays by (1 - omega).
         // g, total split: g^eq = w_i [rho (c_v - 1) T + rho |C_i|^2 / 2] has
         //    a0 = rho c_v T + rho |u|^2 / 2, a1 = rho sqrt(T) u, a2 = rho T I, a3 = 0;
-        // g, internal split: C_i - u in place of C_i, so a0 = rho c_v T, a1 = 0.
+        // g, internal split: C_i - u in place of C_i, so a0 = rho c_v T, a1 = 0;
+        // g, non-translational split: g^eq = w_i rho (c_v - 1) T, a0 only.
         const double om = a.omega;
-        double geq[kNM];
+        double geq[NM];
+#pragma unroll
+        for (int k = 0; k < NM; ++k) geq[k] = 0.0;
         if constexpr (S == 1) {
             geq[0] = rho * a.cv * ln2;
             geq[1] = geq[2] = 0.0;
+        } else if constexpr (S == 2) {
+            geq[0] = rho * (a.cv - 1.0) * ln2;
         } else {
             geq[0] = rho * (a.cv - 1.0) * ln2 + 0.5 * rho * (2.0 * ln2 + ln0 * ln0 + ln1 * ln1);
             geq[1] = rho * sT * ln0;
             geq[2] = rho * sT * ln1;
         }
-        geq[3] = rho * ln2;
-        geq[4] = 0.0;
-        geq[5] = rho * ln2;
-        geq[6] = geq[7] = geq[8] = geq[9] = 0.0;
-        if (S == 1 || a.unit_prandtl) {
+        if constexpr (S != 2) {
+            geq[3] = rho * ln2;
+            geq[4] = 0.0;
+            geq[5] = rho * ln2;
+            geq[6] = geq[7] = geq[8] = geq[9] = 0.0;
+        }
+        if (S == 1 || S == 2 || a.unit_prandtl) {
             // internal split: the flux of g is the heat flux alone, relaxed at omega_1
-            // (omega at Pr = 1)
+            // (omega at Pr = 1); the non-translational split runs at Pr = 1 only
             const double og = a.unit_prandtl ? om : a.omega1;
 #pragma unroll
-            for (int k = 0; k < kNM; ++k) ag[k] = ag[k] + P(og) * (P(geq[k]) - ag[k]);
+            for (int k = 0; k < NM; ++k) ag[k] = ag[k] + P(og) * (P(geq[k]) - ag[k]);
         } else {
             // quasi-equilibrium: energy flux of g^eq plus the viscous heating u . P^neq,
             // P^neq = T a2(f) + sqrt(T) (u a1(f) + a1(f) u) in lam*.
@@ -332,24 +434,24 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             const double Pyy = ln2 * double(af[5]) + sT * 2.0 * ln1 * a1y;
             const double dqx = ln0 * Pxx + ln1 * Pxy;
             const double dqy = ln0 * Pxy + ln1 * Pyy;
-            double gqe[kNM];
+            double gqe[NM];
 #pragma unroll
-            for (int k = 0; k < kNM; ++k) gqe[k] = geq[k];
+            for (int k = 0; k < NM; ++k) gqe[k] = geq[k];
             gqe[1] += dqx / sT;
             gqe[2] += dqy / sT;
             const double om1 = a.omega1;
 #pragma unroll
-            for (int k = 0; k < kNM; ++k)
+            for (int k = 0; k < NM; ++k)
                 ag[k] = ag[k] + P(om1) * (P(gqe[k]) - ag[k]) + P(om) * (P(geq[k]) - P(gqe[k]));
         }
         // internal split: source of the g-equation, S_i = -f~_i (C_i - u) . (a + C_i . grad u)
         // with f~ the re-projected pre-collision populations, a = d_t u = u* - u(t) and
         // grad[al][be] = d_al u_be from central differences of the time-t frames
-        P afp[kNM];
+        P afp[NM];
         P ax = P(0), ay = P(0), gxx = P(0), gxy = P(0), gyx = P(0), gyy = P(0);
         if constexpr (S == 1) {
 #pragma unroll
-            for (int k = 0; k < kNM; ++k) afp[k] = af[k];
+            for (int k = 0; k < NM; ++k) afp[k] = af[k];
             const long long row = (long long)y * a.nx;
             const long long xm = row + wrap_index(x - 1, a.nx, a.bc_x);
             const long long xp = row + wrap_index(x + 1, a.nx, a.bc_x);
@@ -365,23 +467,23 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
         }
         const P decay = P(1.0 - om);
 #pragma unroll
-        for (int k = 1; k < kNM; ++k) af[k] *= decay;
+        for (int k = 1; k < NM; ++k) af[k] *= decay;
 
         // reconstruct and store the post-collision populations
         const P sTP = P(sT), u0 = P(ln0), u1 = P(ln1);
 #pragma unroll 4
-        for (int i = 0; i < kQ; ++i) {
+        for (int i = 0; i < L::Q; ++i) {
             P fv = P(0), gv = P(0);
 #pragma unroll
-            for (int k = 0; k < kNM; ++k) {
+            for (int k = 0; k < NM; ++k) {
                 fv += tab.herm[i][k] * af[k];
                 gv += tab.herm[i][k] * ag[k];
             }
             if constexpr (S == 1) {
                 P ft = P(0);
 #pragma unroll
-                for (int k = 0; k < kNM; ++k) ft += tab.herm[i][k] * afp[k];
-                const P ex = sTP * P(c1(i / 4)), ey = sTP * P(c1(i % 4));
+                for (int k = 0; k < NM; ++k) ft += tab.herm[i][k] * afp[k];
+                const P ex = sTP * P(L::c(i / L::Q1)), ey = sTP * P(L::c(i % L::Q1));
                 const P Cx = ex + u0, Cy = ey + u1;
                 gv -= ft * (ex * (ax + Cx * gxx + Cy * gyx) + ey * (ay + Cx * gxy + Cy * gyy));
             }

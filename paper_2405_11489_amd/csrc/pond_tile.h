@@ -24,15 +24,15 @@ namespace pond {
 // stride cap; a velocity whose stencil leaves the region reads HBM.  With a
 // single grid row (flat_y) every stencil row is row 0, so the region is one
 // row and all NP stencil rows read it (same arithmetic as the HBM gather).
-template <typename P, int NP>
+template <typename P, int NP, class L = D2Q16>
 struct TileTaps {
     const P *lds;
     int cap, X0, Y0, X1, Y1, W;
     bool flat_y;
-    GlobalTaps<P, NP> glob;
+    GlobalTaps<P, NP, L> glob;
 
     __device__ __forceinline__ void gather(int bx, int by, const P wx[NP], const P wy[NP],
-                                           P Mf[kNM], P Mg[kNM]) const {
+                                           P Mf[L::NM], P Mg[L::NM]) const {
         const bool inside =
             bx >= X0 && bx + NP - 1 <= X1 && (flat_y || (by >= Y0 && by + NP - 1 <= Y1));
         if (inside) {
@@ -46,12 +46,12 @@ struct TileTaps {
                     constexpr int kGroup = sizeof(P) == 8 ? POND_TAP_GROUP_F64 : POND_TAP_GROUP_F32;
                     if (kGroup > 0 && p > 0 && p % kGroup == 0) asm volatile("" ::: "memory");
                     const P Wt = wx[p] * wy[q];
-                    P M[kNMom];
-                    load_moments(lds, cap, base + q * rs + p, M);
+                    P M[nmom_padded<P, L>()];
+                    load_moments<P, nmom<L>()>(lds, cap, base + q * rs + p, M);
 #pragma unroll
-                    for (int k = 0; k < kNM; ++k) {
+                    for (int k = 0; k < L::NM; ++k) {
                         Mf[k] += Wt * M[k];
-                        Mg[k] += Wt * M[kNM + k];
+                        Mg[k] += Wt * M[L::NM + k];
                     }
                 }
             }
@@ -76,10 +76,10 @@ __device__ __forceinline__ int block_min(int v, int *red) {
 
 // Unwrapped index range [lo, hi] of the stencils of every velocity of a node at
 // coordinate x with frame velocity u and sqrt(T) = s along one axis.
-template <int NP>
+template <int NP, class L = D2Q16>
 __device__ __forceinline__ void stencil_extent(int x, double u, double s, int &lo, int &hi) {
     // departure coordinates x - (s c + u) for c = +-c_out bound all stencils
-    const double dlo = double(x) - (s * c1(3) + u), dhi = double(x) - (s * c1(0) + u);
+    const double dlo = double(x) - (s * L::c(L::Q1 - 1) + u), dhi = double(x) - (s * L::c(0) + u);
     const double clo = fmin(fmax(dlo, double(x) - 4096.0), double(x) + 4096.0);
     const double chi = fmin(fmax(dhi, double(x) - 4096.0), double(x) + 4096.0);
     if (NP == 4) {
@@ -161,9 +161,9 @@ __device__ __forceinline__ void clip_region(int tx0, int ty0, int tx, int ty, in
 
 // The tile with first node (tx0, ty0): load the time-t frames, bound the
 // source region (clip_region), stage the region's moments, then run every
-// lane's node step (energy split S).  Every thread of the block must call it
-// (it synchronises the block).  red: 4 x 4 ints of shared memory.
-template <typename P, int NP, int S, class Shape>
+// lane's node step (energy split S, lattice L).  Every thread of the block must
+// call it (it synchronises the block).  red: 4 x 4 ints of shared memory.
+template <typename P, int NP, int S, class L, class Shape>
 __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const P *__restrict__ mom,
                                           DevState dst, DevCounters *cnt, P *lds, int cap, int tx0,
                                           int ty0, Shape sh, int *red) {
@@ -182,8 +182,8 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const
     int lx = kFar, hx = -kFar, ly = kFar, hy = -kFar;
     if (live && isfinite(l0) && isfinite(l1) && l2 > 0.0 && isfinite(l2)) {
         const double s = sqrt(l2);
-        stencil_extent<NP>(x, l0, s, lx, hx);
-        stencil_extent<NP>(y, l1, s, ly, hy);
+        stencil_extent<NP, L>(x, l0, s, lx, hx);
+        stencil_extent<NP, L>(y, l1, s, ly, hy);
     }
     const bool flat_y = a.ny == 1;
     int X0 = block_min(lx, red);
@@ -197,41 +197,56 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const
     for (int idx = threadIdx.x; idx < W * H; idx += nthreads) {
         const int gx = wrap_index(X0 + idx % W, a.nx, a.bc_x);
         const int gy = wrap_index(Y0 + idx / W, a.ny, a.bc_y);
-        P M[kNMom];
-        load_moments(mom, a.N, (long long)gy * a.nx + gx, M);
-        store_moments(lds, cap, idx, M);
+        P M[nmom_padded<P, L>()];
+        load_moments<P, nmom<L>()>(mom, a.N, (long long)gy * a.nx + gx, M);
+        store_moments<P, nmom<L>()>(lds, cap, idx, M);
     }
     __syncthreads();
 
-    const TileTaps<P, NP> taps{lds, cap, X0, Y0, X1, Y1, W, flat_y,
-                               GlobalTaps<P, NP>{mom, a.N, a.nx, a.ny, a.bc_x, a.bc_y}};
-    node_step<P, NP, S>(a, taps, x, y, n, live, l0, l1, l2, src, dst, cnt);
+    const TileTaps<P, NP, L> taps{lds, cap, X0, Y0, X1, Y1, W, flat_y,
+                                  GlobalTaps<P, NP, L>{mom, a.N, a.nx, a.ny, a.bc_x, a.bc_y}};
+    node_step<P, NP, S, L>(a, taps, x, y, n, live, l0, l1, l2, src, dst, cnt);
 }
 
-// Moments up to order three of f and g of node n (Eq. genericMomentUptoO3),
-// about u_ref, stored as grouped planes.
-template <typename P>
+// Moments up to the lattice's Grad order (three on D2Q16, four on D2Q25) of
+// f and g of node n (Eq. genericMomentUptoO3), about u_ref, stored as grouped
+// planes.
+template <typename P, class L = D2Q16>
 __device__ __forceinline__ void node_moments(const StepArgs &a, DevState st, P *__restrict__ mom,
                                              long long n) {
     const P s = P(sqrt(st.T[n]));
     const P dx = P(st.ux[n] - a.uref_x), dy = P(st.uy[n] - a.uref_y);
-    P M[kNMom];
+    constexpr int NM = L::NM;
+    P M[nmom_padded<P, L>()];
 #pragma unroll
-    for (int k = 0; k < kNMom; ++k) M[k] = P(0);
+    for (int k = 0; k < nmom_padded<P, L>(); ++k) M[k] = P(0);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
+    for (int i = 0; i < L::Q; ++i) {
         const P fi = pop_plane<P>(st.f, i, a.N)[n];
         const P gi = pop_plane<P>(st.g, i, a.N)[n];
-        const P Vx = s * P(c1(i / 4)) + dx, Vy = s * P(c1(i % 4)) + dy;
-        const P mono[kNM] = {P(1),         Vx,          Vy,          Vx * Vx,     Vx * Vy,
-                             Vy * Vy,      Vx * Vx * Vx, Vx * Vx * Vy, Vx * Vy * Vy, Vy * Vy * Vy};
+        const P Vx = s * P(L::c(i / L::Q1)) + dx, Vy = s * P(L::c(i % L::Q1)) + dy;
+        P mono[NM];
+        if constexpr (L::Q == 16) {
+            mono[0] = P(1);
+            mono[1] = Vx;
+            mono[2] = Vy;
+            mono[3] = Vx * Vx;
+            mono[4] = Vx * Vy;
+            mono[5] = Vy * Vy;
+            mono[6] = Vx * Vx * Vx;
+            mono[7] = Vx * Vx * Vy;
+            mono[8] = Vx * Vy * Vy;
+            mono[9] = Vy * Vy * Vy;
+        } else {
+            monomials_n<L>(Vx, Vy, mono);
+        }
 #pragma unroll
-        for (int k = 0; k < kNM; ++k) {
+        for (int k = 0; k < NM; ++k) {
             M[k] += fi * mono[k];
-            M[kNM + k] += gi * mono[k];
+            M[NM + k] += gi * mono[k];
         }
     }
-    store_moments(mom, a.N, n, M);
+    store_moments<P, nmom<L>()>(mom, a.N, n, M);
 }
 
 }  // namespace pond

@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("POND_LIB_PATH") or os.path.join(HERE, "libpond.so")
 
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NONPHYSICAL, ERR_STATE = range(7)
-LATTICE_D2Q16 = 16
+LATTICE_D2Q16, LATTICE_D2Q25 = 16, 25
 SPLIT_TOTAL, SPLIT_INTERNAL, SPLIT_NONTRANS = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
 BC_PERIODIC, BC_CLAMP = 0, 1
@@ -388,12 +388,14 @@ class Solver:
 
     def __init__(self, nx, ny, *, tau, gamma=1.4, prandtl=1.0, bc_x=BC_PERIODIC,
                  bc_y=BC_PERIODIC, precision=PREC_FP32, interp_points=4, pc_tol=0.0,
-                 pc_max_iter=32, split=SPLIT_TOTAL, stream=None, tuning=None):
+                 pc_max_iter=32, split=SPLIT_TOTAL, lattice=LATTICE_D2Q16, stream=None,
+                 tuning=None):
         self.params = pond_params_default(nx=nx, ny=ny, tau=tau, gamma=gamma, prandtl=prandtl,
                                           bc_x=bc_x, bc_y=bc_y, precision=precision,
                                           interp_points=interp_points, pc_tol=pc_tol,
-                                          pc_max_iter=pc_max_iter, split=split)
+                                          pc_max_iter=pc_max_iter, split=split, lattice=lattice)
         self.nx, self.ny = nx, ny
+        self.q = lattice
         self.ctx = pond_create(self.params, stream)
         if tuning:
             pond_set_tuning(self.ctx, **tuning)
@@ -423,9 +425,9 @@ class Solver:
         return pond_stats(self.ctx)
 
     def export_state(self):
-        """(f, g, frame, u_ref) with f, g of shape (16, N) and frame (3, N)."""
+        """(f, g, frame, u_ref) with f, g of shape (Q, N) and frame (3, N)."""
         N = self.nx * self.ny
-        f, g, fr, ur = np.zeros((16, N)), np.zeros((16, N)), np.zeros((3, N)), np.zeros(2)
+        f, g, fr, ur = np.zeros((self.q, N)), np.zeros((self.q, N)), np.zeros((3, N)), np.zeros(2)
         pond_export_state(self.ctx, f, g, fr, ur)
         return f, g, fr, ur
 

@@ -49,8 +49,8 @@ def plane_errors(f, g, fr, ostate):
     """Max over planes of ||gpu - oracle||_inf / ||oracle||_inf for f planes, g
     planes and the T plane; u_x, u_y planes relative to the velocity scale
     (oracle state in its node-major layout)."""
-    ef = max(_rel(f[i], ostate.f[:, i]) for i in range(16))
-    eg = max(_rel(g[i], ostate.g[:, i]) for i in range(16))
+    ef = max(_rel(f[i], ostate.f[:, i]) for i in range(f.shape[0]))
+    eg = max(_rel(g[i], ostate.g[:, i]) for i in range(g.shape[0]))
     vs = velocity_scale(ostate.lam[:, 0], ostate.lam[:, 1], ostate.lam[:, 2])
     el = max(_rel(fr[0], ostate.lam[:, 0], vs), _rel(fr[1], ostate.lam[:, 1], vs),
              _rel(fr[2], ostate.lam[:, 2]))

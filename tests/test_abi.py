@@ -61,8 +61,8 @@ def test_state_bytes(pond):
 @pytest.mark.parametrize("field,value,status", [
     ("nx", 0, 1), ("ny", -3, 1), ("tau", 0.5, 1), ("tau", float("nan"), 1),
     ("prandtl", 0.0, 1), ("gamma", 1.0, 1), ("gamma", 2.5, 1), ("bc_x", 2, 1),
-    ("interp_points", 5, 1), ("precision", 7, 1), ("lattice", 25, 2), ("lattice", 7, 1),
-    ("split", 2, 2), ("split", 9, 1), ("struct_size", 64, 1),
+    ("interp_points", 5, 1), ("precision", 7, 1), ("lattice", 9, 2), ("lattice", 7, 1),
+    ("split", 9, 1), ("struct_size", 64, 1),
 ])
 def test_invalid_params_rejected_before_device(pond, field, value, status):
     p = pond.pond_params_default(nx=8, ny=8)
@@ -72,6 +72,33 @@ def test_invalid_params_rejected_before_device(pond, field, value, status):
         pond.pond_create(p)
     assert ei.value.status == status
     assert pond.pond_last_error()
+
+
+@pytest.mark.parametrize("fields", [
+    {"split": 2, "prandtl": 0.71},                     # non-translational: BGK (Pr = 1) only
+    {"lattice": 25, "split": 1},                       # D2Q25: total or non-translational
+    {"lattice": 25, "interp_points": 3},               # D2Q25: cubic stencil
+])
+def test_unsupported_combinations_rejected_before_device(pond, fields):
+    p = pond.pond_params_default(nx=8, ny=8)
+    for k, v in fields.items():
+        setattr(p, k, v)
+    assert pond.pond_state_bytes(p) == 0
+    with pytest.raises(pond.PondError) as ei:
+        pond.pond_create(p)
+    assert ei.value.status == pond.ERR_UNSUPPORTED
+
+
+def test_d2q25_state_size(pond):
+    p = pond.pond_params_default(nx=512, ny=512, lattice=25, precision=pond.PREC_FP32)
+    b32 = pond.pond_state_bytes(p)
+    # two buffers of 25 + 25 float planes and 3 double frame planes, 32 moment floats
+    assert 576 * 512 * 512 <= b32 < 576 * 512 * 512 + 16384
+    p.precision = pond.PREC_FP64
+    b64 = pond.pond_state_bytes(p)
+    assert 1088 * 512 * 512 <= b64 < 1088 * 512 * 512 + 16384
+    p.split, p.prandtl = 2, 1.0
+    assert pond.pond_state_bytes(p) == b64
 
 
 def test_internal_split_accepted_with_the_same_state_size(pond):

@@ -1,0 +1,166 @@
+"""GPU parity of the D2Q25 lattice (Table I, Grad order four) and of the
+non-translational energy split (Eq. nt_energy_g): the HIP path (through the
+C ABI) against the FP64 oracle on the same seeded inputs -- FP64 within 1e-12
+per population and frame plane, FP32 within 1e-5 relative on smooth flows --
+plus bitwise agreement between kernel variants and across export/import."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_11489_amd import workloads
+from parity_util import (field_errors, gpu_run, gpu_solver, oracle_params_for, oracle_run,
+                         plane_errors, to_oracle_state, velocity_scale)
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+TOTAL, NT = oracle.TOTAL, oracle.NONTRANS
+
+
+def modes(n, ny=None, mach=2.0, amp=1e-2, seed=0, tau=0.6, prandtl=1.0, T0=1.0, **kw):
+    return workloads.fourier_modes(n=n, ny=ny, mach=mach, amplitude=amp, seed=seed, tau=tau,
+                                   prandtl=prandtl, T0=T0, **kw)
+
+
+def clamp_x(w):
+    w.bc_x = workloads.CLAMP
+    return w
+
+
+def sod(nx=16, steps=4):
+    w = workloads.sod_tube(nx=nx, nu=2e-3, steps=steps)
+    w.prandtl = 1.0
+    return w
+
+
+CASES = {
+    "4x4_mach2": lambda: modes(4),
+    "7x5_clampx": lambda: clamp_x(modes(7, 5, mach=1.0, seed=3)),
+    "16x1_sod": lambda: sod(),
+    "1x1": lambda: modes(1, 1, mach=0.7),
+    "1x9_column": lambda: modes(1, 9, mach=1.5, seed=5),
+    "6x5_hot_fast": lambda: modes(6, 5, mach=1.2, T0=4.0, seed=7),
+    "9x7_cold": lambda: modes(9, 7, mach=0.5, T0=0.04, seed=8),
+    "8x8_gamma18": lambda: workloads.fourier_modes(n=8, mach=1.0, amplitude=1e-2, seed=2,
+                                                   tau=0.7, prandtl=1.0, gamma=1.8),
+}
+
+VARIANTS = [(25, TOTAL), (25, NT), (16, NT)]
+
+
+@pytest.mark.parametrize("lattice,split", VARIANTS)
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_fp64_tiny_grids_match_oracle(lattice, split, case):
+    w = CASES[case]()
+    for steps in (1, 4):
+        f, g, fr, _, st, m = gpu_run(w, FP64, steps, lattice=lattice, split=split)
+        P, s, ost = oracle_run(w, steps, lattice=lattice, split=split)
+        assert f.shape == (lattice, w.nodes)
+        assert max(plane_errors(f, g, fr, s)) <= 1e-12
+        assert st.nonphysical == 0 and ost.nonphysical == 0
+        errs = field_errors(m, oracle.moments(P, s))
+        assert max(errs.values()) <= 1e-12, errs
+
+
+def test_fp64_d2q25_total_split_with_prandtl():
+    """The total split's quasi-equilibrium (Pr != 1) on D2Q25."""
+    w = modes(9, 6, mach=1.5, seed=15, prandtl=0.71)
+    f, g, fr, _, _, _ = gpu_run(w, FP64, 4, lattice=25)
+    _, s, _ = oracle_run(w, 4, lattice=25)
+    assert max(plane_errors(f, g, fr, s)) <= 1e-12
+
+
+@pytest.mark.parametrize("split", [TOTAL, NT])
+def test_fp64_ragged_tiles(split):
+    """37 x 29 with clamp in x: several 32 x 8 tiles and ragged edges."""
+    w = clamp_x(modes(37, 29, mach=2.0, amp=1e-2, seed=13))
+    f, g, fr, _, _, _ = gpu_run(w, FP64, 4, lattice=25, split=split)
+    _, s, _ = oracle_run(w, 4, lattice=25, split=split)
+    assert max(plane_errors(f, g, fr, s)) <= 1e-12
+
+
+@pytest.mark.parametrize("lattice,split", VARIANTS)
+@pytest.mark.parametrize("case", ["4x4_mach2", "7x5_clampx", "6x5_hot_fast", "9x7_cold"])
+def test_fp32_tiny_grids_within_1e5(lattice, split, case):
+    w = CASES[case]()
+    _, _, _, _, _, m = gpu_run(w, FP32, 5, lattice=lattice, split=split)
+    P, s, _ = oracle_run(w, 5, lattice=lattice, split=split)
+    errs = field_errors(m, oracle.moments(P, s))
+    assert max(errs.values()) <= 1e-5, errs
+
+
+@pytest.mark.parametrize("lattice,split,prec,bar", [(25, TOTAL, FP64, 1e-12),
+                                                    (25, NT, FP64, 1e-12),
+                                                    (25, NT, FP32, 1e-5),
+                                                    (16, NT, FP32, 1e-5)])
+def test_full_size_sampled_nodes(lattice, split, prec, bar):
+    """512 x 512 Mach-2 modes: after a few GPU steps the oracle recomputes one
+    step at sampled nodes (corners included) from the GPU's own state."""
+    w = modes(512, mach=2.0, amp=1e-3, seed=0, tau=0.55)
+    rng = np.random.default_rng(3)
+    nodes = np.concatenate([rng.integers(0, w.nodes, 48),
+                            [0, w.nx - 1, w.nodes - w.nx, w.nodes - 1]])
+    with gpu_solver(w, prec, lattice=lattice, split=split) as sol:
+        sol.step(3)
+        f0, g0, fr0, _ = sol.export_state()
+        sol.step(1)
+        f1, g1, fr1, _ = sol.export_state()
+    P = oracle_params_for(w, lattice=lattice, split=split)
+    fo, go, lo, _, _ = oracle.step_nodes(P, to_oracle_state(f0, g0, fr0), nodes)
+    for a, b in ((f1[:, nodes].T, fo), (g1[:, nodes].T, go)):
+        assert np.max(np.abs(a - b) / np.max(np.abs(b), axis=0)) <= bar
+    vs = velocity_scale(lo[:, 0], lo[:, 1], lo[:, 2])
+    assert np.max(np.abs(fr1[:2, nodes].T - lo[:, :2])) / vs <= bar
+    assert np.max(np.abs(fr1[2, nodes] - lo[:, 2]) / lo[:, 2]) <= bar
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_kernels_and_tiles_bitwise_equal(prec):
+    from paper_2405_11489_amd import pond
+    w = clamp_x(modes(70, 45, mach=2.5, amp=2e-2, seed=12))
+    ref = gpu_run(w, prec, 3, lattice=25, split=NT, tuning={"kernel": pond.KERNEL_GLOBAL})
+    for tile, cap in [(pond.TILE_32x8, 0), (pond.TILE_16x16, 0), (pond.TILE_64x1, 0),
+                      (pond.TILE_8x8, 100)]:
+        out = gpu_run(w, prec, 3, lattice=25, split=NT,
+                      tuning={"kernel": pond.KERNEL_TILED, "tile": tile, "lds_nodes": cap})
+        for x, y in zip(out[:3], ref[:3]):
+            np.testing.assert_array_equal(x, y, err_msg=f"tile {tile} cap {cap}")
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_export_import_resume_bitwise(prec):
+    w = modes(40, 24, mach=1.5, amp=1e-2, seed=6)
+    with gpu_solver(w, prec, lattice=25, split=NT) as s:
+        s.step(5)
+        ref = s.export_state()
+    with gpu_solver(w, prec, lattice=25, split=NT) as s:
+        s.step(2)
+        f, g, fr, ur = s.export_state()
+    with gpu_solver(w, prec, lattice=25, split=NT) as s:
+        s.import_state(f, g, fr, ur)
+        s.step(3)
+        out = s.export_state()
+    for x, y in zip(out[:3], ref[:3]):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_batch_and_server_reject_d2q25_and_nontrans():
+    from paper_2405_11489_amd import pond
+    w = modes(16, 8, mach=1.0, seed=23)
+    for kw in ({"lattice": 25}, {"split": NT}):
+        a = gpu_solver(w, FP32, **kw)
+        try:
+            with pytest.raises(pond.PondError) as ei:
+                pond.pond_batch_create([a.ctx])
+            assert ei.value.status == pond.ERR_UNSUPPORTED
+        finally:
+            a.close()
+    srv = pond.pond_server_create(pond.pond_server_config_default())
+    try:
+        p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma, prandtl=1.0,
+                                     lattice=25)
+        with pytest.raises(pond.PondError) as ei:
+            pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, 4)
+        assert ei.value.status == pond.ERR_UNSUPPORTED
+    finally:
+        pond.pond_server_destroy(srv)
