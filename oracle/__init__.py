@@ -35,7 +35,11 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("prandtl", ctypes.c_double),
         ("gamma", ctypes.c_double), ("pc_tol", ctypes.c_double),
         ("split", ctypes.c_int), ("lattice", ctypes.c_int),
+        ("wall_ux", ctypes.c_double * 2), ("wall_T", ctypes.c_double * 2),
     ]
+
+
+PERIODIC, CLAMP, WALL = 0, 1, 2  # boundary handling (WALL: bc_y only)
 
 
 # energy splits (Eqs. total_energy_g, int_energy_g, nt_energy_g)
@@ -43,13 +47,21 @@ TOTAL, INTERNAL, NONTRANS = 0, 1, 2
 
 
 def params(nx, ny, *, tau, gamma=1.4, prandtl=1.0, bc_x=0, bc_y=0, interp_points=4,
-           pc_tol=1e-13, pc_max_iter=32, split=TOTAL, lattice=16) -> Params:
+           pc_tol=1e-13, pc_max_iter=32, split=TOTAL, lattice=16, wall_ux=(0.0, 0.0),
+           wall_T=(1.0, 1.0)) -> Params:
+    """bc_y = WALL: walls at y = -1/2 (bottom) and ny - 1/2 (top) moving along x
+    at wall_ux = (bottom, top) and held at wall_T = (bottom, top)."""
     if lattice not in (16, 25):
         raise ValueError("lattice must be 16 (D2Q16) or 25 (D2Q25)")
     if split == NONTRANS and prandtl != 1.0:
         raise ValueError("the non-translational split is built with Pr = 1 only")
+    if bc_x == WALL:
+        raise ValueError("walls are built for the y boundaries only")
+    if bc_y == WALL and split == INTERNAL:
+        raise ValueError("walls are built for the total and non-translational splits")
     return Params(nx, ny, bc_x, bc_y, interp_points, pc_max_iter, tau, prandtl, gamma, pc_tol,
-                  split, lattice)
+                  split, lattice, (ctypes.c_double * 2)(*wall_ux),
+                  (ctypes.c_double * 2)(*wall_T))
 
 
 def _q1(q):
@@ -108,7 +120,7 @@ def lib():
         L.oracle_init_split.restype = ctypes.c_int
         L.oracle_moments_split.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp, dp,
                                            ctypes.c_double, dp, dp, dp, dp, dp]
-        if L.oracle_abi_version() != 3:
+        if L.oracle_abi_version() != 4:
             raise RuntimeError("oracle library ABI mismatch; rebuild oracle/")
         _lib = L
     return _lib

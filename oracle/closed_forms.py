@@ -77,3 +77,12 @@ def longitudinal_modes(k: float, tau: float, T: float, gamma: float, prandtl: fl
     ac = ev[np.argmax(ev.imag)]
     ent = ev[np.argmin(np.abs(ev.imag))]
     return complex(ac), complex(ent)
+
+
+def couette_temperature(ny, y, T0, T1, Ec, prandtl):
+    """Thermal Couette flow between a wall at rest (T0, at y = -1/2) and a wall
+    moving along x (T1, at y = ny - 1/2), constant properties (the solution
+    quoted in Sec. "Measuring viscous heating"):
+    (T - T0)/(T1 - T0) = eta + Pr Ec / 2 eta (1 - eta), eta = (y + 1/2) / ny."""
+    eta = (np.asarray(y, dtype=float) + 0.5) / ny
+    return T0 + (T1 - T0) * (eta + 0.5 * prandtl * Ec * eta * (1.0 - eta))

@@ -46,7 +46,10 @@
  *     velocity of the node, grad u central differences of the time-t frame
  *     velocities of the four neighbours (wrapped or clamped like the stencil);
  *   - non-translational split: the paper's single-relaxation BGK only (Pr = 1;
- *     its quasi-equilibrium form is not given and not built here).
+ *     its quasi-equilibrium form is not given and not built here);
+ *   - walls (the thermal Couette flow of Sec. "Measuring viscous heating"; the
+ *     paper gives no boundary scheme): ghost nodes beyond the wall mirror the
+ *     interior, see ghost_node().
  *
  * Units: lattice units, dx = dt = 1, r = 1, T_L = 1 (Table I column rT_L).
  * Layout (oracle only): node n = y*nx + x; populations pop[n*Q + i] with
@@ -61,14 +64,14 @@
 #include <omp.h>
 #endif
 
-#define ORACLE_ABI 3
+#define ORACLE_ABI 4
 #define Q1 4      /* D1Q4 */
 #define Q 16      /* D2Q16 */
 #define QMAX 25   /* D2Q25 */
 
 typedef struct {
     int nx, ny;
-    int bc_x, bc_y;        /* 0 = periodic, 1 = clamp (zero-gradient) */
+    int bc_x, bc_y;        /* 0 = periodic, 1 = clamp (zero-gradient); bc_y = 2: walls */
     int interp_points;     /* 4 = cubic Lagrange, 3 = quadratic Lagrange */
     int pc_max_iter;       /* predictor-corrector iteration cap (>= 1) */
     double tau;            /* discrete relaxation time, > 1/2 */
@@ -79,6 +82,8 @@ typedef struct {
                               (Eq. int_energy_g), 2 = non-translational energy
                               (Eq. nt_energy_g) */
     int lattice;           /* 16 = D2Q16 (D1Q4 x D1Q4), 25 = D2Q25 (D1Q5 x D1Q5) */
+    double wall_ux[2];     /* bc_y = 2: x-velocity of the bottom / top wall */
+    double wall_T[2];      /* bc_y = 2: temperature of the bottom / top wall */
 } oracle_params;
 
 /* status bits per node written by oracle_step */
@@ -509,6 +514,59 @@ static int node_index(int i, int n, int bc)
  *   {f_i, g_i}(x) = sum_s W(y_i - x_s) [M_{lam_s -> lam_bar} {f, g}(x_s)]_i,
  * every stencil node transformed from its own frame lam_s.
  */
+/*
+ * Wall boundary (bc_y = 2).  Walls at y = -1/2 (bottom, index 0) and
+ * y = ny - 1/2 (top, index 1) move along x at wall_ux and are held at wall_T.
+ * The stencil node at row y = -1 - j (bottom) or ny + j (top), j >= 0, is a
+ * ghost mirroring interior row m = j or ny - 1 - j (clamped to the grid) of
+ * the same column:
+ *   - its frame continues the mirror node's through the wall linearly:
+ *     u_gx = 2 U_w - u_mx, u_gy = -u_my, T_g = 2 T_w - T_m (at least T_w / 4);
+ *   - its density keeps the mirror node's pressure: rho_g = rho_m T_m / T_g;
+ *   - its populations are the equilibrium of that state plus the mirror
+ *     node's non-equilibrium part carried into the ghost frame,
+ *       f_g = f^eq(rho_g, lam_g) + M_{lam_m -> lam_g}(f_m - f^eq(rho_m, lam_m)),
+ *     and g likewise with the split's g^eq.
+ */
+static void ghost_node(const oracle_params *P, const double *f, const double *g,
+                       const double *lam, int jx, int jy, double *fo, double *go, double *lo)
+{
+    double cx[QMAX], cy[QMAX], w[QMAX];
+    int q1 = q1_of(P->lattice);
+    int q = oracle_lattice_2d_q(q1, cx, cy, w);
+    int side = jy < 0 ? 0 : 1;
+    int m = side == 0 ? -1 - jy : 2 * P->ny - 1 - jy;
+    if (m < 0)
+        m = 0;
+    if (m > P->ny - 1)
+        m = P->ny - 1;
+    long s = (long)m * P->nx + jx;
+    const double *fm = f + (long)q * s, *gm = g + (long)q * s, *lm = lam + 3 * s;
+    double rho_m = 0.0;
+    for (int i = 0; i < q; i++)
+        rho_m += fm[i];
+    double Tg = 2.0 * P->wall_T[side] - lm[2];
+    if (Tg < 0.25 * P->wall_T[side])
+        Tg = 0.25 * P->wall_T[side];
+    lo[0] = 2.0 * P->wall_ux[side] - lm[0];
+    lo[1] = -lm[1];
+    lo[2] = Tg;
+    double rho_g = rho_m * lm[2] / Tg;
+    double feq[QMAX], geq[QMAX], fn[QMAX], gn[QMAX];
+    oracle_equilibrium_q(q1, P->split, rho_m, lm[0], lm[1], lm[2], P->gamma, feq, geq);
+    for (int i = 0; i < q; i++) {
+        fn[i] = fm[i] - feq[i];
+        gn[i] = gm[i] - geq[i];
+    }
+    oracle_transform_q(q1, fn, lm, lo, fn);
+    oracle_transform_q(q1, gn, lm, lo, gn);
+    oracle_equilibrium_q(q1, P->split, rho_g, lo[0], lo[1], lo[2], P->gamma, feq, geq);
+    for (int i = 0; i < q; i++) {
+        fo[i] = feq[i] + fn[i];
+        go[i] = geq[i] + gn[i];
+    }
+}
+
 static void gather(const oracle_params *P, const double *f, const double *g, const double *lam,
                    int x, int y, const double *lam_bar, double *ft, double *gt)
 {
@@ -527,12 +585,21 @@ static void gather(const oracle_params *P, const double *f, const double *g, con
         oracle_lagrange(np, yy, &by, wy);
         double sf = 0.0, sg = 0.0;
         for (int sy = 0; sy < np; sy++) {
-            int jy = node_index(by + sy, P->ny, P->bc_y);
+            int ry = by + sy;
+            int wall = P->bc_y == 2 && (ry < 0 || ry >= P->ny);
+            int jy = wall ? 0 : node_index(ry, P->ny, P->bc_y);
             for (int sx = 0; sx < np; sx++) {
                 int jx = node_index(bx + sx, P->nx, P->bc_x);
                 long s = (long)jy * P->nx + jx;
-                oracle_transform_q(q1, f + (long)q * s, lam + 3 * s, lam_bar, tf);
-                oracle_transform_q(q1, g + (long)q * s, lam + 3 * s, lam_bar, tg);
+                if (wall) {
+                    double fgh[QMAX], ggh[QMAX], lgh[3];
+                    ghost_node(P, f, g, lam, jx, ry, fgh, ggh, lgh);
+                    oracle_transform_q(q1, fgh, lgh, lam_bar, tf);
+                    oracle_transform_q(q1, ggh, lgh, lam_bar, tg);
+                } else {
+                    oracle_transform_q(q1, f + (long)q * s, lam + 3 * s, lam_bar, tf);
+                    oracle_transform_q(q1, g + (long)q * s, lam + 3 * s, lam_bar, tg);
+                }
                 double W = wx[sx] * wy[sy];
                 sf += W * tf[i];
                 sg += W * tg[i];

@@ -19,6 +19,9 @@ Workloads
 * ``riemann_quadrants`` -- 2-D four-quadrant Riemann problem with seeded states.
 * ``batch_instances`` / ``serving_requests`` -- mixes of the above with
   log-uniform sizes, for the batched and served paths.
+* ``thermal_couette`` -- channel between a wall at rest (T0) and a wall moving
+  along x (T1) at the speed of a given Eckert number (Sec. "Measuring viscous
+  heating").
 """
 from __future__ import annotations
 
@@ -27,7 +30,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-PERIODIC, CLAMP = 0, 1
+PERIODIC, CLAMP, WALL = 0, 1, 2
 
 
 @dataclass
@@ -47,6 +50,8 @@ class Workload:
     T: np.ndarray
     modes: list = field(default_factory=list)
     meta: dict = field(default_factory=dict)
+    wall_ux: tuple = (0.0, 0.0)   # bc_y == WALL: (bottom, top) wall x-velocity
+    wall_T: tuple = (1.0, 1.0)    # bc_y == WALL: (bottom, top) wall temperature
 
     @property
     def nodes(self) -> int:
@@ -309,3 +314,29 @@ def serving_requests(seed=0, count=256, size_range=(64, 2048), steps_range=(100,
         w.meta["request"] = i
         out.append((t, w))
     return out
+
+
+def thermal_couette(ny=32, nx=1, Ec=8.0, T0=1.0, T1=1.005, tau=0.8, gamma=1.4, prandtl=1.0,
+                    steps=None):
+    """Thermal Couette flow: walls at y = -1/2 (at rest, T0) and y = ny - 1/2
+    (moving along x at u0, T1), periodic in x; u0 from the Eckert number
+    Ec = u0^2 / ((c_v + r) (T1 - T0)).  Starts from the linear velocity and
+    temperature profiles at uniform pressure 1; ``steps`` defaults to
+    1.2 ny^2 / alpha (alpha = (tau - 1/2) T / Pr), long enough for the
+    slowest thermal mode to decay by ~e^-12."""
+    cv = 1.0 / (gamma - 1.0)
+    dT = T1 - T0
+    u0 = math.sqrt(Ec * (cv + 1.0) * dT)
+    _, Y = _grid(nx, ny)
+    eta = (Y + 0.5) / ny
+    T = T0 + dT * eta
+    rho = 1.0 / T
+    ux = u0 * eta
+    uy = np.zeros_like(T)
+    alpha = (tau - 0.5) * T0 / prandtl
+    if steps is None:
+        steps = int(math.ceil(1.2 * ny * ny / alpha))
+    return Workload("thermal_couette", nx, ny, PERIODIC, WALL, gamma, prandtl, tau, steps,
+                    rho, ux, uy, T, meta={"u0": u0, "Ec": Ec, "T0": T0, "T1": T1},
+                    wall_ux=(0.0, u0), wall_T=(T0, T1))
+

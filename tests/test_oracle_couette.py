@@ -1,0 +1,85 @@
+"""Pins of the oracle's wall boundary (bc_y = WALL, a reading: the paper gives
+no boundary scheme) against the thermal Couette flow of Sec. "Measuring
+viscous heating": a wall at rest at T0 below, a wall moving along x at u0 and
+T1 above.  The pins are what the Navier-Stokes-Fourier system fixes: a fluid at
+rest between walls at its own temperature stays at rest, the steady velocity
+profile is linear, and the steady temperature converges to the analytical
+profile T0 + (T1 - T0)(eta + Pr Ec / 2 eta (1 - eta)) as the channel is
+resolved (first order in 1/ny with the mirror ghost closure: recorded)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import closed_forms as cf
+from paper_2405_11489_amd import workloads
+
+
+def _params(w, **kw):
+    return oracle.params(w.nx, w.ny, tau=w.tau, gamma=w.gamma, prandtl=w.prandtl, bc_x=w.bc_x,
+                         bc_y=w.bc_y, wall_ux=w.wall_ux, wall_T=w.wall_T, **kw)
+
+
+def steady(w, **kw):
+    P = _params(w, **kw)
+    s = oracle.init(P, w.rho.ravel(), w.ux.ravel(), w.uy.ravel(), w.T.ravel())
+    s, st = oracle.step(P, s, w.steps)
+    assert st.nonphysical == 0
+    return oracle.moments(P, s)
+
+
+def temperature_error(w, m):
+    y = np.arange(w.ny)
+    Ta = cf.couette_temperature(w.ny, y, w.meta["T0"], w.meta["T1"], w.meta["Ec"], w.prandtl)
+    return np.max(np.abs(m["T"][:, 0] - Ta)) / (Ta.max() - w.meta["T0"])
+
+
+@pytest.mark.parametrize("split", [oracle.TOTAL, oracle.NONTRANS])
+def test_fluid_at_rest_between_walls_at_its_temperature_stays_at_rest(split):
+    w = workloads.thermal_couette(ny=10, nx=3, Ec=8.0, steps=20)
+    w.rho[:] = 1.0
+    w.ux[:] = 0.0
+    w.T[:] = 1.3
+    w.wall_ux, w.wall_T = (0.0, 0.0), (1.3, 1.3)
+    P = _params(w, split=split)
+    s = oracle.init(P, w.rho.ravel(), w.ux.ravel(), w.uy.ravel(), w.T.ravel())
+    s1, st = oracle.step(P, s, w.steps)
+    np.testing.assert_allclose(s1.f, s.f, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(s1.g, s.g, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(s1.lam, s.lam, rtol=1e-12, atol=1e-14)
+
+
+def test_couette_velocity_profile_is_linear():
+    w = workloads.thermal_couette(ny=16, Ec=8.0)
+    m = steady(w)
+    y = np.arange(w.ny)
+    ua = w.meta["u0"] * (y + 0.5) / w.ny
+    assert np.max(np.abs(m["ux"][:, 0] - ua)) <= 1e-3 * w.meta["u0"]
+    assert np.max(np.abs(m["uy"])) <= 1e-3 * w.meta["u0"]
+
+
+@pytest.mark.parametrize("Ec,split", [(72.0, oracle.TOTAL), (72.0, oracle.NONTRANS),
+                                      (8.0, oracle.TOTAL)])
+def test_couette_temperature_converges_to_the_analytical_profile(Ec, split):
+    """Recorded: the error is first order in 1/ny (the odd mirror of T kinks its
+    curvature at the wall): at Ec = 72, 6.1 % / 3.3 % / 1.7 % of the heating
+    amplitude at ny = 8 / 16 / 32 (total split)."""
+    errs = []
+    for ny in (8, 16):
+        w = workloads.thermal_couette(ny=ny, Ec=Ec)
+        errs.append(temperature_error(w, steady(w, split=split)))
+    assert errs[1] <= 0.035
+    assert errs[0] / errs[1] >= 1.35
+
+
+def test_heated_walls_let_mass_in():
+    """Recorded finding: the ghost keeps the mirror node's pressure, so next to
+    a fluid heated above the wall temperature the ghost is denser and mass
+    enters through the wall; the gain halves as the channel is refined
+    (steady Ec = 72 runs: +12 % at ny = 8, +5.6 % at ny = 16)."""
+    gains = []
+    for ny in (8, 16):
+        w = workloads.thermal_couette(ny=ny, Ec=72.0)
+        m0 = w.rho.mean()
+        gains.append(steady(w)["rho"].mean() / m0 - 1.0)
+    assert 0.0 < gains[1] < gains[0] < 0.15
+    assert gains[0] / gains[1] > 1.7
