@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define POND_ABI_VERSION 1
+#define POND_ABI_VERSION 2
 
 /* Exported symbols (the library is built with hidden default visibility). */
 #if defined(__GNUC__)
@@ -97,13 +97,25 @@ enum { POND_PREC_FP64 = 0, POND_PREC_FP32 = 1 };
 
 /* Boundary handling per axis: periodic wrap, or clamp (zero-gradient: a
  * stencil index beyond the edge is replaced by the edge node, populations and
- * frame alike). */
-enum { POND_BC_PERIODIC = 0, POND_BC_CLAMP = 1 };
+ * frame alike), or (bc_y only) walls, for the thermal Couette flow of Sec.
+ * "Measuring viscous heating" (the paper gives no boundary scheme; this one is
+ * a reading).  Walls at y = -1/2 (bottom) and y = ny - 1/2 (top) move along x
+ * at wall_ux[0 | 1] and are held at wall_T[0 | 1].  A stencil row beyond a wall
+ * is a ghost mirroring the interior row at the same distance: its velocity and
+ * temperature continue the mirror node's linearly through the wall
+ * (u_g = 2 U_w - u_m with the normal component reversed, T_g = 2 T_w - T_m, at
+ * least T_w / 4), its density keeps the mirror's pressure, and its moments are
+ * the equilibrium moments of that state plus the mirror's non-equilibrium
+ * moments.  The ghost rows reach 8 rows beyond each wall (further stencil rows
+ * read the last one): enough while c_out sqrt(T) + |u_y| + 3 <= 8 at the
+ * walls (c_out = 2.33 on D2Q16, 2.86 on D2Q25).  Walls run the total or the
+ * non-translational split, single instances only. */
+enum { POND_BC_PERIODIC = 0, POND_BC_CLAMP = 1, POND_BC_WALL = 2 };
 
 typedef struct {
     uint32_t struct_size;  /* = sizeof(pond_params); ABI guard */
     int32_t nx, ny;        /* nodes per axis, >= 1; ny == 1 is a quasi-1-D run */
-    int32_t bc_x, bc_y;    /* POND_BC_* */
+    int32_t bc_x, bc_y;    /* POND_BC_*; POND_BC_WALL for bc_y only */
     int32_t lattice;       /* POND_LATTICE_D2Q16 (default) or POND_LATTICE_D2Q25 */
     int32_t interp_points; /* 4 = cubic Lagrange (default); 3 = quadratic, the paper's
                               "2nd-order" stencil (end of Sec. "Streaming") */
@@ -126,6 +138,8 @@ typedef struct {
                               T_E = E / (rho c_v), the scale of the energy T is
                               recovered from (T + |u|^2 / (2 c_v) in the total split,
                               T in the internal split) */
+    double wall_ux[2];     /* bc_y = POND_BC_WALL: x-velocity of the bottom / top wall */
+    double wall_T[2];      /* bc_y = POND_BC_WALL: temperature of the bottom / top wall, > 0 */
 } pond_params;
 
 /* Per-context counters since the last pond_init_fields / pond_import_state. */

@@ -44,12 +44,12 @@ pond_status hip_fail(hipError_t e, const char *what) {
 
 const char *last_error() { return g_last_error.c_str(); }
 
-Layout layout_for(long long N, size_t psize, int lattice) {
+Layout layout_for(long long N, size_t psize, int lattice, long long mom_nodes) {
     Layout L;
     L.pop_bytes = align_up(size_t(N) * size_t(lattice) * psize);
     L.frame_bytes = align_up(size_t(N) * sizeof(double));
     L.buf_bytes = 2 * L.pop_bytes + 3 * L.frame_bytes;
-    L.mom_bytes = align_up(size_t(N) * moment_values(lattice, psize == 8) * psize);
+    L.mom_bytes = align_up(size_t(mom_nodes) * moment_values(lattice, psize == 8) * psize);
     L.cnt_off = 2 * L.buf_bytes + L.mom_bytes;
     L.scratch_off = L.cnt_off + align_up(sizeof(DevCounters));
     L.total = L.scratch_off + align_up(kScratchDoubles * sizeof(double));
@@ -100,8 +100,15 @@ pond_status validate(const pond_params *p) {
     if ((long long)p->nx * p->ny > 0x7fffffffll)
         return fail(POND_ERR_INVALID_ARG, "nx * ny must stay below 2^31");
     if ((p->bc_x != POND_BC_PERIODIC && p->bc_x != POND_BC_CLAMP) ||
-        (p->bc_y != POND_BC_PERIODIC && p->bc_y != POND_BC_CLAMP))
-        return fail(POND_ERR_INVALID_ARG, "bc_x / bc_y must be POND_BC_PERIODIC or POND_BC_CLAMP");
+        (p->bc_y != POND_BC_PERIODIC && p->bc_y != POND_BC_CLAMP && p->bc_y != POND_BC_WALL))
+        return fail(POND_ERR_INVALID_ARG,
+                    "bc_x must be POND_BC_PERIODIC or POND_BC_CLAMP, bc_y also POND_BC_WALL");
+    if (p->bc_y == POND_BC_WALL) {
+        for (int k = 0; k < 2; ++k)
+            if (!(p->wall_T[k] > 0.0) || !std::isfinite(p->wall_T[k]) ||
+                !std::isfinite(p->wall_ux[k]))
+                return fail(POND_ERR_INVALID_ARG, "wall_T must be finite and > 0, wall_ux finite");
+    }
     if (p->lattice != POND_LATTICE_D2Q16 && p->lattice != POND_LATTICE_D2Q25) {
         if (p->lattice == 9)
             return fail(POND_ERR_UNSUPPORTED, "lattice 9 is not implemented (D2Q16, D2Q25)");
@@ -121,6 +128,8 @@ pond_status validate(const pond_params *p) {
     if (p->split == POND_SPLIT_NONTRANS && p->prandtl != 1.0)
         return fail(POND_ERR_UNSUPPORTED,
                     "the non-translational split is built with Pr = 1 (the paper's BGK) only");
+    if (p->bc_y == POND_BC_WALL && p->split == POND_SPLIT_INTERNAL)
+        return fail(POND_ERR_UNSUPPORTED, "walls run the total or non-translational split");
     if (p->lattice == POND_LATTICE_D2Q25 && p->split == POND_SPLIT_INTERNAL)
         return fail(POND_ERR_UNSUPPORTED, "D2Q25 runs the total or non-translational split");
     if (p->lattice == POND_LATTICE_D2Q25 && p->interp_points != 4)
@@ -164,6 +173,13 @@ void fill_args(pond_ctx *c) {
     a.unit_prandtl = p.prandtl == 1.0;
     a.split = p.split;
     a.lattice = p.lattice;
+    a.wall_h = p.bc_y == POND_BC_WALL ? kWallGhostRows : 0;
+    a.moff = (long long)a.wall_h * p.nx;
+    a.mstride = moment_plane_nodes(p);
+    for (int k = 0; k < 2; ++k) {
+        a.wall_ux[k] = p.wall_ux[k];
+        a.wall_T[k] = p.wall_T[k];
+    }
     a.cv = 1.0 / (p.gamma - 1.0);
     a.uref_x = a.uref_y = 0.0;
 }
@@ -320,13 +336,14 @@ pond_status pond_params_default(pond_params *p) {
     p->prandtl = 1.0;
     p->gamma = 1.4;
     p->pc_tol = 0.0;
+    p->wall_T[0] = p->wall_T[1] = 1.0;
     return POND_OK;
 }
 
 size_t pond_state_bytes(const pond_params *p) {
     if (validate(p) != POND_OK) return 0;
     const size_t psize = p->precision == POND_PREC_FP64 ? sizeof(double) : sizeof(float);
-    return layout_for((long long)p->nx * p->ny, psize, p->lattice).total;
+    return layout_for((long long)p->nx * p->ny, psize, p->lattice, moment_plane_nodes(*p)).total;
 }
 
 pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem,
@@ -337,7 +354,7 @@ pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem
     if (s != POND_OK) return s;
     const size_t psize = p->precision == POND_PREC_FP64 ? sizeof(double) : sizeof(float);
     const long long N = (long long)p->nx * p->ny;
-    Layout L = layout_for(N, psize, p->lattice);
+    Layout L = layout_for(N, psize, p->lattice, moment_plane_nodes(*p));
     if (device_mem) {
         if (device_mem_bytes < L.total)
             return fail(POND_ERR_OUT_OF_MEMORY, "device_mem holds %zu bytes, %zu needed",
@@ -484,6 +501,9 @@ hipError_t enqueue_step(pond_ctx *c) {
         if (e == hipSuccess) e = hipEventRecord(ev[0], c->stream);
     }
     if (e == hipSuccess) e = fp64(c) ? launch_prepass_t<double>(c, src) : launch_prepass_t<float>(c, src);
+    if (e == hipSuccess && c->args.wall_h)
+        e = fp64(c) ? launch_wall_ghosts<double>(c->args, src, static_cast<double *>(c->mom), c->stream)
+                    : launch_wall_ghosts<float>(c->args, src, static_cast<float *>(c->mom), c->stream);
     if (e == hipSuccess && c->profiling) e = hipEventRecord(ev[1], c->stream);
     if (e == hipSuccess)
         e = fp64(c) ? launch_step_t<double>(c, src, dst) : launch_step_t<float>(c, src, dst);

@@ -37,7 +37,15 @@ constexpr int kScratchDoubles = 3 * 256;
 // D2Q25 32 floats or 30 doubles.
 inline int moment_values(int lattice, bool dbl) { return lattice == 25 ? (dbl ? 30 : 32) : 20; }
 
-Layout layout_for(long long N, size_t psize, int lattice);
+// Ghost rows of the moment planes beyond each wall (bc_y == POND_BC_WALL).
+constexpr int kWallGhostRows = 8;
+
+// Nodes per moment plane: the grid, plus the ghost rows with walls.
+inline long long moment_plane_nodes(const pond_params &p) {
+    return (long long)p.nx * (p.ny + (p.bc_y == POND_BC_WALL ? 2 * kWallGhostRows : 0));
+}
+
+Layout layout_for(long long N, size_t psize, int lattice, long long mom_nodes);
 
 // LDS nodes per block (the moment groups of one node each) that let
 // blocks_per_cu blocks share the 160 KiB of a CU.

@@ -38,6 +38,10 @@ struct StepArgs {
     int split;           // 0: total energy in g; 1: internal energy in g (plus its source);
                          // 2: non-translational energy in g
     int lattice;         // 16 (D2Q16) or 25 (D2Q25)
+    long long mstride;   // nodes per moment plane: N, or (ny + 2 wall_h) nx with walls
+    long long moff;      // node offset of grid row 0 in a moment plane (wall_h nx)
+    int wall_h;          // ghost rows beyond each wall (bc_y == 2), else 0
+    double wall_ux[2], wall_T[2];
     double cv;           // 1 / (gamma - 1)
     double uref_x, uref_y;
 };
@@ -104,6 +108,10 @@ hipError_t launch_init(const StepArgs &a, const double *rho, const double *ux, c
                        const double *T, DevState st, DevCounters *cnt, hipStream_t s);
 template <typename P>
 hipError_t launch_moments_prepass(const StepArgs &a, DevState st, P *mom, hipStream_t s);
+// Ghost rows of the moment planes beyond walls (bc_y == 2), from the moments
+// the pre-pass wrote; launched after it.
+template <typename P>
+hipError_t launch_wall_ghosts(const StepArgs &a, DevState st, P *mom, hipStream_t s);
 template <typename P>
 hipError_t launch_step(const StepArgs &a, DevState src, const P *mom, DevState dst, DevCounters *cnt,
                        hipStream_t s);

@@ -93,6 +93,12 @@ hipError_t launch_moments_prepass(const StepArgs &a, DevState st, P *mom, hipStr
 }
 
 template <typename P>
+hipError_t launch_wall_ghosts(const StepArgs &a, DevState st, P *mom, hipStream_t s) {
+    return a.lattice == 25 ? Launch<P, D2Q25>::wall_ghosts(a, st, mom, s)
+                           : Launch<P, D2Q16>::wall_ghosts(a, st, mom, s);
+}
+
+template <typename P>
 hipError_t launch_step(const StepArgs &a, DevState src, const P *mom, DevState dst,
                        DevCounters *cnt, hipStream_t s) {
     return a.lattice == 25 ? Launch<P, D2Q25>::step(a, src, mom, dst, cnt, s)
@@ -171,6 +177,7 @@ hipError_t launch_state_mean_velocity(const StepArgs &a, DevState st, double *sc
                                        const double *, const double *, DevState, DevCounters *,    \
                                        hipStream_t);                                               \
     template hipError_t launch_moments_prepass<P>(const StepArgs &, DevState, P *, hipStream_t);   \
+    template hipError_t launch_wall_ghosts<P>(const StepArgs &, DevState, P *, hipStream_t);       \
     template hipError_t launch_step<P>(const StepArgs &, DevState, const P *, DevState,            \
                                        DevCounters *, hipStream_t);                                \
     template hipError_t launch_step_tiled<P>(const StepArgs &, const TileConfig &, DevState,       \

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
         l1 = src.uy[n];
         l2 = src.T[n];
     }
-    const GlobalTaps<P, NP, L> taps{mom, a.N, a.nx, a.ny, a.bc_x, a.bc_y};
+    const GlobalTaps<P, NP, L> taps{mom, a.mstride, a.nx, a.ny, a.bc_x, a.bc_y, a.moff, a.wall_h};
     node_step<P, NP, S, L>(a, taps, x, y, n, live, l0, l1, l2, src, dst, cnt);
 }
 
@@ -123,6 +123,77 @@ __global__ __launch_bounds__(TX *TY) POND_TILED_ATTR(P, S) void step_tiled_kerne
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     tile_step<P, NP, S, L>(a, src, mom, dst, cnt, reinterpret_cast<P *>(smem_raw), cap,
                            (tile % tiles_x) * TX, (tile / tiles_x) * TY, FixedShape<TX, TY>{}, red);
+}
+
+// ------------------------------------------------------ wall ghosts ----
+// Moments of the ghost rows beyond the walls (bc_y == 2): one lane per ghost
+// node (column x, depth j, wall).  The ghost at row -1 - j (bottom) or ny + j
+// (top) mirrors interior row m = j or ny - 1 - j (clamped): frame
+// u_g = (2 U_w - u_mx, -u_my), T_g = max(2 T_w - T_m, T_w / 4), density
+// rho_g = rho_m T_m / T_g (the mirror's pressure), moments
+// M_g = M_m + M^eq(rho_g, lam_g) - M^eq(rho_m, lam_m) for f and g (the
+// equilibrium moments from the split's equilibrium populations), about u_ref.
+template <typename P, class L>
+__global__ __launch_bounds__(kBlock) void wall_ghost_kernel(StepArgs a, DevState st,
+                                                            P *__restrict__ mom) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long per_wall = (long long)a.wall_h * a.nx;
+    if (t >= 2 * per_wall) return;
+    const int side = t >= per_wall ? 1 : 0;
+    const long long r = t - side * per_wall;
+    const int j = int(r / a.nx), x = int(r % a.nx);
+    int m = side == 0 ? j : a.ny - 1 - j;
+    m = m < 0 ? 0 : (m > a.ny - 1 ? a.ny - 1 : m);
+    const int gy = side == 0 ? -1 - j : a.ny + j;
+    const long long nm = (long long)m * a.nx + x;
+    constexpr int NM = L::NM;
+    constexpr int NPAD = nmom_padded<P, L>();
+    P Mm[NPAD];
+    load_moments<P, nmom<L>()>(mom, a.mstride, a.moff + nm, Mm);
+    const double um0 = st.ux[nm], um1 = st.uy[nm], Tm = st.T[nm];
+    const double rho_m = double(Mm[0]);
+    double Tg = 2.0 * a.wall_T[side] - Tm;
+    if (Tg < 0.25 * a.wall_T[side]) Tg = 0.25 * a.wall_T[side];
+    const double ug0 = 2.0 * a.wall_ux[side] - um0, ug1 = -um1;
+    const double rho_g = rho_m * Tm / Tg;
+    const double sm = sqrt(Tm), sg = sqrt(Tg);
+    double D[2 * NM];
+#pragma unroll
+    for (int k = 0; k < 2 * NM; ++k) D[k] = 0.0;
+    const double kin = a.split == 2 ? 0.0 : 0.5;
+    for (int i = 0; i < L::Q; ++i) {
+        const double w = L::w(i / L::Q1) * L::w(i % L::Q1);
+        const double cx = L::c(i / L::Q1), cy = L::c(i % L::Q1);
+        // ghost and mirror equilibria: f^eq = rho w, g^eq of the split (lab velocity C)
+        const double Cgx = sg * cx + ug0, Cgy = sg * cy + ug1;
+        const double Cmx = sm * cx + um0, Cmy = sm * cy + um1;
+        const double fg = rho_g * w, fm = rho_m * w;
+        const double gg = w * (rho_g * (a.cv - 1.0) * Tg + kin * rho_g * (Cgx * Cgx + Cgy * Cgy));
+        const double gm = w * (rho_m * (a.cv - 1.0) * Tm + kin * rho_m * (Cmx * Cmx + Cmy * Cmy));
+        const double Vgx = Cgx - a.uref_x, Vgy = Cgy - a.uref_y;
+        const double Vmx = Cmx - a.uref_x, Vmy = Cmy - a.uref_y;
+#pragma unroll
+        for (int k = 0; k < NM; ++k) {
+            const int p = mom_px(k), q = mom_py(k);
+            double mg = 1.0, mm = 1.0;
+            for (int e = 0; e < p; ++e) {
+                mg *= Vgx;
+                mm *= Vmx;
+            }
+            for (int e = 0; e < q; ++e) {
+                mg *= Vgy;
+                mm *= Vmy;
+            }
+            D[k] += fg * mg - fm * mm;
+            D[NM + k] += gg * mg - gm * mm;
+        }
+    }
+    P Mg[NPAD];
+#pragma unroll
+    for (int k = 0; k < NPAD; ++k) Mg[k] = P(0);
+#pragma unroll
+    for (int k = 0; k < 2 * NM; ++k) Mg[k] = P(double(Mm[k]) + D[k]);
+    store_moments<P, nmom<L>()>(mom, a.mstride, a.moff + (long long)gy * a.nx + x, Mg);
 }
 
 // ------------------------------------------------------ macroscopic ----
@@ -283,6 +354,7 @@ struct Launch {
                            const double *uy, const double *T, DevState st, DevCounters *cnt,
                            hipStream_t s);
     static hipError_t moments(const StepArgs &a, DevState st, P *mom, hipStream_t s);
+    static hipError_t wall_ghosts(const StepArgs &a, DevState st, P *mom, hipStream_t s);
     static hipError_t step(const StepArgs &a, DevState src, const P *mom, DevState dst,
                            DevCounters *cnt, hipStream_t s);
     static hipError_t step_tiled(const StepArgs &a, const TileConfig &tc, DevState src,
@@ -311,6 +383,15 @@ hipError_t Launch<P, L>::init(const StepArgs &a, const double *rho, const double
 template <typename P, class L>
 hipError_t Launch<P, L>::moments(const StepArgs &a, DevState st, P *mom, hipStream_t s) {
     hipLaunchKernelGGL((lk::moments_kernel<P, L>), dim3(lk::grid_for(a.N)), dim3(lk::kBlock), 0,
+                       s, a, st, mom);
+    return hipGetLastError();
+}
+
+template <typename P, class L>
+hipError_t Launch<P, L>::wall_ghosts(const StepArgs &a, DevState st, P *mom, hipStream_t s) {
+    const long long n = 2LL * a.wall_h * a.nx;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((lk::wall_ghost_kernel<P, L>), dim3(lk::grid_for(n)), dim3(lk::kBlock), 0,
                        s, a, st, mom);
     return hipGetLastError();
 }

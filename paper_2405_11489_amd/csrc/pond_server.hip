@@ -311,7 +311,8 @@ pond_status pond_server_submit(pond_server *s, const pond_params *p, const doubl
         return fail(POND_ERR_INVALID_ARG,
                     "request precision / interp_points differ from the server's (%d / %d)",
                     s->cfg.precision, s->cfg.interp_points);
-    if (p->split != POND_SPLIT_TOTAL || p->lattice != POND_LATTICE_D2Q16)
+    if (p->split != POND_SPLIT_TOTAL || p->lattice != POND_LATTICE_D2Q16 ||
+        p->bc_y == POND_BC_WALL)
         return fail(POND_ERR_UNSUPPORTED,
                     "the server runs D2Q16 total-energy-split requests only");
     if (bytes > size_t(s->cfg.hbm_budget_bytes))

@@ -128,11 +128,21 @@ __device__ __forceinline__ const auto &ltab() {
 // Tap source reading the HBM moment planes with periodic / clamp wrapping.
 // gather() accumulates sum_{p,q} wx[p] wy[q] M(bx + p, by + q) for the NP x NP
 // stencil whose first node is (bx, by) in unwrapped grid coordinates.
+// Moment-plane row of the (unwrapped) grid row y: periodic wrap, clamp, or with
+// walls (bc 2) the ghost rows -wall_h .. -1 and ny .. ny + wall_h - 1 around
+// the grid (rows further out read the last ghost row).
+__device__ __forceinline__ int mom_row(int y, int ny, int bc, int wall_h) {
+    if (bc == 2) return min(max(y, -wall_h), ny + wall_h - 1);
+    return wrap_index(y, ny, bc);
+}
+
 template <typename P, int NP, class L = D2Q16>
 struct GlobalTaps {
     const P *mom;
-    long long N;
+    long long N;  // nodes per moment plane
     int nx, ny, bc_x, bc_y;
+    long long moff;  // node offset of grid row 0
+    int wall_h;
 
     __device__ __forceinline__ void gather(int bx, int by, const P wx[NP], const P wy[NP],
                                            P Mf[L::NM], P Mg[L::NM]) const {
@@ -141,7 +151,7 @@ struct GlobalTaps {
         for (int j = 0; j < NP; ++j) col[j] = wrap_index(bx + j, nx, bc_x);
 #pragma unroll POND_ROW_UNROLL
         for (int q = 0; q < NP; ++q) {
-            const long long row = (long long)wrap_index(by + q, ny, bc_y) * nx;
+            const long long row = moff + (long long)mom_row(by + q, ny, bc_y, wall_h) * nx;
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const P W = wx[p] * wy[q];

@@ -185,7 +185,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const
         stencil_extent<NP, L>(x, l0, s, lx, hx);
         stencil_extent<NP, L>(y, l1, s, ly, hy);
     }
-    const bool flat_y = a.ny == 1;
+    const bool flat_y = a.ny == 1 && a.bc_y != 2;  // walls: the ghost rows differ
     int X0 = block_min(lx, red);
     int X1 = -block_min(-hx, red + 4);
     int Y0 = block_min(ly, red + 8);
@@ -196,15 +196,16 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const
 
     for (int idx = threadIdx.x; idx < W * H; idx += nthreads) {
         const int gx = wrap_index(X0 + idx % W, a.nx, a.bc_x);
-        const int gy = wrap_index(Y0 + idx / W, a.ny, a.bc_y);
+        const int gy = mom_row(Y0 + idx / W, a.ny, a.bc_y, a.wall_h);
         P M[nmom_padded<P, L>()];
-        load_moments<P, nmom<L>()>(mom, a.N, (long long)gy * a.nx + gx, M);
+        load_moments<P, nmom<L>()>(mom, a.mstride, a.moff + (long long)gy * a.nx + gx, M);
         store_moments<P, nmom<L>()>(lds, cap, idx, M);
     }
     __syncthreads();
 
-    const TileTaps<P, NP, L> taps{lds, cap, X0, Y0, X1, Y1, W, flat_y,
-                                  GlobalTaps<P, NP, L>{mom, a.N, a.nx, a.ny, a.bc_x, a.bc_y}};
+    const TileTaps<P, NP, L> taps{
+        lds, cap, X0, Y0, X1, Y1, W, flat_y,
+        GlobalTaps<P, NP, L>{mom, a.mstride, a.nx, a.ny, a.bc_x, a.bc_y, a.moff, a.wall_h}};
     node_step<P, NP, S, L>(a, taps, x, y, n, live, l0, l1, l2, src, dst, cnt);
 }
 
@@ -246,7 +247,7 @@ __device__ __forceinline__ void node_moments(const StepArgs &a, DevState st, P *
             M[NM + k] += gi * mono[k];
         }
     }
-    store_moments<P, nmom<L>()>(mom, a.N, n, M);
+    store_moments<P, nmom<L>()>(mom, a.mstride, a.moff + n, M);
 }
 
 }  // namespace pond

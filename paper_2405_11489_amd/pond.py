@@ -24,8 +24,8 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NONPHYS
 LATTICE_D2Q16, LATTICE_D2Q25 = 16, 25
 SPLIT_TOTAL, SPLIT_INTERNAL, SPLIT_NONTRANS = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
-BC_PERIODIC, BC_CLAMP = 0, 1
-ABI_VERSION = 1
+BC_PERIODIC, BC_CLAMP, BC_WALL = 0, 1, 2
+ABI_VERSION = 2
 
 EXPORTED = [
     "pond_abi_version", "pond_params_default", "pond_state_bytes", "pond_create",
@@ -51,7 +51,8 @@ class pond_params(ctypes.Structure):
         ("interp_points", ctypes.c_int32), ("split", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("pc_max_iter", ctypes.c_int32),
         ("tau", ctypes.c_double), ("prandtl", ctypes.c_double), ("gamma", ctypes.c_double),
-        ("pc_tol", ctypes.c_double),
+        ("pc_tol", ctypes.c_double), ("wall_ux", ctypes.c_double * 2),
+        ("wall_T", ctypes.c_double * 2),
     ]
 
 
@@ -388,12 +389,14 @@ class Solver:
 
     def __init__(self, nx, ny, *, tau, gamma=1.4, prandtl=1.0, bc_x=BC_PERIODIC,
                  bc_y=BC_PERIODIC, precision=PREC_FP32, interp_points=4, pc_tol=0.0,
-                 pc_max_iter=32, split=SPLIT_TOTAL, lattice=LATTICE_D2Q16, stream=None,
-                 tuning=None):
+                 pc_max_iter=32, split=SPLIT_TOTAL, lattice=LATTICE_D2Q16, wall_ux=(0.0, 0.0),
+                 wall_T=(1.0, 1.0), stream=None, tuning=None):
         self.params = pond_params_default(nx=nx, ny=ny, tau=tau, gamma=gamma, prandtl=prandtl,
                                           bc_x=bc_x, bc_y=bc_y, precision=precision,
                                           interp_points=interp_points, pc_tol=pc_tol,
-                                          pc_max_iter=pc_max_iter, split=split, lattice=lattice)
+                                          pc_max_iter=pc_max_iter, split=split, lattice=lattice,
+                                          wall_ux=(ctypes.c_double * 2)(*wall_ux),
+                                          wall_T=(ctypes.c_double * 2)(*wall_T))
         self.nx, self.ny = nx, ny
         self.q = lattice
         self.ctx = pond_create(self.params, stream)
@@ -402,6 +405,9 @@ class Solver:
 
     @classmethod
     def from_workload(cls, w, precision=PREC_FP32, **kw):
+        if w.bc_y == BC_WALL:
+            kw.setdefault("wall_ux", w.wall_ux)
+            kw.setdefault("wall_T", w.wall_T)
         s = cls(w.nx, w.ny, tau=w.tau, gamma=w.gamma, prandtl=w.prandtl, bc_x=w.bc_x,
                 bc_y=w.bc_y, precision=precision, **kw)
         s.init_fields(w.rho, w.ux, w.uy, w.T)

@@ -7,6 +7,9 @@ import oracle
 
 
 def oracle_params_for(w, **kw):
+    if w.bc_y == oracle.WALL:
+        kw.setdefault("wall_ux", w.wall_ux)
+        kw.setdefault("wall_T", w.wall_T)
     return oracle.params(w.nx, w.ny, tau=w.tau, gamma=w.gamma, prandtl=w.prandtl,
                          bc_x=w.bc_x, bc_y=w.bc_y, **kw)
 

@@ -43,10 +43,30 @@ def test_abi_version_and_status_strings(pond):
 
 
 def test_params_struct_size_matches_header(pond):
-    # uint32 + 9 int32 = 40 bytes, then 4 doubles (8-aligned) = 72 bytes
-    assert ctypes.sizeof(pond.pond_params) == 72
+    # uint32 + 9 int32 = 40 bytes, then 4 doubles (8-aligned) and the two wall
+    # pairs = 104 bytes
+    assert ctypes.sizeof(pond.pond_params) == 104
     p = pond.pond_params_default()
-    assert p.struct_size == 72 and p.lattice == 16 and p.interp_points == 4
+    assert p.struct_size == 104 and p.lattice == 16 and p.interp_points == 4
+    assert list(p.wall_T) == [1.0, 1.0] and list(p.wall_ux) == [0.0, 0.0]
+
+
+def test_walls_add_ghost_rows_and_validate(pond):
+    p = pond.pond_params_default(nx=4, ny=32, bc_y=pond.BC_WALL)
+    q = pond.pond_params_default(nx=4, ny=32)
+    # the moment planes gain 8 ghost rows per wall: 20 floats per node
+    assert pond.pond_state_bytes(p) - pond.pond_state_bytes(q) >= 16 * 4 * 80
+    for fields, status in (({"bc_x": pond.BC_WALL}, 1), ({"split": 1}, 2)):
+        r = pond.pond_params_default(nx=4, ny=32, bc_y=pond.BC_WALL)
+        for k, v in fields.items():
+            setattr(r, k, v)
+        assert pond.pond_state_bytes(r) == 0
+        with pytest.raises(pond.PondError) as ei:
+            pond.pond_create(r)
+        assert ei.value.status == status
+    r = pond.pond_params_default(nx=4, ny=32, bc_y=pond.BC_WALL)
+    r.wall_T[1] = 0.0
+    assert pond.pond_state_bytes(r) == 0
 
 
 def test_state_bytes(pond):

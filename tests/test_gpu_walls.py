@@ -1,0 +1,117 @@
+"""GPU parity of the wall boundary (bc_y = WALL; the ghost-row closure the
+oracle states) and the thermal Couette flow of Sec. "Measuring viscous
+heating": the HIP path against the FP64 oracle on the same inputs (FP64 within
+1e-12, FP32 within 1e-5), bitwise agreement between kernels, and the steady
+temperature profile against the analytical one."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import closed_forms as cf
+from paper_2405_11489_amd import workloads
+from parity_util import (field_errors, gpu_run, gpu_solver, oracle_run, plane_errors)
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+TOTAL, NT = oracle.TOTAL, oracle.NONTRANS
+
+
+def couette(ny=16, nx=1, Ec=72.0, **kw):
+    return workloads.thermal_couette(ny=ny, nx=nx, Ec=Ec, **kw)
+
+
+def walled_modes(n, ny, seed, mach=1.0):
+    """2-D flow between walls: Fourier modes on a background along x, walls
+    moving with the background at its temperature."""
+    w = workloads.fourier_modes(n=n, ny=ny, mach=mach, angle_deg=0.0, amplitude=1e-2, seed=seed,
+                                tau=0.7, prandtl=1.0)
+    w.bc_y = workloads.WALL
+    u = float(w.ux.mean())
+    w.wall_ux, w.wall_T = (u, u), (1.0, 1.02)
+    return w
+
+
+CASES = {
+    "couette_16x1": lambda: couette(),
+    "couette_16x3_ec8": lambda: couette(nx=3, Ec=8.0),
+    "couette_5x1": lambda: couette(ny=5),
+    "walls_12x10": lambda: walled_modes(12, 10, 3),
+    "walls_37x29": lambda: walled_modes(37, 29, 4, mach=1.5),
+}
+
+
+@pytest.mark.parametrize("lattice,split", [(16, TOTAL), (16, NT), (25, NT)])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_fp64_walls_match_oracle(lattice, split, case):
+    w = CASES[case]()
+    for steps in (1, 6):
+        f, g, fr, _, st, m = gpu_run(w, FP64, steps, lattice=lattice, split=split)
+        P, s, ost = oracle_run(w, steps, lattice=lattice, split=split)
+        assert max(plane_errors(f, g, fr, s)) <= 1e-12
+        assert st.nonphysical == 0 and ost.nonphysical == 0
+        errs = field_errors(m, oracle.moments(P, s))
+        assert max(errs.values()) <= 1e-12, errs
+
+
+@pytest.mark.parametrize("case", ["couette_16x1", "walls_12x10"])
+def test_fp32_walls_within_1e5(case):
+    w = CASES[case]()
+    _, _, _, _, _, m = gpu_run(w, FP32, 20)
+    P, s, _ = oracle_run(w, 20)
+    errs = field_errors(m, oracle.moments(P, s))
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_fp64_steady_couette_matches_oracle():
+    """The whole run to the steady state (1024 steps at ny = 16)."""
+    w = couette()
+    _, _, _, _, _, m = gpu_run(w, FP64, w.steps)
+    P, s, _ = oracle_run(w, w.steps)
+    mo = oracle.moments(P, s)
+    for k in ("rho", "ux", "T"):
+        assert np.max(np.abs(m[k] - mo[k])) <= 1e-10 * np.max(np.abs(mo[k])), k
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_wall_kernels_and_tiles_bitwise_equal(prec):
+    from paper_2405_11489_amd import pond
+    w = walled_modes(37, 29, 4, mach=1.5)
+    ref = gpu_run(w, prec, 4, tuning={"kernel": pond.KERNEL_GLOBAL})
+    for tile, cap in [(pond.TILE_32x8, 0), (pond.TILE_16x16, 0), (pond.TILE_8x8, 100)]:
+        out = gpu_run(w, prec, 4, tuning={"kernel": pond.KERNEL_TILED, "tile": tile,
+                                          "lds_nodes": cap})
+        for x, y in zip(out[:3], ref[:3]):
+            np.testing.assert_array_equal(x, y, err_msg=f"tile {tile} cap {cap}")
+
+
+@pytest.mark.parametrize("lattice,split", [(16, TOTAL), (16, NT), (25, TOTAL), (25, NT)])
+@pytest.mark.parametrize("Ec", [8.0, 72.0])
+def test_couette_temperature_profile(lattice, split, Ec):
+    """Steady thermal Couette flow at ny = 32 against the analytical profile:
+    within 2.5 % of the heating amplitude for every split and lattice (the
+    closure's first-order error dominates; the D2Q16 non-translational
+    deviation the paper reports at Ec = 72 does not stand out at this
+    resolution: recorded)."""
+    w = couette(ny=32, Ec=Ec)
+    _, _, _, _, st, m = gpu_run(w, FP64, w.steps, lattice=lattice, split=split)
+    assert st.nonphysical == 0
+    y = np.arange(w.ny)
+    Ta = cf.couette_temperature(w.ny, y, w.meta["T0"], w.meta["T1"], Ec, w.prandtl)
+    err = np.max(np.abs(m["T"][:, 0] - Ta)) / (Ta.max() - w.meta["T0"])
+    print(f"Couette Ec={Ec} lattice={lattice} split={split}: max error {err:.4f}")
+    assert err <= 0.025
+    ua = w.meta["u0"] * (y + 0.5) / w.ny
+    assert np.max(np.abs(m["ux"][:, 0] - ua)) <= 2e-3 * w.meta["u0"]
+
+
+def test_walls_rejected_by_batch_and_server():
+    from paper_2405_11489_amd import pond
+    w = couette()
+    a = gpu_solver(w, FP32)
+    try:
+        with pytest.raises(pond.PondError) as ei:
+            pond.pond_batch_create([a.ctx])
+        assert ei.value.status == pond.ERR_UNSUPPORTED
+    finally:
+        a.close()
