@@ -45,12 +45,13 @@ PEAK_HBM_GBS = 8000.0
 #   FMA) = 10496 for the cubic stencil (NP = 4), 5904 for the quadratic one,
 #   frame transformation 16 velocities x 2 distributions x 65 = 2080;
 #   once per node: moments of the gathered populations 784, re-projection 110,
-#   collision 60, reconstruction 640.
+#   collision 60, reconstruction 640, and the moments of the stored populations
+#   for the next step 784 (the step kernel writes them; no separate pre-pass).
 #
 # D2Q25 (Grad order 4, 15 moments per distribution), same accounting: per
 # iteration departure points 175, interpolation 25 x NP^2 x (1 + 15 x 4),
 # transformation 25 x 2 x 85 (30 FMAs and the shared order-4 shift/scale);
-# once per node 1850 + 250 + 80 + 1500.
+# once per node 1850 + 250 + 80 + 1500 + 1850.
 def flops_per_iter(np_, q=16):
     if q == 25:
         return 175 + 25 * np_ * np_ * 61 + 4250
@@ -58,7 +59,7 @@ def flops_per_iter(np_, q=16):
 
 
 def flops_per_node(q=16):
-    return 3680 if q == 25 else 784 + 110 + 60 + 640
+    return 1850 + 250 + 80 + 1500 + 1850 if q == 25 else 784 + 110 + 60 + 640 + 784
 
 
 FLOPS_PER_ITER = flops_per_iter(4)
@@ -70,9 +71,10 @@ FLOPS_SOURCE_PER_NODE = 10 + 16 * (20 + 17)
 FLOPS64_PER_ITER = 140
 FLOPS64_PER_NODE = 60
 # Algorithmic HBM bytes of the step kernel per node (FP32 mode): frame read 24,
-# moment planes read 80, populations + frame written 128 + 24.
-BYTES_STEP_FP32 = 24 + 80 + 152
-BYTES_STEP_FP64 = 24 + 160 + 280
+# moment planes read 80, populations + frame written 128 + 24, the new moment
+# planes written 80.
+BYTES_STEP_FP32 = 24 + 80 + 152 + 80
+BYTES_STEP_FP64 = 24 + 160 + 280 + 160
 TILE_DIMS = {0: "16,16", 1: "32,8", 2: "16,8", 3: "8,8", 4: "256,1", 5: "64,1"}
 
 

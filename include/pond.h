@@ -244,11 +244,14 @@ POND_API pond_status pond_set_tuning(pond_ctx *c, const pond_tuning *t);
 /* Kernel timing on the context stream, for measurement.  While enabled,
  * pond_step brackets each of its launches with HIP events; the results give
  * the summed device time of the moment pre-pass and of the step kernel over
- * the launches since profiling was enabled. */
+ * the launches since profiling was enabled.  The step kernel writes the
+ * moments of the state it produces, so the pre-pass runs only on the first
+ * step after pond_init_fields or pond_import_state. */
 typedef struct {
     int64_t launches;       /* steps timed */
     double prepass_ms;      /* summed duration of the moment pre-pass launches */
-    double step_ms;         /* summed duration of the step-kernel launches */
+    double step_ms;         /* summed duration of the step-kernel launches (with the
+                               wall ghost rows when bc_y is POND_BC_WALL) */
 } pond_profile_t;
 
 /* enable != 0 starts (and clears) timing; 0 stops it and drops pending events. */

@@ -50,7 +50,7 @@ Layout layout_for(long long N, size_t psize, int lattice, long long mom_nodes) {
     L.frame_bytes = align_up(size_t(N) * sizeof(double));
     L.buf_bytes = 2 * L.pop_bytes + 3 * L.frame_bytes;
     L.mom_bytes = align_up(size_t(mom_nodes) * moment_values(lattice, psize == 8) * psize);
-    L.cnt_off = 2 * L.buf_bytes + L.mom_bytes;
+    L.cnt_off = 2 * L.buf_bytes + 2 * L.mom_bytes;
     L.scratch_off = L.cnt_off + align_up(sizeof(DevCounters));
     L.total = L.scratch_off + align_up(kScratchDoubles * sizeof(double));
     return L;
@@ -399,10 +399,13 @@ pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem
         c->buf[b].uy = reinterpret_cast<double *>(base + 2 * L.pop_bytes + L.frame_bytes);
         c->buf[b].T = reinterpret_cast<double *>(base + 2 * L.pop_bytes + 2 * L.frame_bytes);
     }
-    c->mom = c->mem + 2 * L.buf_bytes;
+    c->mom[0] = c->mem + 2 * L.buf_bytes;
+    c->mom[1] = c->mem + 2 * L.buf_bytes + L.mom_bytes;
+    c->mom_fresh = false;
     c->cnt = reinterpret_cast<DevCounters *>(c->mem + L.cnt_off);
     c->scratch = reinterpret_cast<double *>(c->mem + L.scratch_off);
     c->cur = 0;
+    c->mom_fresh = false;
     fill_args(c);
     c->initialized = false;
     c->failed = false;
@@ -430,8 +433,9 @@ pond_status pond_init_fields(pond_ctx *c, const double *rho, const double *ux, c
     if ((s = check_unbatched(c)) != POND_OK) return s;
     if (!rho || !ux || !uy || !T) return fail(POND_ERR_INVALID_ARG, "field pointer is NULL");
     const long long N = c->args.N;
-    // stage host inputs in the moment planes (>= 4 N doubles in either precision)
-    double *stg = static_cast<double *>(c->mom);
+    // stage host inputs in the moment planes (>= 4 N doubles in either precision;
+    // the moments are recomputed after initialisation)
+    double *stg = static_cast<double *>(c->mom[0]);
     const double *in[4] = {rho, ux, uy, T};
     const double *dev[4];
     for (int k = 0; k < 4; ++k) {
@@ -446,6 +450,7 @@ pond_status pond_init_fields(pond_ctx *c, const double *rho, const double *ux, c
     c->initialized = false;
     c->failed = false;
     c->cur = 0;
+    c->mom_fresh = false;
     s = reset_counters(c);
     if (s != POND_OK) return s;
     hipError_t e = fp64(c) ? launch_init_t<double>(c, dev[0], dev[1], dev[2], dev[3])
@@ -474,39 +479,51 @@ pond_status pond_init_fields(pond_ctx *c, const double *rho, const double *ux, c
 
 namespace {
 
+// Moments of buf[k] into mom[k] (and the wall ghost rows).
 template <typename P>
-hipError_t launch_prepass_t(pond_ctx *c, DevState src) {
-    return launch_moments_prepass<P>(c->args, src, static_cast<P *>(c->mom), c->stream);
+hipError_t launch_prepass_t(pond_ctx *c, int k) {
+    hipError_t e = launch_moments_prepass<P>(c->args, c->buf[k], static_cast<P *>(c->mom[k]),
+                                             c->stream);
+    if (e == hipSuccess && c->args.wall_h)
+        e = launch_wall_ghosts<P>(c->args, c->buf[k], static_cast<P *>(c->mom[k]), c->stream);
+    return e;
 }
 
+// Step buf[cur] -> buf[cur ^ 1]; the step kernel also writes the new state's
+// moments into mom[cur ^ 1] (then the wall ghost rows are filled).
 template <typename P>
-hipError_t launch_step_t(pond_ctx *c, DevState src, DevState dst) {
+hipError_t launch_step_t(pond_ctx *c) {
+    const int k = c->cur;
+    DevState src = c->buf[k], dst = c->buf[k ^ 1];
+    const P *mom = static_cast<const P *>(c->mom[k]);
+    P *mom_out = static_cast<P *>(c->mom[k ^ 1]);
+    hipError_t e;
     if (c->tuning.kernel == POND_KERNEL_GLOBAL)
-        return launch_step<P>(c->args, src, static_cast<const P *>(c->mom), dst, c->cnt, c->stream);
-    return launch_step_tiled<P>(c->args, c->tc, src, static_cast<const P *>(c->mom), dst, c->cnt,
-                                c->stream);
+        e = launch_step<P>(c->args, src, mom, dst, mom_out, c->cnt, c->stream);
+    else
+        e = launch_step_tiled<P>(c->args, c->tc, src, mom, dst, mom_out, c->cnt, c->stream);
+    if (e == hipSuccess && c->args.wall_h)
+        e = launch_wall_ghosts<P>(c->args, dst, mom_out, c->stream);
+    return e;
 }
 
-// One step: moment pre-pass on the current buffer, then the step kernel into
-// the other buffer; with profiling on, events bracket both launches.
+// One step: the moments pre-pass when mom[cur] is stale (after init, import or
+// a restore), then the step kernel into the other buffer; with profiling on,
+// events bracket each (three per step: pre-pass start, which stays null when
+// no pre-pass runs, step start, step end).
 hipError_t enqueue_step(pond_ctx *c) {
-    DevState src = c->buf[c->cur], dst = c->buf[c->cur ^ 1];
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     hipError_t e = hipSuccess;
     if (c->profiling) {
-        for (int j = 0; j < 3 && e == hipSuccess; ++j) {
+        for (int j = c->mom_fresh ? 1 : 0; j < 3 && e == hipSuccess; ++j)
             e = hipEventCreate(&ev[j]);
-            if (e == hipSuccess) c->prof_events.push_back(ev[j]);
-        }
-        if (e == hipSuccess) e = hipEventRecord(ev[0], c->stream);
+        for (int j = 0; j < 3; ++j) c->prof_events.push_back(ev[j]);
+        if (e == hipSuccess && ev[0]) e = hipEventRecord(ev[0], c->stream);
     }
-    if (e == hipSuccess) e = fp64(c) ? launch_prepass_t<double>(c, src) : launch_prepass_t<float>(c, src);
-    if (e == hipSuccess && c->args.wall_h)
-        e = fp64(c) ? launch_wall_ghosts<double>(c->args, src, static_cast<double *>(c->mom), c->stream)
-                    : launch_wall_ghosts<float>(c->args, src, static_cast<float *>(c->mom), c->stream);
+    if (e == hipSuccess && !c->mom_fresh)
+        e = fp64(c) ? launch_prepass_t<double>(c, c->cur) : launch_prepass_t<float>(c, c->cur);
     if (e == hipSuccess && c->profiling) e = hipEventRecord(ev[1], c->stream);
-    if (e == hipSuccess)
-        e = fp64(c) ? launch_step_t<double>(c, src, dst) : launch_step_t<float>(c, src, dst);
+    if (e == hipSuccess) e = fp64(c) ? launch_step_t<double>(c) : launch_step_t<float>(c);
     if (e == hipSuccess && c->profiling) e = hipEventRecord(ev[2], c->stream);
     return e;
 }
@@ -523,6 +540,7 @@ pond_status pond_step(pond_ctx *c, int64_t nsteps) {
         hipError_t e = enqueue_step(c);
         if (e != hipSuccess) return hip_fail(e, "step launch");
         c->cur ^= 1;
+        c->mom_fresh = true;
         ++c->steps;
     }
     return POND_OK;
@@ -534,7 +552,8 @@ pond_status pond_moments(pond_ctx *c, double *rho, double *ux, double *uy, doubl
     const long long N = c->args.N;
     double *outs[5] = {rho, ux, uy, T, p};
     double *dev[5];
-    double *stg = static_cast<double *>(c->mom);  // 5 N doubles fit in either precision
+    // staging: the other moment planes (rewritten by the next step), 5 N doubles
+    double *stg = static_cast<double *>(c->mom[c->cur ^ 1]);
     for (int k = 0; k < 5; ++k)
         dev[k] = outs[k] ? (is_device_pointer(outs[k]) ? outs[k] : stg + k * N) : nullptr;
     hipError_t e = fp64(c) ? launch_macro<double>(c->args, c->buf[c->cur], dev[0], dev[1], dev[2],
@@ -659,6 +678,7 @@ pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, con
     c->initialized = false;
     c->failed = false;
     c->cur = 0;
+    c->mom_fresh = false;
     s = reset_counters(c);
     if (s == POND_OK) {
         e = fp64(c) ? launch_import<double>(c->args, df, dg, dfr, c->buf[0], c->stream)
@@ -698,7 +718,8 @@ pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, con
 
 namespace {
 void drop_events(pond_ctx *c) {
-    for (hipEvent_t ev : c->prof_events) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : c->prof_events)
+        if (ev) (void)hipEventDestroy(ev);
     c->prof_events.clear();
 }
 }  // namespace
@@ -741,7 +762,8 @@ pond_status pond_profile_read(pond_ctx *c, pond_profile_t *out) {
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     for (size_t j = 0; j + 2 < c->prof_events.size(); j += 3) {
         float a = 0.f, b = 0.f;
-        e = hipEventElapsedTime(&a, c->prof_events[j], c->prof_events[j + 1]);
+        if (c->prof_events[j])
+            e = hipEventElapsedTime(&a, c->prof_events[j], c->prof_events[j + 1]);
         if (e == hipSuccess) e = hipEventElapsedTime(&b, c->prof_events[j + 1], c->prof_events[j + 2]);
         if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
         c->prof_prepass_ms += a;

@@ -40,7 +40,7 @@ constexpr int kBatchThreads = 256;
 struct BatchMember {
     StepArgs a;
     DevState buf[2];
-    void *mom;
+    void *mom[2];  // moments of buf[0] / buf[1]
     DevCounters *cnt;
     int parity0;   // current buffer of the member when the batch was built
     int lg;        // tile width 2^lg, height 256 >> lg
@@ -70,7 +70,8 @@ __global__ __launch_bounds__(kBatchThreads) void batch_moments_kernel(
     const StepArgs a = mem[i].a;
     const long long n = (long long)(int(blockIdx.x) - mem[i].blk_off) * kBatchThreads + threadIdx.x;
     if (n >= a.N) return;
-    node_moments<P>(a, mem[i].buf[mem[i].parity0 ^ flip], static_cast<P *>(mem[i].mom), n);
+    const int par = mem[i].parity0 ^ flip;
+    node_moments<P>(a, mem[i].buf[par], static_cast<P *>(mem[i].mom[par]), n);
 }
 
 template <typename P, int NP, int S>
@@ -86,7 +87,8 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(
     const int lg = mem[i].lg, tiles_x = mem[i].tiles_x;
     const int lt = t - mem[i].tile_off;
     const int par = mem[i].parity0 ^ flip;
-    tile_step<P, NP, S, D2Q16>(a, mem[i].buf[par], static_cast<const P *>(mem[i].mom), mem[i].buf[par ^ 1],
+    tile_step<P, NP, S, D2Q16>(a, mem[i].buf[par], static_cast<const P *>(mem[i].mom[par]),
+                               mem[i].buf[par ^ 1], static_cast<P *>(mem[i].mom[par ^ 1]),
                      mem[i].cnt, reinterpret_cast<P *>(smem_raw), cap, (lt % tiles_x) << lg,
                      (lt / tiles_x) * (kBatchThreads >> lg), Shape256{lg}, red);
 }
@@ -170,7 +172,8 @@ namespace {
 constexpr int kGraphSteps = 8;
 static_assert(kGraphSteps % 2 == 0, "the long graph must leave the buffer parity unchanged");
 
-hipError_t enqueue_batch_step(pond_batch *b, int flip) {
+// Moments of every member's current buffer (flip: batched steps taken so far).
+hipError_t enqueue_batch_moments(pond_batch *b, int flip) {
     const int n = int(b->members.size());
     if (b->dbl)
         hipLaunchKernelGGL(batch_moments_kernel<double>, dim3(b->blocks), dim3(kBatchThreads), 0,
@@ -178,8 +181,13 @@ hipError_t enqueue_batch_step(pond_batch *b, int flip) {
     else
         hipLaunchKernelGGL(batch_moments_kernel<float>, dim3(b->blocks), dim3(kBatchThreads), 0,
                            b->stream, b->d_mem, b->d_blk_off, n, flip);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+// One batched step: every member's step kernel tiles, which also write the
+// members' new moments (the moments of the current buffers must be fresh).
+hipError_t enqueue_batch_step(pond_batch *b, int flip) {
+    const int n = int(b->members.size());
     const size_t lds = size_t(b->cap) * kNMom * (b->dbl ? sizeof(double) : sizeof(float));
     with_variant(b->np, b->split, [&](auto np, auto sp) {
         if (b->dbl)
@@ -305,7 +313,8 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
         m.a = c->args;
         m.buf[0] = c->buf[0];
         m.buf[1] = c->buf[1];
-        m.mom = c->mom;
+        m.mom[0] = c->mom[0];
+        m.mom[1] = c->mom[1];
         m.cnt = c->cnt;
         m.parity0 = c->cur;
         m.lg = lg;
@@ -389,6 +398,10 @@ pond_status pond_batch_step(pond_batch *b, int64_t nsteps) {
     }
     // kGraphSteps is even: the long graph leaves the parity unchanged
     const int f = int(b->steps & 1);
+    // moments of the members' current buffers, once, if any member's are stale
+    bool stale = false;
+    for (const pond_ctx *c : b->members) stale = stale || !c->mom_fresh;
+    if (stale && e == hipSuccess) e = enqueue_batch_moments(b, f);
     for (int64_t k = 0; k + kGraphSteps <= nsteps && e == hipSuccess; k += kGraphSteps)
         e = hipGraphLaunch(b->exec[f][1], b->stream);
     for (int64_t k = 0; k < nsteps % kGraphSteps && e == hipSuccess; ++k)
@@ -400,6 +413,7 @@ pond_status pond_batch_step(pond_batch *b, int64_t nsteps) {
     for (pond_ctx *c : b->members) {
         c->cur ^= int(nsteps & 1);
         c->steps += nsteps;
+        c->mom_fresh = true;
     }
     b->steps += nsteps;
     return POND_OK;
@@ -483,6 +497,7 @@ pond_status restore_state(pond_ctx *c, const Saved &s) {
                                   c->stream);
     if (e != hipSuccess) return hip_fail(e, "autotune restore");
     c->cur = s.cur;
+    c->mom_fresh = false;
     c->steps = s.steps;
     c->failed = false;
     return write_counters(c, s.cnt);

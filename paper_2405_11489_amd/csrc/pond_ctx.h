@@ -22,12 +22,13 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // One context's device allocation:
-//   [state buffer 0 | state buffer 1 | moment planes | counters | scratch]
+//   [state buffer 0 | state buffer 1 | moment planes 0 | moment planes 1 | counters | scratch]
+// (moment planes k hold the moments of state buffer k)
 struct Layout {
     size_t pop_bytes;    // one set of Q planes (Q = 16 or 25)
     size_t frame_bytes;  // one frame plane
     size_t buf_bytes;    // one state buffer
-    size_t mom_bytes;    // moment planes (2 NM values per node, padded to the groups)
+    size_t mom_bytes;    // one set of moment planes (2 NM values per node, padded to the groups)
     size_t cnt_off, scratch_off, total;
 };
 
@@ -73,7 +74,8 @@ struct pond_ctx {
     bool own_mem;
     pond::DevState buf[2];
     int cur;
-    void *mom;
+    void *mom[2];     // moments of buf[0] / buf[1]
+    bool mom_fresh;   // mom[cur] holds the moments of buf[cur]
     pond::DevCounters *cnt;
     double *scratch;
     pond::StepArgs args;

@@ -112,12 +112,13 @@ hipError_t launch_moments_prepass(const StepArgs &a, DevState st, P *mom, hipStr
 // the pre-pass wrote; launched after it.
 template <typename P>
 hipError_t launch_wall_ghosts(const StepArgs &a, DevState st, P *mom, hipStream_t s);
+// A step reads the moments of src (mom) and writes those of dst (mom_out).
 template <typename P>
-hipError_t launch_step(const StepArgs &a, DevState src, const P *mom, DevState dst, DevCounters *cnt,
-                       hipStream_t s);
+hipError_t launch_step(const StepArgs &a, DevState src, const P *mom, DevState dst, P *mom_out,
+                       DevCounters *cnt, hipStream_t s);
 template <typename P>
 hipError_t launch_step_tiled(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
-                             DevState dst, DevCounters *cnt, hipStream_t s);
+                             DevState dst, P *mom_out, DevCounters *cnt, hipStream_t s);
 template <typename P>
 hipError_t launch_macro(const StepArgs &a, DevState st, double *rho, double *ux, double *uy,
                         double *T, double *p, hipStream_t s);

@@ -99,17 +99,17 @@ hipError_t launch_wall_ghosts(const StepArgs &a, DevState st, P *mom, hipStream_
 }
 
 template <typename P>
-hipError_t launch_step(const StepArgs &a, DevState src, const P *mom, DevState dst,
+hipError_t launch_step(const StepArgs &a, DevState src, const P *mom, DevState dst, P *mom_out,
                        DevCounters *cnt, hipStream_t s) {
-    return a.lattice == 25 ? Launch<P, D2Q25>::step(a, src, mom, dst, cnt, s)
-                           : Launch<P, D2Q16>::step(a, src, mom, dst, cnt, s);
+    return a.lattice == 25 ? Launch<P, D2Q25>::step(a, src, mom, dst, mom_out, cnt, s)
+                           : Launch<P, D2Q16>::step(a, src, mom, dst, mom_out, cnt, s);
 }
 
 template <typename P>
 hipError_t launch_step_tiled(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
-                             DevState dst, DevCounters *cnt, hipStream_t s) {
-    return a.lattice == 25 ? Launch<P, D2Q25>::step_tiled(a, tc, src, mom, dst, cnt, s)
-                           : Launch<P, D2Q16>::step_tiled(a, tc, src, mom, dst, cnt, s);
+                             DevState dst, P *mom_out, DevCounters *cnt, hipStream_t s) {
+    return a.lattice == 25 ? Launch<P, D2Q25>::step_tiled(a, tc, src, mom, dst, mom_out, cnt, s)
+                           : Launch<P, D2Q16>::step_tiled(a, tc, src, mom, dst, mom_out, cnt, s);
 }
 
 int tiled_blocks_per_cu(int lattice, bool dbl, int np, int split, TileShape shape) {
@@ -178,10 +178,11 @@ hipError_t launch_state_mean_velocity(const StepArgs &a, DevState st, double *sc
                                        hipStream_t);                                               \
     template hipError_t launch_moments_prepass<P>(const StepArgs &, DevState, P *, hipStream_t);   \
     template hipError_t launch_wall_ghosts<P>(const StepArgs &, DevState, P *, hipStream_t);       \
-    template hipError_t launch_step<P>(const StepArgs &, DevState, const P *, DevState,            \
+    template hipError_t launch_step<P>(const StepArgs &, DevState, const P *, DevState, P *,       \
                                        DevCounters *, hipStream_t);                                \
     template hipError_t launch_step_tiled<P>(const StepArgs &, const TileConfig &, DevState,       \
-                                             const P *, DevState, DevCounters *, hipStream_t);     \
+                                             const P *, DevState, P *, DevCounters *,              \
+                                             hipStream_t);                                         \
     template hipError_t launch_macro<P>(const StepArgs &, DevState, double *, double *, double *,  \
                                         double *, double *, hipStream_t);                          \
     template hipError_t launch_export<P>(const StepArgs &, DevState, double *, double *, double *, \

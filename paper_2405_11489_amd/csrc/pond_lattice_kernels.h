@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(StepArgs a, DevState st
 template <typename P, int NP, int S, class L>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
                                                       const P *__restrict__ mom, DevState dst,
-                                                      DevCounters *cnt) {
+                                                      P *__restrict__ mom_out, DevCounters *cnt) {
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = n < a.N;
     int x = 0, y = 0;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
         l2 = src.T[n];
     }
     const GlobalTaps<P, NP, L> taps{mom, a.mstride, a.nx, a.ny, a.bc_x, a.bc_y, a.moff, a.wall_h};
-    node_step<P, NP, S, L>(a, taps, x, y, n, live, l0, l1, l2, src, dst, cnt);
+    node_step<P, NP, S, L>(a, taps, x, y, n, live, l0, l1, l2, src, dst, mom_out, cnt);
 }
 
 // ------------------------------------------------------ step (LDS tiles) ----
@@ -116,12 +116,12 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
 template <typename P, int NP, int S, class L, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) POND_TILED_ATTR(P, S) void step_tiled_kernel(StepArgs a, DevState src,
                                                             const P *__restrict__ mom,
-                                                            DevState dst, DevCounters *cnt,
-                                                            int cap, int tiles_x) {
+                                                            DevState dst, P *__restrict__ mom_out,
+                                                            DevCounters *cnt, int cap, int tiles_x) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int red[16];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step<P, NP, S, L>(a, src, mom, dst, cnt, reinterpret_cast<P *>(smem_raw), cap,
+    tile_step<P, NP, S, L>(a, src, mom, dst, mom_out, cnt, reinterpret_cast<P *>(smem_raw), cap,
                            (tile % tiles_x) * TX, (tile / tiles_x) * TY, FixedShape<TX, TY>{}, red);
 }
 
@@ -314,7 +314,7 @@ const void *tiled_kernel_ptr(TileShape shape) {
 
 template <typename P, int NP, int S, class L, int TX, int TY>
 hipError_t launch_tiled_t(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
-                          DevState dst, DevCounters *cnt, hipStream_t s) {
+                          DevState dst, P *mom_out, DevCounters *cnt, hipStream_t s) {
     auto kern = step_tiled_kernel<P, NP, S, L, TX, TY>;
     const size_t lds = size_t(tc.cap) * nmom_padded<P, L>() * sizeof(P);
     if (lds > 64 * 1024) {
@@ -323,21 +323,21 @@ hipError_t launch_tiled_t(const StepArgs &a, const TileConfig &tc, DevState src,
         if (e != hipSuccess) return e;
     }
     const int tiles_x = (a.nx + TX - 1) / TX, tiles_y = (a.ny + TY - 1) / TY;
-    hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y), dim3(TX * TY), lds, s, a, src, mom, dst, cnt,
-                       tc.cap, tiles_x);
+    hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y), dim3(TX * TY), lds, s, a, src, mom, dst,
+                       mom_out, cnt, tc.cap, tiles_x);
     return hipGetLastError();
 }
 
 template <typename P, int NP, int S, class L>
 hipError_t launch_tiled_v(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
-                          DevState dst, DevCounters *cnt, hipStream_t s) {
+                          DevState dst, P *mo, DevCounters *cnt, hipStream_t s) {
     switch (tc.shape) {
-    case TileShape::T16x16: return launch_tiled_t<P, NP, S, L, 16, 16>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T32x8: return launch_tiled_t<P, NP, S, L, 32, 8>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T16x8: return launch_tiled_t<P, NP, S, L, 16, 8>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T8x8: return launch_tiled_t<P, NP, S, L, 8, 8>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T256x1: return launch_tiled_t<P, NP, S, L, 256, 1>(a, tc, src, mom, dst, cnt, s);
-    case TileShape::T64x1: return launch_tiled_t<P, NP, S, L, 64, 1>(a, tc, src, mom, dst, cnt, s);
+    case TileShape::T16x16: return launch_tiled_t<P, NP, S, L, 16, 16>(a, tc, src, mom, dst, mo, cnt, s);
+    case TileShape::T32x8: return launch_tiled_t<P, NP, S, L, 32, 8>(a, tc, src, mom, dst, mo, cnt, s);
+    case TileShape::T16x8: return launch_tiled_t<P, NP, S, L, 16, 8>(a, tc, src, mom, dst, mo, cnt, s);
+    case TileShape::T8x8: return launch_tiled_t<P, NP, S, L, 8, 8>(a, tc, src, mom, dst, mo, cnt, s);
+    case TileShape::T256x1: return launch_tiled_t<P, NP, S, L, 256, 1>(a, tc, src, mom, dst, mo, cnt, s);
+    case TileShape::T64x1: return launch_tiled_t<P, NP, S, L, 64, 1>(a, tc, src, mom, dst, mo, cnt, s);
     }
     return hipErrorInvalidValue;
 }
@@ -356,9 +356,10 @@ struct Launch {
     static hipError_t moments(const StepArgs &a, DevState st, P *mom, hipStream_t s);
     static hipError_t wall_ghosts(const StepArgs &a, DevState st, P *mom, hipStream_t s);
     static hipError_t step(const StepArgs &a, DevState src, const P *mom, DevState dst,
-                           DevCounters *cnt, hipStream_t s);
+                           P *mom_out, DevCounters *cnt, hipStream_t s);
     static hipError_t step_tiled(const StepArgs &a, const TileConfig &tc, DevState src,
-                                 const P *mom, DevState dst, DevCounters *cnt, hipStream_t s);
+                                 const P *mom, DevState dst, P *mom_out, DevCounters *cnt,
+                                 hipStream_t s);
     static hipError_t macro(const StepArgs &a, DevState st, double *rho, double *ux, double *uy,
                             double *T, double *p, hipStream_t s);
     static hipError_t exp(const StepArgs &a, DevState st, double *f, double *g, double *frame,
@@ -398,19 +399,20 @@ hipError_t Launch<P, L>::wall_ghosts(const StepArgs &a, DevState st, P *mom, hip
 
 template <typename P, class L>
 hipError_t Launch<P, L>::step(const StepArgs &a, DevState src, const P *mom, DevState dst,
-                              DevCounters *cnt, hipStream_t s) {
+                              P *mom_out, DevCounters *cnt, hipStream_t s) {
     return with_lattice_variant<L>(a.interp_points, a.split, [&](auto np, auto sp) {
         hipLaunchKernelGGL((lk::step_kernel<P, np(), sp(), L>), dim3(lk::grid_for(a.N)),
-                           dim3(lk::kBlock), 0, s, a, src, mom, dst, cnt);
+                           dim3(lk::kBlock), 0, s, a, src, mom, dst, mom_out, cnt);
         return hipGetLastError();
     });
 }
 
 template <typename P, class L>
 hipError_t Launch<P, L>::step_tiled(const StepArgs &a, const TileConfig &tc, DevState src,
-                                    const P *mom, DevState dst, DevCounters *cnt, hipStream_t s) {
+                                    const P *mom, DevState dst, P *mom_out, DevCounters *cnt,
+                                    hipStream_t s) {
     return with_lattice_variant<L>(a.interp_points, a.split, [&](auto np, auto sp) {
-        return lk::launch_tiled_v<P, np(), sp(), L>(a, tc, src, mom, dst, cnt, s);
+        return lk::launch_tiled_v<P, np(), sp(), L>(a, tc, src, mom, dst, mom_out, cnt, s);
     });
 }
 

@@ -262,21 +262,44 @@ __device__ __forceinline__ void monomials(P Vx, P Vy, P mono[kNM]) {
     mono[9] = Vyy * Vy;
 }
 
+// Monomials V_x^p V_y^q of a stored node (the moments pre-pass's form).
+template <class L, typename P>
+__device__ __forceinline__ void node_monomials(P Vx, P Vy, P mono[L::NM]) {
+    if constexpr (L::Q == 16) {
+        mono[0] = P(1);
+        mono[1] = Vx;
+        mono[2] = Vy;
+        mono[3] = Vx * Vx;
+        mono[4] = Vx * Vy;
+        mono[5] = Vy * Vy;
+        mono[6] = Vx * Vx * Vx;
+        mono[7] = Vx * Vx * Vy;
+        mono[8] = Vx * Vy * Vy;
+        mono[9] = Vy * Vy * Vy;
+    } else {
+        monomials_n<L>(Vx, Vy, mono);
+    }
+}
+
 // The whole step of one destination node (x, y) = node n whose time-t frame
 // is (l0, l1, l2), for the energy split S (0: total energy, 1: internal
 // energy, 2: non-translational energy) on lattice L; src is the time-t state
-// (its frames feed the velocity gradient of the internal-energy split).  Lanes with live == false take part
-// in the wave-level predictor-corrector exit and the counter reduction only.
+// (its frames feed the velocity gradient of the internal-energy split).  The
+// node's moments of the new state (those the next step interpolates) go to
+// mom_out, computed from the stored populations and frame exactly as the
+// moments pre-pass computes them.  Lanes with live == false take part in the
+// wave-level predictor-corrector exit and the counter reduction only.
 //
 // Per predictor-corrector gather, for each velocity i: departure point and
-// Lagrange weights, interpolation of the 20 moments, frame transformation of
+// Lagrange weights, interpolation of the 2 NM moments, frame transformation of
 // the interpolated moments into the iterate frame (population i of f and g);
 // the FP64 sums rho, j, E and the lab moments of the gathered populations are
 // accumulated on the fly, so no population array is kept.
 template <typename P, int NP, int S, class L, class Taps>
 __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, int x, int y,
                                           long long n, bool live, double l0, double l1, double l2,
-                                          const DevState &src, DevState dst, DevCounters *cnt) {
+                                          const DevState &src, DevState dst,
+                                          P *__restrict__ mom_out, DevCounters *cnt) {
     constexpr int NM = L::NM;
     const auto &tab = ltab<P, L>();
     double lg0 = l0, lg1 = l1, lg2 = l2;     // frame of the current gather
@@ -479,8 +502,14 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
 #pragma unroll
         for (int k = 1; k < NM; ++k) af[k] *= decay;
 
-        // reconstruct and store the post-collision populations
+        // reconstruct and store the post-collision populations, and accumulate the
+        // moments of the stored values about u_ref (the next step's taps)
         const P sTP = P(sT), u0 = P(ln0), u1 = P(ln1);
+        const double Tst = bad ? NAN : ln2, uxst = bad ? NAN : ln0, uyst = bad ? NAN : ln1;
+        const P sM = P(sqrt(Tst)), dxM = P(uxst - a.uref_x), dyM = P(uyst - a.uref_y);
+        P MM[nmom_padded<P, L>()];
+#pragma unroll
+        for (int k = 0; k < nmom_padded<P, L>(); ++k) MM[k] = P(0);
 #pragma unroll 4
         for (int i = 0; i < L::Q; ++i) {
             P fv = P(0), gv = P(0);
@@ -500,10 +529,19 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             if (bad) fv = gv = P(NAN);
             pop_plane<P>(dst.f, i, a.N)[n] = fv;
             pop_plane<P>(dst.g, i, a.N)[n] = gv;
+            const P Vx = sM * P(L::c(i / L::Q1)) + dxM, Vy = sM * P(L::c(i % L::Q1)) + dyM;
+            P mono[NM];
+            node_monomials<L>(Vx, Vy, mono);
+#pragma unroll
+            for (int k = 0; k < NM; ++k) {
+                MM[k] += fv * mono[k];
+                MM[NM + k] += gv * mono[k];
+            }
         }
-        dst.ux[n] = bad ? NAN : ln0;
-        dst.uy[n] = bad ? NAN : ln1;
-        dst.T[n] = bad ? NAN : ln2;
+        dst.ux[n] = uxst;
+        dst.uy[n] = uyst;
+        dst.T[n] = Tst;
+        store_moments<P, nmom<L>()>(mom_out, a.mstride, a.moff + n, MM);
     }
 
     // counters: one atomic per wave

@@ -165,8 +165,8 @@ __device__ __forceinline__ void clip_region(int tx0, int ty0, int tx, int ty, in
 // call it (it synchronises the block).  red: 4 x 4 ints of shared memory.
 template <typename P, int NP, int S, class L, class Shape>
 __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const P *__restrict__ mom,
-                                          DevState dst, DevCounters *cnt, P *lds, int cap, int tx0,
-                                          int ty0, Shape sh, int *red) {
+                                          DevState dst, P *__restrict__ mom_out, DevCounters *cnt,
+                                          P *lds, int cap, int tx0, int ty0, Shape sh, int *red) {
     const int nthreads = sh.tx() * sh.ty();
     const int x = tx0 + sh.lx(int(threadIdx.x)), y = ty0 + sh.ly(int(threadIdx.x));
     const bool live = x < a.nx && y < a.ny;
@@ -206,7 +206,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const
     const TileTaps<P, NP, L> taps{
         lds, cap, X0, Y0, X1, Y1, W, flat_y,
         GlobalTaps<P, NP, L>{mom, a.mstride, a.nx, a.ny, a.bc_x, a.bc_y, a.moff, a.wall_h}};
-    node_step<P, NP, S, L>(a, taps, x, y, n, live, l0, l1, l2, src, dst, cnt);
+    node_step<P, NP, S, L>(a, taps, x, y, n, live, l0, l1, l2, src, dst, mom_out, cnt);
 }
 
 // Moments up to the lattice's Grad order (three on D2Q16, four on D2Q25) of
@@ -227,20 +227,7 @@ __device__ __forceinline__ void node_moments(const StepArgs &a, DevState st, P *
         const P gi = pop_plane<P>(st.g, i, a.N)[n];
         const P Vx = s * P(L::c(i / L::Q1)) + dx, Vy = s * P(L::c(i % L::Q1)) + dy;
         P mono[NM];
-        if constexpr (L::Q == 16) {
-            mono[0] = P(1);
-            mono[1] = Vx;
-            mono[2] = Vy;
-            mono[3] = Vx * Vx;
-            mono[4] = Vx * Vy;
-            mono[5] = Vy * Vy;
-            mono[6] = Vx * Vx * Vx;
-            mono[7] = Vx * Vx * Vy;
-            mono[8] = Vx * Vy * Vy;
-            mono[9] = Vy * Vy * Vy;
-        } else {
-            monomials_n<L>(Vx, Vy, mono);
-        }
+        node_monomials<L>(Vx, Vy, mono);
 #pragma unroll
         for (int k = 0; k < NM; ++k) {
             M[k] += fi * mono[k];

@@ -72,10 +72,12 @@ def test_walls_add_ghost_rows_and_validate(pond):
 def test_state_bytes(pond):
     p = pond.pond_params_default(nx=512, ny=512, precision=pond.PREC_FP32)
     b32 = pond.pond_state_bytes(p)
-    assert 384 * 512 * 512 <= b32 < 384 * 512 * 512 + 16384
+    # two state buffers (16 + 16 float planes, 3 double frame planes) and the
+    # moment planes of each (20 floats)
+    assert 464 * 512 * 512 <= b32 < 464 * 512 * 512 + 16384
     p.precision = pond.PREC_FP64
     b64 = pond.pond_state_bytes(p)
-    assert 720 * 512 * 512 <= b64 < 720 * 512 * 512 + 16384
+    assert 880 * 512 * 512 <= b64 < 880 * 512 * 512 + 16384
 
 
 @pytest.mark.parametrize("field,value,status", [
@@ -112,11 +114,12 @@ def test_unsupported_combinations_rejected_before_device(pond, fields):
 def test_d2q25_state_size(pond):
     p = pond.pond_params_default(nx=512, ny=512, lattice=25, precision=pond.PREC_FP32)
     b32 = pond.pond_state_bytes(p)
-    # two buffers of 25 + 25 float planes and 3 double frame planes, 32 moment floats
-    assert 576 * 512 * 512 <= b32 < 576 * 512 * 512 + 16384
+    # two buffers of 25 + 25 float planes and 3 double frame planes, and the
+    # moment planes of each (32 floats)
+    assert 704 * 512 * 512 <= b32 < 704 * 512 * 512 + 16384
     p.precision = pond.PREC_FP64
     b64 = pond.pond_state_bytes(p)
-    assert 1088 * 512 * 512 <= b64 < 1088 * 512 * 512 + 16384
+    assert 1328 * 512 * 512 <= b64 < 1328 * 512 * 512 + 16384
     p.split, p.prandtl = 2, 1.0
     assert pond.pond_state_bytes(p) == b64
 
