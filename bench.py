@@ -95,11 +95,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def traffic_record(kernel, precision):
-    """HBM bytes per launch of ``kernel`` from a 'traffic-record:' line of a
-    profiles/*.md summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled
-    by the same counter's reading for a plain copy of known size), or None when
-    no record matches the current kernel sources."""
+def traffic_record(kernel, precision, workload):
+    """HBM bytes per launch of ``kernel`` on ``workload`` from a
+    'traffic-record:' line of a profiles/*.md summary (FETCH_SIZE and
+    WRITE_SIZE per dispatch, each scaled by the same counter's reading for a
+    plain copy of known size), or None when no record matches the workload and
+    the current kernel sources."""
     d = os.path.join(ROOT, "profiles")
     if not os.path.isdir(d):
         return None
@@ -113,7 +114,7 @@ def traffic_record(kernel, precision):
                     continue
                 kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
                 if (kv.get("kernel") == kernel and kv.get("precision") == precision
-                        and kv.get("sources_sha256") == want):
+                        and kv.get("workload") == workload and kv.get("sources_sha256") == want):
                     return float(kv["bytes_per_launch"])
     return None
 
@@ -377,6 +378,11 @@ def main():
                     help="predictor-corrector tolerance (0: the library default)")
     ap.add_argument("--size", type=int, default=512,
                     help="modes512 workload: grid edge (other sizes are diagnostics)")
+    ap.add_argument("--mach", type=float, default=2.0,
+                    help="modes512 workload: Mach number of the background flow (the halo "
+                         "of a tile grows with it; 2 is the headline case)")
+    ap.add_argument("--tau", type=float, default=0.55,
+                    help="modes512 workload: relaxation time (0.55 is the headline case)")
     ap.add_argument("--split", choices=["total", "internal", "nontrans"], default="total",
                     help="energy split carried by g (single-instance workloads); nontrans "
                          "runs at Pr = 1")
@@ -433,9 +439,10 @@ def main():
                                                        "states": w.meta["states"]}
     else:
         n = args.size
-        w = workloads.fourier_modes(n=n, mach=2.0, angle_deg=30.0, amplitude=1e-3, seed=0,
-                                    tau=0.55, prandtl=0.71, gamma=1.4, steps=2000)
-        wname, wconf = f"mach2_fourier_modes_{n}x{n}", {"mach": 2.0}
+        w = workloads.fourier_modes(n=n, mach=args.mach, angle_deg=30.0, amplitude=1e-3, seed=0,
+                                    tau=args.tau, prandtl=0.71, gamma=1.4, steps=2000)
+        wname = f"mach{args.mach:g}_fourier_modes_{n}x{n}" + ("" if args.tau == 0.55 else f"_tau{args.tau:g}")
+        wconf = {"mach": args.mach}
     stream = torch.cuda.Stream()
     tuning = {"kernel": pond.KERNEL_TILED if args.kernel == "tiled" else pond.KERNEL_GLOBAL}
     if args.tile is not None:
@@ -499,7 +506,7 @@ def main():
     lat = f"D2Q{args.lattice}"
     kname = f"step_tiled_kernel<{ptype},{args.interp_points},{split},{lat},{TILE_DIMS[tun.tile]}>" \
         if args.kernel == "tiled" else f"step_kernel<{ptype},{args.interp_points},{split},{lat}>"
-    traffic = traffic_record(kname, args.precision)
+    traffic = traffic_record(kname, args.precision, wname)
     if prec == pond.PREC_FP32:
         achieved = flops / (step_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
