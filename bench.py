@@ -75,7 +75,7 @@ FLOPS64_PER_NODE = 60
 # planes written 80.
 BYTES_STEP_FP32 = 24 + 80 + 152 + 80
 BYTES_STEP_FP64 = 24 + 160 + 280 + 160
-TILE_DIMS = {0: "16,16", 1: "32,8", 2: "16,8", 3: "8,8", 4: "256,1", 5: "64,1"}
+TILE_DIMS = {0: "16,16", 1: "32,8", 2: "16,8", 3: "8,8", 4: "256,1", 5: "64,1", 6: "32,16"}
 
 
 def log(*a):

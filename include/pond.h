@@ -222,14 +222,17 @@ POND_API pond_status pond_import_state(pond_ctx *c, const double *f, const doubl
  *              LDS; POND_KERNEL_GLOBAL reads every tap from HBM (reference).
  *   tile:      POND_TILE_* block shape of the tiled kernel (destination nodes).
  *   lds_nodes: LDS capacity per block, in nodes (20 moments each: 80 B in FP32,
- *              160 B in FP64); taps outside the staged region read HBM.
+ *              160 B in FP64; 30 on D2Q25); taps outside the staged region
+ *              read HBM.  At most 159 KiB: one KiB of the CU's 160 stays for
+ *              the kernels' static shared memory.
  *   batch_tile_width: tile of this context when it steps inside a pond_batch.
  * pond_set_tuning validates the values (POND_ERR_INVALID_ARG otherwise);
  * lds_nodes <= 0 selects the default for the tile.  Refused (POND_ERR_STATE)
  * while the context is a member of a batch. */
 enum { POND_KERNEL_TILED = 0, POND_KERNEL_GLOBAL = 1 };
 enum { POND_TILE_16x16 = 0, POND_TILE_32x8 = 1, POND_TILE_16x8 = 2, POND_TILE_8x8 = 3,
-       POND_TILE_256x1 = 4, POND_TILE_64x1 = 5 };
+       POND_TILE_256x1 = 4, POND_TILE_64x1 = 5,
+       POND_TILE_32x16 = 6 /* 512 lanes, D2Q16 only (POND_ERR_UNSUPPORTED on D2Q25) */ };
 typedef struct {
     int32_t kernel;
     int32_t tile;

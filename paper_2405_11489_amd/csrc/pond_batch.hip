@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(
     const BatchMember *__restrict__ mem, const int *__restrict__ tile_off, int nmem, int cap,
     int flip) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int red[16];
+    __shared__ int red[4 * red_slots<Shape256::kThreads>()];
     const int t = xcd_tile(int(blockIdx.x), int(gridDim.x));
     const int i = __builtin_amdgcn_readfirstlane(find_member(tile_off, nmem, t));
     const StepArgs a = mem[i].a;

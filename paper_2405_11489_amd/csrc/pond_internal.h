@@ -48,7 +48,8 @@ struct StepArgs {
 
 // Tiled step launch configuration: block shape, LDS capacity (nodes of the
 // staged source region) and the largest halo that fits it.
-enum class TileShape : int { T16x16 = 0, T32x8 = 1, T16x8 = 2, T8x8 = 3, T256x1 = 4, T64x1 = 5 };
+enum class TileShape : int { T16x16 = 0, T32x8 = 1, T16x8 = 2, T8x8 = 3, T256x1 = 4, T64x1 = 5,
+                             T32x16 = 6 };
 
 struct TileConfig {
     TileShape shape;
@@ -64,6 +65,7 @@ inline void tile_dims(TileShape s, int &tx, int &ty) {
     case TileShape::T8x8: tx = 8; ty = 8; return;
     case TileShape::T256x1: tx = 256; ty = 1; return;
     case TileShape::T64x1: tx = 64; ty = 1; return;
+    case TileShape::T32x16: tx = 32; ty = 16; return;
     }
     tx = ty = 0;
 }

@@ -109,17 +109,17 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
 #ifndef POND_TILED_WAVES_PER_EU
 #define POND_TILED_WAVES_PER_EU 0
 #endif
-#define POND_TILED_ATTR(P, S)                                                            \
+#define POND_TILED_ATTR(P, S, NT, L)                                                     \
     __attribute__((amdgpu_waves_per_eu(POND_TILED_WAVES_PER_EU > 0 ? POND_TILED_WAVES_PER_EU \
-                                                                   : step_min_waves<P, S>())))
+                                                                   : step_min_waves<P, S, NT, L>())))
 
 template <typename P, int NP, int S, class L, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) POND_TILED_ATTR(P, S) void step_tiled_kernel(StepArgs a, DevState src,
+__global__ __launch_bounds__(TX *TY) POND_TILED_ATTR(P, S, TX *TY, L) void step_tiled_kernel(StepArgs a, DevState src,
                                                             const P *__restrict__ mom,
                                                             DevState dst, P *__restrict__ mom_out,
                                                             DevCounters *cnt, int cap, int tiles_x) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int red[16];
+    __shared__ int red[4 * red_slots<TX * TY>()];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     tile_step<P, NP, S, L>(a, src, mom, dst, mom_out, cnt, reinterpret_cast<P *>(smem_raw), cap,
                            (tile % tiles_x) * TX, (tile / tiles_x) * TY, FixedShape<TX, TY>{}, red);
@@ -308,6 +308,11 @@ const void *tiled_kernel_ptr(TileShape shape) {
     case TileShape::T8x8: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, L, 8, 8>);
     case TileShape::T256x1: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, L, 256, 1>);
     case TileShape::T64x1: return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, L, 64, 1>);
+    case TileShape::T32x16:
+        if constexpr (L::Q == 16)
+            return reinterpret_cast<const void *>(step_tiled_kernel<P, NP, S, L, 32, 16>);
+        else
+            return nullptr;
     }
     return nullptr;
 }
@@ -338,6 +343,11 @@ hipError_t launch_tiled_v(const StepArgs &a, const TileConfig &tc, DevState src,
     case TileShape::T8x8: return launch_tiled_t<P, NP, S, L, 8, 8>(a, tc, src, mom, dst, mo, cnt, s);
     case TileShape::T256x1: return launch_tiled_t<P, NP, S, L, 256, 1>(a, tc, src, mom, dst, mo, cnt, s);
     case TileShape::T64x1: return launch_tiled_t<P, NP, S, L, 64, 1>(a, tc, src, mom, dst, mo, cnt, s);
+    case TileShape::T32x16:  // D2Q16 only (the host refuses it on D2Q25)
+        if constexpr (L::Q == 16)
+            return launch_tiled_t<P, NP, S, L, 32, 16>(a, tc, src, mom, dst, mo, cnt, s);
+        else
+            return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }

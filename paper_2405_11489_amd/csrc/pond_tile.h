@@ -10,6 +10,8 @@
 // taps are loaded only after these are consumed (0: the whole row at once).
 // Fewer loads in flight per lane -> fewer live registers -> more waves per
 // SIMD: FP32 165 VGPRs (3 waves) with groups of 2, FP64 238 (2 waves) with 1.
+// The four-wave FP32 kernel (512-lane blocks) loads one tap at a time: its
+// 128 VGPRs then spill 17 registers instead of 30.
 #ifndef POND_TAP_GROUP_F32
 #define POND_TAP_GROUP_F32 2
 #endif
@@ -24,7 +26,9 @@ namespace pond {
 // stride cap; a velocity whose stencil leaves the region reads HBM.  With a
 // single grid row (flat_y) every stencil row is row 0, so the region is one
 // row and all NP stencil rows read it (same arithmetic as the HBM gather).
-template <typename P, int NP, class L = D2Q16>
+// G: taps per group of LDS loads (the arithmetic does not depend on it).
+template <typename P, int NP, class L = D2Q16,
+          int G = sizeof(P) == 8 ? POND_TAP_GROUP_F64 : POND_TAP_GROUP_F32>
 struct TileTaps {
     const P *lds;
     int cap, X0, Y0, X1, Y1, W;
@@ -43,8 +47,7 @@ struct TileTaps {
             for (int q = 0; q < NP; ++q) {
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
-                    constexpr int kGroup = sizeof(P) == 8 ? POND_TAP_GROUP_F64 : POND_TAP_GROUP_F32;
-                    if (kGroup > 0 && p > 0 && p % kGroup == 0) asm volatile("" ::: "memory");
+                    if (G > 0 && p > 0 && p % G == 0) asm volatile("" ::: "memory");
                     const P Wt = wx[p] * wy[q];
                     P M[nmom_padded<P, L>()];
                     load_moments<P, nmom<L>()>(lds, cap, base + q * rs + p, M);
@@ -61,7 +64,15 @@ struct TileTaps {
     }
 };
 
-// Minimum over the block (at most 4 waves); red holds one int per wave.
+// Ints of shared memory per block_min of a block of NT lanes: one per wave, at
+// least four (blocks of up to 256 lanes keep a 16-int array; a larger static
+// array moves the dynamic LDS and costs the step kernel a register).
+template <int NT>
+constexpr int red_slots() {
+    return NT > 256 ? (NT + 63) / 64 : 4;
+}
+
+// Minimum over the block (at most 8 waves); red holds one int per wave.
 __device__ __forceinline__ int block_min(int v, int *red) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
@@ -92,12 +103,18 @@ __device__ __forceinline__ void stencil_extent(int x, double u, double s, int &l
 }
 
 // Minimum waves per SIMD asked of the register allocator for the step kernels
-// (168 VGPRs allow three).  FP32 with the internal-energy split needs the
-// request: its source term would otherwise tip the allocation over to two
-// waves; the FP32 total split reaches three unforced, FP64 holds two.
-template <typename P, int S>
+// of NT lanes per block (168 VGPRs allow three, 128 four).  FP32 asks for three:
+// the allocation sits at that boundary, and one register more halves the
+// waves that hide the LDS latency.  FP32 blocks of 512 lanes ask for four: two
+// such blocks share a CU's LDS, half of it each, which holds the source region
+// of a 32 x 16 tile of an advected flow, and a grid of 4096 waves (512^2
+// nodes) then runs in a single round.  FP64 holds two unforced; D2Q25 keeps
+// the compiler's choice (two waves in FP32, one in FP64: more would spill).
+template <typename P, int S, int NT = 256, class L = D2Q16>
 constexpr int step_min_waves() {
-    return (sizeof(P) == 4 && S == 1) ? 3 : 1;
+    if (L::Q != 16) return 1;
+    if (sizeof(P) == 4) return NT == 512 ? 4 : 3;
+    return 1;
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
@@ -111,6 +128,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // Tile shapes: TX x TY destination nodes, one lane each, lane t at (t % TX, t / TX).
 template <int TX, int TY>
 struct FixedShape {
+    static constexpr int kThreads = TX * TY;
     __device__ __forceinline__ int tx() const { return TX; }
     __device__ __forceinline__ int ty() const { return TY; }
     __device__ __forceinline__ int lx(int t) const { return t % TX; }
@@ -118,6 +136,7 @@ struct FixedShape {
 };
 // 256 lanes, TX = 2^lg, TY = 256 / TX.
 struct Shape256 {
+    static constexpr int kThreads = 256;
     int lg;
     __device__ __forceinline__ int tx() const { return 1 << lg; }
     __device__ __forceinline__ int ty() const { return 256 >> lg; }
@@ -162,7 +181,8 @@ __device__ __forceinline__ void clip_region(int tx0, int ty0, int tx, int ty, in
 // The tile with first node (tx0, ty0): load the time-t frames, bound the
 // source region (clip_region), stage the region's moments, then run every
 // lane's node step (energy split S, lattice L).  Every thread of the block must
-// call it (it synchronises the block).  red: 4 x 4 ints of shared memory.
+// call it (it synchronises the block).  red: 4 red_slots<Shape::kThreads>()
+// ints of shared memory.
 template <typename P, int NP, int S, class L, class Shape>
 __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const P *__restrict__ mom,
                                           DevState dst, P *__restrict__ mom_out, DevCounters *cnt,
@@ -186,10 +206,11 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const
         stencil_extent<NP, L>(y, l1, s, ly, hy);
     }
     const bool flat_y = a.ny == 1 && a.bc_y != 2;  // walls: the ghost rows differ
+    constexpr int RS = red_slots<Shape::kThreads>();
     int X0 = block_min(lx, red);
-    int X1 = -block_min(-hx, red + 4);
-    int Y0 = block_min(ly, red + 8);
-    int Y1 = -block_min(-hy, red + 12);
+    int X1 = -block_min(-hx, red + RS);
+    int Y0 = block_min(ly, red + 2 * RS);
+    int Y1 = -block_min(-hy, red + 3 * RS);
     clip_region(tx0, ty0, sh.tx(), sh.ty(), cap, flat_y, X0, X1, Y0, Y1);
     const int W = X1 >= X0 ? X1 - X0 + 1 : 0;
     const int H = Y1 >= Y0 ? Y1 - Y0 + 1 : 0;
@@ -203,7 +224,9 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const
     }
     __syncthreads();
 
-    const TileTaps<P, NP, L> taps{
+    constexpr int G = sizeof(P) == 4 && Shape::kThreads == 512 ? 1
+                      : (sizeof(P) == 8 ? POND_TAP_GROUP_F64 : POND_TAP_GROUP_F32);
+    const TileTaps<P, NP, L, G> taps{
         lds, cap, X0, Y0, X1, Y1, W, flat_y,
         GlobalTaps<P, NP, L>{mom, a.mstride, a.nx, a.ny, a.bc_x, a.bc_y, a.moff, a.wall_h}};
     node_step<P, NP, S, L>(a, taps, x, y, n, live, l0, l1, l2, src, dst, mom_out, cnt);

@@ -41,7 +41,7 @@ EXPORTED = [
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
 REQ_KEEP_MOMENTS, REQ_KEEP_STATE = 1, 2
 KERNEL_TILED, KERNEL_GLOBAL = 0, 1
-TILE_16x16, TILE_32x8, TILE_16x8, TILE_8x8, TILE_256x1, TILE_64x1 = range(6)
+TILE_16x16, TILE_32x8, TILE_16x8, TILE_8x8, TILE_256x1, TILE_64x1, TILE_32x16 = range(7)
 
 
 class pond_params(ctypes.Structure):

@@ -127,6 +127,16 @@ def test_kernels_and_tiles_bitwise_equal(prec):
             np.testing.assert_array_equal(x, y, err_msg=f"tile {tile} cap {cap}")
 
 
+def test_512_lane_tile_refused():
+    """The 32 x 16 tile is built for D2Q16 only."""
+    from paper_2405_11489_amd import pond
+    w = modes(16, 12, mach=1.0, seed=3)
+    with gpu_solver(w, FP32, lattice=25, split=NT) as s:
+        with pytest.raises(pond.PondError) as e:
+            pond.pond_set_tuning(s.ctx, tile=pond.TILE_32x16)
+        assert e.value.status == pond.ERR_UNSUPPORTED
+
+
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_export_import_resume_bitwise(prec):
     w = modes(40, 24, mach=1.5, amp=1e-2, seed=6)

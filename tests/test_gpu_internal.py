@@ -118,7 +118,7 @@ def test_kernels_and_tiles_bitwise_equal(prec):
     w = clamp_x(modes(70, 45, mach=2.5, amp=2e-2, seed=12))
     ref = gpu_run(w, prec, 4, split=INT, tuning={"kernel": pond.KERNEL_GLOBAL})
     for tile, cap in [(pond.TILE_32x8, 0), (pond.TILE_16x16, 0), (pond.TILE_64x1, 0),
-                      (pond.TILE_256x1, 0), (pond.TILE_8x8, 100)]:
+                      (pond.TILE_256x1, 0), (pond.TILE_8x8, 100), (pond.TILE_32x16, 0)]:
         out = gpu_run(w, prec, 4, split=INT,
                       tuning={"kernel": pond.KERNEL_TILED, "tile": tile, "lds_nodes": cap})
         for x, y in zip(out[:3], ref[:3]):

@@ -272,11 +272,39 @@ def test_kernels_tiles_and_lds_capacities_bitwise_equal(prec):
     ref = gpu_run(w, prec, 4, tuning={"kernel": pond.KERNEL_GLOBAL})
     configs = [(pond.TILE_16x16, 0), (pond.TILE_32x8, 0), (pond.TILE_16x8, 0), (pond.TILE_8x8, 0),
                (pond.TILE_64x1, 0), (pond.TILE_256x1, 0), (pond.TILE_16x16, 300),
-               (pond.TILE_8x8, 100)]
+               (pond.TILE_8x8, 100), (pond.TILE_32x16, 0), (pond.TILE_32x16, 600)]
     for tile, cap in configs:
         out = gpu_run(w, prec, 4, tuning={"kernel": pond.KERNEL_TILED, "tile": tile, "lds_nodes": cap})
         for x, y in zip(out[:3], ref[:3]):
             np.testing.assert_array_equal(x, y, err_msg=f"tile {tile} cap {cap}")
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_512_lane_tiles_bitwise_equal_at_full_size(prec):
+    """512^2 Mach-2 modes, the benchmark's grid: the 32 x 16 tile (512 lanes,
+    two blocks per CU) and the 32 x 8 tile give the same bits after 3 steps."""
+    from paper_2405_11489_amd import pond
+    w = modes(512, mach=2.0, amp=1e-3, seed=0, tau=0.55)
+    ref = gpu_run(w, prec, 3, tuning={"kernel": pond.KERNEL_TILED, "tile": pond.TILE_32x8,
+                                      "lds_nodes": 0})
+    out = gpu_run(w, prec, 3, tuning={"kernel": pond.KERNEL_TILED, "tile": pond.TILE_32x16,
+                                      "lds_nodes": 0})
+    for x, y in zip(out[:3], ref[:3]):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_lds_capacity_beyond_the_cu_refused():
+    """LDS capacities whose dynamic share leaves no room for the kernels'
+    static shared memory are refused at pond_set_tuning, not at launch."""
+    from paper_2405_11489_amd import pond
+    w = modes(16, 12, mach=1.0, seed=3)
+    with gpu_solver(w, FP64) as s:
+        pond.pond_set_tuning(s.ctx, tile=pond.TILE_32x8, lds_nodes=159 * 1024 // 160)
+        s.step(1)
+        with pytest.raises(pond.PondError) as e:
+            pond.pond_set_tuning(s.ctx, tile=pond.TILE_32x8, lds_nodes=1024)
+        assert e.value.status == pond.ERR_INVALID_ARG
+        s.step(1)
 
 
 def test_quasi_1d_tiled_matches_oracle():
