@@ -114,14 +114,19 @@ def test_full_size_sampled_nodes(lattice, split, prec, bar):
     assert np.max(np.abs(fr1[2, nodes] - lo[:, 2]) / lo[:, 2]) <= bar
 
 
+@pytest.mark.parametrize("lattice", [25, 16])
 @pytest.mark.parametrize("prec", [FP64, FP32])
-def test_kernels_and_tiles_bitwise_equal(prec):
+def test_kernels_and_tiles_bitwise_equal(prec, lattice):
+    """Non-translational split: the HBM-tap kernel and the tiled kernel in
+    every shape the lattice is built for give the same bits."""
     from paper_2405_11489_amd import pond
     w = clamp_x(modes(70, 45, mach=2.5, amp=2e-2, seed=12))
-    ref = gpu_run(w, prec, 3, lattice=25, split=NT, tuning={"kernel": pond.KERNEL_GLOBAL})
-    for tile, cap in [(pond.TILE_32x8, 0), (pond.TILE_16x16, 0), (pond.TILE_64x1, 0),
-                      (pond.TILE_8x8, 100)]:
-        out = gpu_run(w, prec, 3, lattice=25, split=NT,
+    ref = gpu_run(w, prec, 3, lattice=lattice, split=NT, tuning={"kernel": pond.KERNEL_GLOBAL})
+    tiles = [(pond.TILE_32x8, 0), (pond.TILE_16x16, 0), (pond.TILE_64x1, 0), (pond.TILE_8x8, 100)]
+    if lattice == 16:
+        tiles.append((pond.TILE_32x16, 0))
+    for tile, cap in tiles:
+        out = gpu_run(w, prec, 3, lattice=lattice, split=NT,
                       tuning={"kernel": pond.KERNEL_TILED, "tile": tile, "lds_nodes": cap})
         for x, y in zip(out[:3], ref[:3]):
             np.testing.assert_array_equal(x, y, err_msg=f"tile {tile} cap {cap}")

@@ -293,6 +293,25 @@ def test_512_lane_tiles_bitwise_equal_at_full_size(prec):
         np.testing.assert_array_equal(x, y)
 
 
+def test_default_tile_saves_the_partial_round():
+    """Default block shapes on MI355X (256 CUs): FP32 takes the four-wave
+    32 x 16 tile where a grid needs more than one round of three-wave 32 x 8
+    blocks but fits one of 32 x 16 blocks (512^2), FP64 wherever its tiles
+    cover every CU; single rows take 64 x 1."""
+    from paper_2405_11489_amd import pond
+    want = {(512, FP32): pond.TILE_32x16, (1024, FP32): pond.TILE_32x8,
+            (256, FP32): pond.TILE_32x8, (512, FP64): pond.TILE_32x16,
+            (1024, FP64): pond.TILE_32x16, (256, FP64): pond.TILE_32x8}
+    for (n, prec), tile in want.items():
+        w = modes(n, mach=2.0, amp=1e-3, seed=0, tau=0.55)
+        with gpu_solver(w, prec) as s:
+            t = pond.pond_get_tuning(s.ctx)
+            assert (t.tile, t.kernel) == (tile, pond.KERNEL_TILED), (n, prec, t.tile)
+    w = workloads.sod_tube(nx=400, nu=2e-3, steps=4)
+    with gpu_solver(w, FP32) as s:
+        assert pond.pond_get_tuning(s.ctx).tile == pond.TILE_64x1
+
+
 def test_lds_capacity_beyond_the_cu_refused():
     """LDS capacities whose dynamic share leaves no room for the kernels'
     static shared memory are refused at pond_set_tuning, not at launch."""

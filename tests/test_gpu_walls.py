@@ -78,7 +78,8 @@ def test_wall_kernels_and_tiles_bitwise_equal(prec):
     from paper_2405_11489_amd import pond
     w = walled_modes(37, 29, 4, mach=1.5)
     ref = gpu_run(w, prec, 4, tuning={"kernel": pond.KERNEL_GLOBAL})
-    for tile, cap in [(pond.TILE_32x8, 0), (pond.TILE_16x16, 0), (pond.TILE_8x8, 100)]:
+    for tile, cap in [(pond.TILE_32x8, 0), (pond.TILE_16x16, 0), (pond.TILE_8x8, 100),
+                      (pond.TILE_32x16, 0)]:
         out = gpu_run(w, prec, 4, tuning={"kernel": pond.KERNEL_TILED, "tile": tile,
                                           "lds_nodes": cap})
         for x, y in zip(out[:3], ref[:3]):
