@@ -41,10 +41,14 @@
  *     quasi-equilibrium approach without giving its form); in the internal-
  *     energy split g carries no viscous-heating flux, so g relaxes at omega_1;
  *   - internal-energy split source -f (v - u).(d_t u + v.grad u): added after
- *     the collision with the re-projected gathered f, u the new frame
+ *     the collision with f the time-centred population, the mean of the
+ *     re-projected gathered f and the collided f (with the gathered f alone the
+ *     viscous heating came out 2 tau / (2 tau - 1) times too large), u the new frame
  *     velocity, d_t u the difference between the new and the time-t frame
  *     velocity of the node, grad u central differences of the time-t frame
- *     velocities of the four neighbours (wrapped or clamped like the stencil);
+ *     velocities of the four neighbours (wrapped or clamped like the stencil;
+ *     a neighbour row beyond a wall takes the ghost frame velocity of the
+ *     wall closure, 2 U_wall - u of the mirror node along x, -u along y);
  *   - non-translational split: the paper's single-relaxation BGK only (Pr = 1;
  *     its quasi-equilibrium form is not given and not built here);
  *   - walls (the thermal Couette flow of Sec. "Measuring viscous heating"; the
@@ -567,6 +571,29 @@ static void ghost_node(const oracle_params *P, const double *f, const double *g,
     }
 }
 
+/* Time-t frame velocity at column x of row jy, for the central differences of
+ * the internal-energy split's source: a row beyond a wall takes the ghost
+ * frame velocity of ghost_node() (the mirror node's, reflected about the wall
+ * velocity); other rows wrap or clamp like the stencil. */
+static void row_velocity(const oracle_params *P, const double *lam, int x, int jy, double u[2])
+{
+    if (P->bc_y == 2 && (jy < 0 || jy >= P->ny)) {
+        int side = jy < 0 ? 0 : 1;
+        int m = side == 0 ? -1 - jy : 2 * P->ny - 1 - jy;
+        if (m < 0)
+            m = 0;
+        if (m > P->ny - 1)
+            m = P->ny - 1;
+        const double *lm = lam + 3 * ((long)m * P->nx + x);
+        u[0] = 2.0 * P->wall_ux[side] - lm[0];
+        u[1] = -lm[1];
+        return;
+    }
+    const double *l = lam + 3 * ((long)node_index(jy, P->ny, P->bc_y) * P->nx + x);
+    u[0] = l[0];
+    u[1] = l[1];
+}
+
 static void gather(const oracle_params *P, const double *f, const double *g, const double *lam,
                    int x, int y, const double *lam_bar, double *ft, double *gt)
 {
@@ -701,16 +728,23 @@ static int node_step(const oracle_params *P, const double *f, const double *g, c
         const double *l0 = lam + 3 * n;
         long xm = (long)y * P->nx + node_index(x - 1, P->nx, P->bc_x);
         long xp = (long)y * P->nx + node_index(x + 1, P->nx, P->bc_x);
-        long ym = (long)node_index(y - 1, P->ny, P->bc_y) * P->nx + x;
-        long yp = (long)node_index(y + 1, P->ny, P->bc_y) * P->nx + x;
+        double uym[2], uyp[2];
+        row_velocity(P, lam, x, y - 1, uym);
+        row_velocity(P, lam, x, y + 1, uyp);
         double a[2] = {ln[0] - l0[0], ln[1] - l0[1]};
         double grad[2][2];
         for (int b = 0; b < 2; b++) {
             grad[0][b] = 0.5 * (lam[3 * xp + b] - lam[3 * xm + b]);
-            grad[1][b] = 0.5 * (lam[3 * yp + b] - lam[3 * ym + b]);
+            grad[1][b] = 0.5 * (uyp[b] - uym[b]);
         }
-        double S[QMAX];
-        oracle_internal_source_q(q1, ft, ln, a, grad, S);
+        /* the source's f is the step's time-centred population, the mean of
+           the gathered (pre-collision) and the collided f: its stress is the
+           physical one, (1 - omega/2) times the pre-collision non-equilibrium
+           stress, the same midpoint rule that makes nu = (tau - 1/2) T */
+        double fmid[QMAX], S[QMAX];
+        for (int i = 0; i < q; i++)
+            fmid[i] = 0.5 * (ft[i] + fo[i]);
+        oracle_internal_source_q(q1, fmid, ln, a, grad, S);
         for (int i = 0; i < q; i++)
             go[i] += S[i];
     }
