@@ -79,10 +79,12 @@ enum { POND_LATTICE_D2Q16 = 16, POND_LATTICE_D2Q25 = 25 };
  *   POND_SPLIT_INTERNAL: g carries the internal energy (Eq. int_energy_g,
  *     g^eq = (U'/rho + (v - u)^2/2) f^eq, sum g = rho c_v T) and, after the
  *     collision, receives the source of Eq. int_g_evolution once per step,
- *     S_i = -f~_i (C_i - u) . (d_t u + C_i . grad u), with f~ the re-projected
- *     pre-collision populations, d_t u the new minus the old frame velocity of
- *     the node and grad u central differences of the neighbours' old frame
- *     velocities (the boundary rule of bc_x / bc_y picks the neighbours).
+ *     S_i = -f_i (C_i - u) . (d_t u + C_i . grad u), with f the step's
+ *     time-centred populations (the mean of the re-projected pre-collision and
+ *     the collided f, whose stress is the physical one), d_t u the new minus
+ *     the old frame velocity of the node and grad u central differences of the
+ *     neighbours' old frame velocities (the boundary rule of bc_x / bc_y picks
+ *     the neighbours; beyond a wall, the ghost frame velocity).
  *     With prandtl != 1, g relaxes at 1/tau_1 (its flux is the heat flux).
  *   POND_SPLIT_NONTRANS: g carries the non-translational energy (Eq. nt_energy_g,
  *     g^eq = (U'/rho) f^eq, U' = rho (c_v - 1) T); the energy is
@@ -108,8 +110,8 @@ enum { POND_PREC_FP64 = 0, POND_PREC_FP32 = 1 };
  * the equilibrium moments of that state plus the mirror's non-equilibrium
  * moments.  The ghost rows reach 8 rows beyond each wall (further stencil rows
  * read the last one): enough while c_out sqrt(T) + |u_y| + 3 <= 8 at the
- * walls (c_out = 2.33 on D2Q16, 2.86 on D2Q25).  Walls run the total or the
- * non-translational split, single instances only. */
+ * walls (c_out = 2.33 on D2Q16, 2.86 on D2Q25).  Walls run every split the
+ * lattice runs (the internal split on D2Q16), single instances only. */
 enum { POND_BC_PERIODIC = 0, POND_BC_CLAMP = 1, POND_BC_WALL = 2 };
 
 typedef struct {

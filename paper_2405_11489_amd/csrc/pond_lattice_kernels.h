@@ -161,15 +161,20 @@ __global__ __launch_bounds__(kBlock) void wall_ghost_kernel(StepArgs a, DevState
 #pragma unroll
     for (int k = 0; k < 2 * NM; ++k) D[k] = 0.0;
     const double kin = a.split == 2 ? 0.0 : 0.5;
+    // the kinetic part of g^eq: lab velocity C (total split), peculiar C - u
+    // (internal split), none (non-translational split)
+    const double uk = a.split == 1 ? 0.0 : 1.0;
     for (int i = 0; i < L::Q; ++i) {
         const double w = L::w(i / L::Q1) * L::w(i % L::Q1);
         const double cx = L::c(i / L::Q1), cy = L::c(i % L::Q1);
-        // ghost and mirror equilibria: f^eq = rho w, g^eq of the split (lab velocity C)
+        // ghost and mirror equilibria: f^eq = rho w, g^eq of the split
         const double Cgx = sg * cx + ug0, Cgy = sg * cy + ug1;
         const double Cmx = sm * cx + um0, Cmy = sm * cy + um1;
+        const double Kgx = sg * cx + uk * ug0, Kgy = sg * cy + uk * ug1;
+        const double Kmx = sm * cx + uk * um0, Kmy = sm * cy + uk * um1;
         const double fg = rho_g * w, fm = rho_m * w;
-        const double gg = w * (rho_g * (a.cv - 1.0) * Tg + kin * rho_g * (Cgx * Cgx + Cgy * Cgy));
-        const double gm = w * (rho_m * (a.cv - 1.0) * Tm + kin * rho_m * (Cmx * Cmx + Cmy * Cmy));
+        const double gg = w * (rho_g * (a.cv - 1.0) * Tg + kin * rho_g * (Kgx * Kgx + Kgy * Kgy));
+        const double gm = w * (rho_m * (a.cv - 1.0) * Tm + kin * rho_m * (Kmx * Kmx + Kmy * Kmy));
         const double Vgx = Cgx - a.uref_x, Vgy = Cgy - a.uref_y;
         const double Vmx = Cmx - a.uref_x, Vmy = Cmy - a.uref_y;
 #pragma unroll

@@ -477,14 +477,20 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             for (int k = 0; k < NM; ++k)
                 ag[k] = ag[k] + P(om1) * (P(gqe[k]) - ag[k]) + P(om) * (P(geq[k]) - P(gqe[k]));
         }
-        // internal split: source of the g-equation, S_i = -f~_i (C_i - u) . (a + C_i . grad u)
-        // with f~ the re-projected pre-collision populations, a = d_t u = u* - u(t) and
-        // grad[al][be] = d_al u_be from central differences of the time-t frames
+        // internal split: source of the g-equation, S_i = -f_i (C_i - u) . (a + C_i . grad u)
+        // with f the step's time-centred population (the mean of the re-projected
+        // pre-collision and the collided f: a0 and (1 - omega / 2) times the higher
+        // coefficients, whose stress is the physical one), a = d_t u = u* - u(t) and
+        // grad[al][be] = d_al u_be from central differences of the time-t frames; a
+        // row beyond a wall takes the ghost frame velocity of the wall closure (the
+        // mirror node, here the node itself, reflected about the wall velocity)
         P afp[NM];
         P ax = P(0), ay = P(0), gxx = P(0), gxy = P(0), gyx = P(0), gyy = P(0);
         if constexpr (S == 1) {
+            const P half_decay = P(1.0 - 0.5 * om);
+            afp[0] = af[0];
 #pragma unroll
-            for (int k = 0; k < NM; ++k) afp[k] = af[k];
+            for (int k = 1; k < NM; ++k) afp[k] = af[k] * half_decay;
             const long long row = (long long)y * a.nx;
             const long long xm = row + wrap_index(x - 1, a.nx, a.bc_x);
             const long long xp = row + wrap_index(x + 1, a.nx, a.bc_x);
@@ -493,10 +499,19 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             // the time-t velocity is read again rather than kept live across the loop
             ax = P(ln0 - src.ux[n]);
             ay = P(ln1 - src.uy[n]);
+            double uxm = src.ux[ym], uym = src.uy[ym], uxp = src.ux[yp], uyp = src.uy[yp];
+            if (a.bc_y == 2 && y == 0) {
+                uxm = 2.0 * a.wall_ux[0] - src.ux[n];
+                uym = -src.uy[n];
+            }
+            if (a.bc_y == 2 && y == a.ny - 1) {
+                uxp = 2.0 * a.wall_ux[1] - src.ux[n];
+                uyp = -src.uy[n];
+            }
             gxx = P(0.5 * (src.ux[xp] - src.ux[xm]));
             gxy = P(0.5 * (src.uy[xp] - src.uy[xm]));
-            gyx = P(0.5 * (src.ux[yp] - src.ux[ym]));
-            gyy = P(0.5 * (src.uy[yp] - src.uy[ym]));
+            gyx = P(0.5 * (uxp - uxm));
+            gyy = P(0.5 * (uyp - uym));
         }
         const P decay = P(1.0 - om);
 #pragma unroll

@@ -56,7 +56,12 @@ def test_walls_add_ghost_rows_and_validate(pond):
     q = pond.pond_params_default(nx=4, ny=32)
     # the moment planes gain 8 ghost rows per wall: 20 floats per node
     assert pond.pond_state_bytes(p) - pond.pond_state_bytes(q) >= 16 * 4 * 80
-    for fields, status in (({"bc_x": pond.BC_WALL}, 1), ({"split": 1}, 2)):
+    # walls run the internal split on D2Q16 (as every other split), not on D2Q25
+    r = pond.pond_params_default(nx=4, ny=32, bc_y=pond.BC_WALL)
+    r.split = pond.SPLIT_INTERNAL
+    assert pond.pond_state_bytes(r) == pond.pond_state_bytes(p)
+    for fields, status in (({"bc_x": pond.BC_WALL}, 1),
+                           ({"split": pond.SPLIT_INTERNAL, "lattice": pond.LATTICE_D2Q25}, 2)):
         r = pond.pond_params_default(nx=4, ny=32, bc_y=pond.BC_WALL)
         for k, v in fields.items():
             setattr(r, k, v)

@@ -14,7 +14,7 @@ from parity_util import (field_errors, gpu_run, gpu_solver, oracle_run, plane_er
 pytestmark = pytest.mark.gpu
 
 FP64, FP32 = 0, 1
-TOTAL, NT = oracle.TOTAL, oracle.NONTRANS
+TOTAL, INT, NT = oracle.TOTAL, oracle.INTERNAL, oracle.NONTRANS
 
 
 def couette(ny=16, nx=1, Ec=72.0, **kw):
@@ -41,7 +41,7 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("lattice,split", [(16, TOTAL), (16, NT), (25, NT)])
+@pytest.mark.parametrize("lattice,split", [(16, TOTAL), (16, NT), (16, INT), (25, NT)])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_fp64_walls_match_oracle(lattice, split, case):
     w = CASES[case]()
@@ -54,11 +54,12 @@ def test_fp64_walls_match_oracle(lattice, split, case):
         assert max(errs.values()) <= 1e-12, errs
 
 
+@pytest.mark.parametrize("split", [TOTAL, INT])
 @pytest.mark.parametrize("case", ["couette_16x1", "walls_12x10"])
-def test_fp32_walls_within_1e5(case):
+def test_fp32_walls_within_1e5(case, split):
     w = CASES[case]()
-    _, _, _, _, _, m = gpu_run(w, FP32, 20)
-    P, s, _ = oracle_run(w, 20)
+    _, _, _, _, _, m = gpu_run(w, FP32, 20, split=split)
+    P, s, _ = oracle_run(w, 20, split=split)
     errs = field_errors(m, oracle.moments(P, s))
     assert max(errs.values()) <= 1e-5, errs
 
@@ -73,20 +74,22 @@ def test_fp64_steady_couette_matches_oracle():
         assert np.max(np.abs(m[k] - mo[k])) <= 1e-10 * np.max(np.abs(mo[k])), k
 
 
+@pytest.mark.parametrize("split", [TOTAL, INT])
 @pytest.mark.parametrize("prec", [FP64, FP32])
-def test_wall_kernels_and_tiles_bitwise_equal(prec):
+def test_wall_kernels_and_tiles_bitwise_equal(prec, split):
     from paper_2405_11489_amd import pond
     w = walled_modes(37, 29, 4, mach=1.5)
-    ref = gpu_run(w, prec, 4, tuning={"kernel": pond.KERNEL_GLOBAL})
+    ref = gpu_run(w, prec, 4, split=split, tuning={"kernel": pond.KERNEL_GLOBAL})
     for tile, cap in [(pond.TILE_32x8, 0), (pond.TILE_16x16, 0), (pond.TILE_8x8, 100),
                       (pond.TILE_32x16, 0)]:
-        out = gpu_run(w, prec, 4, tuning={"kernel": pond.KERNEL_TILED, "tile": tile,
-                                          "lds_nodes": cap})
+        out = gpu_run(w, prec, 4, split=split, tuning={"kernel": pond.KERNEL_TILED, "tile": tile,
+                                                       "lds_nodes": cap})
         for x, y in zip(out[:3], ref[:3]):
             np.testing.assert_array_equal(x, y, err_msg=f"tile {tile} cap {cap}")
 
 
-@pytest.mark.parametrize("lattice,split", [(16, TOTAL), (16, NT), (25, TOTAL), (25, NT)])
+@pytest.mark.parametrize("lattice,split", [(16, TOTAL), (16, NT), (16, INT), (25, TOTAL),
+                                           (25, NT)])
 @pytest.mark.parametrize("Ec", [8.0, 72.0])
 def test_couette_temperature_profile(lattice, split, Ec):
     """Steady thermal Couette flow at ny = 32 against the analytical profile:
