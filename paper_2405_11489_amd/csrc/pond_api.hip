@@ -87,6 +87,79 @@ pond_status write_counters(pond_ctx *c, const DevCounters &in) {
     return POND_OK;
 }
 
+// The step kernels are register-limited (two or three waves per SIMD in FP32,
+// one in FP64 with the cubic stencil); the LDS of a CU is split between the
+// blocks that fit by registers.  A 32 x 8 tile at T = 1, Mach 2 needs a
+// 40 x 16 source region.
+int default_lds_nodes(int tile, bool dbl, int np, int split, int lattice) {
+    return lds_nodes_for_blocks(
+        tiled_blocks_per_cu(lattice, dbl, np, split, static_cast<TileShape>(tile)), dbl, lattice);
+}
+
+// Compute units of the current device (0 if the query fails).
+static int device_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+static long long tiles_of(const pond_params &p, int tx, int ty) {
+    return (long long)((p.nx + tx - 1) / tx) * ((p.ny + ty - 1) / ty);
+}
+
+// Block shape: 64 x 1 rows for (quasi-)one-dimensional grids, else 32 x 8.
+// D2Q16 takes the 512-lane 32 x 16 tile in FP64 when its tiles cover every CU
+// (one block per CU holds the whole LDS, as one 32 x 8 block does, with twice
+// the waves: 717 against 545 MLUPS at 512^2, Mach 2, 718 against 562 at
+// 1024^2, 1157 against 864 on the 2048^2 quadrants; at 256^2 its 128 tiles
+// leave half the CUs idle: 376 against 479), and in FP32 when the grid needs
+// more than one round of 32 x 8 blocks at three waves per SIMD but fits one
+// round of 32 x 16 blocks at four (512^2: 1664 against 1487 MLUPS; internal
+// split 1491 against 1380).  Beyond one round the four-wave kernel's spills
+// cost about what the partial round saves (1024^2: 2035 against 2068; 2048^2
+// quadrants: 2941 against 3077), and below it both shapes finish in one round
+// and the three-wave kernel is the faster.
+pond_tuning default_tuning(const pond_params &p) {
+    pond_tuning t;
+    t.kernel = POND_KERNEL_TILED;
+    const bool dbl = p.precision == POND_PREC_FP64;
+    if (p.ny < 8) {
+        t.tile = POND_TILE_64x1;
+    } else {
+        t.tile = POND_TILE_32x8;
+        if (p.lattice == POND_LATTICE_D2Q16 && p.ny >= 16) {
+            const long long cus = device_cus();
+            if (dbl) {
+                if (cus > 0 && tiles_of(p, 32, 16) >= cus) t.tile = POND_TILE_32x16;
+            } else {
+                const long long cap8 =
+                    cus * tiled_blocks_per_cu(p.lattice, false, p.interp_points, p.split,
+                                              TileShape::T32x8);
+                const long long cap16 =
+                    cus * tiled_blocks_per_cu(p.lattice, false, p.interp_points, p.split,
+                                              TileShape::T32x16);
+                if (cus > 0 && tiles_of(p, 32, 8) > cap8 && tiles_of(p, 32, 16) <= cap16)
+                    t.tile = POND_TILE_32x16;
+            }
+        }
+    }
+    t.lds_nodes =
+        default_lds_nodes(t.tile, p.precision == POND_PREC_FP64, p.interp_points, p.split,
+                          p.lattice);
+    // FP64 moments take twice the LDS: measured at 512^2, Mach 2, one 32 x 8
+    // block per CU holding its whole 40 x 16 source region beats two blocks
+    // that fall back to HBM for part of the taps (527 vs 323 MLUPS); a 32 x 16
+    // block fills one CU by its registers alone
+    if (dbl && p.ny >= 8 && p.lattice == POND_LATTICE_D2Q16)
+        t.lds_nodes = lds_nodes_for_blocks(1, true);
+    t.batch_tile_width = 0;
+    return t;
+}
+
 }  // namespace pond
 
 namespace {
@@ -184,83 +257,10 @@ void fill_args(pond_ctx *c) {
 
 bool fp64(const pond_ctx *c) { return c->p.precision == POND_PREC_FP64; }
 
-// The step kernels are register-limited (two or three waves per SIMD in FP32,
-// one in FP64 with the cubic stencil); the LDS of a CU is split between the
-// blocks that fit by registers.  A 32 x 8 tile at T = 1, Mach 2 needs a
-// 40 x 16 source region.
-int default_lds_nodes(int tile, bool dbl, int np, int split, int lattice) {
-    return lds_nodes_for_blocks(
-        tiled_blocks_per_cu(lattice, dbl, np, split, static_cast<TileShape>(tile)), dbl, lattice);
-}
-
 int halo_for(int tile, int cap, bool single_row) {
     int tx, ty;
     tile_dims(static_cast<TileShape>(tile), tx, ty);
     return halo_for_dims(tx, ty, cap, single_row);
-}
-
-// Compute units of the current device (0 if the query fails).
-int device_cus() {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    return n;
-}
-
-long long tiles_of(const pond_params &p, int tx, int ty) {
-    return (long long)((p.nx + tx - 1) / tx) * ((p.ny + ty - 1) / ty);
-}
-
-// Block shape: 64 x 1 rows for (quasi-)one-dimensional grids, else 32 x 8.
-// D2Q16 takes the 512-lane 32 x 16 tile in FP64 when its tiles cover every CU
-// (one block per CU holds the whole LDS, as one 32 x 8 block does, with twice
-// the waves: 717 against 545 MLUPS at 512^2, Mach 2, 718 against 562 at
-// 1024^2, 1157 against 864 on the 2048^2 quadrants; at 256^2 its 128 tiles
-// leave half the CUs idle: 376 against 479), and in FP32 when the grid needs
-// more than one round of 32 x 8 blocks at three waves per SIMD but fits one
-// round of 32 x 16 blocks at four (512^2: 1664 against 1487 MLUPS; internal
-// split 1491 against 1380).  Beyond one round the four-wave kernel's spills
-// cost about what the partial round saves (1024^2: 2035 against 2068; 2048^2
-// quadrants: 2941 against 3077), and below it both shapes finish in one round
-// and the three-wave kernel is the faster.
-pond_tuning default_tuning(const pond_params &p) {
-    pond_tuning t;
-    t.kernel = POND_KERNEL_TILED;
-    const bool dbl = p.precision == POND_PREC_FP64;
-    if (p.ny < 8) {
-        t.tile = POND_TILE_64x1;
-    } else {
-        t.tile = POND_TILE_32x8;
-        if (p.lattice == POND_LATTICE_D2Q16 && p.ny >= 16) {
-            const long long cus = device_cus();
-            if (dbl) {
-                if (cus > 0 && tiles_of(p, 32, 16) >= cus) t.tile = POND_TILE_32x16;
-            } else {
-                const long long cap8 =
-                    cus * tiled_blocks_per_cu(p.lattice, false, p.interp_points, p.split,
-                                              TileShape::T32x8);
-                const long long cap16 =
-                    cus * tiled_blocks_per_cu(p.lattice, false, p.interp_points, p.split,
-                                              TileShape::T32x16);
-                if (cus > 0 && tiles_of(p, 32, 8) > cap8 && tiles_of(p, 32, 16) <= cap16)
-                    t.tile = POND_TILE_32x16;
-            }
-        }
-    }
-    t.lds_nodes =
-        default_lds_nodes(t.tile, p.precision == POND_PREC_FP64, p.interp_points, p.split,
-                          p.lattice);
-    // FP64 moments take twice the LDS: measured at 512^2, Mach 2, one 32 x 8
-    // block per CU holding its whole 40 x 16 source region beats two blocks
-    // that fall back to HBM for part of the taps (527 vs 323 MLUPS); a 32 x 16
-    // block fills one CU by its registers alone
-    if (dbl && p.ny >= 8 && p.lattice == POND_LATTICE_D2Q16)
-        t.lds_nodes = lds_nodes_for_blocks(1, true);
-    t.batch_tile_width = 0;
-    return t;
 }
 
 pond_status apply_tuning(pond_ctx *c, const pond_tuning &t) {

@@ -570,16 +570,17 @@ pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out) {
     if (c->failed) return fail(POND_ERR_STATE, "context is in the error state");
     if (steps < 1) return fail(POND_ERR_INVALID_ARG, "steps must be >= 1");
     const bool dbl = c->p.precision == POND_PREC_FP64, row = c->p.ny < 8;
-    std::vector<int> tiles, widths;  // default first
+    std::vector<int> tiles, widths;  // the context's default tile first
     if (row) {
         tiles = {POND_TILE_64x1, POND_TILE_256x1};
         widths = {256};
-    } else if (dbl) {
-        tiles = {POND_TILE_16x8, POND_TILE_16x16, POND_TILE_8x8};
-        widths = {16, 32, 64};
     } else {
-        tiles = {POND_TILE_32x8, POND_TILE_16x16, POND_TILE_16x8};
-        widths = {32, 16, 64};
+        tiles = {default_tuning(c->p).tile, POND_TILE_32x8, POND_TILE_16x16, POND_TILE_16x8};
+        if (c->p.lattice == POND_LATTICE_D2Q16) tiles.push_back(POND_TILE_32x16);
+        if (dbl) tiles.push_back(POND_TILE_8x8);
+        for (size_t i = 1; i < tiles.size(); ++i)  // the default appears once
+            if (tiles[i] == tiles[0]) tiles.erase(tiles.begin() + long(i--));
+        widths = dbl ? std::vector<int>{16, 32, 64} : std::vector<int>{32, 16, 64};
     }
     Saved sv;
     s = save_state(c, sv);

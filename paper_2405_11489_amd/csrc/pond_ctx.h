@@ -51,6 +51,11 @@ Layout layout_for(long long N, size_t psize, int lattice, long long mom_nodes);
 // LDS nodes per block (the moment groups of one node each) that let
 // blocks_per_cu blocks share the 160 KiB of a CU.
 int lds_nodes_for_blocks(int blocks_per_cu, bool dbl, int lattice = 16);
+// LDS nodes per block of the tiled kernel's default share for a tile shape.
+int default_lds_nodes(int tile, bool dbl, int np, int split, int lattice);
+// Default launch configuration of a context with these parameters (on the
+// current device).
+pond_tuning default_tuning(const pond_params &p);
 
 // Largest halo h of a tx x ty tile whose source region fits cap nodes:
 // (tx + 2h)(ty + 2h) <= cap, or tx + 2h <= cap for a single-row grid (whose
