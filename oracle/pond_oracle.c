@@ -40,15 +40,24 @@
  *     and the viscous-heating part u . P^neq at omega (Sec. II points to the
  *     quasi-equilibrium approach without giving its form); in the internal-
  *     energy split g carries no viscous-heating flux, so g relaxes at omega_1;
- *   - internal-energy split source -f (v - u).(d_t u + v.grad u): added after
- *     the collision with f the time-centred population, the mean of the
- *     re-projected gathered f and the collided f (with the gathered f alone the
- *     viscous heating came out 2 tau / (2 tau - 1) times too large), u the new frame
- *     velocity, d_t u the difference between the new and the time-t frame
- *     velocity of the node, grad u central differences of the time-t frame
- *     velocities of the four neighbours (wrapped or clamped like the stencil;
- *     a neighbour row beyond a wall takes the ghost frame velocity of the
- *     wall closure, 2 U_wall - u of the mirror node along x, -u along y);
+ *   - internal-energy split source G = -f (v - u).(d_t u + v.grad u), taken
+ *     to second order in the time step the way a BGK source is: g relaxes to
+ *     the equilibrium of U = sum g + (sum G)/2 and receives (1 - omega_g/2) G
+ *     after the collision (omega_g its relaxation rate), so the energy gains
+ *     sum G per step; f in G is the time-centred population, the mean of the
+ *     re-projected gathered f and the collided f (with the gathered f alone
+ *     the viscous heating came out 2 tau / (2 tau - 1) times too large),
+ *     whose pressure tensor is rho T I + (1 - omega/2) P~neq, so that
+ *     sum G = -(omega/2) rho T div u - (1 - omega/2) P~ : grad u and the frame
+ *     temperature solves rho c_v T = sum g + (sum G)/2 in closed form (see
+ *     conserved()); u the new frame velocity, d_t u the difference between
+ *     the new and the time-t frame velocity of the node, grad u central
+ *     differences of the time-t frame velocities of the four neighbours
+ *     (wrapped or clamped like the stencil; a neighbour row beyond a wall
+ *     takes the ghost frame velocity of the wall closure, 2 U_wall - u of the
+ *     mirror node along x, -u along y).  grad u at time t lags the step's
+ *     middle by half a step, which leaves acoustic waves under-damped by
+ *     (gamma - 1) T k^2 / 2 (recorded);
  *   - non-translational split: the paper's single-relaxation BGK only (Pr = 1;
  *     its quasi-equilibrium form is not given and not built here);
  *   - walls (the thermal Couette flow of Sec. "Measuring viscous heating"; the
@@ -641,32 +650,46 @@ static void gather(const oracle_params *P, const double *f, const double *g, con
  * Conserved moments of (f, g) living in frame lam (Sec. II): density and
  * momentum of f, and the frame they imply: u = j/rho and
  *   total-energy split:    E = sum g,     T = (E - |j|^2/(2 rho)) / (rho c_v);
- *   internal-energy split: U = sum g,     T = U / (rho c_v)  (E = U + K);
+ *   internal-energy split: rho c_v T = sum g + (sum G)/2 with the step's
+ *     source sum G = -(omega/2) rho T div u - (1 - omega/2) P : grad u (P the
+ *     pressure tensor of f about u; zero grad: T = sum g / (rho c_v));
  *   non-translational split: E = sum (g + |C_i|^2 f / 2) (Eq. nt_energy_g),
  *                          T = (E - |j|^2/(2 rho)) / (rho c_v).
  * *E receives the split's energy sum (sum g, or E of the non-translational
  * split).
  */
 static void conserved(int q1, int split, const double *ft, const double *gt, const double *lam,
-                      double cv, double *rho, double *jx, double *jy, double *E, double *lam_new)
+                      double cv, double omega, const double grad[2][2], double *rho, double *jx,
+                      double *jy, double *E, double *lam_new)
 {
     double cx[QMAX], cy[QMAX], w[QMAX];
     int q = oracle_lattice_2d_q(q1, cx, cy, w);
     double sT = sqrt(lam[2]);
-    double r = 0.0, px = 0.0, py = 0.0, e = 0.0;
+    double r = 0.0, px = 0.0, py = 0.0, e = 0.0, sxx = 0.0, sxy = 0.0, syy = 0.0;
     for (int i = 0; i < q; i++) {
         double Cx = sT * cx[i] + lam[0], Cy = sT * cy[i] + lam[1];
         r += ft[i];
         px += ft[i] * Cx;
         py += ft[i] * Cy;
         e += gt[i];
+        sxx += ft[i] * Cx * Cx;
+        sxy += ft[i] * Cx * Cy;
+        syy += ft[i] * Cy * Cy;
         if (split == 2)
             e += 0.5 * (Cx * Cx + Cy * Cy) * ft[i];
     }
     *rho = r; *jx = px; *jy = py; *E = e;
     lam_new[0] = px / r;
     lam_new[1] = py / r;
-    lam_new[2] = split == 1 ? e / (r * cv) : (e - (px * px + py * py) / (2.0 * r)) / (r * cv);
+    if (split == 1) {
+        double ux = px / r, uy = py / r;
+        double Pxx = sxx - r * ux * ux, Pxy = sxy - r * ux * uy, Pyy = syy - r * uy * uy;
+        double PdU = Pxx * grad[0][0] + Pxy * (grad[0][1] + grad[1][0]) + Pyy * grad[1][1];
+        double div = grad[0][0] + grad[1][1];
+        lam_new[2] = (e - 0.5 * (1.0 - 0.5 * omega) * PdU) / (r * (cv + 0.25 * omega * div));
+    } else {
+        lam_new[2] = (e - (px * px + py * py) / (2.0 * r)) / (r * cv);
+    }
 }
 
 /*
@@ -691,11 +714,23 @@ static int node_step(const oracle_params *P, const double *f, const double *g, c
     double lg[3] = {lam[3 * n], lam[3 * n + 1], lam[3 * n + 2]};
     double ln[3] = {lg[0], lg[1], lg[2]};
     double ft[QMAX], gt[QMAX];
+    double gradu[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    if (P->split == 1) {
+        long xm = (long)y * P->nx + node_index(x - 1, P->nx, P->bc_x);
+        long xp = (long)y * P->nx + node_index(x + 1, P->nx, P->bc_x);
+        double uym[2], uyp[2];
+        row_velocity(P, lam, x, y - 1, uym);
+        row_velocity(P, lam, x, y + 1, uyp);
+        for (int b = 0; b < 2; b++) {
+            gradu[0][b] = 0.5 * (lam[3 * xp + b] - lam[3 * xm + b]);
+            gradu[1][b] = 0.5 * (uyp[b] - uym[b]);
+        }
+    }
     int k, conv = 0, bad = 0, used = 0;
     for (k = 0; k < P->pc_max_iter; k++) {
         double rho, jx, jy, E;
         gather(P, f, g, lam, x, y, lg, ft, gt);
-        conserved(q1, P->split, ft, gt, lg, cv, &rho, &jx, &jy, &E, ln);
+        conserved(q1, P->split, ft, gt, lg, cv, 1.0 / P->tau, gradu, &rho, &jx, &jy, &E, ln);
         used = k + 1;
         if (!(rho > 0.0) || !(ln[2] > 0.0) || !isfinite(ln[0]) || !isfinite(ln[1]) ||
             !isfinite(ln[2]) || !isfinite(E)) {
@@ -745,8 +780,9 @@ static int node_step(const oracle_params *P, const double *f, const double *g, c
         for (int i = 0; i < q; i++)
             fmid[i] = 0.5 * (ft[i] + fo[i]);
         oracle_internal_source_q(q1, fmid, ln, a, grad, S);
+        double tau_g = P->prandtl == 1.0 ? P->tau : 0.5 + (P->tau - 0.5) / P->prandtl;
         for (int i = 0; i < q; i++)
-            go[i] += S[i];
+            go[i] += (1.0 - 0.5 / tau_g) * S[i];
     }
     lamo[0] = ln[0];
     lamo[1] = ln[1];
@@ -838,7 +874,9 @@ void oracle_moments_q(int q1, int split, long N, const double *f, const double *
     long q = (long)q1 * q1;
     for (long n = 0; n < N; n++) {
         double r, jx, jy, E, ln[3];
-        conserved(q1, split, f + q * n, g + q * n, lam + 3 * n, cv, &r, &jx, &jy, &E, ln);
+        const double nograd[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        conserved(q1, split, f + q * n, g + q * n, lam + 3 * n, cv, 0.0, nograd, &r, &jx, &jy,
+                  &E, ln);
         rho[n] = r;
         ux[n] = ln[0];
         uy[n] = ln[1];
