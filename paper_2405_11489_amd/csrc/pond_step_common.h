@@ -281,6 +281,34 @@ __device__ __forceinline__ void node_monomials(P Vx, P Vy, P mono[L::NM]) {
     }
 }
 
+// Velocity gradient of the time-t frames at node n = (x, y) for the
+// internal-energy split: central differences of the four neighbours' frame
+// velocities (wrapped or clamped like the stencil; a row beyond a wall takes
+// the ghost frame velocity of the wall closure, the mirror node -- here the
+// node itself -- reflected about the wall velocity).  gab = d_a u_b.
+__device__ __forceinline__ void frame_gradient(const StepArgs &a, const DevState &src, int x, int y,
+                                               long long n, double &gxx, double &gxy, double &gyx,
+                                               double &gyy) {
+    const long long row = (long long)y * a.nx;
+    const long long xm = row + wrap_index(x - 1, a.nx, a.bc_x);
+    const long long xp = row + wrap_index(x + 1, a.nx, a.bc_x);
+    const long long ym = (long long)wrap_index(y - 1, a.ny, a.bc_y) * a.nx + x;
+    const long long yp = (long long)wrap_index(y + 1, a.ny, a.bc_y) * a.nx + x;
+    double uxm = src.ux[ym], uym = src.uy[ym], uxp = src.ux[yp], uyp = src.uy[yp];
+    if (a.bc_y == 2 && y == 0) {
+        uxm = 2.0 * a.wall_ux[0] - src.ux[n];
+        uym = -src.uy[n];
+    }
+    if (a.bc_y == 2 && y == a.ny - 1) {
+        uxp = 2.0 * a.wall_ux[1] - src.ux[n];
+        uyp = -src.uy[n];
+    }
+    gxx = 0.5 * (src.ux[xp] - src.ux[xm]);
+    gxy = 0.5 * (src.uy[xp] - src.uy[xm]);
+    gyx = 0.5 * (uxp - uxm);
+    gyy = 0.5 * (uyp - uym);
+}
+
 // The whole step of one destination node (x, y) = node n whose time-t frame
 // is (l0, l1, l2), for the energy split S (0: total energy, 1: internal
 // energy, 2: non-translational energy) on lattice L; src is the time-t state
@@ -310,6 +338,19 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
     for (int k = 0; k < NM; ++k) Mf[k] = Mg[k] = P(0);
     bool done = !live, conv = false, bad = false;
     int used = 0;
+    // internal split: velocity gradient of the time-t frames (the same for every
+    // iterate), in the arithmetic's precision
+    P gxx = P(0), gxy = P(0), gyx = P(0), gyy = P(0);
+    if constexpr (S == 1) {
+        if (live) {
+            double dxx, dxy, dyx, dyy;
+            frame_gradient(a, src, x, y, n, dxx, dxy, dyx, dyy);
+            gxx = P(dxx);
+            gxy = P(dxy);
+            gyx = P(dyx);
+            gyy = P(dyy);
+        }
+    }
 
     for (int it = 0; it < a.pc_max_iter; ++it) {
         if (!done) {
@@ -377,9 +418,23 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             ln1 = jy / r;
             // total split: sum g = E = rho c_v T + |j|^2 / (2 rho); internal: sum g = rho c_v T;
             // non-translational: E = sum g + sum f |C|^2 / 2 = rho c_v T + |j|^2 / (2 rho)
-            if constexpr (S == 1)
-                ln2 = E / (r * a.cv);
-            else
+            if constexpr (S == 1) {
+                // the energy of the step's middle, U = sum g + (sum G) / 2, with the
+                // source's sum G = -(omega / 2) rho T div u - (1 - omega / 2) P : grad u
+                // (P the pressure tensor of the gathered f about u, from its moments
+                // about u_ref): rho c_v T = U solved for T
+                const double dx = ln0 - a.uref_x, dy = ln1 - a.uref_y;
+                const double m00 = double(Mf[mom_index(0, 0)]), m10 = double(Mf[mom_index(1, 0)]);
+                const double m01 = double(Mf[mom_index(0, 1)]), m20 = double(Mf[mom_index(2, 0)]);
+                const double m11 = double(Mf[mom_index(1, 1)]), m02 = double(Mf[mom_index(0, 2)]);
+                const double Pxx = m20 - 2.0 * dx * m10 + dx * dx * m00;
+                const double Pxy = m11 - dx * m01 - dy * m10 + dx * dy * m00;
+                const double Pyy = m02 - 2.0 * dy * m01 + dy * dy * m00;
+                const double PdU = Pxx * double(gxx) + Pxy * (double(gxy) + double(gyx)) +
+                                   Pyy * double(gyy);
+                ln2 = (E - 0.5 * (1.0 - 0.5 * a.omega) * PdU) /
+                      (r * (a.cv + 0.25 * a.omega * (double(gxx) + double(gyy))));
+            } else
                 ln2 = (E - (jx * jx + jy * jy) / (2.0 * r)) / (r * a.cv);
             used = it + 1;
             if (!(r > 0.0) || !(ln2 > 0.0) || !isfinite(ln0) || !isfinite(ln1) || !isfinite(ln2) ||
@@ -480,38 +535,20 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
         // internal split: source of the g-equation, S_i = -f_i (C_i - u) . (a + C_i . grad u)
         // with f the step's time-centred population (the mean of the re-projected
         // pre-collision and the collided f: a0 and (1 - omega / 2) times the higher
-        // coefficients, whose stress is the physical one), a = d_t u = u* - u(t) and
-        // grad[al][be] = d_al u_be from central differences of the time-t frames; a
-        // row beyond a wall takes the ghost frame velocity of the wall closure (the
-        // mirror node, here the node itself, reflected about the wall velocity)
+        // coefficients, whose stress is the physical one), a = d_t u = u* - u(t),
+        // grad u from frame_gradient; g receives (1 - omega_g / 2) S, omega_g its
+        // relaxation rate (its equilibrium already holds the other half of sum S)
         P afp[NM];
-        P ax = P(0), ay = P(0), gxx = P(0), gxy = P(0), gyx = P(0), gyy = P(0);
+        P ax = P(0), ay = P(0), src_w = P(0);
         if constexpr (S == 1) {
             const P half_decay = P(1.0 - 0.5 * om);
             afp[0] = af[0];
 #pragma unroll
             for (int k = 1; k < NM; ++k) afp[k] = af[k] * half_decay;
-            const long long row = (long long)y * a.nx;
-            const long long xm = row + wrap_index(x - 1, a.nx, a.bc_x);
-            const long long xp = row + wrap_index(x + 1, a.nx, a.bc_x);
-            const long long ym = (long long)wrap_index(y - 1, a.ny, a.bc_y) * a.nx + x;
-            const long long yp = (long long)wrap_index(y + 1, a.ny, a.bc_y) * a.nx + x;
             // the time-t velocity is read again rather than kept live across the loop
             ax = P(ln0 - src.ux[n]);
             ay = P(ln1 - src.uy[n]);
-            double uxm = src.ux[ym], uym = src.uy[ym], uxp = src.ux[yp], uyp = src.uy[yp];
-            if (a.bc_y == 2 && y == 0) {
-                uxm = 2.0 * a.wall_ux[0] - src.ux[n];
-                uym = -src.uy[n];
-            }
-            if (a.bc_y == 2 && y == a.ny - 1) {
-                uxp = 2.0 * a.wall_ux[1] - src.ux[n];
-                uyp = -src.uy[n];
-            }
-            gxx = P(0.5 * (src.ux[xp] - src.ux[xm]));
-            gxy = P(0.5 * (src.uy[xp] - src.uy[xm]));
-            gyx = P(0.5 * (uxp - uxm));
-            gyy = P(0.5 * (uyp - uym));
+            src_w = P(1.0 - 0.5 * (a.unit_prandtl ? om : a.omega1));
         }
         const P decay = P(1.0 - om);
 #pragma unroll
@@ -539,7 +576,7 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                 for (int k = 0; k < NM; ++k) ft += tab.herm[i][k] * afp[k];
                 const P ex = sTP * P(L::c(i / L::Q1)), ey = sTP * P(L::c(i % L::Q1));
                 const P Cx = ex + u0, Cy = ey + u1;
-                gv -= ft * (ex * (ax + Cx * gxx + Cy * gyx) + ey * (ay + Cx * gxy + Cy * gyy));
+                gv -= src_w * ft * (ex * (ax + Cx * gxx + Cy * gyx) + ey * (ay + Cx * gxy + Cy * gyy));
             }
             if (bad) fv = gv = P(NAN);
             pop_plane<P>(dst.f, i, a.N)[n] = fv;

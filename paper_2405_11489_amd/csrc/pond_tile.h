@@ -108,13 +108,14 @@ __device__ __forceinline__ void stencil_extent(int x, double u, double s, int &l
 // waves that hide the LDS latency.  FP32 blocks of 512 lanes ask for four: two
 // such blocks share a CU's LDS, half of it each, which holds the source region
 // of a 32 x 16 tile of an advected flow, and a grid of 4096 waves (512^2
-// nodes) then runs in a single round.  FP64 holds two unforced; D2Q25 keeps
+// nodes) then runs in a single round.  FP64 holds two unforced (the internal
+// split, whose frame temperature takes the source's work, asks); D2Q25 keeps
 // the compiler's choice (two waves in FP32, one in FP64: more would spill).
 template <typename P, int S, int NT = 256, class L = D2Q16>
 constexpr int step_min_waves() {
     if (L::Q != 16) return 1;
     if (sizeof(P) == 4) return NT == 512 ? 4 : 3;
-    return 1;
+    return S == 1 ? 2 : 1;
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
