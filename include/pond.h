@@ -69,8 +69,8 @@ typedef enum {
  * D2Q25 = D1Q5 x D1Q5, the fifth-order rule (abscissae 0, +-sqrt(5 -+ sqrt 10),
  * weights 8/15, (7 +- 2 sqrt 10)/60), Grad order 4: the frame transformation
  * keeps the moments up to order four, which the non-translational split needs
- * for f (Sec. II).  D2Q25 runs the cubic stencil with the total or the
- * non-translational split (other combinations: POND_ERR_UNSUPPORTED). */
+ * for f (Sec. II).  D2Q25 runs the cubic stencil (interp_points = 3:
+ * POND_ERR_UNSUPPORTED) with each of the three energy splits. */
 enum { POND_LATTICE_D2Q16 = 16, POND_LATTICE_D2Q25 = 25 };
 
 /* Energy split: Eqs. Es.
@@ -110,8 +110,8 @@ enum { POND_PREC_FP64 = 0, POND_PREC_FP32 = 1 };
  * the equilibrium moments of that state plus the mirror's non-equilibrium
  * moments.  The ghost rows reach 8 rows beyond each wall (further stencil rows
  * read the last one): enough while c_out sqrt(T) + |u_y| + 3 <= 8 at the
- * walls (c_out = 2.33 on D2Q16, 2.86 on D2Q25).  Walls run every split the
- * lattice runs (the internal split on D2Q16), single instances only. */
+ * walls (c_out = 2.33 on D2Q16, 2.86 on D2Q25).  Walls run every split on
+ * both lattices, single instances only. */
 enum { POND_BC_PERIODIC = 0, POND_BC_CLAMP = 1, POND_BC_WALL = 2 };
 
 typedef struct {

@@ -57,8 +57,6 @@ def params(nx, ny, *, tau, gamma=1.4, prandtl=1.0, bc_x=0, bc_y=0, interp_points
         raise ValueError("the non-translational split is built with Pr = 1 only")
     if bc_x == WALL:
         raise ValueError("walls are built for the y boundaries only")
-    if bc_y == WALL and split == INTERNAL and lattice != 16:
-        raise ValueError("walls with the internal-energy split are built on D2Q16")
     return Params(nx, ny, bc_x, bc_y, interp_points, pc_max_iter, tau, prandtl, gamma, pc_tol,
                   split, lattice, (ctypes.c_double * 2)(*wall_ux),
                   (ctypes.c_double * 2)(*wall_T))

@@ -201,8 +201,6 @@ pond_status validate(const pond_params *p) {
     if (p->split == POND_SPLIT_NONTRANS && p->prandtl != 1.0)
         return fail(POND_ERR_UNSUPPORTED,
                     "the non-translational split is built with Pr = 1 (the paper's BGK) only");
-    if (p->lattice == POND_LATTICE_D2Q25 && p->split == POND_SPLIT_INTERNAL)
-        return fail(POND_ERR_UNSUPPORTED, "D2Q25 runs the total or non-translational split");
     if (p->lattice == POND_LATTICE_D2Q25 && p->interp_points != 4)
         return fail(POND_ERR_UNSUPPORTED, "D2Q25 runs the cubic stencil (interp_points = 4)");
     if (!(p->gamma > 1.0) || !(p->gamma <= 2.0))

@@ -89,8 +89,8 @@ inline auto with_variant(int np, int split, F &&f) {
 
 // The single-instance variants of a lattice: D2Q16 takes both stencils and the
 // three energy splits (0 total, 1 internal, 2 non-translational); D2Q25 the
-// cubic stencil with the total or non-translational split (the API rejects
-// other combinations before a launch).
+// cubic stencil with the three splits (the API rejects other combinations
+// before a launch).
 template <class L, class F>
 inline auto with_lattice_variant(int np, int split, F &&f) {
     using std::integral_constant;
@@ -100,7 +100,8 @@ inline auto with_lattice_variant(int np, int split, F &&f) {
                            : f(integral_constant<int, 4>{}, integral_constant<int, 2>{});
         return with_variant(np, split, static_cast<F &&>(f));
     } else {
-        return split == 2 ? f(integral_constant<int, 4>{}, integral_constant<int, 2>{})
+        if (split == 2) return f(integral_constant<int, 4>{}, integral_constant<int, 2>{});
+        return split == 1 ? f(integral_constant<int, 4>{}, integral_constant<int, 1>{})
                           : f(integral_constant<int, 4>{}, integral_constant<int, 0>{});
     }
 }

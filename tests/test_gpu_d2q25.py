@@ -14,7 +14,7 @@ from parity_util import (field_errors, gpu_run, gpu_solver, oracle_params_for, o
 pytestmark = pytest.mark.gpu
 
 FP64, FP32 = 0, 1
-TOTAL, NT = oracle.TOTAL, oracle.NONTRANS
+TOTAL, INT, NT = oracle.TOTAL, oracle.INTERNAL, oracle.NONTRANS
 
 
 def modes(n, ny=None, mach=2.0, amp=1e-2, seed=0, tau=0.6, prandtl=1.0, T0=1.0, **kw):
@@ -45,7 +45,7 @@ CASES = {
                                                    tau=0.7, prandtl=1.0, gamma=1.8),
 }
 
-VARIANTS = [(25, TOTAL), (25, NT), (16, NT)]
+VARIANTS = [(25, TOTAL), (25, NT), (25, INT), (16, NT)]
 
 
 @pytest.mark.parametrize("lattice,split", VARIANTS)
@@ -92,6 +92,7 @@ def test_fp32_tiny_grids_within_1e5(lattice, split, case):
 @pytest.mark.parametrize("lattice,split,prec,bar", [(25, TOTAL, FP64, 1e-12),
                                                     (25, NT, FP64, 1e-12),
                                                     (25, NT, FP32, 1e-5),
+                                                    (25, INT, FP64, 1e-12),
                                                     (16, NT, FP32, 1e-5)])
 def test_full_size_sampled_nodes(lattice, split, prec, bar):
     """512 x 512 Mach-2 modes: after a few GPU steps the oracle recomputes one

@@ -41,7 +41,7 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("lattice,split", [(16, TOTAL), (16, NT), (16, INT), (25, NT)])
+@pytest.mark.parametrize("lattice,split", [(16, TOTAL), (16, NT), (16, INT), (25, NT), (25, INT)])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_fp64_walls_match_oracle(lattice, split, case):
     w = CASES[case]()
@@ -89,7 +89,7 @@ def test_wall_kernels_and_tiles_bitwise_equal(prec, split):
 
 
 @pytest.mark.parametrize("lattice,split", [(16, TOTAL), (16, NT), (16, INT), (25, TOTAL),
-                                           (25, NT)])
+                                           (25, NT), (25, INT)])
 @pytest.mark.parametrize("Ec", [8.0, 72.0])
 def test_couette_temperature_profile(lattice, split, Ec):
     """Steady thermal Couette flow at ny = 32 against the analytical profile:

@@ -78,9 +78,10 @@ def _params(w, **kw):
                          bc_x=w.bc_x, bc_y=w.bc_y, split=INTERNAL, **kw)
 
 
-def test_uniform_flow_is_a_fixed_point():
+@pytest.mark.parametrize("lattice", [16, 25])
+def test_uniform_flow_is_a_fixed_point(lattice):
     w = workloads.fourier_modes(n=6, ny=5, mach=1.5, amplitude=0.0, seed=0, tau=0.6)
-    P = _params(w)
+    P = _params(w, lattice=lattice)
     s = oracle.init(P, w.rho.ravel(), w.ux.ravel(), w.uy.ravel(), w.T.ravel())
     s1, st = oracle.step(P, s, 3)
     assert st.nonphysical == 0
@@ -127,8 +128,8 @@ def test_shear_wave_decays_at_nu_k2(U):
     assert freq == pytest.approx(k * U, abs=1e-6)
 
 
-@pytest.mark.parametrize("tau", [0.8, 0.6])
-def test_viscous_heating_balances_the_kinetic_energy_lost(tau):
+@pytest.mark.parametrize("tau,lattice", [(0.8, 16), (0.6, 16), (0.8, 25)])
+def test_viscous_heating_balances_the_kinetic_energy_lost(tau, lattice):
     """A decaying periodic shear wave (u_y = 0.1 sin kx, divergence-free): the
     internal energy the source term adds equals the kinetic energy the
     viscosity removes, up to the central differences' second-order error
@@ -141,7 +142,8 @@ def test_viscous_heating_balances_the_kinetic_energy_lost(tau):
         x = np.arange(nx)
         rho, T = np.ones((4, nx)), np.ones((4, nx))
         ux, uy = np.zeros((4, nx)), np.repeat(0.1 * np.sin(2 * np.pi * x / nx)[None, :], 4, 0)
-        P = oracle.params(nx, 4, tau=tau, gamma=1.4, prandtl=0.71, split=INTERNAL)
+        P = oracle.params(nx, 4, tau=tau, gamma=1.4, prandtl=0.71, split=INTERNAL,
+                          lattice=lattice)
         cv = 1.0 / (1.4 - 1.0)
 
         def energies(s):
