@@ -119,12 +119,14 @@ def traffic_record(kernel, precision, workload):
     return None
 
 
-def cpu_baseline(w, seconds, split=0, lattice=16):
+def cpu_baseline(w, seconds, split=0, lattice=16, threads=0):
     """The FP64 oracle, unmodified, timed on this host's cores: whole-grid steps
     of the same workload from its initial state, as many as fit in
     ~``seconds`` (at least one); if one whole-grid step would take much
     longer, one step at a random sample of nodes instead."""
     import oracle
+    if threads > 0:
+        oracle.set_num_threads(threads)
     P = oracle.params(w.nx, w.ny, tau=w.tau, gamma=w.gamma, prandtl=w.prandtl, bc_x=w.bc_x,
                       bc_y=w.bc_y, split=split, lattice=lattice)
     s = oracle.init(P, w.rho.ravel(), w.ux.ravel(), w.uy.ravel(), w.T.ravel())
@@ -389,6 +391,8 @@ def main():
     ap.add_argument("--lattice", type=int, choices=[16, 25], default=16,
                     help="D2Q16 or D2Q25 (single-instance workloads)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the CPU oracle baseline (0: all of the host's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", choices=["tiled", "global"], default="tiled")
     ap.add_argument("--tile", type=int, default=None, help="POND_TILE_* id (default: library's)")
@@ -527,7 +531,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
-        cpu = cpu_baseline(w, args.cpu_seconds, split, args.lattice)
+        cpu = cpu_baseline(w, args.cpu_seconds, split, args.lattice, args.cpu_threads)
         log(f"oracle: {cpu['value']:.4f} MLUPS on {cpu['cores']} threads ({cpu['sample']})")
 
     out = {

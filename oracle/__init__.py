@@ -78,6 +78,8 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         L.oracle_abi_version.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         L.oracle_lattice_1d.argtypes = [dp, dp]
         L.oracle_lattice_2d.argtypes = [dp, dp, dp]
         L.oracle_transform.argtypes = [dp, dp, dp, dp]
@@ -142,6 +144,11 @@ def _f64(a, shape=None):
 def num_threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's following loops (n >= 1)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def lattice_1d(q1=4):

@@ -115,6 +115,17 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Sets the threads of the following OpenMP loops (n >= 1). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Table I, row D1Q4 (rT_L = 1): abscissae +-sqrt(3 -+ sqrt 6) with weights
  * (3 +- sqrt 6)/12, the inner pair carrying the larger weight. */
 void oracle_lattice_1d(double c[Q1], double w[Q1])
