@@ -57,7 +57,7 @@ typedef struct pond_ctx pond_ctx; /* opaque; created by pond_create, owned by th
 typedef enum {
     POND_OK = 0,
     POND_ERR_INVALID_ARG = 1,   /* a parameter or input field is out of range */
-    POND_ERR_UNSUPPORTED = 2,   /* a valid option this build does not implement */
+    POND_ERR_UNSUPPORTED = 2,   /* a valid option the library does not implement */
     POND_ERR_OUT_OF_MEMORY = 3, /* device allocation failed or caller memory too small */
     POND_ERR_DEVICE = 4,        /* a HIP runtime call or kernel launch failed */
     POND_ERR_NONPHYSICAL = 5,   /* the state produced rho <= 0, T <= 0 or NaN/Inf */

@@ -177,7 +177,7 @@ def test_riemann_interfaces_with_large_velocity_jumps_fail():
 
 @pytest.mark.parametrize("npts", [4, 3])
 def test_stencil_accuracy_shear_decay_and_sod(npts):
-    """The paper's quadratic stencil (3 points) against this build's cubic one
+    """The paper's quadratic stencil (3 points) against the default cubic one
     (4 points): an advected shear wave (L = 64, U = 0.6, T = 1, tau = 0.6,
     800 steps) must decay at nu k^2 with nu = (tau - 1/2) T, and the 400 x 1
     shock tube must match the exact Riemann solution.  The measured errors
