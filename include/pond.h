@@ -273,14 +273,17 @@ POND_API pond_status pond_destroy(pond_ctx *c);
  * A batch advances several contexts together, each by the same step as
  * pond_step (the step of Sec. "Discrete velocity solver ...: PonD" with
  * Eq. propagationInterpolated; results are bit for bit those of pond_step on
- * the member alone).  One batched step is one moment pre-pass over the nodes
- * of every member and one step launch over the tiles of every member (one
- * block per tile, each XCD taking a contiguous range of the tile list); both
- * launches are replayed from HIP graphs captured at creation.
+ * the member alone).  One batched step is one step launch over the tiles of
+ * every member (one block per tile, each XCD taking a contiguous range of the
+ * tile list), which also writes the moments of the state it produces; a
+ * moment pre-pass over every member's nodes runs before it only when some
+ * member's moments are stale (after pond_init_fields or pond_import_state).
+ * Both launches are replayed from HIP graphs captured at creation.
  *
- * Members must be initialised, not in the error state, not in another batch,
- * and share precision and interp_points; sizes, boundary conditions and
- * physical parameters may differ.  While a context is a member it refuses
+ * Members must be D2Q16 contexts without walls (POND_ERR_UNSUPPORTED
+ * otherwise), initialised, not in the error state, not in another batch, and
+ * share precision, interp_points and the energy split; sizes, boundary
+ * conditions and physical parameters may differ.  While a context is a member it refuses
  * pond_step, pond_init_fields, pond_import_state, pond_set_tuning and
  * pond_destroy (POND_ERR_STATE); pond_moments, pond_stats and
  * pond_export_state stay available and see every batched step enqueued

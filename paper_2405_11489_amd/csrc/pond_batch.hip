@@ -251,11 +251,9 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
         if (!c->initialized) return fail(POND_ERR_STATE, "context %d has no state", i);
         if (c->failed) return fail(POND_ERR_STATE, "context %d is in the error state", i);
         if (c->batch) return fail(POND_ERR_STATE, "context %d already belongs to a batch", i);
-        if (c->p.lattice != POND_LATTICE_D2Q16 || c->p.split == POND_SPLIT_NONTRANS ||
-            c->p.bc_y == POND_BC_WALL)
+        if (c->p.lattice != POND_LATTICE_D2Q16 || c->p.bc_y == POND_BC_WALL)
             return fail(POND_ERR_UNSUPPORTED,
-                        "context %d: batches run D2Q16 with the total or internal split, no walls",
-                        i);
+                        "context %d: batches run D2Q16 (every energy split), no walls", i);
         if (c->p.precision != ctxs[0]->p.precision ||
             c->p.interp_points != ctxs[0]->p.interp_points || c->p.split != ctxs[0]->p.split)
             return fail(POND_ERR_INVALID_ARG,

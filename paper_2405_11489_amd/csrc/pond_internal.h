@@ -75,14 +75,18 @@ inline void tile_dims(TileShape s, int &tx, int &ty) {
 int tiled_blocks_per_cu(int lattice, bool dbl, int np, int split, TileShape shape);
 
 // Calls f(np, split) with both as std::integral_constant (np: 3 or 4 stencil
-// points per axis, split: 0 total, 1 internal energy), so kernels can be
-// picked by compile-time variant.  The batched path's variants (D2Q16).
+// points per axis, split: 0 total, 1 internal, 2 non-translational energy), so
+// kernels can be picked by compile-time variant: the D2Q16 variants, of the
+// single-instance and the batched paths alike.
 template <class F>
 inline auto with_variant(int np, int split, F &&f) {
     using std::integral_constant;
-    if (np == 3)
+    if (np == 3) {
+        if (split == 2) return f(integral_constant<int, 3>{}, integral_constant<int, 2>{});
         return split == 1 ? f(integral_constant<int, 3>{}, integral_constant<int, 1>{})
                           : f(integral_constant<int, 3>{}, integral_constant<int, 0>{});
+    }
+    if (split == 2) return f(integral_constant<int, 4>{}, integral_constant<int, 2>{});
     return split == 1 ? f(integral_constant<int, 4>{}, integral_constant<int, 1>{})
                       : f(integral_constant<int, 4>{}, integral_constant<int, 0>{});
 }
@@ -95,9 +99,6 @@ template <class L, class F>
 inline auto with_lattice_variant(int np, int split, F &&f) {
     using std::integral_constant;
     if constexpr (L::Q == 16) {
-        if (split == 2)
-            return np == 3 ? f(integral_constant<int, 3>{}, integral_constant<int, 2>{})
-                           : f(integral_constant<int, 4>{}, integral_constant<int, 2>{});
         return with_variant(np, split, static_cast<F &&>(f));
     } else {
         if (split == 2) return f(integral_constant<int, 4>{}, integral_constant<int, 2>{});

@@ -160,10 +160,34 @@ def test_export_import_resume_bitwise(prec):
         np.testing.assert_array_equal(x, y)
 
 
-def test_batch_and_server_reject_d2q25_and_nontrans():
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_nontrans_batched_equals_alone_bitwise(prec):
+    """D2Q16 with the non-translational split in a batch: every member
+    bitwise equal to its run alone."""
+    from paper_2405_11489_amd import pond
+    ws = [modes(48, 40, mach=1.5, seed=21), clamp_x(modes(33, 17, mach=2.0, seed=22)),
+          sod(nx=100, steps=10)]
+    alone = [gpu_run(w, prec, 7, split=NT)[:3] for w in ws]
+    sols = [gpu_solver(w, prec, split=NT) for w in ws]
+    try:
+        b = pond.pond_batch_create([s.ctx for s in sols])
+        try:
+            pond.pond_batch_step(b, 7)
+            pond.pond_batch_synchronize(b)
+        finally:
+            pond.pond_batch_destroy(b)
+        for s, ref in zip(sols, alone):
+            for x, y in zip(s.export_state()[:3], ref):
+                np.testing.assert_array_equal(x, y)
+    finally:
+        for s in sols:
+            s.close()
+
+
+def test_batch_rejects_d2q25_and_server_rejects_d2q25_and_nontrans():
     from paper_2405_11489_amd import pond
     w = modes(16, 8, mach=1.0, seed=23)
-    for kw in ({"lattice": 25}, {"split": NT}):
+    for kw in ({"lattice": 25},):
         a = gpu_solver(w, FP32, **kw)
         try:
             with pytest.raises(pond.PondError) as ei:
@@ -173,10 +197,11 @@ def test_batch_and_server_reject_d2q25_and_nontrans():
             a.close()
     srv = pond.pond_server_create(pond.pond_server_config_default())
     try:
-        p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma, prandtl=1.0,
-                                     lattice=25)
-        with pytest.raises(pond.PondError) as ei:
-            pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, 4)
-        assert ei.value.status == pond.ERR_UNSUPPORTED
+        for kw in ({"lattice": 25}, {"split": NT}):
+            p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma,
+                                         prandtl=1.0, **kw)
+            with pytest.raises(pond.PondError) as ei:
+                pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, 4)
+            assert ei.value.status == pond.ERR_UNSUPPORTED
     finally:
         pond.pond_server_destroy(srv)
