@@ -138,7 +138,9 @@ def test_viscous_heating_balances_the_kinetic_energy_lost(tau, lattice):
     pre-collision f alone the stress, and so the heating, came out
     2 tau / (2 tau - 1) times too large (+140 % at tau = 0.6)."""
     res = []
-    for nx in (32, 64):
+    # the second-order convergence is checked on D2Q16; D2Q25 (five times the
+    # oracle's work per node) checks the balance at the coarser grid only
+    for nx in ((32, 64) if lattice == 16 else (32,)):
         x = np.arange(nx)
         rho, T = np.ones((4, nx)), np.ones((4, nx))
         ux, uy = np.zeros((4, nx)), np.repeat(0.1 * np.sin(2 * np.pi * x / nx)[None, :], 4, 0)
@@ -157,7 +159,8 @@ def test_viscous_heating_balances_the_kinetic_energy_lost(tau, lattice):
         assert st.nonphysical == 0
         res.append(abs((k1 - k0) + (u1 - u0)) / abs(k1 - k0))
     assert res[0] <= 0.06, res
-    assert res[0] / res[1] >= 3.0, res  # second order
+    if lattice == 16:
+        assert res[0] / res[1] >= 3.0, res  # second order
 
 
 @pytest.mark.parametrize("gamma,T0", [(1.4, 1.0), (1.8, 0.25)])
