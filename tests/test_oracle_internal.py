@@ -168,7 +168,7 @@ def test_sound_speed(gamma, T0):
     """Recorded finding: the compression work enters through finite
     differences of the frame velocities, so the sound speed carries a
     spatial truncation error that the total-energy split does not have:
-    -1.8 % at L = 32, -0.46 % at L = 64 (tested here within 1 %)."""
+    -0.83 % at L = 32, -0.21 % at L = 64 (tested here within 1 %)."""
     w = workloads.acoustic_wave(L=64, tau=0.6, gamma=gamma, T0=T0, steps=96)
     _, freq = run_mode(w, 4)
     assert freq / w.meta["k"] == pytest.approx(cf.sound_speed(gamma, T0), rel=0.01)
