@@ -261,20 +261,23 @@ def test_device_tensor_fields_and_caller_memory():
         pond.pond_destroy(ctx)
 
 
+@pytest.mark.parametrize("npts", [4, 3])
 @pytest.mark.parametrize("prec", [FP64, FP32])
-def test_kernels_tiles_and_lds_capacities_bitwise_equal(prec):
+def test_kernels_tiles_and_lds_capacities_bitwise_equal(prec, npts):
     """The step is computed per node with a fixed operation order, so the
     reference kernel (taps from HBM), the tiled kernel with every block shape,
     and LDS capacities small enough to force the HBM fallback for part of the
-    taps all give the same bits (ragged 70 x 45 grid, Mach 2.5, clamp in x)."""
+    taps all give the same bits (ragged 70 x 45 grid, Mach 2.5, clamp in x),
+    with the cubic and the quadratic stencil."""
     from paper_2405_11489_amd import pond
     w = clamp_x(modes(70, 45, mach=2.5, amp=2e-2, seed=12))
-    ref = gpu_run(w, prec, 4, tuning={"kernel": pond.KERNEL_GLOBAL})
+    ref = gpu_run(w, prec, 4, interp_points=npts, tuning={"kernel": pond.KERNEL_GLOBAL})
     configs = [(pond.TILE_16x16, 0), (pond.TILE_32x8, 0), (pond.TILE_16x8, 0), (pond.TILE_8x8, 0),
                (pond.TILE_64x1, 0), (pond.TILE_256x1, 0), (pond.TILE_16x16, 300),
                (pond.TILE_8x8, 100), (pond.TILE_32x16, 0), (pond.TILE_32x16, 600)]
     for tile, cap in configs:
-        out = gpu_run(w, prec, 4, tuning={"kernel": pond.KERNEL_TILED, "tile": tile, "lds_nodes": cap})
+        out = gpu_run(w, prec, 4, interp_points=npts,
+                      tuning={"kernel": pond.KERNEL_TILED, "tile": tile, "lds_nodes": cap})
         for x, y in zip(out[:3], ref[:3]):
             np.testing.assert_array_equal(x, y, err_msg=f"tile {tile} cap {cap}")
 
