@@ -378,6 +378,7 @@ typedef struct {
     int64_t autotune_steps;    /* > 0: pond_autotune (with this many steps) the first
                                   request of every new size class at admission
                                   (default 0) */
+    int32_t split;             /* POND_SPLIT_* shared by all requests (default TOTAL) */
 } pond_server_config;
 
 enum { POND_REQ_QUEUED = 0, POND_REQ_RUNNING = 1, POND_REQ_DONE = 2, POND_REQ_FAILED = 3 };

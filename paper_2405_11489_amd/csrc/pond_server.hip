@@ -261,6 +261,7 @@ pond_status pond_server_config_default(pond_server_config *c) {
     c->autotune_steps = 0;
     c->precision = POND_PREC_FP32;
     c->interp_points = 4;
+    c->split = POND_SPLIT_TOTAL;
     return POND_OK;
 }
 
@@ -274,6 +275,9 @@ pond_status pond_server_create(const pond_server_config *cfg, pond_server **out)
         return fail(POND_ERR_INVALID_ARG, "unknown precision %d", cfg->precision);
     if (cfg->interp_points != 3 && cfg->interp_points != 4)
         return fail(POND_ERR_INVALID_ARG, "interp_points must be 3 or 4");
+    if (cfg->split != POND_SPLIT_TOTAL && cfg->split != POND_SPLIT_INTERNAL &&
+        cfg->split != POND_SPLIT_NONTRANS)
+        return fail(POND_ERR_INVALID_ARG, "unknown split %d", cfg->split);
     if (cfg->chunk_steps < 0 || cfg->autotune_steps < 0)
         return fail(POND_ERR_INVALID_ARG, "chunk_steps and autotune_steps must be >= 0");
     pond_server *s = new (std::nothrow) pond_server();
@@ -307,14 +311,14 @@ pond_status pond_server_submit(pond_server *s, const pond_params *p, const doubl
         return fail(POND_ERR_INVALID_ARG, "unknown flags 0x%x", unsigned(flags));
     const size_t bytes = pond_state_bytes(p);
     if (bytes == 0) return fail(POND_ERR_INVALID_ARG, "invalid parameters: %s", last_error());
-    if (p->precision != s->cfg.precision || p->interp_points != s->cfg.interp_points)
+    if (p->precision != s->cfg.precision || p->interp_points != s->cfg.interp_points ||
+        p->split != s->cfg.split)
         return fail(POND_ERR_INVALID_ARG,
-                    "request precision / interp_points differ from the server's (%d / %d)",
-                    s->cfg.precision, s->cfg.interp_points);
-    if (p->split != POND_SPLIT_TOTAL || p->lattice != POND_LATTICE_D2Q16 ||
-        p->bc_y == POND_BC_WALL)
-        return fail(POND_ERR_UNSUPPORTED,
-                    "the server runs D2Q16 total-energy-split requests only");
+                    "request precision / interp_points / split differ from the server's "
+                    "(%d / %d / %d)",
+                    s->cfg.precision, s->cfg.interp_points, s->cfg.split);
+    if (p->lattice != POND_LATTICE_D2Q16 || p->bc_y == POND_BC_WALL)
+        return fail(POND_ERR_UNSUPPORTED, "the server runs D2Q16 requests without walls");
     if (bytes > size_t(s->cfg.hbm_budget_bytes))
         return fail(POND_ERR_INVALID_ARG, "request needs %zu bytes, above the budget of %lld", bytes,
                     (long long)s->cfg.hbm_budget_bytes);

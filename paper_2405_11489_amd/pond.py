@@ -85,7 +85,8 @@ class pond_server_config(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32),
                 ("interp_points", ctypes.c_int32), ("max_members", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_int64), ("chunk_steps", ctypes.c_int64),
-                ("fill_nodes", ctypes.c_int64), ("autotune_steps", ctypes.c_int64)]
+                ("fill_nodes", ctypes.c_int64), ("autotune_steps", ctypes.c_int64),
+                ("split", ctypes.c_int32)]
 
 
 class pond_request_info(ctypes.Structure):

@@ -156,7 +156,7 @@ def test_batch_and_server_structs_and_host_side_validation(pond):
     any device call (these calls need no GPU)."""
     assert ctypes.sizeof(pond.pond_tuning) == 16
     assert ctypes.sizeof(pond.pond_batch_info_t) == 40
-    assert ctypes.sizeof(pond.pond_server_config) == 48
+    assert ctypes.sizeof(pond.pond_server_config) == 56
     assert ctypes.sizeof(pond.pond_request_info) == 56
     assert ctypes.sizeof(pond.pond_server_stats_t) == 128
     for call in (lambda: pond.pond_batch_create([]),
@@ -172,11 +172,12 @@ def test_batch_and_server_structs_and_host_side_validation(pond):
     pond.pond_batch_destroy(None)
     pond.pond_server_destroy(None)
     c = pond.pond_server_config_default()
-    assert c.struct_size == 48 and c.hbm_budget_bytes == 64 << 30 and c.chunk_steps == 64
+    assert c.struct_size == 56 and c.hbm_budget_bytes == 64 << 30 and c.chunk_steps == 64
     assert c.fill_nodes == 1 << 19
     assert c.precision == pond.PREC_FP32 and c.interp_points == 4
+    assert c.split == pond.SPLIT_TOTAL
     for bad in (dict(struct_size=12), dict(hbm_budget_bytes=0), dict(chunk_steps=-1),
-                dict(precision=7), dict(interp_points=5)):
+                dict(precision=7), dict(interp_points=5), dict(split=3)):
         cfg = pond.pond_server_config_default(**bad)
         with pytest.raises(pond.PondError) as ei:
             pond.pond_server_create(cfg)

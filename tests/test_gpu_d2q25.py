@@ -184,7 +184,7 @@ def test_nontrans_batched_equals_alone_bitwise(prec):
             s.close()
 
 
-def test_batch_rejects_d2q25_and_server_rejects_d2q25_and_nontrans():
+def test_batch_and_server_reject_d2q25():
     from paper_2405_11489_amd import pond
     w = modes(16, 8, mach=1.0, seed=23)
     for kw in ({"lattice": 25},):
@@ -197,11 +197,14 @@ def test_batch_rejects_d2q25_and_server_rejects_d2q25_and_nontrans():
             a.close()
     srv = pond.pond_server_create(pond.pond_server_config_default())
     try:
-        for kw in ({"lattice": 25}, {"split": NT}):
+        # D2Q25 is unsupported; a non-translational request differs from the
+        # default server's (total) split
+        for kw, status in (({"lattice": 25}, pond.ERR_UNSUPPORTED),
+                           ({"split": NT}, pond.ERR_INVALID_ARG)):
             p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma,
                                          prandtl=1.0, **kw)
             with pytest.raises(pond.PondError) as ei:
                 pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, 4)
-            assert ei.value.status == pond.ERR_UNSUPPORTED
+            assert ei.value.status == status
     finally:
         pond.pond_server_destroy(srv)

@@ -161,7 +161,7 @@ def test_batched_equals_alone_bitwise(prec):
             s.close()
 
 
-def test_batch_rejects_mixed_splits_and_server_rejects_internal():
+def test_batch_rejects_mixed_splits_and_server_another_split():
     from paper_2405_11489_amd import pond
     w = modes(16, 8, mach=1.0, seed=23)
     a, b = gpu_solver(w, FP32), gpu_solver(w, FP32, split=INT)
@@ -176,9 +176,9 @@ def test_batch_rejects_mixed_splits_and_server_rejects_internal():
     try:
         p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma,
                                      prandtl=w.prandtl, split=pond.SPLIT_INTERNAL)
-        with pytest.raises(pond.PondError) as ei:
+        with pytest.raises(pond.PondError) as ei:  # the server's split is the total one
             pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, 4)
-        assert ei.value.status == pond.ERR_UNSUPPORTED
+        assert ei.value.status == pond.ERR_INVALID_ARG
     finally:
         pond.pond_server_destroy(srv)
 

@@ -91,6 +91,42 @@ def test_served_results_equal_solo_results_bitwise():
         pond.pond_server_destroy(srv)
 
 
+@pytest.mark.parametrize("split", [1, 2])
+def test_internal_and_nontrans_servers_equal_solo_bitwise(split):
+    """A server set to the internal (1) or non-translational (2) split serves
+    requests of that split, each equal to its run alone bit for bit; a request
+    of another split is refused."""
+    from paper_2405_11489_amd import pond
+    reqs = [(workloads.fourier_modes(n=24, ny=16, mach=1.5, amplitude=1e-2, seed=31, tau=0.6,
+                                     prandtl=1.0), 9),
+            (workloads.shear_wave(L=32, ny=4, tau=0.6, U=1.0, A=1e-2), 5),
+            (workloads.fourier_modes(n=40, ny=24, mach=0.8, amplitude=1e-2, seed=32, tau=0.7,
+                                     prandtl=1.0), 12)]
+    srv = _server(pond, split=split, chunk_steps=4)
+    try:
+        ids = []
+        for w, steps in reqs:
+            p = _params(pond, w)
+            p.split = split
+            ids.append(pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, steps,
+                                               pond.REQ_KEEP_STATE))
+        other = _params(pond, reqs[0][0])
+        with pytest.raises(pond.PondError) as ei:
+            pond.pond_server_submit(srv, other, reqs[0][0].rho, reqs[0][0].ux, reqs[0][0].uy,
+                                    reqs[0][0].T, 3)
+        assert ei.value.status == pond.ERR_INVALID_ARG
+        pond.pond_server_wait(srv, 0)
+        for (w, steps), i in zip(reqs, ids):
+            N = w.nodes
+            x = np.zeros(35 * N + 2)
+            pond.pond_server_result(srv, i, None, x)
+            f, g, fr, _, _, _ = gpu_run(w, FP32, steps, split=split)
+            for a, b in zip(_unpack_state(x, N), (f, g, fr)):
+                np.testing.assert_array_equal(a, b, err_msg=w.name)
+    finally:
+        pond.pond_server_destroy(srv)
+
+
 def test_failures_and_refusals():
     from paper_2405_11489_amd import pond
     good = workloads.fourier_modes(n=20, ny=12, mach=1.0, amplitude=1e-2, seed=1, tau=0.6)
