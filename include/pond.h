@@ -111,7 +111,7 @@ enum { POND_PREC_FP64 = 0, POND_PREC_FP32 = 1 };
  * moments.  The ghost rows reach 8 rows beyond each wall (further stencil rows
  * read the last one): enough while c_out sqrt(T) + |u_y| + 3 <= 8 at the
  * walls (c_out = 2.33 on D2Q16, 2.86 on D2Q25).  Walls run every split on
- * both lattices, single instances only. */
+ * both lattices, in batches and the server too (D2Q16). */
 enum { POND_BC_PERIODIC = 0, POND_BC_CLAMP = 1, POND_BC_WALL = 2 };
 
 typedef struct {
@@ -280,8 +280,9 @@ POND_API pond_status pond_destroy(pond_ctx *c);
  * member's moments are stale (after pond_init_fields or pond_import_state).
  * Both launches are replayed from HIP graphs captured at creation.
  *
- * Members must be D2Q16 contexts without walls (POND_ERR_UNSUPPORTED
- * otherwise), initialised, not in the error state, not in another batch, and
+ * Members must be D2Q16 contexts (POND_ERR_UNSUPPORTED otherwise; walls
+ * included: their ghost rows are refilled after every batched step),
+ * initialised, not in the error state, not in another batch, and
  * share precision, interp_points and the energy split; sizes, boundary
  * conditions and physical parameters may differ.  While a context is a member it refuses
  * pond_step, pond_init_fields, pond_import_state, pond_set_tuning and

@@ -148,6 +148,7 @@ using namespace pond;
 
 struct pond_batch {
     std::vector<pond_ctx *> members;
+    std::vector<int> parity0;  // each member's current buffer when the batch was built
     std::vector<int> widths;
     bool dbl;
     int np, split;
@@ -173,6 +174,22 @@ constexpr int kGraphSteps = 8;
 static_assert(kGraphSteps % 2 == 0, "the long graph must leave the buffer parity unchanged");
 
 // Moments of every member's current buffer (flip: batched steps taken so far).
+// Ghost rows of the moment planes of every walled member, for the state in
+// buffer parity0 ^ flip ^ next (next = 1: the state a batched step produces).
+hipError_t enqueue_batch_wall_ghosts(pond_batch *b, int flip, int next) {
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < b->members.size() && e == hipSuccess; ++i) {
+        const pond_ctx *c = b->members[i];
+        if (c->args.bc_y != POND_BC_WALL) continue;
+        const int par = b->parity0[i] ^ flip ^ next;
+        e = b->dbl ? launch_wall_ghosts<double>(c->args, c->buf[par],
+                                                static_cast<double *>(c->mom[par]), b->stream)
+                   : launch_wall_ghosts<float>(c->args, c->buf[par],
+                                               static_cast<float *>(c->mom[par]), b->stream);
+    }
+    return e;
+}
+
 hipError_t enqueue_batch_moments(pond_batch *b, int flip) {
     const int n = int(b->members.size());
     if (b->dbl)
@@ -181,7 +198,8 @@ hipError_t enqueue_batch_moments(pond_batch *b, int flip) {
     else
         hipLaunchKernelGGL(batch_moments_kernel<float>, dim3(b->blocks), dim3(kBatchThreads), 0,
                            b->stream, b->d_mem, b->d_blk_off, n, flip);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? enqueue_batch_wall_ghosts(b, flip, 0) : e;
 }
 
 // One batched step: every member's step kernel tiles, which also write the
@@ -200,7 +218,9 @@ hipError_t enqueue_batch_step(pond_batch *b, int flip) {
                                b->cap, flip);
         return 0;
     });
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    // walled members: the ghost rows of the moments the step wrote
+    return e == hipSuccess ? enqueue_batch_wall_ghosts(b, flip, 1) : e;
 }
 
 hipError_t capture(pond_batch *b, int steps, int flip, hipGraph_t *g, hipGraphExec_t *x) {
@@ -251,9 +271,9 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
         if (!c->initialized) return fail(POND_ERR_STATE, "context %d has no state", i);
         if (c->failed) return fail(POND_ERR_STATE, "context %d is in the error state", i);
         if (c->batch) return fail(POND_ERR_STATE, "context %d already belongs to a batch", i);
-        if (c->p.lattice != POND_LATTICE_D2Q16 || c->p.bc_y == POND_BC_WALL)
+        if (c->p.lattice != POND_LATTICE_D2Q16)
             return fail(POND_ERR_UNSUPPORTED,
-                        "context %d: batches run D2Q16 (every energy split), no walls", i);
+                        "context %d: batches run D2Q16 (every energy split and boundary)", i);
         if (c->p.precision != ctxs[0]->p.precision ||
             c->p.interp_points != ctxs[0]->p.interp_points || c->p.split != ctxs[0]->p.split)
             return fail(POND_ERR_INVALID_ARG,
@@ -315,6 +335,7 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
         m.mom[1] = c->mom[1];
         m.cnt = c->cnt;
         m.parity0 = c->cur;
+        b->parity0.push_back(c->cur);
         m.lg = lg;
         m.tiles_x = tx;
         m.tile_off = int(tiles);

@@ -317,8 +317,8 @@ pond_status pond_server_submit(pond_server *s, const pond_params *p, const doubl
                     "request precision / interp_points / split differ from the server's "
                     "(%d / %d / %d)",
                     s->cfg.precision, s->cfg.interp_points, s->cfg.split);
-    if (p->lattice != POND_LATTICE_D2Q16 || p->bc_y == POND_BC_WALL)
-        return fail(POND_ERR_UNSUPPORTED, "the server runs D2Q16 requests without walls");
+    if (p->lattice != POND_LATTICE_D2Q16)
+        return fail(POND_ERR_UNSUPPORTED, "the server runs D2Q16 requests");
     if (bytes > size_t(s->cfg.hbm_budget_bytes))
         return fail(POND_ERR_INVALID_ARG, "request needs %zu bytes, above the budget of %lld", bytes,
                     (long long)s->cfg.hbm_budget_bytes);

@@ -109,13 +109,44 @@ def test_couette_temperature_profile(lattice, split, Ec):
     assert np.max(np.abs(m["ux"][:, 0] - ua)) <= 2e-3 * w.meta["u0"]
 
 
-def test_walls_rejected_by_batch_and_server():
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_walls_in_batches_and_the_server_equal_solo_bitwise(prec):
+    """Walled members (their ghost rows refilled after every batched step)
+    next to a periodic one, over 9 steps (the 8-step graph and a single step),
+    and a walled request served: each bitwise equal to its run alone."""
     from paper_2405_11489_amd import pond
-    w = couette()
-    a = gpu_solver(w, FP32)
+    ws = [couette(ny=16, nx=3, Ec=8.0), walled_modes(37, 29, 4, mach=1.5),
+          workloads.fourier_modes(n=24, ny=20, mach=1.0, amplitude=1e-2, seed=5, tau=0.6)]
+    alone = [gpu_run(w, prec, 9)[:3] for w in ws]
+    sols = [gpu_solver(w, prec) for w in ws]
     try:
-        with pytest.raises(pond.PondError) as ei:
-            pond.pond_batch_create([a.ctx])
-        assert ei.value.status == pond.ERR_UNSUPPORTED
+        b = pond.pond_batch_create([s.ctx for s in sols])
+        try:
+            pond.pond_batch_step(b, 9)
+            pond.pond_batch_synchronize(b)
+        finally:
+            pond.pond_batch_destroy(b)
+        for s, ref, w in zip(sols, alone, ws):
+            for x, y in zip(s.export_state()[:3], ref):
+                np.testing.assert_array_equal(x, y, err_msg=w.name)
     finally:
-        a.close()
+        for s in sols:
+            s.close()
+    w = ws[1]
+    srv = pond.pond_server_create(pond.pond_server_config_default(precision=prec, chunk_steps=4))
+    try:
+        p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma,
+                                     prandtl=w.prandtl, bc_x=w.bc_x, bc_y=w.bc_y, precision=prec)
+        p.wall_ux[0], p.wall_ux[1] = w.wall_ux
+        p.wall_T[0], p.wall_T[1] = w.wall_T
+        i = pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, 9, pond.REQ_KEEP_STATE)
+        pond.pond_server_wait(srv, 0)
+        N = w.nodes
+        x = np.zeros(35 * N + 2)
+        pond.pond_server_result(srv, i, None, x)
+        got = (x[:16 * N].reshape(16, N), x[16 * N:32 * N].reshape(16, N),
+               x[32 * N:35 * N].reshape(3, N))
+        for a, b_ in zip(got, alone[1]):
+            np.testing.assert_array_equal(a, b_)
+    finally:
+        pond.pond_server_destroy(srv)
