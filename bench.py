@@ -1,22 +1,36 @@
 #!/usr/bin/env python3
 """Benchmark of the PonD f+g step (DDF-BGK, total-energy split, D2Q16) on one MI355X.
-(``--split internal``: the internal-energy split with its source term.)
 
-Workload: 512 x 512 periodic grid, uniform background (rho = 1, T = 1) advected
-at Mach 2 (30 degrees), plus 8 seeded random-phase shear / acoustic / entropy
-Fourier modes of amplitude 1e-3; tau = 0.55, Pr = 0.71, gamma = 1.4; FP32
-populations with FP64 conserved moments and frame iteration (``--precision
-fp64`` for the all-double path).  A step is one pass of the whole hot path over
-the grid: moment pre-pass + step kernel (gather, predictor-corrector,
-re-projection, collision, store).  Inputs are resident in HBM before the timed
-region; W untimed warm-up steps, then exactly K timed steps bracketed by
-synchronisations, timed with HIP events on the context's stream.
+Headline workload (the default): the 2048 x 2048 periodic four-quadrant 2-D
+Riemann problem (seeded quadrant states: rho in [0.5, 2], p in [0.3, 1.5],
+Mach up to 1.5, lattice T = 0.04 p / rho), gamma = 1.4, Pr = 0.71, nu = 2e-3;
+FP32 populations and interpolation with FP64 conserved moments, temperature
+recovery and frame iteration.  A step is one pass of the whole hot path over
+the grid (one step-kernel launch: staging, gather, predictor-corrector,
+re-projection, collision, store of the new state and of its moments).  Inputs
+are resident in HBM before the timed region; W untimed warm-up steps, then
+exactly K timed steps bracketed by device synchronisations, timed with HIP
+events on the context's stream.  Nothing else runs inside the timed region.
 
-Other workloads (``--workload``): ``sod400`` (the 400 x 1 shock tube),
-``quadrants2048`` (the 2048 x 2048 four-quadrant Riemann problem), ``batch``
-(256 mixed instances through pond_batch, against each alone) and ``serve``
-(a Poisson request stream through pond_server, against serial FIFO through
-the plain path).
+After the timed region (all untimed):
+  * kernel durations: the state saved (on the device) before the timed region
+    is restored and the same K steps run again with per-launch HIP events
+    (pond_profile_*); the replay produces the same iterations, bit for bit;
+  * the roofline of the step kernel: canonical flops per node-update
+    FP32 2750 + 13730 K, FP64 150 K + 30 (K = mean predictor-corrector gathers
+    per node), against the published MI355X peaks; HBM traffic from the
+    committed rocprofv3 counter record of the same kernel sources, if any;
+  * the FP32 result's error: the same W + K steps in FP64 (the path that
+    matches the CPU oracle to 1e-12), relative L1 and L-infinity of rho, u, T;
+  * the 512^2 Mach-2 Fourier-mode workload (same K, W) as a second line of
+    figures, a batched subset (instances through pond_batch against each
+    alone) and a served subset (a Poisson request stream through pond_server
+    against serial FIFO through the plain path, with p50 / p99 latency);
+  * the CPU oracle on a bounded sample of the headline workload.
+
+Other workloads (``--workload``): ``modes512`` (512^2 Mach-2 modes),
+``sod400`` (the 400 x 1 shock tube), ``batch`` (256 mixed instances) and
+``serve`` (the full request stream); these print their own line.
 
 Prints ONE JSON line on stdout (everything else goes to stderr).
 """
@@ -24,6 +38,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -32,14 +47,32 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "PonD f+g MLUPS & roofline %, batched/served vs plain; p50/p99 solve latency"
+
 # Published MI355X peaks (dense, no sparsity).
 PEAK_FP32_TFLOPS = 157.3        # vector FP32 with packed (dual) FMA
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic flops of the step kernel per node-update, from the method's
-# arithmetic in interpolate-then-transform form (derivation in the design notes):
+# Canonical algorithmic cost of a node-update of the D2Q16 step (the cost model
+# the roofline is quoted on): per predictor-corrector gather 13730 FP32 flops
+# (interpolation of 20 moments over 16 taps for 16 velocities 10240, the
+# moment-to-Grad transformation 2720, the reconstruction 640, departure points
+# and weights 130), once per node 2750 (source moments, re-projection,
+# collision, store); FP64: 150 per gather (conserved sums, frame) + 30.
+CANON_F32_PER_ITER = 13730
+CANON_F32_PER_NODE = 2750
+CANON_F64_PER_ITER = 150
+CANON_F64_PER_NODE = 30
+# Canonical HBM bytes of a node-update: the state (32 FP32 populations + the
+# FP64 frame) read once and written once.
+CANON_BYTES_FP32 = 2 * (128 + 24)
+CANON_BYTES_FP64 = 2 * (256 + 24)
+
+
+# This build's own count of the flops its step kernel performs per
+# node-update, in interpolate-then-transform form:
 #   per predictor-corrector iteration: departure points and weights 112,
 #   interpolation 16 velocities x NP^2 taps x (1 weight product + 20 moments x
 #   FMA) = 10496 for the cubic stencil (NP = 4), 5904 for the quadratic one,
@@ -47,7 +80,6 @@ PEAK_HBM_GBS = 8000.0
 #   once per node: moments of the gathered populations 784, re-projection 110,
 #   collision 60, reconstruction 640, and the moments of the stored populations
 #   for the next step 784 (the step kernel writes them; no separate pre-pass).
-#
 # D2Q25 (Grad order 4, 15 moments per distribution), same accounting: per
 # iteration departure points 175, interpolation 25 x NP^2 x (1 + 15 x 4),
 # transformation 25 x 2 x 85 (30 FMAs and the shared order-4 shift/scale);
@@ -62,17 +94,12 @@ def flops_per_node(q=16):
     return 1850 + 250 + 80 + 1500 + 1850 if q == 25 else 784 + 110 + 60 + 640 + 784
 
 
-FLOPS_PER_ITER = flops_per_iter(4)
-FLOPS_PER_NODE = flops_per_node()
 # internal-energy split, once per node: velocity gradient and d_t u 10, and per
 # velocity the pre-collision population (10 FMA) and the source term 17
 FLOPS_SOURCE_PER_NODE = 10 + 16 * (20 + 17)
-# double-precision part: conserved sums and frame per iteration, equilibrium once
-FLOPS64_PER_ITER = 140
-FLOPS64_PER_NODE = 60
-# Algorithmic HBM bytes of the step kernel per node (FP32 mode): frame read 24,
-# moment planes read 80, populations + frame written 128 + 24, the new moment
-# planes written 80.
+# The step kernel's own HBM bytes per node (FP32 mode): frame read 24, moment
+# planes read 80, populations + frame written 128 + 24, the new moment planes
+# written 80.
 BYTES_STEP_FP32 = 24 + 80 + 152 + 80
 BYTES_STEP_FP64 = 24 + 160 + 280 + 160
 TILE_DIMS = {0: "16,16", 1: "32,8", 2: "16,8", 3: "8,8", 4: "256,1", 5: "64,1", 6: "32,16"}
@@ -119,6 +146,25 @@ def traffic_record(kernel, precision, workload):
     return None
 
 
+def host_description():
+    """CPU model (as lscpu reports it, from /proc/cpuinfo), logical CPUs of the
+    host and CPUs this process may run on."""
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc_host": os.cpu_count(), "nproc_usable": usable}
+
+
 def cpu_baseline(w, seconds, split=0, lattice=16, threads=0):
     """The FP64 oracle, unmodified, timed on this host's cores: whole-grid steps
     of the same workload from its initial state, as many as fit in
@@ -156,7 +202,7 @@ def cpu_baseline(w, seconds, split=0, lattice=16, threads=0):
         sample = (f"one step at {count} random nodes of the {w.nx}x{w.ny} workload "
                   f"(initial state, mean {iters.mean():.2f} PC gathers), {dt:.1f} s")
     return {"value": updates / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle", "sample": sample}
+            "kind": "oracle", "sample": sample, **host_description()}
 
 
 def _ctx_for(pond, w, prec, stream=None):
@@ -369,11 +415,161 @@ def bench_serve(args, pond, workloads):
     }
 
 
+def load_workload(name, args, workloads):
+    """(workload, config name, extra config keys) of a single-instance workload."""
+    if name == "sod400":
+        w = workloads.sod_tube(nx=400, nu=2e-3)
+        return w, "sod_tube_400x1", {"nu": 2e-3, "T_scale": 0.04}
+    if name == "quadrants2048":
+        w = workloads.riemann_quadrants(n=2048, seed=0)
+        return w, "riemann_quadrants_2048x2048", {"nu": w.meta["nu"], "seed": 0,
+                                                  "states_rho_ux_uy_T": w.meta["states"]}
+    n = args.size
+    w = workloads.fourier_modes(n=n, mach=args.mach, angle_deg=30.0, amplitude=1e-3, seed=0,
+                                tau=args.tau, prandtl=0.71, gamma=1.4, steps=2000)
+    wname = f"mach{args.mach:g}_fourier_modes_{n}x{n}" + ("" if args.tau == 0.55 else f"_tau{args.tau:g}")
+    return w, wname, {"mach": args.mach}
+
+
+def measure(pond, torch, w, args, prec, split=0, lattice=16, interp_points=4, tuning=None,
+            replay=True):
+    """Time K steps (after W warm-up steps) of workload w with HIP events on the
+    context stream; then, untimed, restore the state saved before the timed
+    region and replay the same K steps with per-launch events for the kernel
+    durations.  Returns a dict of figures."""
+    stream = torch.cuda.Stream()
+    sol = pond.Solver.from_workload(w, precision=prec, stream=stream.cuda_stream,
+                                    interp_points=interp_points, split=split,
+                                    lattice=lattice, pc_tol=args.pc_tol, tuning=tuning)
+    tun = pond.pond_get_tuning(sol.ctx)
+    sol.step(args.warmup)
+    sol.synchronize()
+    st0 = sol.stats()
+    saved = None
+    if replay:
+        N, Q = w.nodes, lattice
+        dev = torch.device("cuda")
+        # f, g, frame on the device; u_ref is written through a host pointer
+        saved = [torch.empty((Q, N), dtype=torch.float64, device=dev),
+                 torch.empty((Q, N), dtype=torch.float64, device=dev),
+                 torch.empty((3, N), dtype=torch.float64, device=dev),
+                 np.zeros(2)]
+        pond.pond_export_state(sol.ctx, *saved)
+    # ---- timed region: K steps, nothing else
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sol.step(args.steps)
+    ev1.record(stream)
+    ev1.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # ---- end of the timed region
+    ms = ev0.elapsed_time(ev1)
+    st1 = sol.stats()
+    updates = w.nodes * args.steps
+    kbar = (st1.pc_iterations - st0.pc_iterations) / updates
+    out = {"ms": ms, "wall_s": wall, "mlups": updates / (ms * 1e-3) / 1e6, "kbar": kbar,
+           "nonconverged": st1.nonconverged - st0.nonconverged,
+           "nonphysical": int(st1.nonphysical), "tuning": tun, "updates": updates}
+    if replay:
+        pond.pond_import_state(sol.ctx, *saved)
+        del saved
+        pond.pond_profile_enable(sol.ctx, True)
+        sol.step(args.steps)
+        prof = pond.pond_profile_read(sol.ctx)
+        pond.pond_profile_enable(sol.ctx, False)
+        st2 = sol.stats()
+        out["step_kernel_ms"] = prof.step_ms / max(prof.launches, 1)
+        out["prepass_ms_once"] = prof.prepass_ms
+        out["replay_identical"] = st2.pc_iterations == st1.pc_iterations - st0.pc_iterations
+        if not out["replay_identical"]:
+            log(f"warning: replay took {st2.pc_iterations} gathers, the timed run "
+                f"{st1.pc_iterations - st0.pc_iterations}")
+    sol.close()
+    torch.cuda.synchronize()
+    return out
+
+
+def roofline(m, N, prec, interp_points, lattice, split, kname, traffic):
+    """Roofline of the step kernel from the replayed per-launch duration."""
+    t = m["step_kernel_ms"] * 1e-3
+    k = m["kbar"]
+    own = N * (flops_per_iter(interp_points, lattice) * k + flops_per_node(lattice) +
+               (FLOPS_SOURCE_PER_NODE if split == 1 else 0))
+    if prec == "fp32":
+        f32 = N * (CANON_F32_PER_NODE + CANON_F32_PER_ITER * k)
+        f64 = N * (CANON_F64_PER_NODE + CANON_F64_PER_ITER * k)
+        # FP32-equivalent rate: FP64 flops weighted by the ratio of the peaks
+        achieved = (f32 + f64 * PEAK_FP32_TFLOPS / PEAK_FP64_TFLOPS) / t / 1e12
+        peak, own_peak, canon_bytes, own_bytes = (PEAK_FP32_TFLOPS, PEAK_FP32_TFLOPS,
+                                                  CANON_BYTES_FP32, BYTES_STEP_FP32)
+        extra = {"peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+                 "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS}
+    else:
+        f32, f64 = 0.0, N * (CANON_F32_PER_NODE + CANON_F32_PER_ITER * k +
+                             CANON_F64_PER_NODE + CANON_F64_PER_ITER * k)
+        achieved = f64 / t / 1e12
+        peak, own_peak, canon_bytes, own_bytes = (PEAK_FP64_TFLOPS, PEAK_FP64_TFLOPS,
+                                                  CANON_BYTES_FP64, BYTES_STEP_FP64)
+        extra = {}
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                            "copy-calibrated)",
+            "kernel": kname, "kernel_ms": m["step_kernel_ms"],
+            "flops": "canonical per node-update: FP32 2750 + 13730 K, FP64 150 K + 30 "
+                     "(FP64 weighted by the FP32/FP64 peak ratio)",
+            "flops_fp32_per_launch": f32, "flops_fp64_per_launch": f64,
+            "hbm_bytes_algorithmic_per_launch": N * canon_bytes,
+            "hbm_GBs_algorithmic": N * canon_bytes / t / 1e9,
+            "hbm_frac": N * canon_bytes / t / 1e9 / PEAK_HBM_GBS,
+            "own_count": {"flops_per_launch": own, "achieved": own / t / 1e12,
+                          "frac": own / t / 1e12 / own_peak,
+                          "hbm_bytes_per_launch": N * own_bytes},
+            **extra}
+
+
+def kernel_name(m, prec, interp_points, split, lattice, kernel):
+    ptype = "float" if prec == "fp32" else "double"
+    lat = f"D2Q{lattice}"
+    if kernel == "tiled":
+        return f"step_tiled_kernel<{ptype},{interp_points},{split},{lat},{TILE_DIMS[m['tuning'].tile]}>"
+    return f"step_kernel<{ptype},{interp_points},{split},{lat}>"
+
+
+def fp32_error(pond, torch, w, args, split, lattice, interp_points):
+    """The W + K steps of w in FP32 and in FP64 (the path that agrees with the CPU
+    oracle to 1e-12): relative L1 and L-infinity of rho, u, T (u scaled by
+    max(|u|, sqrt(T)) of the FP64 field)."""
+    res = {}
+    for prec in (pond.PREC_FP32, pond.PREC_FP64):
+        with pond.Solver.from_workload(w, precision=prec, interp_points=interp_points,
+                                       split=split, lattice=lattice) as s:
+            s.step(args.warmup + args.steps)
+            res[prec] = s.moments()
+    a, b = res[pond.PREC_FP32], res[pond.PREC_FP64]
+    uscale = max(float(np.max(np.hypot(b["ux"], b["uy"]))), float(np.sqrt(np.max(b["T"]))))
+    out = {}
+    for k in ("rho", "ux", "uy", "T"):
+        d = np.abs(a[k] - b[k])
+        sc = uscale if k in ("ux", "uy") else float(np.max(np.abs(b[k])))
+        out[k] = {"L1_rel": float(np.mean(d) / (np.mean(np.abs(b[k])) if k not in ("ux", "uy")
+                                                else uscale)),
+                  "Linf_rel": float(np.max(d) / sc)}
+    return {"steps": args.warmup + args.steps, "vs": "GPU FP64 path (FP64 parity with the "
+            "CPU oracle <= 1e-12 is tested)", "fields": out,
+            "L1_rel_max": max(v["L1_rel"] for v in out.values()),
+            "Linf_rel_max": max(v["Linf_rel"] for v in out.values())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--interp-points", type=int, default=4, choices=[3, 4])
     ap.add_argument("--pc-tol", type=float, default=0.0,
@@ -381,10 +577,9 @@ def main():
     ap.add_argument("--size", type=int, default=512,
                     help="modes512 workload: grid edge (other sizes are diagnostics)")
     ap.add_argument("--mach", type=float, default=2.0,
-                    help="modes512 workload: Mach number of the background flow (the halo "
-                         "of a tile grows with it; 2 is the headline case)")
+                    help="modes512 workload: Mach number of the background flow")
     ap.add_argument("--tau", type=float, default=0.55,
-                    help="modes512 workload: relaxation time (0.55 is the headline case)")
+                    help="modes512 workload: relaxation time")
     ap.add_argument("--split", choices=["total", "internal", "nontrans"], default="total",
                     help="energy split carried by g (single-instance workloads); nontrans "
                          "runs at Pr = 1")
@@ -394,14 +589,19 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the CPU oracle baseline (0: all of the host's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only: no FP32 error run, no 512^2 line, no batched or "
+                         "served subsets")
     ap.add_argument("--kernel", choices=["tiled", "global"], default="tiled")
     ap.add_argument("--tile", type=int, default=None, help="POND_TILE_* id (default: library's)")
     ap.add_argument("--lds-nodes", type=int, default=None)
-    ap.add_argument("--workload", choices=["modes512", "sod400", "quadrants2048", "batch", "serve"],
-                    default="modes512",
-                    help="modes512: one 512^2 Mach-2 instance (headline); sod400: the 400x1 shock "
-                         "tube; quadrants2048: the 2048^2 four-quadrant Riemann problem; batch: the "
-                         "mixed 256-instance batch; serve: a Poisson request stream through the server")
+    ap.add_argument("--workload",
+                    choices=["quadrants2048", "modes512", "sod400", "batch", "serve"],
+                    default="quadrants2048",
+                    help="quadrants2048: the 2048^2 four-quadrant Riemann problem (headline); "
+                         "modes512: one 512^2 Mach-2 instance; sod400: the 400x1 shock tube; "
+                         "batch: the mixed 256-instance batch; serve: a Poisson request "
+                         "stream through the server")
     ap.add_argument("--instances", type=int, default=256, help="batch / serve: instance count")
     ap.add_argument("--max-size", type=int, default=None,
                     help="batch: largest 2-D side (default 1024); serve: largest side (default 1024)")
@@ -434,20 +634,6 @@ def main():
         print(json.dumps(bench_serve(args, pond, workloads)), flush=True)
         return
     prec = pond.PREC_FP32 if args.precision == "fp32" else pond.PREC_FP64
-    if args.workload == "sod400":
-        w = workloads.sod_tube(nx=400, nu=2e-3)
-        wname, wconf = "sod_tube_400x1", {"nu": 2e-3, "T_scale": 0.04}
-    elif args.workload == "quadrants2048":
-        w = workloads.riemann_quadrants(n=2048, seed=0)
-        wname, wconf = "riemann_quadrants_2048x2048", {"nu": w.meta["nu"], "seed": 0,
-                                                       "states": w.meta["states"]}
-    else:
-        n = args.size
-        w = workloads.fourier_modes(n=n, mach=args.mach, angle_deg=30.0, amplitude=1e-3, seed=0,
-                                    tau=args.tau, prandtl=0.71, gamma=1.4, steps=2000)
-        wname = f"mach{args.mach:g}_fourier_modes_{n}x{n}" + ("" if args.tau == 0.55 else f"_tau{args.tau:g}")
-        wconf = {"mach": args.mach}
-    stream = torch.cuda.Stream()
     tuning = {"kernel": pond.KERNEL_TILED if args.kernel == "tiled" else pond.KERNEL_GLOBAL}
     if args.tile is not None:
         tuning["tile"] = args.tile
@@ -456,34 +642,20 @@ def main():
         tuning["lds_nodes"] = args.lds_nodes
     split = {"total": pond.SPLIT_TOTAL, "internal": pond.SPLIT_INTERNAL,
              "nontrans": pond.SPLIT_NONTRANS}[args.split]
+
+    w, wname, wconf = load_workload(args.workload, args, workloads)
     if split == pond.SPLIT_NONTRANS:
         w.prandtl = 1.0
-    sol = pond.Solver.from_workload(w, precision=prec, stream=stream.cuda_stream,
-                                    interp_points=args.interp_points, split=split,
-                                    lattice=args.lattice, pc_tol=args.pc_tol, tuning=tuning)
-    tun = pond.pond_get_tuning(sol.ctx)
     log(f"workload {w.name} {w.nx}x{w.ny}, {args.precision}, {args.split} split, "
         f"warmup {args.warmup}, steps {args.steps}")
-    sol.step(args.warmup)
-    sol.synchronize()
-    st0 = sol.stats()
+    m = measure(pond, torch, w, args, prec, split, args.lattice, args.interp_points, tuning)
+    kname = kernel_name(m, args.precision, args.interp_points, split, args.lattice, args.kernel)
+    roof = roofline(m, w.nodes, args.precision, args.interp_points, args.lattice, split, kname,
+                    traffic_record(kname, args.precision, wname))
+    log(f"time {m['ms']:.1f} ms (host {m['wall_s'] * 1e3:.1f} ms), {m['mlups']:.1f} MLUPS, "
+        f"K {m['kbar']:.3f}, step kernel {m['step_kernel_ms']:.4f} ms per launch (replay), "
+        f"roofline {roof['frac']:.3f} of {roof['peak']} TFLOP/s")
 
-    pond.pond_profile_enable(sol.ctx, True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    sol.step(args.steps)
-    ev1.record(stream)
-    ev1.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1)
-    prof = pond.pond_profile_read(sol.ctx)
-    pond.pond_profile_enable(sol.ctx, False)
-    st1 = sol.stats()
-    sol.close()
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -494,39 +666,53 @@ def main():
         log(f"copy calibration: 3 x {n * 4} bytes read + written")
         del a, b
 
-    N = w.nodes
-    updates = N * args.steps
-    mlups = updates / (ms * 1e-3) / 1e6
-    kbar = (st1.pc_iterations - st0.pc_iterations) / updates
-    step_ms = prof.step_ms / max(prof.launches, 1)
-    pre_ms = prof.prepass_ms / max(prof.launches, 1)
-    log(f"time {ms:.1f} ms (host {wall * 1e3:.1f} ms), {mlups:.1f} MLUPS, K {kbar:.3f}, "
-        f"kernels: step {step_ms:.4f} ms, prepass {pre_ms:.4f} ms per launch")
-
-    flops = N * (flops_per_iter(args.interp_points, args.lattice) * kbar +
-                 flops_per_node(args.lattice) +
-                 (FLOPS_SOURCE_PER_NODE if split == pond.SPLIT_INTERNAL else 0))
-    ptype = "float" if prec == pond.PREC_FP32 else "double"
-    lat = f"D2Q{args.lattice}"
-    kname = f"step_tiled_kernel<{ptype},{args.interp_points},{split},{lat},{TILE_DIMS[tun.tile]}>" \
-        if args.kernel == "tiled" else f"step_kernel<{ptype},{args.interp_points},{split},{lat}>"
-    traffic = traffic_record(kname, args.precision, wname)
-    if prec == pond.PREC_FP32:
-        achieved = flops / (step_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                "traffic_unit": "HBM bytes per launch",
-                "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
-                "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
-                "kernel": kname, "flops_per_launch": flops,
-                "hbm_GBs_algorithmic": N * BYTES_STEP_FP32 / (step_ms * 1e-3) / 1e9}
-    else:
-        achieved = flops / (step_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                "traffic_unit": "HBM bytes per launch",
-                "kernel": kname, "flops_per_launch": flops,
-                "hbm_GBs_algorithmic": N * BYTES_STEP_FP64 / (step_ms * 1e-3) / 1e9}
+    extras = {}
+    if not args.no_extras and args.precision == "fp32":
+        log("FP32 against FP64 over the same steps ...")
+        extras["accuracy_fp32"] = fp32_error(pond, torch, w, args, split, args.lattice,
+                                             args.interp_points)
+        log(f"  L1 {extras['accuracy_fp32']['L1_rel_max']:.2e}, "
+            f"Linf {extras['accuracy_fp32']['Linf_rel_max']:.2e}")
+    if not args.no_extras and args.workload == "quadrants2048":
+        # the 512^2 Mach-2 modes workload, same K and W
+        a2 = argparse.Namespace(**vars(args))
+        w2, wname2, _ = load_workload("modes512", a2, workloads)
+        m2 = measure(pond, torch, w2, args, prec, split, args.lattice, args.interp_points, tuning)
+        kname2 = kernel_name(m2, args.precision, args.interp_points, split, args.lattice,
+                             args.kernel)
+        r2 = roofline(m2, w2.nodes, args.precision, args.interp_points, args.lattice, split,
+                      kname2, traffic_record(kname2, args.precision, wname2))
+        extras["mach2_fourier_modes_512x512"] = {
+            "value": m2["mlups"], "unit": "MLUPS", "ms_per_step": m2["ms"] / args.steps,
+            "pc_iterations_mean": m2["kbar"], "kernel": kname2,
+            "kernel_ms": m2["step_kernel_ms"], "roofline_frac": r2["frac"],
+            "roofline_achieved_TFLOPs": r2["achieved"], "traffic": r2["traffic"]}
+        log(f"512^2 modes: {m2['mlups']:.1f} MLUPS, K {m2['kbar']:.3f}, kernel "
+            f"{m2['step_kernel_ms']:.4f} ms, roofline {r2['frac']:.3f}")
+        # batched subset
+        ab = argparse.Namespace(**vars(args))
+        ab.instances, ab.max_size, ab.max_steps, ab.no_autotune = 32, 512, 600, False
+        bres = bench_batch(ab, pond, workloads)
+        extras["batched"] = {
+            "workload": f"mixed batch subset: {bres['config']['instances']} instances "
+                        f"(tubes {bres['config']['tubes']}, flows {bres['config']['flows']}, "
+                        f"Mach {bres['config']['mach']}, steps {bres['config']['steps']})",
+            "value": bres["value"], "unit": "MLUPS", "plain_MLUPS": bres["plain"]["value"],
+            "speedup_vs_plain": bres["speedup_vs_plain"], "node_updates": bres["node_updates"],
+            "pc_iterations_mean": bres["pc_iterations_mean"]}
+        # served subset
+        asv = argparse.Namespace(**vars(args))
+        asv.instances, asv.max_size, asv.max_steps, asv.dump = 64, 1024, 2000, None
+        sres = bench_serve(asv, pond, workloads)
+        extras["served"] = {
+            "workload": f"Poisson stream subset: {sres['config']['requests']} requests, "
+                        f"{sres['config']['sizes']}, steps {sres['config']['steps']}, load "
+                        f"{sres['config']['load']} of the plain capacity, HBM budget "
+                        f"{sres['config']['hbm_budget_gib']} GiB",
+            "value": sres["value"], "unit": "MLUPS",
+            "latency_s": sres["latency_s"], "failed": sres["failed"],
+            "plain_serial_fifo": {"MLUPS": sres["serial_fifo"]["plain_MLUPS"],
+                                  "latency_s": sres["serial_fifo"]["latency_s"]}}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -535,8 +721,8 @@ def main():
         log(f"oracle: {cpu['value']:.4f} MLUPS on {cpu['cores']} threads ({cpu['sample']})")
 
     out = {
-        "metric": "PonD f+g MLUPS", "value": mlups, "unit": "MLUPS", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+        "metric": METRIC, "value": m["mlups"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms"] / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if prec == pond.PREC_FP32 else "f64", "data": "synthetic",
         "config": {"workload": wname, "nx": w.nx, "ny": w.ny, **wconf,
@@ -544,13 +730,17 @@ def main():
                    "precision": args.precision, "interp_points": args.interp_points,
                    "split": args.split, "lattice": args.lattice,
                    "parallelism": "single_gpu"},
-        "tuning": {"kernel": args.kernel, "tile": tun.tile, "lds_nodes": tun.lds_nodes},
-        "pc_iterations_mean": kbar,
-        "nonconverged_node_steps": st1.nonconverged - st0.nonconverged,
-        "nonphysical_node_steps": st1.nonphysical - st0.nonphysical,
-        "kernel_ms": {"step": step_ms, "prepass": pre_ms},
+        "tuning": {"kernel": args.kernel, "tile": m["tuning"].tile,
+                   "lds_nodes": m["tuning"].lds_nodes},
+        "pc_iterations_mean": m["kbar"],
+        "nonconverged_node_steps": m["nonconverged"],
+        "nonphysical": m["nonphysical"],
+        "kernel_ms": {"step": m["step_kernel_ms"], "prepass_once": m["prepass_ms_once"],
+                      "how": "same K steps replayed untimed from the saved state, HIP events "
+                             "around each launch", "replay_identical": m["replay_identical"]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        **extras,
     }
     print(json.dumps(out), flush=True)
 
