@@ -1,6 +1,6 @@
 /*
  * pond.h -- C ABI of the MI355X particles-on-demand (PonD) f+g step library
- * (libpond.so), ABI version 1.
+ * (libpond.so).
  *
  * The library advances the double-distribution-function BGK model in its
  * total-energy split (Hosseini, Bhadauria, Karlin, arXiv:2405.11489, Sec. II,
@@ -30,8 +30,9 @@
  *     stream; pond_step does not.
  *   - One host thread may use a given context at a time.
  *   - Device-side failure flags (density or temperature <= 0, non-finite
- *     values) surface as POND_ERR_NONPHYSICAL at the next synchronising call;
- *     the context then refuses further steps with POND_ERR_STATE.
+ *     values) surface as POND_ERR_NONPHYSICAL at the next synchronising call
+ *     (stencils beyond a wall's ghost rows as POND_ERR_UNSUPPORTED); the
+ *     context then refuses further steps with POND_ERR_STATE.
  */
 #ifndef POND_H
 #define POND_H
@@ -108,10 +109,17 @@ enum { POND_PREC_FP64 = 0, POND_PREC_FP32 = 1 };
  * (u_g = 2 U_w - u_m with the normal component reversed, T_g = 2 T_w - T_m, at
  * least T_w / 4), its density keeps the mirror's pressure, and its moments are
  * the equilibrium moments of that state plus the mirror's non-equilibrium
- * moments.  The ghost rows reach 8 rows beyond each wall (further stencil rows
- * read the last one): enough while c_out sqrt(T) + |u_y| + 3 <= 8 at the
- * walls (c_out = 2.33 on D2Q16, 2.86 on D2Q25).  Walls run every split on
- * both lattices, in batches and the server too (D2Q16). */
+ * moments.  The ghost rows reach 8 rows beyond each wall: every departure
+ * stencil must stay within them, i.e. near the bottom wall, for a node on row
+ * y, floor(y - c_out sqrt(T) - u_y) - 1 >= -8 with the cubic stencil (at
+ * rest on the first row: c_out sqrt(T) <= 7, T <= 8.99 on D2Q16, 6.00 on
+ * D2Q25; c_out = 2.33 on D2Q16, 2.86 on D2Q25), likewise at the top wall.
+ * A frame that reaches further is refused at pond_init_fields and
+ * pond_import_state (POND_ERR_UNSUPPORTED); an iterate frame that gets there
+ * during a step is flagged on the device and reported as
+ * POND_ERR_UNSUPPORTED at the next synchronising call, after which the
+ * context is in the error state (as for POND_ERR_NONPHYSICAL).  Walls run
+ * every split on both lattices, in batches and the server too (D2Q16). */
 enum { POND_BC_PERIODIC = 0, POND_BC_CLAMP = 1, POND_BC_WALL = 2 };
 
 typedef struct {
@@ -163,8 +171,10 @@ POND_API int pond_abi_version(void);
 POND_API pond_status pond_params_default(pond_params *p);
 
 /* Bytes of device memory a context with these parameters uses (two state
- * buffers, the moment planes and counters), or 0 if *p is invalid.  FP32:
- * 384 B per node; FP64: 720 B per node; plus a few KiB. */
+ * buffers, two sets of moment planes, counters), or 0 if *p is invalid.
+ * D2Q16: FP32 464 B per node (2 x 152 B of state, 2 x 80 B of moments), FP64
+ * 880 B (2 x 280 + 2 x 160); D2Q25: FP32 704 B, FP64 1328 B; walls add the
+ * moment planes' ghost rows (16 rows); plus a few KiB. */
 POND_API size_t pond_state_bytes(const pond_params *p);
 
 /* Create a context.  Validates *p before touching the device: invalid values
@@ -190,7 +200,17 @@ POND_API pond_status pond_create(const pond_params *p, void *hip_stream, void *d
 POND_API pond_status pond_init_fields(pond_ctx *c, const double *rho, const double *ux, const double *uy,
                              const double *T);
 
-/* Advance nsteps >= 0 steps, asynchronously on the context stream. */
+/* Advance nsteps >= 0 steps, asynchronously on the context stream.  One step
+ * updates every node (Jacobi: each reads only the state of the previous step):
+ * the populations of each velocity are gathered at its departure point
+ * x - C_i dt by Lagrange interpolation over the stencil nodes, each stencil
+ * node's populations taken from its own frame into the node's frame (Sec.
+ * "Frame transformation", Eqs. gradGeneralTransform, a0..a3, Eq.
+ * propagationInterpolated), the node's frame is found by the
+ * predictor-corrector iteration on the gathered moments, and f and g relax
+ * toward their equilibria (Sec. II, the BGK equations of f and g).  Refused
+ * (POND_ERR_STATE) before initialisation, while the context is a batch member
+ * or once it is in the error state. */
 POND_API pond_status pond_step(pond_ctx *c, int64_t nsteps);
 
 /* Macroscopic fields of the current state (Sec. II): rho = sum f, rho u =
@@ -209,12 +229,14 @@ POND_API pond_status pond_synchronize(pond_ctx *c);
  * lattice, 16 or 25; plane i = velocity i = q1 a + b with c_i = (c_a, c_b),
  * q1 = 4 or 5, c_a ascending), frame
  * as 3 planes (u_x, u_y, T), and the 2-vector reference velocity the FP32
- * moments are taken about (nullable).  Synchronises the stream. */
+ * moments are taken about (nullable; host memory).  Synchronises the stream. */
 POND_API pond_status pond_export_state(pond_ctx *c, double *f, double *g, double *frame, double *u_ref);
 
 /* Load a raw state in the layout of pond_export_state (FP32 contexts round to
- * float).  u_ref may be NULL (mass-weighted mean velocity).  Resets the
- * counters.  Synchronises the stream. */
+ * float).  u_ref (host memory) may be NULL (mass-weighted mean velocity).
+ * With walls, a frame whose departure stencils leave the ghost rows is
+ * refused (POND_ERR_UNSUPPORTED).  Resets the counters.  Synchronises the
+ * stream. */
 POND_API pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, const double *frame,
                               const double *u_ref);
 
@@ -223,9 +245,10 @@ POND_API pond_status pond_import_state(pond_ctx *c, const double *f, const doubl
  *   kernel:    POND_KERNEL_TILED (default) stages each block's source region in
  *              LDS; POND_KERNEL_GLOBAL reads every tap from HBM (reference).
  *   tile:      POND_TILE_* block shape of the tiled kernel (destination nodes).
- *   lds_nodes: LDS capacity per block, in nodes (20 moments each: 80 B in FP32,
- *              160 B in FP64; 30 on D2Q25); taps outside the staged region
- *              read HBM.  At most 159 KiB: one KiB of the CU's 160 stays for
+ *   lds_nodes: LDS capacity per block, in nodes (the 20 moments of a node,
+ *              30 on D2Q25, padded against bank conflicts: D2Q16 80 B in FP32,
+ *              176 B in FP64; D2Q25 144 B in FP32, 240 B in FP64); taps
+ *              outside the staged region read HBM.  At most 159 KiB: one KiB of the CU's 160 stays for
  *              the kernels' static shared memory.
  *   batch_tile_width: tile of this context when it steps inside a pond_batch.
  * pond_set_tuning validates the values (POND_ERR_INVALID_ARG otherwise);
@@ -268,6 +291,7 @@ POND_API pond_status pond_profile_read(pond_ctx *c, pond_profile_t *out);
 /* Release the context and the memory it allocated.  NULL-safe.  Refused
  * (POND_ERR_STATE) while the context is a member of a batch. */
 POND_API pond_status pond_destroy(pond_ctx *c);
+
 
 /* ------------------------------------------------------------- batches ----
  * A batch advances several contexts together, each by the same step as

@@ -61,7 +61,7 @@ int lds_nodes_for_blocks(int blocks_per_cu, bool dbl, int lattice) {
     // the allocation granularity
     if (blocks_per_cu < 1) blocks_per_cu = 1;
     const int bytes = 160 * 1024 / blocks_per_cu - 1024;
-    return bytes / (moment_values(lattice, dbl) * (dbl ? 8 : 4));
+    return bytes / (lds_node_values(lattice, dbl) * (dbl ? 8 : 4));
 }
 
 pond_status check_ctx(const pond_ctx *c, bool need_init) {
@@ -76,6 +76,24 @@ pond_status read_counters(pond_ctx *c, DevCounters *out) {
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counters)");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return POND_OK;
+}
+
+pond_status counters_status(pond_ctx *c, const DevCounters &h) {
+    if (h.nonphysical) {
+        c->failed = true;
+        c->fail_status = POND_ERR_NONPHYSICAL;
+        return fail(POND_ERR_NONPHYSICAL, "%llu node-steps produced rho <= 0, T <= 0 or NaN",
+                    (unsigned long long)h.nonphysical);
+    }
+    if (h.ghost_overrun) {
+        c->failed = true;
+        c->fail_status = POND_ERR_UNSUPPORTED;
+        return fail(POND_ERR_UNSUPPORTED,
+                    "%llu node-steps had departure stencils beyond the %d ghost rows of a wall "
+                    "(the flow near the wall became too hot or too fast for the wall closure)",
+                    (unsigned long long)h.ghost_overrun, c->args.wall_h);
+    }
     return POND_OK;
 }
 
@@ -162,9 +180,7 @@ pond_tuning default_tuning(const pond_params &p) {
 
 }  // namespace pond
 
-namespace {
-
-pond_status validate(const pond_params *p) {
+pond_status pond::validate_params(const pond_params *p) {
     if (!p) return fail(POND_ERR_INVALID_ARG, "params is NULL");
     if (p->struct_size != sizeof(pond_params))
         return fail(POND_ERR_INVALID_ARG, "params.struct_size %u != %zu (ABI mismatch)",
@@ -210,24 +226,7 @@ pond_status validate(const pond_params *p) {
     return POND_OK;
 }
 
-bool is_device_pointer(const void *ptr) {
-    if (!ptr) return false;
-    hipPointerAttribute_t attr;
-    hipError_t e = hipPointerGetAttributes(&attr, ptr);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return false;
-    }
-    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
-}
-
-}  // namespace
-
-namespace {
-
-void fill_args(pond_ctx *c) {
-    const pond_params &p = c->p;
-    StepArgs &a = c->args;
+void pond::fill_step_args(const pond_params &p, StepArgs &a) {
     a.nx = p.nx;
     a.ny = p.ny;
     a.bc_x = p.bc_x;
@@ -253,6 +252,25 @@ void fill_args(pond_ctx *c) {
     a.uref_x = a.uref_y = 0.0;
 }
 
+namespace {
+
+bool is_device_pointer(const void *ptr) {
+    if (!ptr) return false;
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+namespace {
+
+void fill_args(pond_ctx *c) { fill_step_args(c->p, c->args); }
+
 bool fp64(const pond_ctx *c) { return c->p.precision == POND_PREC_FP64; }
 
 int halo_for(int tile, int cap, bool single_row) {
@@ -272,7 +290,7 @@ pond_status apply_tuning(pond_ctx *c, const pond_tuning &t) {
     if (u.lds_nodes <= 0)
         u.lds_nodes =
             default_lds_nodes(u.tile, fp64(c), c->p.interp_points, c->p.split, c->p.lattice);
-    const size_t bytes = size_t(u.lds_nodes) * moment_values(c->p.lattice, fp64(c)) * c->psize;
+    const size_t bytes = size_t(u.lds_nodes) * lds_node_values(c->p.lattice, fp64(c)) * c->psize;
     if (bytes > 159 * 1024)  // one KiB stays for the static shared memory
         return fail(POND_ERR_INVALID_ARG, "lds_nodes %d needs %zu bytes of LDS (> 159 KiB)",
                     u.lds_nodes, bytes);
@@ -293,12 +311,7 @@ pond_status sync_and_check(pond_ctx *c) {
     DevCounters h;
     pond_status s = read_counters(c, &h);
     if (s != POND_OK) return s;
-    if (h.nonphysical) {
-        c->failed = true;
-        return fail(POND_ERR_NONPHYSICAL, "%llu node-steps produced rho <= 0, T <= 0 or NaN",
-                    (unsigned long long)h.nonphysical);
-    }
-    return POND_OK;
+    return counters_status(c, h);
 }
 
 // Copy n doubles from a caller pointer (host or device) into device memory.
@@ -316,6 +329,14 @@ hipError_t launch_init_t(pond_ctx *c, const double *r, const double *ux, const d
 pond_status reset_counters(pond_ctx *c) {
     hipError_t e = hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), c->stream);
     return e == hipSuccess ? POND_OK : hip_fail(e, "hipMemsetAsync(counters)");
+}
+
+// A frame loaded with walls whose departure stencils reach beyond the ghost rows.
+pond_status ghost_band_refusal(pond_ctx *c, const DevCounters &h) {
+    return fail(POND_ERR_UNSUPPORTED,
+                "%llu nodes have departure stencils beyond the %d ghost rows of a wall: the "
+                "wall closure needs c_out sqrt(T) + |u_y| small enough near the walls",
+                (unsigned long long)h.ghost_overrun, c->args.wall_h);
 }
 
 // Operations that write the state or step it are refused while a batch owns the context.
@@ -384,7 +405,7 @@ pond_status pond_params_default(pond_params *p) {
 }
 
 size_t pond_state_bytes(const pond_params *p) {
-    if (validate(p) != POND_OK) return 0;
+    if (validate_params(p) != POND_OK) return 0;
     const size_t psize = p->precision == POND_PREC_FP64 ? sizeof(double) : sizeof(float);
     return layout_for((long long)p->nx * p->ny, psize, p->lattice, moment_plane_nodes(*p)).total;
 }
@@ -393,7 +414,7 @@ pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem
                         size_t device_mem_bytes, pond_ctx **out) {
     if (!out) return fail(POND_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    pond_status s = validate(p);
+    pond_status s = validate_params(p);
     if (s != POND_OK) return s;
     const size_t psize = p->precision == POND_PREC_FP64 ? sizeof(double) : sizeof(float);
     const long long N = (long long)p->nx * p->ny;
@@ -452,6 +473,7 @@ pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem
     fill_args(c);
     c->initialized = false;
     c->failed = false;
+    c->fail_status = POND_OK;
     c->steps = 0;
     c->profiling = false;
     c->prof_prepass_ms = c->prof_step_ms = 0.0;
@@ -492,6 +514,7 @@ pond_status pond_init_fields(pond_ctx *c, const double *rho, const double *ux, c
     }
     c->initialized = false;
     c->failed = false;
+    c->fail_status = POND_OK;
     c->cur = 0;
     c->mom_fresh = false;
     s = reset_counters(c);
@@ -504,12 +527,18 @@ pond_status pond_init_fields(pond_ctx *c, const double *rho, const double *ux, c
     if (e != hipSuccess) return hip_fail(e, "mean velocity");
     e = launch_frame_reach(N, dev[1], dev[2], dev[3], c->scratch, kScratchDoubles, c->cnt, c->stream);
     if (e != hipSuccess) return hip_fail(e, "frame reach");
+    if (c->args.wall_h) {
+        e = fp64(c) ? launch_ghost_check<double>(c->args, c->buf[0], c->cnt, c->stream)
+                    : launch_ghost_check<float>(c->args, c->buf[0], c->cnt, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "ghost band check");
+    }
     DevCounters h;
     s = read_counters(c, &h);
     if (s != POND_OK) return s;
     if (h.init_rejected)
         return fail(POND_ERR_INVALID_ARG, "%llu nodes with rho <= 0, T <= 0 or non-finite values",
                     (unsigned long long)h.init_rejected);
+    if (h.ghost_overrun) return ghost_band_refusal(c, h);
     s = set_reference_from_counters(c);
     if (s == POND_OK) s = finish_init(c, h);
     if (s != POND_OK) return s;
@@ -577,7 +606,9 @@ pond_status pond_step(pond_ctx *c, int64_t nsteps) {
     pond_status s = check_ctx(c, true);
     if (s != POND_OK) return s;
     if ((s = check_unbatched(c)) != POND_OK) return s;
-    if (c->failed) return fail(POND_ERR_STATE, "context is in the error state (non-physical)");
+    if (c->failed)
+        return fail(POND_ERR_STATE, "context is in the error state (%s)",
+                    pond_status_string(c->fail_status));
     if (nsteps < 0) return fail(POND_ERR_INVALID_ARG, "nsteps < 0");
     for (int64_t k = 0; k < nsteps; ++k) {
         hipError_t e = enqueue_step(c);
@@ -626,12 +657,7 @@ pond_status pond_stats(pond_ctx *c, pond_stats_t *out) {
     out->nonconverged = (int64_t)h.nonconverged;
     out->nonphysical = h.nonphysical ? 1 : 0;
     out->reserved = 0;
-    if (h.nonphysical) {
-        c->failed = true;
-        return fail(POND_ERR_NONPHYSICAL, "%llu node-steps produced rho <= 0, T <= 0 or NaN",
-                    (unsigned long long)h.nonphysical);
-    }
-    return POND_OK;
+    return counters_status(c, h);
 }
 
 pond_status pond_synchronize(pond_ctx *c) {
@@ -720,6 +746,7 @@ pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, con
     }
     c->initialized = false;
     c->failed = false;
+    c->fail_status = POND_OK;
     c->cur = 0;
     c->mom_fresh = false;
     s = reset_counters(c);
@@ -743,8 +770,12 @@ pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, con
     if (s == POND_OK) {
         e = launch_frame_reach(N, c->buf[0].ux, c->buf[0].uy, c->buf[0].T, c->scratch,
                                kScratchDoubles, c->cnt, c->stream);
+        if (e == hipSuccess && c->args.wall_h)
+            e = fp64(c) ? launch_ghost_check<double>(c->args, c->buf[0], c->cnt, c->stream)
+                        : launch_ghost_check<float>(c->args, c->buf[0], c->cnt, c->stream);
         DevCounters h;
         s = e == hipSuccess ? read_counters(c, &h) : hip_fail(e, "frame reach");
+        if (s == POND_OK && h.ghost_overrun) s = ghost_band_refusal(c, h);
         if (s == POND_OK) s = finish_init(c, h);
     }
     if (tmp) {

@@ -206,7 +206,8 @@ hipError_t enqueue_batch_moments(pond_batch *b, int flip) {
 // members' new moments (the moments of the current buffers must be fresh).
 hipError_t enqueue_batch_step(pond_batch *b, int flip) {
     const int n = int(b->members.size());
-    const size_t lds = size_t(b->cap) * kNMom * (b->dbl ? sizeof(double) : sizeof(float));
+    const size_t lds =
+        size_t(b->cap) * lds_node_values(16, b->dbl) * (b->dbl ? sizeof(double) : sizeof(float));
     with_variant(b->np, b->split, [&](auto np, auto sp) {
         if (b->dbl)
             hipLaunchKernelGGL((batch_step_kernel<double, np(), sp()>), dim3(b->tiles),
@@ -443,16 +444,20 @@ pond_status pond_batch_synchronize(pond_batch *b) {
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     int bad = 0;
+    pond_status first = POND_OK;
     for (pond_ctx *c : b->members) {
         DevCounters h;
         pond_status s = read_counters(c, &h);
         if (s != POND_OK) return s;
-        if (h.nonphysical) {
-            c->failed = true;
+        s = counters_status(c, h);
+        if (s != POND_OK) {
+            if (first == POND_OK) first = s;
             ++bad;
         }
     }
-    if (bad) return fail(POND_ERR_NONPHYSICAL, "%d member(s) produced rho <= 0, T <= 0 or NaN", bad);
+    if (bad)
+        return fail(first, "%d member(s) failed: produced rho <= 0, T <= 0 or NaN, or reached "
+                           "beyond a wall's ghost rows", bad);
     return POND_OK;
 }
 
@@ -519,6 +524,7 @@ pond_status restore_state(pond_ctx *c, const Saved &s) {
     c->mom_fresh = false;
     c->steps = s.steps;
     c->failed = false;
+    c->fail_status = POND_OK;
     return write_counters(c, s.cnt);
 }
 

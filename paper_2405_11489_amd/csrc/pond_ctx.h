@@ -38,6 +38,13 @@ constexpr int kScratchDoubles = 3 * 256;
 // D2Q25 32 floats or 30 doubles.
 inline int moment_values(int lattice, bool dbl) { return lattice == 25 ? (dbl ? 30 : 32) : 20; }
 
+// Values (float or double) per node of an LDS tile: the moment groups plus the
+// bank padding of the node stride (D2Q16: 20 floats, 22 doubles; D2Q25: 36
+// floats, 30 doubles).
+inline int lds_node_values(int lattice, bool dbl) {
+    return lattice == 25 ? (dbl ? 30 : 36) : (dbl ? 22 : 20);
+}
+
 // Ghost rows of the moment planes beyond each wall (bc_y == POND_BC_WALL).
 constexpr int kWallGhostRows = 8;
 
@@ -56,6 +63,12 @@ int default_lds_nodes(int tile, bool dbl, int np, int split, int lattice);
 // Default launch configuration of a context with these parameters (on the
 // current device).
 pond_tuning default_tuning(const pond_params &p);
+
+// POND_OK, or the status and message (pond_last_error) of the first invalid or
+// unsupported parameter.  Touches no device.
+pond_status validate_params(const pond_params *p);
+// Kernel arguments of a validated parameter set (reference velocity zero).
+void fill_step_args(const pond_params &p, StepArgs &a);
 
 // Largest halo h of a tx x ty tile whose source region fits cap nodes:
 // (tx + 2h)(ty + 2h) <= cap, or tx + 2h <= cap for a single-row grid (whose
@@ -86,6 +99,8 @@ struct pond_ctx {
     pond::StepArgs args;
     bool initialized;
     bool failed;
+    pond_status fail_status;  // why the context failed: POND_ERR_NONPHYSICAL or
+                              // POND_ERR_UNSUPPORTED (wall ghost rows overrun)
     long long steps;
     pond_tuning tuning;
     pond::TileConfig tc;
@@ -103,6 +118,10 @@ namespace pond {
 pond_status check_ctx(const pond_ctx *c, bool need_init);
 pond_status read_counters(pond_ctx *c, DevCounters *out);
 pond_status write_counters(pond_ctx *c, const DevCounters &in);
+// Status of counters read after steps: POND_ERR_NONPHYSICAL (non-physical
+// values) or POND_ERR_UNSUPPORTED (stencils beyond a wall's ghost rows) put the
+// context into the error state; POND_OK otherwise.
+pond_status counters_status(pond_ctx *c, const DevCounters &h);
 
 // Autotuned launch configuration of c's class (size and stencil reach), if
 // pond_autotune stored one.

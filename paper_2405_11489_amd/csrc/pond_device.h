@@ -169,6 +169,80 @@ struct LatticeTablesP {
     P herm[L::Q][L::NM];
 };
 
+// ------------------------------------------------ mass-exact float tables
+// Rounding every table entry to the nearest float leaves the column that
+// carries the mass -- the weights w_i of a0 in the reconstruction, the weights
+// of m00 in the transformation -- summing to 1 only up to a few ulps (D2Q16:
+// the sixteen weights sum to 1 - 1.96e-8).  That deficit is the same at every
+// node and every step, so FP32 steps would lose (or gain) that fraction of
+// mass and energy each step: 4e-5 of the density over 2000 steps.  The column
+// is therefore rounded so that its float entries sum to 1 exactly: after
+// rounding to nearest, the entries of one symmetry class (equal |c_x|, |c_y|
+// up to exchange of the axes, which keeps the lattice's symmetries) move
+// together by whole ulps, the class with the largest step first.
+
+// ulp of the float nearest to v (|v| normal)
+__host__ __device__ constexpr double ulp_of_float(double v) {
+    v = v < 0 ? -v : v;
+    double u = 1.0;
+    if (v >= 1.0) {
+        while (u * 2.0 <= v) u *= 2.0;
+    } else {
+        while (u > v) u *= 0.5;
+    }
+    return u / 8388608.0;  // 2^-23
+}
+
+// Rounds column col of the Q x NM table d into f (float) so that the float
+// entries sum exactly to target; returns the deficit left (0 when exact).
+template <int Q1, int NM>
+constexpr double round_column_to_sum(const double (&d)[Q1 * Q1][NM], float (&f)[Q1 * Q1][NM],
+                                     int col, double target) {
+    constexpr int Q = Q1 * Q1;
+    double sum = 0.0;  // exact: a few dozen floats within a dozen binades
+    for (int i = 0; i < Q; ++i) {
+        f[i][col] = float(d[i][col]);
+        sum += double(f[i][col]);
+    }
+    double deficit = target - sum;
+    // symmetry classes, keyed by the sorted distances of (a, b) from the centre
+    int key[Q] = {};
+    for (int i = 0; i < Q; ++i) {
+        const int da = 2 * (i / Q1) - (Q1 - 1), db = 2 * (i % Q1) - (Q1 - 1);
+        const int ua = da < 0 ? -da : da, ub = db < 0 ? -db : db;
+        key[i] = ua < ub ? ua * 64 + ub : ub * 64 + ua;
+    }
+    bool done[Q] = {};
+    for (int pass = 0; pass < Q && deficit != 0.0; ++pass) {
+        // the unprocessed class with the largest step (members x ulp)
+        int best = -1;
+        double best_step = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            if (done[i] || f[i][col] == 0.0f) continue;
+            int m = 0;
+            for (int j = 0; j < Q; ++j) m += key[j] == key[i] ? 1 : 0;
+            const double step = m * ulp_of_float(double(f[i][col]));
+            if (step > best_step) {
+                best_step = step;
+                best = i;
+            }
+        }
+        if (best < 0) break;
+        const double q = deficit / best_step;
+        const long long n = (long long)(q < 0 ? -q : q) * (q < 0 ? -1 : 1);  // toward zero
+        for (int j = 0; j < Q; ++j)
+            if (key[j] == key[best]) {
+                done[j] = true;
+                if (n != 0) {
+                    const double nv = double(f[j][col]) + double(n) * ulp_of_float(double(f[j][col]));
+                    deficit -= nv - double(f[j][col]);
+                    f[j][col] = float(nv);
+                }
+            }
+    }
+    return deficit;
+}
+
 template <typename P, class L>
 constexpr LatticeTablesP<P, L> make_lattice_tables_p() {
     const LatticeTables<L> d = make_lattice_tables<L>();
@@ -178,7 +252,19 @@ constexpr LatticeTablesP<P, L> make_lattice_tables_p() {
             t.recon[i][k] = P(d.recon[i][k]);
             t.herm[i][k] = P(d.herm[i][k]);
         }
+    if constexpr (sizeof(P) == 4) {
+        round_column_to_sum<L::Q1, L::NM>(d.recon, t.recon, 0, 1.0);
+        round_column_to_sum<L::Q1, L::NM>(d.herm, t.herm, 0, 1.0);
+    }
     return t;
+}
+
+// Exact float sum of a column (for the static checks below).
+template <int Q, int NM>
+constexpr double float_column_sum(const float (&f)[Q][NM], int col) {
+    double s = 0.0;
+    for (int i = 0; i < Q; ++i) s += double(f[i][col]);
+    return s;
 }
 
 // Generic order-N versions of central_normalised / hermite_from_central (the
@@ -248,8 +334,21 @@ constexpr VelocityTablesP<P> make_velocity_tables_p() {
             t.recon[i][k] = P(d.recon[i][k]);
             t.herm[i][k] = P(d.herm[i][k]);
         }
+    if constexpr (sizeof(P) == 4) {  // mass-exact float tables (see above)
+        round_column_to_sum<4, kNM>(d.recon, t.recon, 0, 1.0);
+        round_column_to_sum<4, kNM>(d.herm, t.herm, 0, 1.0);
+    }
     return t;
 }
+
+static_assert(float_column_sum(make_velocity_tables_p<float>().herm, 0) == 1.0,
+              "D2Q16 float weights must sum to 1 exactly");
+static_assert(float_column_sum(make_velocity_tables_p<float>().recon, 0) == 1.0,
+              "D2Q16 float m00 transform weights must sum to 1 exactly");
+static_assert(float_column_sum(make_lattice_tables_p<float, D2Q25>().herm, 0) == 1.0,
+              "D2Q25 float weights must sum to 1 exactly");
+static_assert(float_column_sum(make_lattice_tables_p<float, D2Q25>().recon, 0) == 1.0,
+              "D2Q25 float m00 transform weights must sum to 1 exactly");
 
 // Central moments about d = (dx, dy), scaled by 1/s^(p+q): the normalised
 // moments m_pq of xi = (V - d)/s, from raw moments M about the same origin.
@@ -297,17 +396,30 @@ __device__ __forceinline__ void hermite_from_central(const P m[kNM], P a[kNM]) {
 // Lagrange interpolation weights for a departure coordinate y (node units).
 // NP = 4: nodes floor(y)-1 .. floor(y)+2 (cubic); NP = 3: nodes m-1, m, m+1 with
 // m = floor(y + 1/2) (quadratic).  Returns the first node.
+// y must be finite and within the int range (the step clamps the frame it
+// computes departure points from).
 template <int NP, typename P>
 __device__ __forceinline__ int lagrange(double y, P w[NP]) {
-    y = fmin(fmax(y, -1.0e9), 1.0e9);  // keeps the node index representable
     if constexpr (NP == 4) {
         const double fl = floor(y);
         const P d = P(y - fl);
         const P dm1 = d - P(1), dm2 = d - P(2), dp1 = d + P(1);
-        w[0] = -d * dm1 * dm2 * P(1.0 / 6.0);
+        if constexpr (sizeof(P) == 4) {
+            // 1/6 is no float: fl(1/6) exceeds it by 3e-8, which would scale both
+            // outer weights, and so the weights' sum, the same way at every node
+            // and every step (a mass drift of -5e-9 per step on average); the
+            // product with 1/6 is taken as x hi + x lo with a single rounding
+            constexpr float kHi = float(1.0 / 6.0);
+            constexpr float kLo = float(1.0 / 6.0 - double(kHi));
+            const P a0 = -d * dm1 * dm2, a3 = dp1 * d * dm1;
+            w[0] = fmaf(a0, kHi, a0 * kLo);
+            w[3] = fmaf(a3, kHi, a3 * kLo);
+        } else {
+            w[0] = -d * dm1 * dm2 * P(1.0 / 6.0);
+            w[3] = dp1 * d * dm1 * P(1.0 / 6.0);
+        }
         w[1] = dp1 * dm1 * dm2 * P(0.5);
         w[2] = -dp1 * d * dm2 * P(0.5);
-        w[3] = dp1 * d * dm1 * P(1.0 / 6.0);
         return int(fl) - 1;
     } else {
         const double m = floor(y + 0.5);

@@ -23,6 +23,9 @@ struct DevCounters {
     unsigned long long nonconverged;
     unsigned long long nonphysical;
     unsigned long long init_rejected;
+    // node-steps (or, at initialisation, nodes) whose departure stencil reached
+    // beyond the ghost rows of a wall
+    unsigned long long ghost_overrun;
     double partial[4];  // scratch for deterministic reductions
 };
 
@@ -123,6 +126,10 @@ hipError_t launch_step(const StepArgs &a, DevState src, const P *mom, DevState d
 template <typename P>
 hipError_t launch_step_tiled(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
                              DevState dst, P *mom_out, DevCounters *cnt, hipStream_t s);
+// Walls (bc_y == 2): adds to cnt->ghost_overrun the nodes of st's frame whose
+// departure stencil reaches beyond the ghost rows.
+template <typename P>
+hipError_t launch_ghost_check(const StepArgs &a, DevState st, DevCounters *cnt, hipStream_t s);
 template <typename P>
 hipError_t launch_macro(const StepArgs &a, DevState st, double *rho, double *ux, double *uy,
                         double *T, double *p, hipStream_t s);

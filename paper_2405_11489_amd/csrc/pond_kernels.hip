@@ -121,6 +121,12 @@ int tiled_blocks_per_cu(int lattice, bool dbl, int np, int split, TileShape shap
 }
 
 template <typename P>
+hipError_t launch_ghost_check(const StepArgs &a, DevState st, DevCounters *cnt, hipStream_t s) {
+    return a.lattice == 25 ? Launch<P, D2Q25>::ghost_check(a, st, cnt, s)
+                           : Launch<P, D2Q16>::ghost_check(a, st, cnt, s);
+}
+
+template <typename P>
 hipError_t launch_macro(const StepArgs &a, DevState st, double *rho, double *ux, double *uy,
                         double *T, double *p, hipStream_t s) {
     return a.lattice == 25 ? Launch<P, D2Q25>::macro(a, st, rho, ux, uy, T, p, s)
@@ -183,6 +189,8 @@ hipError_t launch_state_mean_velocity(const StepArgs &a, DevState st, double *sc
     template hipError_t launch_step_tiled<P>(const StepArgs &, const TileConfig &, DevState,       \
                                              const P *, DevState, P *, DevCounters *,              \
                                              hipStream_t);                                         \
+    template hipError_t launch_ghost_check<P>(const StepArgs &, DevState, DevCounters *,       \
+                                              hipStream_t);                                        \
     template hipError_t launch_macro<P>(const StepArgs &, DevState, double *, double *, double *,  \
                                         double *, double *, hipStream_t);                          \
     template hipError_t launch_export<P>(const StepArgs &, DevState, double *, double *, double *, \

@@ -98,7 +98,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a, DevState src,
         l1 = src.uy[n];
         l2 = src.T[n];
     }
-    const GlobalTaps<P, NP, L> taps{mom, a.mstride, a.nx, a.ny, a.bc_x, a.bc_y, a.moff, a.wall_h};
+    GlobalTaps<P, NP, L> taps{mom, a.mstride, a.nx, a.ny, a.bc_x, a.bc_y, a.moff, a.wall_h, {}};
+    load_moments<P, nmom<L>()>(mom, a.mstride, a.moff + ref_node(x, y, a.nx), taps.ref);
     node_step<P, NP, S, L>(a, taps, x, y, n, live, l0, l1, l2, src, dst, mom_out, cnt);
 }
 
@@ -199,6 +200,26 @@ __global__ __launch_bounds__(kBlock) void wall_ghost_kernel(StepArgs a, DevState
 #pragma unroll
     for (int k = 0; k < 2 * NM; ++k) Mg[k] = P(double(Mm[k]) + D[k]);
     store_moments<P, nmom<L>()>(mom, a.mstride, a.moff + (long long)gy * a.nx + x, Mg);
+}
+
+// ------------------------------------------------------ ghost band ----
+// Walls (bc_y == 2): counts the nodes of a frame whose departure stencil
+// (every velocity, the stencil of NP points per axis) reaches beyond the
+// wall_h ghost rows on either side of the grid.
+template <int NP, class L>
+__global__ __launch_bounds__(kBlock) void ghost_check_kernel(StepArgs a, const double *__restrict__ uy,
+                                                             const double *__restrict__ T,
+                                                             DevCounters *cnt) {
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool out = false;
+    if (n < a.N) {
+        const int y = int(n / a.nx);
+        int lo, hi;
+        stencil_extent<NP, L>(y, uy[n], sqrt(fmax(T[n], 0.0)), lo, hi);
+        out = lo < -a.wall_h || hi > a.ny - 1 + a.wall_h;
+    }
+    const unsigned long long c = wave_sum((unsigned long long)out);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&cnt->ghost_overrun, c);
 }
 
 // ------------------------------------------------------ macroscopic ----
@@ -326,7 +347,7 @@ template <typename P, int NP, int S, class L, int TX, int TY>
 hipError_t launch_tiled_t(const StepArgs &a, const TileConfig &tc, DevState src, const P *mom,
                           DevState dst, P *mom_out, DevCounters *cnt, hipStream_t s) {
     auto kern = step_tiled_kernel<P, NP, S, L, TX, TY>;
-    const size_t lds = size_t(tc.cap) * nmom_padded<P, L>() * sizeof(P);
+    const size_t lds = size_t(tc.cap) * lds_stride<P, L>() * (16 / sizeof(P)) * sizeof(P);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -385,6 +406,7 @@ struct Launch {
     static hipError_t state_partial_sums(const StepArgs &a, DevState st, double *scratch,
                                          int nblocks, hipStream_t s);
     static int tiled_blocks_per_cu(int np, int split, TileShape shape);
+    static hipError_t ghost_check(const StepArgs &a, DevState st, DevCounters *cnt, hipStream_t s);
 };
 
 template <typename P, class L>
@@ -461,6 +483,16 @@ hipError_t Launch<P, L>::state_partial_sums(const StepArgs &a, DevState st, doub
     hipLaunchKernelGGL((lk::partial_sums_kernel<lk::StateLoader<P, L>>), dim3(nblocks),
                        dim3(lk::kBlock), 0, s, a.N, lk::StateLoader<P, L>{st, a.N}, scratch);
     return hipGetLastError();
+}
+
+template <typename P, class L>
+hipError_t Launch<P, L>::ghost_check(const StepArgs &a, DevState st, DevCounters *cnt,
+                                     hipStream_t s) {
+    return with_lattice_variant<L>(a.interp_points, a.split, [&](auto np, auto) {
+        hipLaunchKernelGGL((lk::ghost_check_kernel<np(), L>), dim3(lk::grid_for(a.N)),
+                           dim3(lk::kBlock), 0, s, a, st.uy, st.T, cnt);
+        return hipGetLastError();
+    });
 }
 
 template <typename P, class L>

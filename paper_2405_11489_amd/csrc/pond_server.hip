@@ -208,7 +208,7 @@ void worker_loop(pond_server *s) {
             if (st != POND_OK)
                 outcome[j] = st;
             else if (r->ctx->failed)
-                outcome[j] = POND_ERR_NONPHYSICAL;
+                outcome[j] = r->ctx->fail_status;
             else
                 outcome[j] = collect(r);
         }

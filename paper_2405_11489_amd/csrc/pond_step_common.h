@@ -5,15 +5,15 @@
 // Moment storage ("grouped planes"): the 2 NM moments of a node (f moments
 // 0..NM-1, g moments NM..2NM-1, ordering of pond_device.h; NM = 10 on D2Q16,
 // 15 on D2Q25) are held as G vector groups (float: float4, the last padded;
-// double: double2); group k of node idx sits at base[k * stride + idx].  The
-// same layout serves the HBM moment planes (stride = N) and the LDS tiles
-// (stride = tile capacity).
+// double: double2); in the HBM moment planes group k of node idx sits at
+// base[k * stride + idx] (stride = nodes per plane: lanes of a wave read
+// consecutive vectors); the LDS tiles hold a node's groups contiguously
+// (lds_stride below).
 #pragma once
 
 #include <utility>
 
-// Stencil rows interpolated per loop trip in the tap gather (compile-time
-// tuning: more rows in flight hide more LDS latency at the cost of registers).
+// Stencil rows interpolated per loop trip in the HBM tap gather.
 #ifndef POND_ROW_UNROLL
 #define POND_ROW_UNROLL 1
 #endif
@@ -89,6 +89,56 @@ __device__ __forceinline__ void store_moments(P *__restrict__ base, long long st
     }
 }
 
+// LDS tiles hold the moment groups of a node contiguously (node-major), so
+// every tap and group of a stencil row is reached from one address with
+// immediate offsets.  Node stride, in vectors (float4 / double2): the groups,
+// padded by one where lanes reading neighbouring nodes would otherwise share
+// LDS banks (D2Q25 FP32: 8 -> 9 float4, 144 B; D2Q16 FP64: 10 -> 11 double2,
+// 176 B); D2Q16 FP32 5 float4 (80 B) and D2Q25 FP64 15 double2 (240 B) are
+// conflict-free as they are.
+template <typename P, class L>
+constexpr int lds_stride() {
+    constexpr int G = MomVec<P, nmom<L>()>::G;
+    if constexpr (sizeof(P) == 4)
+        return L::Q == 25 ? G + 1 : G;
+    else
+        return L::Q == 16 ? G + 1 : G;
+}
+
+template <typename P, class L>
+__device__ __forceinline__ void load_node_lds(const P *lds, int idx, P *M) {
+    using MV = MomVec<P, nmom<L>()>;
+    using V = typename MV::V;
+    const V *b = reinterpret_cast<const V *>(lds) + idx * lds_stride<P, L>();
+#pragma unroll
+    for (int k = 0; k < MV::G; ++k) {
+        const V v = b[k];
+        if constexpr (MV::W == 4) {
+            M[4 * k] = v.x;
+            M[4 * k + 1] = v.y;
+            M[4 * k + 2] = v.z;
+            M[4 * k + 3] = v.w;
+        } else {
+            M[2 * k] = v.x;
+            M[2 * k + 1] = v.y;
+        }
+    }
+}
+
+template <typename P, class L>
+__device__ __forceinline__ void store_node_lds(P *lds, int idx, const P *M) {
+    using MV = MomVec<P, nmom<L>()>;
+    using V = typename MV::V;
+    V *b = reinterpret_cast<V *>(lds) + idx * lds_stride<P, L>();
+#pragma unroll
+    for (int k = 0; k < MV::G; ++k) {
+        if constexpr (MV::W == 4)
+            b[k] = V{M[4 * k], M[4 * k + 1], M[4 * k + 2], M[4 * k + 3]};
+        else
+            b[k] = V{M[2 * k], M[2 * k + 1]};
+    }
+}
+
 template <typename P>
 __device__ __forceinline__ P *pop_plane(void *base, int i, long long N) {
     return static_cast<P *>(base) + (long long)i * N;
@@ -136,6 +186,21 @@ __device__ __forceinline__ int mom_row(int y, int ny, int bc, int wall_h) {
     return wrap_index(y, ny, bc);
 }
 
+// Reference blocks.  The gather interpolates the deviations M - M_ref of the
+// taps' moments from those of a reference node and starts its sums at M_ref:
+// equal to interpolating M itself (the weights sum to 1), but the rounding of
+// the weights -- whose sum differs from 1 by ~1e-8 in FP32, the same way at
+// every node of a uniform flow -- then scales only the deviation.  (Otherwise a
+// uniform flow at rest gains or loses ~2e-8 of its mass every step, 7e-8 at
+// T = 0.04.)  The reference node of a destination node is the first node of
+// the aligned kRefBlockX x kRefBlockY block holding it: every tile shape
+// divides the block, so a tile has one reference, and every kernel and tile
+// shape interpolate the same deviations.
+constexpr int kRefBlockX = 256, kRefBlockY = 16;
+__device__ __forceinline__ long long ref_node(int x, int y, int nx) {
+    return (long long)(y / kRefBlockY * kRefBlockY) * nx + (x / kRefBlockX * kRefBlockX);
+}
+
 template <typename P, int NP, class L = D2Q16>
 struct GlobalTaps {
     const P *mom;
@@ -143,7 +208,18 @@ struct GlobalTaps {
     int nx, ny, bc_x, bc_y;
     long long moff;  // node offset of grid row 0
     int wall_h;
+    P ref[nmom_padded<P, L>()];  // moments of the reference node
 
+    // the interpolation sums start at the reference moments
+    __device__ __forceinline__ void init(P Mf[L::NM], P Mg[L::NM]) const {
+#pragma unroll
+        for (int k = 0; k < L::NM; ++k) {
+            Mf[k] = ref[k];
+            Mg[k] = ref[L::NM + k];
+        }
+    }
+
+    // adds sum_{p,q} wx[p] wy[q] (M(bx + p, by + q) - M_ref)
     __device__ __forceinline__ void gather(int bx, int by, const P wx[NP], const P wy[NP],
                                            P Mf[L::NM], P Mg[L::NM]) const {
         int col[NP];
@@ -159,8 +235,8 @@ struct GlobalTaps {
                 load_moments<P, nmom<L>()>(mom, N, row + col[p], M);
 #pragma unroll
                 for (int k = 0; k < L::NM; ++k) {
-                    Mf[k] += W * M[k];
-                    Mg[k] += W * M[L::NM + k];
+                    Mf[k] += W * (M[k] - ref[k]);
+                    Mg[k] += W * (M[L::NM + k] - ref[L::NM + k]);
                 }
             }
         }
@@ -281,6 +357,23 @@ __device__ __forceinline__ void node_monomials(P Vx, P Vy, P mono[L::NM]) {
     }
 }
 
+// Unwrapped index range [lo, hi] of the stencils of every velocity of a node at
+// coordinate x with frame velocity u and sqrt(T) = s along one axis.
+template <int NP, class L = D2Q16>
+__device__ __forceinline__ void stencil_extent(int x, double u, double s, int &lo, int &hi) {
+    // departure coordinates x - (s c + u) for c = +-c_out bound all stencils
+    const double dlo = double(x) - (s * L::c(L::Q1 - 1) + u), dhi = double(x) - (s * L::c(0) + u);
+    const double clo = fmin(fmax(dlo, double(x) - 4096.0), double(x) + 4096.0);
+    const double chi = fmin(fmax(dhi, double(x) - 4096.0), double(x) + 4096.0);
+    if (NP == 4) {
+        lo = int(floor(clo)) - 1;
+        hi = int(floor(chi)) + 2;
+    } else {
+        lo = int(floor(clo + 0.5)) - 1;
+        hi = int(floor(chi + 0.5)) + 1;
+    }
+}
+
 // Velocity gradient of the time-t frames at node n = (x, y) for the
 // internal-energy split: central differences of the four neighbours' frame
 // velocities (wrapped or clamped like the stencil; a row beyond a wall takes
@@ -332,11 +425,11 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
     const auto &tab = ltab<P, L>();
     double lg0 = l0, lg1 = l1, lg2 = l2;     // frame of the current gather
     double ln0 = lg0, ln1 = lg1, ln2 = lg2;  // frame of the gathered moments
-    double rho = 1.0;
+    double rho = 1.0, gsum = 0.0;  // FP64 sums of the last gather's f and g
     P Mf[NM], Mg[NM];  // lab moments (about u_ref) of the last gather's populations
 #pragma unroll
     for (int k = 0; k < NM; ++k) Mf[k] = Mg[k] = P(0);
-    bool done = !live, conv = false, bad = false;
+    bool done = !live, conv = false, bad = false, overrun = false;
     int used = 0;
     // internal split: velocity gradient of the time-t frames (the same for every
     // iterate), in the arithmetic's precision
@@ -355,8 +448,20 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
     for (int it = 0; it < a.pc_max_iter; ++it) {
         if (!done) {
             const double s = sqrt(lg2);
+            if (a.bc_y == 2) {
+                // walls: every stencil row must lie within the ghost rows
+                int lo, hi;
+                stencil_extent<NP, L>(y, lg1, s, lo, hi);
+                if (lo < -a.wall_h || hi > a.ny - 1 + a.wall_h) overrun = true;
+            }
             const P sP = P(s), dux = P(lg0 - a.uref_x), duy = P(lg1 - a.uref_y), is = P(1.0 / s);
-            double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+            // departure coordinates x - (s c + u) = (x - u) - s c, from the iterate
+            // frame clamped to a finite range (a non-physical iterate, which the
+            // test below flags, must still index inside the grid)
+            const double sc = fmin(fmax(s, 0.0), 1.0e6);
+            const double xu = double(x) - fmin(fmax(lg0, -1.0e8), 1.0e8);
+            const double yu = double(y) - fmin(fmax(lg1, -1.0e8), 1.0e8);
+            double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0, Eg = 0.0;
 #pragma unroll
             for (int k = 0; k < NM; ++k) Mf[k] = Mg[k] = P(0);
             // velocity i = Q1 ia + ib has x-component c(ia) and y-component c(ib):
@@ -366,16 +471,15 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                 const double cx = L::c(ia);
                 // departure point x - C_i(lam_bar) dt and its stencil, x then y
                 P wx[NP];
-                const int bx = lagrange<NP>(double(x) - (s * cx + lg0), wx);
+                const int bx = lagrange<NP>(fma(-sc, cx, xu), wx);
 #pragma unroll 1
                 for (int ib = 0; ib < L::Q1; ++ib) {
                 const int i = L::Q1 * ia + ib;
                 const double cy = L::c(ib);
                 P wy[NP];
-                const int by = lagrange<NP>(double(y) - (s * cy + lg1), wy);
+                const int by = lagrange<NP>(fma(-sc, cy, yu), wy);
                 P If[NM], Ig[NM];
-#pragma unroll
-                for (int k = 0; k < NM; ++k) If[k] = Ig[k] = P(0);
+                taps.init(If, Ig);
                 taps.gather(bx, by, wx, wy, If, Ig);
                 // frame transformation of the interpolated moments: population i
                 P B[NM];
@@ -397,6 +501,7 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                 E += double(gi);
                 if constexpr (S == 2) {
                     // non-translational split: f carries the translational energy
+                    Eg += double(gi);
                     const double Cx = s * cx + lg0, Cy = s * cy + lg1;
                     E += 0.5 * fd * (Cx * Cx + Cy * Cy);
                 }
@@ -414,6 +519,7 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                 }
             }
             rho = r;
+            gsum = S == 2 ? Eg : E;
             ln0 = jx / r;
             ln1 = jy / r;
             // total split: sum g = E = rho c_v T + |j|^2 / (2 rho); internal: sum g = rho c_v T;
@@ -469,6 +575,12 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
         const P is = P(1.0 / sT);
         const P tx = P(ln0 - a.uref_x), ty = P(ln1 - a.uref_y);
         P m[NM], af[NM], ag[NM];
+        // the zeroth moments are the exact FP64 sums of the gathered populations,
+        // rounded once: a float sum of the Q populations loses ~1e-7 of the mass
+        // in a way that repeats from step to step in a near-uniform flow (a
+        // drift); in FP64 the two are the same sums
+        Mf[0] = P(rho);
+        Mg[0] = P(gsum);
         if constexpr (L::Q == 16) {
             central_normalised(Mf, tx, ty, is, m);
             hermite_from_central(m, af);
@@ -562,6 +674,7 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
         P MM[nmom_padded<P, L>()];
 #pragma unroll
         for (int k = 0; k < nmom_padded<P, L>(); ++k) MM[k] = P(0);
+        double mass = 0.0, gzero = 0.0;  // zeroth moments summed in FP64 (see above)
 #pragma unroll 4
         for (int i = 0; i < L::Q; ++i) {
             P fv = P(0), gv = P(0);
@@ -589,7 +702,11 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                 MM[k] += fv * mono[k];
                 MM[NM + k] += gv * mono[k];
             }
+            mass += double(fv);
+            gzero += double(gv);
         }
+        MM[0] = P(mass);
+        MM[NM] = P(gzero);
         dst.ux[n] = uxst;
         dst.uy[n] = uyst;
         dst.T[n] = Tst;
@@ -600,10 +717,12 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
     const unsigned long long itc = wave_sum((unsigned long long)used);
     const unsigned long long nc = wave_sum((unsigned long long)(live && !conv && !bad));
     const unsigned long long nb = wave_sum((unsigned long long)(live && bad));
+    const unsigned long long no = wave_sum((unsigned long long)(live && overrun));
     if ((threadIdx.x & 63) == 0) {
         if (itc) atomicAdd(&cnt->pc_iterations, itc);
         if (nc) atomicAdd(&cnt->nonconverged, nc);
         if (nb) atomicAdd(&cnt->nonphysical, nb);
+        if (no) atomicAdd(&cnt->ghost_overrun, no);
     }
 }
 

@@ -22,8 +22,9 @@
 namespace pond {
 
 // Tap source of a tile: the moments of the block's source region (unwrapped
-// rectangle [X0, X1] x [Y0, Y1], W wide) staged in LDS as grouped planes of
-// stride cap; a velocity whose stencil leaves the region reads HBM.  With a
+// rectangle [X0, X1] x [Y0, Y1], W wide, row-major) staged in LDS node-major
+// (lds_stride), cap nodes at most; a velocity whose stencil leaves the region
+// reads HBM.  With a
 // single grid row (flat_y) every stencil row is row 0, so the region is one
 // row and all NP stencil rows read it (same arithmetic as the HBM gather).
 // G: taps per group of LDS loads (the arithmetic does not depend on it).
@@ -35,6 +36,9 @@ struct TileTaps {
     bool flat_y;
     GlobalTaps<P, NP, L> glob;
 
+    __device__ __forceinline__ void init(P Mf[L::NM], P Mg[L::NM]) const { glob.init(Mf, Mg); }
+
+    // the staged moments are the deviations from the tile's reference node
     __device__ __forceinline__ void gather(int bx, int by, const P wx[NP], const P wy[NP],
                                            P Mf[L::NM], P Mg[L::NM]) const {
         const bool inside =
@@ -42,15 +46,17 @@ struct TileTaps {
         if (inside) {
             const int rs = flat_y ? 0 : W;
             const int base = (flat_y ? 0 : by - Y0) * W + (bx - X0);
-            // POND_ROW_UNROLL stencil rows per trip: bounds the loads in flight per lane
-#pragma unroll POND_ROW_UNROLL
+            // every stencil row unrolled (its weight wy[q] is a register); a
+            // compiler barrier after each G taps bounds the loads in flight
+#pragma unroll
             for (int q = 0; q < NP; ++q) {
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
-                    if (G > 0 && p > 0 && p % G == 0) asm volatile("" ::: "memory");
+                    if (G > 0 && (q > 0 || p > 0) && (q * NP + p) % G == 0)
+                        asm volatile("" ::: "memory");
                     const P Wt = wx[p] * wy[q];
                     P M[nmom_padded<P, L>()];
-                    load_moments<P, nmom<L>()>(lds, cap, base + q * rs + p, M);
+                    load_node_lds<P, L>(lds, base + q * rs + p, M);
 #pragma unroll
                     for (int k = 0; k < L::NM; ++k) {
                         Mf[k] += Wt * M[k];
@@ -59,7 +65,12 @@ struct TileTaps {
                 }
             }
         } else {
-            glob.gather(bx, by, wx, wy, Mf, Mg);
+            // the HBM gather's column indices depend on bx alone; the empty asm
+            // keeps the compiler from hoisting them out of the velocity loop into
+            // the path every lane runs
+            int bxv = bx;
+            asm volatile("" : "+v"(bxv));
+            glob.gather(bxv, by, wx, wy, Mf, Mg);
         }
     }
 };
@@ -83,23 +94,6 @@ __device__ __forceinline__ int block_min(int v, int *red) {
     int r = red[0];
     for (int i = 1; i < nw; ++i) r = min(r, red[i]);
     return r;
-}
-
-// Unwrapped index range [lo, hi] of the stencils of every velocity of a node at
-// coordinate x with frame velocity u and sqrt(T) = s along one axis.
-template <int NP, class L = D2Q16>
-__device__ __forceinline__ void stencil_extent(int x, double u, double s, int &lo, int &hi) {
-    // departure coordinates x - (s c + u) for c = +-c_out bound all stencils
-    const double dlo = double(x) - (s * L::c(L::Q1 - 1) + u), dhi = double(x) - (s * L::c(0) + u);
-    const double clo = fmin(fmax(dlo, double(x) - 4096.0), double(x) + 4096.0);
-    const double chi = fmin(fmax(dhi, double(x) - 4096.0), double(x) + 4096.0);
-    if (NP == 4) {
-        lo = int(floor(clo)) - 1;
-        hi = int(floor(chi)) + 2;
-    } else {
-        lo = int(floor(clo + 0.5)) - 1;
-        hi = int(floor(chi + 0.5)) + 1;
-    }
 }
 
 // Minimum waves per SIMD asked of the register allocator for the step kernels
@@ -216,20 +210,24 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const
     const int W = X1 >= X0 ? X1 - X0 + 1 : 0;
     const int H = Y1 >= Y0 ? Y1 - Y0 + 1 : 0;
 
+    // the tile's reference moments (every node of the tile shares its block)
+    GlobalTaps<P, NP, L> glob{mom, a.mstride, a.nx, a.ny, a.bc_x, a.bc_y, a.moff, a.wall_h, {}};
+    load_moments<P, nmom<L>()>(mom, a.mstride, a.moff + ref_node(tx0, ty0, a.nx), glob.ref);
+
     for (int idx = threadIdx.x; idx < W * H; idx += nthreads) {
         const int gx = wrap_index(X0 + idx % W, a.nx, a.bc_x);
         const int gy = mom_row(Y0 + idx / W, a.ny, a.bc_y, a.wall_h);
         P M[nmom_padded<P, L>()];
         load_moments<P, nmom<L>()>(mom, a.mstride, a.moff + (long long)gy * a.nx + gx, M);
-        store_moments<P, nmom<L>()>(lds, cap, idx, M);
+#pragma unroll
+        for (int k = 0; k < nmom<L>(); ++k) M[k] -= glob.ref[k];
+        store_node_lds<P, L>(lds, idx, M);
     }
     __syncthreads();
 
     constexpr int G = sizeof(P) == 4 && Shape::kThreads == 512 ? 1
                       : (sizeof(P) == 8 ? POND_TAP_GROUP_F64 : POND_TAP_GROUP_F32);
-    const TileTaps<P, NP, L, G> taps{
-        lds, cap, X0, Y0, X1, Y1, W, flat_y,
-        GlobalTaps<P, NP, L>{mom, a.mstride, a.nx, a.ny, a.bc_x, a.bc_y, a.moff, a.wall_h}};
+    const TileTaps<P, NP, L, G> taps{lds, cap, X0, Y0, X1, Y1, W, flat_y, glob};
     node_step<P, NP, S, L>(a, taps, x, y, n, live, l0, l1, l2, src, dst, mom_out, cnt);
 }
 
@@ -245,10 +243,13 @@ __device__ __forceinline__ void node_moments(const StepArgs &a, DevState st, P *
     P M[nmom_padded<P, L>()];
 #pragma unroll
     for (int k = 0; k < nmom_padded<P, L>(); ++k) M[k] = P(0);
+    double mass = 0.0, gzero = 0.0;  // zeroth moments summed in FP64, as the step does
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const P fi = pop_plane<P>(st.f, i, a.N)[n];
         const P gi = pop_plane<P>(st.g, i, a.N)[n];
+        mass += double(fi);
+        gzero += double(gi);
         const P Vx = s * P(L::c(i / L::Q1)) + dx, Vy = s * P(L::c(i % L::Q1)) + dy;
         P mono[NM];
         node_monomials<L>(Vx, Vy, mono);
@@ -258,6 +259,8 @@ __device__ __forceinline__ void node_moments(const StepArgs &a, DevState st, P *
             M[NM + k] += gi * mono[k];
         }
     }
+    M[0] = P(mass);
+    M[NM] = P(gzero);
     store_moments<P, nmom<L>()>(mom, a.mstride, a.moff + n, M);
 }
 

@@ -109,7 +109,12 @@ def test_full_size_sampled_nodes(lattice, split, prec, bar):
     P = oracle_params_for(w, lattice=lattice, split=split)
     fo, go, lo, _, _ = oracle.step_nodes(P, to_oracle_state(f0, g0, fr0), nodes)
     for a, b in ((f1[:, nodes].T, fo), (g1[:, nodes].T, go)):
-        assert np.max(np.abs(a - b) / np.max(np.abs(b), axis=0)) <= bar
+        # FP64: each population plane against its own max norm; FP32: against the
+        # largest population of the distribution, the scale float populations are
+        # resolved on (the outermost D2Q25 populations, weights 1.3e-4 of the
+        # central one, are rebuilt from moments of order one)
+        scale = np.max(np.abs(b), axis=0) if prec == FP64 else np.max(np.abs(b))
+        assert np.max(np.abs(a - b) / scale) <= bar
     vs = velocity_scale(lo[:, 0], lo[:, 1], lo[:, 2])
     assert np.max(np.abs(fr1[:2, nodes].T - lo[:, :2])) / vs <= bar
     assert np.max(np.abs(fr1[2, nodes] - lo[:, 2]) / lo[:, 2]) <= bar

@@ -1,0 +1,47 @@
+"""The four-quadrant 2-D Riemann problem of the benchmark (the same seeded
+quadrant states) on a 256 x 256 grid against the CPU oracle's stored result
+after 200 steps (tests/golden/quadrants256_oracle.npz, written by
+tests/golden/make_quadrants256.py, which runs the oracle alone): the FP64 GPU
+path within 1e-12 per field (max norm), the FP32 path (FP64 moments and frame
+iteration) within 1e-4 in L1."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2405_11489_amd import workloads
+from parity_util import field_errors, field_l1, gpu_run
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "quadrants256_oracle.npz")
+
+
+def _golden():
+    z = np.load(GOLDEN)
+    m = {k: z[k] for k in ("rho", "ux", "uy", "T")}
+    m["p"] = m["rho"] * m["T"]
+    return int(z["steps"]), int(z["n"]), m, z
+
+
+def test_golden_matches_the_workload_recipe():
+    steps, n, _, z = _golden()
+    w = workloads.riemann_quadrants(n=n, seed=0)
+    assert np.allclose(np.array(w.meta["states"]), z["states"], rtol=0, atol=0)
+    assert float(z["tau"]) == w.tau and float(z["prandtl"]) == w.prandtl
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_quadrants_256_match_the_stored_oracle_run(prec):
+    steps, n, mo, _ = _golden()
+    w = workloads.riemann_quadrants(n=n, seed=0)
+    _, _, _, _, st, m = gpu_run(w, prec, steps)
+    assert st.nonphysical == 0
+    if prec == FP64:
+        errs = field_errors(m, mo)
+        assert max(errs.values()) <= 1e-12, errs
+    else:
+        l1 = field_l1(m, mo)
+        assert max(l1.values()) <= 1e-4, l1

@@ -185,3 +185,44 @@ def test_autotuning_server_and_zero_step_requests():
     finally:
         pond.pond_server_destroy(srv)
         pond.pond_tuning_cache_clear()
+
+
+def test_fp64_served_requests_match_the_oracle():
+    """An FP64 server (continuous batching, a budget that holds about two
+    requests at a time, 5-step chunks): every served state equals the CPU
+    oracle's on the same inputs within 1e-12 per plane (Eq.
+    propagationInterpolated, the step the oracle runs literally)."""
+    from paper_2405_11489_amd import pond
+    from parity_util import oracle_run, plane_errors
+    rng = np.random.default_rng(7)
+    reqs = []
+    for i in range(6):
+        n = int(rng.integers(8, 20))
+        steps = int(rng.integers(3, 12))
+        if i % 3 == 0:
+            w = workloads.fourier_modes(n=n, ny=int(rng.integers(6, 16)), mach=1.5,
+                                        amplitude=1e-2, seed=int(rng.integers(1 << 20)), tau=0.6)
+        elif i % 3 == 1:
+            w = workloads.sod_tube(nx=4 * n, frame_mach=0.7, nu=2e-3)
+        else:
+            w = workloads.riemann_quadrants(n=n, seed=int(rng.integers(1 << 20)))
+        reqs.append((w, steps))
+    sizes = sorted(pond.pond_state_bytes(_params(pond, w, FP64)) for w, _ in reqs)
+    srv = _server(pond, precision=FP64, hbm_budget_bytes=sizes[-1] + sizes[-2], chunk_steps=5)
+    try:
+        ids = [pond.pond_server_submit(srv, _params(pond, w, FP64), w.rho, w.ux, w.uy, w.T, steps,
+                                       pond.REQ_KEEP_STATE)
+               for w, steps in reqs]
+        pond.pond_server_wait(srv, 0)
+        st = pond.pond_server_get_stats(srv)
+        assert st.completed == len(reqs) and st.failed == 0
+        for rid, (w, steps) in zip(ids, reqs):
+            N = w.nodes
+            x = np.zeros(35 * N + 2)
+            pond.pond_server_result(srv, rid, None, x)
+            f, g, fr = _unpack_state(x, N)
+            P, s, ost = oracle_run(w, steps)
+            assert ost.nonphysical == 0
+            assert max(plane_errors(f, g, fr, s)) <= 1e-12, (w.name, w.nx, w.ny, steps)
+    finally:
+        pond.pond_server_destroy(srv)

@@ -150,3 +150,88 @@ def test_walls_in_batches_and_the_server_equal_solo_bitwise(prec):
             np.testing.assert_array_equal(a, b_)
     finally:
         pond.pond_server_destroy(srv)
+
+
+# ---------------------------------------------------------------- ghost band
+# With walls the moment planes hold 8 ghost rows beyond each wall.  The
+# library refuses (POND_ERR_UNSUPPORTED) a frame whose departure stencils
+# reach further -- at initialisation, at import, and when a step's iterate
+# frames get there (flagged on the device, reported at the next
+# synchronising call) -- instead of departing silently from the oracle, which
+# builds the mirror ghost at any depth.  For a node at rest on the bottom row
+# the cubic stencil's lowest row is floor(-c_out sqrt(T)) - 1, so T above
+# (7 / c_out)^2 = 8.995 on D2Q16 reaches row -9.
+
+C_OUT = float(np.sqrt(3.0 + np.sqrt(6.0)))
+
+
+def hot_channel(T0, Tw, nx=4, ny=16):
+    """Fluid at rest at T0 between walls at rest held at Tw (tau = 0.8, Pr = 1)."""
+    shape = (ny, nx)
+    return workloads.Workload("hot_channel", nx, ny, workloads.PERIODIC, workloads.WALL, 1.4,
+                              1.0, 0.8, 20, np.ones(shape), np.zeros(shape), np.zeros(shape),
+                              np.full(shape, T0), wall_ux=(0.0, 0.0), wall_T=(Tw, Tw))
+
+
+def oracle_overrun_rows(P, s, ny):
+    """Nodes of an oracle state whose cubic departure stencil leaves the 8 ghost rows."""
+    m = oracle.moments(P, s)
+    y = np.arange(ny)[:, None]
+    sq = np.sqrt(m["T"])
+    lo = np.floor(y - (sq * C_OUT + m["uy"])) - 1
+    hi = np.floor(y - (-sq * C_OUT + m["uy"])) + 2
+    return int(np.count_nonzero((lo < -8) | (hi > ny - 1 + 8)))
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_walls_refuse_a_frame_beyond_the_ghost_rows(prec):
+    from paper_2405_11489_amd import pond
+    w = hot_channel(9.2, 9.2)  # c_out sqrt(9.2) = 7.08 > 7
+    with pytest.raises(pond.PondError) as e:
+        gpu_solver(w, prec)
+    assert e.value.status == pond.ERR_UNSUPPORTED
+    # just inside the band: accepted
+    ok = hot_channel(8.9, 8.9)
+    with gpu_solver(ok, prec) as s:
+        s.step(1)
+        s.synchronize()
+        f, g, fr, ur = s.export_state()
+    # import of a state whose frame is too hot: refused as well
+    fr_hot = fr.copy()
+    fr_hot[2, :] = 9.2
+    with gpu_solver(ok, prec) as s:
+        with pytest.raises(pond.PondError) as e:
+            s.import_state(f, g, fr_hot, ur)
+        assert e.value.status == pond.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_walls_flag_a_flow_heated_beyond_the_ghost_rows(prec):
+    """Walls at T = 10 heat fluid started at 8.5: the first row passes 8.995
+    within the first step (the oracle's frames confirm it), so the step's
+    iterates reach beyond the ghost band; the GPU flags it at the next
+    synchronising call and refuses further steps."""
+    from paper_2405_11489_amd import pond
+    w = hot_channel(8.5, 10.0)
+    P, s, _ = oracle_run(w, 1)
+    assert oracle_overrun_rows(P, s, w.ny) > 0
+    with gpu_solver(w, prec) as sol:
+        sol.step(3)
+        with pytest.raises(pond.PondError) as e:
+            sol.synchronize()
+        assert e.value.status == pond.ERR_UNSUPPORTED
+        with pytest.raises(pond.PondError) as e:
+            sol.step(1)
+        assert e.value.status == pond.ERR_STATE
+
+
+def test_walls_inside_the_ghost_rows_match_oracle():
+    """The control: walls at 8.8 heat fluid at 8.4; every frame stays inside
+    the band (oracle: c_out sqrt(T) at most 6.93) and the GPU matches the
+    oracle to 1e-12."""
+    w = hot_channel(8.4, 8.8)
+    f, g, fr, _, st, m = gpu_run(w, FP64, 20)
+    P, s, ost = oracle_run(w, 20)
+    assert oracle_overrun_rows(P, s, w.ny) == 0
+    assert max(plane_errors(f, g, fr, s)) <= 1e-12
+    assert st.nonphysical == 0
