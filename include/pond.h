@@ -292,6 +292,49 @@ POND_API pond_status pond_profile_read(pond_ctx *c, pond_profile_t *out);
  * (POND_ERR_STATE) while the context is a member of a batch. */
 POND_API pond_status pond_destroy(pond_ctx *c);
 
+/* ------------------------------------------------- no-allocation step ----
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops that must not call hipMalloc.  The steps of
+ * pond_step, on two state buffers the caller owns, with no context: the call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ *
+ * The library's working memory for the steps (the moment planes of the two
+ * states and the counters) is a fixed 64 MiB device workspace, one per GPU,
+ * held until the process ends.  It holds grids of up to about 419 000 nodes
+ * in FP32 on D2Q16 (e.g. 640 x 640), 209 000 in FP64 (456 x 456), 262 000 in
+ * FP32 on D2Q25 (512 x 512); larger grids are refused with
+ * POND_ERR_OUT_OF_MEMORY before any device work.  Every call on a GPU shares
+ * that GPU's workspace and keeps nothing in it between calls (each call
+ * clears its counters and recomputes the moments of its input): calls that
+ * overlap on one GPU (other streams, other threads) race and must not be made.
+ *
+ * p:       the parameters of pond_create (validated the same way).
+ * u_ref:   host pointer to the 2-vector reference velocity the FP32 moments
+ *          are taken about (pond_export_state returns a context's), or NULL
+ *          for (0, 0).  Results equal pond_step's bit for bit when it equals
+ *          the context's.
+ * f_a, g_a, frame_a: buffer A, the input state, device memory of the current
+ *          GPU: Q planes of f, Q planes of g (float in FP32, double in FP64,
+ *          plane i = velocity i, nx*ny values each, the layout of
+ *          pond_export_state), and 3 planes u_x, u_y, T (double).
+ * f_b, g_b, frame_b: buffer B, the same layout, device memory.
+ * nsteps:  >= 0 steps; A and B are ping-pong buffers: step k reads A and
+ *          writes B when k is even, reads B and writes A when k is odd, so the
+ *          result is in B when nsteps is odd and in A (overwritten) when it is
+ *          even (nsteps = 0 leaves both untouched).
+ * hip_stream: the stream to enqueue on (NULL: the null stream).  Asynchronous
+ *          unless stats is given.
+ * stats:   NULL, or host memory for the counters of these steps; then the call
+ *          synchronises the stream (so it cannot be captured) and returns
+ *          POND_ERR_NONPHYSICAL or POND_ERR_UNSUPPORTED (a wall's ghost rows
+ *          overrun) as pond_stats would.
+ * Errors: POND_ERR_INVALID_ARG (parameters, NULL or host buffers, nsteps < 0),
+ * POND_ERR_UNSUPPORTED (options pond_create refuses), POND_ERR_OUT_OF_MEMORY
+ * (grid larger than the workspace), POND_ERR_DEVICE (launch failure). */
+POND_API pond_status pond_step_noalloc(const pond_params *p, const double *u_ref, void *f_a,
+                                       void *g_a, double *frame_a, void *f_b, void *g_b,
+                                       double *frame_b, int64_t nsteps, void *hip_stream,
+                                       pond_stats_t *stats);
 
 /* ------------------------------------------------------------- batches ----
  * A batch advances several contexts together, each by the same step as

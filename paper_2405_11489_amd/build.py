@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpond.so")
 SOURCES = ["pond_kernels.hip", "pond_kernels25.hip", "pond_batch.hip", "pond_server.hip",
-           "pond_api.hip"]
+           "pond_api.hip", "pond_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -37,6 +37,7 @@ EXPORTED = [
     "pond_autotune", "pond_tuning_cache_clear", "pond_server_config_default",
     "pond_server_create", "pond_server_submit", "pond_server_poll", "pond_server_wait",
     "pond_server_result", "pond_server_release", "pond_server_get_stats", "pond_server_destroy",
+    "pond_step_noalloc",
 ]
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
 REQ_KEEP_MOMENTS, REQ_KEEP_STATE = 1, 2
@@ -136,6 +137,8 @@ _L.pond_synchronize.argtypes = [_vp]
 _L.pond_export_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _L.pond_import_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _L.pond_destroy.argtypes = [_vp]
+_L.pond_step_noalloc.argtypes = [ctypes.POINTER(pond_params), _vp, _vp, _vp, _vp, _vp, _vp,
+                                 _vp, ctypes.c_int64, _vp, ctypes.POINTER(pond_stats_t)]
 _L.pond_profile_enable.argtypes = [_vp, ctypes.c_int]
 _L.pond_get_tuning.argtypes = [_vp, ctypes.POINTER(pond_tuning)]
 _L.pond_set_tuning.argtypes = [_vp, ctypes.POINTER(pond_tuning)]
@@ -251,6 +254,32 @@ def pond_import_state(ctx, f, g, frame, u_ref=None):
 
 def pond_destroy(ctx):
     _check(_L.pond_destroy(ctx))
+
+
+def _dptr(a):
+    """Data pointer of a contiguous torch tensor (any dtype), or an int address."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise TypeError("tensors must be contiguous")
+        return a.data_ptr()
+    raise TypeError(f"unsupported buffer type {type(a)}")
+
+
+def pond_step_noalloc(p: pond_params, u_ref, f_a, g_a, frame_a, f_b, g_b, frame_b, nsteps: int,
+                      stream=None, want_stats: bool = False):
+    """pond_step_noalloc: buffers are device tensors (f, g in the precision's
+    dtype, frames float64); u_ref a host sequence of 2 floats or None.  Returns
+    the pond_stats_t of the steps when want_stats (the call then synchronises)."""
+    ur = None if u_ref is None else (ctypes.c_double * 2)(float(u_ref[0]), float(u_ref[1]))
+    st = pond_stats_t() if want_stats else None
+    _check(_L.pond_step_noalloc(ctypes.byref(p), ur, _dptr(f_a), _dptr(g_a), _dptr(frame_a),
+                                _dptr(f_b), _dptr(g_b), _dptr(frame_b), int(nsteps), stream,
+                                ctypes.byref(st) if st is not None else None))
+    return st
 
 
 def pond_get_tuning(ctx) -> pond_tuning:

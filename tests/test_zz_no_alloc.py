@@ -1,0 +1,120 @@
+"""GPU test of pond_step_noalloc, the entry point for callers that cannot
+allocate device memory: through the C ABI, on caller-owned state buffers and
+the library's fixed workspace, it must give the results of pond_step on a
+context bit for bit (the same kernels), on two calls in a row, the second with
+a smaller grid."""
+import numpy as np
+import pytest
+
+from paper_2405_11489_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+
+
+def _modes(n, ny, seed, mach=1.0):
+    return workloads.fourier_modes(n=n, ny=ny, mach=mach, angle_deg=30.0, amplitude=1e-2,
+                                   seed=seed, tau=0.7, prandtl=0.71)
+
+
+def _noalloc_vs_context(w, prec, nsteps, **kw):
+    """Steps a context twice (an off-equilibrium start), exports its state, runs
+    nsteps through pond_step_noalloc from that state and nsteps more on the
+    context, and returns both results as float64 tensors (f, g, frame)."""
+    import torch
+    from paper_2405_11489_amd import pond
+    dev = torch.device("cuda")
+    q = kw.get("lattice", 16)
+    N = w.nodes
+    with pond.Solver.from_workload(w, precision=prec, **kw) as sol:
+        sol.step(2)
+        f = torch.empty((q, N), dtype=torch.float64, device=dev)
+        g = torch.empty_like(f)
+        fr = torch.empty((3, N), dtype=torch.float64, device=dev)
+        ur = np.zeros(2)
+        pond.pond_export_state(sol.ctx, f, g, fr, ur)
+        dt = torch.float64 if prec == FP64 else torch.float32
+        fa, ga, fra = f.to(dt).contiguous(), g.to(dt).contiguous(), fr.clone()
+        fb, gb, frb = torch.empty_like(fa), torch.empty_like(ga), torch.empty_like(fra)
+        torch.cuda.synchronize()
+        st = pond.pond_step_noalloc(sol.params, ur, fa, ga, fra, fb, gb, frb, nsteps,
+                                    want_stats=True)
+        sol.step(nsteps)
+        f2 = torch.empty_like(f)
+        g2 = torch.empty_like(g)
+        fr2 = torch.empty_like(fr)
+        pond.pond_export_state(sol.ctx, f2, g2, fr2, None)
+        ctx_stats = sol.stats()
+    out = (fb, gb, frb) if nsteps % 2 else (fa, ga, fra)
+    torch.cuda.synchronize()
+    return [t.double() for t in out], (f2, g2, fr2), st, ctx_stats
+
+
+CASES = [
+    # (name, workload factory, precision, steps, solver options)
+    ("fp32_48x40", lambda: _modes(48, 40, 1), FP32, 3, {}),
+    ("fp32_20x12", lambda: _modes(20, 12, 2, mach=2.0), FP32, 2, {}),
+    ("fp64_33x17", lambda: _modes(33, 17, 3), FP64, 3, {}),
+    ("fp64_8x8", lambda: _modes(8, 8, 4), FP64, 1, {}),
+    ("fp32_internal_40x24", lambda: _modes(40, 24, 5), FP32, 3, {"split": 1}),
+    ("fp64_couette_16x3", lambda: workloads.thermal_couette(ny=16, nx=3, Ec=72.0), FP64, 3, {}),
+    ("fp32_d2q25_24x16", lambda: _modes(24, 16, 6), FP32, 2, {"lattice": 25}),
+]
+
+
+@pytest.mark.parametrize("first,second", [(0, 1), (2, 3), (4, 1), (2, 5), (6, 1)])
+def test_noalloc_equals_pond_step_on_two_calls(first, second):
+    """Two calls in a row, the second on a smaller grid (the workspace keeps the
+    first call's contents): both bitwise equal to pond_step."""
+    import torch
+    for idx in (first, second):
+        name, make, prec, nsteps, kw = CASES[idx]
+        w = make()
+        got, want, st, cst = _noalloc_vs_context(w, prec, nsteps, **kw)
+        for a, b, what in zip(got, want, ("f", "g", "frame")):
+            assert torch.equal(a, b), (name, what, float((a - b).abs().max()))
+        assert st.steps == nsteps and st.node_updates == nsteps * w.nodes
+        assert st.nonphysical == 0 and st.pc_iterations >= nsteps * w.nodes
+    # the sizes really shrink from the first to the second call
+    assert CASES[second][1]().nodes < CASES[first][1]().nodes
+
+
+def test_noalloc_zero_steps_leaves_buffers_untouched():
+    import torch
+    from paper_2405_11489_amd import pond
+    w = _modes(16, 16, 7)
+    p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma,
+                                 prandtl=w.prandtl, precision=FP32)
+    dev = torch.device("cuda")
+    fa = torch.full((16, w.nodes), 0.25, dtype=torch.float32, device=dev)
+    ga = fa.clone()
+    fra = torch.ones((3, w.nodes), dtype=torch.float64, device=dev)
+    fb, gb, frb = fa.clone(), ga.clone(), fra.clone()
+    st = pond.pond_step_noalloc(p, None, fa, ga, fra, fb, gb, frb, 0, want_stats=True)
+    assert st.steps == 0 and st.pc_iterations == 0
+    assert torch.equal(fa, fb) and torch.equal(fra, frb)
+
+
+def test_noalloc_refuses_grids_beyond_the_workspace_and_bad_buffers():
+    import torch
+    from paper_2405_11489_amd import pond
+    dev = torch.device("cuda")
+    tiny = [torch.zeros(4, dtype=torch.float32, device=dev) for _ in range(4)]
+    tiny_fr = [torch.zeros(4, dtype=torch.float64, device=dev) for _ in range(2)]
+    big = pond.pond_params_default(nx=1024, ny=1024, precision=FP32)
+    with pytest.raises(pond.PondError) as e:
+        pond.pond_step_noalloc(big, None, tiny[0], tiny[1], tiny_fr[0], tiny[2], tiny[3],
+                               tiny_fr[1], 1)
+    assert e.value.status == pond.ERR_OUT_OF_MEMORY
+    assert "workspace" in pond.pond_last_error()
+    small = pond.pond_params_default(nx=4, ny=1, precision=FP32)
+    host = np.zeros(4)
+    with pytest.raises(pond.PondError) as e:
+        pond.pond_step_noalloc(small, None, tiny[0], tiny[1], host.ctypes.data, tiny[2],
+                               tiny[3], tiny_fr[1], 1)
+    assert e.value.status == pond.ERR_INVALID_ARG
+    with pytest.raises(pond.PondError) as e:
+        pond.pond_step_noalloc(small, None, tiny[0], tiny[1], tiny_fr[0], tiny[2], tiny[3],
+                               tiny_fr[1], -1)
+    assert e.value.status == pond.ERR_INVALID_ARG
