@@ -254,6 +254,13 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 // moments about d = (dx, dy) (frame velocity - u_ref) with scale is = 1/sqrt(T),
 // composed with that shift and scaling (the transpose of central_normalised).
 // One coefficient vector serves both f and g.
+//
+// Each coefficient is the table weight plus the terms of the shift: the shift
+// terms are summed first and the weight added last, in one rounding.  Added
+// one by one onto the weight, each term would round at the weight's ulp, and
+// over the sixteen velocities the coefficients of m00 (the mass) would sum to
+// 1 + 7e-9 on average for frames within 1e-3 of u_ref -- a mass drift of that
+// size every step in FP32.  Summed first, the single rounding is unbiased.
 template <typename P>
 __device__ __forceinline__ void pop_coeffs(const P r[kNM], P dx, P dy, P is, P B[kNM]) {
     const P is2 = is * is, is3 = is2 * is;
@@ -265,13 +272,13 @@ __device__ __forceinline__ void pop_coeffs(const P r[kNM], P dx, P dy, P is, P B
     B[8] = r12;
     B[7] = r21;
     B[6] = r30;
-    B[5] = r02 + ex * r12 + P(3) * ey * r03;
-    B[4] = r11 + P(2) * ex * r21 + P(2) * ey * r12;
-    B[3] = r20 + P(3) * ex * r30 + ey * r21;
-    B[2] = r01 + ex * r11 + P(2) * ey * r02 + exx * r21 + P(2) * exy * r12 + P(3) * eyy * r03;
-    B[1] = r10 + P(2) * ex * r20 + ey * r11 + P(3) * exx * r30 + P(2) * exy * r21 + eyy * r12;
-    B[0] = r00 + ex * r10 + ey * r01 + exx * r20 + exy * r11 + eyy * r02 + exx * ex * r30 +
-           exx * ey * r21 + ex * eyy * r12 + eyy * ey * r03;
+    B[5] = r02 + (ex * r12 + P(3) * ey * r03);
+    B[4] = r11 + (P(2) * ex * r21 + P(2) * ey * r12);
+    B[3] = r20 + (P(3) * ex * r30 + ey * r21);
+    B[2] = r01 + (ex * r11 + P(2) * ey * r02 + exx * r21 + P(2) * exy * r12 + P(3) * eyy * r03);
+    B[1] = r10 + (P(2) * ex * r20 + ey * r11 + P(3) * exx * r30 + P(2) * exy * r21 + eyy * r12);
+    B[0] = r00 + (ex * r10 + ey * r01 + exx * r20 + exy * r11 + eyy * r02 + exx * ex * r30 +
+                  exx * ey * r21 + ex * eyy * r12 + eyy * ey * r03);
 }
 
 // pop_coeffs for any order: B_rt = sum_{p >= r, q >= t} r_pq is^(p+q) C(p,r) C(q,t)
@@ -290,23 +297,25 @@ __device__ __forceinline__ void pop_coeffs_n(const P r[L::NM], P dx, P dy, P is,
     P R[L::NM], T[L::NM];
 #pragma unroll
     for (int k = 0; k < L::NM; ++k) R[k] = r[k] * sc[mom_px(k) + mom_py(k)];
+    // each stage sums its shift terms first and adds the leading term last (see
+    // pop_coeffs)
 #pragma unroll
     for (int k = 0; k < L::NM; ++k) {
         const int p = mom_px(k), t = mom_py(k);
-        P acc = R[k];
+        P acc = P(0);
 #pragma unroll
         for (int q = t + 1; q <= N - p; ++q)
             acc += P(binom_c(q, t)) * ey[q - t] * R[mom_index(p, q)];
-        T[k] = acc;
+        T[k] = R[k] + acc;
     }
 #pragma unroll
     for (int k = 0; k < L::NM; ++k) {
         const int rr = mom_px(k), t = mom_py(k);
-        P acc = T[k];
+        P acc = P(0);
 #pragma unroll
         for (int p = rr + 1; p <= N - t; ++p)
             acc += P(binom_c(p, rr)) * ex[p - rr] * T[mom_index(p, t)];
-        B[k] = acc;
+        B[k] = T[k] + acc;
     }
 }
 
