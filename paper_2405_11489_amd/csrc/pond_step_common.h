@@ -105,11 +105,38 @@ constexpr int lds_stride() {
         return L::Q == 16 ? G + 1 : G;
 }
 
+// Bytes of one node in the LDS array.
+template <typename P, class L>
+constexpr unsigned lds_node_bytes() {
+    return unsigned(lds_stride<P, L>() * sizeof(typename MomVec<P, nmom<L>()>::V));
+}
+
 template <typename P, class L>
 __device__ __forceinline__ void load_node_lds(const P *lds, int idx, P *M) {
     using MV = MomVec<P, nmom<L>()>;
     using V = typename MV::V;
     const V *b = reinterpret_cast<const V *>(lds) + idx * lds_stride<P, L>();
+#pragma unroll
+    for (int k = 0; k < MV::G; ++k) {
+        const V v = b[k];
+        if constexpr (MV::W == 4) {
+            M[4 * k] = v.x;
+            M[4 * k + 1] = v.y;
+            M[4 * k + 2] = v.z;
+            M[4 * k + 3] = v.w;
+        } else {
+            M[2 * k] = v.x;
+            M[2 * k + 1] = v.y;
+        }
+    }
+}
+
+// The same from the node's byte offset in the LDS array.
+template <typename P, class L>
+__device__ __forceinline__ void load_node_lds_at(const P *lds, unsigned off, P *M) {
+    using MV = MomVec<P, nmom<L>()>;
+    using V = typename MV::V;
+    const V *b = reinterpret_cast<const V *>(reinterpret_cast<const char *>(lds) + off);
 #pragma unroll
     for (int k = 0; k < MV::G; ++k) {
         const V v = b[k];
@@ -247,6 +274,11 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Lanes of the wave for which c holds (a ballot and a scalar bit count).
+__device__ __forceinline__ unsigned long long wave_count(bool c) {
+    return (unsigned long long)__popcll(__ballot(c));
 }
 
 // Coefficients B with pop_i = sum_j B_j M_j for raw moments M (about u_ref):
@@ -439,7 +471,7 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
 #pragma unroll
     for (int k = 0; k < NM; ++k) Mf[k] = Mg[k] = P(0);
     bool done = !live, conv = false, bad = false, overrun = false;
-    int used = 0;
+    unsigned long long itc = 0;  // gathers of the wave's lanes
     // internal split: velocity gradient of the time-t frames (the same for every
     // iterate), in the arithmetic's precision
     P gxx = P(0), gxy = P(0), gyx = P(0), gyy = P(0);
@@ -455,6 +487,7 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
     }
 
     for (int it = 0; it < a.pc_max_iter; ++it) {
+        itc += wave_count(!done);
         if (!done) {
             const double s = sqrt(lg2);
             if (a.bc_y == 2) {
@@ -551,7 +584,6 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                       (r * (a.cv + 0.25 * a.omega * (double(gxx) + double(gyy))));
             } else
                 ln2 = (E - (jx * jx + jy * jy) / (2.0 * r)) / (r * a.cv);
-            used = it + 1;
             if (!(r > 0.0) || !(ln2 > 0.0) || !isfinite(ln0) || !isfinite(ln1) || !isfinite(ln2) ||
                 !isfinite(E)) {
                 bad = true;
@@ -723,10 +755,9 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
     }
 
     // counters: one atomic per wave
-    const unsigned long long itc = wave_sum((unsigned long long)used);
-    const unsigned long long nc = wave_sum((unsigned long long)(live && !conv && !bad));
-    const unsigned long long nb = wave_sum((unsigned long long)(live && bad));
-    const unsigned long long no = wave_sum((unsigned long long)(live && overrun));
+    const unsigned long long nc = wave_count(live && !conv && !bad);
+    const unsigned long long nb = wave_count(live && bad);
+    const unsigned long long no = wave_count(live && overrun);
     if ((threadIdx.x & 63) == 0) {
         if (itc) atomicAdd(&cnt->pc_iterations, itc);
         if (nc) atomicAdd(&cnt->nonconverged, nc);

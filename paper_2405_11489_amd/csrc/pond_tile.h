@@ -44,8 +44,12 @@ struct TileTaps {
         const bool inside =
             bx >= X0 && bx + NP - 1 <= X1 && (flat_y || (by >= Y0 && by + NP - 1 <= Y1));
         if (inside) {
-            const int rs = flat_y ? 0 : W;
-            const int base = (flat_y ? 0 : by - Y0) * W + (bx - X0);
+            // byte offsets: the region is under 2^24 bytes, so the products are
+            // 24-bit multiplies (full rate, where 32-bit ones take four cycles)
+            constexpr unsigned NB = lds_node_bytes<P, L>();
+            const unsigned rowb = flat_y ? 0u : unsigned(W) * NB;
+            unsigned row = __umul24(unsigned(flat_y ? 0 : by - Y0), rowb) +
+                           __umul24(unsigned(bx - X0), NB);
             // every stencil row unrolled (its weight wy[q] is a register); a
             // compiler barrier after each G taps bounds the loads in flight
 #pragma unroll
@@ -56,13 +60,14 @@ struct TileTaps {
                         asm volatile("" ::: "memory");
                     const P Wt = wx[p] * wy[q];
                     P M[nmom_padded<P, L>()];
-                    load_node_lds<P, L>(lds, base + q * rs + p, M);
+                    load_node_lds_at<P, L>(lds, row + unsigned(p) * NB, M);
 #pragma unroll
                     for (int k = 0; k < L::NM; ++k) {
                         Mf[k] += Wt * M[k];
                         Mg[k] += Wt * M[L::NM + k];
                     }
                 }
+                row += rowb;
             }
         } else {
             // the HBM gather's column indices depend on bx alone; the empty asm
