@@ -15,6 +15,7 @@ from __future__ import annotations
 import ctypes
 import os
 from dataclasses import dataclass
+from typing import Optional
 
 import numpy as np
 
@@ -109,10 +110,10 @@ def lib():
         L.oracle_internal_source.argtypes = [dp, dp, dp, dp, dp]
         L.oracle_lagrange.argtypes = [ctypes.c_int, ctypes.c_double, ip, dp]
         L.oracle_lagrange.restype = ctypes.c_int
-        L.oracle_step.argtypes = [ctypes.POINTER(Params), dp, dp, dp, dp, dp, dp, ip, ip]
+        L.oracle_step.argtypes = [ctypes.POINTER(Params), dp, dp, dp, dp, dp, dp, dp, ip, ip]
         L.oracle_step.restype = ctypes.c_int
         lp = ctypes.POINTER(ctypes.c_long)
-        L.oracle_step_nodes.argtypes = [ctypes.POINTER(Params), dp, dp, dp, ctypes.c_long, lp,
+        L.oracle_step_nodes.argtypes = [ctypes.POINTER(Params), dp, dp, dp, dp, ctypes.c_long, lp,
                                         dp, dp, dp, ip, ip]
         L.oracle_step_nodes.restype = ctypes.c_int
         L.oracle_init_split.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp, dp, dp,
@@ -120,7 +121,7 @@ def lib():
         L.oracle_init_split.restype = ctypes.c_int
         L.oracle_moments_split.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp, dp,
                                            ctypes.c_double, dp, dp, dp, dp, dp]
-        if L.oracle_abi_version() != 4:
+        if L.oracle_abi_version() != 5:
             raise RuntimeError("oracle library ABI mismatch; rebuild oracle/")
         _lib = L
     return _lib
@@ -232,13 +233,18 @@ def lagrange(npts, y):
 
 @dataclass
 class State:
-    """Oracle state: f, g of shape (N, Q), lam of shape (N, 3)."""
+    """Oracle state: f, g of shape (N, Q), lam of shape (N, 3); lam_prev, the
+    frames of the previous time level (the internal-energy split's source
+    extrapolates grad u along trajectories from them); None stands for lam
+    itself (a state that has not been stepped yet)."""
     f: np.ndarray
     g: np.ndarray
     lam: np.ndarray
+    lam_prev: Optional[np.ndarray] = None
 
     def copy(self):
-        return State(self.f.copy(), self.g.copy(), self.lam.copy())
+        return State(self.f.copy(), self.g.copy(), self.lam.copy(),
+                     None if self.lam_prev is None else self.lam_prev.copy())
 
 
 def init(P: Params, rho, ux, uy, T) -> State:
@@ -273,14 +279,28 @@ def step(P: Params, s: State, nsteps: int = 1):
     tot = nonc = nbad = 0
     for _ in range(nsteps):
         bad = lib().oracle_step(ctypes.byref(P), _d(cur.f), _d(cur.g), _d(cur.lam),
-                                _d(nxt.f), _d(nxt.g), _d(nxt.lam), _i(iters), _i(status))
+                                _prev(cur), _d(nxt.f), _d(nxt.g), _d(nxt.lam), _i(iters),
+                                _i(status))
         tot += int(iters.sum())
         nonc += int(((status & NONCONVERGED) != 0).sum())
         nbad += bad
+        # the time-t frames become the new state's previous level (a fresh
+        # array: nxt's buffers are reused for the step after)
+        nxt.lam_prev = cur.lam.copy()
         cur, nxt = nxt, cur
         if bad:
             break
     return cur, StepStats(iters.copy(), status.copy(), tot, nonc, nbad)
+
+
+def _prev(s: State):
+    """The previous frames as a C pointer (NULL when the state has none)."""
+    if s.lam_prev is None:
+        return ctypes.cast(None, ctypes.POINTER(ctypes.c_double))
+    s.lam_prev = np.ascontiguousarray(s.lam_prev, dtype=np.float64)
+    if s.lam_prev.shape != s.lam.shape:
+        raise ValueError("lam_prev must have the shape of lam")
+    return _d(s.lam_prev)
 
 
 def step_nodes(P: Params, s: State, nodes):
@@ -292,7 +312,7 @@ def step_nodes(P: Params, s: State, nodes):
     fo, go, lo = np.zeros((k, q)), np.zeros((k, q)), np.zeros((k, 3))
     iters = np.zeros(k, dtype=np.int32)
     status = np.zeros(k, dtype=np.int32)
-    lib().oracle_step_nodes(ctypes.byref(P), _d(s.f), _d(s.g), _d(s.lam), k,
+    lib().oracle_step_nodes(ctypes.byref(P), _d(s.f), _d(s.g), _d(s.lam), _prev(s), k,
                             nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
                             _d(fo), _d(go), _d(lo), _i(iters), _i(status))
     return fo, go, lo, iters, status

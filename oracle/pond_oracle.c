@@ -51,13 +51,20 @@
  *     sum G = -(omega/2) rho T div u - (1 - omega/2) P~ : grad u and the frame
  *     temperature solves rho c_v T = sum g + (sum G)/2 in closed form (see
  *     conserved()); u the new frame velocity, d_t u the difference between
- *     the new and the time-t frame velocity of the node, grad u central
- *     differences of the time-t frame velocities of the four neighbours
- *     (wrapped or clamped like the stencil; a neighbour row beyond a wall
- *     takes the ghost frame velocity of the wall closure, 2 U_wall - u of the
- *     mirror node along x, -u along y).  grad u at time t lags the step's
- *     middle by half a step, which leaves acoustic waves under-damped by
- *     (gamma - 1) T k^2 / 2 (recorded);
+ *     the new and the time-t frame velocity of the node; grad u is taken at
+ *     the end of the step, where the collision and the source act, by linear
+ *     extrapolation along the node's trajectory: 2 G_t(x - u) - G_{t-1}(x - 2u)
+ *     with u the node's time-t frame velocity and G_t the velocity gradient
+ *     of the time-t frames at a point, the bilinear interpolation of the
+ *     nodal central differences (four neighbours, wrapped or clamped like the
+ *     stencil; a neighbour row beyond a wall takes the ghost frame velocity
+ *     of the wall closure, 2 U_wall - u of the mirror node along x, -u along
+ *     y; a point beyond the wall rows is taken on the last row).  Without
+ *     the frames of t - 1 (the first step after initialisation) the time-t
+ *     frames stand in for them.  Advected with the flow,
+ *     the extrapolation is exact; at rest it is 2 grad u(t) - grad u(t - 1).
+ *     The time-t gradient alone lags the collision by a step and left
+ *     acoustic waves under-damped by (gamma - 1) T k^2 / 2;
  *   - non-translational split: the paper's single-relaxation BGK only (Pr = 1;
  *     its quasi-equilibrium form is not given and not built here);
  *   - walls (the thermal Couette flow of Sec. "Measuring viscous heating"; the
@@ -77,7 +84,7 @@
 #include <omp.h>
 #endif
 
-#define ORACLE_ABI 4
+#define ORACLE_ABI 5
 #define Q1 4      /* D1Q4 */
 #define Q 16      /* D2Q16 */
 #define QMAX 25   /* D2Q25 */
@@ -614,6 +621,69 @@ static void row_velocity(const oracle_params *P, const double *lam, int x, int j
     u[1] = l[1];
 }
 
+/* grad u of the frames lam at node (x, y): central differences of the four
+ * neighbours' frame velocities, grad[alpha][beta] = d_alpha u_beta. */
+static void node_gradient(const oracle_params *P, const double *lam, int x, int y,
+                          double grad[2][2])
+{
+    long xm = (long)y * P->nx + node_index(x - 1, P->nx, P->bc_x);
+    long xp = (long)y * P->nx + node_index(x + 1, P->nx, P->bc_x);
+    double uym[2], uyp[2];
+    row_velocity(P, lam, x, y - 1, uym);
+    row_velocity(P, lam, x, y + 1, uyp);
+    for (int b = 0; b < 2; b++) {
+        grad[0][b] = 0.5 * (lam[3 * xp + b] - lam[3 * xm + b]);
+        grad[1][b] = 0.5 * (uyp[b] - uym[b]);
+    }
+}
+
+/* grad u of the frames lam at the point (px, py): bilinear interpolation of
+ * node_gradient over the four nodes around it (columns and rows wrapped or
+ * clamped like the stencil; with walls a row beyond them is the last row). */
+static void point_gradient(const oracle_params *P, const double *lam, double px, double py,
+                           double grad[2][2])
+{
+    double fx = floor(px), fy = floor(py);
+    double ax = px - fx, ay = py - fy;
+    int x0 = (int)fx, y0 = (int)fy;
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            grad[a][b] = 0.0;
+    for (int j = 0; j < 2; j++) {
+        int yj = y0 + j;
+        if (P->bc_y == 2)
+            yj = yj < 0 ? 0 : (yj > P->ny - 1 ? P->ny - 1 : yj);
+        else
+            yj = node_index(yj, P->ny, P->bc_y);
+        for (int i = 0; i < 2; i++) {
+            int xi = node_index(x0 + i, P->nx, P->bc_x);
+            double w = (i ? ax : 1.0 - ax) * (j ? ay : 1.0 - ay);
+            double gn[2][2];
+            node_gradient(P, lam, xi, yj, gn);
+            for (int a = 0; a < 2; a++)
+                for (int b = 0; b < 2; b++)
+                    grad[a][b] += w * gn[a][b];
+        }
+    }
+}
+
+/* The internal-energy split's grad u for destination node (x, y): the end of
+ * the step along the node's trajectory, 2 G_t(x - u) - G_{t-1}(x - 2u), u the
+ * node's time-t frame velocity; without lam_prev, lam stands in for it. */
+static void source_gradient(const oracle_params *P, const double *lam, const double *lam_prev,
+                            int x, int y, double grad[2][2])
+{
+    if (!lam_prev)
+        lam_prev = lam;
+    const double *l = lam + 3 * ((long)y * P->nx + x);
+    double ga[2][2], gb[2][2];
+    point_gradient(P, lam, x - l[0], y - l[1], ga);
+    point_gradient(P, lam_prev, x - 2.0 * l[0], y - 2.0 * l[1], gb);
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            grad[a][b] = 2.0 * ga[a][b] - gb[a][b];
+}
+
 static void gather(const oracle_params *P, const double *f, const double *g, const double *lam,
                    int x, int y, const double *lam_bar, double *ft, double *gt)
 {
@@ -717,7 +787,8 @@ static void conserved(int q1, int split, const double *ft, const double *gt, con
  * outputs are then NaN), else 0.
  */
 static int node_step(const oracle_params *P, const double *f, const double *g, const double *lam,
-                     long n, double *fo, double *go, double *lamo, int *iters, int *status)
+                     const double *lam_prev, long n, double *fo, double *go, double *lamo,
+                     int *iters, int *status)
 {
     double cv = 1.0 / (P->gamma - 1.0);
     int q1 = q1_of(P->lattice), q = q1 * q1;
@@ -726,17 +797,8 @@ static int node_step(const oracle_params *P, const double *f, const double *g, c
     double ln[3] = {lg[0], lg[1], lg[2]};
     double ft[QMAX], gt[QMAX];
     double gradu[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    if (P->split == 1) {
-        long xm = (long)y * P->nx + node_index(x - 1, P->nx, P->bc_x);
-        long xp = (long)y * P->nx + node_index(x + 1, P->nx, P->bc_x);
-        double uym[2], uyp[2];
-        row_velocity(P, lam, x, y - 1, uym);
-        row_velocity(P, lam, x, y + 1, uyp);
-        for (int b = 0; b < 2; b++) {
-            gradu[0][b] = 0.5 * (lam[3 * xp + b] - lam[3 * xm + b]);
-            gradu[1][b] = 0.5 * (uyp[b] - uym[b]);
-        }
-    }
+    if (P->split == 1)
+        source_gradient(P, lam, lam_prev, x, y, gradu);
     int k, conv = 0, bad = 0, used = 0;
     for (k = 0; k < P->pc_max_iter; k++) {
         double rho, jx, jy, E;
@@ -769,20 +831,10 @@ static int node_step(const oracle_params *P, const double *f, const double *g, c
     oracle_transform_q(q1, gt, lg, ln, gt);
     oracle_collide_q(q1, P->split, ft, gt, ln, P->tau, P->prandtl, P->gamma, fo, go);
     if (P->split == 1) {
-        /* d_t u: new minus time-t frame velocity of the node; grad u: central
-           differences of the neighbours' time-t frame velocities */
+        /* d_t u: new minus time-t frame velocity of the node; grad u: the
+           source gradient of the iteration (source_gradient) */
         const double *l0 = lam + 3 * n;
-        long xm = (long)y * P->nx + node_index(x - 1, P->nx, P->bc_x);
-        long xp = (long)y * P->nx + node_index(x + 1, P->nx, P->bc_x);
-        double uym[2], uyp[2];
-        row_velocity(P, lam, x, y - 1, uym);
-        row_velocity(P, lam, x, y + 1, uyp);
         double a[2] = {ln[0] - l0[0], ln[1] - l0[1]};
-        double grad[2][2];
-        for (int b = 0; b < 2; b++) {
-            grad[0][b] = 0.5 * (lam[3 * xp + b] - lam[3 * xm + b]);
-            grad[1][b] = 0.5 * (uyp[b] - uym[b]);
-        }
         /* the source's f is the step's time-centred population, the mean of
            the gathered (pre-collision) and the collided f: its stress is the
            physical one, (1 - omega/2) times the pre-collision non-equilibrium
@@ -790,7 +842,7 @@ static int node_step(const oracle_params *P, const double *f, const double *g, c
         double fmid[QMAX], S[QMAX];
         for (int i = 0; i < q; i++)
             fmid[i] = 0.5 * (ft[i] + fo[i]);
-        oracle_internal_source_q(q1, fmid, ln, a, grad, S);
+        oracle_internal_source_q(q1, fmid, ln, a, gradu, S);
         double tau_g = P->prandtl == 1.0 ? P->tau : 0.5 + (P->tau - 0.5) / P->prandtl;
         for (int i = 0; i < q; i++)
             go[i] += (1.0 - 0.5 / tau_g) * S[i];
@@ -801,10 +853,13 @@ static int node_step(const oracle_params *P, const double *f, const double *g, c
     return 0;
 }
 
-/* One step for every node (node-major outputs).  Returns the number of
+/* One step for every node (node-major outputs).  lam_prev: the frames of the
+ * previous time level (internal-energy split; NULL on the first step after
+ * initialisation and for the other splits).  Returns the number of
  * non-physical nodes. */
 int oracle_step(const oracle_params *P, const double *f, const double *g, const double *lam,
-                double *fo, double *go, double *lamo, int *iters, int *status)
+                const double *lam_prev, double *fo, double *go, double *lamo, int *iters,
+                int *status)
 {
     long N = (long)P->nx * P->ny;
     long q = (long)P->lattice;
@@ -813,16 +868,16 @@ int oracle_step(const oracle_params *P, const double *f, const double *g, const 
     int nbad = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : nbad)
     for (long n = 0; n < N; n++)
-        nbad += node_step(P, f, g, lam, n, fo + q * n, go + q * n, lamo + 3 * n, iters + n,
-                          status + n);
+        nbad += node_step(P, f, g, lam, lam_prev, n, fo + q * n, go + q * n, lamo + 3 * n,
+                          iters + n, status + n);
     return nbad;
 }
 
 /* One step for the listed nodes only (outputs packed in list order), reading
  * the full time-t state; lets a large state be checked node by node. */
 int oracle_step_nodes(const oracle_params *P, const double *f, const double *g, const double *lam,
-                      long count, const long *nodes, double *fo, double *go, double *lamo,
-                      int *iters, int *status)
+                      const double *lam_prev, long count, const long *nodes, double *fo,
+                      double *go, double *lamo, int *iters, int *status)
 {
     long q = (long)P->lattice;
     if (!q1_of(P->lattice))
@@ -830,8 +885,8 @@ int oracle_step_nodes(const oracle_params *P, const double *f, const double *g, 
     int nbad = 0;
 #pragma omp parallel for schedule(dynamic, 4) reduction(+ : nbad)
     for (long k = 0; k < count; k++)
-        nbad += node_step(P, f, g, lam, nodes[k], fo + q * k, go + q * k, lamo + 3 * k, iters + k,
-                          status + k);
+        nbad += node_step(P, f, g, lam, lam_prev, nodes[k], fo + q * k, go + q * k, lamo + 3 * k,
+                          iters + k, status + k);
     return nbad;
 }
 
