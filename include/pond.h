@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define POND_ABI_VERSION 2
+#define POND_ABI_VERSION 3
 
 /* Exported symbols (the library is built with hidden default visibility). */
 #if defined(__GNUC__)
@@ -173,8 +173,10 @@ POND_API pond_status pond_params_default(pond_params *p);
 /* Bytes of device memory a context with these parameters uses (two state
  * buffers, two sets of moment planes, counters), or 0 if *p is invalid.
  * D2Q16: FP32 464 B per node (2 x 152 B of state, 2 x 80 B of moments), FP64
- * 880 B (2 x 280 + 2 x 160); D2Q25: FP32 704 B, FP64 1328 B; walls add the
- * moment planes' ghost rows (16 rows); plus a few KiB. */
+ * 880 B (2 x 280 + 2 x 160); D2Q25: FP32 704 B, FP64 1328 B; the
+ * internal-energy split adds 2 x 16 B (each buffer keeps the previous level's
+ * frame velocities); walls add the moment planes' ghost rows (16 rows); plus a
+ * few KiB. */
 POND_API size_t pond_state_bytes(const pond_params *p);
 
 /* Create a context.  Validates *p before touching the device: invalid values
@@ -239,6 +241,20 @@ POND_API pond_status pond_export_state(pond_ctx *c, double *f, double *g, double
  * stream. */
 POND_API pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, const double *frame,
                               const double *u_ref);
+
+/* The internal-energy split's previous time level: the frame velocities u_x,
+ * u_y of the state before the current one, which the split's source uses (its
+ * velocity gradient is extrapolated along each node's trajectory from the last
+ * two levels, a reading of Eq. int_g_evolution, which gives the source's
+ * gradient but no discretisation).  prev: 2 planes of nx*ny doubles (u_x, then
+ * u_y), host or device memory.  After pond_init_fields or pond_import_state
+ * the current frames stand in for the previous level; pond_import_prev_frame
+ * (after pond_import_state) loads it, so an exported state resumes bit for bit.
+ * Both synchronise the stream; other splits keep no previous level
+ * (POND_ERR_UNSUPPORTED).  The import is refused while the context is a batch
+ * member (POND_ERR_STATE); its values are taken as given. */
+POND_API pond_status pond_export_prev_frame(pond_ctx *c, double *prev);
+POND_API pond_status pond_import_prev_frame(pond_ctx *c, const double *prev);
 
 /* Launch configuration of the step kernel (performance only: every
  * configuration computes the same numbers, bit for bit).
@@ -316,7 +332,9 @@ POND_API pond_status pond_destroy(pond_ctx *c);
  * f_a, g_a, frame_a: buffer A, the input state, device memory of the current
  *          GPU: Q planes of f, Q planes of g (float in FP32, double in FP64,
  *          plane i = velocity i, nx*ny values each, the layout of
- *          pond_export_state), and 3 planes u_x, u_y, T (double).
+ *          pond_export_state), and 3 planes u_x, u_y, T (double); with the
+ *          internal-energy split 5 planes: u_x, u_y, T and the previous time
+ *          level's u_x, u_y (pond_export_prev_frame).
  * f_b, g_b, frame_b: buffer B, the same layout, device memory.
  * nsteps:  >= 0 steps; A and B are ping-pong buffers: step k reads A and
  *          writes B when k is even, reads B and writes A when k is odd, so the
@@ -452,7 +470,10 @@ typedef struct {
 enum { POND_REQ_QUEUED = 0, POND_REQ_RUNNING = 1, POND_REQ_DONE = 2, POND_REQ_FAILED = 3 };
 /* Request flags: outputs kept in host memory at completion. */
 enum { POND_REQ_KEEP_MOMENTS = 1, /* rho, u_x, u_y, T, p: 5 N doubles */
-       POND_REQ_KEEP_STATE = 2 }; /* pond_export_state layout + u_ref: 35 N + 2 doubles */
+       POND_REQ_KEEP_STATE = 2 }; /* pond_export_state layout + u_ref: 35 N + 2 doubles
+                                     (an internal-split server keeps no previous level:
+                                     imported again, the state resumes as after
+                                     pond_import_state alone) */
 
 typedef struct {
     int32_t state;        /* POND_REQ_* */

@@ -44,11 +44,11 @@ pond_status hip_fail(hipError_t e, const char *what) {
 
 const char *last_error() { return g_last_error.c_str(); }
 
-Layout layout_for(long long N, size_t psize, int lattice, long long mom_nodes) {
+Layout layout_for(long long N, size_t psize, int lattice, long long mom_nodes, int prev_planes) {
     Layout L;
     L.pop_bytes = align_up(size_t(N) * size_t(lattice) * psize);
     L.frame_bytes = align_up(size_t(N) * sizeof(double));
-    L.buf_bytes = 2 * L.pop_bytes + 3 * L.frame_bytes;
+    L.buf_bytes = 2 * L.pop_bytes + size_t(3 + prev_planes) * L.frame_bytes;
     L.mom_bytes = align_up(size_t(mom_nodes) * moment_values(lattice, psize == 8) * psize);
     L.cnt_off = 2 * L.buf_bytes + 2 * L.mom_bytes;
     L.scratch_off = L.cnt_off + align_up(sizeof(DevCounters));
@@ -407,7 +407,9 @@ pond_status pond_params_default(pond_params *p) {
 size_t pond_state_bytes(const pond_params *p) {
     if (validate_params(p) != POND_OK) return 0;
     const size_t psize = p->precision == POND_PREC_FP64 ? sizeof(double) : sizeof(float);
-    return layout_for((long long)p->nx * p->ny, psize, p->lattice, moment_plane_nodes(*p)).total;
+    return layout_for((long long)p->nx * p->ny, psize, p->lattice, moment_plane_nodes(*p),
+                      prev_frame_planes(p->split))
+        .total;
 }
 
 pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem,
@@ -418,7 +420,7 @@ pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem
     if (s != POND_OK) return s;
     const size_t psize = p->precision == POND_PREC_FP64 ? sizeof(double) : sizeof(float);
     const long long N = (long long)p->nx * p->ny;
-    Layout L = layout_for(N, psize, p->lattice, moment_plane_nodes(*p));
+    Layout L = layout_for(N, psize, p->lattice, moment_plane_nodes(*p), prev_frame_planes(p->split));
     if (device_mem) {
         if (device_mem_bytes < L.total)
             return fail(POND_ERR_OUT_OF_MEMORY, "device_mem holds %zu bytes, %zu needed",
@@ -462,6 +464,11 @@ pond_status pond_create(const pond_params *p, void *hip_stream, void *device_mem
         c->buf[b].ux = reinterpret_cast<double *>(base + 2 * L.pop_bytes);
         c->buf[b].uy = reinterpret_cast<double *>(base + 2 * L.pop_bytes + L.frame_bytes);
         c->buf[b].T = reinterpret_cast<double *>(base + 2 * L.pop_bytes + 2 * L.frame_bytes);
+        const bool prev = prev_frame_planes(p->split) > 0;
+        c->buf[b].uxp =
+            prev ? reinterpret_cast<double *>(base + 2 * L.pop_bytes + 3 * L.frame_bytes) : nullptr;
+        c->buf[b].uyp =
+            prev ? reinterpret_cast<double *>(base + 2 * L.pop_bytes + 4 * L.frame_bytes) : nullptr;
     }
     c->mom[0] = c->mem + 2 * L.buf_bytes;
     c->mom[1] = c->mem + 2 * L.buf_bytes + L.mom_bytes;
@@ -787,6 +794,41 @@ pond_status pond_import_state(pond_ctx *c, const double *f, const double *g, con
     if (s != POND_OK) return s;
     c->steps = 0;
     c->initialized = true;
+    return POND_OK;
+}
+
+pond_status pond_export_prev_frame(pond_ctx *c, double *prev) {
+    pond_status s = check_ctx(c, true);
+    if (s != POND_OK) return s;
+    if (!prev) return fail(POND_ERR_INVALID_ARG, "output pointer is NULL");
+    const DevState &st = c->buf[c->cur];
+    if (!st.uxp)
+        return fail(POND_ERR_UNSUPPORTED,
+                    "only the internal-energy split keeps the previous level's frames");
+    const long long N = c->args.N;
+    const size_t bytes = size_t(N) * sizeof(double);
+    hipError_t e = hipMemcpyAsync(prev, st.uxp, bytes, hipMemcpyDefault, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(prev + N, st.uyp, bytes, hipMemcpyDefault, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "export of the previous frames");
+    return sync_and_check(c);
+}
+
+pond_status pond_import_prev_frame(pond_ctx *c, const double *prev) {
+    pond_status s = check_ctx(c, true);
+    if (s != POND_OK) return s;
+    if ((s = check_unbatched(c)) != POND_OK) return s;
+    if (!prev) return fail(POND_ERR_INVALID_ARG, "input pointer is NULL");
+    const DevState &st = c->buf[c->cur];
+    if (!st.uxp)
+        return fail(POND_ERR_UNSUPPORTED,
+                    "only the internal-energy split keeps the previous level's frames");
+    const long long N = c->args.N;
+    const size_t bytes = size_t(N) * sizeof(double);
+    hipError_t e = hipMemcpyAsync(st.uxp, prev, bytes, hipMemcpyDefault, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(st.uyp, prev + N, bytes, hipMemcpyDefault, c->stream);
+    hipError_t e2 = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "import of the previous frames");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamSynchronize");
     return POND_OK;
 }
 

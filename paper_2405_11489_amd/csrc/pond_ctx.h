@@ -23,7 +23,8 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // One context's device allocation:
 //   [state buffer 0 | state buffer 1 | moment planes 0 | moment planes 1 | counters | scratch]
-// (moment planes k hold the moments of state buffer k)
+// (moment planes k hold the moments of state buffer k).  A state buffer is
+//   [Q f planes | Q g planes | u_x | u_y | T | (internal split) u_x, u_y of the previous level]
 struct Layout {
     size_t pop_bytes;    // one set of Q planes (Q = 16 or 25)
     size_t frame_bytes;  // one frame plane
@@ -31,6 +32,11 @@ struct Layout {
     size_t mom_bytes;    // one set of moment planes (2 NM values per node, padded to the groups)
     size_t cnt_off, scratch_off, total;
 };
+
+// Frame planes of the previous time level per state buffer: 2 (u_x, u_y) for
+// the internal-energy split, whose source extrapolates the velocity gradient
+// along trajectories from the last two levels; 0 otherwise.
+inline int prev_frame_planes(int split) { return split == POND_SPLIT_INTERNAL ? 2 : 0; }
 
 constexpr int kScratchDoubles = 3 * 256;
 
@@ -53,7 +59,7 @@ inline long long moment_plane_nodes(const pond_params &p) {
     return (long long)p.nx * (p.ny + (p.bc_y == POND_BC_WALL ? 2 * kWallGhostRows : 0));
 }
 
-Layout layout_for(long long N, size_t psize, int lattice, long long mom_nodes);
+Layout layout_for(long long N, size_t psize, int lattice, long long mom_nodes, int prev_planes);
 
 // LDS nodes per block (the moment groups of one node each) that let
 // blocks_per_cu blocks share the 160 KiB of a CU.

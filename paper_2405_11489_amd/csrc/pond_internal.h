@@ -10,10 +10,14 @@
 namespace pond {
 
 // Device state of one instance.  Population planes: pop[i * N + n] for
-// velocity i and node n = y * nx + x.  Frame planes: double ux, uy, T.
+// velocity i and node n = y * nx + x.  Frame planes: double ux, uy, T.  The
+// internal-energy split also keeps the frame velocities of the previous time
+// level (uxp, uyp: its source extrapolates the velocity gradient along
+// trajectories from the last two levels); NULL for the other splits.
 struct DevState {
     void *f, *g;          // Q planes each (float or double), Q = 16 or 25
     double *ux, *uy, *T;  // frame
+    double *uxp, *uyp;    // frame velocities of the previous time level (internal split)
 };
 
 // Counters accumulated on the device (64-bit integer atomics only, so the sums

@@ -69,6 +69,11 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs a, const double *
     st.ux[n] = vx;
     st.uy[n] = vy;
     st.T[n] = t;
+    if (st.uxp) {
+        // internal split: a fresh state's frames stand in for the previous level
+        st.uxp[n] = vx;
+        st.uyp[n] = vy;
+    }
 }
 
 // ---------------------------------------------------- moments pre-pass ----
@@ -278,6 +283,12 @@ __global__ __launch_bounds__(kBlock) void import_kernel(StepArgs a, const double
     st.ux[n] = frame[n];
     st.uy[n] = frame[a.N + n];
     st.T[n] = frame[2 * a.N + n];
+    if (st.uxp) {
+        // internal split: the imported frames stand in for the previous level
+        // (pond_import_prev_frame may load that level afterwards)
+        st.uxp[n] = frame[n];
+        st.uyp[n] = frame[a.N + n];
+    }
 }
 
 // per-block sums of (rho, rho ux, rho uy) over a fixed contiguous chunk

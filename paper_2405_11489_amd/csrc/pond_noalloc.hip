@@ -131,8 +131,13 @@ pond_status pond_step_noalloc(const pond_params *p, const double *u_ref, void *f
                     base + align_up(sizeof(DevCounters)) + mom_bytes};
     const long long N = a.N;
     DevState st[2];
-    st[0] = DevState{f_a, g_a, frame_a, frame_a + N, frame_a + 2 * N};
-    st[1] = DevState{f_b, g_b, frame_b, frame_b + N, frame_b + 2 * N};
+    // the internal split's frame buffers carry the previous level's u_x, u_y
+    // after u_x, u_y, T
+    const bool prev = prev_frame_planes(p->split) > 0;
+    st[0] = DevState{f_a, g_a, frame_a, frame_a + N, frame_a + 2 * N,
+                     prev ? frame_a + 3 * N : nullptr, prev ? frame_a + 4 * N : nullptr};
+    st[1] = DevState{f_b, g_b, frame_b, frame_b + N, frame_b + 2 * N,
+                     prev ? frame_b + 3 * N : nullptr, prev ? frame_b + 4 * N : nullptr};
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     hipError_t e;
     if (dbl) {

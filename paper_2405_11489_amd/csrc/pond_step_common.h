@@ -415,32 +415,78 @@ __device__ __forceinline__ void stencil_extent(int x, double u, double s, int &l
     }
 }
 
-// Velocity gradient of the time-t frames at node n = (x, y) for the
-// internal-energy split: central differences of the four neighbours' frame
-// velocities (wrapped or clamped like the stencil; a row beyond a wall takes
-// the ghost frame velocity of the wall closure, the mirror node -- here the
-// node itself -- reflected about the wall velocity).  gab = d_a u_b.
-__device__ __forceinline__ void frame_gradient(const StepArgs &a, const DevState &src, int x, int y,
-                                               long long n, double &gxx, double &gxy, double &gyx,
-                                               double &gyy) {
+// Velocity gradient of frame velocities (ux, uy) at grid node (x, y), for the
+// internal-energy split: central differences of the four neighbours' velocities
+// (wrapped or clamped like the stencil; with walls a neighbour row beyond a wall
+// takes the ghost frame velocity of the wall closure, the mirror node -- here
+// the node itself -- reflected about the wall velocity).
+// g = (d_x u_x, d_x u_y, d_y u_x, d_y u_y).
+__device__ __forceinline__ void node_gradient(const StepArgs &a, const double *__restrict__ ux,
+                                              const double *__restrict__ uy, int x, int y,
+                                              double g[4]) {
     const long long row = (long long)y * a.nx;
     const long long xm = row + wrap_index(x - 1, a.nx, a.bc_x);
     const long long xp = row + wrap_index(x + 1, a.nx, a.bc_x);
     const long long ym = (long long)wrap_index(y - 1, a.ny, a.bc_y) * a.nx + x;
     const long long yp = (long long)wrap_index(y + 1, a.ny, a.bc_y) * a.nx + x;
-    double uxm = src.ux[ym], uym = src.uy[ym], uxp = src.ux[yp], uyp = src.uy[yp];
+    double uxm = ux[ym], uym = uy[ym], uxp = ux[yp], uyp = uy[yp];
     if (a.bc_y == 2 && y == 0) {
-        uxm = 2.0 * a.wall_ux[0] - src.ux[n];
-        uym = -src.uy[n];
+        uxm = 2.0 * a.wall_ux[0] - ux[row + x];
+        uym = -uy[row + x];
     }
     if (a.bc_y == 2 && y == a.ny - 1) {
-        uxp = 2.0 * a.wall_ux[1] - src.ux[n];
-        uyp = -src.uy[n];
+        uxp = 2.0 * a.wall_ux[1] - ux[row + x];
+        uyp = -uy[row + x];
     }
-    gxx = 0.5 * (src.ux[xp] - src.ux[xm]);
-    gxy = 0.5 * (src.uy[xp] - src.uy[xm]);
-    gyx = 0.5 * (uxp - uxm);
-    gyy = 0.5 * (uyp - uym);
+    g[0] = 0.5 * (ux[xp] - ux[xm]);
+    g[1] = 0.5 * (uy[xp] - uy[xm]);
+    g[2] = 0.5 * (uxp - uxm);
+    g[3] = 0.5 * (uyp - uym);
+}
+
+// Velocity gradient of frame velocities (ux, uy) at the point (px, py): the
+// bilinear interpolation of node_gradient over the four nodes around it
+// (columns and rows wrapped or clamped like the stencil; with walls a row
+// beyond them is the last row).  The point is clamped to a finite range first,
+// so a non-physical frame still indexes inside the grid.
+__device__ __forceinline__ void point_gradient(const StepArgs &a, const double *__restrict__ ux,
+                                               const double *__restrict__ uy, double px, double py,
+                                               double g[4]) {
+    px = fmin(fmax(px, -1.0e8), 1.0e8);
+    py = fmin(fmax(py, -1.0e8), 1.0e8);
+    const double fx = floor(px), fy = floor(py);
+    const double ax = px - fx, ay = py - fy;
+    const int x0 = int(fx), y0 = int(fy);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[k] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int yj = wrap_index(y0 + j, a.ny, a.bc_y);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int xi = wrap_index(x0 + i, a.nx, a.bc_x);
+            const double w = (i ? ax : 1.0 - ax) * (j ? ay : 1.0 - ay);
+            double gn[4];
+            node_gradient(a, ux, uy, xi, yj, gn);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) g[k] += w * gn[k];
+        }
+    }
+}
+
+// The internal-energy split's velocity gradient for destination node (x, y)
+// with time-t frame velocity (u0, u1): taken at the end of the step, where the
+// collision and the source act, by linear extrapolation along the node's
+// trajectory from the last two time levels, 2 G_t(x - u) - G_{t-1}(x - 2u)
+// (G_t: point_gradient of the time-t frames, G_{t-1}: of the previous level's;
+// exact for a velocity field advected with the flow).
+__device__ __forceinline__ void source_gradient(const StepArgs &a, const DevState &src, int x,
+                                                int y, double u0, double u1, double g[4]) {
+    double ga[4], gb[4];
+    point_gradient(a, src.ux, src.uy, double(x) - u0, double(y) - u1, ga);
+    point_gradient(a, src.uxp, src.uyp, double(x) - 2.0 * u0, double(y) - 2.0 * u1, gb);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[k] = 2.0 * ga[k] - gb[k];
 }
 
 // The whole step of one destination node (x, y) = node n whose time-t frame
@@ -472,17 +518,17 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
     for (int k = 0; k < NM; ++k) Mf[k] = Mg[k] = P(0);
     bool done = !live, conv = false, bad = false, overrun = false;
     unsigned long long itc = 0;  // gathers of the wave's lanes
-    // internal split: velocity gradient of the time-t frames (the same for every
+    // internal split: the source's velocity gradient (the same for every
     // iterate), in the arithmetic's precision
     P gxx = P(0), gxy = P(0), gyx = P(0), gyy = P(0);
     if constexpr (S == 1) {
         if (live) {
-            double dxx, dxy, dyx, dyy;
-            frame_gradient(a, src, x, y, n, dxx, dxy, dyx, dyy);
-            gxx = P(dxx);
-            gxy = P(dxy);
-            gyx = P(dyx);
-            gyy = P(dyy);
+            double gr[4];
+            source_gradient(a, src, x, y, l0, l1, gr);
+            gxx = P(gr[0]);
+            gxy = P(gr[1]);
+            gyx = P(gr[2]);
+            gyy = P(gr[3]);
         }
     }
 
@@ -689,7 +735,7 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
         // with f the step's time-centred population (the mean of the re-projected
         // pre-collision and the collided f: a0 and (1 - omega / 2) times the higher
         // coefficients, whose stress is the physical one), a = d_t u = u* - u(t),
-        // grad u from frame_gradient; g receives (1 - omega_g / 2) S, omega_g its
+        // grad u from source_gradient; g receives (1 - omega_g / 2) S, omega_g its
         // relaxation rate (its equilibrium already holds the other half of sum S)
         P afp[NM];
         P ax = P(0), ay = P(0), src_w = P(0);
@@ -751,6 +797,12 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
         dst.ux[n] = uxst;
         dst.uy[n] = uyst;
         dst.T[n] = Tst;
+        if constexpr (S == 1) {
+            // the time-t frame becomes the new state's previous level (read again
+            // rather than kept live across the loop)
+            dst.uxp[n] = src.ux[n];
+            dst.uyp[n] = src.uy[n];
+        }
         store_moments<P, nmom<L>()>(mom_out, a.mstride, a.moff + n, MM);
     }
 

@@ -25,7 +25,7 @@ LATTICE_D2Q16, LATTICE_D2Q25 = 16, 25
 SPLIT_TOTAL, SPLIT_INTERNAL, SPLIT_NONTRANS = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
 BC_PERIODIC, BC_CLAMP, BC_WALL = 0, 1, 2
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 EXPORTED = [
     "pond_abi_version", "pond_params_default", "pond_state_bytes", "pond_create",
@@ -37,7 +37,7 @@ EXPORTED = [
     "pond_autotune", "pond_tuning_cache_clear", "pond_server_config_default",
     "pond_server_create", "pond_server_submit", "pond_server_poll", "pond_server_wait",
     "pond_server_result", "pond_server_release", "pond_server_get_stats", "pond_server_destroy",
-    "pond_step_noalloc",
+    "pond_step_noalloc", "pond_export_prev_frame", "pond_import_prev_frame",
 ]
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
 REQ_KEEP_MOMENTS, REQ_KEEP_STATE = 1, 2
@@ -136,6 +136,8 @@ _L.pond_stats.argtypes = [_vp, ctypes.POINTER(pond_stats_t)]
 _L.pond_synchronize.argtypes = [_vp]
 _L.pond_export_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _L.pond_import_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_L.pond_export_prev_frame.argtypes = [_vp, _vp]
+_L.pond_import_prev_frame.argtypes = [_vp, _vp]
 _L.pond_destroy.argtypes = [_vp]
 _L.pond_step_noalloc.argtypes = [ctypes.POINTER(pond_params), _vp, _vp, _vp, _vp, _vp, _vp,
                                  _vp, ctypes.c_int64, _vp, ctypes.POINTER(pond_stats_t)]
@@ -250,6 +252,14 @@ def pond_export_state(ctx, f, g, frame, u_ref=None):
 
 def pond_import_state(ctx, f, g, frame, u_ref=None):
     _check(_L.pond_import_state(ctx, _ptr(f), _ptr(g), _ptr(frame), _ptr(u_ref)))
+
+
+def pond_export_prev_frame(ctx, prev):
+    _check(_L.pond_export_prev_frame(ctx, _ptr(prev)))
+
+
+def pond_import_prev_frame(ctx, prev):
+    _check(_L.pond_import_prev_frame(ctx, _ptr(prev)))
 
 
 def pond_destroy(ctx):
@@ -472,6 +482,16 @@ class Solver:
                           np.ascontiguousarray(g, dtype=np.float64),
                           np.ascontiguousarray(frame, dtype=np.float64),
                           None if u_ref is None else np.ascontiguousarray(u_ref, dtype=np.float64))
+
+    def export_prev_frame(self):
+        """Internal-energy split: the previous time level's frame velocities,
+        shape (2, N) (u_x, u_y)."""
+        prev = np.zeros((2, self.nx * self.ny))
+        pond_export_prev_frame(self.ctx, prev)
+        return prev
+
+    def import_prev_frame(self, prev):
+        pond_import_prev_frame(self.ctx, np.ascontiguousarray(prev, dtype=np.float64))
 
     def synchronize(self):
         pond_synchronize(self.ctx)

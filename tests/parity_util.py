@@ -79,7 +79,17 @@ def field_l1(m_gpu, m_or):
     return out
 
 
-def to_oracle_state(f, g, fr):
-    """GPU export layout (planes) -> oracle node-major state."""
+def to_oracle_state(f, g, fr, prev=None):
+    """GPU export layout (planes) -> oracle node-major state; prev: the
+    internal-energy split's previous-level frame velocities (2, N), or None."""
+    lam_prev = None
+    if prev is not None:
+        lam_prev = np.ascontiguousarray(np.vstack([prev, fr[2:3]]).T)
     return oracle.State(np.ascontiguousarray(f.T), np.ascontiguousarray(g.T),
-                        np.ascontiguousarray(fr.T))
+                        np.ascontiguousarray(fr.T), lam_prev)
+
+
+def prev_frame_of(sol, split):
+    """The internal-energy split's previous-level frame velocities of a solver
+    (None for the other splits, which keep none)."""
+    return sol.export_prev_frame() if split == oracle.INTERNAL else None

@@ -63,7 +63,8 @@ def test_walls_add_ghost_rows_and_validate(pond):
         assert pond.pond_state_bytes(r) > 0
     r = pond.pond_params_default(nx=4, ny=32, bc_y=pond.BC_WALL)
     r.split = pond.SPLIT_INTERNAL
-    assert pond.pond_state_bytes(r) == pond.pond_state_bytes(p)
+    # the internal split keeps the previous level's u_x, u_y in each buffer
+    assert pond.pond_state_bytes(r) - pond.pond_state_bytes(p) >= 2 * 2 * 8 * 4 * 32
     for fields, status in (({"bc_x": pond.BC_WALL}, 1),):
         r = pond.pond_params_default(nx=4, ny=32, bc_y=pond.BC_WALL)
         for k, v in fields.items():
@@ -86,6 +87,10 @@ def test_state_bytes(pond):
     p.precision = pond.PREC_FP64
     b64 = pond.pond_state_bytes(p)
     assert 880 * 512 * 512 <= b64 < 880 * 512 * 512 + 16384
+    # the internal split: two more double planes per buffer
+    p.precision = pond.PREC_FP32
+    p.split = pond.SPLIT_INTERNAL
+    assert 496 * 512 * 512 <= pond.pond_state_bytes(p) < 496 * 512 * 512 + 16384
 
 
 @pytest.mark.parametrize("field,value,status", [
@@ -131,11 +136,13 @@ def test_d2q25_state_size(pond):
     assert pond.pond_state_bytes(p) == b64
 
 
-def test_internal_split_accepted_with_the_same_state_size(pond):
+def test_internal_split_accepted_with_the_previous_level(pond):
+    """The internal split's buffers add the previous level's u_x, u_y (two
+    double planes per buffer, each aligned to 256 bytes)."""
     p = pond.pond_params_default(nx=64, ny=32)
     b0 = pond.pond_state_bytes(p)
     p.split = pond.SPLIT_INTERNAL
-    assert pond.pond_state_bytes(p) == b0 > 0
+    assert pond.pond_state_bytes(p) - b0 == 2 * 2 * 64 * 32 * 8 > 0
 
 
 def test_caller_memory_too_small_rejected(pond):

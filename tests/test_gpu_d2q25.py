@@ -9,7 +9,8 @@ import pytest
 import oracle
 from paper_2405_11489_amd import workloads
 from parity_util import (field_errors, gpu_run, gpu_solver, oracle_params_for, oracle_run,
-                         plane_errors, to_oracle_state, velocity_scale)
+                         plane_errors, prev_frame_of, to_oracle_state,
+                         velocity_scale)
 
 pytestmark = pytest.mark.gpu
 
@@ -104,10 +105,11 @@ def test_full_size_sampled_nodes(lattice, split, prec, bar):
     with gpu_solver(w, prec, lattice=lattice, split=split) as sol:
         sol.step(3)
         f0, g0, fr0, _ = sol.export_state()
+        pv0 = prev_frame_of(sol, split)
         sol.step(1)
         f1, g1, fr1, _ = sol.export_state()
     P = oracle_params_for(w, lattice=lattice, split=split)
-    fo, go, lo, _, _ = oracle.step_nodes(P, to_oracle_state(f0, g0, fr0), nodes)
+    fo, go, lo, _, _ = oracle.step_nodes(P, to_oracle_state(f0, g0, fr0, pv0), nodes)
     for a, b in ((f1[:, nodes].T, fo), (g1[:, nodes].T, go)):
         # FP64: each population plane against its own max norm; FP32: against the
         # largest population of the distribution, the scale float populations are

@@ -10,7 +10,8 @@ import pytest
 import oracle
 from paper_2405_11489_amd import workloads
 from parity_util import (field_errors, field_l1, gpu_run, gpu_solver, oracle_params_for,
-                         oracle_run, plane_errors, to_oracle_state, velocity_scale)
+                         oracle_run, plane_errors, prev_frame_of, to_oracle_state,
+                         velocity_scale)
 
 pytestmark = pytest.mark.gpu
 
@@ -99,10 +100,11 @@ def test_full_size_sampled_nodes(prec, bar):
     with gpu_solver(w, prec, split=INT) as sol:
         sol.step(3)
         f0, g0, fr0, _ = sol.export_state()
+        pv0 = sol.export_prev_frame()
         sol.step(1)
         f1, g1, fr1, _ = sol.export_state()
     P = oracle_params_for(w, split=INT)
-    fo, go, lo, _, _ = oracle.step_nodes(P, to_oracle_state(f0, g0, fr0), nodes)
+    fo, go, lo, _, _ = oracle.step_nodes(P, to_oracle_state(f0, g0, fr0, pv0), nodes)
     for a, b in ((f1[:, nodes].T, fo), (g1[:, nodes].T, go)):
         assert np.max(np.abs(a - b) / np.max(np.abs(b), axis=0)) <= bar
     vs = velocity_scale(lo[:, 0], lo[:, 1], lo[:, 2])
@@ -144,7 +146,12 @@ def test_batched_equals_alone_bitwise(prec):
     from paper_2405_11489_amd import pond
     ws = [modes(48, 40, mach=1.5, seed=21), clamp_x(modes(33, 17, mach=2.0, seed=22)),
           workloads.sod_tube(nx=100, nu=2e-3, steps=10)]
-    alone = [gpu_run(w, prec, 9, split=INT)[:3] for w in ws]
+    alone, alone_prev = [], []
+    for w in ws:
+        with gpu_solver(w, prec, split=INT) as s:
+            s.step(9)
+            alone.append(s.export_state()[:3])
+            alone_prev.append(s.export_prev_frame())
     sols = [gpu_solver(w, prec, split=INT) for w in ws]
     try:
         b = pond.pond_batch_create([s.ctx for s in sols])
@@ -153,9 +160,10 @@ def test_batched_equals_alone_bitwise(prec):
             pond.pond_batch_synchronize(b)
         finally:
             pond.pond_batch_destroy(b)
-        for s, ref in zip(sols, alone):
+        for s, ref, pv in zip(sols, alone, alone_prev):
             for x, y in zip(s.export_state()[:3], ref):
                 np.testing.assert_array_equal(x, y)
+            np.testing.assert_array_equal(s.export_prev_frame(), pv)
     finally:
         for s in sols:
             s.close()
@@ -195,3 +203,82 @@ def test_sod_tube_matches_oracle():
     _, _, _, _, _, m32 = gpu_run(w, FP32, w.steps, split=INT)
     l1 = field_l1(m32, oracle.moments(P, s))
     assert max(l1.values()) <= 1e-4, l1
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_resume_with_previous_level_is_bitwise(prec):
+    """The split's state includes the previous level's frame velocities: a
+    state exported with them and imported with them resumes bit for bit; the
+    previous level after a step is the frame before it; a fresh import (the
+    current frames standing in for the previous level) takes another path."""
+    w = modes(40, 24, mach=1.5, amp=1e-2, seed=6)
+    with gpu_solver(w, prec, split=INT) as s:
+        s.step(5)
+        ref = s.export_state()
+        ref_prev = s.export_prev_frame()
+    with gpu_solver(w, prec, split=INT) as s:
+        s.step(2)
+        f, g, fr, ur = s.export_state()
+        prev = s.export_prev_frame()
+        s.step(1)
+        np.testing.assert_array_equal(s.export_prev_frame(), fr[:2])
+    with gpu_solver(w, prec, split=INT) as s:
+        s.import_state(f, g, fr, ur)
+        np.testing.assert_array_equal(s.export_prev_frame(), fr[:2])
+        s.import_prev_frame(prev)
+        s.step(3)
+        out = s.export_state()
+        np.testing.assert_array_equal(s.export_prev_frame(), ref_prev)
+    for x, y in zip(out[:3], ref[:3]):
+        np.testing.assert_array_equal(x, y)
+    with gpu_solver(w, prec, split=INT) as s:
+        s.import_state(f, g, fr, ur)
+        s.step(3)
+        assert not np.array_equal(s.export_state()[1], ref[1])
+
+
+def test_previous_level_refused_for_other_splits():
+    from paper_2405_11489_amd import pond
+    w = modes(8, 6, mach=1.0, seed=4, prandtl=1.0)  # the non-translational split: Pr = 1
+    for split in (oracle.TOTAL, oracle.NONTRANS):
+        with gpu_solver(w, FP32, split=split) as s:
+            for call in (lambda: s.export_prev_frame(),
+                         lambda: s.import_prev_frame(np.zeros((2, w.nodes)))):
+                with pytest.raises(pond.PondError) as ei:
+                    call()
+                assert ei.value.status == pond.ERR_UNSUPPORTED
+
+
+def test_resumed_state_matches_oracle_with_previous_level():
+    """The oracle stepping a GPU state that carries the previous level agrees
+    with the GPU's own next steps (FP64, 1e-12): the previous level enters
+    the source as the oracle reads it."""
+    w = clamp_x(modes(24, 20, mach=1.8, amp=2e-2, seed=17))
+    with gpu_solver(w, FP64, split=INT) as s:
+        s.step(4)
+        f, g, fr, _ = s.export_state()
+        prev = s.export_prev_frame()
+        s.step(3)
+        f1, g1, fr1, _ = s.export_state()
+    P = oracle_params_for(w, split=INT)
+    o, _ = oracle.step(P, to_oracle_state(f, g, fr, prev), 3)
+    assert max(plane_errors(f1, g1, fr1, o)) <= 1e-12
+
+
+def test_mach2_512_stays_physical_for_the_full_run():
+    """The 512^2 Mach-2 Fourier-mode workload (tau = 0.55) with this split
+    over its full 2000 steps in FP32: no non-physical node, and the
+    perturbation decays (its velocity deviation from the background ends
+    below where it started)."""
+    w = modes(512, mach=2.0, amp=1e-3, seed=0, tau=0.55)
+    with gpu_solver(w, FP32, split=INT) as s:
+        m0 = s.moments()
+        s.step(2000)
+        st = s.stats()
+        m1 = s.moments()
+    assert st.nonphysical == 0 and st.nonconverged == 0
+
+    def dev(m):
+        return float(np.max(np.hypot(m["ux"] - m["ux"].mean(), m["uy"] - m["uy"].mean())))
+
+    assert dev(m1) < dev(m0)

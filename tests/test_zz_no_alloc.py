@@ -31,9 +31,13 @@ def _noalloc_vs_context(w, prec, nsteps, **kw):
         sol.step(2)
         f = torch.empty((q, N), dtype=torch.float64, device=dev)
         g = torch.empty_like(f)
-        fr = torch.empty((3, N), dtype=torch.float64, device=dev)
+        internal = kw.get("split", 0) == pond.SPLIT_INTERNAL
+        # the internal split's frame buffers carry the previous level's u_x, u_y
+        fr = torch.empty((5 if internal else 3, N), dtype=torch.float64, device=dev)
         ur = np.zeros(2)
-        pond.pond_export_state(sol.ctx, f, g, fr, ur)
+        pond.pond_export_state(sol.ctx, f, g, fr[:3], ur)
+        if internal:
+            pond.pond_export_prev_frame(sol.ctx, fr[3:])
         dt = torch.float64 if prec == FP64 else torch.float32
         fa, ga, fra = f.to(dt).contiguous(), g.to(dt).contiguous(), fr.clone()
         fb, gb, frb = torch.empty_like(fa), torch.empty_like(ga), torch.empty_like(fra)
@@ -44,7 +48,9 @@ def _noalloc_vs_context(w, prec, nsteps, **kw):
         f2 = torch.empty_like(f)
         g2 = torch.empty_like(g)
         fr2 = torch.empty_like(fr)
-        pond.pond_export_state(sol.ctx, f2, g2, fr2, None)
+        pond.pond_export_state(sol.ctx, f2, g2, fr2[:3], None)
+        if internal:
+            pond.pond_export_prev_frame(sol.ctx, fr2[3:])
         ctx_stats = sol.stats()
     out = (fb, gb, frb) if nsteps % 2 else (fa, ga, fra)
     torch.cuda.synchronize()
