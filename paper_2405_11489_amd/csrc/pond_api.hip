@@ -135,12 +135,11 @@ static long long tiles_of(const pond_params &p, int tx, int ty) {
 // the waves: 717 against 545 MLUPS at 512^2, Mach 2, 718 against 562 at
 // 1024^2, 1157 against 864 on the 2048^2 quadrants; at 256^2 its 128 tiles
 // leave half the CUs idle: 376 against 479), and in FP32 when the grid needs
-// more than one round of 32 x 8 blocks at three waves per SIMD but fits one
-// round of 32 x 16 blocks at four (512^2: 1664 against 1487 MLUPS; internal
-// split 1491 against 1380).  Beyond one round the four-wave kernel's spills
-// cost about what the partial round saves (1024^2: 2035 against 2068; 2048^2
-// quadrants: 2941 against 3077), and below it both shapes finish in one round
-// and the three-wave kernel is the faster.
+// more than one round of 32 x 8 blocks but fits one round of 32 x 16 blocks (a
+// kernel that runs more waves per SIMD with 512-lane blocks than with 256-lane
+// ones).  The FP32 D2Q16 kernels with the shared x-pass run two waves per SIMD
+// at either block size, so they keep 32 x 8 (2048^2 quadrants: 1.13 against
+// 1.32 ms per step with 32 x 16; 512^2 Mach 2: 0.153 against 0.159 ms).
 pond_tuning default_tuning(const pond_params &p) {
     pond_tuning t;
     t.kernel = POND_KERNEL_TILED;

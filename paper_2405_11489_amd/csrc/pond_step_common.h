@@ -246,6 +246,35 @@ struct GlobalTaps {
         }
     }
 
+    __device__ __forceinline__ P ref_at(int k) const { return ref[k]; }
+
+    // Stencil rows r0 .. r0 + n - 1 (unwrapped) of the column stencil bx .. bx +
+    // NP - 1: for each row r, in ascending order, X = sum_p wx[p] (M(bx + p, r) -
+    // M_ref) over the 2 NM moments (the x-pass), handed to visit(r, seg, X).
+    template <class Visit>
+    __device__ __forceinline__ void rows(int bx, const P wx[NP], int r0, int n, int seg,
+                                         Visit &visit) const {
+        int col[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) col[j] = wrap_index(bx + j, nx, bc_x);
+#pragma unroll 1
+        for (int t = 0; t < n; ++t) {
+            const long long row = moff + (long long)mom_row(r0 + t, ny, bc_y, wall_h) * nx;
+            P X[2 * L::NM];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                P M[nmom_padded<P, L>()];
+                load_moments<P, nmom<L>()>(mom, N, row + col[p], M);
+#pragma unroll
+                for (int k = 0; k < 2 * L::NM; ++k) {
+                    const P dv = M[k] - ref[k];
+                    X[k] = p == 0 ? wx[p] * dv : X[k] + wx[p] * dv;
+                }
+            }
+            visit(r0 + t, seg, X);
+        }
+    }
+
     // adds sum_{p,q} wx[p] wy[q] (M(bx + p, by + q) - M_ref)
     __device__ __forceinline__ void gather(int bx, int by, const P wx[NP], const P wy[NP],
                                            P Mf[L::NM], P Mg[L::NM]) const {
@@ -489,6 +518,104 @@ __device__ __forceinline__ void source_gradient(const StepArgs &a, const DevStat
     for (int k = 0; k < 4; ++k) g[k] = 2.0 * ga[k] - gb[k];
 }
 
+// Velocities per shared x-pass of the FP32 D2Q16 gather (4: the Q1 velocities
+// of one x-component; 2: half of them; 1: no sharing, every velocity gathers its
+// own NP x NP taps).  FP64 and D2Q25 gather per velocity.
+#ifndef POND_VEL_GROUP
+#define POND_VEL_GROUP 4
+#endif
+template <typename P, class L>
+constexpr int vel_group() {
+    return (L::Q == 16 && sizeof(P) == 4) ? POND_VEL_GROUP : 1;
+}
+
+// The gather of every velocity of a D2Q16 node in the iterate frame (departure
+// offsets xu = x - u, yu = y - u relative to the node, scale sc = sqrt(T),
+// frame shift (dux, duy) from u_ref and 1 / sqrt(T) = is), with the
+// x-interpolation shared: the VG velocities of a group have the same x-component
+// c(ia), so the same departure abscissa and column stencil, and differ only in
+// their rows.  Each row of the union of their row stencils is interpolated along
+// x once (taps.rows); every velocity whose stencil holds the row takes that
+// x-pass with its row weight, through its frame-transformation coefficients
+// (the scalar f_i = B_i . I_i distributes over the rows).  When the union is
+// longer than the separate stencils (hot flows), each velocity's rows are
+// visited on their own; the sums are the same either way.  take(i, cx, cy, f_i,
+// g_i) receives each gathered population pair.
+template <typename P, int NP, class L, int VG, class Taps, class Take>
+__device__ __forceinline__ void gather_shared_rows(const Taps &taps, const VelocityTablesP<P> &tab,
+                                                   double xu, double yu, double sc, P dux, P duy,
+                                                   P is, Take &take) {
+    constexpr int NM = L::NM;
+    static_assert(L::Q1 % VG == 0, "velocity groups split the x-component's velocities");
+#pragma unroll 1
+    for (int ia = 0; ia < L::Q1; ++ia) {
+        const double cx = L::c(ia);
+        P wx[NP];
+        const int bx = lagrange<NP>(fma(-sc, cx, xu), wx);
+#pragma unroll 1
+        for (int g = 0; g < L::Q1 / VG; ++g) {
+            // rows and weights of the group's velocities b = g VG + v: their
+            // departure ordinates y - u - sqrt(T) c(b) descend with b, and so do
+            // their first stencil rows by[v]
+            int by[VG];
+            P wq[VG][NP];  // row weights, consumed first to last
+            P B[VG][NM];
+            P af[VG], ag[VG];
+#pragma unroll
+            for (int v = 0; v < VG; ++v) {
+                const int b = g * VG + v;
+                by[v] = lagrange<NP>(fma(-sc, L::c(b), yu), wq[v]);
+                pop_coeffs(tab.recon[L::Q1 * ia + b], dux, duy, is, B[v]);
+                // the sums start at the transformed reference moments
+                P sf = P(0), sg = P(0);
+#pragma unroll
+                for (int k = 0; k < NM; ++k) {
+                    sf += B[v][k] * taps.ref_at(k);
+                    sg += B[v][k] * taps.ref_at(NM + k);
+                }
+                af[v] = sf;
+                ag[v] = sg;
+            }
+            auto visit = [&](int r, int seg, const P (&X)[2 * NM]) {
+#pragma unroll
+                for (int v = 0; v < VG; ++v) {
+                    const bool mine = seg < 0 ? unsigned(r - by[v]) < unsigned(NP) : seg == v;
+                    if (mine) {
+                        const P w = wq[v][0];
+#pragma unroll
+                        for (int q = 0; q + 1 < NP; ++q) wq[v][q] = wq[v][q + 1];
+                        P df = P(0), dg = P(0);
+#pragma unroll
+                        for (int k = 0; k < NM; ++k) {
+                            df += B[v][k] * X[k];
+                            dg += B[v][k] * X[NM + k];
+                        }
+                        af[v] += w * df;
+                        ag[v] += w * dg;
+                    }
+                }
+            };
+            const int span = by[0] - by[VG - 1] + NP;
+            if (span <= VG * NP) {
+                taps.rows(bx, wx, by[VG - 1], span, -1, visit);
+            } else {
+#pragma unroll 1
+                for (int v = 0; v < VG; ++v) {
+                    int r0 = by[0];
+#pragma unroll
+                    for (int u = 1; u < VG; ++u) r0 = v == u ? by[u] : r0;
+                    taps.rows(bx, wx, r0, NP, v, visit);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < VG; ++v) {
+                const int b = g * VG + v;
+                take(L::Q1 * ia + b, cx, L::c(b), af[v], ag[v]);
+            }
+        }
+    }
+}
+
 // The whole step of one destination node (x, y) = node n whose time-t frame
 // is (l0, l1, l2), for the energy split S (0: total energy, 1: internal
 // energy, 2: non-translational energy) on lattice L; src is the time-t state
@@ -552,35 +679,9 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0, Eg = 0.0;
 #pragma unroll
             for (int k = 0; k < NM; ++k) Mf[k] = Mg[k] = P(0);
-            // velocity i = Q1 ia + ib has x-component c(ia) and y-component c(ib):
-            // the x-stencil serves the Q1 velocities of one ia
-#pragma unroll 1
-            for (int ia = 0; ia < L::Q1; ++ia) {
-                const double cx = L::c(ia);
-                // departure point x - C_i(lam_bar) dt and its stencil, x then y
-                P wx[NP];
-                const int bx = lagrange<NP>(fma(-sc, cx, xu), wx);
-#pragma unroll 1
-                for (int ib = 0; ib < L::Q1; ++ib) {
-                const int i = L::Q1 * ia + ib;
-                const double cy = L::c(ib);
-                P wy[NP];
-                const int by = lagrange<NP>(fma(-sc, cy, yu), wy);
-                P If[NM], Ig[NM];
-                taps.init(If, Ig);
-                taps.gather(bx, by, wx, wy, If, Ig);
-                // frame transformation of the interpolated moments: population i
-                P B[NM];
-                if constexpr (L::Q == 16)
-                    pop_coeffs(tab.recon[i], dux, duy, is, B);
-                else
-                    pop_coeffs_n<L>(tab.recon[i], dux, duy, is, B);
-                P fi = P(0), gi = P(0);
-#pragma unroll
-                for (int k = 0; k < NM; ++k) {
-                    fi += B[k] * If[k];
-                    gi += B[k] * Ig[k];
-                }
+            // population i of f and g gathered in the iterate frame: the FP64 sums
+            // rho, j, E and the lab moments of the gathered populations
+            auto take = [&](int i, double cx, double cy, P fi, P gi) {
                 // conserved moments in FP64
                 const double fd = double(fi);
                 r += fd;
@@ -604,6 +705,42 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                     Mf[k] += fi * mono[k];
                     Mg[k] += gi * mono[k];
                 }
+            };
+            if constexpr (vel_group<P, L>() > 1) {
+                gather_shared_rows<P, NP, L, vel_group<P, L>()>(taps, tab, xu, yu, sc, dux, duy,
+                                                                 is, take);
+            } else {
+                // velocity i = Q1 ia + ib has x-component c(ia) and y-component c(ib):
+                // the x-stencil serves the Q1 velocities of one ia
+#pragma unroll 1
+                for (int ia = 0; ia < L::Q1; ++ia) {
+                    const double cx = L::c(ia);
+                    // departure point x - C_i(lam_bar) dt and its stencil, x then y
+                    P wx[NP];
+                    const int bx = lagrange<NP>(fma(-sc, cx, xu), wx);
+#pragma unroll 1
+                    for (int ib = 0; ib < L::Q1; ++ib) {
+                        const int i = L::Q1 * ia + ib;
+                        const double cy = L::c(ib);
+                        P wy[NP];
+                        const int by = lagrange<NP>(fma(-sc, cy, yu), wy);
+                        P If[NM], Ig[NM];
+                        taps.init(If, Ig);
+                        taps.gather(bx, by, wx, wy, If, Ig);
+                        // frame transformation of the interpolated moments: population i
+                        P B[NM];
+                        if constexpr (L::Q == 16)
+                            pop_coeffs(tab.recon[i], dux, duy, is, B);
+                        else
+                            pop_coeffs_n<L>(tab.recon[i], dux, duy, is, B);
+                        P fi = P(0), gi = P(0);
+#pragma unroll
+                        for (int k = 0; k < NM; ++k) {
+                            fi += B[k] * If[k];
+                            gi += B[k] * Ig[k];
+                        }
+                        take(i, cx, cy, fi, gi);
+                    }
                 }
             }
             rho = r;

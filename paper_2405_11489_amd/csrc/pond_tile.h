@@ -37,6 +37,43 @@ struct TileTaps {
     GlobalTaps<P, NP, L> glob;
 
     __device__ __forceinline__ void init(P Mf[L::NM], P Mg[L::NM]) const { glob.init(Mf, Mg); }
+    __device__ __forceinline__ P ref_at(int k) const { return glob.ref[k]; }
+
+    // The x-pass over stencil rows r0 .. r0 + n - 1 (see GlobalTaps::rows): from
+    // LDS when the rows' stencil lies in the staged region, else from HBM (the
+    // staged moments are the deviations from the reference node, rounded as
+    // GlobalTaps rounds them, so both give the same bits).
+    template <class Visit>
+    __device__ __forceinline__ void rows(int bx, const P wx[NP], int r0, int n, int seg,
+                                         Visit &visit) const {
+        const bool inside =
+            bx >= X0 && bx + NP - 1 <= X1 && (flat_y || (r0 >= Y0 && r0 + n - 1 <= Y1));
+        if (inside) {
+            constexpr unsigned NB = lds_node_bytes<P, L>();
+            const unsigned rowb = flat_y ? 0u : unsigned(W) * NB;
+            unsigned off = __umul24(unsigned(flat_y ? 0 : r0 - Y0), rowb) +
+                           __umul24(unsigned(bx - X0), NB);
+#pragma unroll 1
+            for (int t = 0; t < n; ++t) {
+                P X[2 * L::NM];
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    if (G > 0 && p > 0 && p % G == 0) asm volatile("" ::: "memory");
+                    P M[nmom_padded<P, L>()];
+                    load_node_lds_at<P, L>(lds, off + unsigned(p) * NB, M);
+#pragma unroll
+                    for (int k = 0; k < 2 * L::NM; ++k)
+                        X[k] = p == 0 ? wx[p] * M[k] : X[k] + wx[p] * M[k];
+                }
+                visit(r0 + t, seg, X);
+                off += rowb;
+            }
+        } else {
+            int bxv = bx;
+            asm volatile("" : "+v"(bxv));
+            glob.rows(bxv, wx, r0, n, seg, visit);
+        }
+    }
 
     // the staged moments are the deviations from the tile's reference node
     __device__ __forceinline__ void gather(int bx, int by, const P wx[NP], const P wy[NP],
@@ -113,7 +150,12 @@ __device__ __forceinline__ int block_min(int v, int *red) {
 template <typename P, int S, int NT = 256, class L = D2Q16>
 constexpr int step_min_waves() {
     if (L::Q != 16) return 1;
-    if (sizeof(P) == 4) return NT == 512 ? 4 : 3;
+    if (sizeof(P) == 4) {
+        // the shared x-pass holds the coefficients and sums of a velocity group
+        // (250 VGPRs with groups of four): two waves
+        if (vel_group<P, L>() > 1) return 2;
+        return NT == 512 ? 4 : 3;
+    }
     return S == 1 ? 2 : 1;
 }
 

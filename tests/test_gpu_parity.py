@@ -297,12 +297,11 @@ def test_512_lane_tiles_bitwise_equal_at_full_size(prec):
 
 
 def test_default_tile_saves_the_partial_round():
-    """Default block shapes on MI355X (256 CUs): FP32 takes the four-wave
-    32 x 16 tile where a grid needs more than one round of three-wave 32 x 8
-    blocks but fits one of 32 x 16 blocks (512^2), FP64 wherever its tiles
-    cover every CU; single rows take 64 x 1."""
+    """Default block shapes on MI355X (256 CUs): FP64 takes the 32 x 16 tile
+    wherever its tiles cover every CU; the FP32 kernels (two waves per SIMD at
+    either block size) keep 32 x 8; single rows take 64 x 1."""
     from paper_2405_11489_amd import pond
-    want = {(512, FP32): pond.TILE_32x16, (1024, FP32): pond.TILE_32x8,
+    want = {(512, FP32): pond.TILE_32x8, (1024, FP32): pond.TILE_32x8,
             (256, FP32): pond.TILE_32x8, (512, FP64): pond.TILE_32x16,
             (1024, FP64): pond.TILE_32x16, (256, FP64): pond.TILE_32x8}
     for (n, prec), tile in want.items():
