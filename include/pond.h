@@ -262,8 +262,8 @@ POND_API pond_status pond_import_prev_frame(pond_ctx *c, const double *prev);
  *              LDS; POND_KERNEL_GLOBAL reads every tap from HBM (reference).
  *   tile:      POND_TILE_* block shape of the tiled kernel (destination nodes).
  *   lds_nodes: LDS capacity per block, in nodes (the 20 moments of a node,
- *              30 on D2Q25, padded against bank conflicts: D2Q16 80 B in FP32,
- *              176 B in FP64; D2Q25 144 B in FP32, 240 B in FP64); taps
+ *              30 on D2Q25: D2Q16 80 B in FP32, 160 B in FP64; D2Q25 128 B
+ *              in FP32 (30 floats and two of padding), 240 B in FP64); taps
  *              outside the staged region read HBM.  At most 159 KiB: one KiB of the CU's 160 stays for
  *              the kernels' static shared memory.
  *   batch_tile_width: tile of this context when it steps inside a pond_batch.

@@ -44,11 +44,11 @@ constexpr int kScratchDoubles = 3 * 256;
 // D2Q25 32 floats or 30 doubles.
 inline int moment_values(int lattice, bool dbl) { return lattice == 25 ? (dbl ? 30 : 32) : 20; }
 
-// Values (float or double) per node of an LDS tile: the moment groups plus the
-// bank padding of the node stride (D2Q16: 20 floats, 22 doubles; D2Q25: 36
-// floats, 30 doubles).
+// Values (float or double) per node of an LDS tile: the moment groups (D2Q16:
+// 20 floats or doubles; D2Q25: 32 floats, 30 doubles; FP32 D2Q16 tiles are
+// node-major, the others grouped planes, neither padded).
 inline int lds_node_values(int lattice, bool dbl) {
-    return lattice == 25 ? (dbl ? 30 : 36) : (dbl ? 22 : 20);
+    return lattice == 25 ? (dbl ? 30 : 32) : 20;
 }
 
 // Ghost rows of the moment planes beyond each wall (bc_y == POND_BC_WALL).

@@ -89,20 +89,27 @@ __device__ __forceinline__ void store_moments(P *__restrict__ base, long long st
     }
 }
 
-// LDS tiles hold the moment groups of a node contiguously (node-major), so
-// every tap and group of a stencil row is reached from one address with
-// immediate offsets.  Node stride, in vectors (float4 / double2): the groups,
-// padded by one where lanes reading neighbouring nodes would otherwise share
-// LDS banks (D2Q25 FP32: 8 -> 9 float4, 144 B; D2Q16 FP64: 10 -> 11 double2,
-// 176 B); D2Q16 FP32 5 float4 (80 B) and D2Q25 FP64 15 double2 (240 B) are
-// conflict-free as they are.
+// LDS tiles of the FP32 D2Q16 kernels hold the moment groups of a node
+// contiguously (node-major, 5 float4 = 80 B per node), so every tap and group of
+// a stencil row is reached from one address with immediate offsets; lanes
+// reading neighbouring nodes then touch disjoint banks (a stride of 20 banks).
+// The per-velocity gather (FP64, D2Q25) stages the region as grouped planes
+// instead: group k of staged node idx at vector k * cap + idx, so the lanes of
+// a wave, which read neighbouring nodes, read neighbouring vectors.  Node-major
+// tiles of those variants either share banks between lanes (D2Q25 FP32, 128 B
+// per node: 161 against 495 MLUPS on the 512^2 Mach-2 modes) or, padded by a
+// group against that, hold fewer nodes (365 MLUPS; FP64 D2Q16 at 512^2: 528
+// against 657).  The staged values are the same in either layout, only their
+// addresses differ.
+template <typename P, class L>
+constexpr bool lds_planar() {
+    return !(sizeof(P) == 4 && L::Q == 16);
+}
+
+// Vectors (float4 / double2) per node of the LDS array: the node's groups.
 template <typename P, class L>
 constexpr int lds_stride() {
-    constexpr int G = MomVec<P, nmom<L>()>::G;
-    if constexpr (sizeof(P) == 4)
-        return L::Q == 25 ? G + 1 : G;
-    else
-        return L::Q == 16 ? G + 1 : G;
+    return MomVec<P, nmom<L>()>::G;
 }
 
 // Bytes of one node in the LDS array.
@@ -153,7 +160,11 @@ __device__ __forceinline__ void load_node_lds_at(const P *lds, unsigned off, P *
 }
 
 template <typename P, class L>
-__device__ __forceinline__ void store_node_lds(P *lds, int idx, const P *M) {
+__device__ __forceinline__ void store_node_lds(P *lds, int idx, int cap, const P *M) {
+    if constexpr (lds_planar<P, L>()) {
+        store_moments<P, nmom<L>()>(lds, cap, idx, M);
+        return;
+    }
     using MV = MomVec<P, nmom<L>()>;
     using V = typename MV::V;
     V *b = reinterpret_cast<V *>(lds) + idx * lds_stride<P, L>();

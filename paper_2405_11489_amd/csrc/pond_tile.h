@@ -46,6 +46,7 @@ struct TileTaps {
     template <class Visit>
     __device__ __forceinline__ void rows(int bx, const P wx[NP], int r0, int n, int seg,
                                          Visit &visit) const {
+        static_assert(!lds_planar<P, L>(), "the shared x-pass reads node-major tiles");
         const bool inside =
             bx >= X0 && bx + NP - 1 <= X1 && (flat_y || (r0 >= Y0 && r0 + n - 1 <= Y1));
         if (inside) {
@@ -80,7 +81,26 @@ struct TileTaps {
                                            P Mf[L::NM], P Mg[L::NM]) const {
         const bool inside =
             bx >= X0 && bx + NP - 1 <= X1 && (flat_y || (by >= Y0 && by + NP - 1 <= Y1));
-        if (inside) {
+        if (inside && lds_planar<P, L>()) {
+            // grouped planes (node idx, group k at vector k * cap + idx)
+            const int rs = flat_y ? 0 : W;
+            const int base = (flat_y ? 0 : by - Y0) * W + (bx - X0);
+#pragma unroll POND_ROW_UNROLL
+            for (int q = 0; q < NP; ++q) {
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    if (G > 0 && p > 0 && p % G == 0) asm volatile("" ::: "memory");
+                    const P Wt = wx[p] * wy[q];
+                    P M[nmom_padded<P, L>()];
+                    load_moments<P, nmom<L>()>(lds, cap, base + q * rs + p, M);
+#pragma unroll
+                    for (int k = 0; k < L::NM; ++k) {
+                        Mf[k] += Wt * M[k];
+                        Mg[k] += Wt * M[L::NM + k];
+                    }
+                }
+            }
+        } else if (inside) {
             // byte offsets: the region is under 2^24 bytes, so the products are
             // 24-bit multiplies (full rate, where 32-bit ones take four cycles)
             constexpr unsigned NB = lds_node_bytes<P, L>();
@@ -268,7 +288,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, DevState src, const
         load_moments<P, nmom<L>()>(mom, a.mstride, a.moff + (long long)gy * a.nx + gx, M);
 #pragma unroll
         for (int k = 0; k < nmom<L>(); ++k) M[k] -= glob.ref[k];
-        store_node_lds<P, L>(lds, idx, M);
+        store_node_lds<P, L>(lds, idx, cap, M);
     }
     __syncthreads();
 

@@ -215,3 +215,13 @@ def test_batch_and_server_reject_d2q25():
             assert ei.value.status == status
     finally:
         pond.pond_server_destroy(srv)
+
+
+def test_default_tile_is_square():
+    """D2Q25 takes 16 x 16 tiles by default (less halo per node than 32 x 8;
+    the tile shape changes no bits: tested above)."""
+    from paper_2405_11489_amd import pond
+    w = modes(64, mach=2.0, amp=1e-3, seed=0, tau=0.55)
+    for prec in (FP32, FP64):
+        with gpu_solver(w, prec, lattice=25) as s:
+            assert pond.pond_get_tuning(s.ctx).tile == pond.TILE_16x16

@@ -317,11 +317,11 @@ def test_default_tile_saves_the_partial_round():
 def test_lds_capacity_beyond_the_cu_refused():
     """LDS capacities whose dynamic share leaves no room for the kernels'
     static shared memory are refused at pond_set_tuning, not at launch (an FP64
-    D2Q16 LDS node takes 176 B: 20 doubles and the bank padding)."""
+    D2Q16 LDS node takes 160 B: its 20 moments)."""
     from paper_2405_11489_amd import pond
     w = modes(16, 12, mach=1.0, seed=3)
     with gpu_solver(w, FP64) as s:
-        pond.pond_set_tuning(s.ctx, tile=pond.TILE_32x8, lds_nodes=159 * 1024 // 176)
+        pond.pond_set_tuning(s.ctx, tile=pond.TILE_32x8, lds_nodes=159 * 1024 // 160)
         s.step(1)
         with pytest.raises(pond.PondError) as e:
             pond.pond_set_tuning(s.ctx, tile=pond.TILE_32x8, lds_nodes=1024)
