@@ -455,7 +455,13 @@ typedef struct {
     int32_t interp_points;     /* 3 or 4, shared by all requests (default 4) */
     int32_t max_members;       /* cap on running requests; <= 0: none (default) */
     int64_t hbm_budget_bytes;  /* admission cap on the summed pond_state_bytes of running
-                                  requests (default 64 GiB) */
+                                  requests (default 64 GiB).  Transient buffers come on
+                                  top of it: one request at a time, the staging of its
+                                  initial fields (4 N doubles, inside its own state
+                                  memory), the state copy of autotune_steps (one state
+                                  buffer) and the export buffer of
+                                  POND_REQ_KEEP_STATE (35 N doubles), each freed before
+                                  the next request is admitted or collected */
     int64_t chunk_steps;       /* batched steps between queue checks; 0: run until the
                                   next request finishes (default 64) */
     int64_t fill_nodes;        /* each round steps the requests with the least remaining
