@@ -436,7 +436,7 @@ def load_workload(name, args, workloads):
 
 
 def measure(pond, torch, w, args, prec, split=0, lattice=16, interp_points=4, tuning=None,
-            replay=True):
+            replay=True, autotune=False):
     """Time K steps (after W warm-up steps) of workload w with HIP events on the
     context stream; then, untimed, restore the state saved before the timed
     region and replay the same K steps with per-launch events for the kernel
@@ -445,6 +445,13 @@ def measure(pond, torch, w, args, prec, split=0, lattice=16, interp_points=4, tu
     sol = pond.Solver.from_workload(w, precision=prec, stream=stream.cuda_stream,
                                     interp_points=interp_points, split=split,
                                     lattice=lattice, pc_tol=args.pc_tol, tuning=tuning)
+    autotuned = False
+    if autotune:
+        # the library's autotuner times its candidate launch configurations on a
+        # copy of the initial state (untimed; every configuration gives the same
+        # bits) and keeps the fastest
+        pond.pond_autotune(sol.ctx, 3)
+        autotuned = True
     tun = pond.pond_get_tuning(sol.ctx)
     sol.step(args.warmup)
     sol.synchronize()
@@ -477,7 +484,8 @@ def measure(pond, torch, w, args, prec, split=0, lattice=16, interp_points=4, tu
     kbar = (st1.pc_iterations - st0.pc_iterations) / updates
     out = {"ms": ms, "wall_s": wall, "mlups": updates / (ms * 1e-3) / 1e6, "kbar": kbar,
            "nonconverged": st1.nonconverged - st0.nonconverged,
-           "nonphysical": int(st1.nonphysical), "tuning": tun, "updates": updates}
+           "nonphysical": int(st1.nonphysical), "tuning": tun, "updates": updates,
+           "autotuned": autotuned}
     if replay:
         pond.pond_import_state(sol.ctx, *saved)
         del saved
@@ -616,7 +624,9 @@ def main():
                     help="serve: arrival rate / plain capacity (<= 0: every request queued at "
                          "t = 0)")
     ap.add_argument("--dump", default=None, help="serve: write per-request records (JSON) here")
-    ap.add_argument("--no-autotune", action="store_true", help="batch: default tiles, no autotuning")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="default tiles, no autotuning (single instances: the library's "
+                         "default launch configuration; batch: default tile widths)")
     ap.add_argument("--fill-nodes", type=int, default=None,
                     help="serve: server fill_nodes (0 = step every admitted request each round)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -646,6 +656,9 @@ def main():
         tuning["lds_nodes"] = 0  # the tile's default unless given
     if args.lds_nodes is not None:
         tuning["lds_nodes"] = args.lds_nodes
+    # the launch configuration is autotuned unless one is given
+    autotune = (not args.no_autotune and args.tile is None and args.lds_nodes is None
+                and args.kernel == "tiled")
     split = {"total": pond.SPLIT_TOTAL, "internal": pond.SPLIT_INTERNAL,
              "nontrans": pond.SPLIT_NONTRANS}[args.split]
 
@@ -654,7 +667,8 @@ def main():
         w.prandtl = 1.0
     log(f"workload {w.name} {w.nx}x{w.ny}, {args.precision}, {args.split} split, "
         f"warmup {args.warmup}, steps {args.steps}")
-    m = measure(pond, torch, w, args, prec, split, args.lattice, args.interp_points, tuning)
+    m = measure(pond, torch, w, args, prec, split, args.lattice, args.interp_points, tuning,
+                autotune=autotune)
     kname = kernel_name(m, args.precision, args.interp_points, split, args.lattice, args.kernel)
     roof = roofline(m, w.nodes, args.precision, args.interp_points, args.lattice, split, kname,
                     traffic_record(kname, args.precision, wname))
@@ -683,7 +697,8 @@ def main():
         # the 512^2 Mach-2 modes workload, same K and W
         a2 = argparse.Namespace(**vars(args))
         w2, wname2, _ = load_workload("modes512", a2, workloads)
-        m2 = measure(pond, torch, w2, args, prec, split, args.lattice, args.interp_points, tuning)
+        m2 = measure(pond, torch, w2, args, prec, split, args.lattice, args.interp_points, tuning,
+                     autotune=autotune)
         kname2 = kernel_name(m2, args.precision, args.interp_points, split, args.lattice,
                              args.kernel)
         r2 = roofline(m2, w2.nodes, args.precision, args.interp_points, args.lattice, split,
@@ -749,7 +764,10 @@ def main():
                    "split": args.split, "lattice": args.lattice,
                    "parallelism": "single_gpu"},
         "tuning": {"kernel": args.kernel, "tile": m["tuning"].tile,
-                   "lds_nodes": m["tuning"].lds_nodes},
+                   "tile_dims": TILE_DIMS[m["tuning"].tile],
+                   "lds_nodes": m["tuning"].lds_nodes, "autotuned": m["autotuned"],
+                   "how": "pond_autotune over the library's candidate tiles and LDS shares "
+                          "before the warm-up, untimed" if m["autotuned"] else "library default"},
         "pc_iterations_mean": m["kbar"],
         "nonconverged_node_steps": m["nonconverged"],
         "nonphysical": m["nonphysical"],
