@@ -84,10 +84,33 @@ CANON_BYTES_FP64 = 2 * (256 + 24)
 # iteration departure points 175, interpolation 25 x NP^2 x (1 + 15 x 4),
 # transformation 25 x 2 x 85 (30 FMAs and the shared order-4 shift/scale);
 # once per node 1850 + 250 + 80 + 1500 + 1850.
-def flops_per_iter(np_, q=16):
+def flops_per_iter(np_, q=16, shared_rows=None):
+    """Per predictor-corrector gather.  shared_rows: the FP32 D2Q16 kernel's
+    mean rows per x-pass (the union of the four row stencils of an
+    x-component, see shared_rows_mean); per x-component it interpolates that
+    many rows along x (NP taps x 20 moments, FMA), and each velocity takes its
+    NP rows through its coefficients (20 FMA + 1 per row); per velocity the
+    coefficients (45) and the transformed reference moments (2 x 20 FMA)."""
     if q == 25:
         return 175 + 25 * np_ * np_ * 61 + 4250
+    if shared_rows is not None:
+        return 112 + 4 * (shared_rows * np_ * 20 * 2) + 16 * np_ * 21 * 2 + 16 * (45 + 80)
     return 112 + 16 * np_ * np_ * 41 + 2080
+
+
+def shared_rows_mean(w, np_=4):
+    """Mean rows per x-pass of the shared gather over the workload's initial
+    frames: the union of the row stencils of the four y-departures
+    y - u_y - sqrt(T) c_b (cubic: floor - 1 .. floor + 2), or the four separate
+    stencils (4 NP rows) where the union is longer."""
+    c_out = 2.3344142183389773
+    yy = np.arange(w.ny, dtype=np.float64)[:, None] - w.uy
+    s = np.sqrt(w.T)
+    if np_ == 4:
+        span = np.floor(yy + s * c_out) - np.floor(yy - s * c_out) + 4
+    else:
+        span = np.floor(yy + s * c_out + 0.5) - np.floor(yy - s * c_out + 0.5) + 3
+    return float(np.mean(np.minimum(span, 4 * np_)))
 
 
 def flops_per_node(q=16):
@@ -505,12 +528,12 @@ def measure(pond, torch, w, args, prec, split=0, lattice=16, interp_points=4, tu
     return out
 
 
-def roofline(m, N, prec, interp_points, lattice, split, kname, traffic):
+def roofline(m, N, prec, interp_points, lattice, split, kname, traffic, shared_rows=None):
     """Roofline of the step kernel from the replayed per-launch duration."""
     t = m["step_kernel_ms"] * 1e-3
     k = m["kbar"]
-    own = N * (flops_per_iter(interp_points, lattice) * k + flops_per_node(lattice) +
-               (FLOPS_SOURCE_PER_NODE if split == 1 else 0))
+    own = N * (flops_per_iter(interp_points, lattice, shared_rows) * k +
+               flops_per_node(lattice) + (FLOPS_SOURCE_PER_NODE if split == 1 else 0))
     if prec == "fp32":
         f32 = N * (CANON_F32_PER_NODE + CANON_F32_PER_ITER * k)
         f64 = N * (CANON_F64_PER_NODE + CANON_F64_PER_ITER * k)
@@ -539,6 +562,7 @@ def roofline(m, N, prec, interp_points, lattice, split, kname, traffic):
             "hbm_GBs_algorithmic": N * canon_bytes / t / 1e9,
             "hbm_frac": N * canon_bytes / t / 1e9 / PEAK_HBM_GBS,
             "own_count": {"flops_per_launch": own, "achieved": own / t / 1e12,
+                          "shared_rows_mean": shared_rows,
                           "frac": own / t / 1e12 / own_peak,
                           "hbm_bytes_per_launch": N * own_bytes},
             **extra}
@@ -670,8 +694,10 @@ def main():
     m = measure(pond, torch, w, args, prec, split, args.lattice, args.interp_points, tuning,
                 autotune=autotune)
     kname = kernel_name(m, args.precision, args.interp_points, split, args.lattice, args.kernel)
+    shared = (shared_rows_mean(w, args.interp_points)
+              if args.precision == "fp32" and args.lattice == 16 else None)
     roof = roofline(m, w.nodes, args.precision, args.interp_points, args.lattice, split, kname,
-                    traffic_record(kname, args.precision, wname))
+                    traffic_record(kname, args.precision, wname), shared)
     log(f"time {m['ms']:.1f} ms (host {m['wall_s'] * 1e3:.1f} ms), {m['mlups']:.1f} MLUPS, "
         f"K {m['kbar']:.3f}, step kernel {m['step_kernel_ms']:.4f} ms per launch (replay), "
         f"roofline {roof['frac']:.3f} of {roof['peak']} TFLOP/s")
@@ -701,8 +727,10 @@ def main():
                      autotune=autotune)
         kname2 = kernel_name(m2, args.precision, args.interp_points, split, args.lattice,
                              args.kernel)
+        shared2 = (shared_rows_mean(w2, args.interp_points)
+                   if args.precision == "fp32" and args.lattice == 16 else None)
         r2 = roofline(m2, w2.nodes, args.precision, args.interp_points, args.lattice, split,
-                      kname2, traffic_record(kname2, args.precision, wname2))
+                      kname2, traffic_record(kname2, args.precision, wname2), shared2)
         extras["mach2_fourier_modes_512x512"] = {
             "value": m2["mlups"], "unit": "MLUPS", "ms_per_step": m2["ms"] / args.steps,
             "pc_iterations_mean": m2["kbar"], "kernel": kname2,

@@ -418,7 +418,8 @@ POND_API pond_status pond_batch_destroy(pond_batch *b);
 
 /* Autotuner: time at least `steps` (>= 1) steps and 2 ms of device time of c
  * with each candidate tile shape and LDS capacity of the single-context
- * kernel and each candidate batch tile width (one-member batches), in two
+ * kernel and each candidate batch tile width (one-member batches; D2Q16
+ * only, the lattice batches run), in two
  * interleaved rounds, restoring c's state, step count and counters after
  * every candidate.  A candidate replaces the default only when more than 3 %
  * faster.  Applies the result to c, stores it for c's class (precision,

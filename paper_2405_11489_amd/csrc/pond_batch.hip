@@ -610,6 +610,8 @@ pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out) {
             if (tiles[i] == tiles[0]) tiles.erase(tiles.begin() + long(i--));
         widths = dbl ? std::vector<int>{16, 32, 64} : std::vector<int>{32, 16, 64};
     }
+    // batches run D2Q16 only: other lattices keep the width they have
+    if (c->p.lattice != POND_LATTICE_D2Q16) widths = {c->tuning.batch_tile_width};
     Saved sv;
     s = save_state(c, sv);
     // two interleaved rounds; each candidate keeps its faster measurement

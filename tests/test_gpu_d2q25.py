@@ -225,3 +225,19 @@ def test_default_tile_is_square():
     for prec in (FP32, FP64):
         with gpu_solver(w, prec, lattice=25) as s:
             assert pond.pond_get_tuning(s.ctx).tile == pond.TILE_16x16
+
+
+def test_autotune_on_d2q25():
+    """The autotuner times D2Q25 tiles (batches, D2Q16 only, are left out) and
+    leaves the state as it was."""
+    from paper_2405_11489_amd import pond
+    pond.pond_tuning_cache_clear()
+    w = modes(48, 40, mach=1.0, amp=1e-2, seed=9)
+    with gpu_solver(w, FP32, lattice=25) as s:
+        s.step(1)
+        before = s.export_state()
+        t = pond.pond_autotune(s.ctx, 1)
+        assert t.kernel == pond.KERNEL_TILED
+        for x, y in zip(s.export_state()[:3], before[:3]):
+            np.testing.assert_array_equal(x, y)
+    pond.pond_tuning_cache_clear()
