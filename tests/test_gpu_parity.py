@@ -355,3 +355,40 @@ def test_fp32_convergence_test_stops_at_the_energy_resolution():
         m64 = s.moments()
     errs = field_errors(m32, m64)
     assert max(errs.values()) <= 1e-5, errs
+
+
+def _hot_flow(n=24, ny=20, seed=31):
+    """A flow whose temperature spans 5 .. 9 along y: the FP32 kernel's four
+    row stencils of an x-component span more than 16 rows where T > ~6.6
+    (each velocity then visits its own rows) and fewer elsewhere (the shared
+    x-pass), so waves mix both paths."""
+    w = modes(n, ny, mach=0.5, amp=1e-2, seed=seed, T0=7.0)
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    w.T = w.T * (1.0 + (2.0 / 7.0) * np.sin(2 * math.pi * y / ny) * np.ones((1, n)))
+    return w
+
+
+def test_fp32_hot_flow_rows_per_velocity_within_1e5():
+    """Where the row stencils of an x-component spread beyond 16 rows the FP32
+    gather takes each velocity's rows on their own: within 1e-5 of the oracle."""
+    w = _hot_flow()
+    assert float(np.max(w.T)) > 8.0 and float(np.min(w.T)) < 5.5
+    _, _, _, _, st, m = gpu_run(w, FP32, 4)
+    P, s, ost = oracle_run(w, 4)
+    assert st.nonphysical == 0 and ost.nonphysical == 0
+    errs = field_errors(m, oracle.moments(P, s))
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_fp32_hot_flow_kernels_bitwise_equal():
+    """The same hot flow through the HBM-tap kernel and every tile shape: the
+    rows-per-velocity and shared paths give the same bits everywhere."""
+    from paper_2405_11489_amd import pond
+    w = _hot_flow(40, 36, seed=32)
+    ref = gpu_run(w, FP32, 3, tuning={"kernel": pond.KERNEL_GLOBAL})
+    for tile, cap in [(pond.TILE_32x8, 0), (pond.TILE_16x16, 0), (pond.TILE_8x8, 0),
+                      (pond.TILE_8x8, 100), (pond.TILE_32x16, 0)]:
+        out = gpu_run(w, FP32, 3, tuning={"kernel": pond.KERNEL_TILED, "tile": tile,
+                                          "lds_nodes": cap})
+        for x, y in zip(out[:3], ref[:3]):
+            np.testing.assert_array_equal(x, y, err_msg=f"tile {tile} cap {cap}")
