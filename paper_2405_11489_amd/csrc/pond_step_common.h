@@ -529,6 +529,12 @@ __device__ __forceinline__ void source_gradient(const StepArgs &a, const DevStat
     for (int k = 0; k < 4; ++k) g[k] = 2.0 * ga[k] - gb[k];
 }
 
+// FP32 D2Q25 shares its x-pass too (gather_shared_rows_transformed; 0: the
+// per-velocity gather).
+#ifndef POND_D2Q25_SHARED
+#define POND_D2Q25_SHARED 1
+#endif
+
 // Velocities per shared x-pass of the FP32 D2Q16 gather (4: the Q1 velocities
 // of one x-component; 2: half of them; 1: no sharing, every velocity gathers its
 // own NP x NP taps).  FP64 and D2Q25 gather per velocity.
@@ -627,6 +633,97 @@ __device__ __forceinline__ void gather_shared_rows(const Taps &taps, const Veloc
     }
 }
 
+// D2Q25 in FP32 shares the x-pass between the five velocities of an
+// x-component too, in a form that holds no per-velocity coefficients (their 75
+// registers do not fit beside the 30-moment rows): each row of the union of the
+// row stencils is interpolated along x once and turned into the normalised
+// central moments of the iterate frame once (central_normalised_n: a linear
+// map, so it commutes with the row weights), and each velocity whose stencil
+// holds the row adds its row weight times the reconstruction weights (the
+// lattice tables, uniform across lanes) dotted with those moments.  The sums
+// start at the reference moments in the same frame.
+template <typename P, class L>
+constexpr bool shared_rows_transformed() {
+    return L::Q == 25 && sizeof(P) == 4 && POND_D2Q25_SHARED != 0;
+}
+
+template <typename P, int NP, class L, class Taps, class Tab, class Take>
+__device__ __forceinline__ void gather_shared_rows_transformed(const Taps &taps, const Tab &tab,
+                                                               double xu, double yu, double sc,
+                                                               P dux, P duy, P is, Take &take) {
+    constexpr int NM = L::NM, Q1 = L::Q1;
+    // the reference moments in the iterate frame (f, then g)
+    P Rf[NM], Rg[NM];
+    {
+        P A[NM];
+#pragma unroll
+        for (int k = 0; k < NM; ++k) A[k] = taps.ref_at(k);
+        central_normalised_n<L>(A, dux, duy, is, Rf);
+#pragma unroll
+        for (int k = 0; k < NM; ++k) A[k] = taps.ref_at(NM + k);
+        central_normalised_n<L>(A, dux, duy, is, Rg);
+    }
+#pragma unroll 1
+    for (int ia = 0; ia < Q1; ++ia) {
+        const double cx = L::c(ia);
+        P wx[NP];
+        const int bx = lagrange<NP>(fma(-sc, cx, xu), wx);
+        int by[Q1];
+        P wq[Q1][NP];  // row weights, consumed first to last
+        P af[Q1], ag[Q1];
+#pragma unroll
+        for (int b = 0; b < Q1; ++b) {
+            by[b] = lagrange<NP>(fma(-sc, L::c(b), yu), wq[b]);
+            const P *r = tab.recon[Q1 * ia + b];
+            P sf = P(0), sg = P(0);
+#pragma unroll
+            for (int k = 0; k < NM; ++k) {
+                sf += r[k] * Rf[k];
+                sg += r[k] * Rg[k];
+            }
+            af[b] = sf;
+            ag[b] = sg;
+        }
+        auto visit = [&](int row, int seg, const P (&X)[2 * NM]) {
+            P Zf[NM], Zg[NM];
+            central_normalised_n<L>(X, dux, duy, is, Zf);
+            central_normalised_n<L>(X + NM, dux, duy, is, Zg);
+#pragma unroll
+            for (int b = 0; b < Q1; ++b) {
+                const bool mine = seg < 0 ? unsigned(row - by[b]) < unsigned(NP) : seg == b;
+                if (mine) {
+                    const P w = wq[b][0];
+#pragma unroll
+                    for (int q = 0; q + 1 < NP; ++q) wq[b][q] = wq[b][q + 1];
+                    const P *r = tab.recon[Q1 * ia + b];
+                    P df = P(0), dg = P(0);
+#pragma unroll
+                    for (int k = 0; k < NM; ++k) {
+                        df += r[k] * Zf[k];
+                        dg += r[k] * Zg[k];
+                    }
+                    af[b] += w * df;
+                    ag[b] += w * dg;
+                }
+            }
+        };
+        const int span = by[0] - by[Q1 - 1] + NP;
+        if (span <= Q1 * NP) {
+            taps.rows(bx, wx, by[Q1 - 1], span, -1, visit);
+        } else {
+#pragma unroll 1
+            for (int b = 0; b < Q1; ++b) {
+                int r0 = by[0];
+#pragma unroll
+                for (int u = 1; u < Q1; ++u) r0 = b == u ? by[u] : r0;
+                taps.rows(bx, wx, r0, NP, b, visit);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < Q1; ++b) take(Q1 * ia + b, cx, L::c(b), af[b], ag[b]);
+    }
+}
+
 // The whole step of one destination node (x, y) = node n whose time-t frame
 // is (l0, l1, l2), for the energy split S (0: total energy, 1: internal
 // energy, 2: non-translational energy) on lattice L; src is the time-t state
@@ -720,6 +817,9 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             if constexpr (vel_group<P, L>() > 1) {
                 gather_shared_rows<P, NP, L, vel_group<P, L>()>(taps, tab, xu, yu, sc, dux, duy,
                                                                  is, take);
+            } else if constexpr (shared_rows_transformed<P, L>()) {
+                gather_shared_rows_transformed<P, NP, L>(taps, tab, xu, yu, sc, dux, duy, is,
+                                                         take);
             } else {
                 // velocity i = Q1 ia + ib has x-component c(ia) and y-component c(ib):
                 // the x-stencil serves the Q1 velocities of one ia

@@ -19,6 +19,10 @@
 #define POND_TAP_GROUP_F64 1
 #endif
 
+#ifndef POND_D2Q25_SHARED_WAVES
+#define POND_D2Q25_SHARED_WAVES 2
+#endif
+
 namespace pond {
 
 // Tap source of a tile: the moments of the block's source region (unwrapped
@@ -46,10 +50,44 @@ struct TileTaps {
     template <class Visit>
     __device__ __forceinline__ void rows(int bx, const P wx[NP], int r0, int n, int seg,
                                          Visit &visit) const {
-        static_assert(!lds_planar<P, L>(), "the shared x-pass reads node-major tiles");
         const bool inside =
             bx >= X0 && bx + NP - 1 <= X1 && (flat_y || (r0 >= Y0 && r0 + n - 1 <= Y1));
-        if (inside) {
+        if (inside && lds_planar<P, L>()) {
+            // grouped planes: group k of node idx at vector k * cap + idx, so the NP
+            // taps of a row are consecutive vectors of each group plane
+            using MV = MomVec<P, nmom<L>()>;
+            using V = typename MV::V;
+            const int rs = flat_y ? 0 : W;
+            int idx = (flat_y ? 0 : r0 - Y0) * W + (bx - X0);
+#pragma unroll 1
+            for (int t = 0; t < n; ++t) {
+                const V *b = reinterpret_cast<const V *>(lds) + idx;
+                P X[2 * L::NM];
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    if (G > 0 && p > 0 && p % G == 0) asm volatile("" ::: "memory");
+                    P M[nmom_padded<P, L>()];
+#pragma unroll
+                    for (int k = 0; k < MV::G; ++k) {
+                        const V v = b[k * cap + p];
+                        if constexpr (MV::W == 4) {
+                            M[4 * k] = v.x;
+                            M[4 * k + 1] = v.y;
+                            M[4 * k + 2] = v.z;
+                            M[4 * k + 3] = v.w;
+                        } else {
+                            M[2 * k] = v.x;
+                            M[2 * k + 1] = v.y;
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 2 * L::NM; ++k)
+                        X[k] = p == 0 ? wx[p] * M[k] : X[k] + wx[p] * M[k];
+                }
+                visit(r0 + t, seg, X);
+                idx += rs;
+            }
+        } else if (inside) {
             constexpr unsigned NB = lds_node_bytes<P, L>();
             const unsigned rowb = flat_y ? 0u : unsigned(W) * NB;
             unsigned off = __umul24(unsigned(flat_y ? 0 : r0 - Y0), rowb) +
@@ -169,7 +207,7 @@ __device__ __forceinline__ int block_min(int v, int *red) {
 // the compiler's choice (two waves in FP32, one in FP64: more would spill).
 template <typename P, int S, int NT = 256, class L = D2Q16>
 constexpr int step_min_waves() {
-    if (L::Q != 16) return 1;
+    if (L::Q != 16) return shared_rows_transformed<P, L>() ? POND_D2Q25_SHARED_WAVES : 1;
     if (sizeof(P) == 4) {
         // the shared x-pass holds the coefficients and sums of a velocity group
         // (250 VGPRs with groups of four): two waves
