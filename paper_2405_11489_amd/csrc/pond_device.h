@@ -282,23 +282,25 @@ __device__ __forceinline__ void central_normalised_n(const P M[L::NM], P dx, P d
         ey[j] = ey[j - 1] * (-dy);
         sc[j] = sc[j - 1] * is;
     }
-    // shift in x: T[p][t] = sum_r C(p,r) ex^(p-r) M[r][t]
+    // shift in x: T[p][t] = sum_r C(p,r) ex^(p-r) M[r][t]; each sum starts at
+    // its unit term (r = p), so it takes p multiply-adds
     P T[L::NM];
 #pragma unroll
     for (int k = 0; k < L::NM; ++k) {
         const int p = mom_px(k), t = mom_py(k);
-        P acc = P(0);
+        P acc = M[k];
 #pragma unroll
-        for (int r = 0; r <= p; ++r) acc += P(binom_c(p, r)) * ex[p - r] * M[mom_index(r, t)];
+        for (int r = p - 1; r >= 0; --r) acc += (P(binom_c(p, r)) * ex[p - r]) * M[mom_index(r, t)];
         T[k] = acc;
     }
+    // shift in y, then the scale is^(p+q)
 #pragma unroll
     for (int k = 0; k < L::NM; ++k) {
         const int p = mom_px(k), q = mom_py(k);
-        P acc = P(0);
+        P acc = T[k];
 #pragma unroll
-        for (int t = 0; t <= q; ++t) acc += P(binom_c(q, t)) * ey[q - t] * T[mom_index(p, t)];
-        m[k] = acc * sc[p + q];
+        for (int t = q - 1; t >= 0; --t) acc += (P(binom_c(q, t)) * ey[q - t]) * T[mom_index(p, t)];
+        m[k] = p + q == 0 ? acc : acc * sc[p + q];
     }
 }
 

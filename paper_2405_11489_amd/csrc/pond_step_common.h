@@ -73,6 +73,60 @@ __device__ __forceinline__ void load_moments(const P *__restrict__ base, long lo
     }
 }
 
+// Stores of the step's outputs in HBM.  This step never reads what it writes,
+// so they may stream past the caches (non-temporal stores), leaving L2 to the
+// halo moments that neighbouring tiles re-read.  POND_STREAM_STORE is a mask
+// of the streams stored that way: 1 the populations, 2 the frame, 4 the
+// moment planes.  Off by default: on the 2048^2 quadrants streaming the moment
+// planes (and the frame) cut the read bytes by 3 % (7.5 %) at the same step
+// time, and streamed population stores (one dword per lane) raised the written
+// bytes by half and slowed the step.
+#ifndef POND_STREAM_STORE
+#define POND_STREAM_STORE 0
+#endif
+typedef float pond_f4v __attribute__((ext_vector_type(4)));
+typedef double pond_d2v __attribute__((ext_vector_type(2)));
+
+template <int Stream, typename T>
+__device__ __forceinline__ void out_store(T *p, T v) {
+    if constexpr ((POND_STREAM_STORE & Stream) != 0)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+template <int Stream>
+__device__ __forceinline__ void out_store(float4 *p, float4 v) {
+    if constexpr ((POND_STREAM_STORE & Stream) != 0)
+        __builtin_nontemporal_store(pond_f4v{v.x, v.y, v.z, v.w}, reinterpret_cast<pond_f4v *>(p));
+    else
+        *p = v;
+}
+template <int Stream>
+__device__ __forceinline__ void out_store(double2 *p, double2 v) {
+    if constexpr ((POND_STREAM_STORE & Stream) != 0)
+        __builtin_nontemporal_store(pond_d2v{v.x, v.y}, reinterpret_cast<pond_d2v *>(p));
+    else
+        *p = v;
+}
+constexpr int kStreamPops = 1, kStreamFrame = 2, kStreamMoments = 4;
+
+template <typename P, int NMOM = kNMom>
+__device__ __forceinline__ void store_moments_out(P *__restrict__ base, long long stride,
+                                                  long long idx, const P *M) {
+    using MV = MomVec<P, NMOM>;
+    using V = typename MV::V;
+    V *b = reinterpret_cast<V *>(base);
+    if constexpr (MV::W == 4) {
+#pragma unroll
+        for (int k = 0; k < MV::G; ++k)
+            out_store<kStreamMoments>(&b[k * stride + idx],
+                                      V{M[4 * k], M[4 * k + 1], M[4 * k + 2], M[4 * k + 3]});
+    } else {
+#pragma unroll
+        for (int k = 0; k < MV::G; ++k) out_store<kStreamMoments>(&b[k * stride + idx], V{M[2 * k], M[2 * k + 1]});
+    }
+}
+
 template <typename P, int NMOM = kNMom>
 __device__ __forceinline__ void store_moments(P *__restrict__ base, long long stride,
                                               long long idx, const P *M) {
@@ -695,7 +749,13 @@ __device__ __forceinline__ void gather_shared_rows_transformed(const Taps &taps,
                     const P w = wq[b][0];
 #pragma unroll
                     for (int q = 0; q + 1 < NP; ++q) wq[b][q] = wq[b][q + 1];
-                    const P *r = tab.recon[Q1 * ia + b];
+                    // the velocity's weights are read from the constant table at
+                    // each visit (a scalar load): the x-component's 75 weights held
+                    // across the row loop would not fit the scalar registers and
+                    // would be spilled into vector-register lanes
+                    int row_tab = Q1 * ia + b;
+                    asm volatile("" : "+s"(row_tab));
+                    const P *r = tab.recon[row_tab];
                     P df = P(0), dg = P(0);
 #pragma unroll
                     for (int k = 0; k < NM; ++k) {
@@ -1027,8 +1087,8 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                 gv -= src_w * ft * (ex * (ax + Cx * gxx + Cy * gyx) + ey * (ay + Cx * gxy + Cy * gyy));
             }
             if (bad) fv = gv = P(NAN);
-            pop_plane<P>(dst.f, i, a.N)[n] = fv;
-            pop_plane<P>(dst.g, i, a.N)[n] = gv;
+            out_store<kStreamPops>(&pop_plane<P>(dst.f, i, a.N)[n], fv);
+            out_store<kStreamPops>(&pop_plane<P>(dst.g, i, a.N)[n], gv);
             const P Vx = sM * P(L::c(i / L::Q1)) + dxM, Vy = sM * P(L::c(i % L::Q1)) + dyM;
             P mono[NM];
             node_monomials<L>(Vx, Vy, mono);
@@ -1042,16 +1102,16 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
         }
         MM[0] = P(mass);
         MM[NM] = P(gzero);
-        dst.ux[n] = uxst;
-        dst.uy[n] = uyst;
-        dst.T[n] = Tst;
+        out_store<kStreamFrame>(&dst.ux[n], uxst);
+        out_store<kStreamFrame>(&dst.uy[n], uyst);
+        out_store<kStreamFrame>(&dst.T[n], Tst);
         if constexpr (S == 1) {
             // the time-t frame becomes the new state's previous level (read again
             // rather than kept live across the loop)
-            dst.uxp[n] = src.ux[n];
-            dst.uyp[n] = src.uy[n];
+            out_store<kStreamFrame>(&dst.uxp[n], src.ux[n]);
+            out_store<kStreamFrame>(&dst.uyp[n], src.uy[n]);
         }
-        store_moments<P, nmom<L>()>(mom_out, a.mstride, a.moff + n, MM);
+        store_moments_out<P, nmom<L>()>(mom_out, a.mstride, a.moff + n, MM);
     }
 
     // counters: one atomic per wave
