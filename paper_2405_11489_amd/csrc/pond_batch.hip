@@ -1,13 +1,14 @@
 // pond_batch.hip -- many PonD instances advanced together, and the tile-shape
 // autotuner.
 //
-// A batch steps its member contexts with two launches per step for all of
-// them at once, replayed from captured HIP graphs:
-//   1. a flat moment pre-pass over every member's nodes (each 256-node block
-//      belongs to one member);
-//   2. one step launch over the flat list of every member's tiles, one block
-//      per tile; the hardware dispatcher balances the tiles over the CUs, and
-//      the block -> tile map gives each XCD a contiguous range of the list.
+// A batch steps its member contexts with one launch per step for all of them
+// at once, replayed from captured HIP graphs: one step launch over the flat
+// list of every member's tiles, one block per tile; the hardware dispatcher
+// balances the tiles over the CUs, and the block -> tile map gives each XCD a
+// contiguous range of the list.  The step writes the moments the next step
+// reads; a flat moment pre-pass over every member's nodes (each 256-node block
+// belongs to one member) runs only where a member's moments are stale (after
+// its initialisation or an import).
 // Which of a member's two state buffers is current alternates every step;
 // the launches take that parity as an argument, so the batch keeps one graph
 // per starting parity and needs no device-side step counter.

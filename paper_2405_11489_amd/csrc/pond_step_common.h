@@ -612,6 +612,15 @@ constexpr int vel_group() {
 // longer than the separate stencils (hot flows), each velocity's rows are
 // visited on their own; the sums are the same either way.  take(i, cx, cy, f_i,
 // g_i) receives each gathered population pair.
+//
+// The populations handed over are those of the interpolated deviations from
+// the reference moments only: the reference's own share, B_i . M_ref, is the
+// same reconstruction of one moment vector for every velocity, and the
+// reconstruction keeps the moments up to order three (the quadrature is exact
+// to degree seven), so its share of every sum that take forms -- mass,
+// momentum, energy, the lab moments -- follows from M_ref itself; the caller
+// adds it once after the gather.  (The share then enters the sums exactly,
+// with no rounding of the coefficients B_i.)
 template <typename P, int NP, class L, int VG, class Taps, class Take>
 __device__ __forceinline__ void gather_shared_rows(const Taps &taps, const VelocityTablesP<P> &tab,
                                                    double xu, double yu, double sc, P dux, P duy,
@@ -637,15 +646,7 @@ __device__ __forceinline__ void gather_shared_rows(const Taps &taps, const Veloc
                 const int b = g * VG + v;
                 by[v] = lagrange<NP>(fma(-sc, L::c(b), yu), wq[v]);
                 pop_coeffs(tab.recon[L::Q1 * ia + b], dux, duy, is, B[v]);
-                // the sums start at the transformed reference moments
-                P sf = P(0), sg = P(0);
-#pragma unroll
-                for (int k = 0; k < NM; ++k) {
-                    sf += B[v][k] * taps.ref_at(k);
-                    sg += B[v][k] * taps.ref_at(NM + k);
-                }
-                af[v] = sf;
-                ag[v] = sg;
+                af[v] = ag[v] = P(0);
             }
             auto visit = [&](int r, int seg, const P (&X)[2 * NM]) {
 #pragma unroll
@@ -877,6 +878,27 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             if constexpr (vel_group<P, L>() > 1) {
                 gather_shared_rows<P, NP, L, vel_group<P, L>()>(taps, tab, xu, yu, sc, dux, duy,
                                                                  is, take);
+                // the reference moments' share of the sums (moments about u_ref;
+                // the lab velocity is V + u_ref), added once after the deviations'
+                const double m00 = double(taps.ref_at(0));
+                const double m10 = double(taps.ref_at(mom_index(1, 0)));
+                const double m01 = double(taps.ref_at(mom_index(0, 1)));
+                r += m00;
+                jx += m10 + a.uref_x * m00;
+                jy += m01 + a.uref_y * m00;
+                E += double(taps.ref_at(NM));
+                if constexpr (S == 2) {
+                    Eg += double(taps.ref_at(NM));
+                    const double m20 = double(taps.ref_at(mom_index(2, 0)));
+                    const double m02 = double(taps.ref_at(mom_index(0, 2)));
+                    E += 0.5 * (m20 + m02) + a.uref_x * m10 + a.uref_y * m01 +
+                         0.5 * (a.uref_x * a.uref_x + a.uref_y * a.uref_y) * m00;
+                }
+#pragma unroll
+                for (int k = 0; k < NM; ++k) {
+                    Mf[k] += taps.ref_at(k);
+                    Mg[k] += taps.ref_at(NM + k);
+                }
             } else if constexpr (shared_rows_transformed<P, L>()) {
                 gather_shared_rows_transformed<P, NP, L>(taps, tab, xu, yu, sc, dux, duy, is,
                                                          take);
