@@ -126,9 +126,10 @@ __global__ __launch_bounds__(TX *TY) POND_TILED_ATTR(P, S, TX *TY, L) void step_
                                                             DevCounters *cnt, int cap, int tiles_x) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int red[4 * red_slots<TX * TY>()];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    int tx, ty;
+    band_tile<TX>(xcd_tile(blockIdx.x, gridDim.x), tiles_x, int(gridDim.x) / tiles_x, tx, ty);
     tile_step<P, NP, S, L>(a, src, mom, dst, mom_out, cnt, reinterpret_cast<P *>(smem_raw), cap,
-                           (tile % tiles_x) * TX, (tile / tiles_x) * TY, FixedShape<TX, TY>{}, red);
+                           tx * TX, ty * TY, FixedShape<TX, TY>{}, red);
 }
 
 // ------------------------------------------------------ wall ghosts ----

@@ -225,6 +225,42 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return x * q + (x < r ? x : r) + b / 8;
 }
 
+// Order of the tiles within the range: column bands about POND_BAND_NODES
+// nodes wide (0: plain row-major order), each walked row by row.  The blocks an
+// XCD holds at once take consecutive tiles, so in row-major order they form a
+// strip one tile high across the grid (8 x 2048 nodes for 8 x 8 tiles on
+// 2048^2), whose source region carries halo rows above and below every tile;
+// in a band they form a square of about POND_BAND_NODES^2 nodes, whose halo is
+// only its perimeter.  (The halo rows shared with the previous set of tiles are
+// gone from L2 by then either way: each set writes more than L2 holds.)  Off by
+// default: on the 2048^2 quadrants bands of 128 (256) nodes cut the step's HBM
+// reads by 21 % (25 %) but lengthened it by 6 % (a band's set of tiles spans
+// 128 rows of every plane where a strip spans 8); on 512^2 the order made no
+// difference.
+#ifndef POND_BAND_NODES
+#define POND_BAND_NODES 0
+#endif
+template <int TX>
+__device__ __forceinline__ void band_tile(int t, int tiles_x, int tiles_y, int &tx, int &ty) {
+    constexpr int bw = POND_BAND_NODES / TX > 1 ? POND_BAND_NODES / TX : 1;  // tiles per band
+    if constexpr (POND_BAND_NODES == 0 || bw == 1) {
+        tx = t % tiles_x;
+        ty = t / tiles_x;
+    } else {
+        const int full = tiles_x / bw, per = bw * tiles_y;  // full bands, tiles per band
+        if (t < full * per) {
+            const int band = t / per, r = t - band * per;
+            ty = r / bw;
+            tx = band * bw + (r - ty * bw);
+        } else {
+            // the last band, narrower (tiles_x is no multiple of bw)
+            const int w = tiles_x - full * bw, r = t - full * per;
+            ty = r / w;
+            tx = full * bw + (r - ty * w);
+        }
+    }
+}
+
 // Tile shapes: TX x TY destination nodes, one lane each, lane t at (t % TX, t / TX).
 template <int TX, int TY>
 struct FixedShape {
