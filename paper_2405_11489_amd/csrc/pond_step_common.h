@@ -695,8 +695,11 @@ __device__ __forceinline__ void gather_shared_rows(const Taps &taps, const Veloc
 // central moments of the iterate frame once (central_normalised_n: a linear
 // map, so it commutes with the row weights), and each velocity whose stencil
 // holds the row adds its row weight times the reconstruction weights (the
-// lattice tables, uniform across lanes) dotted with those moments.  The sums
-// start at the reference moments in the same frame.
+// lattice tables, uniform across lanes) dotted with those moments.  As in
+// gather_shared_rows, the populations handed over are those of the deviations
+// from the reference moments; the order-4 reconstruction keeps the moments up
+// to order four (D1Q5 integrates exactly to degree nine), so the reference's
+// share of the sums is added by the caller, once.
 template <typename P, class L>
 constexpr bool shared_rows_transformed() {
     return L::Q == 25 && sizeof(P) == 4 && POND_D2Q25_SHARED != 0;
@@ -707,17 +710,6 @@ __device__ __forceinline__ void gather_shared_rows_transformed(const Taps &taps,
                                                                double xu, double yu, double sc,
                                                                P dux, P duy, P is, Take &take) {
     constexpr int NM = L::NM, Q1 = L::Q1;
-    // the reference moments in the iterate frame (f, then g)
-    P Rf[NM], Rg[NM];
-    {
-        P A[NM];
-#pragma unroll
-        for (int k = 0; k < NM; ++k) A[k] = taps.ref_at(k);
-        central_normalised_n<L>(A, dux, duy, is, Rf);
-#pragma unroll
-        for (int k = 0; k < NM; ++k) A[k] = taps.ref_at(NM + k);
-        central_normalised_n<L>(A, dux, duy, is, Rg);
-    }
 #pragma unroll 1
     for (int ia = 0; ia < Q1; ++ia) {
         const double cx = L::c(ia);
@@ -729,15 +721,7 @@ __device__ __forceinline__ void gather_shared_rows_transformed(const Taps &taps,
 #pragma unroll
         for (int b = 0; b < Q1; ++b) {
             by[b] = lagrange<NP>(fma(-sc, L::c(b), yu), wq[b]);
-            const P *r = tab.recon[Q1 * ia + b];
-            P sf = P(0), sg = P(0);
-#pragma unroll
-            for (int k = 0; k < NM; ++k) {
-                sf += r[k] * Rf[k];
-                sg += r[k] * Rg[k];
-            }
-            af[b] = sf;
-            ag[b] = sg;
+            af[b] = ag[b] = P(0);
         }
         auto visit = [&](int row, int seg, const P (&X)[2 * NM]) {
             P Zf[NM], Zg[NM];
@@ -875,9 +859,13 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                     Mg[k] += gi * mono[k];
                 }
             };
-            if constexpr (vel_group<P, L>() > 1) {
-                gather_shared_rows<P, NP, L, vel_group<P, L>()>(taps, tab, xu, yu, sc, dux, duy,
-                                                                 is, take);
+            if constexpr (vel_group<P, L>() > 1 || shared_rows_transformed<P, L>()) {
+                if constexpr (vel_group<P, L>() > 1)
+                    gather_shared_rows<P, NP, L, vel_group<P, L>()>(taps, tab, xu, yu, sc, dux,
+                                                                     duy, is, take);
+                else
+                    gather_shared_rows_transformed<P, NP, L>(taps, tab, xu, yu, sc, dux, duy, is,
+                                                             take);
                 // the reference moments' share of the sums (moments about u_ref;
                 // the lab velocity is V + u_ref), added once after the deviations'
                 const double m00 = double(taps.ref_at(0));
@@ -899,9 +887,6 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                     Mf[k] += taps.ref_at(k);
                     Mg[k] += taps.ref_at(NM + k);
                 }
-            } else if constexpr (shared_rows_transformed<P, L>()) {
-                gather_shared_rows_transformed<P, NP, L>(taps, tab, xu, yu, sc, dux, duy, is,
-                                                         take);
             } else {
                 // velocity i = Q1 ia + ib has x-component c(ia) and y-component c(ib):
                 // the x-stencil serves the Q1 velocities of one ia
