@@ -380,7 +380,8 @@ typedef struct pond_batch pond_batch; /* opaque */
 typedef struct {
     int32_t members;      /* contexts in the batch */
     int32_t tiles;        /* tiles per batched step, all members */
-    int32_t grid_blocks;  /* blocks of the step launch (one per tile) */
+    int32_t grid_blocks;  /* blocks of the step launch (one per tile; a build with
+                             POND_BATCH_PERSISTENT=1 launches a fixed grid) */
     int32_t lds_nodes;    /* LDS capacity per block, in nodes */
     int64_t nodes;        /* nodes per batched step, all members */
     int64_t steps;        /* batched steps enqueued since creation */

@@ -15,7 +15,10 @@
 //
 // (A persistent variant -- a fixed grid pulling tiles from per-XCD atomic
 // queues -- ran 2.4x slower on one 512 x 512 instance: same-address
-// device-scope atomics serialise, and the cost grew with the grid.)
+// device-scope atomics serialise, and the cost grew with the grid.  A fixed
+// grid with static shares of the tile list and no atomics, the build option
+// POND_BATCH_PERSISTENT, ran a 256-instance mixed batch 4.6 % slower than the
+// flat launch: static shares do not follow the members' uneven tile costs.)
 //
 // Every node goes through the same per-node code as the single-instance
 // kernels (tile_step / node_step with the member's own arguments), so a
@@ -75,14 +78,11 @@ __global__ __launch_bounds__(kBatchThreads) void batch_moments_kernel(
     node_moments<P>(a, mem[i].buf[par], static_cast<P *>(mem[i].mom[par]), n);
 }
 
+// Tile t of the flat list: its member's step on that tile.
 template <typename P, int NP, int S>
-__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(
-    step_min_waves<P, S>()))) void batch_step_kernel(
-    const BatchMember *__restrict__ mem, const int *__restrict__ tile_off, int nmem, int cap,
-    int flip) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int red[4 * red_slots<Shape256::kThreads>()];
-    const int t = xcd_tile(int(blockIdx.x), int(gridDim.x));
+__device__ __forceinline__ void batch_tile(const BatchMember *__restrict__ mem,
+                                           const int *__restrict__ tile_off, int nmem, int cap,
+                                           int flip, int t, unsigned char *smem_raw, int *red) {
     const int i = __builtin_amdgcn_readfirstlane(find_member(tile_off, nmem, t));
     const StepArgs a = mem[i].a;
     const int lg = mem[i].lg, tiles_x = mem[i].tiles_x;
@@ -92,6 +92,37 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(
                                mem[i].buf[par ^ 1], static_cast<P *>(mem[i].mom[par ^ 1]),
                      mem[i].cnt, reinterpret_cast<P *>(smem_raw), cap, (lt % tiles_x) << lg,
                      (lt / tiles_x) * (kBatchThreads >> lg), Shape256{lg}, red);
+}
+
+// POND_BATCH_PERSISTENT=1: a fixed grid of the blocks the chip holds at once,
+// block b (on XCD b % 8) stepping, in turn, a static share of its XCD's
+// contiguous range of the tile list (no queue, no atomics).  Off by default
+// (slower; see the note at the top of this file).
+#ifndef POND_BATCH_PERSISTENT
+#define POND_BATCH_PERSISTENT 0
+#endif
+
+template <typename P, int NP, int S>
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(
+    step_min_waves<P, S>()))) void batch_step_kernel(
+    const BatchMember *__restrict__ mem, const int *__restrict__ tile_off, int nmem, int cap,
+    int flip, int ntiles) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int red[4 * red_slots<Shape256::kThreads>()];
+#if POND_BATCH_PERSISTENT
+    // the grid has at least 8 blocks, so every XCD has one
+    const int b = int(blockIdx.x), nb = int(gridDim.x), x = b % 8;
+    const int on_xcd = (nb - x + 7) / 8;
+    const int lo = int((long long)x * ntiles / 8), hi = int((long long)(x + 1) * ntiles / 8);
+    for (int t = lo + b / 8; t < hi; t += on_xcd) {
+        batch_tile<P, NP, S>(mem, tile_off, nmem, cap, flip, t, smem_raw, red);
+        __syncthreads();  // the next tile's staging overwrites the LDS
+    }
+#else
+    (void)ntiles;
+    batch_tile<P, NP, S>(mem, tile_off, nmem, cap, flip, xcd_tile(int(blockIdx.x), int(gridDim.x)),
+                         smem_raw, red);
+#endif
 }
 
 template <typename P, int NP, int S>
@@ -159,6 +190,7 @@ struct pond_batch {
     BatchMember *d_mem;
     int *d_tile_off, *d_blk_off;
     int cap, tiles, blocks;
+    int grid;  // blocks of the step launch
     long long nodes;
     long long steps;
     // [parity][0]: one step, [parity][1]: kGraphSteps steps, starting at that parity
@@ -211,13 +243,13 @@ hipError_t enqueue_batch_step(pond_batch *b, int flip) {
         size_t(b->cap) * lds_node_values(16, b->dbl) * (b->dbl ? sizeof(double) : sizeof(float));
     with_variant(b->np, b->split, [&](auto np, auto sp) {
         if (b->dbl)
-            hipLaunchKernelGGL((batch_step_kernel<double, np(), sp()>), dim3(b->tiles),
+            hipLaunchKernelGGL((batch_step_kernel<double, np(), sp()>), dim3(b->grid),
                                dim3(kBatchThreads), lds, b->stream, b->d_mem, b->d_tile_off, n,
-                               b->cap, flip);
+                               b->cap, flip, b->tiles);
         else
-            hipLaunchKernelGGL((batch_step_kernel<float, np(), sp()>), dim3(b->tiles),
+            hipLaunchKernelGGL((batch_step_kernel<float, np(), sp()>), dim3(b->grid),
                                dim3(kBatchThreads), lds, b->stream, b->d_mem, b->d_tile_off, n,
-                               b->cap, flip);
+                               b->cap, flip, b->tiles);
         return 0;
     });
     hipError_t e = hipGetLastError();
@@ -354,6 +386,16 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
         return fail(POND_ERR_INVALID_ARG, "batch too large (%lld tiles)", tiles);
     }
     b->tiles = int(tiles);
+    b->grid = b->tiles;
+    if (POND_BATCH_PERSISTENT) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            per_cu > 0 && cus > 0)
+            b->grid = std::max(8, (per_cu * cus + 7) / 8 * 8);
+        else
+            b->grid = std::max(8, b->tiles);
+    }
     b->blocks = int(blocks);
     b->nodes = nodes;
 
@@ -466,7 +508,7 @@ pond_status pond_batch_get_info(pond_batch *b, pond_batch_info_t *out) {
     if (!b || !out) return fail(POND_ERR_INVALID_ARG, "batch or out is NULL");
     out->members = int32_t(b->members.size());
     out->tiles = b->tiles;
-    out->grid_blocks = b->tiles;
+    out->grid_blocks = b->grid;
     out->lds_nodes = b->cap;
     out->nodes = b->nodes;
     out->steps = b->steps;
