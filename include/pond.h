@@ -119,7 +119,7 @@ enum { POND_PREC_FP64 = 0, POND_PREC_FP32 = 1 };
  * during a step is flagged on the device and reported as
  * POND_ERR_UNSUPPORTED at the next synchronising call, after which the
  * context is in the error state (as for POND_ERR_NONPHYSICAL).  Walls run
- * every split on both lattices, in batches and the server too (D2Q16). */
+ * every split on both lattices, in batches and the server too. */
 enum { POND_BC_PERIODIC = 0, POND_BC_CLAMP = 1, POND_BC_WALL = 2 };
 
 typedef struct {
@@ -389,7 +389,9 @@ typedef struct {
     int32_t reserved;
 } pond_batch_info_t;
 
-/* Build a batch of n contexts (array of n distinct handles, copied).
+/* Build a batch of n contexts (array of n distinct handles, copied), which
+ * share precision, interp_points, energy split and lattice (D2Q16 or D2Q25;
+ * otherwise POND_ERR_INVALID_ARG).
  * hip_stream: stream of the batched steps (NULL: the batch creates its own).
  * Synchronises the members' streams.  Each member steps with tiles of width
  * pond_tuning.batch_tile_width, else the autotuned width of its size class,
@@ -443,7 +445,8 @@ POND_API pond_status pond_tuning_cache_clear(void);
  * round it steps, through one pond_batch (rebuilt when the selection
  * changes), the admitted requests with the least remaining work until the
  * round holds fill_nodes nodes (shortest-remaining-work first, filled to keep
- * the chip busy); it re-examines the queue every chunk_steps steps and as
+ * the chip busy; a round's requests share the lattice of its first one, so
+ * D2Q16 and D2Q25 requests take turns); it re-examines the queue every chunk_steps steps and as
  * soon as a request finishes, and releases a finished request's device memory
  * after copying its outputs to host memory.  Each request's results are those
  * of pond_step on it alone (the step of Sec. "Discrete velocity solver ...:
@@ -462,7 +465,7 @@ typedef struct {
                                   initial fields (4 N doubles, inside its own state
                                   memory), the state copy of autotune_steps (one state
                                   buffer) and the export buffer of
-                                  POND_REQ_KEEP_STATE (35 N doubles), each freed before
+                                  POND_REQ_KEEP_STATE ((2Q + 3) N doubles), each freed before
                                   the next request is admitted or collected */
     int64_t chunk_steps;       /* batched steps between queue checks; 0: run until the
                                   next request finishes (default 64) */
@@ -478,7 +481,8 @@ typedef struct {
 enum { POND_REQ_QUEUED = 0, POND_REQ_RUNNING = 1, POND_REQ_DONE = 2, POND_REQ_FAILED = 3 };
 /* Request flags: outputs kept in host memory at completion. */
 enum { POND_REQ_KEEP_MOMENTS = 1, /* rho, u_x, u_y, T, p: 5 N doubles */
-       POND_REQ_KEEP_STATE = 2 }; /* pond_export_state layout + u_ref: 35 N + 2 doubles
+       POND_REQ_KEEP_STATE = 2 }; /* pond_export_state layout + u_ref: (2Q + 3) N + 2
+                                     doubles, Q = 16 on D2Q16 (35 N + 2), 25 on D2Q25
                                      (an internal-split server keeps no previous level:
                                      imported again, the state resumes as after
                                      pond_import_state alone) */
@@ -532,8 +536,9 @@ POND_API pond_status pond_server_poll(pond_server *s, int64_t id, pond_request_i
 POND_API pond_status pond_server_wait(pond_server *s, int64_t id);
 
 /* Copy a finished request's kept outputs (nullable destinations; host
- * memory): moments 5 N doubles (rho, u_x, u_y, T, p), state 35 N + 2 doubles
- * (f, g, frame, u_ref as pond_export_state).  A failed request returns its
+ * memory): moments 5 N doubles (rho, u_x, u_y, T, p), state (2Q + 3) N + 2
+ * doubles (f, g, frame, u_ref as pond_export_state; Q = 16 on D2Q16, 25 on
+ * D2Q25).  A failed request returns its
  * error. */
 POND_API pond_status pond_server_result(pond_server *s, int64_t id, double *moments, double *state);
 

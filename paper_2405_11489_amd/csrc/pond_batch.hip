@@ -67,7 +67,7 @@ __device__ __forceinline__ int find_member(const int *__restrict__ off, int n, i
 }
 
 // flip: parity of the batched steps taken since the batch was built.
-template <typename P>
+template <typename P, class L>
 __global__ __launch_bounds__(kBatchThreads) void batch_moments_kernel(
     const BatchMember *__restrict__ mem, const int *__restrict__ blk_off, int nmem, int flip) {
     const int i = __builtin_amdgcn_readfirstlane(find_member(blk_off, nmem, int(blockIdx.x)));
@@ -75,11 +75,11 @@ __global__ __launch_bounds__(kBatchThreads) void batch_moments_kernel(
     const long long n = (long long)(int(blockIdx.x) - mem[i].blk_off) * kBatchThreads + threadIdx.x;
     if (n >= a.N) return;
     const int par = mem[i].parity0 ^ flip;
-    node_moments<P>(a, mem[i].buf[par], static_cast<P *>(mem[i].mom[par]), n);
+    node_moments<P, L>(a, mem[i].buf[par], static_cast<P *>(mem[i].mom[par]), n);
 }
 
 // Tile t of the flat list: its member's step on that tile.
-template <typename P, int NP, int S>
+template <typename P, int NP, int S, class L>
 __device__ __forceinline__ void batch_tile(const BatchMember *__restrict__ mem,
                                            const int *__restrict__ tile_off, int nmem, int cap,
                                            int flip, int t, unsigned char *smem_raw, int *red) {
@@ -88,7 +88,7 @@ __device__ __forceinline__ void batch_tile(const BatchMember *__restrict__ mem,
     const int lg = mem[i].lg, tiles_x = mem[i].tiles_x;
     const int lt = t - mem[i].tile_off;
     const int par = mem[i].parity0 ^ flip;
-    tile_step<P, NP, S, D2Q16>(a, mem[i].buf[par], static_cast<const P *>(mem[i].mom[par]),
+    tile_step<P, NP, S, L>(a, mem[i].buf[par], static_cast<const P *>(mem[i].mom[par]),
                                mem[i].buf[par ^ 1], static_cast<P *>(mem[i].mom[par ^ 1]),
                      mem[i].cnt, reinterpret_cast<P *>(smem_raw), cap, (lt % tiles_x) << lg,
                      (lt / tiles_x) * (kBatchThreads >> lg), Shape256{lg}, red);
@@ -102,9 +102,9 @@ __device__ __forceinline__ void batch_tile(const BatchMember *__restrict__ mem,
 #define POND_BATCH_PERSISTENT 0
 #endif
 
-template <typename P, int NP, int S>
+template <typename P, int NP, int S, class L>
 __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(
-    step_min_waves<P, S>()))) void batch_step_kernel(
+    step_min_waves<P, S, kBatchThreads, L>()))) void batch_step_kernel(
     const BatchMember *__restrict__ mem, const int *__restrict__ tile_off, int nmem, int cap,
     int flip, int ntiles) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -115,25 +115,32 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(
     const int on_xcd = (nb - x + 7) / 8;
     const int lo = int((long long)x * ntiles / 8), hi = int((long long)(x + 1) * ntiles / 8);
     for (int t = lo + b / 8; t < hi; t += on_xcd) {
-        batch_tile<P, NP, S>(mem, tile_off, nmem, cap, flip, t, smem_raw, red);
+        batch_tile<P, NP, S, L>(mem, tile_off, nmem, cap, flip, t, smem_raw, red);
         __syncthreads();  // the next tile's staging overwrites the LDS
     }
 #else
     (void)ntiles;
-    batch_tile<P, NP, S>(mem, tile_off, nmem, cap, flip, xcd_tile(int(blockIdx.x), int(gridDim.x)),
-                         smem_raw, red);
+    batch_tile<P, NP, S, L>(mem, tile_off, nmem, cap, flip,
+                            xcd_tile(int(blockIdx.x), int(gridDim.x)), smem_raw, red);
 #endif
 }
 
-template <typename P, int NP, int S>
+template <typename P, int NP, int S, class L>
 const void *step_kernel_ptr() {
-    return reinterpret_cast<const void *>(batch_step_kernel<P, NP, S>);
+    return reinterpret_cast<const void *>(batch_step_kernel<P, NP, S, L>);
 }
 
-const void *batch_step_fn(bool dbl, int np, int split) {
+template <class L>
+const void *batch_step_fn_l(bool dbl, int np, int split) {
     return with_variant(np, split, [&](auto n, auto sp) {
-        return dbl ? step_kernel_ptr<double, n(), sp()>() : step_kernel_ptr<float, n(), sp()>();
+        return dbl ? step_kernel_ptr<double, n(), sp(), L>()
+                   : step_kernel_ptr<float, n(), sp(), L>();
     });
+}
+
+const void *batch_step_fn(bool dbl, int np, int split, int lattice) {
+    return lattice == POND_LATTICE_D2Q25 ? batch_step_fn_l<D2Q25>(dbl, np, split)
+                                         : batch_step_fn_l<D2Q16>(dbl, np, split);
 }
 
 // ----------------------------------------------------- tuning cache ----
@@ -190,7 +197,8 @@ struct pond_batch {
     BatchMember *d_mem;
     int *d_tile_off, *d_blk_off;
     int cap, tiles, blocks;
-    int grid;  // blocks of the step launch
+    int grid;     // blocks of the step launch
+    int lattice;  // of every member
     long long nodes;
     long long steps;
     // [parity][0]: one step, [parity][1]: kGraphSteps steps, starting at that parity
@@ -223,35 +231,51 @@ hipError_t enqueue_batch_wall_ghosts(pond_batch *b, int flip, int next) {
     return e;
 }
 
-hipError_t enqueue_batch_moments(pond_batch *b, int flip) {
+template <class L>
+void launch_batch_moments(pond_batch *b, int flip) {
     const int n = int(b->members.size());
     if (b->dbl)
-        hipLaunchKernelGGL(batch_moments_kernel<double>, dim3(b->blocks), dim3(kBatchThreads), 0,
-                           b->stream, b->d_mem, b->d_blk_off, n, flip);
+        hipLaunchKernelGGL((batch_moments_kernel<double, L>), dim3(b->blocks), dim3(kBatchThreads),
+                           0, b->stream, b->d_mem, b->d_blk_off, n, flip);
     else
-        hipLaunchKernelGGL(batch_moments_kernel<float>, dim3(b->blocks), dim3(kBatchThreads), 0,
-                           b->stream, b->d_mem, b->d_blk_off, n, flip);
+        hipLaunchKernelGGL((batch_moments_kernel<float, L>), dim3(b->blocks), dim3(kBatchThreads),
+                           0, b->stream, b->d_mem, b->d_blk_off, n, flip);
+}
+
+hipError_t enqueue_batch_moments(pond_batch *b, int flip) {
+    if (b->lattice == POND_LATTICE_D2Q25)
+        launch_batch_moments<D2Q25>(b, flip);
+    else
+        launch_batch_moments<D2Q16>(b, flip);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? enqueue_batch_wall_ghosts(b, flip, 0) : e;
 }
 
 // One batched step: every member's step kernel tiles, which also write the
 // members' new moments (the moments of the current buffers must be fresh).
-hipError_t enqueue_batch_step(pond_batch *b, int flip) {
+template <class L>
+void launch_batch_step(pond_batch *b, int flip) {
     const int n = int(b->members.size());
-    const size_t lds =
-        size_t(b->cap) * lds_node_values(16, b->dbl) * (b->dbl ? sizeof(double) : sizeof(float));
+    const size_t lds = size_t(b->cap) * lds_node_values(L::Q, b->dbl) *
+                       (b->dbl ? sizeof(double) : sizeof(float));
     with_variant(b->np, b->split, [&](auto np, auto sp) {
         if (b->dbl)
-            hipLaunchKernelGGL((batch_step_kernel<double, np(), sp()>), dim3(b->grid),
+            hipLaunchKernelGGL((batch_step_kernel<double, np(), sp(), L>), dim3(b->grid),
                                dim3(kBatchThreads), lds, b->stream, b->d_mem, b->d_tile_off, n,
                                b->cap, flip, b->tiles);
         else
-            hipLaunchKernelGGL((batch_step_kernel<float, np(), sp()>), dim3(b->grid),
+            hipLaunchKernelGGL((batch_step_kernel<float, np(), sp(), L>), dim3(b->grid),
                                dim3(kBatchThreads), lds, b->stream, b->d_mem, b->d_tile_off, n,
                                b->cap, flip, b->tiles);
         return 0;
     });
+}
+
+hipError_t enqueue_batch_step(pond_batch *b, int flip) {
+    if (b->lattice == POND_LATTICE_D2Q25)
+        launch_batch_step<D2Q25>(b, flip);
+    else
+        launch_batch_step<D2Q16>(b, flip);
     hipError_t e = hipGetLastError();
     // walled members: the ghost rows of the moments the step wrote
     return e == hipSuccess ? enqueue_batch_wall_ghosts(b, flip, 1) : e;
@@ -305,13 +329,12 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
         if (!c->initialized) return fail(POND_ERR_STATE, "context %d has no state", i);
         if (c->failed) return fail(POND_ERR_STATE, "context %d is in the error state", i);
         if (c->batch) return fail(POND_ERR_STATE, "context %d already belongs to a batch", i);
-        if (c->p.lattice != POND_LATTICE_D2Q16)
-            return fail(POND_ERR_UNSUPPORTED,
-                        "context %d: batches run D2Q16 (every energy split and boundary)", i);
         if (c->p.precision != ctxs[0]->p.precision ||
-            c->p.interp_points != ctxs[0]->p.interp_points || c->p.split != ctxs[0]->p.split)
+            c->p.interp_points != ctxs[0]->p.interp_points || c->p.split != ctxs[0]->p.split ||
+            c->p.lattice != ctxs[0]->p.lattice)
             return fail(POND_ERR_INVALID_ARG,
-                        "context %d: members must share precision, interp_points and split", i);
+                        "context %d: members must share precision, interp_points, split and "
+                        "lattice", i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == c) return fail(POND_ERR_INVALID_ARG, "context %d appears twice", i);
     }
@@ -321,6 +344,7 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
     b->dbl = ctxs[0]->p.precision == POND_PREC_FP64;
     b->np = ctxs[0]->p.interp_points;
     b->split = ctxs[0]->p.split;
+    b->lattice = ctxs[0]->p.lattice;
     b->own_stream = hip_stream == nullptr;
     hipError_t e = hipSuccess;
     if (b->own_stream)
@@ -335,13 +359,13 @@ pond_status pond_batch_create(pond_ctx *const *ctxs, int n, void *hip_stream, po
 
     // LDS per block: the share of a CU of the blocks that fit by registers
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_fn(b->dbl, b->np, b->split),
-                                                     kBatchThreads, 0);
-    b->cap = lds_nodes_for_blocks(e == hipSuccess ? per_cu : 1, b->dbl);
-    const size_t lds = size_t(b->cap) * kNMom * (b->dbl ? sizeof(double) : sizeof(float));
+    const void *kern = batch_step_fn(b->dbl, b->np, b->split, b->lattice);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBatchThreads, 0);
+    b->cap = lds_nodes_for_blocks(e == hipSuccess ? per_cu : 1, b->dbl, b->lattice);
+    const size_t lds = size_t(b->cap) * lds_node_values(b->lattice, b->dbl) *
+                       (b->dbl ? sizeof(double) : sizeof(float));
     if (e == hipSuccess)
-        e = hipFuncSetAttribute(batch_step_fn(b->dbl, b->np, b->split),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) {
         release(b);
         return hip_fail(e, "batch launch configuration");
@@ -653,8 +677,6 @@ pond_status pond_autotune(pond_ctx *c, int steps, pond_tuning *out) {
             if (tiles[i] == tiles[0]) tiles.erase(tiles.begin() + long(i--));
         widths = dbl ? std::vector<int>{16, 32, 64} : std::vector<int>{32, 16, 64};
     }
-    // batches run D2Q16 only: other lattices keep the width they have
-    if (c->p.lattice != POND_LATTICE_D2Q16) widths = {c->tuning.batch_tile_width};
     Saved sv;
     s = save_state(c, sv);
     // two interleaved rounds; each candidate keeps its faster measurement

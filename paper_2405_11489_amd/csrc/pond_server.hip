@@ -4,8 +4,9 @@
 // out.  A worker thread admits the head of the queue whenever its state
 // footprint (pond_state_bytes) fits the HBM budget next to the admitted
 // requests.  Each round steps, through one pond_batch, the admitted requests
-// with the least remaining work (nodes x steps), as many as it takes to hold
-// fill_nodes nodes (enough tiles to fill the chip): small requests finish
+// with the least remaining work (nodes x steps) -- of one lattice, that of the
+// request with the least -- as many as it takes to hold fill_nodes nodes
+// (enough tiles to fill the chip): small requests finish
 // together at full-chip throughput instead of at the pace of the largest
 // co-runner, and large ones absorb the remaining capacity.  The queue is
 // re-examined every chunk_steps steps and as soon as a request finishes.  A finished request's moments (and, on request, its raw state)
@@ -105,9 +106,11 @@ pond_status collect(Request *r) {
         st = pond_moments(r->ctx, m, m + N, m + 2 * N, m + 3 * N, m + 4 * N);
     }
     if (st == POND_OK && (r->flags & POND_REQ_KEEP_STATE)) {
-        r->raw.assign(size_t(35 * N + 2), 0.0);
+        // f (Q N), g (Q N), frame (3 N), u_ref (2): Q = 16 on D2Q16, 25 on D2Q25
+        const int64_t Q = r->p.lattice;
+        r->raw.assign(size_t((2 * Q + 3) * N + 2), 0.0);
         double *x = r->raw.data();
-        st = pond_export_state(r->ctx, x, x + 16 * N, x + 32 * N, x + 35 * N);
+        st = pond_export_state(r->ctx, x, x + Q * N, x + 2 * Q * N, x + (2 * Q + 3) * N);
     }
     return st;
 }
@@ -169,6 +172,13 @@ void worker_loop(pond_server *s) {
                 return nodes_of(a->p) * (a->steps_total - a->steps_done) <
                        nodes_of(b->p) * (b->steps_total - b->steps_done);
             });
+        }
+        // a batch runs one lattice: that of the first request in this order
+        const int lattice = run.front()->p.lattice;
+        run.erase(std::remove_if(run.begin(), run.end(),
+                                 [lattice](const Request *r) { return r->p.lattice != lattice; }),
+                  run.end());
+        if (s->cfg.fill_nodes > 0) {
             int64_t nodes = 0;
             size_t take = 0;
             while (take < run.size() && nodes < s->cfg.fill_nodes) nodes += nodes_of(run[take++]->p);
@@ -317,8 +327,6 @@ pond_status pond_server_submit(pond_server *s, const pond_params *p, const doubl
                     "request precision / interp_points / split differ from the server's "
                     "(%d / %d / %d)",
                     s->cfg.precision, s->cfg.interp_points, s->cfg.split);
-    if (p->lattice != POND_LATTICE_D2Q16)
-        return fail(POND_ERR_UNSUPPORTED, "the server runs D2Q16 requests");
     if (bytes > size_t(s->cfg.hbm_budget_bytes))
         return fail(POND_ERR_INVALID_ARG, "request needs %zu bytes, above the budget of %lld", bytes,
                     (long long)s->cfg.hbm_budget_bytes);

@@ -191,28 +191,94 @@ def test_nontrans_batched_equals_alone_bitwise(prec):
             s.close()
 
 
-def test_batch_and_server_reject_d2q25():
+@pytest.mark.parametrize("prec,split", [(FP32, TOTAL), (FP64, TOTAL), (FP32, NT), (FP64, NT),
+                                        (FP32, INT)])
+def test_d2q25_batched_equals_alone_bitwise(prec, split):
+    """D2Q25 members in a batch (ragged, clamped and single-row grids; 13
+    steps: one 8-step graph launch and five 1-step launches): every member
+    bitwise equal to its run alone.  The internal split keeps the previous
+    level's frames in the state and exports them too."""
+    from paper_2405_11489_amd import pond
+    ws = [modes(48, 40, mach=1.5, seed=41), clamp_x(modes(33, 17, mach=2.0, seed=42)),
+          sod(nx=100, steps=10), modes(5, 3, mach=1.0, seed=43)]
+    steps = 13
+    kw = dict(lattice=25, split=split)
+    alone = []
+    for w in ws:
+        with gpu_solver(w, prec, **kw) as s:
+            s.step(steps)
+            alone.append((s.export_state()[:3], prev_frame_of(s, split)))
+    sols = [gpu_solver(w, prec, **kw) for w in ws]
+    try:
+        b = pond.pond_batch_create([s.ctx for s in sols])
+        try:
+            assert pond.pond_batch_get_info(b).members == len(ws)
+            pond.pond_batch_step(b, 5)
+            pond.pond_batch_step(b, steps - 5)
+            pond.pond_batch_synchronize(b)
+        finally:
+            pond.pond_batch_destroy(b)
+        for k, (s, (ref, ref_prev)) in enumerate(zip(sols, alone)):
+            for x, y in zip(s.export_state()[:3], ref):
+                np.testing.assert_array_equal(x, y, err_msg=f"member {k} ({ws[k].name})")
+            got_prev = prev_frame_of(s, split)
+            if ref_prev is not None:
+                np.testing.assert_array_equal(got_prev, ref_prev)
+    finally:
+        for s in sols:
+            s.close()
+
+
+def test_batch_refuses_mixed_lattices():
     from paper_2405_11489_amd import pond
     w = modes(16, 8, mach=1.0, seed=23)
-    for kw in ({"lattice": 25},):
-        a = gpu_solver(w, FP32, **kw)
-        try:
-            with pytest.raises(pond.PondError) as ei:
-                pond.pond_batch_create([a.ctx])
-            assert ei.value.status == pond.ERR_UNSUPPORTED
-        finally:
-            a.close()
-    srv = pond.pond_server_create(pond.pond_server_config_default())
+    a = gpu_solver(w, FP32, lattice=25)
+    c = gpu_solver(w, FP32, lattice=16)
     try:
-        # D2Q25 is unsupported; a non-translational request differs from the
-        # default server's (total) split
-        for kw, status in (({"lattice": 25}, pond.ERR_UNSUPPORTED),
-                           ({"split": NT}, pond.ERR_INVALID_ARG)):
+        with pytest.raises(pond.PondError) as ei:
+            pond.pond_batch_create([a.ctx, c.ctx])
+        assert ei.value.status == pond.ERR_INVALID_ARG
+    finally:
+        a.close()
+        c.close()
+
+
+def test_d2q25_and_d2q16_requests_served_equal_solo_bitwise():
+    """A server takes D2Q25 and D2Q16 requests together (each round batches
+    one lattice); every served state equals the request's run alone bit for
+    bit.  A request of another split than the server's is still refused."""
+    from paper_2405_11489_amd import pond
+    reqs = [(modes(24, 16, mach=1.5, seed=51), 9, 25), (modes(20, 12, mach=0.8, seed=52), 7, 16),
+            (sod(nx=64, steps=6), 6, 25), (modes(40, 24, mach=2.0, seed=53), 12, 25),
+            (clamp_x(modes(17, 9, mach=1.2, seed=54)), 5, 16), (modes(9, 7, seed=55), 10, 25)]
+    srv = pond.pond_server_create(pond.pond_server_config_default(chunk_steps=4))
+    try:
+        ids = []
+        for w, steps, lat in reqs:
             p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma,
-                                         prandtl=1.0, **kw)
-            with pytest.raises(pond.PondError) as ei:
-                pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, 4)
-            assert ei.value.status == status
+                                         prandtl=w.prandtl, bc_x=w.bc_x, bc_y=w.bc_y, lattice=lat)
+            ids.append(pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, steps,
+                                               pond.REQ_KEEP_STATE | pond.REQ_KEEP_MOMENTS))
+        w = reqs[0][0]
+        p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma, prandtl=1.0,
+                                     lattice=25, split=NT)
+        with pytest.raises(pond.PondError) as ei:
+            pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, 4)
+        assert ei.value.status == pond.ERR_INVALID_ARG
+        pond.pond_server_wait(srv, 0)
+        st = pond.pond_server_get_stats(srv)
+        assert st.completed == len(reqs) and st.failed == 0
+        for (w, steps, lat), i in zip(reqs, ids):
+            N = w.nodes
+            x = np.zeros((2 * lat + 3) * N + 2)
+            m = np.zeros(5 * N)
+            pond.pond_server_result(srv, i, m, x)
+            f, g, fr, _, _, mom = gpu_run(w, FP32, steps, lattice=lat)
+            got = (x[:lat * N].reshape(lat, N), x[lat * N:2 * lat * N].reshape(lat, N),
+                   x[2 * lat * N:(2 * lat + 3) * N].reshape(3, N))
+            for a_, b_ in zip(got, (f, g, fr)):
+                np.testing.assert_array_equal(a_, b_, err_msg=f"D2Q{lat} {w.name}")
+            np.testing.assert_array_equal(m[:N].reshape(w.ny, w.nx), mom["rho"])
     finally:
         pond.pond_server_destroy(srv)
 
