@@ -90,11 +90,14 @@ def flops_per_iter(np_, q=16, shared_rows=None):
     x-component, see shared_rows_mean); per x-component it interpolates that
     many rows along x (NP taps x 20 moments, FMA), and each velocity takes its
     NP rows through its coefficients (20 FMA + 1 per row); per velocity the
-    coefficients (45) and the transformed reference moments (2 x 20 FMA)."""
+    coefficients (45); once, the reference moments' share of the sums (30).
+    D2Q25 (q = 25): the per-velocity count (30 moments at NP^2 taps for each
+    of the 25 velocities), the D2Q25 form of the canonical count; its FP32
+    kernel shares the x-pass, which this count takes as speed."""
     if q == 25:
         return 175 + 25 * np_ * np_ * 61 + 4250
     if shared_rows is not None:
-        return 112 + 4 * (shared_rows * np_ * 20 * 2) + 16 * np_ * 21 * 2 + 16 * (45 + 80)
+        return 112 + 4 * (shared_rows * np_ * 20 * 2) + 16 * np_ * 21 * 2 + 16 * 45 + 30
     return 112 + 16 * np_ * np_ * 41 + 2080
 
 
