@@ -421,13 +421,13 @@ POND_API pond_status pond_batch_destroy(pond_batch *b);
 
 /* Autotuner: time at least `steps` (>= 1) steps and 2 ms of device time of c
  * with each candidate tile shape and LDS capacity of the single-context
- * kernel and each candidate batch tile width (one-member batches; D2Q16
- * only, the lattice batches run), in two
+ * kernel and each candidate batch tile width (one-member batches), in two
  * interleaved rounds, restoring c's state, step count and counters after
  * every candidate.  A candidate replaces the default only when more than 3 %
- * faster.  Applies the result to c, stores it for c's class (precision,
- * stencil, boundary conditions, rounded log2 of nx and of ny, and the stencil
- * reach max(|u_x|, |u_y|) + c_out sqrt(T) of the initial frame, rounded up)
+ * faster.  Applies the result to c, stores it for c's class (lattice,
+ * energy split, precision, stencil, boundary conditions, rounded log2 of nx
+ * and of ny, and the stencil reach max(|u_x|, |u_y|) + c_out sqrt(T) of the
+ * initial frame, rounded up)
  * in a process-wide cache that pond_init_fields / pond_import_state (unless
  * the tuning was set explicitly) and pond_batch_create consult, and returns
  * it in *out (nullable).  Allocates one state buffer's worth of device memory
@@ -446,8 +446,8 @@ POND_API pond_status pond_tuning_cache_clear(void);
  * changes), the admitted requests with the least remaining work until the
  * round holds fill_nodes nodes (shortest-remaining-work first, filled to keep
  * the chip busy; a round's requests share the lattice of its first one, so
- * D2Q16 and D2Q25 requests take turns); it re-examines the queue every chunk_steps steps and as
- * soon as a request finishes, and releases a finished request's device memory
+ * D2Q16 and D2Q25 requests take turns); it re-examines the queue every
+ * chunk_steps steps and as soon as a request finishes, and releases a finished request's device memory
  * after copying its outputs to host memory.  Each request's results are those
  * of pond_step on it alone (the step of Sec. "Discrete velocity solver ...:
  * PonD"), whatever traffic it shared the GPU with.  All API calls are

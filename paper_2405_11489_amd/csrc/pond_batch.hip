@@ -144,9 +144,10 @@ const void *batch_step_fn(bool dbl, int np, int split, int lattice) {
 }
 
 // ----------------------------------------------------- tuning cache ----
-// Class of an instance: energy split, precision, stencil, boundary conditions, the rounded
-// log2 of each axis (a single-row grid is its own class) and the stencil
-// reach of its initial frame (the best tile shape depends on the halo).
+// Class of an instance: lattice, energy split, precision, stencil, boundary
+// conditions, the rounded log2 of each axis (a single-row grid is its own
+// class) and the stencil reach of its initial frame (the best tile shape
+// depends on the halo).
 using TuneKey = std::tuple<int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, pond_tuning> g_tune;
@@ -155,9 +156,10 @@ int log2_class(int n) { return n <= 1 ? -1 : int(std::lround(std::log2(double(n)
 
 TuneKey tune_key(const pond_ctx *c) {
     const pond_params &p = c->p;
-    return TuneKey(p.split * 64 + p.precision * 16 + p.interp_points, p.bc_x * 2 + p.bc_y,
-                   log2_class(p.nx),
-                   log2_class(p.ny), std::min(c->reach, 12));
+    // lattices tune apart: a D2Q16 class may pick a tile D2Q25 does not run
+    return TuneKey(p.lattice * 1024 + p.split * 64 + p.precision * 16 + p.interp_points,
+                   p.bc_x * 2 + p.bc_y, log2_class(p.nx), log2_class(p.ny),
+                   std::min(c->reach, 12));
 }
 
 int default_batch_width(const pond_params &p) {

@@ -243,6 +243,37 @@ def test_batch_refuses_mixed_lattices():
         c.close()
 
 
+def test_lattices_tune_apart():
+    """The autotuner's process-wide cache keeps a class per lattice: a D2Q25
+    context of the size class of an autotuned D2Q16 one keeps its own default
+    tuning (a D2Q16 class may hold a tile D2Q25 does not run), and a server
+    that autotunes at admission serves both lattices of one size class."""
+    from paper_2405_11489_amd import pond
+    pond.pond_tuning_cache_clear()
+    try:
+        w = modes(64, 64, mach=1.0, amp=1e-3, seed=61)
+        with gpu_solver(w, FP32, lattice=16) as s16:
+            pond.pond_autotune(s16.ctx, 2)
+            assert pond.pond_get_tuning(s16.ctx).batch_tile_width > 0
+        with gpu_solver(w, FP32, lattice=25) as s25:
+            t = pond.pond_get_tuning(s25.ctx)
+            assert t.tile == pond.TILE_16x16 and t.batch_tile_width == 0
+            s25.step(2)
+        srv = pond.pond_server_create(pond.pond_server_config_default(autotune_steps=2))
+        try:
+            for lat in (16, 25, 16, 25):
+                p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma,
+                                             prandtl=w.prandtl, lattice=lat)
+                pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, 3)
+            pond.pond_server_wait(srv, 0)
+            st = pond.pond_server_get_stats(srv)
+            assert st.completed == 4 and st.failed == 0
+        finally:
+            pond.pond_server_destroy(srv)
+    finally:
+        pond.pond_tuning_cache_clear()
+
+
 def test_d2q25_and_d2q16_requests_served_equal_solo_bitwise():
     """A server takes D2Q25 and D2Q16 requests together (each round batches
     one lattice); every served state equals the request's run alone bit for
