@@ -471,7 +471,8 @@ typedef struct {
                                   next request finishes (default 64) */
     int64_t fill_nodes;        /* each round steps the requests with the least remaining
                                   work (nodes x steps) until the round holds this many
-                                  nodes; <= 0: every admitted request (default 2^19) */
+                                  nodes; <= 0: every admitted request (of the round's
+                                  lattice; default 2^19) */
     int64_t autotune_steps;    /* > 0: pond_autotune (with this many steps) the first
                                   request of every new size class at admission
                                   (default 0) */
