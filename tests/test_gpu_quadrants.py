@@ -45,3 +45,24 @@ def test_quadrants_256_match_the_stored_oracle_run(prec):
     else:
         l1 = field_l1(m, mo)
         assert max(l1.values()) <= 1e-4, l1
+
+
+def test_block_mean_of_the_2048_run_against_the_256_oracle():
+    """Resolution error, a diagnostic and no parity bar: the benchmark's 2048 x
+    2048 run (FP32 path) over the same physical time as the stored 256 x 256
+    oracle run (8 x the steps: a signal crosses 8 x the nodes), averaged over
+    8 x 8 blocks, against the oracle's fields.  The finer grid carries 8 x less
+    viscosity per unit of physical length, so the difference is that of two
+    resolutions of the problem, not of two implementations; the test prints it
+    and checks only that the fine run stays physical and finite."""
+    steps, n, mo, _ = _golden()
+    r = 2048 // n
+    w = workloads.riemann_quadrants(n=2048, seed=0)
+    _, _, _, _, st, m = gpu_run(w, FP32, r * steps)
+    assert st.nonphysical == 0
+    mean = {k: m[k].reshape(n, r, n, r).mean(axis=(1, 3)) for k in ("rho", "ux", "uy", "T")}
+    mean["p"] = mean["rho"] * mean["T"]
+    l1 = field_l1(mean, mo)
+    print(f"2048^2 ({r * steps} steps) 8x8 block mean vs the 256^2 oracle ({steps} steps), "
+          f"L1: " + ", ".join(f"{k} {v:.2e}" for k, v in l1.items()))
+    assert all(np.isfinite(v) for v in l1.values())
