@@ -231,6 +231,31 @@ def cpu_baseline(w, seconds, split=0, lattice=16, threads=0):
             "kind": "oracle", "sample": sample, **host_description()}
 
 
+def cpu_subset(ws, seconds, threads=0):
+    """The oracle on a representative subset of a set of instances: 8 of them
+    spanning the size range (every size-sorted eighth), each timed for about
+    seconds / 8 (cpu_baseline); every instance of the set is then projected at
+    the rate of the sampled instance nearest to it in node count, giving the
+    projected serial oracle time of the whole set."""
+    order = sorted(range(len(ws)), key=lambda i: ws[i].nodes)
+    pick = sorted({order[min(len(order) - 1, (2 * k + 1) * len(order) // 16)] for k in range(8)})
+    rates = []
+    for i in pick:
+        r = cpu_baseline(ws[i], seconds / len(pick), threads=threads)
+        rates.append((ws[i].nodes, r["value"], r["sample"]))
+        log(f"oracle subset: {ws[i].nx}x{ws[i].ny}: {r['value']:.4f} MLUPS")
+    total_s = 0.0
+    for w in ws:
+        rate = min(rates, key=lambda t: abs(math.log(t[0]) - math.log(w.nodes)))[1]
+        total_s += w.nodes * w.steps / (rate * 1e6)
+    updates = sum(w.nodes * w.steps for w in ws)
+    return {"kind": "oracle", "unit": "MLUPS", "subset": [
+                {"nodes": n, "MLUPS": v, "sample": smp} for n, v, smp in rates],
+            "projected_serial_s": total_s, "projected_MLUPS": updates / total_s / 1e6,
+            "how": "each instance at the rate of the sampled instance nearest in node count",
+            **host_description()}
+
+
 def _ctx_for(pond, w, prec, stream=None):
     p = pond.pond_params_default(nx=w.nx, ny=w.ny, tau=w.tau, gamma=w.gamma, prandtl=w.prandtl,
                                  bc_x=w.bc_x, bc_y=w.bc_y, precision=prec)
@@ -335,6 +360,8 @@ def bench_batch(args, pond, workloads):
                   "how": "each instance alone (pond_step), min(steps, 200) steps timed with "
                          "HIP events, scaled to its step count"},
         "speedup_vs_plain": batched / plain,
+        **({"cpu_subset": cpu_subset(ws, args.cpu_seconds, args.cpu_threads)}
+           if args.cpu_subset else {}),
     }
 
 
@@ -442,6 +469,8 @@ def bench_serve(args, pond, workloads):
                                       "p99": float(np.percentile(sl, 99)),
                                       "mean": float(sl.mean())}},
         "server_stats": {k: getattr(st, k) for k, _ in st._fields_},
+        **({"cpu_subset": cpu_subset(ws, args.cpu_seconds, args.cpu_threads)}
+           if args.cpu_subset else {}),
     }
 
 
@@ -628,6 +657,9 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the CPU oracle baseline (0: all of the host's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-subset", action="store_true",
+                    help="batch / serve: time the oracle on 8 instances spanning the sizes "
+                         "and project its serial time for the whole set")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline only: no FP32 error run, no 512^2 line, no batched or "
                          "served subsets")
