@@ -445,8 +445,9 @@ POND_API pond_status pond_tuning_cache_clear(void);
  * round it steps, through one pond_batch (rebuilt when the selection
  * changes), the admitted requests with the least remaining work until the
  * round holds fill_nodes nodes (shortest-remaining-work first, filled to keep
- * the chip busy; a round's requests share the lattice of its first one, so
- * D2Q16 and D2Q25 requests take turns); it re-examines the queue every
+ * the chip busy; a round's requests share the lattice -- and, in a server
+ * configured with POND_SERVE_ANY, the precision, stencil or split -- of its
+ * first one, so requests of different kinds take turns); it re-examines the queue every
  * chunk_steps steps and as soon as a request finishes, and releases a finished request's device memory
  * after copying its outputs to host memory.  Each request's results are those
  * of pond_step on it alone (the step of Sec. "Discrete velocity solver ...:
@@ -454,10 +455,17 @@ POND_API pond_status pond_tuning_cache_clear(void);
  * thread-safe; the server owns every context it creates. */
 typedef struct pond_server pond_server; /* opaque */
 
+/* POND_SERVE_ANY in a server configuration's precision, interp_points or
+ * split: the server takes requests of any value of that field, and a round
+ * batches requests that agree on it (as on the lattice). */
+enum { POND_SERVE_ANY = -1 };
+
 typedef struct {
     uint32_t struct_size;      /* = sizeof(pond_server_config) */
-    int32_t precision;         /* POND_PREC_* shared by all requests (default FP32) */
-    int32_t interp_points;     /* 3 or 4, shared by all requests (default 4) */
+    int32_t precision;         /* POND_PREC_* shared by all requests, or POND_SERVE_ANY
+                                  (default FP32) */
+    int32_t interp_points;     /* 3 or 4, shared by all requests, or POND_SERVE_ANY
+                                  (default 4) */
     int32_t max_members;       /* cap on running requests; <= 0: none (default) */
     int64_t hbm_budget_bytes;  /* admission cap on the summed pond_state_bytes of running
                                   requests (default 64 GiB).  Transient buffers come on
@@ -472,11 +480,12 @@ typedef struct {
     int64_t fill_nodes;        /* each round steps the requests with the least remaining
                                   work (nodes x steps) until the round holds this many
                                   nodes; <= 0: every admitted request (of the round's
-                                  lattice; default 2^19) */
+                                  kind; default 2^19) */
     int64_t autotune_steps;    /* > 0: pond_autotune (with this many steps) the first
                                   request of every new size class at admission
                                   (default 0) */
-    int32_t split;             /* POND_SPLIT_* shared by all requests (default TOTAL) */
+    int32_t split;             /* POND_SPLIT_* shared by all requests, or POND_SERVE_ANY
+                                  (default TOTAL) */
 } pond_server_config;
 
 enum { POND_REQ_QUEUED = 0, POND_REQ_RUNNING = 1, POND_REQ_DONE = 2, POND_REQ_FAILED = 3 };
@@ -522,8 +531,8 @@ POND_API pond_status pond_server_create(const pond_server_config *cfg, pond_serv
 
 /* Queue a request.  The four fields (host memory, nx * ny doubles each, layout
  * of pond_init_fields) are copied before the call returns.  Requests whose
- * parameters are invalid, whose precision or interp_points differ from the
- * server's, or whose footprint exceeds the whole budget are refused
+ * parameters are invalid, whose precision, interp_points or split differ from
+ * the server's (unless it takes any), or whose footprint exceeds the whole budget are refused
  * (POND_ERR_INVALID_ARG); invalid field values fail the request at admission.
  * *id > 0 identifies it. */
 POND_API pond_status pond_server_submit(pond_server *s, const pond_params *p, const double *rho,

@@ -4,8 +4,9 @@
 // out.  A worker thread admits the head of the queue whenever its state
 // footprint (pond_state_bytes) fits the HBM budget next to the admitted
 // requests.  Each round steps, through one pond_batch, the admitted requests
-// with the least remaining work (nodes x steps) -- of one lattice, that of the
-// request with the least -- as many as it takes to hold fill_nodes nodes
+// with the least remaining work (nodes x steps) -- of one lattice, precision,
+// stencil and energy split, those of the request with the least -- as many as
+// it takes to hold fill_nodes nodes
 // (enough tiles to fill the chip): small requests finish
 // together at full-chip throughput instead of at the pace of the largest
 // co-runner, and large ones absorb the remaining capacity.  The queue is
@@ -173,11 +174,14 @@ void worker_loop(pond_server *s) {
                        nodes_of(b->p) * (b->steps_total - b->steps_done);
             });
         }
-        // a batch runs one lattice: that of the first request in this order
-        const int lattice = run.front()->p.lattice;
-        run.erase(std::remove_if(run.begin(), run.end(),
-                                 [lattice](const Request *r) { return r->p.lattice != lattice; }),
-                  run.end());
+        // a batch runs one lattice, precision, stencil and split: those of the
+        // first request in this order
+        const pond_params &p0 = run.front()->p;
+        const auto other = [&p0](const Request *r) {
+            return r->p.lattice != p0.lattice || r->p.precision != p0.precision ||
+                   r->p.interp_points != p0.interp_points || r->p.split != p0.split;
+        };
+        run.erase(std::remove_if(run.begin(), run.end(), other), run.end());
         if (s->cfg.fill_nodes > 0) {
             int64_t nodes = 0;
             size_t take = 0;
@@ -281,12 +285,15 @@ pond_status pond_server_create(const pond_server_config *cfg, pond_server **out)
     if (!cfg || cfg->struct_size != sizeof(pond_server_config))
         return fail(POND_ERR_INVALID_ARG, "config is NULL or has the wrong struct_size");
     if (cfg->hbm_budget_bytes <= 0) return fail(POND_ERR_INVALID_ARG, "hbm_budget_bytes must be > 0");
-    if (cfg->precision != POND_PREC_FP32 && cfg->precision != POND_PREC_FP64)
+    // -1 (POND_SERVE_ANY): requests of any value, batched apart
+    if (cfg->precision != POND_PREC_FP32 && cfg->precision != POND_PREC_FP64 &&
+        cfg->precision != POND_SERVE_ANY)
         return fail(POND_ERR_INVALID_ARG, "unknown precision %d", cfg->precision);
-    if (cfg->interp_points != 3 && cfg->interp_points != 4)
+    if (cfg->interp_points != 3 && cfg->interp_points != 4 &&
+        cfg->interp_points != POND_SERVE_ANY)
         return fail(POND_ERR_INVALID_ARG, "interp_points must be 3 or 4");
     if (cfg->split != POND_SPLIT_TOTAL && cfg->split != POND_SPLIT_INTERNAL &&
-        cfg->split != POND_SPLIT_NONTRANS)
+        cfg->split != POND_SPLIT_NONTRANS && cfg->split != POND_SERVE_ANY)
         return fail(POND_ERR_INVALID_ARG, "unknown split %d", cfg->split);
     if (cfg->chunk_steps < 0 || cfg->autotune_steps < 0)
         return fail(POND_ERR_INVALID_ARG, "chunk_steps and autotune_steps must be >= 0");
@@ -321,8 +328,9 @@ pond_status pond_server_submit(pond_server *s, const pond_params *p, const doubl
         return fail(POND_ERR_INVALID_ARG, "unknown flags 0x%x", unsigned(flags));
     const size_t bytes = pond_state_bytes(p);
     if (bytes == 0) return fail(POND_ERR_INVALID_ARG, "invalid parameters: %s", last_error());
-    if (p->precision != s->cfg.precision || p->interp_points != s->cfg.interp_points ||
-        p->split != s->cfg.split)
+    const auto differs = [](int32_t v, int32_t c) { return c != POND_SERVE_ANY && v != c; };
+    if (differs(p->precision, s->cfg.precision) ||
+        differs(p->interp_points, s->cfg.interp_points) || differs(p->split, s->cfg.split))
         return fail(POND_ERR_INVALID_ARG,
                     "request precision / interp_points / split differ from the server's "
                     "(%d / %d / %d)",

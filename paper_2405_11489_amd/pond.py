@@ -23,6 +23,7 @@ LIB_PATH = os.environ.get("POND_LIB_PATH") or os.path.join(HERE, "libpond.so")
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NONPHYSICAL, ERR_STATE = range(7)
 LATTICE_D2Q16, LATTICE_D2Q25 = 16, 25
 SPLIT_TOTAL, SPLIT_INTERNAL, SPLIT_NONTRANS = 0, 1, 2
+SERVE_ANY = -1  # server configuration: requests of any precision / stencil / split
 PREC_FP64, PREC_FP32 = 0, 1
 BC_PERIODIC, BC_CLAMP, BC_WALL = 0, 1, 2
 ABI_VERSION = 3

@@ -127,6 +127,42 @@ def test_internal_and_nontrans_servers_equal_solo_bitwise(split):
         pond.pond_server_destroy(srv)
 
 
+def test_server_taking_any_precision_stencil_and_split():
+    """A server configured with SERVE_ANY takes requests of every precision,
+    stencil and energy split; each round batches requests of one kind, and
+    every served state equals the request's run alone bit for bit."""
+    from paper_2405_11489_amd import pond
+    kinds = [(FP32, 4, 0), (FP64, 4, 1), (FP32, 3, 2), (FP32, 4, 1), (FP64, 3, 0), (FP32, 4, 2),
+             (FP32, 4, 0), (FP64, 4, 2)]
+    reqs = []
+    for k, (prec, npts, split) in enumerate(kinds):
+        w = workloads.fourier_modes(n=16 + 4 * k, ny=12 + 2 * k, mach=1.2, amplitude=1e-2,
+                                    seed=70 + k, tau=0.6, prandtl=1.0)
+        reqs.append((w, 5 + k, prec, npts, split))
+    srv = _server(pond, precision=pond.SERVE_ANY, interp_points=pond.SERVE_ANY,
+                  split=pond.SERVE_ANY, chunk_steps=3)
+    try:
+        ids = []
+        for w, steps, prec, npts, split in reqs:
+            p = _params(pond, w, prec)
+            p.interp_points = npts
+            p.split = split
+            ids.append(pond.pond_server_submit(srv, p, w.rho, w.ux, w.uy, w.T, steps,
+                                               pond.REQ_KEEP_STATE))
+        pond.pond_server_wait(srv, 0)
+        st = pond.pond_server_get_stats(srv)
+        assert st.completed == len(reqs) and st.failed == 0
+        for (w, steps, prec, npts, split), i in zip(reqs, ids):
+            N = w.nodes
+            x = np.zeros(35 * N + 2)
+            pond.pond_server_result(srv, i, None, x)
+            f, g, fr, _, _, _ = gpu_run(w, prec, steps, interp_points=npts, split=split)
+            for a_, b_ in zip(_unpack_state(x, N), (f, g, fr)):
+                np.testing.assert_array_equal(a_, b_, err_msg=f"{w.name} {prec} {npts} {split}")
+    finally:
+        pond.pond_server_destroy(srv)
+
+
 def test_failures_and_refusals():
     from paper_2405_11489_amd import pond
     good = workloads.fourier_modes(n=20, ny=12, mach=1.0, amplitude=1e-2, seed=1, tau=0.6)
