@@ -124,7 +124,8 @@ enum { POND_BC_PERIODIC = 0, POND_BC_CLAMP = 1, POND_BC_WALL = 2 };
 
 typedef struct {
     uint32_t struct_size;  /* = sizeof(pond_params); ABI guard */
-    int32_t nx, ny;        /* nodes per axis, >= 1; ny == 1 is a quasi-1-D run */
+    int32_t nx, ny;        /* nodes per axis, >= 1, nx * ny <= 2^31 - 1; ny == 1 is a
+                              quasi-1-D run */
     int32_t bc_x, bc_y;    /* POND_BC_*; POND_BC_WALL for bc_y only */
     int32_t lattice;       /* POND_LATTICE_D2Q16 (default) or POND_LATTICE_D2Q25 */
     int32_t interp_points; /* 4 = cubic Lagrange (default); 3 = quadratic, the paper's

@@ -93,6 +93,20 @@ def test_state_bytes(pond):
     assert 496 * 512 * 512 <= pond.pond_state_bytes(p) < 496 * 512 * 512 + 16384
 
 
+def test_grid_size_limit(pond):
+    """Node indices are 32-bit: nx * ny up to 2^31 - 1 is a valid grid (its
+    state size is reported; nothing is allocated), one node more is refused
+    before any device call."""
+    p = pond.pond_params_default(nx=2**31 - 1, ny=1, precision=pond.PREC_FP32)
+    n = 2**31 - 1
+    assert 464 * n <= pond.pond_state_bytes(p) < 464 * n + 16384
+    p = pond.pond_params_default(nx=46341, ny=46341)  # 2^31 + 4633 nodes
+    assert pond.pond_state_bytes(p) == 0
+    with pytest.raises(pond.PondError) as ei:
+        pond.pond_create(p)
+    assert ei.value.status == pond.ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("field,value,status", [
     ("nx", 0, 1), ("ny", -3, 1), ("tau", 0.5, 1), ("tau", float("nan"), 1),
     ("prandtl", 0.0, 1), ("gamma", 1.0, 1), ("gamma", 2.5, 1), ("bc_x", 2, 1),
