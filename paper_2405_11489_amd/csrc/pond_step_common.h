@@ -445,50 +445,77 @@ __device__ __forceinline__ void pop_coeffs_n(const P r[L::NM], P dx, P dy, P is,
     }
 }
 
+// Moments sum_i f_i V_ix^p V_iy^q of Q populations at the velocities V_i =
+// s c_i + d (c_i = (c(a), c(b)) for i = Q1 a + b; one scale s and offset d for
+// all i) through the lattice sums C_pq = sum_i f_i c(a)^p c(b)^q, which the
+// x-components build in turn: column_add takes population (a, b) into S_q =
+// sum_b f_(a,b) c(b)^q, column_flush adds c(a)^p S_q to C_pq once the
+// x-component is done, and moments_from_lattice_sums expands (s c + d)^p by
+// the binomial theorem at the end.  (Q1 operations per population and NM per
+// x-component, where the monomials of each V_i and their products with f_i
+// cost about 3 NM.)
 template <class L, typename P>
-__device__ __forceinline__ void monomials_n(P Vx, P Vy, P mono[L::NM]) {
-    P px[L::N + 1], py[L::N + 1];
-    px[0] = py[0] = P(1);
+__device__ __forceinline__ void column_add(P S[L::N + 1], int b, P f) {
+    const P cb = P(L::c(b));
+    S[0] += f;
+    if (cb == P(0)) return;  // the zero abscissa of an odd lattice
+    P cq = cb;
 #pragma unroll
-    for (int j = 1; j <= L::N; ++j) {
-        px[j] = px[j - 1] * Vx;
-        py[j] = py[j - 1] * Vy;
+    for (int q = 1; q <= L::N; ++q) {
+        S[q] += f * cq;
+        cq *= cb;
+    }
+}
+
+template <class L, typename P>
+__device__ __forceinline__ void column_flush(P C[L::NM], P S[L::N + 1], int a) {
+    const P ca = P(L::c(a));
+    P cp = P(1);
+#pragma unroll
+    for (int p = 0; p <= L::N; ++p) {
+#pragma unroll
+        for (int q = 0; p + q <= L::N; ++q) C[mom_index(p, q)] += p == 0 ? S[q] : cp * S[q];
+        cp *= ca;
     }
 #pragma unroll
-    for (int k = 0; k < L::NM; ++k) mono[k] = px[mom_px(k)] * py[mom_py(k)];
+    for (int q = 0; q <= L::N; ++q) S[q] = P(0);
 }
 
-template <typename P>
-__device__ __forceinline__ void monomials(P Vx, P Vy, P mono[kNM]) {
-    const P Vxx = Vx * Vx, Vyy = Vy * Vy;
-    mono[0] = P(1);
-    mono[1] = Vx;
-    mono[2] = Vy;
-    mono[3] = Vxx;
-    mono[4] = Vx * Vy;
-    mono[5] = Vyy;
-    mono[6] = Vxx * Vx;
-    mono[7] = Vxx * Vy;
-    mono[8] = Vx * Vyy;
-    mono[9] = Vyy * Vy;
-}
-
-// Monomials V_x^p V_y^q of a stored node (the moments pre-pass's form).
 template <class L, typename P>
-__device__ __forceinline__ void node_monomials(P Vx, P Vy, P mono[L::NM]) {
-    if constexpr (L::Q == 16) {
-        mono[0] = P(1);
-        mono[1] = Vx;
-        mono[2] = Vy;
-        mono[3] = Vx * Vx;
-        mono[4] = Vx * Vy;
-        mono[5] = Vy * Vy;
-        mono[6] = Vx * Vx * Vx;
-        mono[7] = Vx * Vx * Vy;
-        mono[8] = Vx * Vy * Vy;
-        mono[9] = Vy * Vy * Vy;
-    } else {
-        monomials_n<L>(Vx, Vy, mono);
+__device__ __forceinline__ void moments_from_lattice_sums(const P C[L::NM], P s, P dx, P dy,
+                                                          P M[L::NM]) {
+    constexpr int N = L::N, NM = L::NM;
+    P ex[N + 1], ey[N + 1], sc[N + 1];
+    ex[0] = ey[0] = sc[0] = P(1);
+#pragma unroll
+    for (int j = 1; j <= N; ++j) {
+        ex[j] = ex[j - 1] * dx;
+        ey[j] = ey[j - 1] * dy;
+        sc[j] = sc[j - 1] * s;
+    }
+    // U_rt = s^(r+t) C_rt; then T[p][t] = sum_r C(p,r) dx^(p-r) U[r][t] and
+    // M[p][q] = sum_t C(q,t) dy^(q-t) T[p][t], each sum starting at its unit term
+    P U[NM], T[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        const int o = mom_px(k) + mom_py(k);
+        U[k] = o == 0 ? C[k] : C[k] * sc[o];
+    }
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        const int p = mom_px(k), t = mom_py(k);
+        P acc = U[k];
+#pragma unroll
+        for (int r = p - 1; r >= 0; --r) acc += (P(binom_c(p, r)) * ex[p - r]) * U[mom_index(r, t)];
+        T[k] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        const int p = mom_px(k), q = mom_py(k);
+        P acc = T[k];
+#pragma unroll
+        for (int t = q - 1; t >= 0; --t) acc += (P(binom_c(q, t)) * ey[q - t]) * T[mom_index(p, t)];
+        M[k] = acc;
     }
 }
 
@@ -610,8 +637,9 @@ constexpr int vel_group() {
 // x-pass with its row weight, through its frame-transformation coefficients
 // (the scalar f_i = B_i . I_i distributes over the rows).  When the union is
 // longer than the separate stencils (hot flows), each velocity's rows are
-// visited on their own; the sums are the same either way.  take(i, cx, cy, f_i,
-// g_i) receives each gathered population pair.
+// visited on their own; the sums are the same either way.  take(b, cx, cy,
+// f_i, g_i) receives each gathered population pair (i = Q1 ia + b), and
+// column(ia) follows the last of an x-component's.
 //
 // The populations handed over are those of the interpolated deviations from
 // the reference moments only: the reference's own share, B_i . M_ref, is the
@@ -621,10 +649,10 @@ constexpr int vel_group() {
 // momentum, energy, the lab moments -- follows from M_ref itself; the caller
 // adds it once after the gather.  (The share then enters the sums exactly,
 // with no rounding of the coefficients B_i.)
-template <typename P, int NP, class L, int VG, class Taps, class Take>
+template <typename P, int NP, class L, int VG, class Taps, class Take, class Column>
 __device__ __forceinline__ void gather_shared_rows(const Taps &taps, const VelocityTablesP<P> &tab,
                                                    double xu, double yu, double sc, P dux, P duy,
-                                                   P is, Take &take) {
+                                                   P is, Take &take, Column &column) {
     constexpr int NM = L::NM;
     static_assert(L::Q1 % VG == 0, "velocity groups split the x-component's velocities");
 #pragma unroll 1
@@ -682,9 +710,10 @@ __device__ __forceinline__ void gather_shared_rows(const Taps &taps, const Veloc
 #pragma unroll
             for (int v = 0; v < VG; ++v) {
                 const int b = g * VG + v;
-                take(L::Q1 * ia + b, cx, L::c(b), af[v], ag[v]);
+                take(b, cx, L::c(b), af[v], ag[v]);
             }
         }
+        column(ia);
     }
 }
 
@@ -705,10 +734,11 @@ constexpr bool shared_rows_transformed() {
     return L::Q == 25 && sizeof(P) == 4 && POND_D2Q25_SHARED != 0;
 }
 
-template <typename P, int NP, class L, class Taps, class Tab, class Take>
+template <typename P, int NP, class L, class Taps, class Tab, class Take, class Column>
 __device__ __forceinline__ void gather_shared_rows_transformed(const Taps &taps, const Tab &tab,
                                                                double xu, double yu, double sc,
-                                                               P dux, P duy, P is, Take &take) {
+                                                               P dux, P duy, P is, Take &take,
+                                                               Column &column) {
     constexpr int NM = L::NM, Q1 = L::Q1;
 #pragma unroll 1
     for (int ia = 0; ia < Q1; ++ia) {
@@ -765,7 +795,8 @@ __device__ __forceinline__ void gather_shared_rows_transformed(const Taps &taps,
             }
         }
 #pragma unroll
-        for (int b = 0; b < Q1; ++b) take(Q1 * ia + b, cx, L::c(b), af[b], ag[b]);
+        for (int b = 0; b < Q1; ++b) take(b, cx, L::c(b), af[b], ag[b]);
+        column(ia);
     }
 }
 
@@ -781,8 +812,9 @@ __device__ __forceinline__ void gather_shared_rows_transformed(const Taps &taps,
 // Per predictor-corrector gather, for each velocity i: departure point and
 // Lagrange weights, interpolation of the 2 NM moments, frame transformation of
 // the interpolated moments into the iterate frame (population i of f and g);
-// the FP64 sums rho, j, E and the lab moments of the gathered populations are
-// accumulated on the fly, so no population array is kept.
+// the FP64 sums rho, j, E and the lattice sums of the gathered populations
+// (their lab moments follow once, from the last gather's) are accumulated on
+// the fly, so no population array is kept.
 template <typename P, int NP, int S, class L, class Taps>
 __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, int x, int y,
                                           long long n, bool live, double l0, double l1, double l2,
@@ -794,8 +826,9 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
     double ln0 = lg0, ln1 = lg1, ln2 = lg2;  // frame of the gathered moments
     double rho = 1.0, gsum = 0.0;  // FP64 sums of the last gather's f and g
     P Mf[NM], Mg[NM];  // lab moments (about u_ref) of the last gather's populations
+    P Cf[NM], Cg[NM];  // their lattice sums (column_add), in the gather's frame
 #pragma unroll
-    for (int k = 0; k < NM; ++k) Mf[k] = Mg[k] = P(0);
+    for (int k = 0; k < NM; ++k) Mf[k] = Mg[k] = Cf[k] = Cg[k] = P(0);
     bool done = !live, conv = false, bad = false, overrun = false;
     unsigned long long itc = 0;  // gathers of the wave's lanes
     // internal split: the source's velocity gradient (the same for every
@@ -811,6 +844,21 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             gyy = P(gr[3]);
         }
     }
+
+    // lab moments of a gather's populations from its lattice sums (frame scale sP,
+    // offset (dux, duy) from u_ref); the shared gathers sum the deviations from
+    // the reference moments, whose share is added here
+    auto lab_moments = [&](P sP, P dux, P duy) {
+        moments_from_lattice_sums<L>(Cf, sP, dux, duy, Mf);
+        moments_from_lattice_sums<L>(Cg, sP, dux, duy, Mg);
+        if constexpr (vel_group<P, L>() > 1 || shared_rows_transformed<P, L>()) {
+#pragma unroll
+            for (int k = 0; k < NM; ++k) {
+                Mf[k] += taps.ref_at(k);
+                Mg[k] += taps.ref_at(NM + k);
+            }
+        }
+    };
 
     for (int it = 0; it < a.pc_max_iter; ++it) {
         itc += wave_count(!done);
@@ -830,11 +878,14 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             const double xu = double(x) - fmin(fmax(lg0, -1.0e8), 1.0e8);
             const double yu = double(y) - fmin(fmax(lg1, -1.0e8), 1.0e8);
             double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0, Eg = 0.0;
+            P Sf[L::N + 1], Sg[L::N + 1];
 #pragma unroll
-            for (int k = 0; k < NM; ++k) Mf[k] = Mg[k] = P(0);
-            // population i of f and g gathered in the iterate frame: the FP64 sums
-            // rho, j, E and the lab moments of the gathered populations
-            auto take = [&](int i, double cx, double cy, P fi, P gi) {
+            for (int k = 0; k < NM; ++k) Cf[k] = Cg[k] = P(0);
+#pragma unroll
+            for (int q = 0; q <= L::N; ++q) Sf[q] = Sg[q] = P(0);
+            // population i = Q1 ia + b of f and g gathered in the iterate frame: the
+            // FP64 sums rho, j, E and the lattice sums of the gathered populations
+            auto take = [&](int b, double cx, double cy, P fi, P gi) {
                 // conserved moments in FP64
                 const double fd = double(fi);
                 r += fd;
@@ -847,25 +898,21 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                     const double Cx = s * cx + lg0, Cy = s * cy + lg1;
                     E += 0.5 * fd * (Cx * Cx + Cy * Cy);
                 }
-                // lab moments of the gathered populations, for the re-projection
-                P mono[NM];
-                if constexpr (L::Q == 16)
-                    monomials(sP * P(cx) + dux, sP * P(cy) + duy, mono);
-                else
-                    monomials_n<L>(sP * P(cx) + dux, sP * P(cy) + duy, mono);
-#pragma unroll
-                for (int k = 0; k < NM; ++k) {
-                    Mf[k] += fi * mono[k];
-                    Mg[k] += gi * mono[k];
-                }
+                // lattice sums of the gathered populations, for the re-projection
+                column_add<L>(Sf, b, fi);
+                column_add<L>(Sg, b, gi);
+            };
+            auto column = [&](int ia) {
+                column_flush<L>(Cf, Sf, ia);
+                column_flush<L>(Cg, Sg, ia);
             };
             if constexpr (vel_group<P, L>() > 1 || shared_rows_transformed<P, L>()) {
                 if constexpr (vel_group<P, L>() > 1)
                     gather_shared_rows<P, NP, L, vel_group<P, L>()>(taps, tab, xu, yu, sc, dux,
-                                                                     duy, is, take);
+                                                                     duy, is, take, column);
                 else
                     gather_shared_rows_transformed<P, NP, L>(taps, tab, xu, yu, sc, dux, duy, is,
-                                                             take);
+                                                             take, column);
                 // the reference moments' share of the sums (moments about u_ref;
                 // the lab velocity is V + u_ref), added once after the deviations'
                 const double m00 = double(taps.ref_at(0));
@@ -881,11 +928,6 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                     const double m02 = double(taps.ref_at(mom_index(0, 2)));
                     E += 0.5 * (m20 + m02) + a.uref_x * m10 + a.uref_y * m01 +
                          0.5 * (a.uref_x * a.uref_x + a.uref_y * a.uref_y) * m00;
-                }
-#pragma unroll
-                for (int k = 0; k < NM; ++k) {
-                    Mf[k] += taps.ref_at(k);
-                    Mg[k] += taps.ref_at(NM + k);
                 }
             } else {
                 // velocity i = Q1 ia + ib has x-component c(ia) and y-component c(ib):
@@ -917,8 +959,9 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                             fi += B[k] * If[k];
                             gi += B[k] * Ig[k];
                         }
-                        take(i, cx, cy, fi, gi);
+                        take(ib, cx, cy, fi, gi);
                     }
+                    column(ia);
                 }
             }
             rho = r;
@@ -927,6 +970,7 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
             ln1 = jy / r;
             // total split: sum g = E = rho c_v T + |j|^2 / (2 rho); internal: sum g = rho c_v T;
             // non-translational: E = sum g + sum f |C|^2 / 2 = rho c_v T + |j|^2 / (2 rho)
+            if constexpr (S == 1) lab_moments(sP, dux, duy);
             if constexpr (S == 1) {
                 // the energy of the step's middle, U = sum g + (sum G) / 2, with the
                 // source's sum G = -(omega / 2) rho T div u - (1 - omega / 2) P : grad u
@@ -972,6 +1016,11 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
     }
 
     if (live) {
+        if constexpr (S != 1) {
+            // the last gather's frame (lam is only advanced when another gather follows)
+            const double s = sqrt(lg2);
+            lab_moments(P(s), P(lg0 - a.uref_x), P(lg1 - a.uref_y));
+        }
         // re-projection onto lam* = (ln0, ln1, ln2): Grad coefficients there
         const double sT = sqrt(ln2);
         const P is = P(1.0 / sT);
@@ -1076,37 +1125,44 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
         P MM[nmom_padded<P, L>()];
 #pragma unroll
         for (int k = 0; k < nmom_padded<P, L>(); ++k) MM[k] = P(0);
+        P Nf[NM], Ng[NM], Sf[L::N + 1], Sg[L::N + 1];  // lattice sums (column_add)
+#pragma unroll
+        for (int k = 0; k < NM; ++k) Nf[k] = Ng[k] = P(0);
+#pragma unroll
+        for (int q = 0; q <= L::N; ++q) Sf[q] = Sg[q] = P(0);
         double mass = 0.0, gzero = 0.0;  // zeroth moments summed in FP64 (see above)
-#pragma unroll 4
-        for (int i = 0; i < L::Q; ++i) {
-            P fv = P(0), gv = P(0);
+#pragma unroll 1
+        for (int ia = 0; ia < L::Q1; ++ia) {
 #pragma unroll
-            for (int k = 0; k < NM; ++k) {
-                fv += tab.herm[i][k] * af[k];
-                gv += tab.herm[i][k] * ag[k];
-            }
-            if constexpr (S == 1) {
-                P ft = P(0);
+            for (int b = 0; b < L::Q1; ++b) {
+                const int i = L::Q1 * ia + b;
+                P fv = P(0), gv = P(0);
 #pragma unroll
-                for (int k = 0; k < NM; ++k) ft += tab.herm[i][k] * afp[k];
-                const P ex = sTP * P(L::c(i / L::Q1)), ey = sTP * P(L::c(i % L::Q1));
-                const P Cx = ex + u0, Cy = ey + u1;
-                gv -= src_w * ft * (ex * (ax + Cx * gxx + Cy * gyx) + ey * (ay + Cx * gxy + Cy * gyy));
-            }
-            if (bad) fv = gv = P(NAN);
-            out_store<kStreamPops>(&pop_plane<P>(dst.f, i, a.N)[n], fv);
-            out_store<kStreamPops>(&pop_plane<P>(dst.g, i, a.N)[n], gv);
-            const P Vx = sM * P(L::c(i / L::Q1)) + dxM, Vy = sM * P(L::c(i % L::Q1)) + dyM;
-            P mono[NM];
-            node_monomials<L>(Vx, Vy, mono);
+                for (int k = 0; k < NM; ++k) {
+                    fv += tab.herm[i][k] * af[k];
+                    gv += tab.herm[i][k] * ag[k];
+                }
+                if constexpr (S == 1) {
+                    P ft = P(0);
 #pragma unroll
-            for (int k = 0; k < NM; ++k) {
-                MM[k] += fv * mono[k];
-                MM[NM + k] += gv * mono[k];
+                    for (int k = 0; k < NM; ++k) ft += tab.herm[i][k] * afp[k];
+                    const P ex = sTP * P(L::c(ia)), ey = sTP * P(L::c(b));
+                    const P Cx = ex + u0, Cy = ey + u1;
+                    gv -= src_w * ft * (ex * (ax + Cx * gxx + Cy * gyx) + ey * (ay + Cx * gxy + Cy * gyy));
+                }
+                if (bad) fv = gv = P(NAN);
+                out_store<kStreamPops>(&pop_plane<P>(dst.f, i, a.N)[n], fv);
+                out_store<kStreamPops>(&pop_plane<P>(dst.g, i, a.N)[n], gv);
+                column_add<L>(Sf, b, fv);
+                column_add<L>(Sg, b, gv);
+                mass += double(fv);
+                gzero += double(gv);
             }
-            mass += double(fv);
-            gzero += double(gv);
+            column_flush<L>(Nf, Sf, ia);
+            column_flush<L>(Ng, Sg, ia);
         }
+        moments_from_lattice_sums<L>(Nf, sM, dxM, dyM, MM);
+        moments_from_lattice_sums<L>(Ng, sM, dxM, dyM, MM + NM);
         MM[0] = P(mass);
         MM[NM] = P(gzero);
         out_store<kStreamFrame>(&dst.ux[n], uxst);

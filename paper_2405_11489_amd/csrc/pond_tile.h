@@ -384,22 +384,30 @@ __device__ __forceinline__ void node_moments(const StepArgs &a, DevState st, P *
     P M[nmom_padded<P, L>()];
 #pragma unroll
     for (int k = 0; k < nmom_padded<P, L>(); ++k) M[k] = P(0);
+    // through the lattice sums, in the order the step forms them (the same bits)
+    P Cf[NM], Cg[NM], Sf[L::N + 1], Sg[L::N + 1];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) Cf[k] = Cg[k] = P(0);
+#pragma unroll
+    for (int q = 0; q <= L::N; ++q) Sf[q] = Sg[q] = P(0);
     double mass = 0.0, gzero = 0.0;  // zeroth moments summed in FP64, as the step does
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const P fi = pop_plane<P>(st.f, i, a.N)[n];
-        const P gi = pop_plane<P>(st.g, i, a.N)[n];
-        mass += double(fi);
-        gzero += double(gi);
-        const P Vx = s * P(L::c(i / L::Q1)) + dx, Vy = s * P(L::c(i % L::Q1)) + dy;
-        P mono[NM];
-        node_monomials<L>(Vx, Vy, mono);
+    for (int ia = 0; ia < L::Q1; ++ia) {
 #pragma unroll
-        for (int k = 0; k < NM; ++k) {
-            M[k] += fi * mono[k];
-            M[NM + k] += gi * mono[k];
+        for (int b = 0; b < L::Q1; ++b) {
+            const int i = L::Q1 * ia + b;
+            const P fi = pop_plane<P>(st.f, i, a.N)[n];
+            const P gi = pop_plane<P>(st.g, i, a.N)[n];
+            mass += double(fi);
+            gzero += double(gi);
+            column_add<L>(Sf, b, fi);
+            column_add<L>(Sg, b, gi);
         }
+        column_flush<L>(Cf, Sf, ia);
+        column_flush<L>(Cg, Sg, ia);
     }
+    moments_from_lattice_sums<L>(Cf, s, dx, dy, M);
+    moments_from_lattice_sums<L>(Cg, s, dx, dy, M + NM);
     M[0] = P(mass);
     M[NM] = P(gzero);
     store_moments<P, nmom<L>()>(mom, a.mstride, a.moff + n, M);
