@@ -267,6 +267,45 @@ __device__ __forceinline__ const auto &ltab() {
         return kTab25D;
 }
 
+// Lattice monomials c(a)^p c(b)^q of every velocity i = Q1 a + b (exponents
+// of moment k), for the lattice sums of the per-velocity gather.
+template <typename P, class L>
+struct LatticeMonomials {
+    P m[L::Q][L::NM];
+};
+template <typename P, class L>
+constexpr LatticeMonomials<P, L> make_lattice_monomials() {
+    LatticeMonomials<P, L> t{};
+    for (int i = 0; i < L::Q; ++i) {
+        const double ca = L::c(i / L::Q1), cb = L::c(i % L::Q1);
+        for (int k = 0; k < L::NM; ++k) {
+            double v = 1.0;
+            for (int p = 0; p < mom_px(k); ++p) v *= ca;
+            for (int q = 0; q < mom_py(k); ++q) v *= cb;
+            t.m[i][k] = P(v);
+        }
+    }
+    return t;
+}
+static __constant__ LatticeMonomials<float, D2Q16> kMono16F = make_lattice_monomials<float, D2Q16>();
+static __constant__ LatticeMonomials<double, D2Q16> kMono16D = make_lattice_monomials<double, D2Q16>();
+static __constant__ LatticeMonomials<float, D2Q25> kMono25F = make_lattice_monomials<float, D2Q25>();
+static __constant__ LatticeMonomials<double, D2Q25> kMono25D = make_lattice_monomials<double, D2Q25>();
+
+template <typename P, class L>
+__device__ __forceinline__ const LatticeMonomials<P, L> &lmono() {
+    if constexpr (L::Q == 16) {
+        if constexpr (sizeof(P) == 4)
+            return kMono16F;
+        else
+            return kMono16D;
+    } else if constexpr (sizeof(P) == 4) {
+        return kMono25F;
+    } else {
+        return kMono25D;
+    }
+}
+
 // Tap source reading the HBM moment planes with periodic / clamp wrapping.
 // gather() accumulates sum_{p,q} wx[p] wy[q] M(bx + p, by + q) for the NP x NP
 // stencil whose first node is (bx, by) in unwrapped grid coordinates.
@@ -884,8 +923,9 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
 #pragma unroll
             for (int q = 0; q <= L::N; ++q) Sf[q] = Sg[q] = P(0);
             // population i = Q1 ia + b of f and g gathered in the iterate frame: the
-            // FP64 sums rho, j, E and the lattice sums of the gathered populations
-            auto take = [&](int b, double cx, double cy, P fi, P gi) {
+            // FP64 sums rho, j, E (sums) and the lattice sums of the gathered
+            // populations (take: through the column sums)
+            auto sums = [&](double cx, double cy, P fi, P gi) {
                 // conserved moments in FP64
                 const double fd = double(fi);
                 r += fd;
@@ -898,7 +938,9 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                     const double Cx = s * cx + lg0, Cy = s * cy + lg1;
                     E += 0.5 * fd * (Cx * Cx + Cy * Cy);
                 }
-                // lattice sums of the gathered populations, for the re-projection
+            };
+            auto take = [&](int b, double cx, double cy, P fi, P gi) {
+                sums(cx, cy, fi, gi);
                 column_add<L>(Sf, b, fi);
                 column_add<L>(Sg, b, gi);
             };
@@ -959,9 +1001,17 @@ __device__ __forceinline__ void node_step(const StepArgs &a, const Taps &taps, i
                             fi += B[k] * If[k];
                             gi += B[k] * Ig[k];
                         }
-                        take(ib, cx, cy, fi, gi);
+                        // lattice sums with the velocity's monomials from the
+                        // table: column sums held across this loop would take
+                        // registers the FP64 kernels do not have
+                        sums(cx, cy, fi, gi);
+                        const P *mi = lmono<P, L>().m[i];
+#pragma unroll
+                        for (int k = 0; k < NM; ++k) {
+                            Cf[k] += fi * mi[k];
+                            Cg[k] += gi * mi[k];
+                        }
                     }
-                    column(ia);
                 }
             }
             rho = r;
